@@ -1,0 +1,383 @@
+"""FP64 CPU oracle for the stratified Cox model (arXiv 2310.16238).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no code
+with the HIP path (``paper_2310_16238_amd``) and never imports it.
+
+Three levels, each citing the passage it follows:
+
+* **Definitions, brute force** (``*_brute``): the negative log partial
+  likelihood of Eq. strat_l, its gradient (Eq. strat_g), the diagonal of its
+  Hessian (Eq. strat_h) and the full Hessian (the same sums with x x' in place
+  of x_j^2), each as an explicit loop over events and their risk sets
+  R_k(Y_ki) = {r in stratum k : Y_kr >= Y_ki}.  O(E N P); small inputs only.
+* **Scan form** (plain C in ``cox_oracle.c``): rows sorted by stratum and
+  decreasing time (Sec. 2.7), the segmented scan of Sec. 2.6, and the
+  per-coordinate reductions of Eqs. parallel_g / parallel_h; cyclic coordinate
+  descent with trust region and l1 (Sec. 2.4).
+* **Full information and Newton**: the Hessian in the form
+  X' diag(w Lambda) X - sum_g d_g xbar_g xbar_g' (exchanging the order of the
+  sums in Eq. strat_h), evaluated with a matrix product, and a Newton/Cholesky
+  fit for the unpenalised optimum.
+
+Readings of points the paper leaves open (ties, ordering, degenerate columns,
+convergence) are the ones listed in the project's design notes; the important
+ones are restated where they are used.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cox_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_build", "liborc.so")
+_lib = None
+
+
+def build_c(force: bool = False) -> str:
+    """Compile the plain-C part of the oracle with gcc (single-threaded, -O2)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-fno-fast-math",
+                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def load_library(path: str):
+    """Load a compiled copy of cox_oracle.c and declare its signatures."""
+    lib = ctypes.CDLL(path)
+    i64, dp, u8p, i64p = ctypes.c_int64, ctypes.POINTER(ctypes.c_double), \
+        ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int64)
+    lib.orc_segscan.argtypes = [i64, dp, u8p, dp]
+    lib.orc_segscan.restype = None
+    lib.orc_coord_terms.argtypes = [i64, dp, dp, u8p, u8p, i64p, dp]
+    lib.orc_coord_terms.restype = None
+    lib.orc_ccd_step.argtypes = [ctypes.c_double] * 5 + [dp]
+    lib.orc_ccd_step.restype = ctypes.c_double
+    lib.orc_ccd_fit.argtypes = [i64, i64, dp, i64, u8p, u8p, i64p, dp, ctypes.c_double,
+                                ctypes.c_int, dp, dp, dp]
+    lib.orc_ccd_fit.restype = ctypes.c_int
+    lib.orc_group_sums.argtypes = [i64, i64, dp, i64, dp, u8p, u8p, i64p,
+                                   dp, dp, dp, dp, dp, dp]
+    lib.orc_group_sums.restype = i64
+    return lib
+
+
+def _c():
+    global _lib
+    if _lib is None:
+        _lib = load_library(build_c())
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+# ============================================================== canonical layout (Sec. 2.7)
+
+@dataclasses.dataclass
+class Layout:
+    """Rows in canonical order: stratum ascending, time descending, original index ascending.
+
+    perm[i]   original index of canonical row i
+    head[i]   1 iff canonical row i is the first row of its stratum (head flag f, Sec. 2.7)
+    event[i]  delta of canonical row i
+    gend[i]   canonical index of the last row of row i's tie group (same stratum, same time)
+    dcount[i] number of events in the tie group if row i ends its group, else 0
+    meta[i]   packed word: bit 31 head, bit 30 event, bits 0..29 dcount
+    """
+    perm: np.ndarray
+    head: np.ndarray
+    event: np.ndarray
+    gend: np.ndarray
+    dcount: np.ndarray
+    meta: np.ndarray
+    n_strata: int
+
+
+def canonical_layout(time, event, stratum=None) -> Layout:
+    time = np.asarray(time, dtype=np.float64)
+    event = np.asarray(event).astype(np.uint8)
+    n = time.shape[0]
+    if stratum is None:
+        stratum = np.zeros(n, dtype=np.int64)
+    stratum = np.asarray(stratum).astype(np.int64)
+    # np.lexsort sorts by the last key first: stratum, then -time, then index.
+    perm = np.lexsort((np.arange(n), -time, stratum)).astype(np.int64)
+    s = stratum[perm]
+    t = time[perm]
+    ev = event[perm]
+    head = np.ones(n, dtype=np.uint8)
+    head[1:] = (s[1:] != s[:-1]).astype(np.uint8)
+    # a tie group continues while the stratum and the time are unchanged
+    new_group = np.ones(n, dtype=bool)
+    new_group[1:] = (s[1:] != s[:-1]) | (t[1:] != t[:-1])
+    starts = np.flatnonzero(new_group)
+    ends = np.append(starts[1:] - 1, n - 1)
+    gid = np.cumsum(new_group) - 1
+    gend = ends[gid].astype(np.int64)
+    dsum = np.add.reduceat(ev.astype(np.int64), starts)
+    dcount = np.zeros(n, dtype=np.int64)
+    dcount[ends] = dsum
+    meta = (head.astype(np.uint32) << np.uint32(31)) | (ev.astype(np.uint32) << np.uint32(30)) \
+        | dcount.astype(np.uint32)
+    return Layout(perm=perm, head=head, event=ev.astype(np.uint8), gend=gend, dcount=dcount,
+                  meta=meta.astype(np.uint32), n_strata=int(head.sum()))
+
+
+def to_canonical(X, layout: Layout) -> np.ndarray:
+    """Rows of X (n, p) permuted to canonical order, column-major."""
+    return np.asfortranarray(np.asarray(X, dtype=np.float64)[layout.perm, :])
+
+
+# ============================================================== scan (Sec. 2.6)
+
+def seg_op(x, y):
+    """(f_i, a_i) (+)s (f_j, a_j) = (f_i | f_j, a_j if f_j else a_i + a_j)."""
+    return (x[0] | y[0], y[1] if y[0] else x[1] + y[1])
+
+
+def segmented_scan(a, flags):
+    """Inclusive segmented scan by folding seg_op left to right (pure Python)."""
+    out = []
+    acc = None
+    for ai, fi in zip(a, flags):
+        cur = (int(fi), ai)
+        acc = cur if acc is None else seg_op(acc, cur)
+        out.append(acc[1])
+    return out
+
+
+def segmented_scan_c(a, flags) -> np.ndarray:
+    """The same scan in the C oracle (FP64)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    b = np.empty_like(a)
+    _c().orc_segscan(a.shape[0], _p(a, ctypes.c_double), _p(f, ctypes.c_uint8), _p(b, ctypes.c_double))
+    return b
+
+
+# ============================================================== definitions (brute force)
+
+def _risk_sets(time, stratum):
+    """For each row i, the boolean mask of R(Y_i) = {r : same stratum, Y_r >= Y_i}."""
+    time = np.asarray(time, dtype=np.float64)
+    n = time.shape[0]
+    stratum = np.zeros(n, dtype=np.int64) if stratum is None else np.asarray(stratum)
+    for i in range(n):
+        yield i, (stratum == stratum[i]) & (time >= time[i])
+
+
+def neg_loglik_brute(X, time, event, stratum, beta) -> float:
+    """-log of Eq. strat_l: -sum_i delta_i [x_i'b - log sum_{r in R(Y_i)} exp(x_r'b)]."""
+    X = np.asarray(X, dtype=np.float64)
+    eta = X @ np.asarray(beta, dtype=np.float64)
+    total = 0.0
+    for i, R in _risk_sets(time, stratum):
+        if event[i]:
+            total -= eta[i] - np.log(np.sum(np.exp(eta[R])))
+    return float(total)
+
+
+def grad_brute(X, time, event, stratum, beta) -> np.ndarray:
+    """Eq. strat_g for every j: -sum_i delta_i x_ij + sum_i delta_i (sum_R x_rj w_r)/(sum_R w_r)."""
+    X = np.asarray(X, dtype=np.float64)
+    eta = X @ np.asarray(beta, dtype=np.float64)
+    g = np.zeros(X.shape[1])
+    for i, R in _risk_sets(time, stratum):
+        if event[i]:
+            w = np.exp(eta[R])
+            g += -X[i] + (w @ X[R]) / w.sum()
+    return g
+
+
+def hess_diag_brute(X, time, event, stratum, beta) -> np.ndarray:
+    """Eq. strat_h for every j: sum_i delta_i [(sum_R x_rj^2 w)/(sum_R w) - ((sum_R x_rj w)/(sum_R w))^2]."""
+    X = np.asarray(X, dtype=np.float64)
+    eta = X @ np.asarray(beta, dtype=np.float64)
+    h = np.zeros(X.shape[1])
+    for i, R in _risk_sets(time, stratum):
+        if event[i]:
+            w = np.exp(eta[R])
+            m1 = (w @ X[R]) / w.sum()
+            m2 = (w @ (X[R] ** 2)) / w.sum()
+            h += m2 - m1 * m1
+    return h
+
+
+def info_brute(X, time, event, stratum, beta) -> np.ndarray:
+    """Full Hessian of -log L: sum_i delta_i [ (sum_R w x x')/(sum_R w) - xbar xbar' ]."""
+    X = np.asarray(X, dtype=np.float64)
+    eta = X @ np.asarray(beta, dtype=np.float64)
+    p = X.shape[1]
+    H = np.zeros((p, p))
+    for i, R in _risk_sets(time, stratum):
+        if event[i]:
+            w = np.exp(eta[R])
+            XR = X[R]
+            xbar = (w @ XR) / w.sum()
+            H += (XR.T * w) @ XR / w.sum() - np.outer(xbar, xbar)
+    return H
+
+
+# ============================================================== scan form (C)
+
+def coord_terms(Xc, layout: Layout, j: int, eta) -> dict:
+    """g'(beta_j), g''(beta_j), objective and second-moment term for column j.
+
+    Xc is the design in canonical order (see to_canonical); eta = Xc @ beta.
+    Follows Eqs. parallel_g / parallel_h with the segmented scans of Sec. 2.6.
+    """
+    xj = np.ascontiguousarray(Xc[:, j], dtype=np.float64)
+    eta = np.ascontiguousarray(eta, dtype=np.float64)
+    out = np.zeros(4)
+    _c().orc_coord_terms(xj.shape[0], _p(xj, ctypes.c_double), _p(eta, ctypes.c_double),
+                         _p(layout.head, ctypes.c_uint8), _p(layout.event, ctypes.c_uint8),
+                         _p(layout.gend, ctypes.c_int64), _p(out, ctypes.c_double))
+    return {"grad": out[0], "hess": out[1], "obj": out[2], "m2": out[3]}
+
+
+def ccd_step(beta_j, g1, g2, m2, gamma, trust):
+    """One CCD coordinate step (Sec. 2.4); returns (step, new trust half-width)."""
+    t = ctypes.c_double(trust)
+    s = _c().orc_ccd_step(beta_j, g1, g2, m2, gamma, ctypes.byref(t))
+    return s, t.value
+
+
+@dataclasses.dataclass
+class FitResult:
+    beta: np.ndarray
+    converged: bool
+    iters: int
+    objective: float
+    last_step: float
+    grad: np.ndarray
+
+
+def _gamma_vec(p, gamma, penalize):
+    g = np.full(p, float(gamma))
+    if penalize is not None:
+        g = np.where(np.asarray(penalize, dtype=bool), g, 0.0)
+    return np.ascontiguousarray(g)
+
+
+def fit_ccd(X, time, event, stratum=None, *, gamma=0.0, penalize=None, beta0=None,
+            tol=1e-12, max_sweeps=1000, layout: Layout | None = None, Xc=None) -> FitResult:
+    """Cyclic coordinate descent of Sec. 2.4 on -log L + sum_j gamma_j |beta_j| (C oracle)."""
+    layout = layout or canonical_layout(time, event, stratum)
+    Xc = to_canonical(X, layout) if Xc is None else Xc
+    n, p = Xc.shape
+    beta = np.zeros(p) if beta0 is None else np.array(beta0, dtype=np.float64)
+    grad = np.zeros(p)
+    info = np.zeros(3)
+    gam = _gamma_vec(p, gamma, penalize)
+    rc = _c().orc_ccd_fit(n, p, _p(Xc, ctypes.c_double), n, _p(layout.head, ctypes.c_uint8),
+                          _p(layout.event, ctypes.c_uint8), _p(layout.gend, ctypes.c_int64),
+                          _p(gam, ctypes.c_double), float(tol), int(max_sweeps),
+                          _p(beta, ctypes.c_double), _p(grad, ctypes.c_double),
+                          _p(info, ctypes.c_double))
+    return FitResult(beta=beta, converged=(rc == 0), iters=int(info[0]), objective=float(info[2]),
+                     last_step=float(info[1]), grad=grad)
+
+
+@dataclasses.dataclass
+class FullEval:
+    objective: float
+    grad: np.ndarray
+    hess_diag: np.ndarray
+    info: np.ndarray | None
+
+
+def full_eval(Xc, layout: Layout, beta, want_info: bool = True) -> FullEval:
+    """Objective, full gradient, diag Hessian and (optionally) the full Hessian at beta.
+
+    gradient  = -X' delta + sum_g d_g S1_g / S0_g                     (Eq. strat_g, all j)
+    diag      = sum_g d_g (S2_g / S0_g - (S1_g / S0_g)^2)              (Eq. strat_h)
+    Hessian   = X' diag(w Lambda) X - sum_g d_g xbar_g xbar_g'         (Eq. strat_h, x x')
+    where g runs over tie groups with d_g events, S*_g are risk-set sums at the
+    group end, xbar_g = S1_g / S0_g and Lambda_r = sum_{g: Y_g <= Y_r} d_g / S0_g
+    (same stratum): sum_g d_g S2_g / S0_g = sum_r w_r Lambda_r x_r x_r'.
+    """
+    Xc = np.asfortranarray(Xc, dtype=np.float64)
+    n, p = Xc.shape
+    beta = np.asarray(beta, dtype=np.float64)
+    eta = np.ascontiguousarray(Xc @ beta)
+    G = int(np.count_nonzero(layout.dcount))
+    S0 = np.zeros(G); S1 = np.zeros((G, p)); S2 = np.zeros((G, p))
+    d = np.zeros(G); m = np.zeros(G); wl = np.zeros(n)
+    g_out = _c().orc_group_sums(n, p, _p(Xc, ctypes.c_double), n, _p(eta, ctypes.c_double),
+                                _p(layout.head, ctypes.c_uint8), _p(layout.event, ctypes.c_uint8),
+                                _p(layout.gend, ctypes.c_int64), _p(S0, ctypes.c_double),
+                                _p(S1, ctypes.c_double), _p(S2, ctypes.c_double),
+                                _p(d, ctypes.c_double), _p(m, ctypes.c_double), _p(wl, ctypes.c_double))
+    assert g_out == G
+    ev = layout.event.astype(np.float64)
+    xbar = S1 / S0[:, None]
+    obj = float(-(ev @ eta) + d @ (np.log(S0) + m))
+    grad = -(Xc.T @ ev) + d @ xbar
+    hdiag = d @ (S2 / S0[:, None] - xbar * xbar)
+    info = None
+    if want_info:
+        info = (Xc.T * wl) @ Xc - (xbar.T * d) @ xbar
+    return FullEval(objective=obj, grad=grad, hess_diag=hdiag, info=info)
+
+
+def degenerate_columns(Xc, layout: Layout, beta=None) -> np.ndarray:
+    """Columns with numerically zero curvature (g'' <= 1e-12 * second-moment term)."""
+    Xc = np.asfortranarray(Xc, dtype=np.float64)
+    n, p = Xc.shape
+    beta = np.zeros(p) if beta is None else np.asarray(beta, dtype=np.float64)
+    eta = Xc @ beta
+    out = np.zeros(p, dtype=bool)
+    for j in range(p):
+        t = coord_terms(Xc, layout, j, eta)
+        out[j] = not (t["hess"] > 1e-12 * abs(t["m2"]))
+    return out
+
+
+def fit_newton(X, time, event, stratum=None, *, beta0=None, tol=1e-14, max_iter=100,
+               layout: Layout | None = None, Xc=None) -> FitResult:
+    """Unpenalised optimum by Newton's method on the full Hessian (numpy Cholesky).
+
+    Degenerate columns (a ones column, which cancels from every ratio in
+    Eq. strat_l) are held at zero.  Step halving guards the first iterations.
+    Stops when max|step| <= tol * max(1, max|beta|).
+    """
+    layout = layout or canonical_layout(time, event, stratum)
+    Xc = to_canonical(X, layout) if Xc is None else Xc
+    n, p = Xc.shape
+    beta = np.zeros(p) if beta0 is None else np.array(beta0, dtype=np.float64)
+    free = ~degenerate_columns(Xc, layout)
+    beta[~free] = 0.0
+    ev = full_eval(Xc, layout, beta)
+    it = 0
+    step_max = np.inf
+    converged = False
+    while it < max_iter:
+        it += 1
+        H = ev.info[np.ix_(free, free)]
+        L = np.linalg.cholesky(H)
+        step = np.zeros(p)
+        step[free] = -np.linalg.solve(L.T, np.linalg.solve(L, ev.grad[free]))
+        t = 1.0
+        while True:
+            cand = full_eval(Xc, layout, beta + t * step)
+            if cand.objective <= ev.objective + 1e-12 * abs(ev.objective) or t < 1e-6:
+                break
+            t *= 0.5
+        beta = beta + t * step
+        ev = cand
+        step_max = float(np.max(np.abs(t * step))) if p else 0.0
+        if step_max <= tol * max(1.0, float(np.max(np.abs(beta)))):
+            converged = True
+            break
+    return FitResult(beta=beta, converged=converged, iters=it, objective=ev.objective,
+                     last_step=step_max, grad=ev.grad)

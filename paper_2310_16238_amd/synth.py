@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs shaped like the stratified-Cox workloads.
+
+This module only *draws* data: designs, true coefficients, strata and the
+(time, event) response.  It holds none of the estimator's arithmetic (no risk
+sets, scans, likelihoods or derivatives), so it can feed both the HIP path and
+the CPU oracle without coupling them.
+
+Response model (Sec. 2.1, proportional hazards within stratum k):
+    T_i ~ Exponential(rate = lambda_k * exp(x_i' beta_true))
+    C_i ~ Exponential(rate = lambda_k)          (independent censoring)
+    Y_i = min(T_i, C_i),  delta_i = 1[T_i <= C_i]
+with lambda_k = exp(u_k), u_k ~ U(-1, 1) (lambda = 1 when K = 1).  The paper
+does not state how its synthetic times were drawn; this is the reading used
+throughout (about half of the rows are events).
+
+Strata (Sec. 3.1 sweeps the number of strata; equal-sized strata as in the
+propensity-score stratification of Sec. 3.2): stratum_i = floor(pi(i) K / N)
+for a seeded permutation pi, so stratum sizes differ by at most one.
+
+Draw order for a seed: X column by column, then beta_true, then the stratum
+permutation and u_k, then T, then C.
+
+Arrays: X is float64 of shape (n, p) in Fortran (column-major) order, so each
+column is contiguous and ``X.ctypes.data`` is a column-major N x P matrix with
+leading dimension n.  time float64[n], event uint8[n], stratum int32[n].
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class CoxData:
+    X: np.ndarray          # (n, p) float64, Fortran order
+    time: np.ndarray       # (n,) float64
+    event: np.ndarray      # (n,) uint8
+    stratum: np.ndarray    # (n,) int32
+    beta_true: np.ndarray  # (p,) float64
+    gamma: float           # l1 strength used for this workload
+    name: str
+
+    @property
+    def n(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def p(self) -> int:
+        return int(self.X.shape[1])
+
+
+# --------------------------------------------------------------------------- designs
+
+def _design_iid_normal(rng, n, p, intercept):
+    X = np.empty((n, p), dtype=np.float64, order="F")
+    start = 0
+    if intercept:
+        X[:, 0] = 1.0
+        start = 1
+    for j in range(start, p):
+        X[:, j] = rng.standard_normal(n)
+    return X
+
+
+def _design_ar1(rng, n, p, rho=0.5):
+    """Columns x_j = rho x_{j-1} + sqrt(1-rho^2) z_j: unit variance, corr rho^|i-j|."""
+    X = np.empty((n, p), dtype=np.float64, order="F")
+    X[:, 0] = rng.standard_normal(n)
+    c = math.sqrt(1.0 - rho * rho)
+    for j in range(1, p):
+        X[:, j] = rho * X[:, j - 1] + c * rng.standard_normal(n)
+    return X
+
+
+def _design_t3(rng, n, p):
+    """iid Student-t(3) scaled to unit variance (variance of t3 is 3)."""
+    X = np.empty((n, p), dtype=np.float64, order="F")
+    s = 1.0 / math.sqrt(3.0)
+    for j in range(p):
+        X[:, j] = rng.standard_t(3, n) * s
+    return X
+
+
+def _design_binary(rng, n, p, density):
+    """Binary indicators with P(x=1) = density (Sec. 3.1 uses 5% ones)."""
+    X = np.empty((n, p), dtype=np.float64, order="F")
+    for j in range(p):
+        X[:, j] = (rng.random(n) < density).astype(np.float64)
+    return X
+
+
+# --------------------------------------------------------------------------- response
+
+def _strata(rng, n, K):
+    perm = rng.permutation(n)
+    stratum = (perm.astype(np.int64) * K // n).astype(np.int32)
+    u = rng.uniform(-1.0, 1.0, size=K) if K > 1 else np.zeros(1)
+    return stratum, np.exp(u)
+
+
+def _linear_predictor(X, beta):
+    # Data generation only: the true hazard multiplier of each row.
+    eta = np.zeros(X.shape[0])
+    for j in np.flatnonzero(beta):
+        eta += X[:, j] * beta[j]
+    return eta
+
+
+def _times(rng, eta, lam_row, tie_round):
+    rate_t = lam_row * np.exp(eta)
+    T = rng.exponential(1.0, size=eta.shape[0]) / rate_t
+    C = rng.exponential(1.0, size=eta.shape[0]) / lam_row
+    event = (T <= C).astype(np.uint8)
+    Y = np.minimum(T, C)
+    if tie_round:
+        # Discretised follow-up (e.g. days): many exact ties in Y.
+        Y = np.floor(Y * tie_round) / tie_round
+    return Y.astype(np.float64), event
+
+
+def make(design: str, n: int, p: int, K: int, seed: int, *, beta=None,
+         beta_kind: str = "normal", beta_sd: float = 0.5, beta_nonzero: float = 1.0,
+         intercept: bool = False, density: float = 0.05, tie_round: float = 0.0,
+         gamma: float = 0.0, name: str = "") -> CoxData:
+    """Draw one workload.  See the module docstring for the model and order."""
+    if n < 1 or p < 1 or K < 1 or K > n:
+        raise ValueError("need n >= 1, p >= 1, 1 <= K <= n")
+    rng = np.random.default_rng(seed)
+    if design == "iid":
+        X = _design_iid_normal(rng, n, p, intercept)
+    elif design == "ar1":
+        X = _design_ar1(rng, n, p)
+    elif design == "t3":
+        X = _design_t3(rng, n, p)
+    elif design == "binary":
+        X = _design_binary(rng, n, p, density)
+    else:
+        raise ValueError(f"unknown design {design!r}")
+    if beta is not None:
+        b = np.asarray(beta, dtype=np.float64).copy()
+    elif beta_kind == "normal":
+        b = rng.normal(0.0, beta_sd, size=p)
+        if beta_nonzero < 1.0:
+            b *= rng.random(p) < beta_nonzero
+    elif beta_kind == "sparse_count":
+        # exactly round(beta_nonzero * p) nonzero N(0, beta_sd^2) entries at seeded positions
+        b = np.zeros(p)
+        nz = rng.choice(p, size=max(1, int(round(beta_nonzero * p))), replace=False)
+        b[nz] = rng.normal(0.0, beta_sd, size=nz.size)
+    else:
+        raise ValueError(f"unknown beta_kind {beta_kind!r}")
+    stratum, lam = _strata(rng, n, K)
+    eta = _linear_predictor(X, b)
+    Y, event = _times(rng, eta, lam[stratum], tie_round)
+    return CoxData(X=X, time=Y, event=event, stratum=stratum, beta_true=b,
+                   gamma=float(gamma), name=name or f"{design}-n{n}-p{p}-K{K}-s{seed}")
+
+
+# --------------------------------------------------------------------------- named workloads
+
+def config_small(n: int = 10_000, K: int = 1, seed: int = 0, ties: bool = False,
+                 gamma: float = math.sqrt(2.0)) -> CoxData:
+    """N=1e4, P=10: a ones column plus 9 iid N(0,1) columns, beta_true=linspace(-1,1,10).
+
+    The l1 strength defaults to sqrt(2), the value Sec. 3.1 fixes for its synthetic fits.
+    """
+    return make("iid", n, 10, K, seed, beta=np.linspace(-1.0, 1.0, 10), intercept=True,
+                tie_round=100.0 if ties else 0.0, gamma=gamma,
+                name=f"small-n{n}-K{K}{'-ties' if ties else ''}")
+
+
+def config_ar1(n: int = 1_000_000, p: int = 50, K: int = 50_000, seed: int = 1,
+               ties: bool = False) -> CoxData:
+    """AR(1) design corr 0.5^|i-j|, beta_true iid N(0, 0.25), default K = N/20."""
+    return make("ar1", n, p, K, seed, beta_kind="normal", beta_sd=0.5,
+                tie_round=100.0 if ties else 0.0, gamma=0.0,
+                name=f"ar1-n{n}-p{p}-K{K}{'-ties' if ties else ''}")
+
+
+def config_paper(n: int = 100_000, p: int = 1000, K: int = 5000, seed: int = 5) -> CoxData:
+    """Sec. 3.1 shape: binary X with 5% ones, beta ~ N(0,1) x Bernoulli(0.2), gamma = sqrt(2)."""
+    return make("binary", n, p, K, seed, beta_kind="normal", beta_sd=1.0, beta_nonzero=0.2,
+                density=0.05, gamma=math.sqrt(2.0), name=f"paper-n{n}-p{p}-K{K}")
