@@ -1,0 +1,179 @@
+/*
+ * coxmi.h -- C ABI of the MI355X (gfx950) stratified Cox library.
+ *
+ * The library fits the stratified Cox proportional-hazards model of Sec. 2.1
+ * (partial likelihood Eq. strat_l, optional l1 penalty sum_j gamma_j |beta_j|)
+ * by cyclic coordinate descent (Sec. 2.4), evaluating each coordinate's
+ * gradient and Hessian (Eqs. strat_g / strat_h) with one segmented scan over
+ * rows sorted by stratum and decreasing time (Secs. 2.6 and 2.7).
+ *
+ * Conventions for every entry point
+ *   - Return value: COX_OK (0) on success, a negative COX_E* code on error,
+ *     COX_NOT_CONVERGED (1) when an iteration limit is hit (outputs are still
+ *     filled).  On error the per-handle message is set (cox_last_error) and
+ *     no output is written unless stated.
+ *   - Matrices are column-major.  beta, gradients and Hessians are indexed by
+ *     the caller's column order; row outputs use the caller's row order unless
+ *     stated (cox_layout reports the canonical order itself).
+ *   - The caller owns every buffer it passes; the library never keeps a
+ *     pointer to a caller buffer after a call returns.  cox_init copies the
+ *     data into device memory owned by the handle; cox_release frees it.
+ *   - A handle is not thread-safe.  Work is issued on the stream given in
+ *     cox_options (NULL = the default stream); calls return after that work
+ *     has finished, so host outputs are ready on return.
+ *   - Ties in time follow the risk-set definition R_k(Y) = {r : Y_kr >= Y}
+ *     literally (Breslow): tied rows are all in each other's risk sets.
+ */
+#ifndef COXMI_H
+#define COXMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define COX_OK 0
+#define COX_NOT_CONVERGED 1
+#define COX_EINVAL (-1)   /* bad argument: sizes, NaN/inf time, event not 0/1, NULL pointer */
+#define COX_ENOMEM (-2)   /* device or host allocation failed */
+#define COX_EDEVICE (-3)  /* HIP runtime error or a device-side synchronisation time-out */
+#define COX_ENUMERIC (-4) /* a risk-set sum left the normal FP64 range (see cox_fit) */
+#define COX_EUNSUPPORTED (-5) /* option or size this build does not support */
+
+/* ---------------------------------------------------------------- options */
+enum { COX_CCD = 0 };                 /* optimiser: cyclic coordinate descent (Sec. 2.4) */
+enum { COX_F64 = 0 };                 /* precision of X on the device */
+enum { COX_BRESLOW = 0 };             /* tie handling (see above) */
+
+typedef struct cox_handle cox_handle; /* opaque; owns all device state of one data set */
+
+typedef struct {
+    int64_t n;               /* rows (observations), >= 1 */
+    int64_t p;               /* columns (covariates), >= 1 */
+    const double *x;         /* host, column-major n x p, leading dimension ldx >= n */
+    int64_t ldx;
+    const double *time;      /* host, n observed times Y (finite) */
+    const uint8_t *event;    /* host, n event indicators delta in {0, 1} */
+    const int32_t *stratum;  /* host, n stratum labels (any int32 values); NULL = one stratum */
+} cox_data;
+
+typedef struct {
+    double gamma;             /* l1 strength gamma >= 0 (Sec. 2.1); 0 = unpenalised */
+    const uint8_t *penalize;  /* host, p flags: 1 = column penalised; NULL = all columns */
+    int mode;                 /* COX_CCD */
+    int x_precision;          /* COX_F64 */
+    int ties;                 /* COX_BRESLOW */
+    double tol;               /* stop after a sweep whose largest |step| <= tol * max(1, max|beta|) */
+    int max_iter;             /* maximum number of CCD sweeps (cycles over all p coordinates) */
+    void *stream;             /* hipStream_t to issue work on; NULL = default stream */
+} cox_options;
+
+typedef struct {
+    int status;               /* return code of the fit */
+    int iters;                /* CCD sweeps performed */
+    int64_t coord_evals;      /* coordinate (g', g'') evaluations performed = iters * p */
+    double objective;         /* -log partial likelihood + penalty, at the start of the last sweep */
+    double kkt_inf;           /* max_j of the l1 KKT residual from the last sweep's gradients */
+    double last_step;         /* largest |step| of the last sweep */
+    int n_pinned;             /* columns skipped as degenerate (g'' numerically 0) in the last sweep */
+} cox_fit_info;
+
+/* Fill *o with defaults: gamma 0, all columns penalised, COX_CCD, COX_F64,
+ * COX_BRESLOW, tol 1e-12, max_iter 1000, default stream. */
+void cox_default_options(cox_options *o);
+
+/*
+ * Create a handle for data set d (Sec. 2.1: rows (Y_ki, delta_ki, x_ki) in K
+ * strata).  Validates the inputs, sorts rows by (stratum ascending, time
+ * descending, original index ascending) (Sec. 2.7), marks stratum heads and
+ * tie groups, copies X into device memory in that order, and precomputes
+ * delta'X_j for every column (first term of Eq. strat_g).
+ *   out : receives the handle (set to NULL on error)
+ *   d   : data; all pointers host memory, read only during the call
+ *   o   : options (NULL = defaults); penalize is copied
+ * Errors: COX_EINVAL (n < 1, p < 1, ldx < n, NULL x/time/event, non-finite
+ * time, event not 0/1), COX_EUNSUPPORTED (n or p beyond this build's
+ * resident limits), COX_ENOMEM, COX_EDEVICE.  On error *out is NULL and the
+ * message is available through cox_last_error(NULL).
+ */
+int cox_init(cox_handle **out, const cox_data *d, const cox_options *o);
+
+/*
+ * Fit beta by cyclic coordinate descent (Sec. 2.4): for j = 0..p-1 in turn,
+ * evaluate g'(beta_j) and g''(beta_j) by segmented scan (Eqs. parallel_g,
+ * parallel_h), take the Newton step -g'/g'' (Eq. newton) with the l1
+ * directional-derivative rule and the trust-region limit, and update
+ * X beta incrementally (Eq. parallel_xb).  The whole fit runs in one
+ * persistent kernel; only the final result crosses to the host.
+ *   beta0    : host, p start values (NULL = zeros)
+ *   beta_out : host, p entries, receives the estimate
+ *   info     : host, optional (may be NULL)
+ * Degenerate columns (g'' <= 1e-12 * delta'(S[N2]/S[D])) are not moved.
+ * Returns COX_OK, COX_NOT_CONVERGED (max_iter sweeps done; beta_out filled),
+ * COX_ENUMERIC (an event's risk-set sum under- or overflowed FP64 after the
+ * global shift of X beta), COX_EDEVICE.
+ */
+int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *info);
+
+/*
+ * Evaluate at beta (host, p): the negative log partial likelihood of
+ * Eq. strat_l plus the l1 penalty (objective, may be NULL), the gradient of
+ * the unpenalised part (Eq. strat_g, grad: host p, may be NULL) and the
+ * diagonal of its Hessian (Eq. strat_h, hess_diag: host p, may be NULL).
+ * Each column is one segmented-scan evaluation, as inside a CCD sweep but
+ * without moving beta.
+ */
+int cox_evaluate(cox_handle *h, const double *beta, double *objective, double *grad,
+                 double *hess_diag);
+
+/*
+ * The quantities one CCD coordinate step uses, for column j at beta (host, p):
+ *   out[0] = g'(beta_j)   (Eq. strat_g / parallel_g)
+ *   out[1] = g''(beta_j)  (Eq. strat_h / parallel_h)
+ *   out[2] = -log partial likelihood at beta (Eq. strat_l, no penalty)
+ *   out[3] = delta'(S[N2]/S[D])  (scale used for the degeneracy test)
+ * out: host, 4 doubles.  COX_EINVAL if j is out of range.
+ */
+int cox_coordinate(cox_handle *h, const double *beta, int64_t j, double *out);
+
+/*
+ * Canonical order chosen by cox_init (Sec. 2.7).  perm (host, n, may be NULL)
+ * receives the original row index of each canonical row; meta (host, n, may
+ * be NULL) the packed row word: bit 31 = first row of its stratum (head flag),
+ * bit 30 = event, bits 0..29 = number of events in the row's tie group if the
+ * row is the last of that group, else 0.  Padding rows are not reported.
+ */
+int cox_layout(const cox_handle *h, int64_t *perm, uint32_t *meta);
+
+/* Duration in milliseconds of the last persistent-kernel launch on h, from
+ * HIP events recorded on the handle's stream immediately around the launch. */
+int cox_last_kernel_ms(const cox_handle *h, double *ms);
+
+/* Number of rows and columns of the handle; the device row stride (>= n). */
+int cox_shape(const cox_handle *h, int64_t *n, int64_t *p, int64_t *ld);
+
+/*
+ * Segmented inclusive scan of Sec. 2.6 with + on FP64, on device memory:
+ * b[i] = a[i] if head[i] != 0 (or i == 0), else b[i-1] + a[i].
+ *   a, head, b : device pointers to n doubles, n bytes, n doubles (b may not alias a)
+ *   n          : 0 <= n <= 2^31 - 1 (n = 0 is a no-op)
+ *   stream     : hipStream_t or NULL; the call waits for completion.
+ * Uses the same device scan as the Cox kernels.  No handle; errors are
+ * returned as codes only.
+ */
+int cox_segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, void *stream);
+
+/* Free the handle and all device memory it owns.  NULL is a no-op. */
+void cox_release(cox_handle *h);
+
+/* Message for the last error on h (NULL: the last cox_init failure of this thread). */
+const char *cox_last_error(const cox_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COXMI_H */

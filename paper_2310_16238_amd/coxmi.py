@@ -1,0 +1,249 @@
+"""ctypes binding of libcoxmi.so, the C ABI declared in include/coxmi.h.
+
+Argument marshalling only: every step of the path runs in the HIP library.
+Function names match the C entry points.  Errors raise CoxError carrying the
+status code and the library's message.  If the library has not been built the
+first call raises RuntimeError; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+COX_OK = 0
+COX_NOT_CONVERGED = 1
+COX_EINVAL = -1
+COX_ENOMEM = -2
+COX_EDEVICE = -3
+COX_ENUMERIC = -4
+COX_EUNSUPPORTED = -5
+
+COX_CCD = 0
+COX_F64 = 0
+COX_BRESLOW = 0
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcoxmi.so")
+
+
+class CoxError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"[{code}] {message}")
+        self.code = code
+        self.message = message
+
+
+class cox_data(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("x", ctypes.POINTER(ctypes.c_double)), ("ldx", ctypes.c_int64),
+                ("time", ctypes.POINTER(ctypes.c_double)),
+                ("event", ctypes.POINTER(ctypes.c_uint8)),
+                ("stratum", ctypes.POINTER(ctypes.c_int32))]
+
+
+class cox_options(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("penalize", ctypes.POINTER(ctypes.c_uint8)),
+                ("mode", ctypes.c_int), ("x_precision", ctypes.c_int), ("ties", ctypes.c_int),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class cox_fit_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("coord_evals", ctypes.c_int64),
+                ("objective", ctypes.c_double), ("kkt_inf", ctypes.c_double),
+                ("last_step", ctypes.c_double), ("n_pinned", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# (name, restype, argtypes) of every entry point in include/coxmi.h
+_VP = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = [
+    ("cox_default_options", None, [ctypes.POINTER(cox_options)]),
+    ("cox_init", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(cox_data), ctypes.POINTER(cox_options)]),
+    ("cox_fit", ctypes.c_int, [_VP, _DP, _DP, ctypes.POINTER(cox_fit_info)]),
+    ("cox_evaluate", ctypes.c_int, [_VP, _DP, _DP, _DP, _DP]),
+    ("cox_coordinate", ctypes.c_int, [_VP, _DP, ctypes.c_int64, _DP]),
+    ("cox_layout", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32)]),
+    ("cox_last_kernel_ms", ctypes.c_int, [_VP, _DP]),
+    ("cox_shape", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64)]),
+    ("cox_segscan_f64", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
+    ("cox_release", None, [_VP]),
+    ("cox_last_error", ctypes.c_char_p, [_VP]),
+]
+
+
+def lib():
+    """Load libcoxmi.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _check(h, rc, ok=(COX_OK,)):
+    if rc not in ok:
+        msg = lib().cox_last_error(h)
+        raise CoxError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def cox_default_options() -> cox_options:
+    o = cox_options()
+    lib().cox_default_options(ctypes.byref(o))
+    return o
+
+
+def cox_init(X, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-12, max_iter=1000,
+             stream=None):
+    """Create a handle.  X: (n, p) float64 (any order), time float64[n], event 0/1[n],
+    stratum int32[n] or None.  Returns an opaque handle (int)."""
+    X = np.asfortranarray(X, dtype=np.float64)
+    n, p = X.shape
+    time = np.ascontiguousarray(time, dtype=np.float64)
+    event = np.ascontiguousarray(event, dtype=np.uint8)
+    d = cox_data(n=n, p=p, x=_dptr(X), ldx=n, time=_dptr(time),
+                 event=event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    keep = [X, time, event]
+    if stratum is not None:
+        st = np.ascontiguousarray(stratum, dtype=np.int32)
+        keep.append(st)
+        d.stratum = st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    o = cox_default_options()
+    o.gamma = float(gamma)
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    if penalize is not None:
+        pen = np.ascontiguousarray(penalize, dtype=np.uint8)
+        keep.append(pen)
+        o.penalize = pen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    if stream is not None:
+        o.stream = ctypes.c_void_p(int(stream))
+    h = ctypes.c_void_p()
+    rc = lib().cox_init(ctypes.byref(h), ctypes.byref(d), ctypes.byref(o))
+    _check(None, rc)
+    return h.value
+
+
+def cox_fit(h, beta0=None, p=None):
+    """Returns (beta, info_dict).  Raises CoxError unless the status is OK or NOT_CONVERGED."""
+    n_, p_, _ = cox_shape(h)
+    beta = np.zeros(p_)
+    b0 = None if beta0 is None else np.ascontiguousarray(beta0, dtype=np.float64)
+    info = cox_fit_info()
+    rc = lib().cox_fit(h, None if b0 is None else _dptr(b0), _dptr(beta), ctypes.byref(info))
+    _check(h, rc, ok=(COX_OK, COX_NOT_CONVERGED))
+    return beta, info.as_dict()
+
+
+def cox_evaluate(h, beta):
+    """Returns (objective, grad[p], hess_diag[p])."""
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    g = np.zeros(b.shape[0])
+    hd = np.zeros(b.shape[0])
+    obj = ctypes.c_double()
+    _check(h, lib().cox_evaluate(h, _dptr(b), ctypes.byref(obj), _dptr(g), _dptr(hd)))
+    return obj.value, g, hd
+
+
+def cox_coordinate(h, beta, j):
+    """Returns [g', g'', -log L, delta'(S[N2]/S[D])] for column j at beta."""
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    out = np.zeros(4)
+    _check(h, lib().cox_coordinate(h, _dptr(b), int(j), _dptr(out)))
+    return out
+
+
+def cox_layout(h):
+    n, _, _ = cox_shape(h)
+    perm = np.zeros(n, dtype=np.int64)
+    meta = np.zeros(n, dtype=np.uint32)
+    _check(h, lib().cox_layout(h, perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               meta.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return perm, meta
+
+
+def cox_shape(h):
+    n, p, ld = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(h, lib().cox_shape(h, ctypes.byref(n), ctypes.byref(p), ctypes.byref(ld)))
+    return n.value, p.value, ld.value
+
+
+def cox_last_kernel_ms(h) -> float:
+    ms = ctypes.c_double()
+    _check(h, lib().cox_last_kernel_ms(h, ctypes.byref(ms)))
+    return ms.value
+
+
+def cox_segscan_f64(a_ptr: int, head_ptr: int, b_ptr: int, n: int, stream=None) -> int:
+    """Device-pointer segmented scan; returns the status code (raises on error)."""
+    rc = lib().cox_segscan_f64(ctypes.c_void_p(a_ptr), ctypes.c_void_p(head_ptr), ctypes.c_void_p(b_ptr),
+                               int(n), None if stream is None else ctypes.c_void_p(int(stream)))
+    if rc != COX_OK:
+        raise CoxError(rc, "cox_segscan_f64 failed")
+    return rc
+
+
+def cox_release(h) -> None:
+    if h:
+        lib().cox_release(h)
+
+
+def cox_last_error(h=None) -> str:
+    m = lib().cox_last_error(h)
+    return m.decode() if m else ""
+
+
+class CoxModel:
+    """Owns one handle; a thin convenience over the functions above."""
+
+    def __init__(self, X, time, event, stratum=None, **opts):
+        self.h = cox_init(X, time, event, stratum, **opts)
+
+    def fit(self, beta0=None):
+        return cox_fit(self.h, beta0)
+
+    def evaluate(self, beta):
+        return cox_evaluate(self.h, beta)
+
+    def coordinate(self, beta, j):
+        return cox_coordinate(self.h, beta, j)
+
+    def layout(self):
+        return cox_layout(self.h)
+
+    def kernel_ms(self):
+        return cox_last_kernel_ms(self.h)
+
+    def close(self):
+        if self.h:
+            cox_release(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,373 @@
+// coxmi.cpp -- C ABI of the stratified Cox library (declared in include/coxmi.h).
+//
+// Host-side work is limited to what is done once per data set: input checks,
+// the canonical row order of Sec. 2.7 (integer work, exact), tie groups, and
+// copying X into device memory in that order.  Everything per iteration runs
+// in the persistent kernel (ccd_kernel.hip).
+#include "coxmi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace coxmi;
+
+struct cox_handle {
+    int64_t n = 0, p = 0;
+    int device = 0;
+    LaunchShape shape;
+    hipStream_t stream = nullptr;
+    double *d_x = nullptr;
+    uint32_t *d_meta = nullptr;
+    double *d_vec = nullptr;       // q, gamma, beta, g1, g2, m2 (p each), result (8)
+    void *d_sync = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float last_kernel_ms = 0.0f;
+    std::vector<int64_t> perm;
+    std::vector<uint32_t> meta;
+    std::vector<double> gamma;
+    cox_options opt{};
+    std::string err;
+
+    double *q() const { return d_vec; }
+    double *gam() const { return d_vec + p; }
+    double *beta() const { return d_vec + 2 * p; }
+    double *g1() const { return d_vec + 3 * p; }
+    double *g2() const { return d_vec + 4 * p; }
+    double *m2() const { return d_vec + 5 * p; }
+    double *result() const { return d_vec + 6 * p; }
+};
+
+static thread_local std::string g_init_error;
+
+static int fail(cox_handle *h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    else g_init_error = msg;
+    return code;
+}
+
+static int hip_fail(cox_handle *h, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(h, e == hipErrorOutOfMemory ? COX_ENOMEM : COX_EDEVICE, m);
+}
+
+extern "C" void cox_default_options(cox_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->gamma = 0.0;
+    o->penalize = nullptr;
+    o->mode = COX_CCD;
+    o->x_precision = COX_F64;
+    o->ties = COX_BRESLOW;
+    o->tol = 1e-12;
+    o->max_iter = 1000;
+    o->stream = nullptr;
+}
+
+static void free_device(cox_handle *h)
+{
+    if (h->d_x) (void)hipFree(h->d_x);
+    if (h->d_meta) (void)hipFree(h->d_meta);
+    if (h->d_vec) (void)hipFree(h->d_vec);
+    if (h->d_sync) (void)hipFree(h->d_sync);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    h->d_x = nullptr;
+    h->d_meta = nullptr;
+    h->d_vec = nullptr;
+    h->d_sync = nullptr;
+    h->ev0 = h->ev1 = nullptr;
+}
+
+extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *o)
+{
+    if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(nullptr, COX_EINVAL, "data is NULL");
+    const int64_t n = d->n, p = d->p;
+    if (n < 1 || p < 1) return fail(nullptr, COX_EINVAL, "need n >= 1 and p >= 1");
+    if (d->ldx < n) return fail(nullptr, COX_EINVAL, "ldx < n");
+    if (!d->x || !d->time || !d->event) return fail(nullptr, COX_EINVAL, "x, time and event are required");
+    if (n > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "n exceeds 2^30 - 1");
+    if (p > 4096) return fail(nullptr, COX_EUNSUPPORTED, "p > 4096 is not supported by the resident kernel");
+    cox_options opt;
+    if (o) opt = *o;
+    else cox_default_options(&opt);
+    if (opt.mode != COX_CCD) return fail(nullptr, COX_EUNSUPPORTED, "only COX_CCD is available");
+    if (opt.x_precision != COX_F64) return fail(nullptr, COX_EUNSUPPORTED, "only COX_F64 is available");
+    if (opt.ties != COX_BRESLOW) return fail(nullptr, COX_EUNSUPPORTED, "only COX_BRESLOW ties");
+    if (!(opt.gamma >= 0.0) || !std::isfinite(opt.gamma)) return fail(nullptr, COX_EINVAL, "gamma must be finite and >= 0");
+    if (!(opt.tol >= 0.0)) return fail(nullptr, COX_EINVAL, "tol must be >= 0");
+    if (opt.max_iter < 1) return fail(nullptr, COX_EINVAL, "max_iter must be >= 1");
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(d->time[i])) return fail(nullptr, COX_EINVAL, "time contains NaN or inf");
+        if (d->event[i] > 1) return fail(nullptr, COX_EINVAL, "event must be 0 or 1");
+    }
+
+    cox_handle *h = new cox_handle();
+    h->n = n;
+    h->p = p;
+    h->opt = opt;
+    h->opt.penalize = nullptr;
+    h->stream = static_cast<hipStream_t>(opt.stream);
+    (void)hipGetDevice(&h->device);
+    std::string err;
+    int rc = choose_shape(n, (int)p, h->shape, err);
+    if (rc != 0) {
+        delete h;
+        return fail(nullptr, rc == -5 ? COX_EUNSUPPORTED : COX_EDEVICE, err);
+    }
+    const int64_t ld = h->shape.ld;
+
+    // canonical order: stratum ascending, time descending, original index ascending
+    const double *tm = d->time;
+    const int32_t *st = d->stratum;
+    h->perm.resize(n);
+    std::iota(h->perm.begin(), h->perm.end(), int64_t(0));
+    std::sort(h->perm.begin(), h->perm.end(), [tm, st](int64_t a, int64_t b) {
+        const int32_t sa = st ? st[a] : 0, sb = st ? st[b] : 0;
+        if (sa != sb) return sa < sb;
+        if (tm[a] != tm[b]) return tm[a] > tm[b];
+        return a < b;
+    });
+    // head flags, events and tie-group counts on the group's last row
+    h->meta.assign(n, 0u);
+    int64_t gstart = 0;
+    uint32_t gcount = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t r = h->perm[i];
+        const bool new_stratum = (i == 0) || (st && st[r] != st[h->perm[i - 1]]);
+        const bool new_group = new_stratum || tm[r] != tm[h->perm[i - 1]];
+        if (new_group) {
+            gstart = i;
+            gcount = 0;
+        }
+        (void)gstart;
+        if (new_stratum) h->meta[i] |= kHeadBit;
+        if (d->event[r]) {
+            h->meta[i] |= kEventBit;
+            ++gcount;
+        }
+        const bool last_of_group = (i + 1 == n) ||
+            (st && st[h->perm[i + 1]] != st[r]) || tm[h->perm[i + 1]] != tm[r];
+        if (last_of_group) h->meta[i] |= gcount;
+    }
+
+    h->gamma.assign(p, opt.gamma);
+    if (o && o->penalize)
+        for (int64_t j = 0; j < p; ++j) h->gamma[j] = o->penalize[j] ? opt.gamma : 0.0;
+
+    hipError_t e;
+    if ((e = hipMalloc(&h->d_x, sizeof(double) * (size_t)ld * p)) != hipSuccess ||
+        (e = hipMalloc(&h->d_meta, sizeof(uint32_t) * (size_t)ld)) != hipSuccess ||
+        (e = hipMalloc(&h->d_vec, sizeof(double) * (size_t)(6 * p + kResultSlots))) != hipSuccess ||
+        (e = hipMalloc(&h->d_sync, sync_scratch_bytes(h->shape.grid))) != hipSuccess) {
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "device allocation");
+    }
+    // row words, padding rows are single-row strata without events
+    {
+        std::vector<uint32_t> mpad(ld, kHeadBit);
+        std::copy(h->meta.begin(), h->meta.end(), mpad.begin());
+        e = hipMemcpy(h->d_meta, mpad.data(), sizeof(uint32_t) * ld, hipMemcpyHostToDevice);
+    }
+    // X in canonical order, column by column, and q_j = delta'X_j
+    std::vector<double> col(ld, 0.0), q(p, 0.0);
+    for (int64_t j = 0; j < p && e == hipSuccess; ++j) {
+        const double *xj = d->x + j * d->ldx;
+        double qj = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t r = h->perm[i];
+            col[i] = xj[r];
+            if (d->event[r]) qj += col[i];
+        }
+        q[j] = qj;
+        e = hipMemcpy(h->d_x + j * ld, col.data(), sizeof(double) * ld, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemcpy(h->q(), q.data(), sizeof(double) * p, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->gam(), h->gamma.data(), sizeof(double) * p, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev1);
+    if (e != hipSuccess) {
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "device upload");
+    }
+    *out = h;
+    return COX_OK;
+}
+
+// Run the persistent kernel in `mode` over columns [j0, j1) starting from beta (host, p).
+static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *beta_host, double *result)
+{
+    (void)hipSetDevice(h->device);
+    hipError_t e;
+    if (beta_host) e = hipMemcpyAsync(h->beta(), beta_host, sizeof(double) * h->p, hipMemcpyHostToDevice, h->stream);
+    else e = hipMemsetAsync(h->beta(), 0, sizeof(double) * h->p, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->result(), 0, sizeof(double) * kResultSlots, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "staging beta");
+    CcdLaunch L;
+    L.x = h->d_x;
+    L.meta = h->d_meta;
+    L.q = h->q();
+    L.gamma = h->gam();
+    L.n = h->n;
+    L.p = (int)h->p;
+    L.mode = mode;
+    L.j0 = j0;
+    L.j1 = j1;
+    L.max_sweeps = h->opt.max_iter;
+    L.tol = h->opt.tol;
+    L.beta = h->beta();
+    L.g1 = h->g1();
+    L.g2 = h->g2();
+    L.m2 = h->m2();
+    L.result = h->result();
+    carve_sync_scratch(h->d_sync, h->shape.grid, L);
+    int rc = launch_ccd(h->shape, L, h->stream, h->ev0, h->ev1);
+    if (rc != (int)hipSuccess) return hip_fail(h, (hipError_t)rc, "kernel launch");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "kernel execution");
+    (void)hipEventElapsedTime(&h->last_kernel_ms, h->ev0, h->ev1);
+    uint32_t ctl[2] = {0, 0};
+    if ((e = hipMemcpy(ctl, L.ctl, sizeof(ctl), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(h, e, "reading control words");
+    if ((e = hipMemcpy(result, h->result(), sizeof(double) * kResultSlots, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(h, e, "reading results");
+    if (ctl[0] != 0u || result[kResCompleted] != 1.0)
+        return fail(h, COX_EDEVICE, "device-side synchronisation timed out; results are not valid");
+    if (result[kResNumeric] != 0.0)
+        return fail(h, COX_ENUMERIC, "a risk-set sum left the FP64 normal range after the global shift");
+    return COX_OK;
+}
+
+extern "C" int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *info)
+{
+    if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (!beta_out) return fail(h, COX_EINVAL, "beta_out is NULL");
+    if (beta0)
+        for (int64_t j = 0; j < h->p; ++j)
+            if (!std::isfinite(beta0[j])) return fail(h, COX_EINVAL, "beta0 is not finite");
+    double res[kResultSlots];
+    int rc = run_kernel(h, kModeFit, 0, (int)h->p, beta0, res);
+    if (rc != COX_OK && rc != COX_ENUMERIC) return rc;
+    hipError_t e = hipMemcpy(beta_out, h->beta(), sizeof(double) * h->p, hipMemcpyDeviceToHost);
+    std::vector<double> g(h->p);
+    if (e == hipSuccess) e = hipMemcpy(g.data(), h->g1(), sizeof(double) * h->p, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "reading beta");
+    const bool converged = res[kResConverged] == 1.0;
+    if (rc == COX_OK && !converged) rc = COX_NOT_CONVERGED;
+    if (info) {
+        info->status = rc;
+        info->iters = (int)res[kResSweeps];
+        info->coord_evals = (int64_t)res[kResSweeps] * h->p;
+        info->objective = res[kResObjective];
+        info->last_step = res[kResLastStep];
+        info->n_pinned = (int)res[kResPinned];
+        double kkt = 0.0;
+        for (int64_t j = 0; j < h->p; ++j) {
+            const double gj = g[j], gm = h->gamma[j], b = beta_out[j];
+            double r;
+            if (gm <= 0.0) r = std::fabs(gj);
+            else if (b != 0.0) r = std::fabs(gj + (b > 0 ? gm : -gm));
+            else r = std::max(std::fabs(gj) - gm, 0.0);
+            kkt = std::max(kkt, r);
+        }
+        info->kkt_inf = kkt;
+    }
+    return rc;
+}
+
+extern "C" int cox_evaluate(cox_handle *h, const double *beta, double *objective, double *grad,
+                            double *hess_diag)
+{
+    if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (!beta) return fail(h, COX_EINVAL, "beta is NULL");
+    double res[kResultSlots];
+    int rc = run_kernel(h, kModeEval, 0, (int)h->p, beta, res);
+    if (rc != COX_OK) return rc;
+    hipError_t e = hipSuccess;
+    if (grad) e = hipMemcpy(grad, h->g1(), sizeof(double) * h->p, hipMemcpyDeviceToHost);
+    if (hess_diag && e == hipSuccess) e = hipMemcpy(hess_diag, h->g2(), sizeof(double) * h->p, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "reading gradient");
+    if (objective) {
+        double pen = 0.0;
+        for (int64_t j = 0; j < h->p; ++j) pen += h->gamma[j] * std::fabs(beta[j]);
+        *objective = res[kResObjective] + pen;
+    }
+    return COX_OK;
+}
+
+extern "C" int cox_coordinate(cox_handle *h, const double *beta, int64_t j, double *out)
+{
+    if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (!beta || !out) return fail(h, COX_EINVAL, "beta and out are required");
+    if (j < 0 || j >= h->p) return fail(h, COX_EINVAL, "column index out of range");
+    double res[kResultSlots];
+    int rc = run_kernel(h, kModeEval, (int)j, (int)j + 1, beta, res);
+    if (rc != COX_OK) return rc;
+    double v[3];
+    hipError_t e = hipMemcpy(&v[0], h->g1() + j, sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&v[1], h->g2() + j, sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&v[2], h->m2() + j, sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "reading coordinate");
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = res[kResObjective];
+    out[3] = v[2];
+    return COX_OK;
+}
+
+extern "C" int cox_layout(const cox_handle *h, int64_t *perm, uint32_t *meta)
+{
+    if (!h) return COX_EINVAL;
+    if (perm) std::memcpy(perm, h->perm.data(), sizeof(int64_t) * h->n);
+    if (meta) std::memcpy(meta, h->meta.data(), sizeof(uint32_t) * h->n);
+    return COX_OK;
+}
+
+extern "C" int cox_shape(const cox_handle *h, int64_t *n, int64_t *p, int64_t *ld)
+{
+    if (!h) return COX_EINVAL;
+    if (n) *n = h->n;
+    if (p) *p = h->p;
+    if (ld) *ld = h->shape.ld;
+    return COX_OK;
+}
+
+extern "C" int cox_last_kernel_ms(const cox_handle *h, double *ms)
+{
+    if (!h || !ms) return COX_EINVAL;
+    *ms = h->last_kernel_ms;
+    return COX_OK;
+}
+
+extern "C" int cox_segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, void *stream)
+{
+    if (n > 0x7fffffffLL) return COX_EUNSUPPORTED;
+    return segscan_f64(a, head, b, n, static_cast<hipStream_t>(stream));
+}
+
+extern "C" void cox_release(cox_handle *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    free_device(h);
+    delete h;
+}
+
+extern "C" const char *cox_last_error(const cox_handle *h)
+{
+    return h ? h->err.c_str() : g_init_error.c_str();
+}

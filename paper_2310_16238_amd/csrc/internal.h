@@ -1,0 +1,76 @@
+// internal.h -- interface between the C ABI (coxmi.cpp) and the kernels (ccd_kernel.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace coxmi {
+
+// Row word in canonical order (see cox_layout in include/coxmi.h).
+constexpr uint32_t kHeadBit = 0x80000000u;
+constexpr uint32_t kEventBit = 0x40000000u;
+constexpr uint32_t kCountMask = 0x3fffffffu;
+
+constexpr int kThreads = 512;           // threads per workgroup of the CCD kernel
+constexpr int kPartialDoubles = 6;      // per-workgroup partial record (see ccd_kernel.hip)
+
+enum KernelMode { kModeFit = 0, kModeEval = 1 };
+
+// Resident launch shape of a data set: `grid` workgroups of kThreads threads,
+// each thread owning `ipt` consecutive rows; ld = grid * kThreads * ipt rows.
+struct LaunchShape {
+    int ipt = 0;
+    int grid = 0;
+    int64_t ld = 0;
+};
+
+// Arguments of one persistent launch (device pointers unless noted).
+struct CcdLaunch {
+    const double *x = nullptr;       // [p][ld] canonical rows, padding rows zero
+    const uint32_t *meta = nullptr;  // [ld]
+    const double *q = nullptr;       // [p] delta' X_j
+    const double *gamma = nullptr;   // [p] l1 weights
+    int64_t n = 0;                   // real rows (rows n..ld-1 are padding)
+    int p = 0;
+    int mode = kModeFit;
+    int j0 = 0, j1 = 0;              // evaluation: columns [j0, j1)
+    int max_sweeps = 0;
+    double tol = 0.0;
+    double *beta = nullptr;          // [p] in: start point; out (fit): estimate
+    double *g1 = nullptr;            // [p] g' of each coordinate's last evaluation
+    double *g2 = nullptr;            // [p] g''
+    double *m2 = nullptr;            // [p] delta'(S[N2]/S[D])
+    double *result = nullptr;        // [8] see ccd_kernel.hip
+    void *agg = nullptr;             // [grid] tile aggregates
+    uint32_t *stat1 = nullptr;       // [grid]
+    double *part = nullptr;          // [2][grid][kPartialDoubles]
+    uint32_t *stat2 = nullptr;       // [2][grid]
+    void *ctl = nullptr;             // control words
+};
+
+// Bytes of the per-launch synchronisation scratch for `grid` workgroups.
+size_t sync_scratch_bytes(int grid);
+// Carve the scratch block into the CcdLaunch fields (agg, stat1, part, stat2, ctl).
+void carve_sync_scratch(void *base, int grid, CcdLaunch &L);
+
+// Pick ipt and grid for n rows on the current device (one workgroup per CU at most).
+int choose_shape(int64_t n, int p, LaunchShape &shape, std::string &err);
+
+// Launch the persistent CCD / evaluation kernel; returns a hipError_t value.
+// Zeroes the synchronisation words first; records ev0/ev1 around the kernel if non-null.
+int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream,
+               hipEvent_t ev0, hipEvent_t ev1);
+
+// Segmented +scan of n doubles on device memory; returns a COX_* code.
+int segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, hipStream_t stream);
+
+// Result slots written by the persistent kernel.
+enum ResultSlot {
+    kResSweeps = 0, kResLastStep = 1, kResObjective = 2, kResPinned = 3,
+    kResConverged = 4, kResNumeric = 5, kResCompleted = 6
+};
+constexpr int kResultSlots = 8;
+
+}  // namespace coxmi

@@ -1,0 +1,94 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol that
+include/coxmi.h declares, and rejects bad inputs before touching a device."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_16238_amd import coxmi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "coxmi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\**\s*(cox_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared()
+    for must in ["cox_init", "cox_fit", "cox_evaluate", "cox_release", "cox_coordinate",
+                 "cox_layout", "cox_segscan_f64", "cox_last_error", "cox_default_options"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(coxmi.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    bound = {name for name, _, _ in coxmi.SIGNATURES}
+    assert bound == set(_declared())
+
+
+def test_default_options():
+    o = coxmi.cox_default_options()
+    assert o.gamma == 0.0 and o.tol == 1e-12 and o.max_iter == 1000
+    assert o.mode == coxmi.COX_CCD and o.x_precision == coxmi.COX_F64 and o.ties == coxmi.COX_BRESLOW
+
+
+def _data(n=20, p=3):
+    rng = np.random.default_rng(0)
+    return rng.standard_normal((n, p)), rng.exponential(1.0, n), (rng.random(n) < 0.5).astype(np.uint8)
+
+
+@pytest.mark.parametrize("case", ["nan_time", "inf_time", "event2", "gamma_neg", "tol_neg", "maxit0"])
+def test_init_rejects_bad_inputs(case):
+    X, t, e = _data()
+    kw = {}
+    if case == "nan_time":
+        t[3] = math.nan
+    elif case == "inf_time":
+        t[0] = math.inf
+    elif case == "event2":
+        e[5] = 2
+    elif case == "gamma_neg":
+        kw["gamma"] = -1.0
+    elif case == "tol_neg":
+        kw["tol"] = -1e-3
+    elif case == "maxit0":
+        kw["max_iter"] = 0
+    with pytest.raises(coxmi.CoxError) as ei:
+        coxmi.cox_init(X, t, e, **kw)
+    assert ei.value.code == coxmi.COX_EINVAL
+    assert coxmi.cox_last_error(None)
+
+
+def test_init_rejects_bad_shapes():
+    lib = coxmi.lib()
+    X, t, e = _data()
+    dp = ctypes.POINTER(ctypes.c_double)
+    Xf = np.asfortranarray(X)
+    base = dict(x=Xf.ctypes.data_as(dp), time=t.ctypes.data_as(dp),
+                event=e.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    h = ctypes.c_void_p()
+    for n, p, ldx in [(0, 3, 20), (20, 0, 20), (20, 3, 19)]:
+        d = coxmi.cox_data(n=n, p=p, ldx=ldx, **base)
+        assert lib.cox_init(ctypes.byref(h), ctypes.byref(d), None) == coxmi.COX_EINVAL
+        assert not h.value
+    d = coxmi.cox_data(n=20, p=3, ldx=20, time=base["time"], event=base["event"])
+    assert lib.cox_init(ctypes.byref(h), ctypes.byref(d), None) == coxmi.COX_EINVAL
+    assert lib.cox_init(None, ctypes.byref(d), None) == coxmi.COX_EINVAL
+
+
+def test_null_handle_calls_are_errors():
+    lib = coxmi.lib()
+    b = np.zeros(3)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.cox_fit(None, None, b.ctypes.data_as(dp), None) == coxmi.COX_EINVAL
+    assert lib.cox_evaluate(None, b.ctypes.data_as(dp), None, None, None) == coxmi.COX_EINVAL
+    assert lib.cox_layout(None, None, None) == coxmi.COX_EINVAL
+    lib.cox_release(None)
