@@ -143,7 +143,7 @@ int cox_coordinate(cox_handle *h, const double *beta, int64_t j, double *out);
  * Canonical order chosen by cox_init (Sec. 2.7).  perm (host, n, may be NULL)
  * receives the original row index of each canonical row; meta (host, n, may
  * be NULL) the packed row word: bit 31 = first row of its stratum (head flag),
- * bit 30 = event, bits 0..29 = number of events in the row's tie group if the
+ * bit 30 = event, bits 0..28 = number of events in the row's tie group if the
  * row is the last of that group, else 0.  Padding rows are not reported.
  */
 int cox_layout(const cox_handle *h, int64_t *perm, uint32_t *meta);

@@ -9,7 +9,7 @@
 //   X beta += X_j * step                                        (Eq. parallel_xb)
 // Ties: an event reads the scans at the last row of its tie group; the row
 // word carries d = number of events of the group on that row, so the
-// reductions are sum over group ends of d * (...).
+// reductions are sums over group ends of d * (...).
 //
 // How it maps onto the MI355X (our design, not the paper's):
 //   * One persistent cooperative launch runs the whole fit.  Workgroup b of
@@ -17,15 +17,16 @@
 //     its IPT rows of X beta and of the row word in registers for the whole
 //     fit, so a coordinate reads only x_j from HBM (8 B/row).  x_{j+1} is
 //     loaded while coordinate j synchronises.
-//   * Rows inside a workgroup: thread fold -> wave64 shuffle scan -> LDS scan
-//     of the 16 wave totals.  Between workgroups: each publishes its tile
-//     aggregate with an agent-scope release; a workgroup whose first row is
-//     not a stratum head folds its predecessors' aggregates back to the
-//     nearest one containing a head (look-back, one wave, 64 tiles per step).
-//   * The per-coordinate sums are reduced per workgroup (shuffles + LDS) and
-//     published into a double-buffered array; every workgroup gathers all of
-//     them in the same fixed order and computes the same scalar step, so no
-//     broadcast round trip is needed and results are bit-reproducible.
+//   * Rows inside a workgroup: thread fold -> DPP wave scan -> LDS fold of the
+//     wave totals.  A workgroup whose first row is not a stratum head takes
+//     its carry from its predecessors' published tile aggregates (look-back,
+//     one wave, 64 tiles per round).  When strata fit in a tile the host pads
+//     the row layout so no stratum crosses a tile boundary, and the look-back
+//     never runs.
+//   * Per-coordinate sums are reduced per workgroup (DPP + LDS) and published
+//     as epoch-tagged packets; workgroup 0 gathers them in a fixed order,
+//     takes the scalar CCD step and publishes it; the other workgroups read
+//     that one packet pair.  Results are bit-reproducible.
 //   * exp() uses one global shift c (the largest X beta of the previous
 //     coordinate); ratios are shift-invariant and the objective adds c back.
 //     A risk-set sum outside [1e-300, 1e300] stops the fit with a flag.
@@ -36,37 +37,39 @@
 
 namespace coxmi {
 
-// Per-workgroup partial record.
-enum { kPC1 = 0, kPC2 = 1, kPM2 = 2, kPObj = 3, kPEtaMax = 4, kPErr = 5 };
+// Per-workgroup partial record (5 doubles + an error flag).
+enum { kPC1 = 0, kPC2 = 1, kPM2 = 2, kPObj = 3, kPEtaMax = 4, kPN = 5 };
 
-struct alignas(16) CtlBlock {
-    SyncCtl ctl;
+struct Partial {
+    double v[kPN];
+    uint32_t err;
 };
+
+// Flags carried in the step packet.
+enum : uint32_t { kFlagNumeric = 1u, kFlagConverged = 2u, kFlagSweepLimit = 4u };
+
+namespace {
+
+size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
 
 size_t sync_scratch_bytes(int grid)
 {
-    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-    size_t s = up(sizeof(SyncCtl));
-    s += up(sizeof(TileAgg<3>) * (size_t)grid);
-    s += up(sizeof(uint32_t) * (size_t)grid);
-    s += up(sizeof(double) * kPartialDoubles * 2 * (size_t)grid);
-    s += up(sizeof(uint32_t) * 2 * (size_t)grid);
-    return s;
+    return up256(sizeof(SyncCtl)) + up256(sizeof(Packet) * 3 * (size_t)grid) +
+           up256(sizeof(Packet) * kPN * (size_t)grid) + up256(sizeof(Packet) * 2);
 }
 
 void carve_sync_scratch(void *base, int grid, CcdLaunch &L)
 {
-    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
     char *c = static_cast<char *>(base);
     L.ctl = c;
-    c += up(sizeof(SyncCtl));
+    c += up256(sizeof(SyncCtl));
     L.agg = c;
-    c += up(sizeof(TileAgg<3>) * (size_t)grid);
-    L.stat1 = reinterpret_cast<uint32_t *>(c);
-    c += up(sizeof(uint32_t) * (size_t)grid);
-    L.part = reinterpret_cast<double *>(c);
-    c += up(sizeof(double) * kPartialDoubles * 2 * (size_t)grid);
-    L.stat2 = reinterpret_cast<uint32_t *>(c);
+    c += up256(sizeof(Packet) * 3 * (size_t)grid);
+    L.part = c;
+    c += up256(sizeof(Packet) * kPN * (size_t)grid);
+    L.res = c;
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -78,7 +81,7 @@ __device__ __forceinline__ void load_rows(double (&v)[IPT], const double *p)
         const double2 *q = reinterpret_cast<const double2 *>(p);
 #pragma unroll
         for (int i = 0; i < IPT / 2; ++i) {
-            double2 t = q[i];
+            const double2 t = q[i];
             v[2 * i] = t.x;
             v[2 * i + 1] = t.y;
         }
@@ -95,7 +98,7 @@ __device__ __forceinline__ void load_words(uint32_t (&v)[IPT], const uint32_t *p
         const uint4 *q = reinterpret_cast<const uint4 *>(p);
 #pragma unroll
         for (int i = 0; i < IPT / 4; ++i) {
-            uint4 t = q[i];
+            const uint4 t = q[i];
             v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w;
         }
     } else {
@@ -104,94 +107,70 @@ __device__ __forceinline__ void load_words(uint32_t (&v)[IPT], const uint32_t *p
     }
 }
 
-__device__ __forceinline__ void partial_identity(double (&v)[kPartialDoubles])
+__device__ __forceinline__ Partial partial_identity()
 {
-    v[kPC1] = 0.0; v[kPC2] = 0.0; v[kPM2] = 0.0; v[kPObj] = 0.0;
-    v[kPEtaMax] = -INFINITY; v[kPErr] = 0.0;
+    Partial r;
+    r.v[kPC1] = 0.0; r.v[kPC2] = 0.0; r.v[kPM2] = 0.0; r.v[kPObj] = 0.0;
+    r.v[kPEtaMax] = -INFINITY;
+    r.err = 0u;
+    return r;
 }
 
-__device__ __forceinline__ void partial_combine(double (&a)[kPartialDoubles], const double (&b)[kPartialDoubles])
+__device__ __forceinline__ void partial_combine(Partial &a, const Partial &b)
 {
-    a[kPC1] += b[kPC1];
-    a[kPC2] += b[kPC2];
-    a[kPM2] += b[kPM2];
-    a[kPObj] += b[kPObj];
-    a[kPEtaMax] = fmax(a[kPEtaMax], b[kPEtaMax]);
-    a[kPErr] = fmax(a[kPErr], b[kPErr]);
+    a.v[kPC1] += b.v[kPC1];
+    a.v[kPC2] += b.v[kPC2];
+    a.v[kPM2] += b.v[kPM2];
+    a.v[kPObj] += b.v[kPObj];
+    a.v[kPEtaMax] = fmax(a.v[kPEtaMax], b.v[kPEtaMax]);
+    a.err |= b.err;
 }
 
-// Butterfly reduction: every lane ends with the same total (+ and max commute).
-__device__ __forceinline__ void wave_allreduce_partial(double (&v)[kPartialDoubles])
+template <int CTRL, int ROWS>
+__device__ __forceinline__ Partial dpp_partial(const Partial &x)
 {
-#pragma unroll
-    for (int off = kWave / 2; off >= 1; off >>= 1) {
-        double o[kPartialDoubles];
-#pragma unroll
-        for (int k = 0; k < kPartialDoubles; ++k) o[k] = __shfl_xor(v[k], off, kWave);
-        partial_combine(v, o);
-    }
+    Partial r;
+    r.v[kPC1] = dpp_f64<CTRL, ROWS>(x.v[kPC1]);
+    r.v[kPC2] = dpp_f64<CTRL, ROWS>(x.v[kPC2]);
+    r.v[kPM2] = dpp_f64<CTRL, ROWS>(x.v[kPM2]);
+    r.v[kPObj] = dpp_f64<CTRL, ROWS>(x.v[kPObj]);
+    // lanes without a source must see the identity of max
+    r.v[kPEtaMax] = __builtin_amdgcn_update_dpp(-(double)INFINITY, x.v[kPEtaMax], CTRL, ROWS, 0xF, false);
+    r.err = dpp_u32<CTRL, ROWS>(x.err);
+    return r;
 }
 
-// Workgroup reduction; the total is valid in every lane of wave 0.
+// Wave reduction in a fixed lane order; the total ends in lane 63.
+__device__ __forceinline__ Partial wave_reduce_partial(Partial x)
+{
+    Partial o;
+    o = dpp_partial<0x111, 0xF>(x); partial_combine(x, o);
+    o = dpp_partial<0x112, 0xF>(x); partial_combine(x, o);
+    o = dpp_partial<0x114, 0xF>(x); partial_combine(x, o);
+    o = dpp_partial<0x118, 0xF>(x); partial_combine(x, o);
+    o = dpp_partial<0x142, 0xA>(x); partial_combine(x, o);
+    o = dpp_partial<0x143, 0xC>(x); partial_combine(x, o);
+    return x;
+}
+
+// Workgroup reduction; every thread receives the same total.  One barrier.
 template <int NW>
-__device__ __forceinline__ void block_reduce_partial(double (&v)[kPartialDoubles],
-                                                     double (*red)[kPartialDoubles])
+__device__ __forceinline__ Partial block_reduce_partial(const Partial &x, Partial *red)
 {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    wave_allreduce_partial(v);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < kPartialDoubles; ++k) red[w][k] = v[k];
-    }
+    const Partial wr = wave_reduce_partial(x);
+    if (lane == kWave - 1) red[w] = wr;
     __syncthreads();
-    if (w == 0) {
-        double x[kPartialDoubles];
-        if (lane < NW) {
+    Partial tot = red[0];
 #pragma unroll
-            for (int k = 0; k < kPartialDoubles; ++k) x[k] = red[lane][k];
-        } else {
-            partial_identity(x);
-        }
-        wave_allreduce_partial(x);
-#pragma unroll
-        for (int k = 0; k < kPartialDoubles; ++k) v[k] = x[k];
-    }
+    for (int k = 1; k < NW; ++k) partial_combine(tot, red[k]);
+    return tot;
 }
 
-// Publish this workgroup's record for `epoch` and gather the records of all
-// workgroups (wave 0 only).  Sums in a fixed order, so every workgroup gets a
-// bit-identical total.  Returns false on abort.
-__device__ __forceinline__ bool exchange_partials(double (&v)[kPartialDoubles], int b, int G,
-                                                  uint32_t epoch, double *part, uint32_t *stat2,
-                                                  SyncCtl *ctl)
+__device__ __forceinline__ void publish_partial(Packet *slot, const Partial &x, uint32_t epoch)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const size_t par = epoch & 1u;
-    double *base = part + par * (size_t)G * kPartialDoubles;
-    uint32_t *st = stat2 + par * (size_t)G;
-    if (lane == 0) {
-        double *mine = base + (size_t)b * kPartialDoubles;
 #pragma unroll
-        for (int k = 0; k < kPartialDoubles; ++k) mine[k] = v[k];
-        store_release(&st[b], epoch);
-    }
-    bool ok = true;
-    for (int q = lane; q < G; q += kWave)
-        if (ok) ok = wait_equal(&st[q], epoch, ctl);
-    if (__any(!ok)) return false;
-    double acc[kPartialDoubles];
-    partial_identity(acc);
-    for (int q = lane; q < G; q += kWave) {
-        double o[kPartialDoubles];
-        const double *pq = base + (size_t)q * kPartialDoubles;
-#pragma unroll
-        for (int k = 0; k < kPartialDoubles; ++k) o[k] = pq[k];
-        partial_combine(acc, o);
-    }
-    wave_allreduce_partial(acc);
-#pragma unroll
-    for (int k = 0; k < kPartialDoubles; ++k) v[k] = acc[k];
-    return true;
+    for (int k = 0; k < kPN; ++k) packet_put(slot + k, x.v[k], epoch, k == 0 ? x.err : 0u);
 }
 
 // One CCD coordinate update (Sec. 2.4).  Newton step on the smooth part; with
@@ -233,45 +212,78 @@ __device__ __forceinline__ double ccd_step(double beta, double g1, double g2, do
     return s;
 }
 
+// Workgroup 0 gathers the partial records of all G workgroups for `epoch`
+// (one thread per workgroup) and reduces them in workgroup order.  Returns
+// false (uniformly) if a wait was aborted.
+template <int BLOCK>
+__device__ __forceinline__ bool gather_partials(const Packet *part, int G, uint32_t epoch, SyncCtl *ctl,
+                                                Partial *red, Partial &total)
+{
+    constexpr int NW = BLOCK / kWave;
+    Partial x = partial_identity();
+    bool ok = true;
+    const int q = threadIdx.x;
+    if (q < G) {
+        u32x4 r[kPN];
+        ok = packets_wait<kPN>(part + kPN * (size_t)q, epoch, ctl, r);
+        if (ok) {
+#pragma unroll
+            for (int k = 0; k < kPN; ++k) x.v[k] = packet_value(r[k]);
+            x.err = r[0].w;
+        }
+    }
+    if (__syncthreads_or(ok ? 0 : 1)) return false;
+    total = block_reduce_partial<NW>(x, red);
+    return true;
+}
+
 // ------------------------------------------------------------------ the persistent kernel
 
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 {
     constexpr int NW = BLOCK / kWave;
-    extern __shared__ double smem_dyn[];
-    __shared__ BlockScanSmem<3, NW> ss;
-    __shared__ double red[NW][kPartialDoubles];
+    static_assert(BLOCK % kWave == 0 && NW <= 16, "block shape");
+    extern __shared__ double smem_dyn[];     // workgroup 0: beta, trust, gamma
+    __shared__ SegVal<3> s_wtot[NW];
+    __shared__ Partial s_red[NW];
     __shared__ SegVal<3> s_carry;
     __shared__ double s_step, s_shift;
-    __shared__ int s_flag;   // 0 go on, 1 abort, 2 numeric stop, 3 converged, 4 sweep limit
+    __shared__ uint32_t s_flags;
+    __shared__ int s_abort;
 
     const int p = L.p;
     const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
     const int lane = t & (kWave - 1), w = t / kWave;
+    const bool reducer = (b == 0);
     SyncCtl *ctl = static_cast<SyncCtl *>(L.ctl);
-    TileAgg<3> *agg = static_cast<TileAgg<3> *>(L.agg);
+    Packet *agg = static_cast<Packet *>(L.agg);
+    Packet *part = static_cast<Packet *>(L.part);
+    Packet *res = static_cast<Packet *>(L.res);
     const int64_t ld = (int64_t)G * BLOCK * IPT;
     const int64_t tile0 = (int64_t)b * BLOCK * IPT;
     const int64_t row0 = tile0 + (int64_t)t * IPT;
+    const bool fit = (L.mode == kModeFit);
 
     double *sbeta = smem_dyn, *strust = smem_dyn + p, *sgamma = smem_dyn + 2 * p;
-    for (int j = t; j < p; j += BLOCK) {
-        sbeta[j] = L.beta[j];
-        strust[j] = 1.0;
-        sgamma[j] = L.gamma[j];
+    if (reducer) {
+        for (int j = t; j < p; j += BLOCK) {
+            sbeta[j] = L.beta[j];
+            strust[j] = 1.0;
+            sgamma[j] = L.gamma[j];
+        }
     }
+    if (t == 0) s_abort = 0;
     uint32_t meta[IPT];
     double eta[IPT];
     load_words<IPT>(meta, L.meta + row0);
 #pragma unroll
     for (int i = 0; i < IPT; ++i) eta[i] = 0.0;
     const bool tile_head = (L.meta[tile0] & kHeadBit) != 0u;
-    __syncthreads();
 
     // X beta0 (columns with beta0_j = 0 are skipped)
     for (int j = 0; j < p; ++j) {
-        const double bj = sbeta[j];
+        const double bj = L.beta[j];
         if (bj != 0.0) {
             double xv[IPT];
             load_rows<IPT>(xv, L.x + (int64_t)j * ld + row0);
@@ -279,38 +291,44 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             for (int i = 0; i < IPT; ++i) eta[i] = fma(xv[i], bj, eta[i]);
         }
     }
+    __syncthreads();
 
-    // initial shift: the largest X beta over the real rows
+    // epoch 1: the initial shift, the largest X beta over the real rows
     uint32_t epoch = 1;
     {
-        double v[kPartialDoubles];
-        partial_identity(v);
+        Partial v = partial_identity();
 #pragma unroll
         for (int i = 0; i < IPT; ++i)
-            if (row0 + i < L.n) v[kPEtaMax] = fmax(v[kPEtaMax], eta[i]);
-        block_reduce_partial<NW>(v, red);
-        if (w == 0) {
-            const bool ok = exchange_partials(v, b, G, epoch, L.part, L.stat2, ctl);
-            if (lane == 0) {
-                s_flag = ok ? 0 : 1;
-                s_shift = v[kPEtaMax];
+            if (!(meta[i] & kPadBit)) v.v[kPEtaMax] = fmax(v.v[kPEtaMax], eta[i]);
+        v = block_reduce_partial<NW>(v, s_red);
+        if (t == 0) publish_partial(part + kPN * (size_t)b, v, epoch);
+        if (reducer) {
+            Partial tot;
+            if (!gather_partials<BLOCK>(part, G, epoch, ctl, s_red, tot)) return;
+            if (t == 0) {
+                packet_put(res, 0.0, epoch, 0u);
+                packet_put(res + 1, tot.v[kPEtaMax], epoch, 0u);
+                s_shift = tot.v[kPEtaMax];
             }
+        } else if (t == 0) {
+            u32x4 r[2];
+            if (packets_wait<2>(res, epoch, ctl, r)) s_shift = packet_value(r[1]);
+            else s_abort = 1;
         }
         __syncthreads();
-        if (s_flag == 1) return;
+        if (s_abort) return;
     }
     double c = s_shift;
 
-    const bool fit = (L.mode == kModeFit);
     const int jfirst = fit ? 0 : L.j0;
     const int jend = fit ? p : L.j1;
     double xc[IPT];
     load_rows<IPT>(xc, L.x + (int64_t)jfirst * ld + row0);
 
-    // bookkeeping held by thread 0 of every workgroup (identical everywhere)
+    // bookkeeping of workgroup 0, thread 0
     int sweeps = 0, pinned = 0, pinned_last = 0;
     double maxstep = 0.0, last_maxstep = 0.0, objective = 0.0;
-    int stop = 0;
+    uint32_t stop = 0;
 
     for (;;) {
         for (int j = jfirst; j < jend; ++j) {
@@ -318,6 +336,8 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             const int jn = (j + 1 < jend) ? j + 1 : jfirst;
             double xn[IPT];
             load_rows<IPT>(xn, L.x + (int64_t)jn * ld + row0);
+            double qj = 0.0;
+            if (reducer && t == 0) qj = L.q[j];
             const bool want_obj = (j == jfirst);
 
             // pass 1: D, N1, N2 of the thread's rows and their fold
@@ -333,31 +353,25 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
                 r.v[2] = xc[i] * r.v[1];
                 tagg = seg_combine(tagg, r);
             }
-            SegVal<3> exc = block_exclusive_scan(tagg, ss);
-            if (t == 0) {
-                agg[b].f = ss.block_total.f ? 1.0 : 0.0;
-                agg[b].v[0] = ss.block_total.v[0];
-                agg[b].v[1] = ss.block_total.v[1];
-                agg[b].v[2] = ss.block_total.v[2];
-                store_release(&L.stat1[b], epoch);
-            }
+            SegVal<3> btot;
+            SegVal<3> exc = block_exclusive_scan<3, NW>(tagg, s_wtot, btot);
+            if (t == 0) publish_aggregate<3>(agg + 3 * (size_t)b, btot, epoch);
             if (!tile_head) {
                 if (w == 0) {
                     SegVal<3> carry;
-                    const bool ok = look_back<3>(b, epoch, agg, L.stat1, ctl, carry);
+                    const bool ok = look_back<3>(b, epoch, agg, ctl, carry);
                     if (lane == 0) {
                         s_carry = carry;
-                        s_flag = ok ? 0 : 1;
+                        if (!ok) s_abort = 1;
                     }
                 }
                 __syncthreads();
-                if (s_flag == 1) return;
+                if (s_abort) return;
                 exc = seg_combine(s_carry, exc);
             }
 
             // pass 2: inclusive prefixes at group ends -> per-coordinate sums
-            double v[kPartialDoubles];
-            partial_identity(v);
+            Partial v = partial_identity();
             SegVal<3> run = exc;
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
@@ -367,57 +381,78 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
                 r.v[1] = xc[i] * wv[i];
                 r.v[2] = xc[i] * r.v[1];
                 run = seg_combine(run, r);
-                if (row0 + i < L.n) v[kPEtaMax] = fmax(v[kPEtaMax], eta[i]);
+                if (!(meta[i] & kPadBit)) v.v[kPEtaMax] = fmax(v.v[kPEtaMax], eta[i]);
                 const uint32_t d = meta[i] & kCountMask;
                 if (d != 0u) {
                     const double s0 = run.v[0];
-                    if (!(s0 >= 1e-300) || !(s0 <= 1e300)) v[kPErr] = 1.0;
+                    if (!(s0 >= 1e-300) || !(s0 <= 1e300)) v.err = 1u;
                     const double inv = 1.0 / s0;
                     const double r1 = run.v[1] * inv, r2 = run.v[2] * inv;
                     const double dd = (double)d;
-                    v[kPC1] += dd * r1;
-                    v[kPC2] += dd * (r2 - r1 * r1);
-                    v[kPM2] += dd * r2;
-                    if (want_obj) v[kPObj] += dd * (log(s0) + c);
+                    v.v[kPC1] += dd * r1;
+                    v.v[kPC2] += dd * (r2 - r1 * r1);
+                    v.v[kPM2] += dd * r2;
+                    if (want_obj) v.v[kPObj] += dd * (log(s0) + c);
                 }
-                if (want_obj && (meta[i] & kEventBit)) v[kPObj] -= eta[i];
+                if (want_obj && (meta[i] & kEventBit)) v.v[kPObj] -= eta[i];
             }
-            block_reduce_partial<NW>(v, red);
-            if (w == 0) {
-                const bool ok = exchange_partials(v, b, G, epoch, L.part, L.stat2, ctl);
-                if (lane == 0) {
-                    int flag = ok ? 0 : 1;
+            v = block_reduce_partial<NW>(v, s_red);
+            if (t == 0) publish_partial(part + kPN * (size_t)b, v, epoch);
+
+            if (reducer) {
+                Partial tot;
+                if (!gather_partials<BLOCK>(part, G, epoch, ctl, s_red, tot)) return;
+                if (t == 0) {
+                    uint32_t flags = tot.err ? kFlagNumeric : 0u;
+                    const double g1 = -qj + tot.v[kPC1], g2 = tot.v[kPC2], m2 = tot.v[kPM2];
+                    L.g1[j] = g1;
+                    L.g2[j] = g2;
+                    L.m2[j] = m2;
+                    if (want_obj) {
+                        objective = tot.v[kPObj];
+                        if (fit)
+                            for (int k = 0; k < p; ++k) objective += sgamma[k] * fabs(sbeta[k]);
+                    }
                     double step = 0.0;
-                    if (ok) {
-                        const double g1 = -L.q[j] + v[kPC1], g2 = v[kPC2], m2 = v[kPM2];
-                        if (v[kPErr] != 0.0) flag = 2;
-                        if (b == 0) {
-                            L.g1[j] = g1;
-                            L.g2[j] = g2;
-                            L.m2[j] = m2;
-                        }
-                        if (want_obj) {
-                            objective = v[kPObj];
-                            if (fit)
-                                for (int k = 0; k < p; ++k) objective += sgamma[k] * fabs(sbeta[k]);
-                        }
-                        if (fit && flag == 0) {
-                            int pin = 0;
-                            step = ccd_step(sbeta[j], g1, g2, m2, sgamma[j], &strust[j], &pin);
-                            sbeta[j] += step;
-                            maxstep = fmax(maxstep, fabs(step));
-                            pinned += pin;
+                    if (fit && !(flags & kFlagNumeric)) {
+                        int pin = 0;
+                        step = ccd_step(sbeta[j], g1, g2, m2, sgamma[j], &strust[j], &pin);
+                        sbeta[j] += step;
+                        maxstep = fmax(maxstep, fabs(step));
+                        pinned += pin;
+                        if (j == jend - 1) {
+                            ++sweeps;
+                            double bmax = 1.0;
+                            for (int k = 0; k < p; ++k) bmax = fmax(bmax, fabs(sbeta[k]));
+                            if (maxstep <= L.tol * bmax) flags |= kFlagConverged;
+                            else if (sweeps >= L.max_sweeps) flags |= kFlagSweepLimit;
+                            last_maxstep = maxstep;
+                            pinned_last = pinned;
+                            maxstep = 0.0;
+                            pinned = 0;
                         }
                     }
+                    packet_put(res, step, epoch, flags);
+                    packet_put(res + 1, tot.v[kPEtaMax], epoch, 0u);
                     s_step = step;
-                    s_shift = v[kPEtaMax];
-                    s_flag = flag;
+                    s_shift = tot.v[kPEtaMax];
+                    s_flags = flags;
+                }
+            } else if (t == 0) {
+                u32x4 r[2];
+                if (packets_wait<2>(res, epoch, ctl, r)) {
+                    s_step = packet_value(r[0]);
+                    s_flags = r[0].w;
+                    s_shift = packet_value(r[1]);
+                } else {
+                    s_abort = 1;
                 }
             }
             __syncthreads();
-            if (s_flag == 1) return;
-            if (s_flag == 2) {
-                stop = 2;
+            if (s_abort) return;
+            const uint32_t flags = s_flags;
+            if (flags & kFlagNumeric) {
+                stop = kFlagNumeric;
                 break;
             }
             const double step = s_step;
@@ -428,30 +463,15 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             }
 #pragma unroll
             for (int i = 0; i < IPT; ++i) xc[i] = xn[i];
+            if (flags & (kFlagConverged | kFlagSweepLimit)) {
+                stop = flags;
+                break;
+            }
         }
         if (stop || !fit) break;
-        ++sweeps;
-        if (t == 0) {
-            double bmax = 1.0;
-            for (int k = 0; k < p; ++k) bmax = fmax(bmax, fabs(sbeta[k]));
-            int flag = 0;
-            if (maxstep <= L.tol * bmax) flag = 3;
-            else if (sweeps >= L.max_sweeps) flag = 4;
-            last_maxstep = maxstep;
-            pinned_last = pinned;
-            maxstep = 0.0;
-            pinned = 0;
-            s_flag = flag;
-        }
-        __syncthreads();
-        if (s_flag != 0) {
-            stop = s_flag;
-            break;
-        }
     }
 
-    if (b == 0) {
-        __syncthreads();
+    if (reducer) {
         if (fit)
             for (int j = t; j < p; j += BLOCK) L.beta[j] = sbeta[j];
         if (t == 0) {
@@ -459,8 +479,8 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             L.result[kResLastStep] = last_maxstep;
             L.result[kResObjective] = objective;
             L.result[kResPinned] = pinned_last;
-            L.result[kResConverged] = (stop == 3) ? 1.0 : 0.0;
-            L.result[kResNumeric] = (stop == 2) ? 1.0 : 0.0;
+            L.result[kResConverged] = (stop & kFlagConverged) ? 1.0 : 0.0;
+            L.result[kResNumeric] = (stop & kFlagNumeric) ? 1.0 : 0.0;
             L.result[kResCompleted] = 1.0;
         }
     }
@@ -472,16 +492,16 @@ constexpr int kScanBlock = 1024;
 
 template <int IPT>
 __global__ __launch_bounds__(kScanBlock) void segscan_kernel(const double *a, const uint8_t *head,
-                                                             double *out, int64_t n, TileAgg<1> *agg,
-                                                             uint32_t *stat, SyncCtl *ctl)
+                                                             double *out, int64_t n, Packet *agg,
+                                                             SyncCtl *ctl)
 {
-    constexpr int kBlock = kScanBlock;
-    __shared__ BlockScanSmem<1, kBlock / kWave> ss;
+    constexpr int NW = kScanBlock / kWave;
+    __shared__ SegVal<1> s_wtot[NW];
     __shared__ SegVal<1> s_carry;
-    __shared__ int s_flag;
+    __shared__ int s_abort;
     const int b = blockIdx.x, t = threadIdx.x;
     const int lane = t & (kWave - 1), w = t / kWave;
-    const int64_t tile0 = (int64_t)b * kBlock * IPT;
+    const int64_t tile0 = (int64_t)b * kScanBlock * IPT;
     const int64_t row0 = tile0 + (int64_t)t * IPT;
     SegVal<1> e[IPT];
     SegVal<1> tagg = seg_identity<1>();
@@ -497,25 +517,23 @@ __global__ __launch_bounds__(kScanBlock) void segscan_kernel(const double *a, co
         }
         tagg = seg_combine(tagg, e[i]);
     }
+    if (t == 0) s_abort = 0;
     const uint32_t epoch = 1;
-    SegVal<1> exc = block_exclusive_scan(tagg, ss);
-    if (t == 0) {
-        agg[b].f = ss.block_total.f ? 1.0 : 0.0;
-        agg[b].v[0] = ss.block_total.v[0];
-        store_release(&stat[b], epoch);
-    }
+    SegVal<1> btot;
+    SegVal<1> exc = block_exclusive_scan<1, NW>(tagg, s_wtot, btot);
+    if (t == 0) publish_aggregate<1>(agg + b, btot, epoch);
     const bool tile_head = tile0 >= n || tile0 == 0 || head[tile0] != 0;
     if (!tile_head) {
         if (w == 0) {
             SegVal<1> carry;
-            const bool ok = look_back<1>(b, epoch, agg, stat, ctl, carry);
+            const bool ok = look_back<1>(b, epoch, agg, ctl, carry);
             if (lane == 0) {
                 s_carry = carry;
-                s_flag = ok ? 0 : 1;
+                if (!ok) s_abort = 1;
             }
         }
         __syncthreads();
-        if (s_flag) return;
+        if (s_abort) return;
         exc = seg_combine(s_carry, exc);
     }
     SegVal<1> run = exc;
@@ -561,36 +579,21 @@ int device_cus(int *cus)
 
 }  // namespace
 
-int choose_shape(int64_t n, int p, LaunchShape &shape, std::string &err)
+int max_resident_groups(int ipt, int p, int *groups, std::string &err)
 {
+    *groups = 0;
     int cus = 0;
-    int e = device_cus(&cus);
-    if (e != (int)hipSuccess || cus <= 0) {
+    if (device_cus(&cus) != (int)hipSuccess || cus <= 0) {
         err = "cannot query the device's compute-unit count";
         return -3;
     }
-    const int ipts[] = {1, 2, 4, 8, 16};
-    for (int ipt : ipts) {
-        const int64_t rows_per_wg = (int64_t)kCcdBlock * ipt;
-        const int64_t grid = (n + rows_per_wg - 1) / rows_per_wg;
-        if (grid > cus) continue;
-        int blocks = 0;
-        e = occupancy_for(ipt, p, &blocks);
-        if (e != (int)hipSuccess) {
-            err = "occupancy query failed";
-            return -3;
-        }
-        if (blocks < 1) {
-            err = "the persistent kernel does not fit on one compute unit for this p";
-            return -5;
-        }
-        shape.ipt = ipt;
-        shape.grid = (int)grid;
-        shape.ld = grid * rows_per_wg;
-        return 0;
+    int blocks = 0;
+    if (occupancy_for(ipt, p, &blocks) != (int)hipSuccess) {
+        err = "occupancy query failed";
+        return -3;
     }
-    err = "n exceeds the register-resident limit of the persistent kernel (CUs x 512 x 16 rows)";
-    return -5;
+    *groups = blocks >= 1 ? cus : 0;   // one workgroup per compute unit
+    return 0;
 }
 
 int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream, hipEvent_t ev0,
@@ -634,19 +637,16 @@ int segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, hipS
         }
     }
     if (!ipt) return -5;
-    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-    const size_t bytes = up(sizeof(SyncCtl)) + up(sizeof(TileAgg<1>) * grid) + up(sizeof(uint32_t) * grid);
+    const size_t bytes = up256(sizeof(SyncCtl)) + up256(sizeof(Packet) * (size_t)grid);
     void *scratch = nullptr;
     if (hipMalloc(&scratch, bytes) != hipSuccess) return -2;
     char *cb = static_cast<char *>(scratch);
     SyncCtl *ctl = reinterpret_cast<SyncCtl *>(cb);
-    TileAgg<1> *agg = reinterpret_cast<TileAgg<1> *>(cb + up(sizeof(SyncCtl)));
-    uint32_t *stat = reinterpret_cast<uint32_t *>(cb + up(sizeof(SyncCtl)) + up(sizeof(TileAgg<1>) * grid));
+    Packet *agg = reinterpret_cast<Packet *>(cb + up256(sizeof(SyncCtl)));
     int rc = 0;
     hipError_t e = hipMemsetAsync(scratch, 0, bytes, stream);
     if (e == hipSuccess) {
-        void *args[] = {(void *)&a, (void *)&head, (void *)&b, (void *)&n, (void *)&agg, (void *)&stat,
-                        (void *)&ctl};
+        void *args[] = {(void *)&a, (void *)&head, (void *)&b, (void *)&n, (void *)&agg, (void *)&ctl};
         const void *fn = nullptr;
         switch (ipt) {
         case 1: fn = reinterpret_cast<const void *>(&segscan_kernel<1>); break;

@@ -31,8 +31,9 @@ struct cox_handle {
     void *d_sync = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float last_kernel_ms = 0.0f;
-    std::vector<int64_t> perm;
-    std::vector<uint32_t> meta;
+    std::vector<int64_t> perm;     // canonical row -> original row
+    std::vector<uint32_t> meta;    // canonical row words
+    std::vector<int64_t> pos;      // canonical row -> row of the device layout
     std::vector<double> gamma;
     cox_options opt{};
     std::string err;
@@ -90,6 +91,61 @@ static void free_device(cox_handle *h)
     h->ev0 = h->ev1 = nullptr;
 }
 
+// Device row of every canonical row when tiles hold R rows and no stratum that
+// fits in one tile may cross a tile boundary (the gap is filled with padding
+// rows).  Returns the padded length.
+static int64_t aligned_positions(const std::vector<uint32_t> &meta, int64_t R, std::vector<int64_t> *pos)
+{
+    const int64_t n = (int64_t)meta.size();
+    int64_t cur = 0, i = 0;
+    while (i < n) {
+        int64_t e = i + 1;
+        while (e < n && !(meta[e] & kHeadBit)) ++e;
+        const int64_t m = e - i;
+        const int64_t room = R - (cur % R);
+        if (m <= R && m > room) cur += room;
+        if (pos)
+            for (int64_t k = 0; k < m; ++k) (*pos)[i + k] = cur + k;
+        cur += m;
+        i = e;
+    }
+    return cur;
+}
+
+// Rows per thread, workgroups and device row positions for the persistent
+// kernel: the fewest rows per thread whose workgroup count fits one per
+// compute unit, preferring the stratum-aligned layout.
+static int choose_layout(const std::vector<uint32_t> &meta, int p, LaunchShape &shape,
+                         std::vector<int64_t> &pos, std::string &err)
+{
+    const int64_t n = (int64_t)meta.size();
+    pos.assign(n, 0);
+    const int ipts[] = {1, 2, 4, 8, 16};
+    for (int ipt : ipts) {
+        int groups = 0;
+        if (max_resident_groups(ipt, p, &groups, err) != 0) return COX_EDEVICE;
+        if (groups < 1) continue;
+        const int64_t R = (int64_t)kThreads * ipt;
+        const int64_t la = aligned_positions(meta, R, nullptr);
+        if ((la + R - 1) / R <= groups) {
+            aligned_positions(meta, R, &pos);
+            shape.ipt = ipt;
+            shape.grid = (int)((la + R - 1) / R);
+            shape.ld = (int64_t)shape.grid * R;
+            return 0;
+        }
+        if ((n + R - 1) / R <= groups) {
+            std::iota(pos.begin(), pos.end(), int64_t(0));
+            shape.ipt = ipt;
+            shape.grid = (int)((n + R - 1) / R);
+            shape.ld = (int64_t)shape.grid * R;
+            return 0;
+        }
+    }
+    err = "n exceeds the register-resident capacity of the persistent kernel (CUs x 512 x 16 rows)";
+    return COX_EUNSUPPORTED;
+}
+
 extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *o)
 {
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
@@ -99,7 +155,7 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     if (n < 1 || p < 1) return fail(nullptr, COX_EINVAL, "need n >= 1 and p >= 1");
     if (d->ldx < n) return fail(nullptr, COX_EINVAL, "ldx < n");
     if (!d->x || !d->time || !d->event) return fail(nullptr, COX_EINVAL, "x, time and event are required");
-    if (n > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "n exceeds 2^30 - 1");
+    if (n > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "n exceeds 2^29 - 1");
     if (p > 4096) return fail(nullptr, COX_EUNSUPPORTED, "p > 4096 is not supported by the resident kernel");
     cox_options opt;
     if (o) opt = *o;
@@ -122,13 +178,6 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     h->opt.penalize = nullptr;
     h->stream = static_cast<hipStream_t>(opt.stream);
     (void)hipGetDevice(&h->device);
-    std::string err;
-    int rc = choose_shape(n, (int)p, h->shape, err);
-    if (rc != 0) {
-        delete h;
-        return fail(nullptr, rc == -5 ? COX_EUNSUPPORTED : COX_EDEVICE, err);
-    }
-    const int64_t ld = h->shape.ld;
 
     // canonical order: stratum ascending, time descending, original index ascending
     const double *tm = d->time;
@@ -168,6 +217,14 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     if (o && o->penalize)
         for (int64_t j = 0; j < p; ++j) h->gamma[j] = o->penalize[j] ? opt.gamma : 0.0;
 
+    std::string err;
+    int rc = choose_layout(h->meta, (int)p, h->shape, h->pos, err);
+    if (rc != 0) {
+        delete h;
+        return fail(nullptr, rc, err);
+    }
+    const int64_t ld = h->shape.ld;
+
     hipError_t e;
     if ((e = hipMalloc(&h->d_x, sizeof(double) * (size_t)ld * p)) != hipSuccess ||
         (e = hipMalloc(&h->d_meta, sizeof(uint32_t) * (size_t)ld)) != hipSuccess ||
@@ -177,21 +234,22 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
         delete h;
         return hip_fail(nullptr, e, "device allocation");
     }
-    // row words, padding rows are single-row strata without events
+    // row words; padding rows are single-row strata without events
     {
-        std::vector<uint32_t> mpad(ld, kHeadBit);
-        std::copy(h->meta.begin(), h->meta.end(), mpad.begin());
+        std::vector<uint32_t> mpad(ld, kHeadBit | kPadBit);
+        for (int64_t i = 0; i < n; ++i) mpad[h->pos[i]] = h->meta[i];
         e = hipMemcpy(h->d_meta, mpad.data(), sizeof(uint32_t) * ld, hipMemcpyHostToDevice);
     }
-    // X in canonical order, column by column, and q_j = delta'X_j
+    // X in canonical order at the layout positions, column by column, and q_j = delta'X_j
     std::vector<double> col(ld, 0.0), q(p, 0.0);
     for (int64_t j = 0; j < p && e == hipSuccess; ++j) {
         const double *xj = d->x + j * d->ldx;
         double qj = 0.0;
         for (int64_t i = 0; i < n; ++i) {
             const int64_t r = h->perm[i];
-            col[i] = xj[r];
-            if (d->event[r]) qj += col[i];
+            const double v = xj[r];
+            col[h->pos[i]] = v;
+            if (d->event[r]) qj += v;
         }
         q[j] = qj;
         e = hipMemcpy(h->d_x + j * ld, col.data(), sizeof(double) * ld, hipMemcpyHostToDevice);

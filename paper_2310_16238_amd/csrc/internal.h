@@ -11,10 +11,10 @@ namespace coxmi {
 // Row word in canonical order (see cox_layout in include/coxmi.h).
 constexpr uint32_t kHeadBit = 0x80000000u;
 constexpr uint32_t kEventBit = 0x40000000u;
-constexpr uint32_t kCountMask = 0x3fffffffu;
+constexpr uint32_t kPadBit = 0x20000000u;     // device layout only: a padding row
+constexpr uint32_t kCountMask = 0x1fffffffu;
 
 constexpr int kThreads = 512;           // threads per workgroup of the CCD kernel
-constexpr int kPartialDoubles = 6;      // per-workgroup partial record (see ccd_kernel.hip)
 
 enum KernelMode { kModeFit = 0, kModeEval = 1 };
 
@@ -25,6 +25,10 @@ struct LaunchShape {
     int grid = 0;
     int64_t ld = 0;
 };
+
+// Workgroups that fit on the device at once for the persistent kernel with
+// `ipt` rows per thread (0 if it does not fit); at most one per compute unit.
+int max_resident_groups(int ipt, int p, int *groups, std::string &err);
 
 // Arguments of one persistent launch (device pointers unless noted).
 struct CcdLaunch {
@@ -42,11 +46,10 @@ struct CcdLaunch {
     double *g1 = nullptr;            // [p] g' of each coordinate's last evaluation
     double *g2 = nullptr;            // [p] g''
     double *m2 = nullptr;            // [p] delta'(S[N2]/S[D])
-    double *result = nullptr;        // [8] see ccd_kernel.hip
-    void *agg = nullptr;             // [grid] tile aggregates
-    uint32_t *stat1 = nullptr;       // [grid]
-    double *part = nullptr;          // [2][grid][kPartialDoubles]
-    uint32_t *stat2 = nullptr;       // [2][grid]
+    double *result = nullptr;        // [kResultSlots] see ResultSlot
+    void *agg = nullptr;             // [grid][3] packets: tile aggregates for the look-back
+    void *part = nullptr;            // [grid][5] packets: per-workgroup partial sums
+    void *res = nullptr;             // [2] packets: the step broadcast by workgroup 0
     void *ctl = nullptr;             // control words
 };
 
@@ -55,8 +58,6 @@ size_t sync_scratch_bytes(int grid);
 // Carve the scratch block into the CcdLaunch fields (agg, stat1, part, stat2, ctl).
 void carve_sync_scratch(void *base, int grid, CcdLaunch &L);
 
-// Pick ipt and grid for n rows on the current device (one workgroup per CU at most).
-int choose_shape(int64_t n, int p, LaunchShape &shape, std::string &err);
 
 // Launch the persistent CCD / evaluation kernel; returns a hipError_t value.
 // Zeroes the synchronisation words first; records ev0/ev1 around the kernel if non-null.

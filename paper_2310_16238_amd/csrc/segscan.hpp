@@ -4,16 +4,23 @@
 // The operator is the flag-value operator of Sec. 2.6 with + as the base:
 //     (f_a, a) (+)s (f_b, b) = (f_a | f_b, f_b ? b : a + b)
 // It is associative but not commutative: the left operand is the earlier row.
-// (0, 0) is its identity on both sides.
+// (0, 0) -- all bits zero -- is its identity on both sides.
 //
 // Layout of work on the chip (ours, not the paper's): a workgroup of NW
 // wave64s owns a contiguous tile of rows, each thread IPT consecutive rows.
 // The tile's scan is
 //   thread-sequential fold over its IPT rows
-//   -> wave64 inclusive scan with cross-lane shuffles (6 steps)
-//   -> scan of the NW wave totals through LDS
-// and the carry between tiles comes from the preceding tiles' published
-// aggregates (look-back), read with agent-scope acquire loads.
+//   -> wave64 inclusive scan with DPP lane moves (row_shr 1/2/4/8 inside each
+//      16-lane row, then row_bcast 15 and 31 across rows: 6 steps, no LDS)
+//   -> the NW wave totals through LDS, folded by every wave (one barrier).
+//
+// Between workgroups, values travel as 16-byte packets (a double, the epoch
+// it belongs to, and a 32-bit side word) written and read with single
+// 16-byte vector accesses that go through to the device coherence point
+// (the sc1 cache policy).  A 16-byte aligned dwordx4 access is performed as
+// one transaction, so a reader sees a packet either whole-old or whole-new
+// and the epoch inside it says which: no flag, fence or cache write-back is
+// needed, and a wait costs one round trip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,162 +57,258 @@ __device__ __forceinline__ SegVal<K> seg_combine(const SegVal<K> &a, const SegVa
     return r;
 }
 
-template <int K>
-__device__ __forceinline__ SegVal<K> shfl_up_seg(const SegVal<K> &x, int off)
+// ------------------------------------------------------------------ DPP lane moves
+// dpp_ctrl codes (GFX9 encoding): row_shr:n = 0x110 + n, wave_shr:1 = 0x138,
+// row_bcast:15 = 0x142, row_bcast:31 = 0x143.  Lanes without a source (or in
+// rows masked off) receive 0, which is the identity of every operator here.
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    return __builtin_amdgcn_update_dpp(0.0, x, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS, int K>
+__device__ __forceinline__ SegVal<K> dpp_seg(const SegVal<K> &x)
 {
     SegVal<K> r;
-    r.f = __shfl_up(x.f, off, kWave);
+    r.f = dpp_u32<CTRL, ROWS>(x.f);
 #pragma unroll
-    for (int k = 0; k < K; ++k) r.v[k] = __shfl_up(x.v[k], off, kWave);
+    for (int k = 0; k < K; ++k) r.v[k] = dpp_f64<CTRL, ROWS>(x.v[k]);
     return r;
 }
 
+// Inclusive segmented scan across the 64 lanes (lane order = row order).
+// All 64 lanes must be active.
 template <int K>
-__device__ __forceinline__ SegVal<K> shfl_down_seg(const SegVal<K> &x, int off)
+__device__ __forceinline__ SegVal<K> wave_inclusive_scan(SegVal<K> x)
+{
+    x = seg_combine(dpp_seg<0x111, 0xF>(x), x);
+    x = seg_combine(dpp_seg<0x112, 0xF>(x), x);
+    x = seg_combine(dpp_seg<0x114, 0xF>(x), x);
+    x = seg_combine(dpp_seg<0x118, 0xF>(x), x);
+    x = seg_combine(dpp_seg<0x142, 0xA>(x), x);
+    x = seg_combine(dpp_seg<0x143, 0xC>(x), x);
+    return x;
+}
+
+// Lane i receives lane i-1's value; lane 0 receives the identity.
+template <int K>
+__device__ __forceinline__ SegVal<K> wave_shift_right(const SegVal<K> &x)
+{
+    return dpp_seg<0x138, 0xF, K>(x);
+}
+
+__device__ __forceinline__ double lane63_f64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int K>
+__device__ __forceinline__ SegVal<K> lane63_seg(const SegVal<K> &x)
 {
     SegVal<K> r;
-    r.f = __shfl_down(x.f, off, kWave);
+    r.f = (uint32_t)__builtin_amdgcn_readlane((int)x.f, 63);
 #pragma unroll
-    for (int k = 0; k < K; ++k) r.v[k] = __shfl_down(x.v[k], off, kWave);
+    for (int k = 0; k < K; ++k) r.v[k] = lane63_f64(x.v[k]);
     return r;
 }
 
-// Inclusive scan across the 64 lanes of a wave (lane order = row order).
-template <int K>
-__device__ __forceinline__ SegVal<K> wave_inclusive_scan(SegVal<K> x, int lane)
-{
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        SegVal<K> o = shfl_up_seg(x, off);
-        if (lane >= off) x = seg_combine(o, x);
-    }
-    return x;
-}
-
-// Ordered reduction where lane 63 holds the leftmost element and lane 0 the
-// rightmost: lane 0 ends with x[63] (+)s x[62] (+)s ... (+)s x[0].
-template <int K>
-__device__ __forceinline__ SegVal<K> wave_reduce_right_to_left(SegVal<K> x, int lane)
-{
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        SegVal<K> o = shfl_down_seg(x, off);
-        if (lane + off < kWave) x = seg_combine(o, x);
-    }
-    return x;
-}
-
+// Exclusive scan of one element per thread over the workgroup (NW waves).
+// Returns the thread's exclusive prefix; `total` receives the workgroup's
+// total in every thread.  One barrier.  `wtot` is LDS of NW elements that
+// must not be rewritten before a later barrier.
 template <int K, int NW>
-struct BlockScanSmem {
-    SegVal<K> wave_total[NW];
-    SegVal<K> wave_prefix[NW];
-    SegVal<K> block_total;
-};
-
-// Exclusive scan of one element per thread over the whole workgroup.
-// Returns the thread's exclusive prefix (identity for thread 0); the block
-// total is left in sm.block_total.  Contains two workgroup barriers.
-template <int K, int NW>
-__device__ __forceinline__ SegVal<K> block_exclusive_scan(const SegVal<K> &x, BlockScanSmem<K, NW> &sm)
+__device__ __forceinline__ SegVal<K> block_exclusive_scan(const SegVal<K> &x, SegVal<K> *wtot, SegVal<K> &total)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    SegVal<K> inc = wave_inclusive_scan(x, lane);
-    SegVal<K> exc = shfl_up_seg(inc, 1);
-    if (lane == 0) exc = seg_identity<K>();
-    if (lane == kWave - 1) sm.wave_total[w] = inc;
+    const SegVal<K> inc = wave_inclusive_scan(x);
+    const SegVal<K> exc = wave_shift_right(inc);
+    if (lane == kWave - 1) wtot[w] = inc;
     __syncthreads();
-    if (w == 0) {
-        SegVal<K> t = lane < NW ? sm.wave_total[lane] : seg_identity<K>();
-        SegVal<K> ti = wave_inclusive_scan(t, lane);
-        SegVal<K> te = shfl_up_seg(ti, 1);
-        if (lane == 0) te = seg_identity<K>();
-        if (lane < NW) sm.wave_prefix[lane] = te;
-        if (lane == NW - 1) sm.block_total = ti;
+    SegVal<K> pre = seg_identity<K>(), tot = seg_identity<K>();
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const SegVal<K> t = wtot[k];
+        if (k < w) pre = seg_combine(pre, t);
+        tot = seg_combine(tot, t);
     }
-    __syncthreads();
-    return seg_combine(sm.wave_prefix[w], exc);
+    total = tot;
+    return seg_combine(pre, exc);
 }
 
-// ---------------------------------------------------------------- cross-workgroup flags
+// ------------------------------------------------------------------ packets
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct alignas(16) Packet {
+    double v;
+    uint32_t epoch;
+    uint32_t aux;
+};
+
+__device__ __forceinline__ void packet_put(Packet *p, double v, uint32_t epoch, uint32_t aux)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const u32x4 d = {(unsigned)b, (unsigned)(b >> 32), epoch, aux};
+#if defined(__HIP_DEVICE_COMPILE__)   // the host pass never runs device code
+    asm volatile("global_store_dwordx4 %0, %1, off sc1" : : "v"(p), "v"(d) : "memory");
+#else
+    (void)p; (void)d;
+#endif
+}
+
+__device__ __forceinline__ double packet_value(const u32x4 &r)
+{
+    return __longlong_as_double((long long)(((unsigned long long)r.y << 32) | r.x));
+}
+
+// Read N consecutive packets in one round trip.
+template <int N>
+__device__ __forceinline__ void packets_get(const Packet *p, u32x4 (&r)[N]);
+
+template <>
+__device__ __forceinline__ void packets_get<1>(const Packet *p, u32x4 (&r)[1])
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("global_load_dwordx4 %0, %1, off sc1\n\ts_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]) : "v"(p) : "memory");
+#else
+    (void)p; (void)r;
+#endif
+}
+
+template <>
+__device__ __forceinline__ void packets_get<2>(const Packet *p, u32x4 (&r)[2])
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("global_load_dwordx4 %0, %2, off sc1\n\t"
+                 "global_load_dwordx4 %1, %2, off offset:16 sc1\n\ts_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]) : "v"(p) : "memory");
+#else
+    (void)p; (void)r;
+#endif
+}
+
+template <>
+__device__ __forceinline__ void packets_get<3>(const Packet *p, u32x4 (&r)[3])
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("global_load_dwordx4 %0, %3, off sc1\n\t"
+                 "global_load_dwordx4 %1, %3, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %3, off offset:32 sc1\n\ts_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]) : "v"(p) : "memory");
+#else
+    (void)p; (void)r;
+#endif
+}
+
+template <>
+__device__ __forceinline__ void packets_get<5>(const Packet *p, u32x4 (&r)[5])
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("global_load_dwordx4 %0, %5, off sc1\n\t"
+                 "global_load_dwordx4 %1, %5, off offset:16 sc1\n\t"
+                 "global_load_dwordx4 %2, %5, off offset:32 sc1\n\t"
+                 "global_load_dwordx4 %3, %5, off offset:48 sc1\n\t"
+                 "global_load_dwordx4 %4, %5, off offset:64 sc1\n\ts_waitcnt vmcnt(0)"
+                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]) : "v"(p) : "memory");
+#else
+    (void)p; (void)r;
+#endif
+}
 
 // Control words shared by all workgroups of one launch.
 struct SyncCtl {
     uint32_t abort;        // set to 1 by any workgroup whose wait timed out
-    uint32_t numeric;      // set to 1 if a risk-set sum left the FP64 normal range
-    uint32_t pad[62];
+    uint32_t pad[63];
 };
-
-__device__ __forceinline__ uint32_t load_acquire(const uint32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void store_release(uint32_t *p, uint32_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Wall-clock bound on any single wait (the constant-rate 100 MHz counter).
 constexpr uint64_t kWaitTicks = 200000000ull;   // 2 s
 
-// Wait until *flag == want.  Returns false (and raises ctl->abort) if the wait
-// exceeds kWaitTicks or another workgroup has raised abort; the caller must
-// then leave the kernel.  Every wait therefore ends.
-__device__ __forceinline__ bool wait_equal(const uint32_t *flag, uint32_t want, SyncCtl *ctl)
+__device__ __forceinline__ bool abort_raised(const SyncCtl *ctl)
 {
-    if (load_acquire(flag) == want) return true;
-    const uint64_t t0 = wall_clock64();
-    for (;;) {
-        __builtin_amdgcn_s_sleep(1);
-        if (load_acquire(flag) == want) return true;
-        if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+    return __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+}
+
+__device__ __forceinline__ void raise_abort(SyncCtl *ctl)
+{
+    __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until all N packets at p carry `epoch`; r receives them.  Returns
+// false (raising abort) after kWaitTicks, or if another workgroup aborted.
+// Every wait therefore ends.
+template <int N>
+__device__ __forceinline__ bool packets_wait(const Packet *p, uint32_t epoch, SyncCtl *ctl, u32x4 (&r)[N])
+{
+    uint64_t t0 = 0;
+    for (int spin = 0;; ++spin) {
+        packets_get<N>(p, r);
+        bool ready = true;
+#pragma unroll
+        for (int k = 0; k < N; ++k) ready = ready && (r[k].z == epoch);
+        if (ready) return true;
+        if (spin == 0) t0 = wall_clock64();
+        else if (abort_raised(ctl)) return false;
         if (wall_clock64() - t0 > kWaitTicks) {
-            __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            raise_abort(ctl);
             return false;
         }
+        __builtin_amdgcn_s_sleep(1);
     }
 }
 
-// Published tile aggregate for the look-back: flag and values as doubles.
-template <int K>
-struct alignas(16) TileAgg {
-    double f;
-    double v[K];
-};
+// ------------------------------------------------------------------ look-back
 
-// Carry into tile `b` = ordered combination of the aggregates of tiles
-// 0..b-1, stopping at the nearest tile that contains a head flag (everything
-// before it is discarded by the operator anyway).  Executed by one whole wave;
-// the result is valid in lane 0.  Returns false on abort.
+// Publish a tile aggregate as K packets: (v0, epoch, f), (v1, epoch), ...
 template <int K>
-__device__ __forceinline__ bool look_back(int b, uint32_t epoch, const TileAgg<K> *agg,
-                                          const uint32_t *status, SyncCtl *ctl, SegVal<K> &carry)
+__device__ __forceinline__ void publish_aggregate(Packet *slot, const SegVal<K> &a, uint32_t epoch)
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) packet_put(slot + k, a.v[k], epoch, k == 0 ? a.f : 0u);
+}
+
+// Carry into tile b: the ordered combination of the aggregates published by
+// tiles 0..b-1 for `epoch`, back to the nearest tile that contains a head
+// flag (the operator discards everything before it).  Executed by one whole
+// wave, 64 predecessors per round; lane 63 holds the nearest predecessor so
+// that lane order is row order.  The result is uniform across the wave.
+// Returns false on abort.
+template <int K>
+__device__ __forceinline__ bool look_back(int b, uint32_t epoch, const Packet *agg, SyncCtl *ctl,
+                                          SegVal<K> &carry)
 {
     const int lane = threadIdx.x & (kWave - 1);
     carry = seg_identity<K>();
-    int base = b - 1;
-    bool ok = true;
-    while (base >= 0) {
-        const int q = base - lane;
+    for (int top = b - 1; top >= 0; top -= kWave) {
+        const int q = top - (kWave - 1) + lane;
         SegVal<K> x = seg_identity<K>();
+        bool ok = true;
         if (q >= 0) {
-            ok = wait_equal(&status[q], epoch, ctl);
+            u32x4 r[K];
+            ok = packets_wait<K>(agg + K * (size_t)q, epoch, ctl, r);
             if (ok) {
-                x.f = agg[q].f != 0.0 ? 1u : 0u;
+                x.f = r[0].w;
 #pragma unroll
-                for (int k = 0; k < K; ++k) x.v[k] = agg[q].v[k];
+                for (int k = 0; k < K; ++k) x.v[k] = packet_value(r[k]);
             }
         }
         if (__any(!ok)) return false;
-        SegVal<K> win = wave_reduce_right_to_left(x, lane);
-        // broadcast lane 0's window total
-        win.f = __shfl(win.f, 0, kWave);
-#pragma unroll
-        for (int k = 0; k < K; ++k) win.v[k] = __shfl(win.v[k], 0, kWave);
+        const SegVal<K> win = lane63_seg(wave_inclusive_scan(x));
         carry = seg_combine(win, carry);
         if (win.f) break;
-        base -= kWave;
     }
     return true;
 }

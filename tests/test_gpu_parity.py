@@ -2,8 +2,11 @@
 
 Tolerances (FP64 on both sides, different summation orders):
 * integer work (canonical order, row words, scans of integers): bit-exact;
-* per-coordinate sums g', g'', -log L: |gpu - oracle| <= 1e-11 * max(1, E) where
-  E is the number of events (each sum has E terms of size O(1));
+* per-coordinate sums g', g'': |gpu - oracle| <= 1e-11 * max(1, E) where E is the
+  number of events (each sum has E terms of size O(1));
+* -log L: |gpu - oracle| <= 1e-11 * max(E, |-log L|): its terms are logs of risk-set
+  sums of up to n_k rows, and a sequential n_k-term sum has relative rounding error
+  up to n_k * 2^-53 (about 7e-11 for a 6e5-row stratum), correlated across events;
 * fitted beta: max|gpu - oracle| / max|oracle| <= 1e-10; l1 zero pattern identical.
 """
 import math
@@ -99,11 +102,11 @@ def test_coordinate_and_evaluate_parity(n, K):
             ref = orc.coord_terms(Xc, L, j, eta)
             assert abs(got[0] - ref["grad"]) <= tol, (j, got[0], ref["grad"])
             assert abs(got[1] - ref["hess"]) <= tol, (j, got[1], ref["hess"])
-            assert abs(got[2] - ref["obj"]) <= tol, (j, got[2], ref["obj"])
+            assert abs(got[2] - ref["obj"]) <= 1e-11 * max(d.event.sum(), abs(ref["obj"])), (j, got[2], ref["obj"])
             assert abs(got[3] - ref["m2"]) <= tol
         obj, g, h = m.evaluate(beta)
     fe = orc.full_eval(Xc, L, beta, want_info=False)
-    assert abs(obj - fe.objective) <= tol
+    assert abs(obj - fe.objective) <= 1e-11 * max(d.event.sum(), abs(fe.objective))
     np.testing.assert_allclose(g, fe.grad, rtol=0, atol=tol)
     np.testing.assert_allclose(h, fe.hess_diag, rtol=0, atol=tol)
 
