@@ -24,9 +24,12 @@
 //     the row layout so no stratum crosses a tile boundary, and the look-back
 //     never runs.
 //   * Per-coordinate sums are reduced per workgroup (DPP + LDS) and published
-//     as epoch-tagged packets; workgroup 0 gathers them in a fixed order,
-//     takes the scalar CCD step and publishes it; the other workgroups read
-//     that one packet pair.  Results are bit-reproducible.
+//     as epoch-tagged packets (two per workgroup, double-buffered by epoch
+//     parity).  Every workgroup gathers all of them -- one thread per
+//     workgroup, all in flight at once -- reduces them in a fixed order and
+//     takes the same scalar CCD step, so one memory round trip after the
+//     last workgroup publishes, everyone can move on.  Results are
+//     bit-reproducible.
 //   * exp() uses one global shift c (the largest X beta of the previous
 //     coordinate); ratios are shift-invariant and the objective adds c back.
 //     A risk-set sum outside [1e-300, 1e300] stops the fit with a flag.
@@ -45,8 +48,17 @@ struct Partial {
     uint32_t err;
 };
 
-// Flags carried in the step packet.
+// Stop flags decided after a coordinate.
 enum : uint32_t { kFlagNumeric = 1u, kFlagConverged = 2u, kFlagSweepLimit = 4u };
+
+// A published record is 4 packet slots:
+//   [0] (sum d S1/S0,              epoch, float(max eta))
+//   [1] (sum d (S2/S0 - (S1/S0)^2), epoch, float(sum d S2/S0), NaN if a risk-set sum left range)
+//   [2] (objective part,            epoch, 0)   -- only when the objective is wanted
+//   [3] (sum d S2/S0,               epoch, 0)   -- only when evaluating (exact value for the caller)
+// In a fit the side words only steer the shift and the degeneracy
+// threshold, for which single precision is ample.
+constexpr int kRecPackets = 4;
 
 namespace {
 
@@ -57,7 +69,7 @@ size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t sync_scratch_bytes(int grid)
 {
     return up256(sizeof(SyncCtl)) + up256(sizeof(Packet) * 3 * (size_t)grid) +
-           up256(sizeof(Packet) * kPN * (size_t)grid) + up256(sizeof(Packet) * 2);
+           up256(sizeof(Packet) * kRecPackets * 2 * (size_t)grid);
 }
 
 void carve_sync_scratch(void *base, int grid, CcdLaunch &L)
@@ -68,8 +80,7 @@ void carve_sync_scratch(void *base, int grid, CcdLaunch &L)
     L.agg = c;
     c += up256(sizeof(Packet) * 3 * (size_t)grid);
     L.part = c;
-    c += up256(sizeof(Packet) * kPN * (size_t)grid);
-    L.res = c;
+    L.res = nullptr;
 }
 
 // ------------------------------------------------------------------ small helpers
@@ -167,10 +178,20 @@ __device__ __forceinline__ Partial block_reduce_partial(const Partial &x, Partia
     return tot;
 }
 
-__device__ __forceinline__ void publish_partial(Packet *slot, const Partial &x, uint32_t epoch)
+// Publish this workgroup's record for `epoch` (thread 0); `extra` adds
+// slots [2] and [3].
+__device__ __forceinline__ void publish_partial(const PacketArray &part, int G, int b, const Partial &x,
+                                                uint32_t epoch, bool extra)
 {
-#pragma unroll
-    for (int k = 0; k < kPN; ++k) packet_put(slot + k, x.v[k], epoch, k == 0 ? x.err : 0u);
+    const uint32_t slot = (uint32_t)(kRecPackets * ((epoch & 1u) * (uint32_t)G + (uint32_t)b));
+    const float emax = (float)x.v[kPEtaMax];
+    const float m2 = x.err ? __builtin_nanf("") : (float)fmin(x.v[kPM2], 3.0e38);
+    packet_put(part, slot, x.v[kPC1], epoch, __float_as_uint(emax));
+    packet_put(part, slot + 1, x.v[kPC2], epoch, __float_as_uint(m2));
+    if (extra) {
+        packet_put(part, slot + 2, x.v[kPObj], epoch, 0u);
+        packet_put(part, slot + 3, x.v[kPM2], epoch, 0u);
+    }
 }
 
 // One CCD coordinate update (Sec. 2.4).  Newton step on the smooth part; with
@@ -212,28 +233,53 @@ __device__ __forceinline__ double ccd_step(double beta, double g1, double g2, do
     return s;
 }
 
-// Workgroup 0 gathers the partial records of all G workgroups for `epoch`
-// (one thread per workgroup) and reduces them in workgroup order.  Returns
-// false (uniformly) if a wait was aborted.
-template <int BLOCK>
-__device__ __forceinline__ bool gather_partials(const Packet *part, int G, uint32_t epoch, SyncCtl *ctl,
-                                                Partial *red, Partial &total)
+// Every workgroup gathers the records of all G <= 256 workgroups for
+// `epoch`: thread q waits for workgroup q's record (all in flight at once),
+// each wave reduces its 64 records in lane order and every thread folds the
+// wave totals in wave order -- a fixed order, so all workgroups obtain the
+// same bits regardless of arrival times.  Called by every thread; returns
+// false (uniformly) on abort.
+template <int NW>
+__device__ __forceinline__ bool gather_partials(const PacketArray &part, int G, uint32_t epoch, bool extra,
+                                                SyncCtl *ctl, Partial *red, int *abort_flag, Partial &total)
 {
-    constexpr int NW = BLOCK / kWave;
-    Partial x = partial_identity();
-    bool ok = true;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int q = threadIdx.x;
+    Partial x = partial_identity();
     if (q < G) {
-        u32x4 r[kPN];
-        ok = packets_wait<kPN>(part + kPN * (size_t)q, epoch, ctl, r);
+        const uint32_t slot = (uint32_t)(kRecPackets * ((epoch & 1u) * (uint32_t)G + (uint32_t)q));
+        bool ok;
+        u32x4 r[4];
+        if (extra) {
+            ok = packets_wait<4>(part, slot, epoch, ctl, r);
+        } else {
+            u32x4 r2[2];
+            ok = packets_wait<2>(part, slot, epoch, ctl, r2);
+            r[0] = r2[0];
+            r[1] = r2[1];
+            r[2] = r2[0];
+            r[3] = r2[0];
+        }
         if (ok) {
-#pragma unroll
-            for (int k = 0; k < kPN; ++k) x.v[k] = packet_value(r[k]);
-            x.err = r[0].w;
+            x.v[kPC1] = packet_value(r[0]);
+            x.v[kPEtaMax] = (double)__uint_as_float(r[0].w);
+            x.v[kPC2] = packet_value(r[1]);
+            const float m2 = __uint_as_float(r[1].w);
+            x.v[kPM2] = extra ? packet_value(r[3]) : (double)m2;
+            x.err = (m2 == m2) ? 0u : 1u;
+            x.v[kPObj] = extra ? packet_value(r[2]) : 0.0;
+        } else {
+            *abort_flag = 1;
         }
     }
-    if (__syncthreads_or(ok ? 0 : 1)) return false;
-    total = block_reduce_partial<NW>(x, red);
+    const Partial wr = wave_reduce_partial(x);
+    if (lane == kWave - 1) red[w] = wr;
+    __syncthreads();
+    if (*abort_flag) return false;
+    Partial tot = red[0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) partial_combine(tot, red[k]);
+    total = tot;
     return true;
 }
 
@@ -244,10 +290,11 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 {
     constexpr int NW = BLOCK / kWave;
     static_assert(BLOCK % kWave == 0 && NW <= 16, "block shape");
-    extern __shared__ double smem_dyn[];     // workgroup 0: beta, trust, gamma
+    extern __shared__ double smem_dyn[];     // beta, trust, gamma (the same in every workgroup)
     __shared__ SegVal<3> s_wtot[NW];
-    __shared__ Partial s_red[NW];
-    __shared__ SegVal<3> s_carry;
+    __shared__ Partial s_red[NW];        // this workgroup's own reduction
+    __shared__ Partial s_gat[NW];        // the gathered records
+    __shared__ SegVal<3> s_win[kMaxGroups / kWave];
     __shared__ double s_step, s_shift;
     __shared__ uint32_t s_flags;
     __shared__ int s_abort;
@@ -255,23 +302,20 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
     const int p = L.p;
     const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
     const int lane = t & (kWave - 1), w = t / kWave;
-    const bool reducer = (b == 0);
+    const bool writer = (b == 0);   // workgroup 0 writes the outputs
     SyncCtl *ctl = static_cast<SyncCtl *>(L.ctl);
-    Packet *agg = static_cast<Packet *>(L.agg);
-    Packet *part = static_cast<Packet *>(L.part);
-    Packet *res = static_cast<Packet *>(L.res);
+    const PacketArray agg = packet_array(L.agg, sizeof(Packet) * 3 * (size_t)G);
+    const PacketArray part = packet_array(L.part, sizeof(Packet) * kRecPackets * 2 * (size_t)G);
     const int64_t ld = (int64_t)G * BLOCK * IPT;
     const int64_t tile0 = (int64_t)b * BLOCK * IPT;
     const int64_t row0 = tile0 + (int64_t)t * IPT;
     const bool fit = (L.mode == kModeFit);
 
     double *sbeta = smem_dyn, *strust = smem_dyn + p, *sgamma = smem_dyn + 2 * p;
-    if (reducer) {
-        for (int j = t; j < p; j += BLOCK) {
-            sbeta[j] = L.beta[j];
-            strust[j] = 1.0;
-            sgamma[j] = L.gamma[j];
-        }
+    for (int j = t; j < p; j += BLOCK) {
+        sbeta[j] = L.beta[j];
+        strust[j] = 1.0;
+        sgamma[j] = L.gamma[j];
     }
     if (t == 0) s_abort = 0;
     uint32_t meta[IPT];
@@ -301,22 +345,11 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
         for (int i = 0; i < IPT; ++i)
             if (!(meta[i] & kPadBit)) v.v[kPEtaMax] = fmax(v.v[kPEtaMax], eta[i]);
         v = block_reduce_partial<NW>(v, s_red);
-        if (t == 0) publish_partial(part + kPN * (size_t)b, v, epoch);
-        if (reducer) {
-            Partial tot;
-            if (!gather_partials<BLOCK>(part, G, epoch, ctl, s_red, tot)) return;
-            if (t == 0) {
-                packet_put(res, 0.0, epoch, 0u);
-                packet_put(res + 1, tot.v[kPEtaMax], epoch, 0u);
-                s_shift = tot.v[kPEtaMax];
-            }
-        } else if (t == 0) {
-            u32x4 r[2];
-            if (packets_wait<2>(res, epoch, ctl, r)) s_shift = packet_value(r[1]);
-            else s_abort = 1;
-        }
+        if (t == 0) publish_partial(part, G, b, v, epoch, false);
+        Partial tot;
+        if (!gather_partials<NW>(part, G, epoch, false, ctl, s_gat, &s_abort, tot)) return;
+        if (t == 0) s_shift = tot.v[kPEtaMax];
         __syncthreads();
-        if (s_abort) return;
     }
     double c = s_shift;
 
@@ -337,7 +370,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             double xn[IPT];
             load_rows<IPT>(xn, L.x + (int64_t)jn * ld + row0);
             double qj = 0.0;
-            if (reducer && t == 0) qj = L.q[j];
+            if (t == 0) qj = L.q[j];
             const bool want_obj = (j == jfirst);
 
             // pass 1: D, N1, N2 of the thread's rows and their fold
@@ -355,19 +388,11 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             }
             SegVal<3> btot;
             SegVal<3> exc = block_exclusive_scan<3, NW>(tagg, s_wtot, btot);
-            if (t == 0) publish_aggregate<3>(agg + 3 * (size_t)b, btot, epoch);
+            if (t == 0) publish_aggregate<3>(agg, b, btot, epoch);
             if (!tile_head) {
-                if (w == 0) {
-                    SegVal<3> carry;
-                    const bool ok = look_back<3>(b, epoch, agg, ctl, carry);
-                    if (lane == 0) {
-                        s_carry = carry;
-                        if (!ok) s_abort = 1;
-                    }
-                }
-                __syncthreads();
-                if (s_abort) return;
-                exc = seg_combine(s_carry, exc);
+                SegVal<3> carry;
+                if (!look_back<3>(b, epoch, agg, ctl, s_win, &s_abort, carry)) return;
+                exc = seg_combine(carry, exc);
             }
 
             // pass 2: inclusive prefixes at group ends -> per-coordinate sums
@@ -397,56 +422,46 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
                 if (want_obj && (meta[i] & kEventBit)) v.v[kPObj] -= eta[i];
             }
             v = block_reduce_partial<NW>(v, s_red);
-            if (t == 0) publish_partial(part + kPN * (size_t)b, v, epoch);
+            const bool extra = want_obj || !fit;
+            if (t == 0) publish_partial(part, G, b, v, epoch, extra);
 
-            if (reducer) {
-                Partial tot;
-                if (!gather_partials<BLOCK>(part, G, epoch, ctl, s_red, tot)) return;
-                if (t == 0) {
-                    uint32_t flags = tot.err ? kFlagNumeric : 0u;
-                    const double g1 = -qj + tot.v[kPC1], g2 = tot.v[kPC2], m2 = tot.v[kPM2];
+            Partial tot;
+            if (!gather_partials<NW>(part, G, epoch, extra, ctl, s_gat, &s_abort, tot)) return;
+            if (t == 0) {
+                uint32_t flags = tot.err ? kFlagNumeric : 0u;
+                const double g1 = -qj + tot.v[kPC1], g2 = tot.v[kPC2], m2 = tot.v[kPM2];
+                if (writer) {
                     L.g1[j] = g1;
                     L.g2[j] = g2;
                     L.m2[j] = m2;
-                    if (want_obj) {
-                        objective = tot.v[kPObj];
-                        if (fit)
-                            for (int k = 0; k < p; ++k) objective += sgamma[k] * fabs(sbeta[k]);
-                    }
-                    double step = 0.0;
-                    if (fit && !(flags & kFlagNumeric)) {
-                        int pin = 0;
-                        step = ccd_step(sbeta[j], g1, g2, m2, sgamma[j], &strust[j], &pin);
-                        sbeta[j] += step;
-                        maxstep = fmax(maxstep, fabs(step));
-                        pinned += pin;
-                        if (j == jend - 1) {
-                            ++sweeps;
-                            double bmax = 1.0;
-                            for (int k = 0; k < p; ++k) bmax = fmax(bmax, fabs(sbeta[k]));
-                            if (maxstep <= L.tol * bmax) flags |= kFlagConverged;
-                            else if (sweeps >= L.max_sweeps) flags |= kFlagSweepLimit;
-                            last_maxstep = maxstep;
-                            pinned_last = pinned;
-                            maxstep = 0.0;
-                            pinned = 0;
-                        }
-                    }
-                    packet_put(res, step, epoch, flags);
-                    packet_put(res + 1, tot.v[kPEtaMax], epoch, 0u);
-                    s_step = step;
-                    s_shift = tot.v[kPEtaMax];
-                    s_flags = flags;
                 }
-            } else if (t == 0) {
-                u32x4 r[2];
-                if (packets_wait<2>(res, epoch, ctl, r)) {
-                    s_step = packet_value(r[0]);
-                    s_flags = r[0].w;
-                    s_shift = packet_value(r[1]);
-                } else {
-                    s_abort = 1;
+                if (want_obj) {
+                    objective = tot.v[kPObj];
+                    if (fit)
+                        for (int k = 0; k < p; ++k) objective += sgamma[k] * fabs(sbeta[k]);
                 }
+                double step = 0.0;
+                if (fit && !(flags & kFlagNumeric)) {
+                    int pin = 0;
+                    step = ccd_step(sbeta[j], g1, g2, m2, sgamma[j], &strust[j], &pin);
+                    sbeta[j] += step;
+                    maxstep = fmax(maxstep, fabs(step));
+                    pinned += pin;
+                    if (j == jend - 1) {
+                        ++sweeps;
+                        double bmax = 1.0;
+                        for (int k = 0; k < p; ++k) bmax = fmax(bmax, fabs(sbeta[k]));
+                        if (maxstep <= L.tol * bmax) flags |= kFlagConverged;
+                        else if (sweeps >= L.max_sweeps) flags |= kFlagSweepLimit;
+                        last_maxstep = maxstep;
+                        pinned_last = pinned;
+                        maxstep = 0.0;
+                        pinned = 0;
+                    }
+                }
+                s_step = step;
+                s_shift = tot.v[kPEtaMax];
+                s_flags = flags;
             }
             __syncthreads();
             if (s_abort) return;
@@ -471,7 +486,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
         if (stop || !fit) break;
     }
 
-    if (reducer) {
+    if (writer) {
         if (fit)
             for (int j = t; j < p; j += BLOCK) L.beta[j] = sbeta[j];
         if (t == 0) {
@@ -492,12 +507,13 @@ constexpr int kScanBlock = 1024;
 
 template <int IPT>
 __global__ __launch_bounds__(kScanBlock) void segscan_kernel(const double *a, const uint8_t *head,
-                                                             double *out, int64_t n, Packet *agg,
+                                                             double *out, int64_t n, Packet *aggp,
                                                              SyncCtl *ctl)
 {
+    const PacketArray agg = packet_array(aggp, sizeof(Packet) * gridDim.x);
     constexpr int NW = kScanBlock / kWave;
     __shared__ SegVal<1> s_wtot[NW];
-    __shared__ SegVal<1> s_carry;
+    __shared__ SegVal<1> s_win[kMaxGroups / kWave];
     __shared__ int s_abort;
     const int b = blockIdx.x, t = threadIdx.x;
     const int lane = t & (kWave - 1), w = t / kWave;
@@ -521,20 +537,12 @@ __global__ __launch_bounds__(kScanBlock) void segscan_kernel(const double *a, co
     const uint32_t epoch = 1;
     SegVal<1> btot;
     SegVal<1> exc = block_exclusive_scan<1, NW>(tagg, s_wtot, btot);
-    if (t == 0) publish_aggregate<1>(agg + b, btot, epoch);
+    if (t == 0) publish_aggregate<1>(agg, b, btot, epoch);
     const bool tile_head = tile0 >= n || tile0 == 0 || head[tile0] != 0;
     if (!tile_head) {
-        if (w == 0) {
-            SegVal<1> carry;
-            const bool ok = look_back<1>(b, epoch, agg, ctl, carry);
-            if (lane == 0) {
-                s_carry = carry;
-                if (!ok) s_abort = 1;
-            }
-        }
-        __syncthreads();
-        if (s_abort) return;
-        exc = seg_combine(s_carry, exc);
+        SegVal<1> carry;
+        if (!look_back<1>(b, epoch, agg, ctl, s_win, &s_abort, carry)) return;
+        exc = seg_combine(carry, exc);
     }
     SegVal<1> run = exc;
 #pragma unroll
@@ -592,7 +600,7 @@ int max_resident_groups(int ipt, int p, int *groups, std::string &err)
         err = "occupancy query failed";
         return -3;
     }
-    *groups = blocks >= 1 ? cus : 0;   // one workgroup per compute unit
+    *groups = blocks >= 1 ? (cus < kMaxGroups ? cus : kMaxGroups) : 0;   // one workgroup per compute unit
     return 0;
 }
 
@@ -631,7 +639,7 @@ int segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, hipS
     int64_t grid = 0;
     for (int c : ipts) {
         grid = (n + (int64_t)kScanBlock * c - 1) / ((int64_t)kScanBlock * c);
-        if (grid <= cus) {
+        if (grid <= cus && grid <= kMaxGroups) {
             ipt = c;
             break;
         }

@@ -15,6 +15,7 @@ constexpr uint32_t kPadBit = 0x20000000u;     // device layout only: a padding r
 constexpr uint32_t kCountMask = 0x1fffffffu;
 
 constexpr int kThreads = 512;           // threads per workgroup of the CCD kernel
+constexpr int kMaxGroups = 256;         // workgroups of one persistent launch (one per compute unit)
 
 enum KernelMode { kModeFit = 0, kModeEval = 1 };
 

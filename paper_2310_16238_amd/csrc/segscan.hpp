@@ -16,7 +16,7 @@
 //
 // Between workgroups, values travel as 16-byte packets (a double, the epoch
 // it belongs to, and a 32-bit side word) written and read with single
-// 16-byte vector accesses that go through to the device coherence point
+// 16-byte buffer accesses that go through to the device coherence point
 // (the sc1 cache policy).  A 16-byte aligned dwordx4 access is performed as
 // one transaction, so a reader sees a packet either whole-old or whole-new
 // and the epoch inside it says which: no flag, fence or cache write-back is
@@ -157,75 +157,43 @@ struct alignas(16) Packet {
     uint32_t aux;
 };
 
-__device__ __forceinline__ void packet_put(Packet *p, double v, uint32_t epoch, uint32_t aux)
+// A packet array addressed through a buffer resource: accesses beyond
+// `bytes` are dropped (stores) or read as zero (loads) by the hardware, so a
+// wrong index can never touch other memory.
+struct PacketArray {
+    __amdgpu_buffer_rsrc_t rsrc;
+};
+
+// gfx9 raw-buffer descriptor word 3 (32-bit data format, no swizzle)
+constexpr int kBufferWord3 = 0x00020000;
+// cache-policy bits of the buffer builtins: sc1 = device-coherent; bit 31 = volatile
+constexpr int kPolicyCoherent = 1 << 4;
+constexpr int kPolicyVolatile = 1 << 31;
+
+__device__ __forceinline__ PacketArray packet_array(const void *base, size_t bytes)
+{
+    PacketArray a;
+    a.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufferWord3);
+    return a;
+}
+
+__device__ __forceinline__ void packet_put(const PacketArray &a, uint32_t index, double v, uint32_t epoch,
+                                           uint32_t aux)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
     const u32x4 d = {(unsigned)b, (unsigned)(b >> 32), epoch, aux};
-#if defined(__HIP_DEVICE_COMPILE__)   // the host pass never runs device code
-    asm volatile("global_store_dwordx4 %0, %1, off sc1" : : "v"(p), "v"(d) : "memory");
-#else
-    (void)p; (void)d;
-#endif
+    __builtin_amdgcn_raw_buffer_store_b128(d, a.rsrc, (int)(index * sizeof(Packet)), 0, kPolicyCoherent);
+}
+
+__device__ __forceinline__ u32x4 packet_get(const PacketArray &a, uint32_t index)
+{
+    return __builtin_amdgcn_raw_buffer_load_b128(a.rsrc, (int)(index * sizeof(Packet)), 0,
+                                                 kPolicyCoherent | kPolicyVolatile);
 }
 
 __device__ __forceinline__ double packet_value(const u32x4 &r)
 {
     return __longlong_as_double((long long)(((unsigned long long)r.y << 32) | r.x));
-}
-
-// Read N consecutive packets in one round trip.
-template <int N>
-__device__ __forceinline__ void packets_get(const Packet *p, u32x4 (&r)[N]);
-
-template <>
-__device__ __forceinline__ void packets_get<1>(const Packet *p, u32x4 (&r)[1])
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    asm volatile("global_load_dwordx4 %0, %1, off sc1\n\ts_waitcnt vmcnt(0)"
-                 : "=&v"(r[0]) : "v"(p) : "memory");
-#else
-    (void)p; (void)r;
-#endif
-}
-
-template <>
-__device__ __forceinline__ void packets_get<2>(const Packet *p, u32x4 (&r)[2])
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    asm volatile("global_load_dwordx4 %0, %2, off sc1\n\t"
-                 "global_load_dwordx4 %1, %2, off offset:16 sc1\n\ts_waitcnt vmcnt(0)"
-                 : "=&v"(r[0]), "=&v"(r[1]) : "v"(p) : "memory");
-#else
-    (void)p; (void)r;
-#endif
-}
-
-template <>
-__device__ __forceinline__ void packets_get<3>(const Packet *p, u32x4 (&r)[3])
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    asm volatile("global_load_dwordx4 %0, %3, off sc1\n\t"
-                 "global_load_dwordx4 %1, %3, off offset:16 sc1\n\t"
-                 "global_load_dwordx4 %2, %3, off offset:32 sc1\n\ts_waitcnt vmcnt(0)"
-                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]) : "v"(p) : "memory");
-#else
-    (void)p; (void)r;
-#endif
-}
-
-template <>
-__device__ __forceinline__ void packets_get<5>(const Packet *p, u32x4 (&r)[5])
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    asm volatile("global_load_dwordx4 %0, %5, off sc1\n\t"
-                 "global_load_dwordx4 %1, %5, off offset:16 sc1\n\t"
-                 "global_load_dwordx4 %2, %5, off offset:32 sc1\n\t"
-                 "global_load_dwordx4 %3, %5, off offset:48 sc1\n\t"
-                 "global_load_dwordx4 %4, %5, off offset:64 sc1\n\ts_waitcnt vmcnt(0)"
-                 : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]) : "v"(p) : "memory");
-#else
-    (void)p; (void)r;
-#endif
 }
 
 // Control words shared by all workgroups of one launch.
@@ -236,6 +204,8 @@ struct SyncCtl {
 
 // Wall-clock bound on any single wait (the constant-rate 100 MHz counter).
 constexpr uint64_t kWaitTicks = 200000000ull;   // 2 s
+// Polls between checks of the clock and of the abort word.
+constexpr int kPollsPerCheck = 256;
 
 __device__ __forceinline__ bool abort_raised(const SyncCtl *ctl)
 {
@@ -247,69 +217,90 @@ __device__ __forceinline__ void raise_abort(SyncCtl *ctl)
     __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait until all N packets at p carry `epoch`; r receives them.  Returns
-// false (raising abort) after kWaitTicks, or if another workgroup aborted.
-// Every wait therefore ends.
-template <int N>
-__device__ __forceinline__ bool packets_wait(const Packet *p, uint32_t epoch, SyncCtl *ctl, u32x4 (&r)[N])
-{
-    uint64_t t0 = 0;
-    for (int spin = 0;; ++spin) {
-        packets_get<N>(p, r);
-        bool ready = true;
-#pragma unroll
-        for (int k = 0; k < N; ++k) ready = ready && (r[k].z == epoch);
-        if (ready) return true;
-        if (spin == 0) t0 = wall_clock64();
-        else if (abort_raised(ctl)) return false;
-        if (wall_clock64() - t0 > kWaitTicks) {
-            raise_abort(ctl);
-            return false;
+// Bounded wait used by every poll loop: call once per failed poll; returns
+// false once the wait has exceeded kWaitTicks (raising abort) or another
+// workgroup has aborted.  Every wait therefore ends.
+struct WaitBudget {
+    uint64_t t0;
+    int polls;
+    __device__ __forceinline__ WaitBudget() : t0(wall_clock64()), polls(0) {}
+    __device__ __forceinline__ bool keep_waiting(SyncCtl *ctl)
+    {
+        if (++polls % kPollsPerCheck == 0) {
+            if (abort_raised(ctl)) return false;
+            if (wall_clock64() - t0 > kWaitTicks) {
+                raise_abort(ctl);
+                return false;
+            }
         }
         __builtin_amdgcn_s_sleep(1);
+        return true;
+    }
+};
+
+// Wait until the N packets starting at `index` all carry `epoch`.
+template <int N>
+__device__ __forceinline__ bool packets_wait(const PacketArray &a, uint32_t index, uint32_t epoch, SyncCtl *ctl,
+                                             u32x4 (&r)[N])
+{
+    WaitBudget wb;
+    for (;;) {
+        bool ready = true;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            r[k] = packet_get(a, index + k);
+            ready = ready && (r[k].z == epoch);
+        }
+        if (ready) return true;
+        if (!wb.keep_waiting(ctl)) return false;
     }
 }
 
 // ------------------------------------------------------------------ look-back
 
-// Publish a tile aggregate as K packets: (v0, epoch, f), (v1, epoch), ...
+// Publish a tile aggregate as K packets at index K*b: (v0, epoch, f), (v1, epoch), ...
 template <int K>
-__device__ __forceinline__ void publish_aggregate(Packet *slot, const SegVal<K> &a, uint32_t epoch)
+__device__ __forceinline__ void publish_aggregate(const PacketArray &agg, int b, const SegVal<K> &a, uint32_t epoch)
 {
 #pragma unroll
-    for (int k = 0; k < K; ++k) packet_put(slot + k, a.v[k], epoch, k == 0 ? a.f : 0u);
+    for (int k = 0; k < K; ++k) packet_put(agg, (uint32_t)(K * b + k), a.v[k], epoch, k == 0 ? a.f : 0u);
 }
 
 // Carry into tile b: the ordered combination of the aggregates published by
-// tiles 0..b-1 for `epoch`, back to the nearest tile that contains a head
-// flag (the operator discards everything before it).  Executed by one whole
-// wave, 64 predecessors per round; lane 63 holds the nearest predecessor so
-// that lane order is row order.  The result is uniform across the wave.
-// Returns false on abort.
+// tiles 0..b-1 for `epoch`.  Called by every thread of the workgroup (b
+// uniform, 1 <= b <= 256).  Wave k reads the window of predecessors
+// [b - 64(k+1), b - 64k - 1] -- all windows in flight at once -- with lane
+// order equal to row order, scans it, and leaves the window total in
+// win[k]; after one barrier every thread folds the windows from the
+// farthest to the nearest.  Heads inside a window cut the carry as the
+// operator requires.  Returns false (uniformly) on abort.
 template <int K>
-__device__ __forceinline__ bool look_back(int b, uint32_t epoch, const Packet *agg, SyncCtl *ctl,
-                                          SegVal<K> &carry)
+__device__ __forceinline__ bool look_back(int b, uint32_t epoch, const PacketArray &agg, SyncCtl *ctl,
+                                          SegVal<K> *win, int *abort_flag, SegVal<K> &carry)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    carry = seg_identity<K>();
-    for (int top = b - 1; top >= 0; top -= kWave) {
-        const int q = top - (kWave - 1) + lane;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int nwin = (b + kWave - 1) / kWave;
+    if (w < nwin) {
+        const int q = b - kWave * (w + 1) + lane;
         SegVal<K> x = seg_identity<K>();
         bool ok = true;
         if (q >= 0) {
             u32x4 r[K];
-            ok = packets_wait<K>(agg + K * (size_t)q, epoch, ctl, r);
+            ok = packets_wait<K>(agg, (uint32_t)(K * q), epoch, ctl, r);
             if (ok) {
                 x.f = r[0].w;
 #pragma unroll
                 for (int k = 0; k < K; ++k) x.v[k] = packet_value(r[k]);
             }
         }
-        if (__any(!ok)) return false;
-        const SegVal<K> win = lane63_seg(wave_inclusive_scan(x));
-        carry = seg_combine(win, carry);
-        if (win.f) break;
+        if (!ok) *abort_flag = 1;
+        const SegVal<K> inc = wave_inclusive_scan(x);
+        if (lane == kWave - 1) win[w] = inc;
     }
+    __syncthreads();
+    if (*abort_flag) return false;
+    carry = seg_identity<K>();
+    for (int k = nwin - 1; k >= 0; --k) carry = seg_combine(carry, win[k]);
     return true;
 }
 
