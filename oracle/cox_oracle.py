@@ -294,6 +294,8 @@ class FullEval:
     grad: np.ndarray
     hess_diag: np.ndarray
     info: np.ndarray | None
+    info_first: np.ndarray | None = None    # X' diag(w Lambda) X
+    info_second: np.ndarray | None = None   # sum_g d_g xbar_g xbar_g'
 
 
 def full_eval(Xc, layout: Layout, beta, want_info: bool = True) -> FullEval:
@@ -324,10 +326,12 @@ def full_eval(Xc, layout: Layout, beta, want_info: bool = True) -> FullEval:
     obj = float(-(ev @ eta) + d @ (np.log(S0) + m))
     grad = -(Xc.T @ ev) + d @ xbar
     hdiag = d @ (S2 / S0[:, None] - xbar * xbar)
-    info = None
+    info = first = second = None
     if want_info:
-        info = (Xc.T * wl) @ Xc - (xbar.T * d) @ xbar
-    return FullEval(objective=obj, grad=grad, hess_diag=hdiag, info=info)
+        first = (Xc.T * wl) @ Xc
+        second = (xbar.T * d) @ xbar
+        info = first - second
+    return FullEval(objective=obj, grad=grad, hess_diag=hdiag, info=info, info_first=first, info_second=second)
 
 
 def degenerate_columns(Xc, layout: Layout, beta=None) -> np.ndarray:

@@ -83,6 +83,24 @@ def _design_t3(rng, n, p):
     return X
 
 
+def _design_mixed(rng, n, p):
+    """Two common factors: x_i = z_i + f_i1 a_1 + f_i2 a_2, column j scaled by 2^(e_j).
+
+    z_i iid N(0, I_p), f iid N(0, 1), a_1, a_2 iid N(0, I_p) loadings and
+    e_j uniform in {-3..3}.  The correlation I + a_1 a_1' + a_2 a_2' makes every
+    entry of X'X of the order of its diagonal, with varied signs, so a
+    misplaced entry of a cross-product stands out, while the condition number
+    stays of the order of p.
+    """
+    a = rng.standard_normal((2, p))
+    X = np.empty((n, p), dtype=np.float64, order="F")
+    f = rng.standard_normal((n, 2))
+    for j in range(p):
+        X[:, j] = rng.standard_normal(n) + f @ a[:, j]
+    X *= np.exp2(rng.integers(-3, 4, size=p)).astype(np.float64)
+    return X
+
+
 def _design_binary(rng, n, p, density):
     """Binary indicators with P(x=1) = density (Sec. 3.1 uses 5% ones)."""
     X = np.empty((n, p), dtype=np.float64, order="F")
@@ -136,6 +154,8 @@ def make(design: str, n: int, p: int, K: int, seed: int, *, beta=None,
         X = _design_t3(rng, n, p)
     elif design == "binary":
         X = _design_binary(rng, n, p, density)
+    elif design == "mixed":
+        X = _design_mixed(rng, n, p)
     else:
         raise ValueError(f"unknown design {design!r}")
     if beta is not None:
@@ -183,3 +203,9 @@ def config_paper(n: int = 100_000, p: int = 1000, K: int = 5000, seed: int = 5) 
     """Sec. 3.1 shape: binary X with 5% ones, beta ~ N(0,1) x Bernoulli(0.2), gamma = sqrt(2)."""
     return make("binary", n, p, K, seed, beta_kind="normal", beta_sd=1.0, beta_nonzero=0.2,
                 density=0.05, gamma=math.sqrt(2.0), name=f"paper-n{n}-p{p}-K{K}")
+
+
+def config_mixed(n: int = 1_000_000, p: int = 200, K: int = 50_000, seed: int = 2) -> CoxData:
+    """The AR(1) design at P = 200 for the reduced-precision Newton fit (seed 2)."""
+    return make("ar1", n, p, K, seed, beta_kind="normal", beta_sd=0.5, gamma=0.0,
+                name=f"mixed-n{n}-p{p}-K{K}")
