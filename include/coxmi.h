@@ -44,8 +44,12 @@ extern "C" {
 #define COX_EUNSUPPORTED (-5) /* option or size this build does not support */
 
 /* ---------------------------------------------------------------- options */
-enum { COX_CCD = 0 };                 /* optimiser: cyclic coordinate descent (Sec. 2.4) */
-enum { COX_F64 = 0 };                 /* precision of X on the device */
+/* optimiser: cyclic coordinate descent (Sec. 2.4), or Newton steps on the full
+ * information matrix with an FP64 Cholesky solve and iterative refinement */
+enum { COX_CCD = 0, COX_NEWTON_REFINE = 1 };
+/* storage precision of X for the information-matrix contraction (the
+ * gradient and objective are always formed in FP64) */
+enum { COX_F64 = 0, COX_F32 = 1, COX_BF16 = 2, COX_FP8_E4M3 = 3 };
 enum { COX_BRESLOW = 0 };             /* tie handling (see above) */
 
 typedef struct cox_handle cox_handle; /* opaque; owns all device state of one data set */
@@ -63,18 +67,18 @@ typedef struct {
 typedef struct {
     double gamma;             /* l1 strength gamma >= 0 (Sec. 2.1); 0 = unpenalised */
     const uint8_t *penalize;  /* host, p flags: 1 = column penalised; NULL = all columns */
-    int mode;                 /* COX_CCD */
-    int x_precision;          /* COX_F64 */
+    int mode;                 /* COX_CCD or COX_NEWTON_REFINE */
+    int x_precision;          /* contraction precision: COX_F64 or COX_BF16 (F32/FP8: COX_EUNSUPPORTED) */
     int ties;                 /* COX_BRESLOW */
-    double tol;               /* stop after a sweep whose largest |step| <= tol * max(1, max|beta|) */
-    int max_iter;             /* maximum number of CCD sweeps (cycles over all p coordinates) */
+    double tol;               /* stop when the largest |step| of a CCD sweep or Newton step <= tol * max(1, max|beta|) */
+    int max_iter;             /* maximum number of CCD sweeps or Newton iterations */
     void *stream;             /* hipStream_t to issue work on; NULL = default stream */
 } cox_options;
 
 typedef struct {
     int status;               /* return code of the fit */
-    int iters;                /* CCD sweeps performed */
-    int64_t coord_evals;      /* coordinate (g', g'') evaluations performed = iters * p */
+    int iters;                /* CCD sweeps or Newton iterations performed */
+    int64_t coord_evals;      /* CCD: coordinate (g', g'') evaluations = iters * p; Newton: full evaluations */
     double objective;         /* -log partial likelihood + penalty, at the start of the last sweep */
     double kkt_inf;           /* max_j of the l1 KKT residual from the last sweep's gradients */
     double last_step;         /* largest |step| of the last sweep */
@@ -96,7 +100,8 @@ void cox_default_options(cox_options *o);
  *   o   : options (NULL = defaults); penalize is copied
  * Errors: COX_EINVAL (n < 1, p < 1, ldx < n, NULL x/time/event, non-finite
  * time, event not 0/1), COX_EUNSUPPORTED (n or p beyond this build's
- * resident limits), COX_ENOMEM, COX_EDEVICE.  On error *out is NULL and the
+ * resident limits; mode COX_NEWTON_REFINE with gamma != 0; an x_precision
+ * other than COX_F64 / COX_BF16), COX_ENOMEM, COX_EDEVICE.  On error *out is NULL and the
  * message is available through cox_last_error(NULL).
  */
 int cox_init(cox_handle **out, const cox_data *d, const cox_options *o);
@@ -112,6 +117,12 @@ int cox_init(cox_handle **out, const cox_data *d, const cox_options *o);
  *   beta_out : host, p entries, receives the estimate
  *   info     : host, optional (may be NULL)
  * Degenerate columns (g'' <= 1e-12 * delta'(S[N2]/S[D])) are not moved.
+ * With mode COX_NEWTON_REFINE (gamma must be 0, else COX_EUNSUPPORTED): Newton steps
+ * beta -= I^{-1} grad with I from cox_evaluate_full's contraction in
+ * x_precision, factored by an FP64 Cholesky on the device; once a step is
+ * below 1e-3 * max(1, max|beta|) the factor is kept and only the FP64
+ * gradient is recomputed (iterative refinement), until the step is below
+ * tol * max(1, max|beta|).  A step that raises the objective is halved.
  * Returns COX_OK, COX_NOT_CONVERGED (max_iter sweeps done; beta_out filled),
  * COX_ENUMERIC (an event's risk-set sum under- or overflowed FP64 after the
  * global shift of X beta), COX_EDEVICE.
@@ -128,6 +139,22 @@ int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *
  */
 int cox_evaluate(cox_handle *h, const double *beta, double *objective, double *grad,
                  double *hess_diag);
+
+/*
+ * Full evaluation at beta (host, p) through the exchanged-sum form of
+ * Eqs. strat_g / strat_h: with Lambda_r the Breslow cumulative hazard of row
+ * r's stratum at Y_r and w = exp(X beta),
+ *   gradient = X'(w o Lambda - delta),
+ *   Hessian  = X' diag(w o Lambda) X - sum_g d_g xbar_g xbar_g',
+ * xbar_g the risk-set mean of x at event group g (Sec. 2.7 scans, one pass
+ * over X per product).  Outputs (host, any may be NULL): objective (-log L of
+ * Eq. strat_l plus the l1 penalty), grad (p), hess_diag (p), info (p x p,
+ * row-major, symmetric).  objective, grad and hess_diag are FP64; info is
+ * formed in the handle's x_precision (FP64, or BF16 on the matrix cores with
+ * FP32 accumulation) and returned as FP64.
+ */
+int cox_evaluate_full(cox_handle *h, const double *beta, double *objective, double *grad, double *hess_diag,
+                      double *info);
 
 /*
  * The quantities one CCD coordinate step uses, for column j at beta (host, p):

@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcoxmi.so")
-SOURCES = [os.path.join(CSRC, "ccd_kernel.hip"), os.path.join(CSRC, "coxmi.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in
+           ["ccd_kernel.hip", "newton.hip", "contraction.hip", "coxmi.cpp", "newton_host.cpp"]]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -21,7 +21,11 @@ COX_ENUMERIC = -4
 COX_EUNSUPPORTED = -5
 
 COX_CCD = 0
+COX_NEWTON_REFINE = 1
 COX_F64 = 0
+COX_F32 = 1
+COX_BF16 = 2
+COX_FP8_E4M3 = 3
 COX_BRESLOW = 0
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcoxmi.so")
@@ -67,6 +71,7 @@ SIGNATURES = [
     ("cox_init", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(cox_data), ctypes.POINTER(cox_options)]),
     ("cox_fit", ctypes.c_int, [_VP, _DP, _DP, ctypes.POINTER(cox_fit_info)]),
     ("cox_evaluate", ctypes.c_int, [_VP, _DP, _DP, _DP, _DP]),
+    ("cox_evaluate_full", ctypes.c_int, [_VP, _DP, _DP, _DP, _DP, _DP]),
     ("cox_coordinate", ctypes.c_int, [_VP, _DP, ctypes.c_int64, _DP]),
     ("cox_layout", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32)]),
     ("cox_last_kernel_ms", ctypes.c_int, [_VP, _DP]),
@@ -111,7 +116,7 @@ def cox_default_options() -> cox_options:
 
 
 def cox_init(X, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-12, max_iter=1000,
-             stream=None):
+             stream=None, mode=COX_CCD, x_precision=COX_F64):
     """Create a handle.  X: (n, p) float64 (any order), time float64[n], event 0/1[n],
     stratum int32[n] or None.  Returns an opaque handle (int)."""
     X = np.asfortranarray(X, dtype=np.float64)
@@ -129,6 +134,8 @@ def cox_init(X, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-1
     o.gamma = float(gamma)
     o.tol = float(tol)
     o.max_iter = int(max_iter)
+    o.mode = int(mode)
+    o.x_precision = int(x_precision)
     if penalize is not None:
         pen = np.ascontiguousarray(penalize, dtype=np.uint8)
         keep.append(pen)
@@ -160,6 +167,19 @@ def cox_evaluate(h, beta):
     obj = ctypes.c_double()
     _check(h, lib().cox_evaluate(h, _dptr(b), ctypes.byref(obj), _dptr(g), _dptr(hd)))
     return obj.value, g, hd
+
+
+def cox_evaluate_full(h, beta, want_info=True):
+    """Returns (objective, grad[p], hess_diag[p], info[p, p] or None)."""
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    p = b.shape[0]
+    g = np.zeros(p)
+    hd = np.zeros(p)
+    info = np.zeros((p, p)) if want_info else None
+    obj = ctypes.c_double()
+    _check(h, lib().cox_evaluate_full(h, _dptr(b), ctypes.byref(obj), _dptr(g), _dptr(hd),
+                                      None if info is None else _dptr(info)))
+    return obj.value, g, hd, info
 
 
 def cox_coordinate(h, beta, j):
@@ -224,6 +244,9 @@ class CoxModel:
 
     def coordinate(self, beta, j):
         return cox_coordinate(self.h, beta, j)
+
+    def evaluate_full(self, beta, want_info=True):
+        return cox_evaluate_full(self.h, beta, want_info)
 
     def layout(self):
         return cox_layout(self.h)

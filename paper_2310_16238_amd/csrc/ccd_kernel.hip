@@ -85,6 +85,35 @@ void carve_sync_scratch(void *base, int grid, CcdLaunch &L)
 
 // ------------------------------------------------------------------ small helpers
 
+// exp(x) by the table-driven method of Tang (ACM TOMS 15(2), 1989):
+// x = (64 m + j) ln2/64 + r with |r| <= ln2/128, exp(x) = 2^m 2^(j/64) e^r, and
+// e^r from its degree-5 Taylor polynomial (truncation below 2^-54 there).
+// ln2/64 is split in two (the high part has 30 trailing zero bits, so n times
+// it is exact) to form r without cancellation.  tab[j] = 2^(j/64), rounded
+// to nearest, built on the host.  Accuracy about 1 ulp, like the libm exp.
+__device__ __forceinline__ double exp_table(double x, const double *tab)
+{
+    x = fmin(fmax(x, -746.0), 710.0);                 // keeps n an int; results saturate to 0 / inf
+    const double n = rint(x * 0x1.71547652b82fep+6);   // 64 / ln 2
+    double r = fma(-n, 0x1.62e42c0000000p-7, x);       // ln2/64, high part
+    r = fma(-n, 0x1.f7d1cf79abc9ep-30, r);             // ln2/64, low part
+    const double p = r * fma(r, fma(r, fma(r, fma(r, 1.0 / 120.0, 1.0 / 24.0), 1.0 / 6.0), 0.5), 1.0);
+    const int k = (int)n;
+    const double t = tab[k & 63];
+    return ldexp(fma(t, p, t), k >> 6);
+}
+
+// 1/a from the hardware estimate refined by two Newton steps (each squares
+// the relative error), ending within about 1 ulp.
+__device__ __forceinline__ double recip(double a)
+{
+    double r = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-a, r, 1.0);
+    return fma(r, e, r);
+}
+
 template <int IPT>
 __device__ __forceinline__ void load_rows(double (&v)[IPT], const double *p)
 {
@@ -298,6 +327,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
     __shared__ double s_step, s_shift;
     __shared__ uint32_t s_flags;
     __shared__ int s_abort;
+    __shared__ double s_exptab[64];
 
     const int p = L.p;
     const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
@@ -318,6 +348,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
         sgamma[j] = L.gamma[j];
     }
     if (t == 0) s_abort = 0;
+    if (t < 64) s_exptab[t] = L.exp_tab[t];
     uint32_t meta[IPT];
     double eta[IPT];
     load_words<IPT>(meta, L.meta + row0);
@@ -378,7 +409,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             SegVal<3> tagg = seg_identity<3>();
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
-                wv[i] = exp(eta[i] - c);
+                wv[i] = exp_table(eta[i] - c, s_exptab);
                 SegVal<3> r;
                 r.f = meta[i] >> 31;
                 r.v[0] = wv[i];
@@ -411,7 +442,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
                 if (d != 0u) {
                     const double s0 = run.v[0];
                     if (!(s0 >= 1e-300) || !(s0 <= 1e300)) v.err = 1u;
-                    const double inv = 1.0 / s0;
+                    const double inv = recip(s0);
                     const double r1 = run.v[1] * inv, r2 = run.v[2] * inv;
                     const double dd = (double)d;
                     v.v[kPC1] += dd * r1;

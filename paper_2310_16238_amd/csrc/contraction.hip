@@ -1,0 +1,380 @@
+// contraction.hip -- the information matrix as two symmetric rank-K products,
+// and the FP64 Cholesky solve of a Newton step (gfx950).
+//
+//   I = X' diag(b) X - Z'Z,   b_r = w_r Lambda_r,   Z_gj = sqrt(d_g) xbar_gj
+// (the Hessian of Eq. strat_h with the order of its sums exchanged; see
+// newton.hip).  Both products have the form C = sum_k c_k u_k u_k' over K
+// rows with u_k in R^p stored column-wise ([p][ld], k contiguous).
+//
+// FP64 reference kernel: 64x64 tiles of the upper triangle, K split across
+// workgroups, 32-row chunks staged in LDS, each thread owning a 4x4 block;
+// the split partials are summed in split order (deterministic).
+//
+// BF16 kernel (matrix cores): u is stored as BF16 with a power-of-two scale
+// per column; v_mfma_f32_32x32x16_bf16 accumulates 32x32 tiles in FP32.  The
+// weights c_k multiply one operand in FP32 before it is rounded to BF16.
+// Each wave owns up to 8 tiles of the upper triangle, a workgroup's 4 waves
+// share one K range, and the FP32 partials of the K ranges are summed in FP64
+// in range order with the column scales applied.
+#include <hip/hip_bf16.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace coxmi {
+
+namespace {
+
+constexpr int kTile = 64, kKc = 32, kSyrkThreads = 256;
+
+__device__ __forceinline__ void tile_pair(int pair, int nt, int &ti, int &tj)
+{
+    // pairs (ti <= tj) in row-major order of the upper triangle
+    int i = 0, rem = pair;
+    while (rem >= nt - i) {
+        rem -= nt - i;
+        ++i;
+    }
+    ti = i;
+    tj = i + rem;
+}
+
+__global__ __launch_bounds__(kSyrkThreads) void syrk_f64_kernel(const double *u, int64_t ldu, int p,
+                                                                const double *c, int64_t K, int64_t kchunk,
+                                                                double *part)
+{
+    __shared__ double As[kTile][kKc + 1];
+    __shared__ double Bs[kTile][kKc + 1];
+    const int nt = (p + kTile - 1) / kTile;
+    const int npairs = nt * (nt + 1) / 2;
+    const int pair = blockIdx.x, s = blockIdx.y;
+    int ti, tj;
+    tile_pair(pair, nt, ti, tj);
+    const int t = threadIdx.x, tx = t % 16, ty = t / 16;
+    const int64_t k0 = (int64_t)s * kchunk;
+    const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) acc[a][bb] = 0.0;
+    for (int64_t k = k0; k < k1; k += kKc) {
+#pragma unroll
+        for (int e = 0; e < kTile * kKc / kSyrkThreads; ++e) {
+            const int idx = t + kSyrkThreads * e;
+            const int i = idx / kKc, kk = idx % kKc;
+            const int64_t kr = k + kk;
+            const int ri = ti * kTile + i, rj = tj * kTile + i;
+            double av = 0.0, bv = 0.0;
+            if (kr < k1) {
+                const double ck = c ? c[kr] : 1.0;
+                if (ri < p) av = u[(int64_t)ri * ldu + kr] * ck;
+                if (rj < p) bv = u[(int64_t)rj * ldu + kr];
+            }
+            As[i][kk] = av;
+            Bs[i][kk] = bv;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < kKc; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[ty * 4 + a][kk];
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) bv[bb] = Bs[tx * 4 + bb][kk];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) acc[a][bb] = fma(av[a], bv[bb], acc[a][bb]);
+        }
+        __syncthreads();
+    }
+    double *out = part + ((int64_t)s * npairs + pair) * (kTile * kTile);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) out[(ty * 4 + a) * kTile + tx * 4 + bb] = acc[a][bb];
+}
+
+// C (p x p, row-major, symmetric) = sign * sum over splits (in order) of the
+// partial tiles, added to C when accumulate != 0.
+__global__ __launch_bounds__(kSyrkThreads) void syrk_reduce_kernel(const double *part, int p, int S, double sign,
+                                                                   int accumulate, double *C)
+{
+    const int nt = (p + kTile - 1) / kTile;
+    const int npairs = nt * (nt + 1) / 2;
+    const int pair = blockIdx.x;
+    int ti, tj;
+    tile_pair(pair, nt, ti, tj);
+    for (int e = threadIdx.x; e < kTile * kTile; e += kSyrkThreads) {
+        const int a = e / kTile, bb = e % kTile;
+        const int i = ti * kTile + a, j = tj * kTile + bb;
+        if (i >= p || j >= p) continue;
+        if (ti == tj && j < i) continue;     // the diagonal tile: upper half only
+        double s = 0.0;
+        for (int q = 0; q < S; ++q) s += part[((int64_t)q * npairs + pair) * (kTile * kTile) + e];
+        s *= sign;
+        if (accumulate) {
+            C[(int64_t)i * p + j] += s;
+            if (i != j) C[(int64_t)j * p + i] += s;
+        } else {
+            C[(int64_t)i * p + j] = s;
+            if (i != j) C[(int64_t)j * p + i] = s;
+        }
+    }
+}
+
+// One workgroup: A (p x p, row-major, symmetric positive definite on the free
+// columns) is overwritten by its Cholesky factor L (lower triangle) unless
+// `factored`; then dx = -A^{-1} g on the free columns, 0 on the others.
+// status[0] = 1 if a pivot was not positive.
+__global__ __launch_bounds__(256) void chol_solve_kernel(double *A, int p, const double *g, const uint8_t *free_col,
+                                                         int factored, double *dx, int *status)
+{
+    extern __shared__ double sy[];   // [p]
+    __shared__ double s_piv;
+    __shared__ int s_bad;
+    const int t = threadIdx.x;
+    if (t == 0) s_bad = 0;
+    if (!factored) {
+        for (int64_t e = t; e < (int64_t)p * p; e += 256) {
+            const int i = (int)(e / p), j = (int)(e % p);
+            if (!free_col[i] || !free_col[j]) A[e] = (i == j) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        for (int k = 0; k < p; ++k) {
+            if (t == 0) {
+                double d = A[(int64_t)k * p + k];
+                if (!(d > 0.0)) {
+                    s_bad = 1;
+                    d = 1.0;
+                }
+                s_piv = sqrt(d);
+                A[(int64_t)k * p + k] = s_piv;
+            }
+            __syncthreads();
+            const double piv = s_piv;
+            for (int i = k + 1 + t; i < p; i += 256) A[(int64_t)i * p + k] /= piv;
+            __syncthreads();
+            const int m = p - k - 1;
+            for (int64_t e = t; e < (int64_t)m * m; e += 256) {
+                const int i = k + 1 + (int)(e / m), j = k + 1 + (int)(e % m);
+                if (j <= i) A[(int64_t)i * p + j] -= A[(int64_t)i * p + k] * A[(int64_t)j * p + k];
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = t; i < p; i += 256) sy[i] = free_col[i] ? -g[i] : 0.0;
+    __syncthreads();
+    for (int k = 0; k < p; ++k) {          // L y = -g
+        if (t == 0) sy[k] /= A[(int64_t)k * p + k];
+        __syncthreads();
+        const double yk = sy[k];
+        for (int i = k + 1 + t; i < p; i += 256) sy[i] -= A[(int64_t)i * p + k] * yk;
+        __syncthreads();
+    }
+    for (int k = p - 1; k >= 0; --k) {     // L' x = y
+        if (t == 0) sy[k] /= A[(int64_t)k * p + k];
+        __syncthreads();
+        const double xk = sy[k];
+        for (int i = t; i < k; i += 256) sy[i] -= A[(int64_t)k * p + i] * xk;
+        __syncthreads();
+    }
+    for (int i = t; i < p; i += 256) dx[i] = free_col[i] ? sy[i] : 0.0;
+    if (t == 0) status[0] = s_bad;
+}
+
+// ------------------------------------------------------------------ BF16 on the matrix cores
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+
+constexpr int kMT = 32;              // MFMA tile edge
+constexpr int kTilesPerWave = 8;
+constexpr int kSyrkBfWaves = 4;
+constexpr int kPairsPerGroup = kTilesPerWave * kSyrkBfWaves;
+
+__host__ __device__ __forceinline__ int npairs32(int p)
+{
+    const int nt = (p + kMT - 1) / kMT;
+    return nt * (nt + 1) / 2;
+}
+
+// Fragment of 8 consecutive K values of row `row` (0 beyond p).
+__device__ __forceinline__ bf16x8 load_frag(const uint16_t *u, int64_t ldu, int p, int row, int64_t k)
+{
+    if (row >= p) {
+        bf16x8 z;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) z[i] = (__bf16)0.0f;
+        return z;
+    }
+    const u32x4v v = *reinterpret_cast<const u32x4v *>(u + (int64_t)row * ldu + k);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ bf16x8 weight_frag(bf16x8 a, const double *c, int64_t k)
+{
+    bf16x8 r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = (__bf16)((float)a[i] * (float)c[k + i]);
+    return r;
+}
+
+// part[(s * npairs + pair) * 1024 + m * 32 + n] = sum over K range s of
+// c_k u[ti*32+m][k] u[tj*32+n][k] (scaled units).  Grid (S, pair groups).
+__global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_kernel(const uint16_t *u, int64_t ldu, int p,
+                                                                      const double *c, int64_t K,
+                                                                      int64_t kchunk, float *part)
+{
+    const int nt = (p + kMT - 1) / kMT;
+    const int npairs = nt * (nt + 1) / 2;
+    const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+    const int s = blockIdx.x;
+    const int pair0 = blockIdx.y * kPairsPerGroup + w * kTilesPerWave;
+    const int64_t k0 = (int64_t)s * kchunk;
+    const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+    int ti[kTilesPerWave], tj[kTilesPerWave];
+    f32x16 acc[kTilesPerWave];
+#pragma unroll
+    for (int q = 0; q < kTilesPerWave; ++q) {
+        tile_pair(pair0 + q < npairs ? pair0 + q : 0, nt, ti[q], tj[q]);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[q][i] = 0.0f;
+    }
+    const int nq = npairs - pair0 < kTilesPerWave ? (npairs - pair0 > 0 ? npairs - pair0 : 0) : kTilesPerWave;
+    const int rsub = lane % 32, ksub = 8 * (lane / 32);
+    for (int64_t k = k0; k < k1; k += 16) {
+        const int64_t kk = k + ksub;
+#pragma unroll
+        for (int q = 0; q < kTilesPerWave; ++q) {
+            if (q < nq) {
+                bf16x8 a = load_frag(u, ldu, p, ti[q] * kMT + rsub, kk);
+                if (c) a = weight_frag(a, c, kk);
+                const bf16x8 bv = load_frag(u, ldu, p, tj[q] * kMT + rsub, kk);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[q], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kTilesPerWave; ++q) {
+        if (q < nq) {
+            float *out = part + ((int64_t)s * npairs + pair0 + q) * (kMT * kMT);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = 8 * (i / 4) + 4 * (lane / 32) + (i % 4), n = lane % 32;
+                out[m * kMT + n] = acc[q][i];
+            }
+        }
+    }
+}
+
+// C (+)= sign * scale_i * scale_j * sum over ranges of the partial tiles (FP64).
+__global__ __launch_bounds__(256) void syrk_bf16_reduce_kernel(const float *part, int p, int S, const float *scale,
+                                                               double sign, int accumulate, double *C)
+{
+    const int nt = (p + kMT - 1) / kMT;
+    const int npairs = nt * (nt + 1) / 2;
+    const int pair = blockIdx.x;
+    int ti, tj;
+    tile_pair(pair, nt, ti, tj);
+    for (int e = threadIdx.x; e < kMT * kMT; e += 256) {
+        const int a = e / kMT, bb = e % kMT;
+        const int i = ti * kMT + a, j = tj * kMT + bb;
+        if (i >= p || j >= p) continue;
+        if (ti == tj && j < i) continue;
+        double s = 0.0;
+        for (int q = 0; q < S; ++q) s += (double)part[((int64_t)q * npairs + pair) * (kMT * kMT) + e];
+        s *= sign * (double)scale[i] * (double)scale[j];
+        if (accumulate) {
+            C[(int64_t)i * p + j] += s;
+            if (i != j) C[(int64_t)j * p + i] += s;
+        } else {
+            C[(int64_t)i * p + j] = s;
+            if (i != j) C[(int64_t)j * p + i] = s;
+        }
+    }
+}
+
+// Per column: the power-of-two scale s_j >= max |x_j| (1 for a zero column).
+__global__ __launch_bounds__(256) void colscale_kernel(const double *x, int64_t ld, float *xscale, float *zscale)
+{
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    double m = 0.0;
+    for (int64_t r = threadIdx.x; r < ld; r += 256) m = fmax(m, fabs(x[(int64_t)j * ld + r]));
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        const float sc = m > 0.0 ? (float)exp2(ceil(log2(m))) : 1.0f;
+        xscale[j] = sc;
+        zscale[j] = sc;
+    }
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const double *x, int64_t ld, const float *xscale,
+                                                      uint16_t *xlp)
+{
+    const int j = blockIdx.y;
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r < ld) {
+        const __hip_bfloat16 v = __float2bfloat16((float)(x[(int64_t)j * ld + r] / (double)xscale[j]));
+        xlp[(int64_t)j * ld + r] = __builtin_bit_cast(uint16_t, v);
+    }
+}
+
+}  // namespace
+
+size_t syrk_partial_bytes(int p, int splits)
+{
+    const int nt = (p + kTile - 1) / kTile;
+    return sizeof(double) * (size_t)splits * (size_t)(nt * (nt + 1) / 2) * kTile * kTile;
+}
+
+int syrk_f64(const double *u, int64_t ldu, int p, const double *c, int64_t K, int splits, double *part,
+             double sign, int accumulate, double *C, hipStream_t stream)
+{
+    const int nt = (p + kTile - 1) / kTile;
+    const int npairs = nt * (nt + 1) / 2;
+    int64_t kchunk = (K + splits - 1) / splits;
+    kchunk = (kchunk + kKc - 1) / kKc * kKc;
+    syrk_f64_kernel<<<dim3(npairs, splits), kSyrkThreads, 0, stream>>>(u, ldu, p, c, K, kchunk, part);
+    syrk_reduce_kernel<<<npairs, kSyrkThreads, 0, stream>>>(part, p, splits, sign, accumulate, C);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int make_bf16_copy(const double *x, int64_t ld, int p, void *xlp, float *xscale, float *zscale, hipStream_t stream)
+{
+    colscale_kernel<<<p, 256, 0, stream>>>(x, ld, xscale, zscale);
+    to_bf16_kernel<<<dim3((unsigned)((ld + 255) / 256), p), 256, 0, stream>>>(x, ld, xscale,
+                                                                             static_cast<uint16_t *>(xlp));
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const double *c, int64_t K, int splits,
+              double *part, double sign, int accumulate, double *C, hipStream_t stream)
+{
+    if (ldu % 16 != 0) return -1;
+    const int npairs = npairs32(p);
+    const int ngroups = (npairs + kPairsPerGroup - 1) / kPairsPerGroup;
+    const int64_t K16 = (K + 15) / 16 * 16;          // entries K..K16-1 are zero (padding)
+    if (K16 > ldu) return -1;
+    int64_t kchunk = (K16 + splits - 1) / splits;
+    kchunk = (kchunk + 15) / 16 * 16;
+    float *fpart = reinterpret_cast<float *>(part);
+    syrk_bf16_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, 0, stream>>>(u, ldu, p, c, K16, kchunk, fpart);
+    syrk_bf16_reduce_kernel<<<npairs, 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int chol_solve(double *A, int p, const double *g, const uint8_t *free_col, int factored, double *dx, int *status,
+               hipStream_t stream)
+{
+    chol_solve_kernel<<<1, 256, sizeof(double) * (size_t)p, stream>>>(A, p, g, free_col, factored, dx, status);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace coxmi

@@ -16,36 +16,10 @@
 #include <string>
 #include <vector>
 
+#include "handle.h"
 #include "internal.h"
 
 using namespace coxmi;
-
-struct cox_handle {
-    int64_t n = 0, p = 0;
-    int device = 0;
-    LaunchShape shape;
-    hipStream_t stream = nullptr;
-    double *d_x = nullptr;
-    uint32_t *d_meta = nullptr;
-    double *d_vec = nullptr;       // q, gamma, beta, g1, g2, m2 (p each), result (8)
-    void *d_sync = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    float last_kernel_ms = 0.0f;
-    std::vector<int64_t> perm;     // canonical row -> original row
-    std::vector<uint32_t> meta;    // canonical row words
-    std::vector<int64_t> pos;      // canonical row -> row of the device layout
-    std::vector<double> gamma;
-    cox_options opt{};
-    std::string err;
-
-    double *q() const { return d_vec; }
-    double *gam() const { return d_vec + p; }
-    double *beta() const { return d_vec + 2 * p; }
-    double *g1() const { return d_vec + 3 * p; }
-    double *g2() const { return d_vec + 4 * p; }
-    double *m2() const { return d_vec + 5 * p; }
-    double *result() const { return d_vec + 6 * p; }
-};
 
 static thread_local std::string g_init_error;
 
@@ -61,6 +35,9 @@ static int hip_fail(cox_handle *h, hipError_t e, const char *what)
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
     return fail(h, e == hipErrorOutOfMemory ? COX_ENOMEM : COX_EDEVICE, m);
 }
+
+int handle_fail(cox_handle *h, int code, const std::string &msg) { return fail(h, code, msg); }
+int handle_hip_fail(cox_handle *h, hipError_t e, const char *what) { return hip_fail(h, e, what); }
 
 extern "C" void cox_default_options(cox_options *o)
 {
@@ -78,6 +55,7 @@ extern "C" void cox_default_options(cox_options *o)
 
 static void free_device(cox_handle *h)
 {
+    newton_free(h);
     if (h->d_x) (void)hipFree(h->d_x);
     if (h->d_meta) (void)hipFree(h->d_meta);
     if (h->d_vec) (void)hipFree(h->d_vec);
@@ -160,8 +138,11 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     cox_options opt;
     if (o) opt = *o;
     else cox_default_options(&opt);
-    if (opt.mode != COX_CCD) return fail(nullptr, COX_EUNSUPPORTED, "only COX_CCD is available");
-    if (opt.x_precision != COX_F64) return fail(nullptr, COX_EUNSUPPORTED, "only COX_F64 is available");
+    if (opt.mode != COX_CCD && opt.mode != COX_NEWTON_REFINE) return fail(nullptr, COX_EINVAL, "unknown mode");
+    if (opt.x_precision != COX_F64 && opt.x_precision != COX_BF16)
+        return fail(nullptr, COX_EUNSUPPORTED, "x_precision must be COX_F64 or COX_BF16");
+    if (opt.mode == COX_NEWTON_REFINE && opt.gamma != 0.0)
+        return fail(nullptr, COX_EUNSUPPORTED, "COX_NEWTON_REFINE fits the unpenalised model (gamma = 0)");
     if (opt.ties != COX_BRESLOW) return fail(nullptr, COX_EUNSUPPORTED, "only COX_BRESLOW ties");
     if (!(opt.gamma >= 0.0) || !std::isfinite(opt.gamma)) return fail(nullptr, COX_EINVAL, "gamma must be finite and >= 0");
     if (!(opt.tol >= 0.0)) return fail(nullptr, COX_EINVAL, "tol must be >= 0");
@@ -228,7 +209,7 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     hipError_t e;
     if ((e = hipMalloc(&h->d_x, sizeof(double) * (size_t)ld * p)) != hipSuccess ||
         (e = hipMalloc(&h->d_meta, sizeof(uint32_t) * (size_t)ld)) != hipSuccess ||
-        (e = hipMalloc(&h->d_vec, sizeof(double) * (size_t)(6 * p + kResultSlots))) != hipSuccess ||
+        (e = hipMalloc(&h->d_vec, sizeof(double) * (size_t)(6 * p + kResultSlots + 64))) != hipSuccess ||
         (e = hipMalloc(&h->d_sync, sync_scratch_bytes(h->shape.grid))) != hipSuccess) {
         free_device(h);
         delete h;
@@ -256,6 +237,12 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     }
     if (e == hipSuccess) e = hipMemcpy(h->q(), q.data(), sizeof(double) * p, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->gam(), h->gamma.data(), sizeof(double) * p, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        // 2^(j/64), j = 0..63, rounded to nearest from extended precision (table of the device exp)
+        double tab[64];
+        for (int j = 0; j < 64; ++j) tab[j] = (double)std::exp2l((long double)j / 64.0L);
+        e = hipMemcpy(h->exp_tab(), tab, sizeof(tab), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipEventCreate(&h->ev0);
     if (e == hipSuccess) e = hipEventCreate(&h->ev1);
     if (e != hipSuccess) {
@@ -281,6 +268,7 @@ static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *bet
     L.meta = h->d_meta;
     L.q = h->q();
     L.gamma = h->gam();
+    L.exp_tab = h->exp_tab();
     L.n = h->n;
     L.p = (int)h->p;
     L.mode = mode;
@@ -317,6 +305,7 @@ extern "C" int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox
     if (beta0)
         for (int64_t j = 0; j < h->p; ++j)
             if (!std::isfinite(beta0[j])) return fail(h, COX_EINVAL, "beta0 is not finite");
+    if (h->opt.mode == COX_NEWTON_REFINE) return newton_fit(h, beta0, beta_out, info);
     double res[kResultSlots];
     int rc = run_kernel(h, kModeFit, 0, (int)h->p, beta0, res);
     if (rc != COX_OK && rc != COX_ENUMERIC) return rc;

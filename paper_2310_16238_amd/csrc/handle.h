@@ -1,0 +1,69 @@
+// handle.h -- the library-owned state behind a cox_handle (private to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "coxmi.h"
+#include "internal.h"
+
+// Device buffers of the full-evaluation / Newton path, allocated on first use.
+struct NewtonState {
+    bool ready = false;
+    int splits = 1;
+    int max_blocks = 0;
+    int64_t n_groups = 0, ldz = 0;
+    int32_t *gidx = nullptr;       // [ld]
+    double *rows = nullptr;        // 7 x [ld]: eta, w, s0, h, lam, a, b
+    double *blockbuf = nullptr;    // [max_blocks]
+    double *xtpart = nullptr;      // [splits][p][2]
+    double *vec = nullptr;         // beta, grad, diag1, diag2, dx (p each), scal (8)
+    unsigned *flags = nullptr;
+    int *status = nullptr;
+    uint8_t *free_col = nullptr;   // [p]
+    void *z = nullptr;             // [p][ldz] in the contraction type
+    float *zscale = nullptr;       // [p]
+    void *xlp = nullptr;           // [p][ld] low-precision copy of X (BF16)
+    float *xscale = nullptr;       // [p]
+    double *syrk_part = nullptr;   // split partials of the contraction
+    size_t syrk_part_bytes = 0;
+    double *info = nullptr;        // [p][p] information matrix, then its Cholesky factor
+    void *scan_scratch = nullptr;
+    size_t scan_scratch_bytes = 0;
+};
+
+struct cox_handle {
+    int64_t n = 0, p = 0;
+    int device = 0;
+    coxmi::LaunchShape shape;
+    hipStream_t stream = nullptr;
+    double *d_x = nullptr;
+    uint32_t *d_meta = nullptr;
+    double *d_vec = nullptr;       // q, gamma, beta, g1, g2, m2 (p each), result (8), exp table (64)
+    void *d_sync = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float last_kernel_ms = 0.0f;
+    std::vector<int64_t> perm;     // canonical row -> original row
+    std::vector<uint32_t> meta;    // canonical row words
+    std::vector<int64_t> pos;      // canonical row -> row of the device layout
+    std::vector<double> gamma;
+    cox_options opt{};
+    std::string err;
+    NewtonState nt;
+
+    double *q() const { return d_vec; }
+    double *gam() const { return d_vec + p; }
+    double *beta() const { return d_vec + 2 * p; }
+    double *g1() const { return d_vec + 3 * p; }
+    double *g2() const { return d_vec + 4 * p; }
+    double *m2() const { return d_vec + 5 * p; }
+    double *result() const { return d_vec + 6 * p; }
+    double *exp_tab() const { return d_vec + 6 * p + coxmi::kResultSlots; }
+};
+
+int handle_fail(cox_handle *h, int code, const std::string &msg);
+int handle_hip_fail(cox_handle *h, hipError_t e, const char *what);
+void newton_free(cox_handle *h);
+int newton_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *info);

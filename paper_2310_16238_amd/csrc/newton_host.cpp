@@ -1,0 +1,304 @@
+// newton_host.cpp -- full evaluation and the Newton / iterative-refinement fit
+// (host side; kernels in newton.hip and contraction.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "handle.h"
+#include "internal.h"
+
+using namespace coxmi;
+
+namespace {
+
+constexpr int kScalSlots = 8;
+
+double *nrow(const NewtonState &s, int64_t ld, int k) { return s.rows + (int64_t)k * ld; }
+
+template <typename T>
+hipError_t dalloc(T **p, size_t bytes)
+{
+    return hipMalloc(reinterpret_cast<void **>(p), bytes);
+}
+
+size_t ztype_bytes(int prec) { return prec == COX_BF16 ? 2 : 8; }
+
+int newton_setup(cox_handle *h)
+{
+    NewtonState &s = h->nt;
+    if (s.ready) return COX_OK;
+    const int64_t ld = h->shape.ld, n = h->n;
+    const int p = (int)h->p;
+    std::vector<int32_t> gidx(ld, -1);
+    int64_t G = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (h->meta[i] & kCountMask) gidx[h->pos[i]] = (int32_t)G++;
+    s.n_groups = G;
+    s.ldz = std::max<int64_t>(64, (G + 63) / 64 * 64);
+    s.max_blocks = (int)((ld + 255) / 256) + 1;
+    s.splits = std::max(1, std::min(64, (int)((2048 + p - 1) / p)));
+    while (s.splits > 1 && ld / s.splits < 4096) --s.splits;
+    const int S1 = 128, S2 = 64;
+    s.syrk_part_bytes = std::max(syrk_partial_bytes(p, S1), syrk_partial_bytes(p, S2));
+    s.scan_scratch_bytes = 256 + sizeof(double) * 2 * kMaxGroups;
+    const size_t zb = ztype_bytes(h->opt.x_precision);
+    hipError_t e;
+    if ((e = dalloc(&s.gidx, sizeof(int32_t) * ld)) != hipSuccess ||
+        (e = dalloc(&s.rows, sizeof(double) * 7 * ld)) != hipSuccess ||
+        (e = dalloc(&s.blockbuf, sizeof(double) * s.max_blocks)) != hipSuccess ||
+        (e = dalloc(&s.xtpart, sizeof(double) * 2 * (size_t)s.splits * p)) != hipSuccess ||
+        (e = dalloc(&s.vec, sizeof(double) * (5 * (size_t)p + kScalSlots))) != hipSuccess ||
+        (e = dalloc(&s.flags, sizeof(unsigned))) != hipSuccess ||
+        (e = dalloc(&s.status, sizeof(int))) != hipSuccess ||
+        (e = dalloc(&s.free_col, (size_t)p)) != hipSuccess ||
+        (e = dalloc(&s.z, zb * (size_t)p * s.ldz)) != hipSuccess ||
+        (e = dalloc(&s.zscale, sizeof(float) * p)) != hipSuccess ||
+        (e = dalloc(&s.syrk_part, s.syrk_part_bytes)) != hipSuccess ||
+        (e = dalloc(&s.info, sizeof(double) * (size_t)p * p)) != hipSuccess ||
+        (e = dalloc(&s.scan_scratch, s.scan_scratch_bytes)) != hipSuccess) {
+        newton_free(h);
+        return handle_hip_fail(h, e, "allocating full-evaluation buffers");
+    }
+    e = hipMemcpy(s.gidx, gidx.data(), sizeof(int32_t) * ld, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(s.z, 0, zb * (size_t)p * s.ldz);
+    if (e != hipSuccess) {
+        newton_free(h);
+        return handle_hip_fail(h, e, "uploading group indices");
+    }
+    if (h->opt.x_precision == COX_BF16) {
+        // low-precision copy of X with power-of-two column scales (|x / s| <= 1)
+        if ((e = dalloc(&s.xlp, sizeof(uint16_t) * (size_t)p * ld)) != hipSuccess ||
+            (e = dalloc(&s.xscale, sizeof(float) * p)) != hipSuccess) {
+            newton_free(h);
+            return handle_hip_fail(h, e, "allocating the BF16 copy of X");
+        }
+        int rc = make_bf16_copy(h->d_x, ld, p, s.xlp, s.xscale, s.zscale, h->stream);
+        if (rc == 0 && hipStreamSynchronize(h->stream) != hipSuccess) rc = -3;
+        if (rc != 0) {
+            newton_free(h);
+            return handle_fail(h, COX_EDEVICE, "building the BF16 copy of X");
+        }
+    }
+    s.ready = true;
+    return COX_OK;
+}
+
+struct EvalOut {
+    double objective = 0.0;
+    std::vector<double> grad, diag1, diag2;
+    unsigned flags = 0;
+};
+
+// Full evaluation at beta (host); xbar (and diag2) only when want_xbar.
+int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
+{
+    NewtonState &s = h->nt;
+    const int64_t ld = h->shape.ld;
+    const int p = (int)h->p;
+    double *d_beta = s.vec, *d_grad = s.vec + p, *d_d1 = s.vec + 2 * p, *d_d2 = s.vec + 3 * p;
+    double *d_scal = s.vec + 5 * p;
+    hipError_t e = hipMemcpyAsync(d_beta, beta, sizeof(double) * p, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return handle_hip_fail(h, e, "staging beta");
+    FullEvalArgs A;
+    A.x = h->d_x;
+    A.meta = h->d_meta;
+    A.gidx = s.gidx;
+    A.beta = d_beta;
+    A.ld = ld;
+    A.p = p;
+    A.splits = s.splits;
+    A.max_blocks = s.max_blocks;
+    A.eta = nrow(s, ld, 0);
+    A.w = nrow(s, ld, 1);
+    A.s0 = nrow(s, ld, 2);
+    A.h = nrow(s, ld, 3);
+    A.lam = nrow(s, ld, 4);
+    A.a = nrow(s, ld, 5);
+    A.b = nrow(s, ld, 6);
+    A.blockbuf = s.blockbuf;
+    A.xtpart = s.xtpart;
+    A.grad = d_grad;
+    A.diag1 = d_d1;
+    A.diag2 = d_d2;
+    A.scal = d_scal;
+    A.flags = s.flags;
+    A.ztype = h->opt.x_precision == COX_BF16 ? kZBF16 : kZF64;
+    A.z = s.z;
+    A.ldz = s.ldz;
+    A.zscale = h->opt.x_precision == COX_BF16 ? s.zscale : nullptr;
+    A.want_xbar = want_xbar;
+    A.scan_scratch = s.scan_scratch;
+    A.scan_scratch_bytes = s.scan_scratch_bytes;
+    int rc = full_eval_launch(A, h->stream);
+    if (rc != 0) return handle_fail(h, rc == -5 ? COX_EUNSUPPORTED : COX_EDEVICE, "full evaluation launch");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return handle_hip_fail(h, e, "full evaluation");
+    double scal[2];
+    out.grad.resize(p);
+    out.diag1.resize(p);
+    out.diag2.assign(p, 0.0);
+    if ((e = hipMemcpy(scal, d_scal, sizeof(scal), hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(&out.flags, s.flags, sizeof(unsigned), hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(out.grad.data(), d_grad, sizeof(double) * p, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(out.diag1.data(), d_d1, sizeof(double) * p, hipMemcpyDeviceToHost)) != hipSuccess)
+        return handle_hip_fail(h, e, "reading the evaluation");
+    if (want_xbar &&
+        (e = hipMemcpy(out.diag2.data(), d_d2, sizeof(double) * p, hipMemcpyDeviceToHost)) != hipSuccess)
+        return handle_hip_fail(h, e, "reading the evaluation");
+    out.objective = scal[1];
+    if (out.flags & 1u) return handle_fail(h, COX_ENUMERIC, "a risk-set sum left the FP64 normal range");
+    return COX_OK;
+}
+
+// info = X' diag(b) X - Z'Z in the handle's precision, left in s.info (FP64).
+int newton_info(cox_handle *h)
+{
+    NewtonState &s = h->nt;
+    const int64_t ld = h->shape.ld;
+    const int p = (int)h->p;
+    const double *b = nrow(s, ld, 6);
+    int rc;
+    if (h->opt.x_precision == COX_BF16) {
+        rc = syrk_bf16(static_cast<const uint16_t *>(s.xlp), ld, p, s.xscale, b, ld, 128, s.syrk_part, 1.0, 0,
+                       s.info, h->stream);
+        if (rc == 0 && s.n_groups > 0)
+            rc = syrk_bf16(static_cast<const uint16_t *>(s.z), s.ldz, p, s.zscale, nullptr, s.n_groups, 64,
+                           s.syrk_part, -1.0, 1, s.info, h->stream);
+    } else {
+        rc = syrk_f64(h->d_x, ld, p, b, ld, 128, s.syrk_part, 1.0, 0, s.info, h->stream);
+        if (rc == 0 && s.n_groups > 0)
+            rc = syrk_f64(static_cast<const double *>(s.z), s.ldz, p, nullptr, s.n_groups, 64, s.syrk_part, -1.0,
+                          1, s.info, h->stream);
+    }
+    if (rc != 0) return handle_fail(h, COX_EDEVICE, "information-matrix contraction launch");
+    return COX_OK;
+}
+
+}  // namespace
+
+void newton_free(cox_handle *h)
+{
+    NewtonState &s = h->nt;
+    void *ptrs[] = {s.gidx, s.rows, s.blockbuf, s.xtpart, s.vec, s.flags, s.status, s.free_col, s.z,
+                    s.zscale, s.xlp, s.xscale, s.syrk_part, s.info, s.scan_scratch};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    s = NewtonState();
+}
+
+extern "C" int cox_evaluate_full(cox_handle *h, const double *beta, double *objective, double *grad,
+                                 double *hess_diag, double *info)
+{
+    if (!h) return handle_fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (!beta) return handle_fail(h, COX_EINVAL, "beta is NULL");
+    (void)hipSetDevice(h->device);
+    int rc = newton_setup(h);
+    if (rc != COX_OK) return rc;
+    EvalOut ev;
+    rc = newton_eval(h, beta, hess_diag || info, ev);
+    if (rc != COX_OK) return rc;
+    const int p = (int)h->p;
+    if (objective) {
+        double pen = 0.0;
+        for (int j = 0; j < p; ++j) pen += h->gamma[j] * std::fabs(beta[j]);
+        *objective = ev.objective + pen;
+    }
+    if (grad) std::memcpy(grad, ev.grad.data(), sizeof(double) * p);
+    if (hess_diag)
+        for (int j = 0; j < p; ++j) hess_diag[j] = ev.diag1[j] - ev.diag2[j];
+    if (info) {
+        rc = newton_info(h);
+        if (rc != COX_OK) return rc;
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy(info, h->nt.info, sizeof(double) * (size_t)p * p, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return handle_hip_fail(h, e, "information matrix");
+    }
+    return COX_OK;
+}
+
+int newton_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *info)
+{
+    (void)hipSetDevice(h->device);
+    int rc = newton_setup(h);
+    if (rc != COX_OK) return rc;
+    NewtonState &s = h->nt;
+    const int p = (int)h->p;
+    std::vector<double> beta(p, 0.0), prev(p, 0.0), dx(p, 0.0);
+    if (beta0) std::memcpy(beta.data(), beta0, sizeof(double) * p);
+    std::vector<uint8_t> freec(p, 1);
+    double *d_grad = s.vec + p, *d_dx = s.vec + 4 * p;
+    bool frozen = false, have_free = false, converged = false;
+    double obj_prev = INFINITY, last_step = 0.0, objective = 0.0;
+    int iters = 0, evals = 0, halvings = 0;
+    EvalOut ev;
+    while (iters < h->opt.max_iter) {
+        rc = newton_eval(h, beta.data(), !frozen || !have_free, ev);
+        ++evals;
+        if (rc != COX_OK) return rc;
+        if (!have_free) {
+            for (int j = 0; j < p; ++j) {
+                const double hd = ev.diag1[j] - ev.diag2[j];
+                freec[j] = (hd > 1e-12 * std::fabs(ev.diag1[j]) && std::isfinite(hd)) ? 1 : 0;
+            }
+            hipError_t e = hipMemcpy(s.free_col, freec.data(), (size_t)p, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return handle_hip_fail(h, e, "free columns");
+            have_free = true;
+        }
+        // a step that raised the objective is halved (and re-evaluated)
+        if (ev.objective > obj_prev + 1e-12 * std::fabs(obj_prev) && halvings < 40) {
+            for (int j = 0; j < p; ++j) beta[j] = prev[j] + 0.5 * (beta[j] - prev[j]);
+            ++halvings;
+            continue;
+        }
+        halvings = 0;
+        objective = ev.objective;
+        if (!frozen) {
+            rc = newton_info(h);
+            if (rc != COX_OK) return rc;
+        }
+        if (chol_solve(s.info, p, d_grad, s.free_col, frozen ? 1 : 0, d_dx, s.status, h->stream) != 0)
+            return handle_fail(h, COX_EDEVICE, "Cholesky launch");
+        hipError_t e = hipStreamSynchronize(h->stream);
+        int status = 0;
+        if (e == hipSuccess) e = hipMemcpy(&status, s.status, sizeof(int), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(dx.data(), d_dx, sizeof(double) * p, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return handle_hip_fail(h, e, "Cholesky solve");
+        if (status) return handle_fail(h, COX_ENUMERIC, "the information matrix is not positive definite");
+        prev = beta;
+        obj_prev = ev.objective;
+        double step = 0.0, bmax = 1.0;
+        for (int j = 0; j < p; ++j) {
+            beta[j] += dx[j];
+            step = std::max(step, std::fabs(dx[j]));
+        }
+        for (int j = 0; j < p; ++j) bmax = std::max(bmax, std::fabs(beta[j]));
+        ++iters;
+        last_step = step;
+        if (step <= h->opt.tol * bmax) {
+            converged = true;
+            break;
+        }
+        if (!frozen && h->opt.x_precision != COX_F64 && step <= 1e-3 * bmax) frozen = true;
+    }
+    std::memcpy(beta_out, beta.data(), sizeof(double) * p);
+    rc = converged ? COX_OK : COX_NOT_CONVERGED;
+    if (info) {
+        info->status = rc;
+        info->iters = iters;
+        info->coord_evals = evals;
+        info->objective = objective;
+        info->last_step = last_step;
+        int pinned = 0;
+        double kkt = 0.0;
+        for (int j = 0; j < p; ++j) {
+            if (!freec[j]) ++pinned;
+            else kkt = std::max(kkt, std::fabs(ev.grad[j]));
+        }
+        info->n_pinned = pinned;
+        info->kkt_inf = kkt;
+    }
+    return rc;
+}

@@ -1,0 +1,220 @@
+"""GPU parity of the full evaluation, the information contraction and the Newton fit.
+
+Everything goes through the C ABI (cox_evaluate_full, cox_fit in
+COX_NEWTON_REFINE mode) and is compared with the FP64 CPU oracle on the same
+seeded inputs.
+
+Tolerances:
+* objective, gradient, diagonal Hessian (FP64 on both sides): 1e-11 * max(E, |obj|)
+  for the objective (E = number of events); for column j with m_j = max(1, max_r |x_rj|),
+  1e-11 * 2 E m_j for the score and 1e-11 * E m_j^2 for the diagonal: the weights
+  w_r Lambda_r sum to E over the rows (each event group g contributes d_g S0_g / S0_g),
+  so these bound the sums of absolute values of the terms;
+* information matrix in FP64: |gpu_ij - oracle_ij| <= 1e-11 * r_ij with
+  r_ij = sqrt(F_ii F_jj) + sqrt(S_ii S_jj), where F = X' diag(w Lambda) X and
+  S = sum_g d_g xbar_g xbar_g' are the two terms (both PSD, so by Cauchy-Schwarz
+  r_ij bounds the sum of absolute values of every product that enters entry ij);
+* information matrix with X in BF16 (per-column power-of-two scales): a product
+  b_k x_ik x_jk of the first term is formed from three values rounded to 8
+  significant bits (x_ik, x_jk and the weighted operand b_k x_ik), a product
+  z_gi z_gj of the second from two; FP32 accumulation adds at most k 2^-24
+  relative over a K range of k rows (the contraction splits N into 128 ranges
+  and the groups into 64).  With u = 2^-8 and a margin for second-order terms,
+      |gpu_ij - oracle_ij| <= (3.5 u + k 2^-24) r_ij;
+* fitted beta (FP64 or BF16 factor + FP64 refinement): max|gpu - oracle| /
+  max|oracle| <= 1e-10, with the oracle's own Newton fit to 1e-14.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cox_oracle as orc
+from paper_2310_16238_amd import coxmi, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+U_BF16 = 2.0 ** -8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    coxmi.lib()
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def _oracle_eval(d, beta):
+    lay = orc.canonical_layout(d.time, d.event, d.stratum)
+    Xc = orc.to_canonical(d.X, lay)
+    return orc.full_eval(Xc, lay, beta, want_info=True)
+
+
+def _scale(fe):
+    f = np.sqrt(np.clip(np.diag(fe.info_first), 0, None))
+    s = np.sqrt(np.clip(np.diag(fe.info_second), 0, None))
+    return np.outer(f, f) + np.outer(s, s)
+
+
+def _first_order_tols(X, E):
+    m = np.maximum(1.0, np.max(np.abs(X), axis=0))
+    return 1e-11 * 2.0 * max(1.0, E) * m, 1e-11 * max(1.0, E) * m * m
+
+
+def _check_first_order(d, obj, g, hd, fe):
+    E = float(d.event.sum())
+    tg, th = _first_order_tols(d.X, E)
+    assert abs(obj - fe.objective) <= 1e-11 * max(E, abs(fe.objective)), (obj, fe.objective)
+    assert np.all(np.abs(g - fe.grad) <= tg), float(np.max(np.abs(g - fe.grad) / tg))
+    assert np.all(np.abs(hd - fe.hess_diag) <= th), float(np.max(np.abs(hd - fe.hess_diag) / th))
+
+
+def _mixed(n, p, K, seed, ties=False):
+    return synth.make("mixed", n, p, K, seed, beta_sd=0.05, tie_round=100.0 if ties else 0.0)
+
+
+# (name, data factory): several 64-column and 32-column tiles with ragged tails,
+# N not a multiple of the row tile, ties, one and many strata
+CASES = [
+    ("small-K1", lambda: synth.config_small(K=1, gamma=0.0)),
+    ("small-K10-ties", lambda: synth.config_small(K=10, ties=True, gamma=0.0)),
+    ("mixed-p70-K37", lambda: _mixed(20_011, 70, 37, 3)),
+    ("mixed-p97-K1-ties", lambda: _mixed(9_001, 97, 1, 4, ties=True)),
+    ("ar1-p130-K500", lambda: synth.config_ar1(n=30_000, p=130, K=500)),
+]
+
+
+def _beta_probe(d, seed=11):
+    rng = np.random.default_rng(seed)
+    return d.beta_true * 0.7 + rng.normal(0.0, 0.02, size=d.p) / np.maximum(d.X.std(0), 1e-3)
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_full_evaluation_f64(name, make):
+    d = make()
+    beta = _beta_probe(d)
+    _say(f"evaluate_full F64 {name} n={d.n} p={d.p}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum) as m:
+        obj, g, hd, info = m.evaluate_full(beta)
+        obj2, g2, hd2, none = m.evaluate_full(beta, want_info=False)
+    fe = _oracle_eval(d, beta)
+    _check_first_order(d, obj, g, hd, fe)
+    assert none is None and obj2 == obj and np.array_equal(g2, g) and np.array_equal(hd2, hd)
+    r = _scale(fe)
+    err = np.abs(info - fe.info)
+    assert np.all(err <= 1e-11 * r), float(np.max(err / r))
+    assert np.array_equal(info, info.T)
+    # its diagonal is the diagonal Hessian of the scan path
+    assert np.all(np.abs(np.diag(info) - hd) <= _first_order_tols(d.X, float(d.event.sum()))[1])
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_information_bf16_within_bound(name, make):
+    d = make()
+    beta = _beta_probe(d)
+    _say(f"evaluate_full BF16 {name} n={d.n} p={d.p}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, x_precision=coxmi.COX_BF16) as m:
+        obj, g, hd, info = m.evaluate_full(beta)
+    fe = _oracle_eval(d, beta)
+    # objective, gradient and diagonal stay FP64
+    _check_first_order(d, obj, g, hd, fe)
+    r = _scale(fe)
+    k = math.ceil(d.n / 128) + 16
+    bound = (3.5 * U_BF16 + k * 2.0 ** -24) * r
+    err = np.abs(info - fe.info)
+    worst = float(np.max(err / r))
+    _say(f"  max |err| / r = {worst:.3e} (bound {3.5 * U_BF16 + k * 2.0 ** -24:.3e})")
+    assert np.all(err <= bound), worst
+    assert np.array_equal(info, info.T)
+    # rounding errors, not misplaced entries: the typical error is far below the bound
+    assert float(np.median(err / r)) <= 0.1 * 3.5 * U_BF16
+
+
+@pytest.mark.parametrize("prec", [coxmi.COX_F64, coxmi.COX_BF16], ids=["f64", "bf16"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_newton_fit(name, make, prec):
+    d = make()
+    _say(f"newton fit {name} prec={prec}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE, x_precision=prec,
+                        tol=1e-13, max_iter=200) as m:
+        beta, info = m.fit()
+    ref = orc.fit_newton(d.X, d.time, d.event, d.stratum, tol=1e-14)
+    assert ref.converged
+    assert info["status"] == coxmi.COX_OK, info
+    err = _rel(beta, ref.beta)
+    _say(f"  iters={info['iters']} evals={info['coord_evals']} rel err {err:.3e}")
+    assert err <= 1e-10
+    free = ~orc.degenerate_columns(orc.to_canonical(d.X, orc.canonical_layout(d.time, d.event, d.stratum)),
+                                   orc.canonical_layout(d.time, d.event, d.stratum))
+    assert np.all(beta[~free] == 0.0)
+    assert info["n_pinned"] == int(np.count_nonzero(~free))
+    assert abs(info["objective"] - ref.objective) <= 1e-11 * max(float(d.event.sum()), abs(ref.objective))
+
+
+def test_newton_fit_mixed_precision_full_size():
+    """N = 1e6, P = 200 AR(1), K = 5e4: BF16 contraction + FP64 refinement vs the oracle's optimum."""
+    from conftest import read_golden
+    gold = read_golden("newton_mixed_n1e6_p200.txt")
+    d = synth.config_mixed()
+    _say("newton fit BF16 n=1e6 p=200 K=5e4")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE,
+                        x_precision=coxmi.COX_BF16, tol=1e-13, max_iter=200) as m:
+        beta, info = m.fit()
+        obj, g, _, _ = m.evaluate_full(beta, want_info=False)
+    ref = np.array(gold["beta"])
+    err = _rel(beta, ref)
+    _say(f"  iters={info['iters']} evals={info['coord_evals']} rel err {err:.3e} max|grad| {np.max(np.abs(g)):.3e}")
+    assert info["status"] == coxmi.COX_OK
+    assert err <= 1e-10
+    assert abs(obj - gold["objective"][0]) <= 1e-11 * abs(gold["objective"][0])
+
+
+def test_newton_options_rejected():
+    d = synth.config_small(n=500, K=1)
+    with pytest.raises(coxmi.CoxError) as e:
+        coxmi.cox_init(d.X, d.time, d.event, gamma=1.0, mode=coxmi.COX_NEWTON_REFINE)
+    assert e.value.code == coxmi.COX_EUNSUPPORTED
+    for prec in (coxmi.COX_F32, coxmi.COX_FP8_E4M3):
+        with pytest.raises(coxmi.CoxError) as e:
+            coxmi.cox_init(d.X, d.time, d.event, x_precision=prec)
+        assert e.value.code == coxmi.COX_EUNSUPPORTED
+
+
+def test_full_evaluation_edge_cases():
+    # no events: zero objective, gradient and information
+    n, p = 300, 5
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((n, p))
+    t = rng.random(n)
+    with coxmi.CoxModel(X, t, np.zeros(n, np.uint8)) as m:
+        obj, g, hd, info = m.evaluate_full(np.full(p, 0.3))
+    assert obj == 0.0 and not np.any(g) and not np.any(hd) and not np.any(info)
+    # one row, one column; and a single event per stratum (every xbar is the row itself)
+    for (n, p, K) in [(1, 1, 1), (64, 3, 64), (257, 33, 2)]:
+        X = rng.standard_normal((n, p))
+        t = rng.random(n)
+        ev = np.ones(n, np.uint8)
+        st = np.arange(n, dtype=np.int32) % K
+        beta = rng.normal(0, 0.3, p)
+        for prec in (coxmi.COX_F64, coxmi.COX_BF16):
+            with coxmi.CoxModel(X, t, ev, st, x_precision=prec) as m:
+                obj, g, hd, info = m.evaluate_full(beta)
+            lay = orc.canonical_layout(t, ev, st)
+            fe = orc.full_eval(orc.to_canonical(X, lay), lay, beta)
+            assert abs(obj - fe.objective) <= 1e-11 * max(n, abs(fe.objective))
+            tg, _ = _first_order_tols(X, float(n))
+            assert np.all(np.abs(g - fe.grad) <= tg)
+            r = _scale(fe) + 1e-300
+            lim = 1e-11 if prec == coxmi.COX_F64 else 3.5 * U_BF16 + 64 * 2.0 ** -24
+            assert np.all(np.abs(info - fe.info) <= lim * r + 1e-12), (n, p, K, prec)
