@@ -15,7 +15,7 @@ Prints one JSON line on stdout; progress goes to stderr.
                  plus 4 B per row for the row words read once) over the kernel
                  duration measured with HIP events on its stream
   cpu_baseline   the CPU oracle's CCD (plain C, one thread) on a bounded
-                 sample of the same workload: its first 5 sweeps
+                 sample of the same workload: its first 20 sweeps
 """
 import argparse
 import json
@@ -35,7 +35,37 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(d, sweeps=5):
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ccd_kernel_ar1_n1e6_p50_K5e4.md")
+KERNEL_SOURCES = ["ccd_kernel.hip", "segscan.hpp", "internal.h"]
+
+
+def recorded_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when the
+    kernel sources no longer hash to the value the counters were taken on."""
+    import hashlib
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    fields = {}
+    for line in lines:
+        key, sep, val = line.partition(": ")
+        if sep and key and " " not in key:
+            fields[key] = val.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2310_16238_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(d, sweeps=20):
     """Oracle CCD (single-threaded C) on the first `sweeps` sweeps of the same data."""
     from oracle import cox_oracle as orc
     L = orc.canonical_layout(d.time, d.event, d.stratum)
@@ -55,6 +85,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed fits, run a copy kernel (y = 1 * x) over a buffer of this many "
+                         "MiB three times: known bytes against which hardware byte counters are scaled")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -121,13 +154,24 @@ def main():
         "kernel_ms_per_fit": 1e3 * kernel_s,
         "us_per_coordinate": 1e6 * kernel_s / evals_per_fit,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
                      "kernel": "ccd_kernel (persistent, one launch per fit)",
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
     model.close()
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)   # an elementwise kernel: reads and writes nbytes (a copy engine would not show)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 copies of {nbytes} bytes (read {nbytes} + write {nbytes} each)")
+        out["copy_probe_bytes"] = nbytes
+        del src, dst
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle CCD, first 5 sweeps")
+        log("cpu baseline: oracle CCD, first 20 sweeps")
         out["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(out), flush=True)
 
