@@ -79,9 +79,134 @@ def cpu_baseline(d, sweeps=20):
                       f"N={d.n} P={d.p} K=50000 data, plain C, one thread, {dt:.1f} s"}
 
 
+def _rel(a, b):
+    import numpy as np
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def run_serve(args):
+    """Serving stream: independent fits of uneven (n, p) through the fit server, against the
+    plain FP64 GPU path (cox_init + cox_fit per request, one after another)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+    from paper_2310_16238_amd import coxmi, synth
+
+    torch.cuda.set_device(0)
+    R = args.requests
+    log(f"drawing {R} serving requests (n log-uniform in [1e3, 1e5], p in 5..100, seed 3)")
+    with ThreadPoolExecutor(16) as ex:
+        reqs = list(ex.map(synth.serving_request, range(R)))
+    rows = sum(d.n for d in reqs)
+    log(f"  {rows} rows, {sum(d.n * d.p for d in reqs) * 8 / 1e9:.1f} GB of FP64 X")
+
+    # plain FP64 GPU path on a sample of the stream
+    sample = reqs[:args.plain_sample]
+    plain = {}
+    plain_beta = {}
+    for mode, name in [(coxmi.COX_CCD, "ccd"), (coxmi.COX_NEWTON_REFINE, "newton_f64")]:
+        with coxmi.CoxModel(sample[0].X, sample[0].time, sample[0].event, sample[0].stratum, mode=mode) as m:
+            m.fit()   # warm the code paths
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, d in enumerate(sample):
+            with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=mode, tol=1e-12) as m:
+                beta, info = m.fit()
+            plain_beta[(name, i)] = beta
+        plain[name] = len(sample) / (time.perf_counter() - t0)
+        log(f"plain {name}: {plain[name]:.1f} fits/s over {len(sample)} requests")
+    plain_best = max(plain.values())
+
+    def serve(batch, arrivals=None):
+        with coxmi.CoxServer(hbm_budget=args.hbm_gib << 30, prep_threads=args.prep_threads) as srv:
+            warm = [srv.submit(d.X, d.time, d.event, d.stratum) for d in batch[:4]]
+            srv.drain()
+            for t in warm:
+                srv.poll(t)
+            st0 = srv.stats()
+            tickets = []
+            t_start = time.perf_counter()
+            for i, d in enumerate(batch):
+                if arrivals is not None:
+                    delay = arrivals[i] - (time.perf_counter() - t_start)
+                    if delay > 0:
+                        time.sleep(delay)
+                tickets.append(srv.submit(d.X, d.time, d.event, d.stratum))
+            srv.drain()
+            res = [srv.poll(t) for t in tickets]
+            st1 = srv.stats()
+        sub = np.array([r[2]["submit_s"] for r in res])
+        done = np.array([r[2]["done_s"] for r in res])
+        lat = done - sub
+        span = float(done.max() - sub.min())
+        stats = {k: st1[k] - st0[k] for k in ("completed", "iterations", "gpu_busy_s")}
+        stats.update(resident_peak=st1["resident_peak"], arena_peak=st1["arena_peak"],
+                     mean_resident=st1["mean_resident"])
+        return res, {"fits_per_s": len(batch) / span, "makespan_s": span,
+                     "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                                    "p99": 1e3 * float(np.percentile(lat, 99))},
+                     "statuses": sorted(set(int(r[1]["status"]) for r in res)), "server": stats}
+
+    log(f"served, saturating (all {R} requests at once)")
+    res_sat, sat = serve(reqs)
+    log(f"  {sat['fits_per_s']:.1f} fits/s, p50 {sat['latency_ms']['p50']:.1f} ms, p99 {sat['latency_ms']['p99']:.1f} ms")
+    lam = 1.5 * plain_best
+    R2 = int(min(R, max(64, args.poisson_seconds * lam)))
+    log(f"served, Poisson arrivals at {lam:.1f}/s (1.5 x plain), {R2} requests")
+    res_poi, poi = serve(reqs[:R2], synth.arrival_times(R2, lam))
+    log(f"  {poi['fits_per_s']:.1f} fits/s, p50 {poi['latency_ms']['p50']:.1f} ms, p99 {poi['latency_ms']['p99']:.1f} ms")
+
+    # accuracy on a spread sample: served and plain against the oracle
+    from oracle import cox_oracle as orc
+    idx = sorted(set(list(range(min(len(sample), 8))) + list(np.linspace(0, R - 1, args.check).astype(int))))
+    worst_served, worst_plain = 0.0, 0.0
+    for i in idx:
+        d = reqs[i]
+        ref = orc.fit_newton(d.X, d.time, d.event, d.stratum, tol=1e-14)
+        worst_served = max(worst_served, _rel(res_sat[i][0], ref.beta))
+        for name in plain:
+            if (name, i) in plain_beta:
+                worst_plain = max(worst_plain, _rel(plain_beta[(name, i)], ref.beta))
+    log(f"rel err vs oracle on {len(idx)} requests: served {worst_served:.2e}, plain {worst_plain:.2e}")
+
+    evals = sum(r[1]["coord_evals"] for r in res_sat)
+    alg_bytes = sum(r[1]["coord_evals"] * (16.0 * d.n * d.p + 64.0 * d.n) for r, d in zip(res_sat, reqs))
+    busy = sat["server"]["gpu_busy_s"]
+    achieved = alg_bytes / busy / 1e9
+    out = {
+        "metric": METRIC,
+        "value": sat["fits_per_s"],
+        "unit": "fits/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * sat["makespan_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 score, f32 contraction", "data": "synthetic",
+        "config": {"workload": f"serving stream: {R} independent unpenalised fits, n log-uniform in [1e3, 1e5], "
+                               "p uniform in 5..100 with a ones column, K = n/100 strata, seed 3",
+                   "requests": R, "rows": rows},
+        "plain_fp64_fits_per_s": plain, "speedup_vs_plain": sat["fits_per_s"] / plain_best,
+        "saturating": sat, "poisson": dict(poi, rate_per_s=lam, requests=R2),
+        "rel_err_vs_oracle": {"served_max": worst_served, "plain_max": worst_plain, "requests_checked": len(idx)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "served rounds (all batched kernels), algorithmic bytes 16 n p + 64 n per evaluation",
+                     "evaluations": evals},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["ccd", "serve"], default="ccd",
+                    help="ccd: the CCD fit of the N=1e6 P=50 workload (default); serve: the serving stream")
+    ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
+    ap.add_argument("--plain-sample", type=int, default=32, help="serve: requests timed on the plain FP64 path")
+    ap.add_argument("--poisson-seconds", type=float, default=30.0, help="serve: length of the Poisson run")
+    ap.add_argument("--check", type=int, default=16, help="serve: requests checked against the oracle")
+    ap.add_argument("--hbm-gib", type=int, default=32, help="serve: device budget of the server")
+    ap.add_argument("--prep-threads", type=int, default=12, help="serve: host prep threads")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
@@ -94,6 +219,9 @@ def main():
         print("bench.py runs on one GPU only: there is no multi-GPU path (--gpus must be 1)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        run_serve(args)
+        return
 
     import numpy as np
     import torch

@@ -199,6 +199,91 @@ void cox_release(cox_handle *h);
 /* Message for the last error on h (NULL: the last cox_init failure of this thread). */
 const char *cox_last_error(const cox_handle *h);
 
+/* ------------------------------------------------------------------ fit server
+ *
+ * Continuous batching of many independent, unpenalised stratified Cox fits
+ * of uneven size (Eq. strat_l per request, gamma = 0).  Each request is put
+ * in the canonical order of Sec. 2.7 by a host thread pool and admitted to
+ * the device as soon as a slot is free and its footprint fits in the
+ * server's device budget; every resident fit then takes one Newton step per
+ * round of batched kernels (FP64 objective and score by the segmented scans
+ * of Sec. 2.6-2.7; information matrix in FP32 on the matrix cores; FP64
+ * Cholesky and iterative refinement as in COX_NEWTON_REFINE).  Requests that
+ * arrive while others run join at the next round.  No work item mixes two
+ * fits and each fit's sums run in an order fixed by its own (n, p), so a
+ * result does not depend on what else is resident.
+ */
+typedef struct cox_server cox_server;
+
+typedef struct {
+    size_t hbm_budget;      /* device bytes for resident fits (default 8 GiB) */
+    size_t staging_bytes;   /* pinned host bytes for staged uploads (default 1 GiB) */
+    int max_resident;       /* fits resident at once (default 1024) */
+    int prep_threads;       /* host threads that canonicalise requests (default 8) */
+    int x_precision;        /* COX_F32 (the only value accepted) */
+    double tol;             /* stop when max|step| <= tol * max(1, max|beta|) (default 1e-12) */
+    int max_iter;           /* Newton steps per fit (default 100) */
+    int device;             /* HIP device ordinal, -1 = the current device */
+} cox_server_options;
+
+typedef struct {
+    double submit_s;        /* seconds on the server's monotonic clock */
+    double admit_s;         /* the fit was given device memory */
+    double done_s;          /* its result was available */
+} cox_request_times;
+
+typedef struct {
+    int64_t submitted, completed, iterations;
+    int64_t resident_now, resident_peak;
+    double mean_resident;   /* resident fits per round, averaged over rounds */
+    size_t arena_bytes, arena_peak;
+    double gpu_busy_s;      /* sum over rounds of launch-to-completion time */
+    double now_s;           /* the server's clock */
+} cox_server_counters;
+
+/* cox_server_submit flag: do not copy the inputs; the caller keeps x, time,
+ * event and stratum valid and unchanged until the ticket's result is ready */
+#define COX_SUBMIT_BORROW 1
+
+void cox_server_default_options(cox_server_options *o);
+
+/* Allocate the device arena (hbm_budget) and pinned staging, start the
+ * threads.  Errors: COX_EINVAL (bad options), COX_EUNSUPPORTED (x_precision
+ * other than COX_F32), COX_ENOMEM, COX_EDEVICE; message via
+ * cox_server_last_error(NULL). */
+int cox_server_create(cox_server **out, const cox_server_options *o);
+
+/* Queue one fit; returns at once with its ticket (tickets start at 1).
+ *   d     : host data as for cox_init (stratum may be NULL)
+ *   flags : 0 (inputs copied) or COX_SUBMIT_BORROW
+ * Errors: COX_EINVAL (the checks of cox_init), COX_EUNSUPPORTED (p > 128),
+ * or the server's fatal device error.  A request whose device footprint
+ * exceeds hbm_budget (or staging_bytes) completes with status COX_EUNSUPPORTED. */
+int cox_server_submit(cox_server *s, const cox_data *d, int flags, uint64_t *ticket);
+
+/* Collect a result: returns COX_OK and fills beta_out (p doubles, original
+ * column order), info (status COX_OK, COX_NOT_CONVERGED, COX_ENUMERIC, ...;
+ * iters = Newton steps, coord_evals = evaluations) and times (each may be
+ * NULL); the result is then released.  Returns 1 while the fit is pending and
+ * COX_EINVAL for an unknown or already collected ticket. */
+int cox_server_poll(cox_server *s, uint64_t ticket, double *beta_out, cox_fit_info *info,
+                    cox_request_times *times);
+
+/* Block until the ticket's result is ready (COX_OK), the timeout passes
+ * (1; timeout_s < 0 waits for ever) or the server failed (its error code). */
+int cox_server_wait(cox_server *s, uint64_t ticket, double timeout_s);
+
+/* Block until every submitted fit has finished; codes as cox_server_wait. */
+int cox_server_drain(cox_server *s, double timeout_s);
+
+int cox_server_stats(cox_server *s, cox_server_counters *st);
+
+/* Message for the last error on s (NULL: the last failed cox_server_create of this thread). */
+const char *cox_server_last_error(cox_server *s);
+
+/* Stop the threads (fits still running are abandoned) and free everything. */
+void cox_server_destroy(cox_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,28 +1,47 @@
-"""Build the HIP library libcoxmi.so in-tree for gfx950 (hipcc, no JIT)."""
+"""Build the HIP library libcoxmi.so in-tree for gfx950 (hipcc, no JIT).
+
+Each source is compiled to an object under csrc/_build/ (in parallel), then
+linked; build() always recompiles every source.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
+OBJ = os.path.join(CSRC, "_build")
 LIB = os.path.join(PKG, "libcoxmi.so")
-SOURCES = [os.path.join(CSRC, f) for f in
-           ["ccd_kernel.hip", "newton.hip", "contraction.hip", "coxmi.cpp", "newton_host.cpp"]]
+SOURCES = ["ccd_kernel.hip", "newton.hip", "contraction.hip", "serve.hip",
+           "canonical.cpp", "coxmi.cpp", "newton_host.cpp", "server.cpp"]
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
 
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", *FLAGS, *SOURCES, "-o", tmp]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-lpthread", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

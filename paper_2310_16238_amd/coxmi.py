@@ -61,6 +61,32 @@ class cox_fit_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class cox_server_options(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("staging_bytes", ctypes.c_size_t),
+                ("max_resident", ctypes.c_int), ("prep_threads", ctypes.c_int),
+                ("x_precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("device", ctypes.c_int)]
+
+
+class cox_request_times(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class cox_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("resident_now", ctypes.c_int64), ("resident_peak", ctypes.c_int64),
+                ("mean_resident", ctypes.c_double), ("arena_bytes", ctypes.c_size_t),
+                ("arena_peak", ctypes.c_size_t), ("gpu_busy_s", ctypes.c_double), ("now_s", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+COX_SUBMIT_BORROW = 1
+
 _lib = None
 
 # (name, restype, argtypes) of every entry point in include/coxmi.h
@@ -80,6 +106,17 @@ SIGNATURES = [
     ("cox_segscan_f64", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
     ("cox_release", None, [_VP]),
     ("cox_last_error", ctypes.c_char_p, [_VP]),
+    ("cox_server_default_options", None, [ctypes.POINTER(cox_server_options)]),
+    ("cox_server_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(cox_server_options)]),
+    ("cox_server_submit", ctypes.c_int, [_VP, ctypes.POINTER(cox_data), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    ("cox_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, _DP, ctypes.POINTER(cox_fit_info),
+                                       ctypes.POINTER(cox_request_times)]),
+    ("cox_server_wait", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_double]),
+    ("cox_server_drain", ctypes.c_int, [_VP, ctypes.c_double]),
+    ("cox_server_stats", ctypes.c_int, [_VP, ctypes.POINTER(cox_server_counters)]),
+    ("cox_server_last_error", ctypes.c_char_p, [_VP]),
+    ("cox_server_destroy", None, [_VP]),
 ]
 
 
@@ -258,6 +295,121 @@ class CoxModel:
         if self.h:
             cox_release(self.h)
             self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ fit server
+
+def cox_server_default_options() -> cox_server_options:
+    o = cox_server_options()
+    lib().cox_server_default_options(ctypes.byref(o))
+    return o
+
+
+class CoxServer:
+    """Continuous-batching server of independent unpenalised fits (cox_server_* in the C ABI).
+
+    submit() returns a ticket at once; poll() returns None while the fit is
+    pending, else (beta, info, times).  Inputs are borrowed by default (the
+    arrays are kept referenced here until their result is collected).
+    """
+
+    def __init__(self, hbm_budget=None, staging_bytes=None, max_resident=None, prep_threads=None,
+                 tol=None, max_iter=None, device=None):
+        o = cox_server_default_options()
+        if hbm_budget is not None:
+            o.hbm_budget = int(hbm_budget)
+        if staging_bytes is not None:
+            o.staging_bytes = int(staging_bytes)
+        if max_resident is not None:
+            o.max_resident = int(max_resident)
+        if prep_threads is not None:
+            o.prep_threads = int(prep_threads)
+        if tol is not None:
+            o.tol = float(tol)
+        if max_iter is not None:
+            o.max_iter = int(max_iter)
+        if device is not None:
+            o.device = int(device)
+        h = ctypes.c_void_p()
+        rc = lib().cox_server_create(ctypes.byref(h), ctypes.byref(o))
+        if rc != COX_OK:
+            msg = lib().cox_server_last_error(None)
+            raise CoxError(rc, msg.decode() if msg else "")
+        self.h = h.value
+        self._keep = {}
+        self._p = {}
+
+    def _check(self, rc, ok=(COX_OK,)):
+        if rc not in ok:
+            msg = lib().cox_server_last_error(self.h)
+            raise CoxError(rc, msg.decode() if msg else "")
+        return rc
+
+    def submit(self, X, time, event, stratum=None, borrow=True) -> int:
+        X = np.asfortranarray(X, dtype=np.float64)
+        n, p = X.shape
+        time = np.ascontiguousarray(time, dtype=np.float64)
+        event = np.ascontiguousarray(event, dtype=np.uint8)
+        keep = [X, time, event]
+        d = cox_data(n=n, p=p, x=_dptr(X), ldx=n, time=_dptr(time),
+                     event=event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        if stratum is not None:
+            st = np.ascontiguousarray(stratum, dtype=np.int32)
+            keep.append(st)
+            d.stratum = st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        t = ctypes.c_uint64()
+        self._check(lib().cox_server_submit(self.h, ctypes.byref(d), COX_SUBMIT_BORROW if borrow else 0,
+                                            ctypes.byref(t)))
+        if borrow:
+            self._keep[t.value] = keep
+        self._p[t.value] = p
+        return t.value
+
+    def poll(self, ticket):
+        p = self._p[ticket]
+        beta = np.zeros(p)
+        info = cox_fit_info()
+        times = cox_request_times()
+        rc = self._check(lib().cox_server_poll(self.h, ticket, _dptr(beta), ctypes.byref(info), ctypes.byref(times)),
+                         ok=(COX_OK, 1))
+        if rc == 1:
+            return None
+        self._keep.pop(ticket, None)
+        self._p.pop(ticket, None)
+        return beta, info.as_dict(), times.as_dict()
+
+    def wait(self, ticket, timeout=None) -> bool:
+        rc = self._check(lib().cox_server_wait(self.h, ticket, -1.0 if timeout is None else float(timeout)),
+                         ok=(COX_OK, 1))
+        return rc == COX_OK
+
+    def drain(self, timeout=None) -> bool:
+        rc = self._check(lib().cox_server_drain(self.h, -1.0 if timeout is None else float(timeout)),
+                         ok=(COX_OK, 1))
+        return rc == COX_OK
+
+    def stats(self) -> dict:
+        c = cox_server_counters()
+        self._check(lib().cox_server_stats(self.h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().cox_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
 
     def __enter__(self):
         return self

@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "canonical.h"
 #include "handle.h"
 #include "internal.h"
 
@@ -130,10 +131,8 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     *out = nullptr;
     if (!d) return fail(nullptr, COX_EINVAL, "data is NULL");
     const int64_t n = d->n, p = d->p;
-    if (n < 1 || p < 1) return fail(nullptr, COX_EINVAL, "need n >= 1 and p >= 1");
-    if (d->ldx < n) return fail(nullptr, COX_EINVAL, "ldx < n");
-    if (!d->x || !d->time || !d->event) return fail(nullptr, COX_EINVAL, "x, time and event are required");
     if (n > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "n exceeds 2^29 - 1");
+    if (const char *bad = check_data(n, p, d->ldx, d->x, d->time, d->event)) return fail(nullptr, COX_EINVAL, bad);
     if (p > 4096) return fail(nullptr, COX_EUNSUPPORTED, "p > 4096 is not supported by the resident kernel");
     cox_options opt;
     if (o) opt = *o;
@@ -147,10 +146,6 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     if (!(opt.gamma >= 0.0) || !std::isfinite(opt.gamma)) return fail(nullptr, COX_EINVAL, "gamma must be finite and >= 0");
     if (!(opt.tol >= 0.0)) return fail(nullptr, COX_EINVAL, "tol must be >= 0");
     if (opt.max_iter < 1) return fail(nullptr, COX_EINVAL, "max_iter must be >= 1");
-    for (int64_t i = 0; i < n; ++i) {
-        if (!std::isfinite(d->time[i])) return fail(nullptr, COX_EINVAL, "time contains NaN or inf");
-        if (d->event[i] > 1) return fail(nullptr, COX_EINVAL, "event must be 0 or 1");
-    }
 
     cox_handle *h = new cox_handle();
     h->n = n;
@@ -161,38 +156,7 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     (void)hipGetDevice(&h->device);
 
     // canonical order: stratum ascending, time descending, original index ascending
-    const double *tm = d->time;
-    const int32_t *st = d->stratum;
-    h->perm.resize(n);
-    std::iota(h->perm.begin(), h->perm.end(), int64_t(0));
-    std::sort(h->perm.begin(), h->perm.end(), [tm, st](int64_t a, int64_t b) {
-        const int32_t sa = st ? st[a] : 0, sb = st ? st[b] : 0;
-        if (sa != sb) return sa < sb;
-        if (tm[a] != tm[b]) return tm[a] > tm[b];
-        return a < b;
-    });
-    // head flags, events and tie-group counts on the group's last row
-    h->meta.assign(n, 0u);
-    int64_t gstart = 0;
-    uint32_t gcount = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t r = h->perm[i];
-        const bool new_stratum = (i == 0) || (st && st[r] != st[h->perm[i - 1]]);
-        const bool new_group = new_stratum || tm[r] != tm[h->perm[i - 1]];
-        if (new_group) {
-            gstart = i;
-            gcount = 0;
-        }
-        (void)gstart;
-        if (new_stratum) h->meta[i] |= kHeadBit;
-        if (d->event[r]) {
-            h->meta[i] |= kEventBit;
-            ++gcount;
-        }
-        const bool last_of_group = (i + 1 == n) ||
-            (st && st[h->perm[i + 1]] != st[r]) || tm[h->perm[i + 1]] != tm[r];
-        if (last_of_group) h->meta[i] |= gcount;
-    }
+    canonical_order(n, d->time, d->event, d->stratum, h->perm, h->meta);
 
     h->gamma.assign(p, opt.gamma);
     if (o && o->penalize)

@@ -1,0 +1,82 @@
+// serve.h -- device-side layout of the fit server (kernels in serve.hip, host
+// engine in server.cpp).
+//
+// Every resident fit owns a block of the server's device arena holding its
+// canonical data and its Newton state; one launch of each batched kernel
+// covers all resident fits through a list of (fit, piece) work items, so fits
+// of any size and at any stage of their iteration share the same launches.
+// No work item mixes two fits, and each fit's sums are taken in an order that
+// depends only on its own (n, p), so a fit's result is the same whatever else
+// is resident.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace coxmi {
+namespace serve {
+
+constexpr int kMaxP = 128;        // columns of a served fit (its Cholesky factor lives in LDS)
+constexpr int kRowPad = 64;       // rows are padded to a multiple of this
+constexpr int kEtaRows = 256;     // rows per work item of the X beta kernel
+constexpr int kXRange = 4096;     // rows per K range of the X' diag(b) X contraction
+constexpr int kZRange = 4096;     // event groups per K range of the Z'Z contraction
+constexpr int kTile = 32;         // edge of a contraction tile (one MFMA block)
+
+// FitState.flags
+enum : int {
+    kHaveFree = 1,   // the non-degenerate columns have been chosen
+    kFrozen = 2,     // the Cholesky factor is kept; only the FP64 score is recomputed
+    kDone = 4,       // status is final
+};
+
+// Written by the kernels, read back by the host after every iteration.
+struct alignas(16) FitState {
+    double obj_eval;    // objective at the current beta (rows kernel)
+    double obj;         // objective at the last accepted point
+    double obj_prev;    // objective where the last accepted step started
+    double last_step;   // max |step| of the last accepted step
+    double kkt;         // max |score| over the free columns at the last evaluation
+    int iters;          // accepted Newton steps
+    int evals;          // evaluations (accepted steps + halvings)
+    int halvings;       // consecutive halvings of the current step
+    int flags;
+    int status;         // COX_OK / COX_NOT_CONVERGED / COX_ENUMERIC once kDone
+    unsigned range;     // set when an event's risk-set sum left the FP64 normal range
+    int n_pinned;       // columns held at zero
+    int pad_;
+};
+
+// Everything a kernel needs to know about one resident fit (device pointers).
+struct FitDesc {
+    const double *x;        // [p][ld] FP64, canonical rows, padding rows zero
+    float *xf;              // [p][ld] FP32 copy for the contraction
+    const uint32_t *meta;   // [ld] row words (padding rows: head | pad)
+    const int32_t *gidx;    // [ld] event-group index at group ends, else -1
+    double *eta, *w, *s0, *hz, *a, *b;   // [ld] row vectors
+    float *z;               // [p][ldz] sqrt(d_g) xbar_g
+    double *beta, *prev, *grad, *diag1, *diag2;   // [p]
+    uint8_t *free_col;      // [p]
+    double *L;              // [p][p] Cholesky factor (row-major, lower)
+    float *part;            // [(nxr + nzr) * npairs][32 * 32] contraction partials
+    double *tilemax;        // [ntile]
+    FitState *st;
+    int64_t n, ld, ldz;
+    int p, G;               // columns, event groups
+    int nxr, nzr;           // K ranges of the two products (nzr = 0 without events)
+    int npairs, ntile;      // tile pairs of the upper triangle; X beta work items
+    double tol;
+    int max_iter;
+    int freeze;             // 1: keep the factor once steps are small (reduced-precision contraction)
+};
+
+// Launchers (return a hipError_t value).  Work-item arrays are device memory.
+int launch_admit(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
+int launch_eta(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
+int launch_rows(const FitDesc *fits, const int *slots, int nslots, hipStream_t s);
+int launch_cols(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
+int launch_syrk(const FitDesc *fits, const int4 *items, int nitems, hipStream_t s);
+int launch_step(const FitDesc *fits, const int *slots, int nslots, int max_p, hipStream_t s);
+
+}  // namespace serve
+}  // namespace coxmi

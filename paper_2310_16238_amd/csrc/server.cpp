@@ -1,0 +1,855 @@
+// server.cpp -- the fit server: continuous batching of independent Cox fits
+// (C ABI in include/coxmi.h, kernels in serve.hip).
+//
+// Threads:
+//   caller      cox_server_submit: checks the arguments, queues the request
+//               (copying the inputs unless they are borrowed) and returns a ticket
+//   prep pool   puts each request in canonical order (Sec. 2.7) and writes its
+//               device image (X column-major, row words, group indices) into a
+//               pinned staging area
+//   worker      owns the GPU: admits staged requests into free slots of the
+//               device arena while the previous iteration runs (uploads on a
+//               copy stream), runs one batched Newton iteration of every
+//               resident fit, reads the fits' states back, retires finished fits
+//
+// Admission is first come, first served, by device footprint: a request is
+// admitted when a slot is free and its block fits in the arena; the fits
+// behind it wait.  Fits that finish free their block for the next ones.
+#include "coxmi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "canonical.h"
+#include "internal.h"
+#include "serve.h"
+
+using namespace coxmi;
+using namespace coxmi::serve;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// First-fit allocator over [0, capacity).
+class RangeAlloc {
+public:
+    void reset(size_t cap)
+    {
+        free_.clear();
+        if (cap) free_[0] = cap;
+        cap_ = cap;
+        used_ = peak_ = 0;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = round_up(bytes, kAlign);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, next = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[next] = rest;
+            used_ += bytes;
+            peak_ = std::max(peak_, used_);
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = round_up(bytes, kAlign);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t capacity() const { return cap_; }
+    size_t peak() const { return peak_; }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t cap_ = 0, used_ = 0, peak_ = 0;
+};
+
+// Where each piece of one fit lives inside its arena block (byte offsets).
+struct FitLayout {
+    int64_t n = 0, ld = 0, ldz = 0;
+    int p = 0, G = 0, nxr = 0, nzr = 0, npairs = 0, ntile = 0;
+    size_t x = 0, meta = 0, gidx = 0, upload = 0;   // [x | meta | gidx] is uploaded in one copy
+    size_t xf = 0, rows = 0, z = 0, beta = 0, prev = 0, zero_end = 0;
+    size_t vec = 0, free_col = 0, L = 0, part = 0, tilemax = 0, total = 0;
+};
+
+FitLayout plan(int64_t n, int p, int64_t G)
+{
+    FitLayout L;
+    L.n = n;
+    L.p = p;
+    L.G = (int)G;
+    L.ld = (int64_t)round_up((size_t)n, kRowPad);
+    L.ldz = (int64_t)round_up((size_t)std::max<int64_t>(G, 1), kRowPad);
+    const int nt = (p + kTile - 1) / kTile;
+    L.npairs = nt * (nt + 1) / 2;
+    L.nxr = (int)((L.ld + kXRange - 1) / kXRange);
+    L.nzr = G > 0 ? (int)((L.ldz + kZRange - 1) / kZRange) : 0;
+    L.ntile = (int)((L.ld + kEtaRows - 1) / kEtaRows);
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+        const size_t at = o;
+        o = round_up(o + bytes, kAlign);
+        return at;
+    };
+    L.x = take(sizeof(double) * (size_t)p * L.ld);
+    L.meta = take(sizeof(uint32_t) * (size_t)L.ld);
+    L.gidx = take(sizeof(int32_t) * (size_t)L.ld);
+    L.upload = o;
+    L.xf = take(sizeof(float) * (size_t)p * L.ld);
+    L.rows = take(sizeof(double) * 6 * (size_t)L.ld);
+    L.z = take(sizeof(float) * (size_t)p * L.ldz);   // zeroed at admission, with beta and prev
+    L.beta = take(sizeof(double) * p);
+    L.prev = take(sizeof(double) * p);
+    L.zero_end = o;
+    L.vec = take(sizeof(double) * 3 * p);
+    L.free_col = take((size_t)p);
+    L.L = take(sizeof(double) * (size_t)p * p);
+    L.part = take(sizeof(float) * (size_t)(L.nxr + L.nzr) * L.npairs * kTile * kTile);
+    L.tilemax = take(sizeof(double) * L.ntile);
+    L.total = o;
+    return L;
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    int64_t n = 0, p = 0, ldx = 0;
+    const double *x = nullptr, *time = nullptr;
+    const uint8_t *event = nullptr;
+    const int32_t *stratum = nullptr;
+    std::vector<double> own_x, own_t;
+    std::vector<uint8_t> own_e;
+    std::vector<int32_t> own_s;
+    double t_submit = 0.0;
+    FitLayout lay;
+    size_t stage_off = 0;
+};
+
+struct Result {
+    std::vector<double> beta;
+    cox_fit_info info{};
+    cox_request_times times{};
+};
+
+struct Slot {
+    bool used = false, active = false, frozen = false;
+    std::unique_ptr<Request> req;
+    size_t arena_off = 0;
+    double t_admit = 0.0;
+};
+
+}  // namespace
+
+struct cox_server {
+    cox_server_options opt{};
+    int device = 0;
+    hipStream_t compute = nullptr, copy = nullptr;
+    hipEvent_t iter_ev = nullptr;
+    std::chrono::steady_clock::time_point t0;
+
+    char *arena = nullptr;
+    RangeAlloc arena_alloc;
+    FitDesc *d_desc = nullptr;
+    FitState *d_state = nullptr;
+    char *staging = nullptr;
+    RangeAlloc stage_alloc;
+    FitDesc *h_desc = nullptr;
+    FitState *h_state = nullptr;
+    double *h_beta = nullptr;
+
+    // work lists: pinned host copies and device arrays (capacity in bytes)
+    struct List {
+        char *h = nullptr, *d = nullptr;
+        size_t cap = 0;
+    } l_admit, l_eta, l_slots, l_cols, l_syrk;
+
+    std::vector<Slot> slots;
+
+    std::mutex mu;
+    std::condition_variable cv_prep, cv_ready, cv_done, cv_stage;
+    std::deque<std::unique_ptr<Request>> prep_q, ready_q;
+    std::unordered_map<uint64_t, Result> results;
+    std::unordered_map<uint64_t, char> pending;   // submitted, not finished
+    uint64_t next_ticket = 1;
+    int64_t outstanding = 0;
+    bool stop = false;
+    int fatal = 0;
+    std::string err, fatal_msg;
+
+    // statistics (worker thread; read under mu)
+    int64_t submitted = 0, completed = 0, iterations = 0, resident_peak = 0;
+    double resident_sum = 0.0, gpu_busy_s = 0.0;
+
+    std::vector<std::thread> preps;
+    std::thread worker;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+int srv_fail(cox_server *s, int code, const std::string &msg)
+{
+    if (s) {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->err = msg;
+    }
+    return code;
+}
+
+thread_local std::string g_create_error;
+
+void finish_locked(cox_server *s, uint64_t ticket, Result &&r)
+{
+    s->pending.erase(ticket);
+    s->results[ticket] = std::move(r);
+    s->outstanding -= 1;
+    s->completed += 1;
+    s->cv_done.notify_all();
+}
+
+void fail_request_locked(cox_server *s, const Request &q, int code, double t)
+{
+    Result r;
+    r.info.status = code;
+    r.times.submit_s = q.t_submit;
+    r.times.admit_s = t;
+    r.times.done_s = t;
+    finish_locked(s, q.ticket, std::move(r));
+}
+
+// ------------------------------------------------------------------ prep pool
+
+void write_image(const Request &q, const std::vector<int64_t> &perm, const std::vector<uint32_t> &meta, char *dst)
+{
+    const FitLayout &L = q.lay;
+    double *x = reinterpret_cast<double *>(dst + L.x);
+    uint32_t *mw = reinterpret_cast<uint32_t *>(dst + L.meta);
+    int32_t *gi = reinterpret_cast<int32_t *>(dst + L.gidx);
+    for (int64_t j = 0; j < q.p; ++j) {
+        double *col = x + j * L.ld;
+        const double *src = q.x + j * q.ldx;
+        for (int64_t i = 0; i < q.n; ++i) col[i] = src[perm[i]];
+        for (int64_t i = q.n; i < L.ld; ++i) col[i] = 0.0;
+    }
+    int32_t g = 0;
+    for (int64_t i = 0; i < q.n; ++i) {
+        mw[i] = meta[i];
+        gi[i] = (meta[i] & kCountMask) ? g++ : -1;
+    }
+    for (int64_t i = q.n; i < L.ld; ++i) {
+        mw[i] = kHeadBit | kPadBit;
+        gi[i] = -1;
+    }
+}
+
+void prep_loop(cox_server *s)
+{
+    std::vector<int64_t> perm;
+    std::vector<uint32_t> meta;
+    for (;;) {
+        std::unique_ptr<Request> q;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_prep.wait(lk, [s] { return s->stop || !s->prep_q.empty(); });
+            if (s->stop) return;
+            q = std::move(s->prep_q.front());
+            s->prep_q.pop_front();
+        }
+        canonical_order(q->n, q->time, q->event, q->stratum, perm, meta);
+        int64_t G = 0;
+        for (int64_t i = 0; i < q->n; ++i) G += (meta[i] & kCountMask) ? 1 : 0;
+        q->lay = plan(q->n, (int)q->p, G);
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (q->lay.total > s->arena_alloc.capacity() || q->lay.upload > s->stage_alloc.capacity()) {
+                fail_request_locked(s, *q, COX_EUNSUPPORTED, s->now());
+                continue;
+            }
+            s->cv_stage.wait(lk, [s, &q] { return s->stop || s->stage_alloc.alloc(q->lay.upload, &q->stage_off); });
+            if (s->stop) return;
+        }
+        write_image(*q, perm, meta, s->staging + q->stage_off);
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->ready_q.push_back(std::move(q));
+        }
+        s->cv_ready.notify_all();
+    }
+}
+
+// ------------------------------------------------------------------ worker
+
+bool ensure_list(cox_server::List &l, size_t bytes, std::string &err)
+{
+    if (bytes <= l.cap) return true;
+    size_t cap = std::max<size_t>(bytes, 2 * l.cap);
+    cap = round_up(cap, 4096);
+    if (l.h) (void)hipHostFree(l.h);
+    if (l.d) (void)hipFree(l.d);
+    l.h = l.d = nullptr;
+    l.cap = 0;
+    if (hipHostMalloc(reinterpret_cast<void **>(&l.h), cap, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&l.d), cap) != hipSuccess) {
+        err = "allocating a work list";
+        return false;
+    }
+    l.cap = cap;
+    return true;
+}
+
+FitDesc make_desc(cox_server *s, const Request &q, size_t off)
+{
+    const FitLayout &L = q.lay;
+    char *B = s->arena + off;
+    FitDesc F{};
+    F.x = reinterpret_cast<const double *>(B + L.x);
+    F.xf = reinterpret_cast<float *>(B + L.xf);
+    F.meta = reinterpret_cast<const uint32_t *>(B + L.meta);
+    F.gidx = reinterpret_cast<const int32_t *>(B + L.gidx);
+    double *rows = reinterpret_cast<double *>(B + L.rows);
+    F.eta = rows;
+    F.w = rows + L.ld;
+    F.s0 = rows + 2 * L.ld;
+    F.hz = rows + 3 * L.ld;
+    F.a = rows + 4 * L.ld;
+    F.b = rows + 5 * L.ld;
+    F.z = reinterpret_cast<float *>(B + L.z);
+    F.beta = reinterpret_cast<double *>(B + L.beta);
+    F.prev = reinterpret_cast<double *>(B + L.prev);
+    double *vec = reinterpret_cast<double *>(B + L.vec);
+    F.grad = vec;
+    F.diag1 = vec + L.p;
+    F.diag2 = vec + 2 * L.p;
+    F.free_col = reinterpret_cast<uint8_t *>(B + L.free_col);
+    F.L = reinterpret_cast<double *>(B + L.L);
+    F.part = reinterpret_cast<float *>(B + L.part);
+    F.tilemax = reinterpret_cast<double *>(B + L.tilemax);
+    F.n = L.n;
+    F.ld = L.ld;
+    F.ldz = L.ldz;
+    F.p = L.p;
+    F.G = L.G;
+    F.nxr = L.nxr;
+    F.nzr = L.nzr;
+    F.npairs = L.npairs;
+    F.ntile = L.ntile;
+    F.tol = s->opt.tol;
+    F.max_iter = s->opt.max_iter;
+    F.freeze = 1;
+    return F;
+}
+
+// Everything the worker does per round; returns false on a device error (message in `err`).
+struct WorkerState {
+    std::vector<int> uploading;   // slots whose upload was queued in the previous round
+    std::vector<int> upload_stage_release;
+    hipEvent_t copy_ev = nullptr;
+    bool copy_pending = false;
+};
+
+#define WCHECK(expr, what)                      \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) {                 \
+            err = std::string(what) + ": " + hipGetErrorString(e_); \
+            return false;                       \
+        }                                       \
+    } while (0)
+
+bool admit_ready(cox_server *s, WorkerState &ws, std::string &err)
+{
+    // take staged requests in order while a slot is free and the arena has room
+    std::vector<std::pair<int, std::unique_ptr<Request>>> taken;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        while (!s->ready_q.empty()) {
+            Request &q = *s->ready_q.front();
+            int slot = -1;
+            for (int i = 0; i < (int)s->slots.size(); ++i)
+                if (!s->slots[i].used) {
+                    slot = i;
+                    break;
+                }
+            size_t off = 0;
+            if (slot < 0 || !s->arena_alloc.alloc(q.lay.total, &off)) break;
+            Slot &S = s->slots[slot];
+            S.used = true;
+            S.active = false;
+            S.frozen = false;
+            S.arena_off = off;
+            S.t_admit = s->now();
+            taken.emplace_back(slot, std::move(s->ready_q.front()));
+            s->ready_q.pop_front();
+        }
+    }
+    if (taken.empty()) return true;
+    for (auto &tk : taken) {
+        const int slot = tk.first;
+        Request &q = *tk.second;
+        Slot &S = s->slots[slot];
+        char *B = s->arena + S.arena_off;
+        s->h_desc[slot] = make_desc(s, q, S.arena_off);
+        WCHECK(hipMemcpyAsync(B, s->staging + q.stage_off, q.lay.upload, hipMemcpyHostToDevice, s->copy),
+               "uploading a fit");
+        WCHECK(hipMemsetAsync(B + q.lay.z, 0, q.lay.zero_end - q.lay.z, s->copy), "clearing a fit");
+        WCHECK(hipMemcpyAsync(s->d_desc + slot, s->h_desc + slot, sizeof(FitDesc), hipMemcpyHostToDevice, s->copy),
+               "uploading a descriptor");
+        WCHECK(hipMemsetAsync(s->d_state + slot, 0, sizeof(FitState), s->copy), "clearing a fit state");
+        S.req = std::move(tk.second);
+        ws.uploading.push_back(slot);
+    }
+    WCHECK(hipEventRecord(ws.copy_ev, s->copy), "recording the upload");
+    ws.copy_pending = true;
+    return true;
+}
+
+bool run_round(cox_server *s, WorkerState &ws, std::string &err)
+{
+    // 1. fits uploaded in the previous round join: FP32 copy of X
+    std::vector<int> joining;
+    if (ws.copy_pending) {
+        WCHECK(hipStreamWaitEvent(s->compute, ws.copy_ev, 0), "ordering the upload");
+        joining.swap(ws.uploading);
+        ws.copy_pending = false;
+        size_t nitems = 0;
+        for (int sl : joining) nitems += (size_t)s->slots[sl].req->lay.ntile;
+        if (!ensure_list(s->l_admit, sizeof(int2) * std::max<size_t>(nitems, 1), err)) return false;
+        int2 *it = reinterpret_cast<int2 *>(s->l_admit.h);
+        size_t k = 0;
+        for (int sl : joining)
+            for (int t = 0; t < s->slots[sl].req->lay.ntile; ++t) it[k++] = make_int2(sl, t);
+        WCHECK(hipMemcpyAsync(s->l_admit.d, s->l_admit.h, sizeof(int2) * k, hipMemcpyHostToDevice, s->compute),
+               "admit list");
+        WCHECK((hipError_t)launch_admit(s->d_desc, reinterpret_cast<const int2 *>(s->l_admit.d), (int)k, s->compute),
+               "admit kernel");
+        for (int sl : joining) s->slots[sl].active = true;
+    }
+    // 2. one Newton iteration of every active fit
+    std::vector<int> act;
+    for (int i = 0; i < (int)s->slots.size(); ++i)
+        if (s->slots[i].used && s->slots[i].active) act.push_back(i);
+    const bool launched = !act.empty();
+    double t_launch = s->now();
+    if (launched) {
+        size_t n_eta = 0, n_cols = 0, n_syrk = 0;
+        for (int sl : act) {
+            const FitLayout &L = s->slots[sl].req->lay;
+            n_eta += L.ntile;
+            n_cols += L.p;
+            if (!s->slots[sl].frozen) n_syrk += (size_t)L.npairs * (L.nxr + L.nzr);
+        }
+        if (!ensure_list(s->l_eta, sizeof(int2) * n_eta, err) || !ensure_list(s->l_cols, sizeof(int2) * n_cols, err) ||
+            !ensure_list(s->l_syrk, sizeof(int4) * std::max<size_t>(n_syrk, 1), err) ||
+            !ensure_list(s->l_slots, sizeof(int) * act.size(), err))
+            return false;
+        int2 *eta = reinterpret_cast<int2 *>(s->l_eta.h);
+        int2 *cols = reinterpret_cast<int2 *>(s->l_cols.h);
+        int4 *syrk = reinterpret_cast<int4 *>(s->l_syrk.h);
+        int *sl_list = reinterpret_cast<int *>(s->l_slots.h);
+        size_t ke = 0, kc = 0, ks = 0;
+        for (size_t a = 0; a < act.size(); ++a) {
+            const int sl = act[a];
+            const FitLayout &L = s->slots[sl].req->lay;
+            sl_list[a] = sl;
+            for (int t = 0; t < L.ntile; ++t) eta[ke++] = make_int2(sl, t);
+            for (int j = 0; j < L.p; ++j) cols[kc++] = make_int2(sl, j);
+            if (!s->slots[sl].frozen)
+                for (int pr = 0; pr < L.npairs; ++pr) {
+                    for (int r = 0; r < L.nxr; ++r) syrk[ks++] = make_int4(sl, pr, r, 0);
+                    for (int r = 0; r < L.nzr; ++r) syrk[ks++] = make_int4(sl, pr, r, 1);
+                }
+        }
+        int max_p = 1;
+        for (int sl : act) max_p = std::max(max_p, s->slots[sl].req->lay.p);
+        WCHECK(hipMemcpyAsync(s->l_eta.d, s->l_eta.h, sizeof(int2) * ke, hipMemcpyHostToDevice, s->compute), "lists");
+        WCHECK(hipMemcpyAsync(s->l_cols.d, s->l_cols.h, sizeof(int2) * kc, hipMemcpyHostToDevice, s->compute), "lists");
+        if (ks)
+            WCHECK(hipMemcpyAsync(s->l_syrk.d, s->l_syrk.h, sizeof(int4) * ks, hipMemcpyHostToDevice, s->compute),
+                   "lists");
+        WCHECK(hipMemcpyAsync(s->l_slots.d, s->l_slots.h, sizeof(int) * act.size(), hipMemcpyHostToDevice, s->compute),
+               "lists");
+        const int *dsl = reinterpret_cast<const int *>(s->l_slots.d);
+        WCHECK((hipError_t)launch_eta(s->d_desc, reinterpret_cast<const int2 *>(s->l_eta.d), (int)ke, s->compute), "eta");
+        WCHECK((hipError_t)launch_rows(s->d_desc, dsl, (int)act.size(), s->compute), "rows");
+        WCHECK((hipError_t)launch_cols(s->d_desc, reinterpret_cast<const int2 *>(s->l_cols.d), (int)kc, s->compute),
+               "cols");
+        if (ks)
+            WCHECK((hipError_t)launch_syrk(s->d_desc, reinterpret_cast<const int4 *>(s->l_syrk.d), (int)ks, s->compute),
+                   "syrk");
+        WCHECK((hipError_t)launch_step(s->d_desc, dsl, (int)act.size(), max_p, s->compute), "step");
+        const int hi = act.back() + 1;   // act is in slot order
+        WCHECK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(FitState) * hi, hipMemcpyDeviceToHost, s->compute),
+               "reading fit states");
+        WCHECK(hipEventRecord(s->iter_ev, s->compute), "recording the iteration");
+    }
+    // 3. while the GPU iterates: admit what the prep pool has staged (uploads on the copy stream)
+    if (!admit_ready(s, ws, err)) return false;
+    if (!launched) {
+        // nothing resident: the staging of this round's uploads is released next round
+        return true;
+    }
+    WCHECK(hipEventSynchronize(s->iter_ev), "iteration");
+    const double t_done = s->now();
+    // staging of the fits that joined this round has been copied (the compute stream waited on it)
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (int sl : joining) s->stage_alloc.release(s->slots[sl].req->stage_off, s->slots[sl].req->lay.upload);
+    }
+    if (!joining.empty()) s->cv_stage.notify_all();
+    // 4. retire finished fits
+    std::vector<int> done;
+    for (int sl : act) {
+        const FitState &st = s->h_state[sl];
+        if (st.flags & kDone) done.push_back(sl);
+        else s->slots[sl].frozen = (st.flags & kFrozen) != 0;
+    }
+    for (int sl : done) {
+        const FitDesc &F = s->h_desc[sl];
+        WCHECK(hipMemcpyAsync(s->h_beta + (size_t)sl * kMaxP, F.beta, sizeof(double) * F.p, hipMemcpyDeviceToHost,
+                              s->compute),
+               "reading an estimate");
+    }
+    if (!done.empty()) WCHECK(hipStreamSynchronize(s->compute), "reading estimates");
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->iterations += 1;
+        s->resident_sum += (double)act.size();
+        s->resident_peak = std::max<int64_t>(s->resident_peak, (int64_t)act.size());
+        s->gpu_busy_s += t_done - t_launch;
+        for (int sl : done) {
+            Slot &S = s->slots[sl];
+            const FitState &st = s->h_state[sl];
+            Result r;
+            r.beta.assign(s->h_beta + (size_t)sl * kMaxP, s->h_beta + (size_t)sl * kMaxP + S.req->p);
+            r.info.status = st.status;
+            r.info.iters = st.iters;
+            r.info.coord_evals = st.evals;
+            r.info.objective = st.obj;
+            r.info.kkt_inf = st.kkt;
+            r.info.last_step = st.last_step;
+            r.info.n_pinned = st.n_pinned;
+            r.times.submit_s = S.req->t_submit;
+            r.times.admit_s = S.t_admit;
+            r.times.done_s = t_done;
+            s->arena_alloc.release(S.arena_off, S.req->lay.total);
+            finish_locked(s, S.req->ticket, std::move(r));
+            S = Slot();
+        }
+    }
+    return true;
+}
+
+void worker_loop(cox_server *s)
+{
+    (void)hipSetDevice(s->device);
+    WorkerState ws;
+    std::string err;
+    if (hipEventCreateWithFlags(&ws.copy_ev, hipEventDisableTiming) != hipSuccess) {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->fatal = COX_EDEVICE;
+        s->fatal_msg = "creating an event";
+    }
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (s->fatal) break;
+            bool any_resident = false;
+            for (const Slot &S : s->slots) any_resident |= S.used;
+            if (!any_resident) {
+                s->cv_ready.wait(lk, [s] { return s->stop || !s->ready_q.empty(); });
+                if (s->stop) break;
+            } else if (s->stop) {
+                break;
+            }
+        }
+        if (!run_round(s, ws, err)) {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->fatal = COX_EDEVICE;
+            s->fatal_msg = err;
+            break;
+        }
+    }
+    (void)hipStreamSynchronize(s->copy);
+    (void)hipStreamSynchronize(s->compute);
+    if (ws.copy_ev) (void)hipEventDestroy(ws.copy_ev);
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->fatal) {
+        // fail everything still outstanding
+        const double t = s->now();
+        for (Slot &S : s->slots)
+            if (S.used && S.req) {
+                fail_request_locked(s, *S.req, s->fatal, t);
+                S = Slot();
+            }
+        for (auto &q : s->ready_q) fail_request_locked(s, *q, s->fatal, t);
+        s->ready_q.clear();
+        for (auto &q : s->prep_q) fail_request_locked(s, *q, s->fatal, t);
+        s->prep_q.clear();
+        s->stop = true;
+        s->cv_prep.notify_all();
+        s->cv_stage.notify_all();
+    }
+    s->cv_done.notify_all();
+}
+
+void free_server(cox_server *s)
+{
+    if (s->arena) (void)hipFree(s->arena);
+    if (s->d_desc) (void)hipFree(s->d_desc);
+    if (s->d_state) (void)hipFree(s->d_state);
+    if (s->staging) (void)hipHostFree(s->staging);
+    if (s->h_desc) (void)hipHostFree(s->h_desc);
+    if (s->h_state) (void)hipHostFree(s->h_state);
+    if (s->h_beta) (void)hipHostFree(s->h_beta);
+    for (cox_server::List *l : {&s->l_admit, &s->l_eta, &s->l_slots, &s->l_cols, &s->l_syrk}) {
+        if (l->h) (void)hipHostFree(l->h);
+        if (l->d) (void)hipFree(l->d);
+    }
+    if (s->iter_ev) (void)hipEventDestroy(s->iter_ev);
+    if (s->compute) (void)hipStreamDestroy(s->compute);
+    if (s->copy) (void)hipStreamDestroy(s->copy);
+}
+
+}  // namespace
+
+extern "C" void cox_server_default_options(cox_server_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->hbm_budget = (size_t)8 << 30;
+    o->staging_bytes = (size_t)1 << 30;
+    o->max_resident = 1024;
+    o->prep_threads = 8;
+    o->x_precision = COX_F32;
+    o->tol = 1e-12;
+    o->max_iter = 100;
+    o->device = -1;
+}
+
+extern "C" int cox_server_create(cox_server **out, const cox_server_options *o)
+{
+    if (!out) return COX_EINVAL;
+    *out = nullptr;
+    cox_server_options opt;
+    if (o) opt = *o;
+    else cox_server_default_options(&opt);
+    if (opt.x_precision != COX_F32) {
+        g_create_error = "the server forms the information matrix in FP32 (x_precision = COX_F32)";
+        return COX_EUNSUPPORTED;
+    }
+    if (opt.hbm_budget < ((size_t)1 << 20) || opt.staging_bytes < ((size_t)1 << 20) || opt.max_resident < 1 ||
+        opt.prep_threads < 1 || !(opt.tol >= 0.0) || opt.max_iter < 1) {
+        g_create_error = "invalid server options";
+        return COX_EINVAL;
+    }
+    std::unique_ptr<cox_server> s(new cox_server());
+    s->opt = opt;
+    s->t0 = std::chrono::steady_clock::now();
+    if (opt.device >= 0) {
+        if (hipSetDevice(opt.device) != hipSuccess) {
+            g_create_error = "hipSetDevice failed";
+            return COX_EDEVICE;
+        }
+    }
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        g_create_error = "no HIP device";
+        return COX_EDEVICE;
+    }
+    const size_t ns = (size_t)opt.max_resident;
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->iter_ev, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&s->arena), opt.hbm_budget)) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&s->d_desc), sizeof(FitDesc) * ns)) != hipSuccess ||
+        (e = hipMalloc(reinterpret_cast<void **>(&s->d_state), sizeof(FitState) * ns)) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void **>(&s->staging), opt.staging_bytes, hipHostMallocDefault)) !=
+            hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_desc), sizeof(FitDesc) * ns, hipHostMallocDefault)) !=
+            hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_state), sizeof(FitState) * ns, hipHostMallocDefault)) !=
+            hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_beta), sizeof(double) * kMaxP * ns, hipHostMallocDefault)) !=
+            hipSuccess) {
+        g_create_error = std::string("server allocation: ") + hipGetErrorString(e);
+        free_server(s.get());
+        return e == hipErrorOutOfMemory ? COX_ENOMEM : COX_EDEVICE;
+    }
+    s->arena_alloc.reset(opt.hbm_budget);
+    s->stage_alloc.reset(opt.staging_bytes);
+    s->slots.resize(ns);
+    cox_server *raw = s.release();
+    for (int i = 0; i < opt.prep_threads; ++i) raw->preps.emplace_back(prep_loop, raw);
+    raw->worker = std::thread(worker_loop, raw);
+    *out = raw;
+    return COX_OK;
+}
+
+extern "C" int cox_server_submit(cox_server *s, const cox_data *d, int flags, uint64_t *ticket)
+{
+    if (!s) return COX_EINVAL;
+    if (!d || !ticket) return srv_fail(s, COX_EINVAL, "data and ticket are required");
+    if (flags & ~COX_SUBMIT_BORROW) return srv_fail(s, COX_EINVAL, "unknown submit flags");
+    if (const char *bad = check_data(d->n, d->p, d->ldx, d->x, d->time, d->event)) return srv_fail(s, COX_EINVAL, bad);
+    if (d->p > kMaxP) return srv_fail(s, COX_EUNSUPPORTED, "the server fits at most 128 columns");
+    std::unique_ptr<Request> q(new Request());
+    q->n = d->n;
+    q->p = d->p;
+    if (flags & COX_SUBMIT_BORROW) {
+        q->x = d->x;
+        q->ldx = d->ldx;
+        q->time = d->time;
+        q->event = d->event;
+        q->stratum = d->stratum;
+    } else {
+        q->own_x.resize((size_t)d->n * d->p);
+        for (int64_t j = 0; j < d->p; ++j)
+            std::memcpy(q->own_x.data() + j * d->n, d->x + j * d->ldx, sizeof(double) * d->n);
+        q->own_t.assign(d->time, d->time + d->n);
+        q->own_e.assign(d->event, d->event + d->n);
+        if (d->stratum) q->own_s.assign(d->stratum, d->stratum + d->n);
+        q->x = q->own_x.data();
+        q->ldx = d->n;
+        q->time = q->own_t.data();
+        q->event = q->own_e.data();
+        q->stratum = d->stratum ? q->own_s.data() : nullptr;
+    }
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->fatal) {
+            s->err = s->fatal_msg;
+            return s->fatal;
+        }
+        if (s->stop) return COX_EINVAL;
+        q->ticket = s->next_ticket++;
+        q->t_submit = s->now();
+        *ticket = q->ticket;
+        s->pending[q->ticket] = 1;
+        s->outstanding += 1;
+        s->submitted += 1;
+        s->prep_q.push_back(std::move(q));
+    }
+    s->cv_prep.notify_one();
+    return COX_OK;
+}
+
+extern "C" int cox_server_poll(cox_server *s, uint64_t ticket, double *beta_out, cox_fit_info *info,
+                               cox_request_times *times)
+{
+    if (!s) return COX_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) {
+        if (s->pending.count(ticket)) return 1;
+        s->err = "unknown or already collected ticket";
+        return COX_EINVAL;
+    }
+    if (beta_out) std::memcpy(beta_out, it->second.beta.data(), sizeof(double) * it->second.beta.size());
+    if (info) *info = it->second.info;
+    if (times) *times = it->second.times;
+    s->results.erase(it);
+    return COX_OK;
+}
+
+extern "C" int cox_server_wait(cox_server *s, uint64_t ticket, double timeout_s)
+{
+    if (!s) return COX_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (!s->results.count(ticket) && !s->pending.count(ticket)) return COX_EINVAL;
+    auto ready = [s, ticket] { return s->results.count(ticket) > 0 || s->fatal != 0; };
+    if (timeout_s < 0) s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) return 1;
+    return s->results.count(ticket) ? COX_OK : s->fatal;
+}
+
+extern "C" int cox_server_drain(cox_server *s, double timeout_s)
+{
+    if (!s) return COX_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto ready = [s] { return s->outstanding == 0 || s->fatal != 0; };
+    if (timeout_s < 0) s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) return 1;
+    return s->outstanding == 0 ? COX_OK : s->fatal;
+}
+
+extern "C" int cox_server_stats(cox_server *s, cox_server_counters *st)
+{
+    if (!s || !st) return COX_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    st->submitted = s->submitted;
+    st->completed = s->completed;
+    st->iterations = s->iterations;
+    int64_t resident = 0;
+    for (const Slot &S : s->slots) resident += S.used ? 1 : 0;
+    st->resident_now = resident;
+    st->resident_peak = s->resident_peak;
+    st->mean_resident = s->iterations ? s->resident_sum / (double)s->iterations : 0.0;
+    st->arena_bytes = s->arena_alloc.capacity();
+    st->arena_peak = s->arena_alloc.peak();
+    st->gpu_busy_s = s->gpu_busy_s;
+    st->now_s = s->now();
+    return COX_OK;
+}
+
+extern "C" const char *cox_server_last_error(cox_server *s)
+{
+    if (!s) return g_create_error.c_str();
+    static thread_local std::string copy;
+    std::lock_guard<std::mutex> g(s->mu);
+    copy = s->err;
+    return copy.c_str();
+}
+
+extern "C" void cox_server_destroy(cox_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv_prep.notify_all();
+    s->cv_ready.notify_all();
+    s->cv_stage.notify_all();
+    for (auto &t : s->preps) t.join();
+    if (s->worker.joinable()) s->worker.join();
+    free_server(s);
+    delete s;
+}

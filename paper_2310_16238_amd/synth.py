@@ -209,3 +209,23 @@ def config_mixed(n: int = 1_000_000, p: int = 200, K: int = 50_000, seed: int = 
     """The AR(1) design at P = 200 for the reduced-precision Newton fit (seed 2)."""
     return make("ar1", n, p, K, seed, beta_kind="normal", beta_sd=0.5, gamma=0.0,
                 name=f"mixed-n{n}-p{p}-K{K}")
+
+
+def serving_request(i: int, seed: int = 3, n_range=(1_000, 100_000), p_range=(5, 100)) -> CoxData:
+    """Request i of the serving stream: n log-uniform in n_range, p uniform in p_range,
+    a ones column plus p-1 iid N(0,1) columns, beta_true iid N(0, 0.25) (sd 0.5),
+    K = max(1, round(n / 100)) strata; drawn from default_rng((seed, i))."""
+    rng = np.random.default_rng((seed, i))
+    lo, hi = math.log(n_range[0]), math.log(n_range[1])
+    n = int(round(math.exp(rng.uniform(lo, hi))))
+    p = int(rng.integers(p_range[0], p_range[1] + 1))
+    K = max(1, int(round(n / 100)))
+    sub = int(rng.integers(0, 2**31 - 1))
+    return make("iid", n, p, K, sub, beta_kind="normal", beta_sd=0.5, intercept=True, gamma=0.0,
+                name=f"serve-{seed}-{i}-n{n}-p{p}")
+
+
+def arrival_times(count: int, rate: float, seed: int = 3) -> np.ndarray:
+    """Poisson arrivals at `rate` per second: cumulative sums of Exp(rate) gaps (seconds)."""
+    rng = np.random.default_rng((seed, 1 << 20))
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))

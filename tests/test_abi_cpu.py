@@ -92,3 +92,22 @@ def test_null_handle_calls_are_errors():
     assert lib.cox_evaluate(None, b.ctypes.data_as(dp), None, None, None) == coxmi.COX_EINVAL
     assert lib.cox_layout(None, None, None) == coxmi.COX_EINVAL
     lib.cox_release(None)
+
+
+def test_server_rejects_bad_options_before_the_device():
+    lib = coxmi.lib()
+    h = ctypes.c_void_p()
+    for field, value, code in [("x_precision", coxmi.COX_F64, coxmi.COX_EUNSUPPORTED),
+                               ("max_iter", 0, coxmi.COX_EINVAL), ("tol", -1.0, coxmi.COX_EINVAL),
+                               ("prep_threads", 0, coxmi.COX_EINVAL), ("hbm_budget", 1024, coxmi.COX_EINVAL)]:
+        o = coxmi.cox_server_default_options()
+        setattr(o, field, value)
+        assert lib.cox_server_create(ctypes.byref(h), ctypes.byref(o)) == code, field
+        assert h.value is None
+        assert lib.cox_server_last_error(None)
+
+
+def test_server_default_options():
+    o = coxmi.cox_server_default_options()
+    assert o.x_precision == coxmi.COX_F32 and o.tol == 1e-12 and o.max_iter == 100
+    assert o.hbm_budget == 8 << 30 and o.staging_bytes == 1 << 30 and o.device == -1

@@ -1,0 +1,172 @@
+"""GPU tests of the fit server (cox_server_*): every served fit against the oracle,
+the same result alone and in a mix, admission by device footprint, arrivals
+while other fits run, and the error paths.
+
+Tolerance: max|beta_gpu - beta_oracle| / max|beta_oracle| <= 1e-10 with the
+oracle's FP64 Newton fit to 1e-14 (the server's information matrix is FP32,
+its score and objective FP64, refined to tol = 1e-12).  Alone-vs-mix: bit-identical.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import cox_oracle as orc
+from paper_2310_16238_amd import coxmi, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    coxmi.lib()
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(float(np.max(np.abs(b))), 1e-300))
+
+
+def _requests(count, seed=3, n_range=(300, 20_000), p_range=(2, 70)):
+    return [synth.serving_request(i, seed=seed, n_range=n_range, p_range=p_range) for i in range(count)]
+
+
+def _check_against_oracle(d, beta, info):
+    ref = orc.fit_newton(d.X, d.time, d.event, d.stratum, tol=1e-14)
+    assert ref.converged, d.name
+    assert info["status"] == coxmi.COX_OK, (d.name, info)
+    err = _rel(beta, ref.beta)
+    assert err <= 1e-10, (d.name, err)
+    assert beta[0] == 0.0 and info["n_pinned"] >= 1   # the ones column is held at zero
+    return err
+
+
+def test_served_stream_matches_oracle():
+    reqs = _requests(24)
+    _say(f"serving {len(reqs)} fits, n in [{min(d.n for d in reqs)}, {max(d.n for d in reqs)}], "
+         f"p in [{min(d.p for d in reqs)}, {max(d.p for d in reqs)}]")
+    with coxmi.CoxServer(hbm_budget=1 << 30, staging_bytes=256 << 20, prep_threads=4) as srv:
+        tickets = [srv.submit(d.X, d.time, d.event, d.stratum) for d in reqs]
+        assert srv.drain(timeout=100.0)
+        out = [srv.poll(t) for t in tickets]
+        st = srv.stats()
+    _say(f"  stats {st}")
+    worst = 0.0
+    for d, (beta, info, times) in zip(reqs, out):
+        worst = max(worst, _check_against_oracle(d, beta, info))
+        assert times["submit_s"] <= times["admit_s"] <= times["done_s"]
+    _say(f"  worst rel err {worst:.3e}")
+    assert st["completed"] == len(reqs) and st["resident_now"] == 0
+
+
+def test_same_result_alone_and_in_mix():
+    reqs = _requests(12, seed=7)
+    probe = reqs[5]
+    with coxmi.CoxServer(hbm_budget=256 << 20, prep_threads=2) as srv:
+        t = srv.submit(probe.X, probe.time, probe.event, probe.stratum)
+        assert srv.wait(t, timeout=60.0)
+        alone, info_a, _ = srv.poll(t)
+    # the same request among others, with a budget that staggers admission
+    with coxmi.CoxServer(hbm_budget=96 << 20, prep_threads=3) as srv:
+        tickets = [srv.submit(d.X, d.time, d.event, d.stratum) for d in reqs[:5]]
+        tp = srv.submit(probe.X, probe.time, probe.event, probe.stratum)
+        tickets += [srv.submit(d.X, d.time, d.event, d.stratum) for d in reqs[6:]]
+        assert srv.drain(timeout=100.0)
+        mixed, info_m, _ = srv.poll(tp)
+        for tk in tickets:
+            assert srv.poll(tk)[1]["status"] == coxmi.COX_OK
+        st = srv.stats()
+    _say(f"  mix stats {st}")
+    assert st["resident_peak"] > 1
+    assert np.array_equal(alone, mixed)
+    assert info_a["iters"] == info_m["iters"] and info_a["objective"] == info_m["objective"]
+    _check_against_oracle(probe, mixed, info_m)
+
+
+def test_admission_by_footprint_and_oversized_request():
+    reqs = _requests(10, seed=11, n_range=(20_000, 40_000), p_range=(40, 60))
+    with coxmi.CoxServer(hbm_budget=80 << 20, prep_threads=4) as srv:
+        tickets = [srv.submit(d.X, d.time, d.event, d.stratum) for d in reqs]
+        big = synth.make("iid", 120_000, 100, 10, 1, intercept=True)
+        tb = srv.submit(big.X, big.time, big.event, big.stratum)
+        assert srv.drain(timeout=150.0)
+        res = [srv.poll(t) for t in tickets]
+        rb = srv.poll(tb)
+        st = srv.stats()
+    _say(f"  footprint stats {st}")
+    assert rb[1]["status"] == coxmi.COX_EUNSUPPORTED
+    assert st["arena_peak"] <= 80 << 20 and st["resident_peak"] < len(reqs)
+    for d, (beta, info, _) in zip(reqs, res):
+        _check_against_oracle(d, beta, info)
+
+
+def test_arrivals_while_others_run():
+    reqs = _requests(16, seed=13, n_range=(2_000, 60_000), p_range=(10, 90))
+    with coxmi.CoxServer(prep_threads=4) as srv:
+        tickets = []
+        for i, d in enumerate(reqs):
+            tickets.append(srv.submit(d.X, d.time, d.event, d.stratum, borrow=(i % 2 == 0)))
+            time.sleep(0.002)
+        assert srv.drain(timeout=150.0)
+        res = [srv.poll(t) for t in tickets]
+    # at least one request was admitted while an earlier one was still running
+    admits = [r[2]["admit_s"] for r in res]
+    dones = [r[2]["done_s"] for r in res]
+    assert any(admits[j] < max(dones[:j]) for j in range(1, len(res)))
+    for d, (beta, info, _) in zip(reqs, res):
+        _check_against_oracle(d, beta, info)
+
+
+def test_copied_inputs_can_be_reused():
+    d = synth.serving_request(0, seed=17, n_range=(3_000, 3_001), p_range=(12, 12))
+    X = np.asfortranarray(d.X.copy())
+    with coxmi.CoxServer(prep_threads=1) as srv:
+        t = srv.submit(X, d.time, d.event, d.stratum, borrow=False)
+        X[:] = 0.0   # the server copied the inputs
+        assert srv.wait(t, timeout=60.0)
+        beta, info, _ = srv.poll(t)
+    _check_against_oracle(d, beta, info)
+
+
+def test_server_edge_cases():
+    rng = np.random.default_rng(3)
+    with coxmi.CoxServer(prep_threads=2) as srv:
+        # one row; no events; a single column
+        cases = [
+            (np.ones((1, 1)), np.array([1.0]), np.array([1], np.uint8), None),
+            (rng.standard_normal((50, 3)), rng.random(50), np.zeros(50, np.uint8), None),
+            (rng.standard_normal((400, 1)), rng.exponential(1.0, 400), (rng.random(400) < 0.5).astype(np.uint8),
+             (np.arange(400) % 4).astype(np.int32)),
+        ]
+        tickets = [srv.submit(*c) for c in cases]
+        assert srv.drain(timeout=60.0)
+        res = [srv.poll(t) for t in tickets]
+        for (X, t, e, s), (beta, info, _) in zip(cases, res):
+            assert info["status"] == coxmi.COX_OK, info
+            if e.sum() == 0 or X.shape[0] == 1:
+                assert np.all(beta == 0.0)
+            else:
+                ref = orc.fit_newton(X, t, e, s, tol=1e-14)
+                assert _rel(beta, ref.beta) <= 1e-10
+        # errors at submit
+        with pytest.raises(coxmi.CoxError) as ei:
+            srv.submit(rng.standard_normal((10, 129)), rng.random(10), np.ones(10, np.uint8))
+        assert ei.value.code == coxmi.COX_EUNSUPPORTED
+        bad_t = rng.random(10)
+        bad_t[2] = np.nan
+        with pytest.raises(coxmi.CoxError) as ei:
+            srv.submit(rng.standard_normal((10, 2)), bad_t, np.ones(10, np.uint8))
+        assert ei.value.code == coxmi.COX_EINVAL
+        # a collected ticket is unknown afterwards
+        with pytest.raises(coxmi.CoxError) as ei:
+            srv._p[tickets[0]] = 1
+            srv.poll(tickets[0])
+        assert ei.value.code == coxmi.COX_EINVAL
