@@ -99,9 +99,12 @@ void cox_default_options(cox_options *o);
  *   d   : data; all pointers host memory, read only during the call
  *   o   : options (NULL = defaults); penalize is copied
  * Errors: COX_EINVAL (n < 1, p < 1, ldx < n, NULL x/time/event, non-finite
- * time, event not 0/1), COX_EUNSUPPORTED (n or p beyond this build's
- * resident limits; mode COX_NEWTON_REFINE with gamma != 0; an x_precision
- * other than COX_F64 / COX_BF16), COX_ENOMEM, COX_EDEVICE.  On error *out is NULL and the
+ * time, event not 0/1), COX_EUNSUPPORTED (p > 4096; in mode COX_CCD, n
+ * beyond the persistent kernel's register-resident capacity of about
+ * CUs x 512 x 16 rows -- a COX_NEWTON_REFINE handle of that size is created,
+ * and then supports cox_fit and cox_evaluate_full only; mode COX_NEWTON_REFINE
+ * with gamma != 0; an x_precision other than COX_F64 / COX_BF16),
+ * COX_ENOMEM, COX_EDEVICE.  On error *out is NULL and the
  * message is available through cox_last_error(NULL).
  */
 int cox_init(cox_handle **out, const cox_data *d, const cox_options *o);
@@ -178,6 +181,21 @@ int cox_layout(const cox_handle *h, int64_t *perm, uint32_t *meta);
 /* Duration in milliseconds of the last persistent-kernel launch on h, from
  * HIP events recorded on the handle's stream immediately around the launch. */
 int cox_last_kernel_ms(const cox_handle *h, double *ms);
+
+/* Device time of the last cox_fit / cox_evaluate / cox_evaluate_full call on
+ * h, by phase, from HIP events recorded on the handle's stream around each
+ * launch sequence. */
+typedef struct {
+    double kernel_ms;        /* the persistent CCD / evaluation kernel */
+    int evaluations;         /* full evaluations (cox_evaluate_full, COX_NEWTON_REFINE fits) */
+    double evaluation_ms;
+    int contractions;        /* information-matrix contractions */
+    double contraction_ms;
+    int solves;              /* Cholesky factor-and-solve or solve-only launches */
+    double solve_ms;
+} cox_profile;
+
+int cox_last_profile(const cox_handle *h, cox_profile *out);
 
 /* Number of rows and columns of the handle; the device row stride (>= n). */
 int cox_shape(const cox_handle *h, int64_t *n, int64_t *p, int64_t *ld);

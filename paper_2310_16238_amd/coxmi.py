@@ -61,6 +61,15 @@ class cox_fit_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class cox_profile(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double), ("evaluations", ctypes.c_int), ("evaluation_ms", ctypes.c_double),
+                ("contractions", ctypes.c_int), ("contraction_ms", ctypes.c_double), ("solves", ctypes.c_int),
+                ("solve_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class cox_server_options(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("staging_bytes", ctypes.c_size_t),
                 ("max_resident", ctypes.c_int), ("prep_threads", ctypes.c_int),
@@ -101,6 +110,7 @@ SIGNATURES = [
     ("cox_coordinate", ctypes.c_int, [_VP, _DP, ctypes.c_int64, _DP]),
     ("cox_layout", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32)]),
     ("cox_last_kernel_ms", ctypes.c_int, [_VP, _DP]),
+    ("cox_last_profile", ctypes.c_int, [_VP, ctypes.POINTER(cox_profile)]),
     ("cox_shape", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64)]),
     ("cox_segscan_f64", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
@@ -248,6 +258,12 @@ def cox_last_kernel_ms(h) -> float:
     return ms.value
 
 
+def cox_last_profile(h) -> dict:
+    prof = cox_profile()
+    _check(h, lib().cox_last_profile(h, ctypes.byref(prof)))
+    return prof.as_dict()
+
+
 def cox_segscan_f64(a_ptr: int, head_ptr: int, b_ptr: int, n: int, stream=None) -> int:
     """Device-pointer segmented scan; returns the status code (raises on error)."""
     rc = lib().cox_segscan_f64(ctypes.c_void_p(a_ptr), ctypes.c_void_p(head_ptr), ctypes.c_void_p(b_ptr),
@@ -290,6 +306,9 @@ class CoxModel:
 
     def kernel_ms(self):
         return cox_last_kernel_ms(self.h)
+
+    def profile(self):
+        return cox_last_profile(self.h)
 
     def close(self):
         if self.h:

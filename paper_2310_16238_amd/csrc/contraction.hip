@@ -20,12 +20,13 @@
 #include <math.h>
 
 #include "internal.h"
+#include "newton.h"
 
 namespace coxmi {
 
 namespace {
 
-constexpr int kTile = 64, kKc = 32, kSyrkThreads = 256;
+constexpr int kTile = 64, kKc = 32, kSyrkThreads = 256, kWaveC = 64;
 
 __device__ __forceinline__ void tile_pair(int pair, int nt, int &ti, int &tj)
 {
@@ -184,6 +185,151 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(double *A, int p, const
     if (t == 0) status[0] = s_bad;
 }
 
+// Blocked variant for p <= kCholMaxP: 32-column panels factored in LDS, the
+// trailing update in 4 x 4 register blocks, triangular solves by 32-row
+// blocks (one wave solves the diagonal block with lane shuffles).  Same
+// contract as chol_solve_kernel.
+constexpr int kCholNB = 32, kCholThreads = 1024, kCholMaxP = 512;
+
+__global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, int p, const double *g,
+                                                                    const uint8_t *free_col, int factored,
+                                                                    double *dx, int *status)
+{
+    extern __shared__ double lds[];   // panel [p][kCholNB], then y[p]
+    double *P = lds;
+    double *y = lds + (size_t)p * kCholNB;
+    __shared__ double s_piv;
+    __shared__ int s_bad;
+    const int t = threadIdx.x;
+    const int lane = t & (kWaveC - 1), wv = t / kWaveC;
+    if (t == 0) s_bad = 0;
+    if (!factored) {
+        for (int64_t e = t; e < (int64_t)p * p; e += kCholThreads) {
+            const int i = (int)(e / p), j = (int)(e % p);
+            if (!free_col[i] || !free_col[j]) A[e] = (i == j) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < p; k0 += kCholNB) {
+            const int nb = p - k0 < kCholNB ? p - k0 : kCholNB;
+            const int m = p - k0;
+            for (int e = t; e < m * kCholNB; e += kCholThreads) {
+                const int i = e / kCholNB, c = e % kCholNB;
+                P[e] = (c < nb) ? A[(int64_t)(k0 + i) * p + k0 + c] : 0.0;
+            }
+            __syncthreads();
+            for (int c = 0; c < nb; ++c) {
+                if (t == 0) {
+                    double d = P[c * kCholNB + c];
+                    if (!(d > 0.0)) {
+                        s_bad = 1;
+                        d = 1.0;
+                    }
+                    s_piv = sqrt(d);
+                    P[c * kCholNB + c] = s_piv;
+                }
+                __syncthreads();
+                const double piv = s_piv;
+                for (int i = c + 1 + t; i < m; i += kCholThreads) P[i * kCholNB + c] /= piv;
+                __syncthreads();
+                const int w = nb - c - 1;
+                if (w > 0)
+                    for (int e = t; e < (m - c - 1) * w; e += kCholThreads) {
+                        const int i = c + 1 + e / w, cc = c + 1 + e % w;
+                        if (cc <= i) P[i * kCholNB + cc] -= P[i * kCholNB + c] * P[cc * kCholNB + c];
+                    }
+                __syncthreads();
+            }
+            for (int e = t; e < m * kCholNB; e += kCholThreads) {
+                const int i = e / kCholNB, c = e % kCholNB;
+                if (c < nb && c <= i) A[(int64_t)(k0 + i) * p + k0 + c] = P[e];
+            }
+            // trailing update of the lower triangle: A22 -= P2 P2'
+            const int m2 = m - nb;
+            if (m2 > 0) {
+                const int nb4 = (m2 + 3) / 4;
+                const int nblk = nb4 * (nb4 + 1) / 2;
+                for (int bk = t; bk < nblk; bk += kCholThreads) {
+                    // block (bi, bj), bj <= bi, in row-major order of the lower triangle
+                    int bi = (int)((sqrt(8.0 * bk + 1.0) - 1.0) * 0.5);
+                    while ((bi + 1) * (bi + 2) / 2 <= bk) ++bi;
+                    while (bi * (bi + 1) / 2 > bk) --bi;
+                    const int bj = bk - bi * (bi + 1) / 2;
+                    double acc[4][4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+                    for (int c = 0; c < nb; ++c) {
+                        double ai[4], aj[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int ii = nb + 4 * bi + u, jj = nb + 4 * bj + u;
+                            ai[u] = ii < m ? P[ii * kCholNB + c] : 0.0;
+                            aj[u] = jj < m ? P[jj * kCholNB + c] : 0.0;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) acc[u][v] = fma(ai[u], aj[v], acc[u][v]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = k0 + nb + 4 * bi + u, j = k0 + nb + 4 * bj + v;
+                            if (i < p && j <= i) A[(int64_t)i * p + j] -= acc[u][v];
+                        }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // solves: L y = -g, then L' x = y (free columns only)
+    for (int i = t; i < p; i += kCholThreads) y[i] = free_col[i] ? -g[i] : 0.0;
+    __syncthreads();
+    for (int k0 = 0; k0 < p; k0 += kCholNB) {
+        const int nb = p - k0 < kCholNB ? p - k0 : kCholNB;
+        if (wv == 0) {
+            double yi = lane < nb ? y[k0 + lane] : 0.0;
+            for (int c = 0; c < nb; ++c) {
+                if (lane == c) yi /= A[(int64_t)(k0 + c) * p + k0 + c];
+                const double yc = __shfl(yi, c, kWaveC);
+                if (lane > c && lane < nb) yi -= A[(int64_t)(k0 + lane) * p + k0 + c] * yc;
+            }
+            if (lane < nb) y[k0 + lane] = yi;
+        }
+        __syncthreads();
+        for (int i = k0 + nb + t; i < p; i += kCholThreads) {
+            const double *row = A + (int64_t)i * p + k0;
+            double s = 0.0;
+            for (int c = 0; c < nb; ++c) s = fma(row[c], y[k0 + c], s);
+            y[i] -= s;
+        }
+        __syncthreads();
+    }
+    for (int k0 = ((p - 1) / kCholNB) * kCholNB; k0 >= 0; k0 -= kCholNB) {
+        const int nb = p - k0 < kCholNB ? p - k0 : kCholNB;
+        if (wv == 0) {
+            double xi = lane < nb ? y[k0 + lane] : 0.0;
+            for (int c = nb - 1; c >= 0; --c) {
+                if (lane == c) xi /= A[(int64_t)(k0 + c) * p + k0 + c];
+                const double xc = __shfl(xi, c, kWaveC);
+                if (lane < c) xi -= A[(int64_t)(k0 + c) * p + k0 + lane] * xc;
+            }
+            if (lane < nb) y[k0 + lane] = xi;
+        }
+        __syncthreads();
+        for (int i = t; i < k0; i += kCholThreads) {
+            double s = 0.0;
+            for (int c = 0; c < nb; ++c) s = fma(A[(int64_t)(k0 + c) * p + i], y[k0 + c], s);
+            y[i] -= s;
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < p; i += kCholThreads) dx[i] = free_col[i] ? y[i] : 0.0;
+    if (t == 0) status[0] = s_bad;
+}
+
 // ------------------------------------------------------------------ BF16 on the matrix cores
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -270,6 +416,85 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_kernel(const uint
     }
 }
 
+// LDS-staged variant for p <= 256 (at most 8 row tiles): per 64-row K chunk
+// the workgroup stages all row tiles of u once (and once more multiplied by
+// the weights, rounded to BF16), then every wave runs its tile pairs' MFMAs
+// from LDS.  Same partial layout as syrk_bf16_kernel.
+constexpr int kLdsKC = 64, kLdsStride = 72, kLdsMaxTiles = 8;
+
+template <bool WEIGHT>
+__global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_lds_kernel(const uint16_t *u, int64_t ldu, int p,
+                                                                          const double *c, int64_t K, int64_t kchunk,
+                                                                          float *part)
+{
+    extern __shared__ uint16_t sh[];   // [nt*32][kLdsStride] plain, then weighted (WEIGHT)
+    __shared__ float cw[kLdsKC];
+    const int nt = (p + kMT - 1) / kMT;
+    const int rows = nt * kMT;
+    uint16_t *plain = sh;
+    uint16_t *wtd = sh + (size_t)rows * kLdsStride;
+    const int npairs = nt * (nt + 1) / 2;
+    const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+    const int s = blockIdx.x;
+    const int pair0 = blockIdx.y * kPairsPerGroup + w * kTilesPerWave;
+    const int nq = npairs - pair0 < kTilesPerWave ? (npairs - pair0 > 0 ? npairs - pair0 : 0) : kTilesPerWave;
+    const int64_t k0 = (int64_t)s * kchunk;
+    const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+    int ti[kTilesPerWave], tj[kTilesPerWave];
+    f32x16 acc[kTilesPerWave];
+#pragma unroll
+    for (int q = 0; q < kTilesPerWave; ++q) {
+        tile_pair(pair0 + q < npairs ? pair0 + q : 0, nt, ti[q], tj[q]);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[q][i] = 0.0f;
+    }
+    const int rsub = lane & 31, ksub = 8 * (lane >> 5);
+    for (int64_t kc = k0; kc < k1; kc += kLdsKC) {
+        if (WEIGHT && threadIdx.x < kLdsKC) cw[threadIdx.x] = (float)c[kc + threadIdx.x];
+        __syncthreads();
+        // stage rows x 64 k: 16-byte pieces, 8 per row
+        for (int e = threadIdx.x; e < rows * 8; e += 64 * kSyrkBfWaves) {
+            const int r = e >> 3, piece = e & 7;
+            u32x4v v = {0u, 0u, 0u, 0u};
+            if (r < p) v = *reinterpret_cast<const u32x4v *>(u + (int64_t)r * ldu + kc + 8 * piece);
+            *reinterpret_cast<u32x4v *>(plain + r * kLdsStride + 8 * piece) = v;
+            if (WEIGHT) {
+                bf16x8 x = __builtin_bit_cast(bf16x8, v), y;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) y[i] = (__bf16)((float)x[i] * cw[8 * piece + i]);
+                *reinterpret_cast<u32x4v *>(wtd + r * kLdsStride + 8 * piece) = __builtin_bit_cast(u32x4v, y);
+            }
+        }
+        __syncthreads();
+        const uint16_t *asrc = WEIGHT ? wtd : plain;
+#pragma unroll
+        for (int sub = 0; sub < kLdsKC / 16; ++sub) {
+            const int kk = 16 * sub + ksub;
+#pragma unroll
+            for (int q = 0; q < kTilesPerWave; ++q) {
+                if (q < nq) {
+                    const bf16x8 a = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const u32x4v *>(asrc + (ti[q] * kMT + rsub) * kLdsStride + kk));
+                    const bf16x8 b = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const u32x4v *>(plain + (tj[q] * kMT + rsub) * kLdsStride + kk));
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kTilesPerWave; ++q) {
+        if (q < nq) {
+            float *out = part + ((int64_t)s * npairs + pair0 + q) * (kMT * kMT);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = 8 * (i / 4) + 4 * (lane / 32) + (i % 4), n = lane % 32;
+                out[m * kMT + n] = acc[q][i];
+            }
+        }
+    }
+}
+
 // C (+)= sign * scale_i * scale_j * sum over ranges of the partial tiles (FP64).
 __global__ __launch_bounds__(256) void syrk_bf16_reduce_kernel(const float *part, int p, int S, const float *scale,
                                                                double sign, int accumulate, double *C)
@@ -328,6 +553,11 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(const double *x, int64_t l
 
 }  // namespace
 
+size_t syrk_bf16_partial_bytes(int p, int splits)
+{
+    return sizeof(float) * (size_t)splits * (size_t)npairs32(p) * kMT * kMT;
+}
+
 size_t syrk_partial_bytes(int p, int splits)
 {
     const int nt = (p + kTile - 1) / kTile;
@@ -362,10 +592,34 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
     const int ngroups = (npairs + kPairsPerGroup - 1) / kPairsPerGroup;
     const int64_t K16 = (K + 15) / 16 * 16;          // entries K..K16-1 are zero (padding)
     if (K16 > ldu) return -1;
-    int64_t kchunk = (K16 + splits - 1) / splits;
-    kchunk = (kchunk + 15) / 16 * 16;
     float *fpart = reinterpret_cast<float *>(part);
-    syrk_bf16_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, 0, stream>>>(u, ldu, p, c, K16, kchunk, fpart);
+    const int nt = (p + kMT - 1) / kMT;
+    const int64_t K64 = (K + kLdsKC - 1) / kLdsKC * kLdsKC;
+    if (nt <= kLdsMaxTiles && K64 <= ldu && ldu % 8 == 0) {
+        int64_t kchunk = (K64 + splits - 1) / splits;
+        kchunk = (kchunk + kLdsKC - 1) / kLdsKC * kLdsKC;
+        const size_t lds = sizeof(uint16_t) * (size_t)nt * kMT * kLdsStride * (c ? 2 : 1);
+        static bool attr = false;
+        if (!attr) {
+            const size_t most = sizeof(uint16_t) * (size_t)kLdsMaxTiles * kMT * kLdsStride * 2;
+            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess ||
+                hipFuncSetAttribute(reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<false>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
+                return -3;
+            attr = true;
+        }
+        if (c)
+            syrk_bf16_lds_kernel<true><<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64,
+                                                                                                 kchunk, fpart);
+        else
+            syrk_bf16_lds_kernel<false><<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64,
+                                                                                                  kchunk, fpart);
+    } else {
+        int64_t kchunk = (K16 + splits - 1) / splits;
+        kchunk = (kchunk + 15) / 16 * 16;
+        syrk_bf16_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, 0, stream>>>(u, ldu, p, c, K16, kchunk, fpart);
+    }
     syrk_bf16_reduce_kernel<<<npairs, 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
@@ -373,7 +627,20 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
 int chol_solve(double *A, int p, const double *g, const uint8_t *free_col, int factored, double *dx, int *status,
                hipStream_t stream)
 {
-    chol_solve_kernel<<<1, 256, sizeof(double) * (size_t)p, stream>>>(A, p, g, free_col, factored, dx, status);
+    if (p <= kCholMaxP) {
+        const size_t lds = sizeof(double) * ((size_t)p * kCholNB + p);
+        static bool attr = false;
+        if (!attr) {
+            const size_t most = sizeof(double) * ((size_t)kCholMaxP * kCholNB + kCholMaxP);
+            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_blocked_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
+                return -3;
+            attr = true;
+        }
+        chol_blocked_kernel<<<1, kCholThreads, lds, stream>>>(A, p, g, free_col, factored, dx, status);
+    } else {
+        chol_solve_kernel<<<1, 256, sizeof(double) * (size_t)p, stream>>>(A, p, g, free_col, factored, dx, status);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

@@ -125,6 +125,27 @@ static int choose_layout(const std::vector<uint32_t> &meta, int p, LaunchShape &
     return COX_EUNSUPPORTED;
 }
 
+// Layout for data sets beyond the persistent kernel (Newton fits only): tiles
+// of kNewtonTile rows, stratum-aligned like the persistent layout.  ipt = 0
+// marks that the persistent kernel cannot run on it.
+constexpr int64_t kNewtonTile = 4096;
+
+static void tile_layout(const std::vector<uint32_t> &meta, LaunchShape &shape, std::vector<int64_t> &pos)
+{
+    const int64_t n = (int64_t)meta.size();
+    pos.assign(n, 0);
+    const int64_t la = aligned_positions(meta, kNewtonTile, nullptr);
+    if (la <= n + n / 8) {
+        aligned_positions(meta, kNewtonTile, &pos);
+    } else {
+        std::iota(pos.begin(), pos.end(), int64_t(0));
+    }
+    const int64_t rows = la <= n + n / 8 ? la : n;
+    shape.ipt = 0;
+    shape.grid = (int)((rows + kNewtonTile - 1) / kNewtonTile);
+    shape.ld = (int64_t)shape.grid * kNewtonTile;
+}
+
 extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *o)
 {
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
@@ -164,6 +185,10 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
 
     std::string err;
     int rc = choose_layout(h->meta, (int)p, h->shape, h->pos, err);
+    if (rc == COX_EUNSUPPORTED && opt.mode == COX_NEWTON_REFINE) {
+        tile_layout(h->meta, h->shape, h->pos);
+        rc = 0;
+    }
     if (rc != 0) {
         delete h;
         return fail(nullptr, rc, err);
@@ -174,7 +199,7 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     if ((e = hipMalloc(&h->d_x, sizeof(double) * (size_t)ld * p)) != hipSuccess ||
         (e = hipMalloc(&h->d_meta, sizeof(uint32_t) * (size_t)ld)) != hipSuccess ||
         (e = hipMalloc(&h->d_vec, sizeof(double) * (size_t)(6 * p + kResultSlots + 64))) != hipSuccess ||
-        (e = hipMalloc(&h->d_sync, sync_scratch_bytes(h->shape.grid))) != hipSuccess) {
+        (e = hipMalloc(&h->d_sync, sync_scratch_bytes(h->shape.ipt ? h->shape.grid : 1))) != hipSuccess) {
         free_device(h);
         delete h;
         return hip_fail(nullptr, e, "device allocation");
@@ -222,6 +247,10 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
 static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *beta_host, double *result)
 {
     (void)hipSetDevice(h->device);
+    if (h->shape.ipt == 0)
+        return fail(h, COX_EUNSUPPORTED,
+                    "n exceeds the register-resident capacity of the persistent kernel: this handle supports "
+                    "COX_NEWTON_REFINE fits and cox_evaluate_full only");
     hipError_t e;
     if (beta_host) e = hipMemcpyAsync(h->beta(), beta_host, sizeof(double) * h->p, hipMemcpyHostToDevice, h->stream);
     else e = hipMemsetAsync(h->beta(), 0, sizeof(double) * h->p, h->stream);
@@ -250,6 +279,8 @@ static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *bet
     if (rc != (int)hipSuccess) return hip_fail(h, (hipError_t)rc, "kernel launch");
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "kernel execution");
     (void)hipEventElapsedTime(&h->last_kernel_ms, h->ev0, h->ev1);
+    h->prof = cox_profile{};
+    h->prof.kernel_ms = h->last_kernel_ms;
     uint32_t ctl[2] = {0, 0};
     if ((e = hipMemcpy(ctl, L.ctl, sizeof(ctl), hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(h, e, "reading control words");
@@ -345,6 +376,13 @@ extern "C" int cox_layout(const cox_handle *h, int64_t *perm, uint32_t *meta)
     if (!h) return COX_EINVAL;
     if (perm) std::memcpy(perm, h->perm.data(), sizeof(int64_t) * h->n);
     if (meta) std::memcpy(meta, h->meta.data(), sizeof(uint32_t) * h->n);
+    return COX_OK;
+}
+
+extern "C" int cox_last_profile(const cox_handle *h, cox_profile *out)
+{
+    if (!h || !out) return COX_EINVAL;
+    *out = h->prof;
     return COX_OK;
 }
 

@@ -12,13 +12,19 @@
 // Device buffers of the full-evaluation / Newton path, allocated on first use.
 struct NewtonState {
     bool ready = false;
-    int splits = 1;
     int max_blocks = 0;
+    int64_t tile = 0;              // rows per column-pass tile
+    int ntiles = 0, n_agg = 0;
     int64_t n_groups = 0, ldz = 0;
     int32_t *gidx = nullptr;       // [ld]
     double *rows = nullptr;        // 7 x [ld]: eta, w, s0, h, lam, a, b
     double *blockbuf = nullptr;    // [max_blocks]
-    double *xtpart = nullptr;      // [splits][p][2]
+    uint8_t *tile_carry = nullptr; // [ntiles]
+    int32_t *lasthead = nullptr;   // [ntiles]
+    int32_t *agg_tiles = nullptr;  // [n_agg]
+    double *agg = nullptr;         // [ntiles][p]
+    double *carry = nullptr;       // [ntiles][p]
+    double *colpart = nullptr;     // [ntiles][p][3]
     double *vec = nullptr;         // beta, grad, diag1, diag2, dx (p each), scal (8)
     unsigned *flags = nullptr;
     int *status = nullptr;
@@ -32,6 +38,7 @@ struct NewtonState {
     double *info = nullptr;        // [p][p] information matrix, then its Cholesky factor
     void *scan_scratch = nullptr;
     size_t scan_scratch_bytes = 0;
+    hipEvent_t ev[6] = {};         // around evaluation, contraction, solve
 };
 
 struct cox_handle {
@@ -45,6 +52,7 @@ struct cox_handle {
     void *d_sync = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float last_kernel_ms = 0.0f;
+    cox_profile prof{};
     std::vector<int64_t> perm;     // canonical row -> original row
     std::vector<uint32_t> meta;    // canonical row words
     std::vector<int64_t> pos;      // canonical row -> row of the device layout

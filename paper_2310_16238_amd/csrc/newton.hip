@@ -14,14 +14,14 @@
 // X' products, and one per-column scan forms xbar; the information matrix is
 // two symmetric rank-K products (contraction.hip).
 //
-// Kernels here are ordinary (non-persistent) launches except the row scans,
-// which reuse the cooperative single-pass scan with look-back.
+// All kernels here are ordinary launches (no cross-workgroup waits).
 #include <hip/hip_bf16.h>
 #include <math.h>
 
 #include <type_traits>
 
 #include "internal.h"
+#include "newton.h"
 #include "segscan.hpp"
 
 namespace coxmi {
@@ -129,47 +129,169 @@ __global__ __launch_bounds__(kRowBlock) void rowweight_kernel(const double *w, c
     }
 }
 
-// Split sums over rows: part[(s * p + j) * 2 + {0,1}] = sum over rows of split s
-// of x_rj a_r and x_rj^2 b_r.  Grid (p, S).
-__global__ __launch_bounds__(kRowBlock) void xt_kernel(const double *x, int64_t ld, int p, const double *a,
-                                                       const double *b, int64_t rows_per_split, double *part)
+template <typename ZT>
+__device__ __forceinline__ void store_z(ZT *p, double v, float inv_scale)
 {
-    __shared__ double red[kRowBlock / kWave];
-    const int j = blockIdx.x, s = blockIdx.y;
-    const int64_t r0 = (int64_t)s * rows_per_split;
-    const int64_t r1 = r0 + rows_per_split < ld ? r0 + rows_per_split : ld;
+    if constexpr (std::is_same<ZT, double>::value) *p = v;
+    else if constexpr (std::is_same<ZT, float>::value) *p = (float)v * inv_scale;
+    else *p = __float2bfloat16((float)v * inv_scale);
+}
+
+// ------------------------------------------------------------------ column pass
+//
+// Rows are cut into tiles of `tile` rows (the persistent kernel's tiles, so in
+// the stratum-aligned layout most tiles start with a stratum head).  One wave
+// handles one (tile, column): the forward segmented scan of w x_j over the
+// tile's rows (S1, carried in from the previous tiles when the tile's first
+// row continues a stratum), xbar = S1/S0 at event-group ends with
+// z = sqrt(d) xbar and sum d xbar^2, and the tile's parts of x'(w Lambda - delta)
+// and (x o x)'(w Lambda).  The carries come from a masked sum per (tile,
+// column) -- the rows after the tile's last head -- chained per column.
+
+constexpr int kColWaves = 4, kColIpt = 4, kColChunk = kWave * kColIpt;
+
+__device__ __forceinline__ void load4(const double *p, double *v)
+{
+    const double2 lo = *reinterpret_cast<const double2 *>(p);
+    const double2 hi = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = lo.x;
+    v[1] = lo.y;
+    v[2] = hi.x;
+    v[3] = hi.y;
+}
+
+// agg[t][j] = sum of w x_j over the rows of tile t from its last head (or its
+// first row) to its end, for the tiles listed in `tiles`.
+__global__ __launch_bounds__(kWave * kColWaves) void colagg_kernel(const double *x, int64_t ld, int p, const double *w,
+                                                                   int64_t tile, const int32_t *tiles, int ntl,
+                                                                   const int32_t *lasthead, double *agg)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kColWaves + threadIdx.x / kWave);
+    if (item >= ntl * p) return;
+    const int t = tiles[item / p], j = item % p;
+    const int64_t r1 = (int64_t)(t + 1) * tile;
+    const int64_t r0 = lasthead[t] >= 0 ? (int64_t)lasthead[t] : (int64_t)t * tile;
     const double *xj = x + (int64_t)j * ld;
-    double ga = 0.0, gb = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kRowBlock) {
-        const double v = xj[r];
-        ga = fma(v, a[r], ga);
-        gb = fma(v * v, b[r], gb);
-    }
-    ga = block_sum(ga, red);
-    gb = block_sum(gb, red);
-    if (threadIdx.x == 0) {
-        part[((int64_t)s * p + j) * 2] = ga;
-        part[((int64_t)s * p + j) * 2 + 1] = gb;
+    double s = 0.0;
+    for (int64_t r = r0 + lane; r < r1; r += kWave) s = fma(w[r], xj[r], s);
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if (lane == 0) agg[(int64_t)t * p + j] = s;
+}
+
+// carry[t][j] = the S1 running sum entering tile t (for tiles whose first row
+// continues a stratum).  One thread per column, tiles in order.
+__global__ __launch_bounds__(256) void colcarry_kernel(int p, int ntiles, const uint8_t *tile_carry,
+                                                       const int32_t *lasthead, const double *agg, double *carry)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= p) return;
+    double c = 0.0;
+    for (int t = 0; t < ntiles; ++t) {
+        carry[(int64_t)t * p + j] = c;
+        if (t + 1 < ntiles && tile_carry[t + 1]) c = (lasthead[t] >= 0 ? 0.0 : c) + agg[(int64_t)t * p + j];
+        else c = 0.0;
     }
 }
 
-// Fixed-order sums of the split partials: out_a[j], out_b[j]; also the
-// objective (sum of blockobj, by workgroup 0).
-__global__ __launch_bounds__(kRowBlock) void xt_reduce_kernel(const double *part, int p, int S, double *out_a,
-                                                              double *out_b, const double *blockobj, int nb,
-                                                              double *scal)
+template <typename ZT, bool XBAR>
+__global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double *x, int64_t ld, int p, int64_t tile,
+                                                                    int ntiles, const double *w, const double *s0,
+                                                                    const double *a, const double *b,
+                                                                    const uint32_t *meta, const int32_t *gidx,
+                                                                    const uint8_t *tile_carry, const double *carry,
+                                                                    int64_t ldz, const float *zscale, ZT *z,
+                                                                    double *part)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kColWaves + threadIdx.x / kWave);
+    if (item >= ntiles * p) return;   // whole wave; no workgroup barrier below
+    const int t = item / p, j = item % p;
+    const double *xj = x + (int64_t)j * ld;
+    const int64_t r_begin = (int64_t)t * tile, r_end = r_begin + tile;
+    double g = 0.0, d1 = 0.0, d2 = 0.0;
+    SegVal<1> run_carry = seg_identity<1>();
+    if (XBAR && tile_carry[t]) run_carry.v[0] = carry[(int64_t)t * p + j];
+    const float zs = zscale ? 1.0f / zscale[j] : 1.0f;
+    for (int64_t base = r_begin; base < r_end; base += kColChunk) {
+        const int64_t r0 = base + (int64_t)lane * kColIpt;
+        // 4 consecutive rows per lane: 16-byte loads (r0 is a multiple of 4)
+        double xv[kColIpt], wv[kColIpt], av[kColIpt], bv[kColIpt];
+        uint32_t m[kColIpt];
+        load4(xj + r0, xv);
+        load4(a + r0, av);
+        load4(b + r0, bv);
+        if (XBAR) load4(w + r0, wv);
+        {
+            const uint4 mm = *reinterpret_cast<const uint4 *>(meta + r0);
+            m[0] = mm.x;
+            m[1] = mm.y;
+            m[2] = mm.z;
+            m[3] = mm.w;
+        }
+#pragma unroll
+        for (int i = 0; i < kColIpt; ++i) {
+            g = fma(xv[i], av[i], g);
+            d1 = fma(xv[i] * xv[i], bv[i], d1);
+        }
+        if (XBAR) {
+            SegVal<1> e[kColIpt];
+            SegVal<1> tot = seg_identity<1>();
+#pragma unroll
+            for (int i = 0; i < kColIpt; ++i) {
+                e[i].f = m[i] >> 31;
+                e[i].v[0] = wv[i] * xv[i];
+                tot = seg_combine(tot, e[i]);
+            }
+            const SegVal<1> inc = wave_inclusive_scan(tot);
+            SegVal<1> run = seg_combine(run_carry, wave_shift_right(inc));
+#pragma unroll
+            for (int i = 0; i < kColIpt; ++i) {
+                run = seg_combine(run, e[i]);
+                const uint32_t d = m[i] & kCountMask;
+                if (d != 0u) {
+                    const int64_t r = r0 + i;
+                    const double xb = run.v[0] / s0[r];
+                    d2 = fma((double)d * xb, xb, d2);
+                    store_z<ZT>(&z[(int64_t)j * ldz + gidx[r]], sqrt((double)d) * xb, zs);
+                }
+            }
+            run_carry = seg_combine(run_carry, lane63_seg(inc));
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        g += __shfl_xor(g, off, kWave);
+        d1 += __shfl_xor(d1, off, kWave);
+        d2 += __shfl_xor(d2, off, kWave);
+    }
+    if (lane == 0) {
+        double *o = part + ((int64_t)t * p + j) * 3;
+        o[0] = g;
+        o[1] = d1;
+        o[2] = d2;
+    }
+}
+
+// Fixed-order sums over tiles: grad[j], diag1[j], diag2[j]; workgroup p sums
+// the objective parts.
+__global__ __launch_bounds__(kRowBlock) void colreduce_kernel(const double *part, int p, int ntiles, double *grad,
+                                                              double *diag1, double *diag2, const double *blockobj,
+                                                              int nb, double *scal)
 {
     __shared__ double red[kRowBlock / kWave];
     const int j = blockIdx.x;
     if (j < p) {
         if (threadIdx.x == 0) {
-            double sa = 0.0, sb = 0.0;
-            for (int s = 0; s < S; ++s) {
-                sa += part[((int64_t)s * p + j) * 2];
-                sb += part[((int64_t)s * p + j) * 2 + 1];
+            double sg = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int t = 0; t < ntiles; ++t) {
+                const double *o = part + ((int64_t)t * p + j) * 3;
+                sg += o[0];
+                s1 += o[1];
+                s2 += o[2];
             }
-            out_a[j] = sa;
-            out_b[j] = sb;
+            grad[j] = sg;
+            diag1[j] = s1;
+            diag2[j] = s2;
         }
     } else {
         double o = 0.0;
@@ -179,131 +301,107 @@ __global__ __launch_bounds__(kRowBlock) void xt_reduce_kernel(const double *part
     }
 }
 
-template <typename ZT>
-__device__ __forceinline__ void store_z(ZT *p, double v, float inv_scale)
-{
-    if constexpr (std::is_same<ZT, double>::value) *p = v;
-    else if constexpr (std::is_same<ZT, float>::value) *p = (float)v * inv_scale;
-    else *p = __float2bfloat16((float)v * inv_scale);
-}
-
-// Per column j (one workgroup of 1024 threads): forward segmented scan of
-// w x_j over the rows, tile by tile with the carry in registers; at each
-// event-group end (gidx >= 0): xbar = S1 / S0, diag2_j += d xbar^2, and
-// z[j][g] = sqrt(d) xbar in the contraction's storage type.
-template <typename ZT>
-__global__ __launch_bounds__(1024) void xbar_kernel(const double *x, int64_t ld, const double *w, const double *s0,
-                                                    const uint32_t *meta, const int32_t *gidx, int64_t ldz,
-                                                    const float *zscale, ZT *z, double *diag2)
-{
-    constexpr int NW = 1024 / kWave, IPT = 4, TILE = 1024 * IPT;
-    __shared__ SegVal<1> wtot[NW];
-    __shared__ double red[NW];
-    const int j = blockIdx.x, t = threadIdx.x;
-    const double *xj = x + (int64_t)j * ld;
-    const float zs = zscale ? 1.0f / zscale[j] : 1.0f;
-    SegVal<1> carry = seg_identity<1>();
-    double d2 = 0.0;
-    for (int64_t base = 0; base < ld; base += TILE) {
-        SegVal<1> e[IPT];
-        SegVal<1> tagg = seg_identity<1>();
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            const int64_t r = base + (int64_t)t * IPT + i;
-            if (r < ld) {
-                e[i].f = meta[r] >> 31;
-                e[i].v[0] = w[r] * xj[r];
-            } else {
-                e[i] = seg_identity<1>();
-                e[i].f = 1u;
-            }
-            tagg = seg_combine(tagg, e[i]);
-        }
-        SegVal<1> btot;
-        SegVal<1> exc = block_exclusive_scan<1, NW>(tagg, wtot, btot);
-        SegVal<1> run = seg_combine(carry, exc);
-#pragma unroll
-        for (int i = 0; i < IPT; ++i) {
-            const int64_t r = base + (int64_t)t * IPT + i;
-            run = seg_combine(run, e[i]);
-            if (r < ld) {
-                const int32_t g = gidx[r];
-                if (g >= 0) {
-                    const double d = (double)(meta[r] & kCountMask);
-                    const double xb = run.v[0] / s0[r];
-                    d2 = fma(d * xb, xb, d2);
-                    store_z<ZT>(&z[(int64_t)j * ldz + g], sqrt(d) * xb, zs);
-                }
-            }
-        }
-        carry = seg_combine(carry, btot);
-        __syncthreads();   // wtot is rewritten by the next tile
-    }
-    // fixed-order workgroup sum of the diag2 parts
-    for (int off = 32; off >= 1; off >>= 1) d2 += __shfl_xor(d2, off, kWave);
-    if ((t & (kWave - 1)) == 0) red[t / kWave] = d2;
-    __syncthreads();
-    if (t == 0) {
-        double s = 0.0;
-        for (int k = 0; k < NW; ++k) s += red[k];
-        diag2[j] = s;
-    }
-}
-
 // ------------------------------------------------------------------ row scans (forward / reverse)
+//
+// Segmented +scan of one FP64 value per row over all ld rows, in tiles of
+// `tile` rows: (1) each workgroup folds its tile into one aggregate, (2) one
+// workgroup scans the aggregates into the carry entering every tile, (3) each
+// workgroup rescans its tile from its carry.  REV scans from the last row
+// backwards, a segment then starting at the last row of each stratum.
 
-// Inclusive segmented +scan of `a` over rows 0..n-1 with the head flags of
-// `meta`; REV scans from the last row backwards, a segment then starting at
-// the last row of each stratum.  Same single-pass cooperative scheme as the
-// scan primitive.
-template <int IPT, bool REV>
-__global__ __launch_bounds__(1024) void rowscan_kernel(const double *a, const uint32_t *meta, double *out, int64_t n,
-                                                       Packet *aggp, SyncCtl *ctl)
+constexpr int kScanThreads = 256, kScanWaves = kScanThreads / kWave;
+
+template <bool REV>
+__device__ __forceinline__ uint32_t scan_head(const uint32_t *meta, int64_t n, int64_t k)
 {
-    constexpr int NW = 1024 / kWave;
-    __shared__ SegVal<1> s_wtot[NW];
-    __shared__ SegVal<1> s_win[kMaxGroups / kWave];
-    __shared__ int s_abort;
-    const PacketArray agg = packet_array(aggp, sizeof(Packet) * gridDim.x);
-    const int b = blockIdx.x, t = threadIdx.x;
-    const int64_t tile0 = (int64_t)b * 1024 * IPT;
-    const int64_t row0 = tile0 + (int64_t)t * IPT;
-    auto head_at = [&](int64_t i) -> uint32_t {   // i in scan order
-        if (!REV) return (i == 0 || (meta[i] & kHeadBit)) ? 1u : 0u;
-        const int64_t r = n - 1 - i;   // row; a reverse segment starts at a stratum's last row
-        return (i == 0 || (meta[r + 1] & kHeadBit)) ? 1u : 0u;
-    };
-    SegVal<1> e[IPT];
-    SegVal<1> tagg = seg_identity<1>();
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        const int64_t k = row0 + i;
-        if (k < n) {
-            e[i].f = head_at(k);
-            e[i].v[0] = a[REV ? n - 1 - k : k];
-        } else {
-            e[i].f = 1u;
-            e[i].v[0] = 0.0;
+    if (k == 0) return 1u;
+    if (!REV) return (meta[k] & kHeadBit) ? 1u : 0u;
+    return (meta[n - k] & kHeadBit) ? 1u : 0u;   // row n-1-k is a stratum's last row
+}
+
+template <bool REV>
+__global__ __launch_bounds__(kScanThreads) void tileagg_kernel(const double *a, const uint32_t *meta, int64_t n,
+                                                                 int64_t tile, double *aggv, uint32_t *aggf)
+{
+    __shared__ SegVal<1> wtot[kScanWaves];
+    const int t = blockIdx.x;
+    const int64_t per = tile / kScanThreads;
+    const int64_t k0 = (int64_t)t * tile + (int64_t)threadIdx.x * per;
+    SegVal<1> f = seg_identity<1>();
+    for (int64_t i = 0; i < per; ++i) {
+        const int64_t k = k0 + i;
+        SegVal<1> e;
+        e.f = scan_head<REV>(meta, n, k);
+        e.v[0] = a[REV ? n - 1 - k : k];
+        f = seg_combine(f, e);
+    }
+    SegVal<1> total;
+    (void)block_exclusive_scan<1, kScanWaves>(f, wtot, total);
+    if (threadIdx.x == 0) {
+        aggv[t] = total.v[0];
+        aggf[t] = total.f;
+    }
+}
+
+// carry[t] = the running segment sum entering tile t (one workgroup)
+__global__ __launch_bounds__(1024) void tilecarry_kernel(const double *aggv, const uint32_t *aggf, int ntiles,
+                                                         double *carry)
+{
+    __shared__ SegVal<1> wtot[1024 / kWave];
+    const int per = (ntiles + 1023) / 1024;
+    const int t0 = threadIdx.x * per;
+    SegVal<1> f = seg_identity<1>();
+    for (int i = 0; i < per; ++i) {
+        const int t = t0 + i;
+        if (t < ntiles) {
+            SegVal<1> e;
+            e.f = aggf[t];
+            e.v[0] = aggv[t];
+            f = seg_combine(f, e);
         }
-        tagg = seg_combine(tagg, e[i]);
     }
-    if (t == 0) s_abort = 0;
-    const uint32_t epoch = 1;
-    SegVal<1> btot;
-    SegVal<1> exc = block_exclusive_scan<1, NW>(tagg, s_wtot, btot);
-    if (t == 0) publish_aggregate<1>(agg, b, btot, epoch);
-    const bool tile_head = tile0 >= n || head_at(tile0) != 0u;
-    if (!tile_head) {
-        SegVal<1> carry;
-        if (!look_back<1>(b, epoch, agg, ctl, s_win, &s_abort, carry)) return;
-        exc = seg_combine(carry, exc);
+    SegVal<1> total;
+    SegVal<1> run = block_exclusive_scan<1, 1024 / kWave>(f, wtot, total);
+    for (int i = 0; i < per; ++i) {
+        const int t = t0 + i;
+        if (t < ntiles) {
+            carry[t] = run.v[0];
+            SegVal<1> e;
+            e.f = aggf[t];
+            e.v[0] = aggv[t];
+            run = seg_combine(run, e);
+        }
     }
-    SegVal<1> run = exc;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-        run = seg_combine(run, e[i]);
-        const int64_t k = row0 + i;
-        if (k < n) out[REV ? n - 1 - k : k] = run.v[0];
+}
+
+template <bool REV>
+__global__ __launch_bounds__(kScanThreads) void tileapply_kernel(const double *a, const uint32_t *meta, double *out,
+                                                                   int64_t n, int64_t tile, const double *carry)
+{
+    __shared__ SegVal<1> wtot[kScanWaves];
+    const int t = blockIdx.x;
+    const int64_t per = tile / kScanThreads;
+    const int64_t k0 = (int64_t)t * tile + (int64_t)threadIdx.x * per;
+    SegVal<1> f = seg_identity<1>();
+    for (int64_t i = 0; i < per; ++i) {
+        const int64_t k = k0 + i;
+        SegVal<1> e;
+        e.f = scan_head<REV>(meta, n, k);
+        e.v[0] = a[REV ? n - 1 - k : k];
+        f = seg_combine(f, e);
+    }
+    SegVal<1> total;
+    const SegVal<1> exc = block_exclusive_scan<1, kScanWaves>(f, wtot, total);
+    SegVal<1> run = seg_identity<1>();
+    run.v[0] = carry[t];
+    run = seg_combine(run, exc);
+    for (int64_t i = 0; i < per; ++i) {
+        const int64_t k = k0 + i;
+        SegVal<1> e;
+        e.f = scan_head<REV>(meta, n, k);
+        e.v[0] = a[REV ? n - 1 - k : k];
+        run = seg_combine(run, e);
+        out[REV ? n - 1 - k : k] = run.v[0];
     }
 }
 
@@ -311,45 +409,24 @@ __global__ __launch_bounds__(1024) void rowscan_kernel(const double *a, const ui
 
 // ------------------------------------------------------------------ host launchers
 
-int rowscan(const double *a, const uint32_t *meta, double *out, int64_t n, bool reverse, void *scratch,
-            size_t scratch_bytes, hipStream_t stream)
+int rowscan(const double *a, const uint32_t *meta, double *out, int64_t n, int64_t tile, bool reverse,
+            void *scratch, size_t scratch_bytes, hipStream_t stream)
 {
-    int cus = 0, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return -3;
-    const int ipts[] = {1, 2, 4, 8, 16};
-    int ipt = 0;
-    int64_t grid = 0;
-    for (int c : ipts) {
-        grid = (n + 1024LL * c - 1) / (1024LL * c);
-        if (grid <= cus && grid <= kMaxGroups) {
-            ipt = c;
-            break;
-        }
-    }
-    if (!ipt) return -5;
-    const size_t need = 256 + sizeof(Packet) * (size_t)grid;
-    if (need > scratch_bytes) return -5;
-    SyncCtl *ctl = static_cast<SyncCtl *>(scratch);
-    Packet *agg = reinterpret_cast<Packet *>(static_cast<char *>(scratch) + 256);
-    hipError_t e = hipMemsetAsync(scratch, 0, need, stream);
-    if (e != hipSuccess) return -3;
-    void *args[] = {(void *)&a, (void *)&meta, (void *)&out, (void *)&n, (void *)&agg, (void *)&ctl};
-    const void *fn = nullptr;
-#define COXMI_PICK(I) (reverse ? reinterpret_cast<const void *>(&rowscan_kernel<I, true>) \
-                               : reinterpret_cast<const void *>(&rowscan_kernel<I, false>))
-    switch (ipt) {
-    case 1: fn = COXMI_PICK(1); break;
-    case 2: fn = COXMI_PICK(2); break;
-    case 4: fn = COXMI_PICK(4); break;
-    case 8: fn = COXMI_PICK(8); break;
-    default: fn = COXMI_PICK(16); break;
-    }
-#undef COXMI_PICK
-    e = hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(1024), args, 0, stream);
-    return e == hipSuccess ? 0 : -3;
+    if (tile <= 0 || tile % kScanThreads != 0 || n % tile != 0) return -5;
+    const int ntiles = (int)(n / tile);
+    if (rowscan_scratch_bytes(ntiles) > scratch_bytes) return -5;
+    double *aggv = static_cast<double *>(scratch);
+    double *carry = aggv + ntiles;
+    uint32_t *aggf = reinterpret_cast<uint32_t *>(carry + ntiles);
+    if (reverse) tileagg_kernel<true><<<ntiles, kScanThreads, 0, stream>>>(a, meta, n, tile, aggv, aggf);
+    else tileagg_kernel<false><<<ntiles, kScanThreads, 0, stream>>>(a, meta, n, tile, aggv, aggf);
+    tilecarry_kernel<<<1, 1024, 0, stream>>>(aggv, aggf, ntiles, carry);
+    if (reverse) tileapply_kernel<true><<<ntiles, kScanThreads, 0, stream>>>(a, meta, out, n, tile, carry);
+    else tileapply_kernel<false><<<ntiles, kScanThreads, 0, stream>>>(a, meta, out, n, tile, carry);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
 }
+
+size_t rowscan_scratch_bytes(int ntiles) { return (sizeof(double) * 2 + sizeof(uint32_t)) * (size_t)ntiles + 256; }
 
 int full_eval_launch(const FullEvalArgs &A, hipStream_t stream)
 {
@@ -361,32 +438,31 @@ int full_eval_launch(const FullEvalArgs &A, hipStream_t stream)
     eta_kernel<<<nb, kRowBlock, 0, stream>>>(A.x, ld, A.p, A.beta, A.meta, A.eta, A.blockbuf);
     max_kernel<<<1, kRowBlock, 0, stream>>>(A.blockbuf, nb, A.scal);
     weight_kernel<<<nb, kRowBlock, 0, stream>>>(A.eta, A.scal, ld, A.w);
-    int rc = rowscan(A.w, A.meta, A.s0, ld, false, A.scan_scratch, A.scan_scratch_bytes, stream);
+    int rc = rowscan(A.w, A.meta, A.s0, ld, A.tile, false, A.scan_scratch, A.scan_scratch_bytes, stream);
     if (rc) return rc;
     hazard_kernel<<<nb, kRowBlock, 0, stream>>>(A.s0, A.eta, A.meta, A.scal, ld, A.h, A.blockbuf, A.flags);
-    rc = rowscan(A.h, A.meta, A.lam, ld, true, A.scan_scratch, A.scan_scratch_bytes, stream);
+    rc = rowscan(A.h, A.meta, A.lam, ld, A.tile, true, A.scan_scratch, A.scan_scratch_bytes, stream);
     if (rc) return rc;
     rowweight_kernel<<<nb, kRowBlock, 0, stream>>>(A.w, A.lam, A.meta, ld, A.a, A.b);
-    const int64_t rps = (ld + A.splits - 1) / A.splits;
-    xt_kernel<<<dim3(A.p, A.splits), kRowBlock, 0, stream>>>(A.x, ld, A.p, A.a, A.b, rps, A.xtpart);
-    xt_reduce_kernel<<<A.p + 1, kRowBlock, 0, stream>>>(A.xtpart, A.p, A.splits, A.grad, A.diag1, A.blockbuf, nb,
-                                                        A.scal);
-    if (!A.want_xbar) return hipGetLastError() == hipSuccess ? 0 : -3;
-    switch (A.ztype) {
-    case kZF64:
-        xbar_kernel<double><<<A.p, 1024, 0, stream>>>(A.x, ld, A.w, A.s0, A.meta, A.gidx, A.ldz, nullptr,
-                                                      static_cast<double *>(A.z), A.diag2);
-        break;
-    case kZF32:
-        xbar_kernel<float><<<A.p, 1024, 0, stream>>>(A.x, ld, A.w, A.s0, A.meta, A.gidx, A.ldz, A.zscale,
-                                                     static_cast<float *>(A.z), A.diag2);
-        break;
-    default:
-        xbar_kernel<__hip_bfloat16><<<A.p, 1024, 0, stream>>>(A.x, ld, A.w, A.s0, A.meta, A.gidx, A.ldz,
-                                                              A.zscale, static_cast<__hip_bfloat16 *>(A.z),
-                                                              A.diag2);
-        break;
+    if (A.n_agg > 0) {
+        colagg_kernel<<<(A.n_agg * A.p + kColWaves - 1) / kColWaves, kWave * kColWaves, 0, stream>>>(
+            A.x, ld, A.p, A.w, A.tile, A.agg_tiles, A.n_agg, A.lasthead, A.agg);
+        colcarry_kernel<<<(A.p + 255) / 256, 256, 0, stream>>>(A.p, A.ntiles, A.tile_carry, A.lasthead, A.agg,
+                                                               A.carry);
     }
+    const int items = A.ntiles * A.p;
+    const int grid = (items + kColWaves - 1) / kColWaves;
+#define COXMI_COLPASS(ZT, XB)                                                                                  \
+    colpass_kernel<ZT, XB><<<grid, kWave * kColWaves, 0, stream>>>(                                            \
+        A.x, ld, A.p, A.tile, A.ntiles, A.w, A.s0, A.a, A.b, A.meta, A.gidx, A.tile_carry, A.carry, A.ldz,     \
+        A.zscale, static_cast<ZT *>(A.z), A.colpart)
+    if (!A.want_xbar) COXMI_COLPASS(double, false);
+    else if (A.ztype == kZF64) COXMI_COLPASS(double, true);
+    else if (A.ztype == kZF32) COXMI_COLPASS(float, true);
+    else COXMI_COLPASS(__hip_bfloat16, true);
+#undef COXMI_COLPASS
+    colreduce_kernel<<<A.p + 1, kRowBlock, 0, stream>>>(A.colpart, A.p, A.ntiles, A.grad, A.diag1, A.diag2,
+                                                        A.blockbuf, nb, A.scal);
     e = hipGetLastError();
     return e == hipSuccess ? 0 : -3;
 }

@@ -9,6 +9,7 @@
 
 #include "handle.h"
 #include "internal.h"
+#include "newton.h"
 
 using namespace coxmi;
 
@@ -17,6 +18,12 @@ namespace {
 constexpr int kScalSlots = 8;
 
 double *nrow(const NewtonState &s, int64_t ld, int k) { return s.rows + (int64_t)k * ld; }
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.0f;
+    return hipEventElapsedTime(&ms, a, b) == hipSuccess ? (double)ms : 0.0;
+}
 
 template <typename T>
 hipError_t dalloc(T **p, size_t bytes)
@@ -33,23 +40,46 @@ int newton_setup(cox_handle *h)
     const int64_t ld = h->shape.ld, n = h->n;
     const int p = (int)h->p;
     std::vector<int32_t> gidx(ld, -1);
+    std::vector<uint8_t> head(ld, 1);   // padding rows are one-row strata
     int64_t G = 0;
-    for (int64_t i = 0; i < n; ++i)
+    for (int64_t i = 0; i < n; ++i) {
         if (h->meta[i] & kCountMask) gidx[h->pos[i]] = (int32_t)G++;
+        head[h->pos[i]] = (h->meta[i] & kHeadBit) ? 1 : 0;
+    }
     s.n_groups = G;
     s.ldz = std::max<int64_t>(64, (G + 63) / 64 * 64);
     s.max_blocks = (int)((ld + 255) / 256) + 1;
-    s.splits = std::max(1, std::min(64, (int)((2048 + p - 1) / p)));
-    while (s.splits > 1 && ld / s.splits < 4096) --s.splits;
-    const int S1 = 128, S2 = 64;
-    s.syrk_part_bytes = std::max(syrk_partial_bytes(p, S1), syrk_partial_bytes(p, S2));
-    s.scan_scratch_bytes = 256 + sizeof(double) * 2 * kMaxGroups;
+    // column-pass tiles: the persistent kernel's tiles (ld = grid * tile)
+    s.tile = ld / h->shape.grid;
+    s.ntiles = h->shape.grid;
+    std::vector<uint8_t> tile_carry(s.ntiles, 0);
+    std::vector<int32_t> lasthead(s.ntiles, -1), agg_tiles;
+    for (int t = 0; t < s.ntiles; ++t) {
+        tile_carry[t] = head[(size_t)t * s.tile] ? 0 : 1;
+        for (int64_t r = (int64_t)(t + 1) * s.tile - 1; r >= (int64_t)t * s.tile; --r)
+            if (head[r]) {
+                lasthead[t] = (int32_t)r;
+                break;
+            }
+    }
+    for (int t = 0; t + 1 < s.ntiles; ++t)
+        if (tile_carry[t + 1]) agg_tiles.push_back(t);
+    s.n_agg = (int)agg_tiles.size();
+    s.syrk_part_bytes = h->opt.x_precision == COX_BF16
+                            ? std::max(syrk_bf16_partial_bytes(p, kSplitsXBF16), syrk_bf16_partial_bytes(p, kSplitsZBF16))
+                            : std::max(syrk_partial_bytes(p, kSplitsXF64), syrk_partial_bytes(p, kSplitsZF64));
+    s.scan_scratch_bytes = rowscan_scratch_bytes(s.ntiles);
     const size_t zb = ztype_bytes(h->opt.x_precision);
     hipError_t e;
     if ((e = dalloc(&s.gidx, sizeof(int32_t) * ld)) != hipSuccess ||
         (e = dalloc(&s.rows, sizeof(double) * 7 * ld)) != hipSuccess ||
         (e = dalloc(&s.blockbuf, sizeof(double) * s.max_blocks)) != hipSuccess ||
-        (e = dalloc(&s.xtpart, sizeof(double) * 2 * (size_t)s.splits * p)) != hipSuccess ||
+        (e = dalloc(&s.tile_carry, (size_t)s.ntiles)) != hipSuccess ||
+        (e = dalloc(&s.lasthead, sizeof(int32_t) * s.ntiles)) != hipSuccess ||
+        (e = dalloc(&s.agg_tiles, sizeof(int32_t) * std::max(1, s.n_agg))) != hipSuccess ||
+        (e = dalloc(&s.agg, sizeof(double) * (size_t)s.ntiles * p)) != hipSuccess ||
+        (e = dalloc(&s.carry, sizeof(double) * (size_t)s.ntiles * p)) != hipSuccess ||
+        (e = dalloc(&s.colpart, sizeof(double) * 3 * (size_t)s.ntiles * p)) != hipSuccess ||
         (e = dalloc(&s.vec, sizeof(double) * (5 * (size_t)p + kScalSlots))) != hipSuccess ||
         (e = dalloc(&s.flags, sizeof(unsigned))) != hipSuccess ||
         (e = dalloc(&s.status, sizeof(int))) != hipSuccess ||
@@ -62,7 +92,17 @@ int newton_setup(cox_handle *h)
         newton_free(h);
         return handle_hip_fail(h, e, "allocating full-evaluation buffers");
     }
+    for (int k = 0; k < 6 && e == hipSuccess; ++k) e = hipEventCreate(&s.ev[k]);
+    if (e != hipSuccess) {
+        newton_free(h);
+        return handle_hip_fail(h, e, "creating events");
+    }
     e = hipMemcpy(s.gidx, gidx.data(), sizeof(int32_t) * ld, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s.tile_carry, tile_carry.data(), (size_t)s.ntiles, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(s.lasthead, lasthead.data(), sizeof(int32_t) * s.ntiles, hipMemcpyHostToDevice);
+    if (e == hipSuccess && s.n_agg)
+        e = hipMemcpy(s.agg_tiles, agg_tiles.data(), sizeof(int32_t) * s.n_agg, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(s.z, 0, zb * (size_t)p * s.ldz);
     if (e != hipSuccess) {
         newton_free(h);
@@ -109,7 +149,6 @@ int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
     A.beta = d_beta;
     A.ld = ld;
     A.p = p;
-    A.splits = s.splits;
     A.max_blocks = s.max_blocks;
     A.eta = nrow(s, ld, 0);
     A.w = nrow(s, ld, 1);
@@ -119,7 +158,15 @@ int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
     A.a = nrow(s, ld, 5);
     A.b = nrow(s, ld, 6);
     A.blockbuf = s.blockbuf;
-    A.xtpart = s.xtpart;
+    A.tile = s.tile;
+    A.ntiles = s.ntiles;
+    A.tile_carry = s.tile_carry;
+    A.lasthead = s.lasthead;
+    A.agg_tiles = s.agg_tiles;
+    A.n_agg = s.n_agg;
+    A.agg = s.agg;
+    A.carry = s.carry;
+    A.colpart = s.colpart;
     A.grad = d_grad;
     A.diag1 = d_d1;
     A.diag2 = d_d2;
@@ -132,9 +179,13 @@ int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
     A.want_xbar = want_xbar;
     A.scan_scratch = s.scan_scratch;
     A.scan_scratch_bytes = s.scan_scratch_bytes;
+    (void)hipEventRecord(s.ev[0], h->stream);
     int rc = full_eval_launch(A, h->stream);
     if (rc != 0) return handle_fail(h, rc == -5 ? COX_EUNSUPPORTED : COX_EDEVICE, "full evaluation launch");
+    (void)hipEventRecord(s.ev[1], h->stream);
     if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return handle_hip_fail(h, e, "full evaluation");
+    h->prof.evaluations += 1;
+    h->prof.evaluation_ms += elapsed_ms(s.ev[0], s.ev[1]);
     double scal[2];
     out.grad.resize(p);
     out.diag1.resize(p);
@@ -160,19 +211,21 @@ int newton_info(cox_handle *h)
     const int p = (int)h->p;
     const double *b = nrow(s, ld, 6);
     int rc;
+    (void)hipEventRecord(s.ev[2], h->stream);
     if (h->opt.x_precision == COX_BF16) {
-        rc = syrk_bf16(static_cast<const uint16_t *>(s.xlp), ld, p, s.xscale, b, ld, 128, s.syrk_part, 1.0, 0,
-                       s.info, h->stream);
+        rc = syrk_bf16(static_cast<const uint16_t *>(s.xlp), ld, p, s.xscale, b, ld, kSplitsXBF16, s.syrk_part, 1.0,
+                       0, s.info, h->stream);
         if (rc == 0 && s.n_groups > 0)
-            rc = syrk_bf16(static_cast<const uint16_t *>(s.z), s.ldz, p, s.zscale, nullptr, s.n_groups, 64,
+            rc = syrk_bf16(static_cast<const uint16_t *>(s.z), s.ldz, p, s.zscale, nullptr, s.n_groups, kSplitsZBF16,
                            s.syrk_part, -1.0, 1, s.info, h->stream);
     } else {
-        rc = syrk_f64(h->d_x, ld, p, b, ld, 128, s.syrk_part, 1.0, 0, s.info, h->stream);
+        rc = syrk_f64(h->d_x, ld, p, b, ld, kSplitsXF64, s.syrk_part, 1.0, 0, s.info, h->stream);
         if (rc == 0 && s.n_groups > 0)
-            rc = syrk_f64(static_cast<const double *>(s.z), s.ldz, p, nullptr, s.n_groups, 64, s.syrk_part, -1.0,
-                          1, s.info, h->stream);
+            rc = syrk_f64(static_cast<const double *>(s.z), s.ldz, p, nullptr, s.n_groups, kSplitsZF64, s.syrk_part,
+                          -1.0, 1, s.info, h->stream);
     }
     if (rc != 0) return handle_fail(h, COX_EDEVICE, "information-matrix contraction launch");
+    (void)hipEventRecord(s.ev[3], h->stream);
     return COX_OK;
 }
 
@@ -181,10 +234,13 @@ int newton_info(cox_handle *h)
 void newton_free(cox_handle *h)
 {
     NewtonState &s = h->nt;
-    void *ptrs[] = {s.gidx, s.rows, s.blockbuf, s.xtpart, s.vec, s.flags, s.status, s.free_col, s.z,
+    void *ptrs[] = {s.gidx, s.rows, s.blockbuf, s.tile_carry, s.lasthead, s.agg_tiles, s.agg, s.carry,
+                    s.colpart, s.vec, s.flags, s.status, s.free_col, s.z,
                     s.zscale, s.xlp, s.xscale, s.syrk_part, s.info, s.scan_scratch};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    for (hipEvent_t ev : s.ev)
+        if (ev) (void)hipEventDestroy(ev);
     s = NewtonState();
 }
 
@@ -196,6 +252,7 @@ extern "C" int cox_evaluate_full(cox_handle *h, const double *beta, double *obje
     (void)hipSetDevice(h->device);
     int rc = newton_setup(h);
     if (rc != COX_OK) return rc;
+    h->prof = cox_profile{};
     EvalOut ev;
     rc = newton_eval(h, beta, hess_diag || info, ev);
     if (rc != COX_OK) return rc;
@@ -215,6 +272,8 @@ extern "C" int cox_evaluate_full(cox_handle *h, const double *beta, double *obje
         if (e == hipSuccess)
             e = hipMemcpy(info, h->nt.info, sizeof(double) * (size_t)p * p, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return handle_hip_fail(h, e, "information matrix");
+        h->prof.contractions += 1;
+        h->prof.contraction_ms += elapsed_ms(h->nt.ev[2], h->nt.ev[3]);
     }
     return COX_OK;
 }
@@ -226,6 +285,7 @@ int newton_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_inf
     if (rc != COX_OK) return rc;
     NewtonState &s = h->nt;
     const int p = (int)h->p;
+    h->prof = cox_profile{};
     std::vector<double> beta(p, 0.0), prev(p, 0.0), dx(p, 0.0);
     if (beta0) std::memcpy(beta.data(), beta0, sizeof(double) * p);
     std::vector<uint8_t> freec(p, 1);
@@ -259,9 +319,17 @@ int newton_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_inf
             rc = newton_info(h);
             if (rc != COX_OK) return rc;
         }
+        (void)hipEventRecord(s.ev[4], h->stream);
         if (chol_solve(s.info, p, d_grad, s.free_col, frozen ? 1 : 0, d_dx, s.status, h->stream) != 0)
             return handle_fail(h, COX_EDEVICE, "Cholesky launch");
+        (void)hipEventRecord(s.ev[5], h->stream);
         hipError_t e = hipStreamSynchronize(h->stream);
+        if (!frozen) {
+            h->prof.contractions += 1;
+            h->prof.contraction_ms += elapsed_ms(s.ev[2], s.ev[3]);
+        }
+        h->prof.solves += 1;
+        h->prof.solve_ms += elapsed_ms(s.ev[4], s.ev[5]);
         int status = 0;
         if (e == hipSuccess) e = hipMemcpy(&status, s.status, sizeof(int), hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = hipMemcpy(dx.data(), d_dx, sizeof(double) * p, hipMemcpyDeviceToHost);

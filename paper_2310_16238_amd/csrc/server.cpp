@@ -335,7 +335,7 @@ bool ensure_list(cox_server::List &l, size_t bytes, std::string &err)
     return true;
 }
 
-FitDesc make_desc(cox_server *s, const Request &q, size_t off)
+FitDesc make_desc(cox_server *s, const Request &q, size_t off, int slot)
 {
     const FitLayout &L = q.lay;
     char *B = s->arena + off;
@@ -362,6 +362,7 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off)
     F.L = reinterpret_cast<double *>(B + L.L);
     F.part = reinterpret_cast<float *>(B + L.part);
     F.tilemax = reinterpret_cast<double *>(B + L.tilemax);
+    F.st = s->d_state + slot;
     F.n = L.n;
     F.ld = L.ld;
     F.ldz = L.ldz;
@@ -375,6 +376,25 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off)
     F.max_iter = s->opt.max_iter;
     F.freeze = 1;
     return F;
+}
+
+// Host-side guard before a descriptor reaches the device: every array lies in
+// the fit's own arena block and the state is the slot's entry.
+bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_t off, int slot)
+{
+    const char *lo = s->arena + off, *hi = s->arena + off + L.total;
+    auto in = [lo, hi](const void *ptr, size_t bytes) {
+        const char *c = static_cast<const char *>(ptr);
+        return c && c >= lo && c + bytes <= hi;
+    };
+    const size_t p = (size_t)L.p, ld = (size_t)L.ld;
+    return in(F.x, 8 * p * ld) && in(F.xf, 4 * p * ld) && in(F.meta, 4 * ld) && in(F.gidx, 4 * ld) &&
+           in(F.eta, 8 * ld) && in(F.b, 8 * ld) && in(F.z, 4 * p * (size_t)L.ldz) && in(F.beta, 8 * p) &&
+           in(F.prev, 8 * p) && in(F.grad, 8 * p) && in(F.diag2, 8 * p) && in(F.free_col, p) &&
+           in(F.L, 8 * p * p) && in(F.part, 4 * (size_t)(L.nxr + L.nzr) * L.npairs * kTile * kTile) &&
+           in(F.tilemax, 8 * (size_t)L.ntile) && F.st == s->d_state + slot && F.p == L.p && F.ld == L.ld &&
+           F.n <= F.ld && F.ld % kRowPad == 0 && F.ldz % kRowPad == 0 && F.G <= F.ldz && F.p >= 1 &&
+           F.p <= kMaxP && F.ntile * (int64_t)kEtaRows >= F.ld;
 }
 
 // Everything the worker does per round; returns false on a device error (message in `err`).
@@ -426,7 +446,11 @@ bool admit_ready(cox_server *s, WorkerState &ws, std::string &err)
         Request &q = *tk.second;
         Slot &S = s->slots[slot];
         char *B = s->arena + S.arena_off;
-        s->h_desc[slot] = make_desc(s, q, S.arena_off);
+        s->h_desc[slot] = make_desc(s, q, S.arena_off, slot);
+        if (!check_desc(s, s->h_desc[slot], q.lay, S.arena_off, slot)) {
+            err = "internal error: a fit descriptor points outside its block";
+            return false;
+        }
         WCHECK(hipMemcpyAsync(B, s->staging + q.stage_off, q.lay.upload, hipMemcpyHostToDevice, s->copy),
                "uploading a fit");
         WCHECK(hipMemsetAsync(B + q.lay.z, 0, q.lay.zero_end - q.lay.z, s->copy), "clearing a fit");

@@ -218,3 +218,31 @@ def test_full_evaluation_edge_cases():
             r = _scale(fe) + 1e-300
             lim = 1e-11 if prec == coxmi.COX_F64 else 3.5 * U_BF16 + 64 * 2.0 ** -24
             assert np.all(np.abs(info - fe.info) <= lim * r + 1e-12), (n, p, K, prec)
+
+
+def test_newton_beyond_the_resident_kernel():
+    """N = 2.5e6 rows exceeds the persistent kernel's register capacity (256 CUs x 512 x 16):
+    the handle takes the tile layout, Newton fits and full evaluations still match the oracle,
+    and the CCD entry points report COX_EUNSUPPORTED."""
+    d = synth.make("ar1", 2_500_000, 8, 1000, 21, beta_sd=0.5)
+    _say("newton fit beyond the resident kernel n=2.5e6 p=8 K=1000")
+    ref = orc.fit_newton(d.X, d.time, d.event, d.stratum, tol=1e-14)
+    for prec in (coxmi.COX_F64, coxmi.COX_BF16):
+        with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE, x_precision=prec,
+                            tol=1e-13) as m:
+            n, p, ld = coxmi.cox_shape(m.h)
+            assert ld % 4096 == 0 and ld >= n
+            beta, info = m.fit()
+            assert info["status"] == coxmi.COX_OK
+            assert _rel(beta, ref.beta) <= 1e-10
+            with pytest.raises(coxmi.CoxError) as ei:
+                m.evaluate(beta)
+            assert ei.value.code == coxmi.COX_EUNSUPPORTED
+            if prec == coxmi.COX_F64:
+                obj, g, hd, info_m = m.evaluate_full(beta)
+                fe = _oracle_eval(d, beta)
+                _check_first_order(d, obj, g, hd, fe)
+                assert np.all(np.abs(info_m - fe.info) <= 1e-11 * _scale(fe))
+    with pytest.raises(coxmi.CoxError) as ei:
+        coxmi.cox_init(d.X, d.time, d.event, d.stratum)   # CCD mode cannot hold it
+    assert ei.value.code == coxmi.COX_EUNSUPPORTED
