@@ -495,9 +495,139 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_lds_kernel(const 
     }
 }
 
+// ------------------------------------------------------------------ FP8 (e4m3) on the matrix cores
+//
+// X is stored as e4m3 with a power-of-two scale per column (|x / s| <= 224).
+// For X' diag(b) X both operands are the same matrix a_rj = (x_rj / s_j)
+// sqrt(b_r) / S, with S the power of two >= sqrt(max b): each 64-row K chunk
+// of every row tile is read once, multiplied by sqrt(b_r)/S in FP32 and
+// rounded to e4m3 into LDS, and the waves run v_mfma_scale_f32_32x32x64_f8f6f4
+// (unit block scales) on their tile pairs.  The FP32 partials are summed in
+// FP64 times s_i s_j S^2.
+
+constexpr float kFp8Max = 224.0f;   // below the e4m3 maximum of either encoding
+constexpr int kF8KC = 64, kF8Stride = 80;   // bytes per LDS row (64 + 16 pad)
+typedef int i32x8v __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(256) void to_fp8_kernel(const double *x, int64_t ld, const float *xscale, uint8_t *x8)
+{
+    const int j = blockIdx.y;
+    const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (r >= ld) return;
+    const double inv = 1.0 / (double)xscale[j];
+    const double *src = x + (int64_t)j * ld + r;
+    int v = __builtin_amdgcn_cvt_pk_fp8_f32((float)(src[0] * inv), (float)(src[1] * inv), 0, false);
+    v = __builtin_amdgcn_cvt_pk_fp8_f32((float)(src[2] * inv), (float)(src[3] * inv), v, true);
+    *reinterpret_cast<int *>(x8 + (int64_t)j * ld + r) = v;
+}
+
+// wsc[0] = S = 2^ceil(log2(sqrt(max b))) (1 if b is all zero), in two launches
+__global__ __launch_bounds__(256) void bmax_kernel(const double *b, int64_t n, double *blockmax)
+{
+    __shared__ double red[4];
+    double m = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n; r += (int64_t)gridDim.x * 256) m = fmax(m, b[r]);
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) blockmax[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void wscale_kernel(const double *blockmax, int nb, double *wsc)
+{
+    __shared__ double red[4];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) m = fmax(m, blockmax[i]);
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        wsc[0] = m > 0.0 ? exp2(ceil(log2(sqrt(m)))) : 1.0;
+    }
+}
+
+__global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_fp8_lds_kernel(const uint8_t *u, int64_t ldu, int p,
+                                                                        const double *c, const double *wsc,
+                                                                        int64_t K, int64_t kchunk, float *part)
+{
+    extern __shared__ uint8_t sh8[];   // [nt*32][kF8Stride]
+    __shared__ float cw[kF8KC];
+    const int nt = (p + kMT - 1) / kMT;
+    const int rows = nt * kMT;
+    const int npairs = nt * (nt + 1) / 2;
+    const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+    const int s = blockIdx.x;
+    const int pair0 = blockIdx.y * kPairsPerGroup + w * kTilesPerWave;
+    const int nq = npairs - pair0 < kTilesPerWave ? (npairs - pair0 > 0 ? npairs - pair0 : 0) : kTilesPerWave;
+    const int64_t k0 = (int64_t)s * kchunk;
+    const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+    const double invS = 1.0 / wsc[0];
+    int ti[kTilesPerWave], tj[kTilesPerWave];
+    f32x16 acc[kTilesPerWave];
+#pragma unroll
+    for (int q = 0; q < kTilesPerWave; ++q) {
+        tile_pair(pair0 + q < npairs ? pair0 + q : 0, nt, ti[q], tj[q]);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[q][i] = 0.0f;
+    }
+    const int rsub = lane & 31, kofs = 32 * (lane >> 5);
+    for (int64_t kc = k0; kc < k1; kc += kF8KC) {
+        if (threadIdx.x < kF8KC) cw[threadIdx.x] = (float)(sqrt(c[kc + threadIdx.x]) * invS);
+        __syncthreads();
+        // rows x 64 bytes: 16-byte pieces, 4 per row; decode, weight, re-encode
+        for (int e = threadIdx.x; e < rows * 4; e += 64 * kSyrkBfWaves) {
+            const int r = e >> 2, piece = e & 3;
+            u32x4v v = {0u, 0u, 0u, 0u};
+            if (r < p) {
+                const u32x4v raw = *reinterpret_cast<const u32x4v *>(u + (int64_t)r * ldu + kc + 16 * piece);
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int word = (int)raw[d];
+                    const float *wk = cw + 16 * piece + 4 * d;
+                    int o = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_cvt_f32_fp8(word, 0) * wk[0],
+                                                            __builtin_amdgcn_cvt_f32_fp8(word, 1) * wk[1], 0, false);
+                    o = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_cvt_f32_fp8(word, 2) * wk[2],
+                                                        __builtin_amdgcn_cvt_f32_fp8(word, 3) * wk[3], o, true);
+                    v[d] = (unsigned)o;
+                }
+            }
+            *reinterpret_cast<u32x4v *>(sh8 + r * kF8Stride + 16 * piece) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kTilesPerWave; ++q) {
+            if (q < nq) {
+                const uint8_t *pa = sh8 + (ti[q] * kMT + rsub) * kF8Stride + kofs;
+                const uint8_t *pb = sh8 + (tj[q] * kMT + rsub) * kF8Stride + kofs;
+                const u32x4v a0 = *reinterpret_cast<const u32x4v *>(pa), a1 = *reinterpret_cast<const u32x4v *>(pa + 16);
+                const u32x4v b0 = *reinterpret_cast<const u32x4v *>(pb), b1 = *reinterpret_cast<const u32x4v *>(pb + 16);
+                const i32x8v av = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3],
+                                   (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+                const i32x8v bv = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3],
+                                   (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+                acc[q] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[q], 0, 0, 0, 127, 0, 127);
+            }
+        }
+        __syncthreads();   // the next chunk rewrites the LDS tiles
+    }
+#pragma unroll
+    for (int q = 0; q < kTilesPerWave; ++q) {
+        if (q < nq) {
+            float *out = part + ((int64_t)s * npairs + pair0 + q) * (kMT * kMT);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = 8 * (i / 4) + 4 * (lane / 32) + (i % 4), n = lane % 32;
+                out[m * kMT + n] = acc[q][i];
+            }
+        }
+    }
+}
+
 // C (+)= sign * scale_i * scale_j * sum over ranges of the partial tiles (FP64).
 __global__ __launch_bounds__(256) void syrk_bf16_reduce_kernel(const float *part, int p, int S, const float *scale,
-                                                               double sign, int accumulate, double *C)
+                                                               double sign, int accumulate, double *C,
+                                                               const double *wsc)
 {
     const int nt = (p + kMT - 1) / kMT;
     const int npairs = nt * (nt + 1) / 2;
@@ -512,6 +642,7 @@ __global__ __launch_bounds__(256) void syrk_bf16_reduce_kernel(const float *part
         double s = 0.0;
         for (int q = 0; q < S; ++q) s += (double)part[((int64_t)q * npairs + pair) * (kMT * kMT) + e];
         s *= sign * (double)scale[i] * (double)scale[j];
+        if (wsc) s *= wsc[0] * wsc[0];
         if (accumulate) {
             C[(int64_t)i * p + j] += s;
             if (i != j) C[(int64_t)j * p + i] += s;
@@ -523,7 +654,10 @@ __global__ __launch_bounds__(256) void syrk_bf16_reduce_kernel(const float *part
 }
 
 // Per column: the power-of-two scale s_j >= max |x_j| (1 for a zero column).
-__global__ __launch_bounds__(256) void colscale_kernel(const double *x, int64_t ld, float *xscale, float *zscale)
+// xscale_j = the power of two s with max|x_j| / s <= xmax (1 for a zero column);
+// zscale_j = the power of two >= max|x_j| (the BF16 scale of xbar_j).
+__global__ __launch_bounds__(256) void colscale_kernel(const double *x, int64_t ld, float xmax, float *xscale,
+                                                       float *zscale)
 {
     __shared__ double red[4];
     const int j = blockIdx.x;
@@ -534,9 +668,8 @@ __global__ __launch_bounds__(256) void colscale_kernel(const double *x, int64_t 
     __syncthreads();
     if (threadIdx.x == 0) {
         m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-        const float sc = m > 0.0 ? (float)exp2(ceil(log2(m))) : 1.0f;
-        xscale[j] = sc;
-        zscale[j] = sc;
+        xscale[j] = m > 0.0 ? (float)exp2(ceil(log2(m / (double)xmax))) : 1.0f;
+        zscale[j] = m > 0.0 ? (float)exp2(ceil(log2(m))) : 1.0f;
     }
 }
 
@@ -578,7 +711,7 @@ int syrk_f64(const double *u, int64_t ldu, int p, const double *c, int64_t K, in
 
 int make_bf16_copy(const double *x, int64_t ld, int p, void *xlp, float *xscale, float *zscale, hipStream_t stream)
 {
-    colscale_kernel<<<p, 256, 0, stream>>>(x, ld, xscale, zscale);
+    colscale_kernel<<<p, 256, 0, stream>>>(x, ld, 1.0f, xscale, zscale);
     to_bf16_kernel<<<dim3((unsigned)((ld + 255) / 256), p), 256, 0, stream>>>(x, ld, xscale,
                                                                              static_cast<uint16_t *>(xlp));
     return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -620,7 +753,35 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
         kchunk = (kchunk + 15) / 16 * 16;
         syrk_bf16_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, 0, stream>>>(u, ldu, p, c, K16, kchunk, fpart);
     }
-    syrk_bf16_reduce_kernel<<<npairs, 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C);
+    syrk_bf16_reduce_kernel<<<npairs, 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C, nullptr);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int make_fp8_copy(const double *x, int64_t ld, int p, uint8_t *x8, float *xscale, float *zscale, hipStream_t stream)
+{
+    if (ld % 4 != 0) return -1;
+    colscale_kernel<<<p, 256, 0, stream>>>(x, ld, kFp8Max, xscale, zscale);
+    to_fp8_kernel<<<dim3((unsigned)((ld / 4 + 255) / 256), p), 256, 0, stream>>>(x, ld, xscale, x8);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int syrk_fp8(const uint8_t *u, int64_t ldu, int p, const float *scale, const double *c, int64_t K, int splits,
+             double *part, double *blockmax, double *wsc, double sign, int accumulate, double *C, hipStream_t stream)
+{
+    const int nt = (p + kMT - 1) / kMT;
+    const int npairs = nt * (nt + 1) / 2;
+    const int ngroups = (npairs + kPairsPerGroup - 1) / kPairsPerGroup;
+    const int64_t K64 = (K + kF8KC - 1) / kF8KC * kF8KC;
+    if (K64 > ldu || ldu % 16 != 0 || (size_t)nt * kMT * kF8Stride > 65536) return -1;   // p <= 800
+    bmax_kernel<<<256, 256, 0, stream>>>(c, K, blockmax);
+    wscale_kernel<<<1, 256, 0, stream>>>(blockmax, 256, wsc);
+    int64_t kchunk = (K64 + splits - 1) / splits;
+    kchunk = (kchunk + kF8KC - 1) / kF8KC * kF8KC;
+    const size_t lds = (size_t)nt * kMT * kF8Stride;
+    float *fpart = reinterpret_cast<float *>(part);
+    syrk_fp8_lds_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, wsc, K64, kchunk,
+                                                                                   fpart);
+    syrk_bf16_reduce_kernel<<<npairs, 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C, wsc);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

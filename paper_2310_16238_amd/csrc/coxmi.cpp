@@ -159,8 +159,10 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     if (o) opt = *o;
     else cox_default_options(&opt);
     if (opt.mode != COX_CCD && opt.mode != COX_NEWTON_REFINE) return fail(nullptr, COX_EINVAL, "unknown mode");
-    if (opt.x_precision != COX_F64 && opt.x_precision != COX_BF16)
-        return fail(nullptr, COX_EUNSUPPORTED, "x_precision must be COX_F64 or COX_BF16");
+    if (opt.x_precision != COX_F64 && opt.x_precision != COX_BF16 && opt.x_precision != COX_FP8_E4M3)
+        return fail(nullptr, COX_EUNSUPPORTED, "x_precision must be COX_F64, COX_BF16 or COX_FP8_E4M3");
+    if (opt.x_precision == COX_FP8_E4M3 && opt.mode != COX_NEWTON_REFINE)
+        return fail(nullptr, COX_EUNSUPPORTED, "COX_FP8_E4M3 applies to COX_NEWTON_REFINE fits");
     if (opt.mode == COX_NEWTON_REFINE && opt.gamma != 0.0)
         return fail(nullptr, COX_EUNSUPPORTED, "COX_NEWTON_REFINE fits the unpenalised model (gamma = 0)");
     if (opt.ties != COX_BRESLOW) return fail(nullptr, COX_EUNSUPPORTED, "only COX_BRESLOW ties");

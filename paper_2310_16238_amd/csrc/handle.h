@@ -31,7 +31,8 @@ struct NewtonState {
     uint8_t *free_col = nullptr;   // [p]
     void *z = nullptr;             // [p][ldz] in the contraction type
     float *zscale = nullptr;       // [p]
-    void *xlp = nullptr;           // [p][ld] low-precision copy of X (BF16)
+    void *xlp = nullptr;           // [p][ld] low-precision copy of X (BF16 or e4m3)
+    double *wscratch = nullptr;    // FP8: 256 block maxima of the weights, then the weight scale
     float *xscale = nullptr;       // [p]
     double *syrk_part = nullptr;   // split partials of the contraction
     size_t syrk_part_bytes = 0;

@@ -31,7 +31,9 @@ hipError_t dalloc(T **p, size_t bytes)
     return hipMalloc(reinterpret_cast<void **>(p), bytes);
 }
 
-size_t ztype_bytes(int prec) { return prec == COX_BF16 ? 2 : 8; }
+// xbar (Z) is kept in BF16 for both reduced-precision modes
+bool lowp(int prec) { return prec == COX_BF16 || prec == COX_FP8_E4M3; }
+size_t ztype_bytes(int prec) { return lowp(prec) ? 2 : 8; }
 
 int newton_setup(cox_handle *h)
 {
@@ -65,8 +67,9 @@ int newton_setup(cox_handle *h)
     for (int t = 0; t + 1 < s.ntiles; ++t)
         if (tile_carry[t + 1]) agg_tiles.push_back(t);
     s.n_agg = (int)agg_tiles.size();
-    s.syrk_part_bytes = h->opt.x_precision == COX_BF16
-                            ? std::max(syrk_bf16_partial_bytes(p, kSplitsXBF16), syrk_bf16_partial_bytes(p, kSplitsZBF16))
+    s.syrk_part_bytes = lowp(h->opt.x_precision)
+                            ? std::max({syrk_bf16_partial_bytes(p, kSplitsXBF16), syrk_bf16_partial_bytes(p, kSplitsXFP8),
+                                        syrk_bf16_partial_bytes(p, kSplitsZBF16)})
                             : std::max(syrk_partial_bytes(p, kSplitsXF64), syrk_partial_bytes(p, kSplitsZF64));
     s.scan_scratch_bytes = rowscan_scratch_bytes(s.ntiles);
     const size_t zb = ztype_bytes(h->opt.x_precision);
@@ -107,6 +110,21 @@ int newton_setup(cox_handle *h)
     if (e != hipSuccess) {
         newton_free(h);
         return handle_hip_fail(h, e, "uploading group indices");
+    }
+    if (h->opt.x_precision == COX_FP8_E4M3) {
+        // e4m3 copy of X with power-of-two column scales (|x / s| <= 224)
+        if ((e = dalloc(&s.xlp, (size_t)p * ld)) != hipSuccess ||
+            (e = dalloc(&s.xscale, sizeof(float) * p)) != hipSuccess ||
+            (e = dalloc(&s.wscratch, sizeof(double) * 264)) != hipSuccess) {
+            newton_free(h);
+            return handle_hip_fail(h, e, "allocating the FP8 copy of X");
+        }
+        int rc = make_fp8_copy(h->d_x, ld, p, static_cast<uint8_t *>(s.xlp), s.xscale, s.zscale, h->stream);
+        if (rc == 0 && hipStreamSynchronize(h->stream) != hipSuccess) rc = -3;
+        if (rc != 0) {
+            newton_free(h);
+            return handle_fail(h, COX_EDEVICE, "building the FP8 copy of X");
+        }
     }
     if (h->opt.x_precision == COX_BF16) {
         // low-precision copy of X with power-of-two column scales (|x / s| <= 1)
@@ -172,10 +190,10 @@ int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
     A.diag2 = d_d2;
     A.scal = d_scal;
     A.flags = s.flags;
-    A.ztype = h->opt.x_precision == COX_BF16 ? kZBF16 : kZF64;
+    A.ztype = lowp(h->opt.x_precision) ? kZBF16 : kZF64;
     A.z = s.z;
     A.ldz = s.ldz;
-    A.zscale = h->opt.x_precision == COX_BF16 ? s.zscale : nullptr;
+    A.zscale = lowp(h->opt.x_precision) ? s.zscale : nullptr;
     A.want_xbar = want_xbar;
     A.scan_scratch = s.scan_scratch;
     A.scan_scratch_bytes = s.scan_scratch_bytes;
@@ -212,9 +230,13 @@ int newton_info(cox_handle *h)
     const double *b = nrow(s, ld, 6);
     int rc;
     (void)hipEventRecord(s.ev[2], h->stream);
-    if (h->opt.x_precision == COX_BF16) {
-        rc = syrk_bf16(static_cast<const uint16_t *>(s.xlp), ld, p, s.xscale, b, ld, kSplitsXBF16, s.syrk_part, 1.0,
-                       0, s.info, h->stream);
+    if (lowp(h->opt.x_precision)) {
+        if (h->opt.x_precision == COX_FP8_E4M3)
+            rc = syrk_fp8(static_cast<const uint8_t *>(s.xlp), ld, p, s.xscale, b, ld, kSplitsXFP8, s.syrk_part,
+                          s.wscratch, s.wscratch + 256, 1.0, 0, s.info, h->stream);
+        else
+            rc = syrk_bf16(static_cast<const uint16_t *>(s.xlp), ld, p, s.xscale, b, ld, kSplitsXBF16, s.syrk_part,
+                           1.0, 0, s.info, h->stream);
         if (rc == 0 && s.n_groups > 0)
             rc = syrk_bf16(static_cast<const uint16_t *>(s.z), s.ldz, p, s.zscale, nullptr, s.n_groups, kSplitsZBF16,
                            s.syrk_part, -1.0, 1, s.info, h->stream);
@@ -236,7 +258,7 @@ void newton_free(cox_handle *h)
     NewtonState &s = h->nt;
     void *ptrs[] = {s.gidx, s.rows, s.blockbuf, s.tile_carry, s.lasthead, s.agg_tiles, s.agg, s.carry,
                     s.colpart, s.vec, s.flags, s.status, s.free_col, s.z,
-                    s.zscale, s.xlp, s.xscale, s.syrk_part, s.info, s.scan_scratch};
+                    s.zscale, s.xlp, s.xscale, s.syrk_part, s.info, s.scan_scratch, s.wscratch};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t ev : s.ev)

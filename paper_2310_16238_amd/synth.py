@@ -229,3 +229,10 @@ def arrival_times(count: int, rate: float, seed: int = 3) -> np.ndarray:
     """Poisson arrivals at `rate` per second: cumulative sums of Exp(rate) gaps (seconds)."""
     rng = np.random.default_rng((seed, 1 << 20))
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def config_heavy(n: int = 10_000_000, p: int = 500, K: int = 500_000, seed: int = 4) -> CoxData:
+    """Student-t(3) columns scaled to unit variance, beta_true with round(0.1 p) nonzero
+    N(0, 1) entries at seeded positions (seed 4)."""
+    return make("t3", n, p, K, seed, beta_kind="sparse_count", beta_sd=1.0, beta_nonzero=0.1, gamma=0.0,
+                name=f"heavy-n{n}-p{p}-K{K}")

@@ -21,7 +21,14 @@ Tolerances:
   relative over a K range of k rows (the contraction splits N into 128 ranges
   and the groups into 64).  With u = 2^-8 and a margin for second-order terms,
       |gpu_ij - oracle_ij| <= (3.5 u + k 2^-24) r_ij;
-* fitted beta (FP64 or BF16 factor + FP64 refinement): max|gpu - oracle| /
+* information matrix with X in FP8 e4m3 (power-of-two column scales) and Z in
+  BF16: the first term's products are formed from operands a_rj = (x_rj/s_j)
+  sqrt(b_r)/S, each rounded twice to 4 significant bits (the stored x, then the
+  weighted value), so a product carries at most 4 such roundings: with
+  u8 = 2^-4 the bound is (4.5 u8 + k 2^-24) r_ij plus the BF16 Z term's 3.5 u;
+  values that fall below the e4m3 normal range (2^-6 after scaling) add an
+  absolute error bounded the same way because |a| <= 224 sets the scale;
+* fitted beta (FP64, BF16 or FP8 factor + FP64 refinement): max|gpu - oracle| /
   max|oracle| <= 1e-10, with the oracle's own Newton fit to 1e-14.
 """
 import math
@@ -37,6 +44,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 U_BF16 = 2.0 ** -8
+U_FP8 = 2.0 ** -4
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -141,7 +149,28 @@ def test_information_bf16_within_bound(name, make):
     assert float(np.median(err / r)) <= 0.1 * 3.5 * U_BF16
 
 
-@pytest.mark.parametrize("prec", [coxmi.COX_F64, coxmi.COX_BF16], ids=["f64", "bf16"])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_information_fp8_within_bound(name, make):
+    d = make()
+    beta = _beta_probe(d)
+    _say(f"evaluate_full FP8 {name} n={d.n} p={d.p}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE,
+                        x_precision=coxmi.COX_FP8_E4M3) as m:
+        obj, g, hd, info = m.evaluate_full(beta)
+    fe = _oracle_eval(d, beta)
+    _check_first_order(d, obj, g, hd, fe)
+    r = _scale(fe)
+    k = math.ceil(d.n / 128) + 16
+    lim = 4.5 * U_FP8 + 3.5 * U_BF16 + k * 2.0 ** -24
+    err = np.abs(info - fe.info)
+    worst = float(np.max(err / r))
+    _say(f"  max |err| / r = {worst:.3e} (bound {lim:.3e}), median {float(np.median(err / r)):.2e}")
+    assert np.all(err <= lim * r), worst
+    assert np.array_equal(info, info.T)
+    assert float(np.median(err / r)) <= 0.1 * lim
+
+
+@pytest.mark.parametrize("prec", [coxmi.COX_F64, coxmi.COX_BF16, coxmi.COX_FP8_E4M3], ids=["f64", "bf16", "fp8"])
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_newton_fit(name, make, prec):
     d = make()
@@ -246,3 +275,19 @@ def test_newton_beyond_the_resident_kernel():
     with pytest.raises(coxmi.CoxError) as ei:
         coxmi.cox_init(d.X, d.time, d.event, d.stratum)   # CCD mode cannot hold it
     assert ei.value.code == coxmi.COX_EUNSUPPORTED
+
+
+def test_newton_fp8_heavy_tailed():
+    """The heavy-tailed shape at reduced size: N = 2e5, P = 500 Student-t(3) columns, 50
+    nonzero coefficients, K = 1e4; FP8 information matrix + FP64 refinement."""
+    d = synth.config_heavy(n=200_000, p=500, K=10_000)
+    _say("newton fit FP8 heavy-tailed n=2e5 p=500 K=1e4")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE,
+                        x_precision=coxmi.COX_FP8_E4M3, tol=1e-13, max_iter=200) as m:
+        beta, info = m.fit()
+        prof = m.profile()
+    ref = orc.fit_newton(d.X, d.time, d.event, d.stratum, tol=1e-14)
+    err = _rel(beta, ref.beta)
+    _say(f"  iters={info['iters']} evals={info['coord_evals']} rel err {err:.3e} profile {prof}")
+    assert info["status"] == coxmi.COX_OK
+    assert err <= 1e-10
