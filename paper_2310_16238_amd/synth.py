@@ -74,12 +74,14 @@ def _design_ar1(rng, n, p, rho=0.5):
     return X
 
 
-def _design_t3(rng, n, p):
+def _design_t3(rng, n, p, progress=None):
     """iid Student-t(3) scaled to unit variance (variance of t3 is 3)."""
     X = np.empty((n, p), dtype=np.float64, order="F")
     s = 1.0 / math.sqrt(3.0)
     for j in range(p):
         X[:, j] = rng.standard_t(3, n) * s
+        if progress is not None:
+            progress(j + 1, p)
     return X
 
 
@@ -141,8 +143,9 @@ def _times(rng, eta, lam_row, tie_round):
 def make(design: str, n: int, p: int, K: int, seed: int, *, beta=None,
          beta_kind: str = "normal", beta_sd: float = 0.5, beta_nonzero: float = 1.0,
          intercept: bool = False, density: float = 0.05, tie_round: float = 0.0,
-         gamma: float = 0.0, name: str = "") -> CoxData:
-    """Draw one workload.  See the module docstring for the model and order."""
+         gamma: float = 0.0, name: str = "", progress=None) -> CoxData:
+    """Draw one workload.  See the module docstring for the model and order.
+    `progress(j, p)`, if given, is called after each column of the t3 design is drawn."""
     if n < 1 or p < 1 or K < 1 or K > n:
         raise ValueError("need n >= 1, p >= 1, 1 <= K <= n")
     rng = np.random.default_rng(seed)
@@ -151,7 +154,7 @@ def make(design: str, n: int, p: int, K: int, seed: int, *, beta=None,
     elif design == "ar1":
         X = _design_ar1(rng, n, p)
     elif design == "t3":
-        X = _design_t3(rng, n, p)
+        X = _design_t3(rng, n, p, progress)
     elif design == "binary":
         X = _design_binary(rng, n, p, density)
     elif design == "mixed":
@@ -231,8 +234,8 @@ def arrival_times(count: int, rate: float, seed: int = 3) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
 
 
-def config_heavy(n: int = 10_000_000, p: int = 500, K: int = 500_000, seed: int = 4) -> CoxData:
+def config_heavy(n: int = 10_000_000, p: int = 500, K: int = 500_000, seed: int = 4, progress=None) -> CoxData:
     """Student-t(3) columns scaled to unit variance, beta_true with round(0.1 p) nonzero
     N(0, 1) entries at seeded positions (seed 4)."""
     return make("t3", n, p, K, seed, beta_kind="sparse_count", beta_sd=1.0, beta_nonzero=0.1, gamma=0.0,
-                name=f"heavy-n{n}-p{p}-K{K}")
+                name=f"heavy-n{n}-p{p}-K{K}", progress=progress)
