@@ -416,11 +416,14 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_kernel(const uint
     }
 }
 
-// LDS-staged variant for p <= 256 (at most 8 row tiles): per 64-row K chunk
+// LDS-staged variant for p <= 256 (at most 8 row tiles): per 128-row K chunk
 // the workgroup stages all row tiles of u once (and once more multiplied by
 // the weights, rounded to BF16), then every wave runs its tile pairs' MFMAs
-// from LDS.  Same partial layout as syrk_bf16_kernel.
-constexpr int kLdsKC = 64, kLdsStride = 72, kLdsMaxTiles = 8;
+// from LDS.  The next chunk's global loads are issued into registers before
+// the current chunk's MFMAs.  Same partial layout as syrk_bf16_kernel.
+constexpr int kLdsKC = 128, kLdsStride = kLdsKC + 8, kLdsMaxTiles = 8;
+constexpr int kLdsPieces = kLdsKC / 8;                                  // 16-byte pieces per row
+constexpr int kLdsPerThread = kLdsMaxTiles * kMT * kLdsPieces / (64 * kSyrkBfWaves);   // 16
 
 template <bool WEIGHT>
 __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_lds_kernel(const uint16_t *u, int64_t ldu, int p,
@@ -449,23 +452,42 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_lds_kernel(const 
         for (int i = 0; i < 16; ++i) acc[q][i] = 0.0f;
     }
     const int rsub = lane & 31, ksub = 8 * (lane >> 5);
-    for (int64_t kc = k0; kc < k1; kc += kLdsKC) {
-        if (WEIGHT && threadIdx.x < kLdsKC) cw[threadIdx.x] = (float)c[kc + threadIdx.x];
-        __syncthreads();
-        // stage rows x 64 k: 16-byte pieces, 8 per row
-        for (int e = threadIdx.x; e < rows * 8; e += 64 * kSyrkBfWaves) {
-            const int r = e >> 3, piece = e & 7;
-            u32x4v v = {0u, 0u, 0u, 0u};
-            if (r < p) v = *reinterpret_cast<const u32x4v *>(u + (int64_t)r * ldu + kc + 8 * piece);
-            *reinterpret_cast<u32x4v *>(plain + r * kLdsStride + 8 * piece) = v;
-            if (WEIGHT) {
-                bf16x8 x = __builtin_bit_cast(bf16x8, v), y;
+    const int npieces = rows * kLdsPieces;
+    // prefetch registers: this thread's pieces e = tid + 256 m
+    u32x4v reg[kLdsPerThread];
+    float creg = 0.0f;
+    auto load_chunk = [&](int64_t kc) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) y[i] = (__bf16)((float)x[i] * cw[8 * piece + i]);
-                *reinterpret_cast<u32x4v *>(wtd + r * kLdsStride + 8 * piece) = __builtin_bit_cast(u32x4v, y);
+        for (int m = 0; m < kLdsPerThread; ++m) {
+            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            const int r = e / kLdsPieces, piece = e % kLdsPieces;
+            u32x4v v = {0u, 0u, 0u, 0u};
+            if (e < npieces && r < p) v = *reinterpret_cast<const u32x4v *>(u + (int64_t)r * ldu + kc + 8 * piece);
+            reg[m] = v;
+        }
+        if (WEIGHT && threadIdx.x < kLdsKC) creg = (float)c[kc + threadIdx.x];
+    };
+    if (k0 < k1) load_chunk(k0);
+    for (int64_t kc = k0; kc < k1; kc += kLdsKC) {
+        if (WEIGHT && threadIdx.x < kLdsKC) cw[threadIdx.x] = creg;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kLdsPerThread; ++m) {
+            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            if (e < npieces) {
+                const int r = e / kLdsPieces, piece = e % kLdsPieces;
+                *reinterpret_cast<u32x4v *>(plain + r * kLdsStride + 8 * piece) = reg[m];
+                if (WEIGHT) {
+                    const bf16x8 x = __builtin_bit_cast(bf16x8, reg[m]);
+                    bf16x8 y;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) y[i] = (__bf16)((float)x[i] * cw[8 * piece + i]);
+                    *reinterpret_cast<u32x4v *>(wtd + r * kLdsStride + 8 * piece) = __builtin_bit_cast(u32x4v, y);
+                }
             }
         }
         __syncthreads();
+        if (kc + kLdsKC < k1) load_chunk(kc + kLdsKC);   // in flight during the MFMAs below
         const uint16_t *asrc = WEIGHT ? wtd : plain;
 #pragma unroll
         for (int sub = 0; sub < kLdsKC / 16; ++sub) {
@@ -481,6 +503,7 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_lds_kernel(const 
                 }
             }
         }
+        __syncthreads();   // the next chunk rewrites the LDS tiles
     }
 #pragma unroll
     for (int q = 0; q < kTilesPerWave; ++q) {
@@ -625,35 +648,42 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_fp8_lds_kernel(const u
 }
 
 // C (+)= sign * scale_i * scale_j * sum over ranges of the partial tiles (FP64).
+// Grid (npairs, 16): each workgroup takes 64 entries of one tile; its four
+// waves sum the splits q = w, w + 4, ... in order, then the four sums are
+// added in wave order (a fixed order, so results do not vary run to run).
 __global__ __launch_bounds__(256) void syrk_bf16_reduce_kernel(const float *part, int p, int S, const float *scale,
                                                                double sign, int accumulate, double *C,
                                                                const double *wsc)
 {
+    __shared__ double red[4][64];
     const int nt = (p + kMT - 1) / kMT;
     const int npairs = nt * (nt + 1) / 2;
     const int pair = blockIdx.x;
     int ti, tj;
     tile_pair(pair, nt, ti, tj);
-    for (int e = threadIdx.x; e < kMT * kMT; e += 256) {
-        const int a = e / kMT, bb = e % kMT;
-        const int i = ti * kMT + a, j = tj * kMT + bb;
-        if (i >= p || j >= p) continue;
-        if (ti == tj && j < i) continue;
-        double s = 0.0;
-        for (int q = 0; q < S; ++q) s += (double)part[((int64_t)q * npairs + pair) * (kMT * kMT) + e];
-        s *= sign * (double)scale[i] * (double)scale[j];
-        if (wsc) s *= wsc[0] * wsc[0];
-        if (accumulate) {
-            C[(int64_t)i * p + j] += s;
-            if (i != j) C[(int64_t)j * p + i] += s;
-        } else {
-            C[(int64_t)i * p + j] = s;
-            if (i != j) C[(int64_t)j * p + i] = s;
-        }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = blockIdx.y * 64 + lane;
+    double s = 0.0;
+    for (int q = w; q < S; q += 4) s += (double)part[((int64_t)q * npairs + pair) * (kMT * kMT) + e];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w != 0) return;
+    s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    const int a = e / kMT, bb = e % kMT;
+    const int i = ti * kMT + a, j = tj * kMT + bb;
+    if (i >= p || j >= p) return;
+    if (ti == tj && j < i) return;
+    s *= sign * (double)scale[i] * (double)scale[j];
+    if (wsc) s *= wsc[0] * wsc[0];
+    if (accumulate) {
+        C[(int64_t)i * p + j] += s;
+        if (i != j) C[(int64_t)j * p + i] += s;
+    } else {
+        C[(int64_t)i * p + j] = s;
+        if (i != j) C[(int64_t)j * p + i] = s;
     }
 }
 
-// Per column: the power-of-two scale s_j >= max |x_j| (1 for a zero column).
 // xscale_j = the power of two s with max|x_j| / s <= xmax (1 for a zero column);
 // zscale_j = the power of two >= max|x_j| (the BF16 scale of xbar_j).
 __global__ __launch_bounds__(256) void colscale_kernel(const double *x, int64_t ld, float xmax, float *xscale,
@@ -753,7 +783,8 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
         kchunk = (kchunk + 15) / 16 * 16;
         syrk_bf16_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, 0, stream>>>(u, ldu, p, c, K16, kchunk, fpart);
     }
-    syrk_bf16_reduce_kernel<<<npairs, 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C, nullptr);
+    syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C,
+                                                                 nullptr);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -781,7 +812,7 @@ int syrk_fp8(const uint8_t *u, int64_t ldu, int p, const float *scale, const dou
     float *fpart = reinterpret_cast<float *>(part);
     syrk_fp8_lds_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, wsc, K64, kchunk,
                                                                                    fpart);
-    syrk_bf16_reduce_kernel<<<npairs, 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C, wsc);
+    syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C, wsc);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -789,10 +820,10 @@ int chol_solve(double *A, int p, const double *g, const uint8_t *free_col, int f
                hipStream_t stream)
 {
     if (p <= kCholMaxP) {
-        const size_t lds = sizeof(double) * ((size_t)p * kCholNB + p);
+        const size_t lds = sizeof(double) * ((size_t)p * kCholNB + 2 * (size_t)p);
         static bool attr = false;
         if (!attr) {
-            const size_t most = sizeof(double) * ((size_t)kCholMaxP * kCholNB + kCholMaxP);
+            const size_t most = sizeof(double) * ((size_t)kCholMaxP * kCholNB + 2 * (size_t)kCholMaxP);
             if (hipFuncSetAttribute(reinterpret_cast<const void *>(&chol_blocked_kernel),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
                 return -3;

@@ -17,7 +17,7 @@ struct NewtonState {
     int ntiles = 0, n_agg = 0;
     int64_t n_groups = 0, ldz = 0;
     int32_t *gidx = nullptr;       // [ld]
-    double *rows = nullptr;        // 7 x [ld]: eta, w, s0, h, lam, a, b
+    double *rows = nullptr;        // 8 x [ld]: eta, w, s0, h, lam, a, b, zq
     double *blockbuf = nullptr;    // [max_blocks]
     uint8_t *tile_carry = nullptr; // [ntiles]
     int32_t *lasthead = nullptr;   // [ntiles]

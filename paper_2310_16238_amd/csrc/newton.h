@@ -23,7 +23,7 @@ struct FullEvalArgs {
     int p = 0;
     int max_blocks = 0;               // capacity of blockbuf
     double *eta = nullptr, *w = nullptr, *s0 = nullptr, *h = nullptr, *lam = nullptr;  // [ld] each
-    double *a = nullptr, *b = nullptr;                                                // [ld] each
+    double *a = nullptr, *b = nullptr, *zq = nullptr;                                 // [ld] each
     double *blockbuf = nullptr;       // [max_blocks]
     // column pass: tiles of `tile` rows (ld = ntiles * tile)
     int64_t tile = 0;
@@ -65,7 +65,7 @@ size_t syrk_partial_bytes(int p, int splits);
 size_t syrk_bf16_partial_bytes(int p, int splits);
 
 // K splits of the contractions: X' diag(b) X and Z'Z, FP64 and BF16.
-constexpr int kSplitsXF64 = 128, kSplitsZF64 = 64, kSplitsXBF16 = 256, kSplitsZBF16 = 64;
+constexpr int kSplitsXF64 = 128, kSplitsZF64 = 64, kSplitsXBF16 = 256, kSplitsZBF16 = 256;
 // C (+)= sign * sum_k c_k u_k u_k' in FP64 (u: [p][ldu]; c NULL means 1).
 int syrk_f64(const double *u, int64_t ldu, int p, const double *c, int64_t K, int splits, double *part,
              double sign, int accumulate, double *C, hipStream_t stream);

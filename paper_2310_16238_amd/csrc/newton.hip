@@ -93,8 +93,10 @@ __global__ __launch_bounds__(kRowBlock) void weight_kernel(const double *eta, co
 
 // At event-group ends: h = d / S0 and the per-block objective part
 // d (log S0 + c); at event rows: -eta.  Range check of S0 as in the CCD kernel.
+// also zq = (d/S0) / sqrt(d) at group ends: xbar_j sqrt(d) = S1_j zq and
+// d xbar_j^2 = (S1_j zq)^2, so the column pass needs no division per column
 __global__ __launch_bounds__(kRowBlock) void hazard_kernel(const double *s0, const double *eta, const uint32_t *meta,
-                                                           const double *scal, int64_t ld, double *h,
+                                                           const double *scal, int64_t ld, double *h, double *zq,
                                                            double *blockobj, unsigned *flags)
 {
     __shared__ double red[kRowBlock / kWave];
@@ -103,15 +105,17 @@ __global__ __launch_bounds__(kRowBlock) void hazard_kernel(const double *s0, con
     if (r < ld) {
         const uint32_t m = meta[r];
         const uint32_t d = m & kCountMask;
-        double hv = 0.0;
+        double hv = 0.0, qv = 0.0;
         if (d != 0u) {
             const double s = s0[r];
             if (!(s >= 1e-300) || !(s <= 1e300)) atomicOr(flags, 1u);
             hv = (double)d / s;
+            qv = hv / sqrt((double)d);
             obj += (double)d * (log(s) + scal[0]);
         }
         if (m & kEventBit) obj -= eta[r];
         h[r] = hv;
+        zq[r] = qv;
     }
     obj = block_sum(obj, red);
     if (threadIdx.x == 0) blockobj[blockIdx.x] = obj;
@@ -194,34 +198,53 @@ __global__ __launch_bounds__(256) void colcarry_kernel(int p, int ntiles, const 
     }
 }
 
+// kColBlock columns per wave: the row vectors (w, b, zq, row words, group
+// indices) are loaded once per chunk for all of them.
+constexpr int kColBlock = 4;
+
 template <typename ZT, bool XBAR>
 __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double *x, int64_t ld, int p, int64_t tile,
-                                                                    int ntiles, const double *w, const double *s0,
-                                                                    const double *a, const double *b,
-                                                                    const uint32_t *meta, const int32_t *gidx,
-                                                                    const uint8_t *tile_carry, const double *carry,
-                                                                    int64_t ldz, const float *zscale, ZT *z,
-                                                                    double *part)
+                                                                    int ntiles, const double *w, const double *zq,
+                                                                    const double *b, const uint32_t *meta,
+                                                                    const int32_t *gidx, const uint8_t *tile_carry,
+                                                                    const double *carry, int64_t ldz,
+                                                                    const float *zscale, ZT *z, double *part)
 {
+    constexpr int CB = kColBlock;
     const int lane = threadIdx.x & (kWave - 1);
-    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kColWaves + threadIdx.x / kWave);
-    if (item >= ntiles * p) return;   // whole wave; no workgroup barrier below
-    const int t = item / p, j = item % p;
-    const double *xj = x + (int64_t)j * ld;
+    // XCD-aware order: workgroups are dealt to the 8 XCDs in turn, so workgroup
+    // wg runs on XCD wg % 8; every column group of a tile goes to one XCD, whose
+    // L2 then holds that tile's row vectors for all of its columns
+    const int per_wg = kColWaves * CB;
+    const int cgroups = (p + per_wg - 1) / per_wg;
+    const int wg = blockIdx.x, xcd = wg & 7, k = wg >> 3;
+    const int t = (k / cgroups) * 8 + xcd;
+    const int j0 = __builtin_amdgcn_readfirstlane((k % cgroups) * per_wg + (int)(threadIdx.x / kWave) * CB);
+    if (t >= ntiles || j0 >= p) return;   // whole wave; no workgroup barrier below
     const int64_t r_begin = (int64_t)t * tile, r_end = r_begin + tile;
-    double g = 0.0, d1 = 0.0, d2 = 0.0;
-    SegVal<1> run_carry = seg_identity<1>();
-    if (XBAR && tile_carry[t]) run_carry.v[0] = carry[(int64_t)t * p + j];
-    const float zs = zscale ? 1.0f / zscale[j] : 1.0f;
+    const double *xc[CB];
+    bool live[CB];
+    float zs[CB];
+    double g[CB], d1[CB], d2[CB];
+    SegVal<1> run_carry[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        const int j = j0 + c;
+        live[c] = j < p;
+        xc[c] = x + (int64_t)(live[c] ? j : j0) * ld;
+        zs[c] = (zscale && live[c]) ? 1.0f / zscale[j] : 1.0f;
+        g[c] = d1[c] = d2[c] = 0.0;
+        run_carry[c] = seg_identity<1>();
+        if (XBAR && live[c] && tile_carry[t]) run_carry[c].v[0] = carry[(int64_t)t * p + j];
+    }
     for (int64_t base = r_begin; base < r_end; base += kColChunk) {
-        const int64_t r0 = base + (int64_t)lane * kColIpt;
-        // 4 consecutive rows per lane: 16-byte loads (r0 is a multiple of 4)
-        double xv[kColIpt], wv[kColIpt], av[kColIpt], bv[kColIpt];
+        const int64_t r0 = base + (int64_t)lane * kColIpt;   // 4 consecutive rows per lane: 16-byte loads
+        double xv[CB][kColIpt], bv[kColIpt], wv[kColIpt], qv[kColIpt];
         uint32_t m[kColIpt];
-        load4(xj + r0, xv);
-        load4(a + r0, av);
+        int32_t gi[kColIpt];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) load4(xc[c] + r0, xv[c]);
         load4(b + r0, bv);
-        if (XBAR) load4(w + r0, wv);
         {
             const uint4 mm = *reinterpret_cast<const uint4 *>(meta + r0);
             m[0] = mm.x;
@@ -229,66 +252,102 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
             m[2] = mm.z;
             m[3] = mm.w;
         }
+        if (XBAR) {
+            load4(w + r0, wv);
+            load4(zq + r0, qv);
+            const int4 gg = *reinterpret_cast<const int4 *>(gidx + r0);
+            gi[0] = gg.x;
+            gi[1] = gg.y;
+            gi[2] = gg.z;
+            gi[3] = gg.w;
+        }
 #pragma unroll
-        for (int i = 0; i < kColIpt; ++i) {
-            g = fma(xv[i], av[i], g);
-            d1 = fma(xv[i] * xv[i], bv[i], d1);
+        for (int c = 0; c < CB; ++c) {
+#pragma unroll
+            for (int i = 0; i < kColIpt; ++i) {
+                const double av = bv[i] - ((m[i] & kEventBit) ? 1.0 : 0.0);   // w Lambda - delta
+                g[c] = fma(xv[c][i], av, g[c]);
+                d1[c] = fma(xv[c][i] * xv[c][i], bv[i], d1[c]);
+            }
         }
         if (XBAR) {
-            SegVal<1> e[kColIpt];
-            SegVal<1> tot = seg_identity<1>();
 #pragma unroll
-            for (int i = 0; i < kColIpt; ++i) {
-                e[i].f = m[i] >> 31;
-                e[i].v[0] = wv[i] * xv[i];
-                tot = seg_combine(tot, e[i]);
-            }
-            const SegVal<1> inc = wave_inclusive_scan(tot);
-            SegVal<1> run = seg_combine(run_carry, wave_shift_right(inc));
+            for (int c = 0; c < CB; ++c) {
+                SegVal<1> e[kColIpt];
+                SegVal<1> tot = seg_identity<1>();
 #pragma unroll
-            for (int i = 0; i < kColIpt; ++i) {
-                run = seg_combine(run, e[i]);
-                const uint32_t d = m[i] & kCountMask;
-                if (d != 0u) {
-                    const int64_t r = r0 + i;
-                    const double xb = run.v[0] / s0[r];
-                    d2 = fma((double)d * xb, xb, d2);
-                    store_z<ZT>(&z[(int64_t)j * ldz + gidx[r]], sqrt((double)d) * xb, zs);
+                for (int i = 0; i < kColIpt; ++i) {
+                    e[i].f = m[i] >> 31;
+                    e[i].v[0] = wv[i] * xv[c][i];
+                    tot = seg_combine(tot, e[i]);
                 }
+                const SegVal<1> inc = wave_inclusive_scan(tot);
+                SegVal<1> run = seg_combine(run_carry[c], wave_shift_right(inc));
+#pragma unroll
+                for (int i = 0; i < kColIpt; ++i) {
+                    run = seg_combine(run, e[i]);
+                    if ((m[i] & kCountMask) && live[c]) {
+                        const double zv = run.v[0] * qv[i];   // sqrt(d) xbar
+                        d2[c] = fma(zv, zv, d2[c]);
+                        store_z<ZT>(&z[(int64_t)(j0 + c) * ldz + gi[i]], zv, zs[c]);
+                    }
+                }
+                run_carry[c] = seg_combine(run_carry[c], lane63_seg(inc));
             }
-            run_carry = seg_combine(run_carry, lane63_seg(inc));
         }
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-        g += __shfl_xor(g, off, kWave);
-        d1 += __shfl_xor(d1, off, kWave);
-        d2 += __shfl_xor(d2, off, kWave);
-    }
-    if (lane == 0) {
-        double *o = part + ((int64_t)t * p + j) * 3;
-        o[0] = g;
-        o[1] = d1;
-        o[2] = d2;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        double gc = g[c], s1 = d1[c], s2 = d2[c];
+        for (int off = 32; off >= 1; off >>= 1) {
+            gc += __shfl_xor(gc, off, kWave);
+            s1 += __shfl_xor(s1, off, kWave);
+            s2 += __shfl_xor(s2, off, kWave);
+        }
+        if (lane == 0 && live[c]) {
+            double *o = part + ((int64_t)t * p + j0 + c) * 3;
+            o[0] = gc;
+            o[1] = s1;
+            o[2] = s2;
+        }
     }
 }
 
-// Fixed-order sums over tiles: grad[j], diag1[j], diag2[j]; workgroup p sums
-// the objective parts.
+// Fixed-order sums over tiles: grad[j], diag1[j], diag2[j] (thread k sums
+// tiles k, k + 256, ... in order, then a fixed-order tree over the threads);
+// workgroup p sums the objective parts.
+__device__ __forceinline__ double tree_sum_256(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
 __global__ __launch_bounds__(kRowBlock) void colreduce_kernel(const double *part, int p, int ntiles, double *grad,
                                                               double *diag1, double *diag2, const double *blockobj,
                                                               int nb, double *scal)
 {
     __shared__ double red[kRowBlock / kWave];
+    __shared__ double tree[256];
     const int j = blockIdx.x;
     if (j < p) {
+        double sg = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int t = threadIdx.x; t < ntiles; t += kRowBlock) {
+            const double *o = part + ((int64_t)t * p + j) * 3;
+            sg += o[0];
+            s1 += o[1];
+            s2 += o[2];
+        }
+        sg = tree_sum_256(sg, tree);
+        s1 = tree_sum_256(s1, tree);
+        s2 = tree_sum_256(s2, tree);
         if (threadIdx.x == 0) {
-            double sg = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int t = 0; t < ntiles; ++t) {
-                const double *o = part + ((int64_t)t * p + j) * 3;
-                sg += o[0];
-                s1 += o[1];
-                s2 += o[2];
-            }
             grad[j] = sg;
             diag1[j] = s1;
             diag2[j] = s2;
@@ -440,7 +499,7 @@ int full_eval_launch(const FullEvalArgs &A, hipStream_t stream)
     weight_kernel<<<nb, kRowBlock, 0, stream>>>(A.eta, A.scal, ld, A.w);
     int rc = rowscan(A.w, A.meta, A.s0, ld, A.tile, false, A.scan_scratch, A.scan_scratch_bytes, stream);
     if (rc) return rc;
-    hazard_kernel<<<nb, kRowBlock, 0, stream>>>(A.s0, A.eta, A.meta, A.scal, ld, A.h, A.blockbuf, A.flags);
+    hazard_kernel<<<nb, kRowBlock, 0, stream>>>(A.s0, A.eta, A.meta, A.scal, ld, A.h, A.zq, A.blockbuf, A.flags);
     rc = rowscan(A.h, A.meta, A.lam, ld, A.tile, true, A.scan_scratch, A.scan_scratch_bytes, stream);
     if (rc) return rc;
     rowweight_kernel<<<nb, kRowBlock, 0, stream>>>(A.w, A.lam, A.meta, ld, A.a, A.b);
@@ -450,11 +509,10 @@ int full_eval_launch(const FullEvalArgs &A, hipStream_t stream)
         colcarry_kernel<<<(A.p + 255) / 256, 256, 0, stream>>>(A.p, A.ntiles, A.tile_carry, A.lasthead, A.agg,
                                                                A.carry);
     }
-    const int items = A.ntiles * A.p;
-    const int grid = (items + kColWaves - 1) / kColWaves;
+    const int grid = 8 * ((A.ntiles + 7) / 8) * ((A.p + kColWaves * kColBlock - 1) / (kColWaves * kColBlock));
 #define COXMI_COLPASS(ZT, XB)                                                                                  \
     colpass_kernel<ZT, XB><<<grid, kWave * kColWaves, 0, stream>>>(                                            \
-        A.x, ld, A.p, A.tile, A.ntiles, A.w, A.s0, A.a, A.b, A.meta, A.gidx, A.tile_carry, A.carry, A.ldz,     \
+        A.x, ld, A.p, A.tile, A.ntiles, A.w, A.zq, A.b, A.meta, A.gidx, A.tile_carry, A.carry, A.ldz,          \
         A.zscale, static_cast<ZT *>(A.z), A.colpart)
     if (!A.want_xbar) COXMI_COLPASS(double, false);
     else if (A.ztype == kZF64) COXMI_COLPASS(double, true);

@@ -49,7 +49,7 @@ int newton_setup(cox_handle *h)
         head[h->pos[i]] = (h->meta[i] & kHeadBit) ? 1 : 0;
     }
     s.n_groups = G;
-    s.ldz = std::max<int64_t>(64, (G + 63) / 64 * 64);
+    s.ldz = std::max<int64_t>(128, (G + 127) / 128 * 128);   // K chunks of the contraction are 128 rows
     s.max_blocks = (int)((ld + 255) / 256) + 1;
     // column-pass tiles: the persistent kernel's tiles (ld = grid * tile)
     s.tile = ld / h->shape.grid;
@@ -75,7 +75,7 @@ int newton_setup(cox_handle *h)
     const size_t zb = ztype_bytes(h->opt.x_precision);
     hipError_t e;
     if ((e = dalloc(&s.gidx, sizeof(int32_t) * ld)) != hipSuccess ||
-        (e = dalloc(&s.rows, sizeof(double) * 7 * ld)) != hipSuccess ||
+        (e = dalloc(&s.rows, sizeof(double) * 8 * ld)) != hipSuccess ||
         (e = dalloc(&s.blockbuf, sizeof(double) * s.max_blocks)) != hipSuccess ||
         (e = dalloc(&s.tile_carry, (size_t)s.ntiles)) != hipSuccess ||
         (e = dalloc(&s.lasthead, sizeof(int32_t) * s.ntiles)) != hipSuccess ||
@@ -173,6 +173,7 @@ int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
     A.s0 = nrow(s, ld, 2);
     A.h = nrow(s, ld, 3);
     A.lam = nrow(s, ld, 4);
+    A.zq = nrow(s, ld, 7);
     A.a = nrow(s, ld, 5);
     A.b = nrow(s, ld, 6);
     A.blockbuf = s.blockbuf;

@@ -53,7 +53,7 @@ struct FitDesc {
     float *xf;              // [p][ld] FP32 copy for the contraction
     const uint32_t *meta;   // [ld] row words (padding rows: head | pad)
     const int32_t *gidx;    // [ld] event-group index at group ends, else -1
-    double *eta, *w, *s0, *hz, *a, *b;   // [ld] row vectors
+    double *eta, *w, *zq, *hz, *a, *b;   // [ld] row vectors (zq = (d/S0)/sqrt(d) at group ends)
     float *z;               // [p][ldz] sqrt(d_g) xbar_g
     double *beta, *prev, *grad, *diag1, *diag2;   // [p]
     uint8_t *free_col;      // [p]

@@ -3,7 +3,8 @@
 // One Newton iteration of every resident fit is five launches:
 //   eta   (fit, 256-row tile)  X beta in FP64 and the tile's max of X beta
 //   rows  (fit)                w = exp(X beta - c), forward segmented scan of w
-//                              (S0), d/S0 at group ends and the objective, reverse
+//                              (S0), d/S0 and (d/S0)/sqrt(d) at group ends and the
+//                              objective, reverse
 //                              segmented scan of d/S0 (Lambda), a = w Lambda - delta,
 //                              b = w Lambda
 //   cols  (fit, column)        one wave: forward segmented scan of w x_j (S1),
@@ -149,16 +150,17 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, 
                 const uint32_t m = F.meta[r];
                 const uint32_t d = m & kCountMask;
                 F.w[r] = e[i].v[0];
-                F.s0[r] = run.v[0];
-                double hv = 0.0;
+                double hv = 0.0, qv = 0.0;
                 if (d != 0u) {
                     const double s = run.v[0];
                     if (!(s >= 1e-300) || !(s <= 1e300)) bad = 1u;
                     hv = (double)d / s;
+                    qv = hv / sqrt((double)d);
                     obj += (double)d * (log(s) + c);
                 }
                 if (m & kEventBit) obj -= F.eta[r];
                 F.hz[r] = hv;
+                F.zq[r] = qv;
             }
         }
         carry = seg_combine(carry, btot);
@@ -255,12 +257,11 @@ __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *
 #pragma unroll
         for (int i = 0; i < kColIpt; ++i) {
             run = seg_combine(run, e[i]);
-            const uint32_t d = m[i] & kCountMask;
-            if (d != 0u) {
+            if (m[i] & kCountMask) {
                 const int64_t r = r0 + i;
-                const double xb = run.v[0] / F.s0[r];
-                d2 = fma((double)d * xb, xb, d2);
-                zj[F.gidx[r]] = (float)(sqrt((double)d) * xb);
+                const double zv = run.v[0] * F.zq[r];   // sqrt(d) xbar
+                d2 = fma(zv, zv, d2);
+                zj[F.gidx[r]] = (float)zv;
             }
         }
         carry = seg_combine(carry, lane63_seg(inc));

@@ -347,7 +347,7 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off, int slot)
     double *rows = reinterpret_cast<double *>(B + L.rows);
     F.eta = rows;
     F.w = rows + L.ld;
-    F.s0 = rows + 2 * L.ld;
+    F.zq = rows + 2 * L.ld;
     F.hz = rows + 3 * L.ld;
     F.a = rows + 4 * L.ld;
     F.b = rows + 5 * L.ld;
