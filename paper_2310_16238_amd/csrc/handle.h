@@ -17,12 +17,12 @@ struct NewtonState {
     int ntiles = 0, n_agg = 0;
     int64_t n_groups = 0, ldz = 0;
     int32_t *gidx = nullptr;       // [ld]
-    double *rows = nullptr;        // 8 x [ld]: eta, w, s0, h, lam, a, b, zq
+    double *rows = nullptr;        // 9 x [ld]: eta, u, s0', h', R, alpha, b, zq, m
     double *blockbuf = nullptr;    // [max_blocks]
     uint8_t *tile_carry = nullptr; // [ntiles]
     int32_t *lasthead = nullptr;   // [ntiles]
     int32_t *agg_tiles = nullptr;  // [n_agg]
-    double *agg = nullptr;         // [ntiles][p]
+    double *agg = nullptr;         // [ntiles][p][2]
     double *carry = nullptr;       // [ntiles][p]
     double *colpart = nullptr;     // [ntiles][p][3]
     double *vec = nullptr;         // beta, grad, diag1, diag2, dx (p each), scal (8)

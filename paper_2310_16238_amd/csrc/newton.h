@@ -22,8 +22,11 @@ struct FullEvalArgs {
     int64_t ld = 0;
     int p = 0;
     int max_blocks = 0;               // capacity of blockbuf
-    double *eta = nullptr, *w = nullptr, *s0 = nullptr, *h = nullptr, *lam = nullptr;  // [ld] each
-    double *a = nullptr, *b = nullptr, *zq = nullptr;                                 // [ld] each
+    // row vectors [ld]: X beta, its running maximum m within the stratum, alpha and
+    // u = exp(eta - m) (see affscan.hpp), S0' = S0 exp(-m), h' = d / S0', the reverse
+    // recurrence R (w Lambda = u R), b = w Lambda, zq = h' / sqrt(d)
+    double *eta = nullptr, *m = nullptr, *alpha = nullptr, *w = nullptr, *s0 = nullptr, *h = nullptr;
+    double *lam = nullptr, *b = nullptr, *zq = nullptr;
     double *blockbuf = nullptr;       // [max_blocks]
     // column pass: tiles of `tile` rows (ld = ntiles * tile)
     int64_t tile = 0;
@@ -32,7 +35,7 @@ struct FullEvalArgs {
     const int32_t *lasthead = nullptr;     // [ntiles] row of the tile's last stratum head, -1 if none
     const int32_t *agg_tiles = nullptr;    // [n_agg] tiles whose successor needs a carry
     int n_agg = 0;
-    double *agg = nullptr;                 // [ntiles][p]
+    double *agg = nullptr;                 // [ntiles][p][2]: map S -> A S + B of the tile's tail rows
     double *carry = nullptr;               // [ntiles][p]
     double *colpart = nullptr;             // [ntiles][p][3]
     double *grad = nullptr, *diag1 = nullptr, *diag2 = nullptr;   // [p] each

@@ -22,6 +22,7 @@
 
 #include "internal.h"
 #include "newton.h"
+#include "affscan.hpp"
 #include "segscan.hpp"
 
 namespace coxmi {
@@ -54,66 +55,57 @@ __device__ __forceinline__ double block_max(double v, double *red)
     return s;
 }
 
-// eta = X beta over all ld rows; per-block max of eta over real rows.
+// eta = X beta over all ld rows.
 __global__ __launch_bounds__(kRowBlock) void eta_kernel(const double *x, int64_t ld, int p, const double *beta,
-                                                        const uint32_t *meta, double *eta, double *blockmax)
+                                                        double *eta)
 {
-    __shared__ double red[kRowBlock / kWave];
     const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
-    double e = 0.0, mx = -INFINITY;
     if (r < ld) {
+        double e = 0.0;
         for (int j = 0; j < p; ++j) {
             const double bj = beta[j];
             if (bj != 0.0) e = fma(x[(int64_t)j * ld + r], bj, e);
         }
         eta[r] = e;
-        if (!(meta[r] & kPadBit)) mx = e;
     }
-    mx = block_max(mx, red);
-    if (threadIdx.x == 0) blockmax[blockIdx.x] = mx;
 }
 
-// Single workgroup: scal[0] = max of blockmax (the shift c), fixed order.
-__global__ __launch_bounds__(kRowBlock) void max_kernel(const double *blockmax, int nb, double *scal)
-{
-    __shared__ double red[kRowBlock / kWave];
-    double mx = -INFINITY;
-    for (int i = threadIdx.x; i < nb; i += kRowBlock) mx = fmax(mx, blockmax[i]);
-    mx = block_max(mx, red);
-    if (threadIdx.x == 0) scal[0] = mx;
-}
-
-// w = exp(eta - c)
-__global__ __launch_bounds__(kRowBlock) void weight_kernel(const double *eta, const double *scal, int64_t ld,
-                                                           double *w)
+// With m the running maximum of eta within the stratum: alpha_r =
+// exp(m_{r-1} - m_r) (1 at a head) and u_r = exp(eta_r - m_r), both in (0, 1].
+__global__ __launch_bounds__(kRowBlock) void prep_kernel(const double *eta, const double *m, const uint32_t *meta,
+                                                         int64_t ld, double *alpha, double *u)
 {
     const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
-    if (r < ld) w[r] = exp(eta[r] - scal[0]);
+    if (r < ld) {
+        const double mr = m[r];
+        alpha[r] = (meta[r] & kHeadBit) ? 1.0 : exp(m[r - 1] - mr);
+        u[r] = exp(eta[r] - mr);
+    }
 }
 
-// At event-group ends: h = d / S0 and the per-block objective part
-// d (log S0 + c); at event rows: -eta.  Range check of S0 as in the CCD kernel.
-// also zq = (d/S0) / sqrt(d) at group ends: xbar_j sqrt(d) = S1_j zq and
-// d xbar_j^2 = (S1_j zq)^2, so the column pass needs no division per column
-__global__ __launch_bounds__(kRowBlock) void hazard_kernel(const double *s0, const double *eta, const uint32_t *meta,
-                                                           const double *scal, int64_t ld, double *h, double *zq,
+// At event-group ends, with S0' = S0 exp(-m) in [1, n]: h' = d / S0', its
+// objective part d (log S0' + m), and zq = h' / sqrt(d) (so that
+// sqrt(d) xbar_j = S1'_j zq and d xbar_j^2 = (S1'_j zq)^2: no division per
+// column); -eta at event rows.  A non-finite S0' (non-finite X beta) is flagged.
+__global__ __launch_bounds__(kRowBlock) void hazard_kernel(const double *s0, const double *eta, const double *m,
+                                                           const uint32_t *meta, int64_t ld, double *h, double *zq,
                                                            double *blockobj, unsigned *flags)
 {
     __shared__ double red[kRowBlock / kWave];
     const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
     double obj = 0.0;
     if (r < ld) {
-        const uint32_t m = meta[r];
-        const uint32_t d = m & kCountMask;
+        const uint32_t mw = meta[r];
+        const uint32_t d = mw & kCountMask;
         double hv = 0.0, qv = 0.0;
         if (d != 0u) {
             const double s = s0[r];
-            if (!(s >= 1e-300) || !(s <= 1e300)) atomicOr(flags, 1u);
+            if (!(s >= 0.5) || !(s <= 1e300)) atomicOr(flags, 1u);
             hv = (double)d / s;
             qv = hv / sqrt((double)d);
-            obj += (double)d * (log(s) + scal[0]);
+            obj += (double)d * (log(s) + m[r]);
         }
-        if (m & kEventBit) obj -= eta[r];
+        if (mw & kEventBit) obj -= eta[r];
         h[r] = hv;
         zq[r] = qv;
     }
@@ -121,16 +113,11 @@ __global__ __launch_bounds__(kRowBlock) void hazard_kernel(const double *s0, con
     if (threadIdx.x == 0) blockobj[blockIdx.x] = obj;
 }
 
-// a = w Lambda - delta, b = w Lambda
-__global__ __launch_bounds__(kRowBlock) void rowweight_kernel(const double *w, const double *lam, const uint32_t *meta,
-                                                              int64_t ld, double *a, double *b)
+// b = w Lambda = u R, with R the reverse recurrence of h' (relative to exp(m_r))
+__global__ __launch_bounds__(kRowBlock) void rowweight_kernel(const double *u, const double *R, int64_t ld, double *b)
 {
     const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
-    if (r < ld) {
-        const double wl = w[r] * lam[r];
-        b[r] = wl;
-        a[r] = wl - ((meta[r] & kEventBit) ? 1.0 : 0.0);
-    }
+    if (r < ld) b[r] = u[r] * R[r];
 }
 
 template <typename ZT>
@@ -164,10 +151,12 @@ __device__ __forceinline__ void load4(const double *p, double *v)
     v[3] = hi.y;
 }
 
-// agg[t][j] = sum of w x_j over the rows of tile t from its last head (or its
-// first row) to its end, for the tiles listed in `tiles`.
-__global__ __launch_bounds__(kWave * kColWaves) void colagg_kernel(const double *x, int64_t ld, int p, const double *w,
-                                                                   int64_t tile, const int32_t *tiles, int ntl,
+// agg[t][j] = the map S -> A S + B of the rows of tile t from its last head (or
+// its first row) to its end for the recurrence S'_r = alpha_r S'_{r-1} + u_r x_rj
+// (stored as A, B), for the tiles listed in `tiles`.
+__global__ __launch_bounds__(kWave * kColWaves) void colagg_kernel(const double *x, int64_t ld, int p, const double *alpha,
+                                                                   const double *u, const uint32_t *meta, int64_t tile,
+                                                                   const int32_t *tiles, int ntl,
                                                                    const int32_t *lasthead, double *agg)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -177,14 +166,22 @@ __global__ __launch_bounds__(kWave * kColWaves) void colagg_kernel(const double 
     const int64_t r1 = (int64_t)(t + 1) * tile;
     const int64_t r0 = lasthead[t] >= 0 ? (int64_t)lasthead[t] : (int64_t)t * tile;
     const double *xj = x + (int64_t)j * ld;
-    double s = 0.0;
-    for (int64_t r = r0 + lane; r < r1; r += kWave) s = fma(w[r], xj[r], s);
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
-    if (lane == 0) agg[(int64_t)t * p + j] = s;
+    AffE acc = AffOp::id();
+    for (int64_t base = r0; base < r1; base += kWave) {
+        const int64_t r = base + lane;
+        AffE e = AffOp::id();
+        if (r < r1) e = AffE{(meta[r] & kHeadBit) ? 1u : 0u, alpha[r], u[r] * xj[r]};
+        const AffE tot = lane63_e(wave_scan_e<AffOp>(e));
+        acc = AffOp::combine(acc, tot);
+    }
+    if (lane == 0) {
+        agg[((int64_t)t * p + j) * 2] = acc.a;
+        agg[((int64_t)t * p + j) * 2 + 1] = acc.b;
+    }
 }
 
-// carry[t][j] = the S1 running sum entering tile t (for tiles whose first row
-// continues a stratum).  One thread per column, tiles in order.
+// carry[t][j] = S'_j entering tile t (for tiles whose first row continues a
+// stratum).  One thread per column, tiles in order.
 __global__ __launch_bounds__(256) void colcarry_kernel(int p, int ntiles, const uint8_t *tile_carry,
                                                        const int32_t *lasthead, const double *agg, double *carry)
 {
@@ -193,22 +190,44 @@ __global__ __launch_bounds__(256) void colcarry_kernel(int p, int ntiles, const 
     double c = 0.0;
     for (int t = 0; t < ntiles; ++t) {
         carry[(int64_t)t * p + j] = c;
-        if (t + 1 < ntiles && tile_carry[t + 1]) c = (lasthead[t] >= 0 ? 0.0 : c) + agg[(int64_t)t * p + j];
-        else c = 0.0;
+        if (t + 1 < ntiles && tile_carry[t + 1]) {
+            const double A = agg[((int64_t)t * p + j) * 2], B = agg[((int64_t)t * p + j) * 2 + 1];
+            c = lasthead[t] >= 0 ? B : fma(A, c, B);
+        } else {
+            c = 0.0;
+        }
     }
 }
 
-// kColBlock columns per wave: the row vectors (w, b, zq, row words, group
-// indices) are loaded once per chunk for all of them.
+// kColBlock columns per wave: the row vectors (alpha, u, b, zq, row words,
+// group indices) are loaded once per chunk for all of them, and the
+// column-independent parts (flags, products of alpha) of the wave scan are
+// formed once.
 constexpr int kColBlock = 4;
+
+// One DPP step of the shared-multiplier scan: every column's b uses the same
+// (f, a) of the element it extends.
+template <int CTRL, int ROWS, int CB>
+__device__ __forceinline__ void aff_step(uint32_t &f, double &a, double (&b)[CB])
+{
+    const uint32_t sf = dpp_keep_u32<CTRL, ROWS>(0u, f);
+    const double sa = dpp_keep<CTRL, ROWS>(1.0, a);
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        const double sb = dpp_keep<CTRL, ROWS>(0.0, b[c]);
+        b[c] = f ? b[c] : fma(a, sb, b[c]);
+    }
+    a = f ? a : sa * a;
+    f = f | sf;
+}
 
 template <typename ZT, bool XBAR>
 __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double *x, int64_t ld, int p, int64_t tile,
-                                                                    int ntiles, const double *w, const double *zq,
-                                                                    const double *b, const uint32_t *meta,
-                                                                    const int32_t *gidx, const uint8_t *tile_carry,
-                                                                    const double *carry, int64_t ldz,
-                                                                    const float *zscale, ZT *z, double *part)
+                                                                    int ntiles, const double *alpha, const double *u,
+                                                                    const double *zq, const double *b,
+                                                                    const uint32_t *meta, const int32_t *gidx,
+                                                                    const uint8_t *tile_carry, const double *carry,
+                                                                    int64_t ldz, const float *zscale, ZT *z, double *part)
 {
     constexpr int CB = kColBlock;
     const int lane = threadIdx.x & (kWave - 1);
@@ -225,8 +244,7 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
     const double *xc[CB];
     bool live[CB];
     float zs[CB];
-    double g[CB], d1[CB], d2[CB];
-    SegVal<1> run_carry[CB];
+    double g[CB], d1[CB], d2[CB], cb[CB];   // cb: S'_j entering the chunk
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
         const int j = j0 + c;
@@ -234,12 +252,11 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
         xc[c] = x + (int64_t)(live[c] ? j : j0) * ld;
         zs[c] = (zscale && live[c]) ? 1.0f / zscale[j] : 1.0f;
         g[c] = d1[c] = d2[c] = 0.0;
-        run_carry[c] = seg_identity<1>();
-        if (XBAR && live[c] && tile_carry[t]) run_carry[c].v[0] = carry[(int64_t)t * p + j];
+        cb[c] = (XBAR && live[c] && tile_carry[t]) ? carry[(int64_t)t * p + j] : 0.0;
     }
     for (int64_t base = r_begin; base < r_end; base += kColChunk) {
         const int64_t r0 = base + (int64_t)lane * kColIpt;   // 4 consecutive rows per lane: 16-byte loads
-        double xv[CB][kColIpt], bv[kColIpt], wv[kColIpt], qv[kColIpt];
+        double xv[CB][kColIpt], bv[kColIpt], av[kColIpt], uv[kColIpt], qv[kColIpt];
         uint32_t m[kColIpt];
         int32_t gi[kColIpt];
 #pragma unroll
@@ -253,7 +270,8 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
             m[3] = mm.w;
         }
         if (XBAR) {
-            load4(w + r0, wv);
+            load4(alpha + r0, av);
+            load4(u + r0, uv);
             load4(zq + r0, qv);
             const int4 gg = *reinterpret_cast<const int4 *>(gidx + r0);
             gi[0] = gg.x;
@@ -265,34 +283,53 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
         for (int c = 0; c < CB; ++c) {
 #pragma unroll
             for (int i = 0; i < kColIpt; ++i) {
-                const double av = bv[i] - ((m[i] & kEventBit) ? 1.0 : 0.0);   // w Lambda - delta
-                g[c] = fma(xv[c][i], av, g[c]);
+                const double aw = bv[i] - ((m[i] & kEventBit) ? 1.0 : 0.0);   // w Lambda - delta
+                g[c] = fma(xv[c][i], aw, g[c]);
                 d1[c] = fma(xv[c][i] * xv[c][i], bv[i], d1[c]);
             }
         }
         if (XBAR) {
+            // this lane's 4 rows folded: flags, product of alphas, and per column the map's offset
+            uint32_t f = 0u;
+            double a = 1.0, bb[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) bb[c] = 0.0;
+#pragma unroll
+            for (int i = 0; i < kColIpt; ++i) {
+                const uint32_t fi = m[i] >> 31;
+#pragma unroll
+                for (int c = 0; c < CB; ++c) bb[c] = fi ? uv[i] * xv[c][i] : fma(av[i], bb[c], uv[i] * xv[c][i]);
+                a = fi ? av[i] : a * av[i];
+                f |= fi;
+            }
+            // inclusive scan across the wave
+            aff_step<0x111, 0xF, CB>(f, a, bb);
+            aff_step<0x112, 0xF, CB>(f, a, bb);
+            aff_step<0x114, 0xF, CB>(f, a, bb);
+            aff_step<0x118, 0xF, CB>(f, a, bb);
+            aff_step<0x142, 0xA, CB>(f, a, bb);
+            aff_step<0x143, 0xC, CB>(f, a, bb);
+            // exclusive prefix of this lane = the inclusive value of lane - 1
+            const uint32_t ef = dpp_keep_u32<0x138, 0xF>(0u, f);
+            const double ea = dpp_keep<0x138, 0xF>(1.0, a);
+            const uint32_t tf = (uint32_t)__builtin_amdgcn_readlane((int)f, 63);
+            const double ta = readlane63(a);
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
-                SegVal<1> e[kColIpt];
-                SegVal<1> tot = seg_identity<1>();
+                const double eb = dpp_keep<0x138, 0xF>(0.0, bb[c]);
+                double run = ef ? eb : fma(ea, cb[c], eb);   // S' entering this lane's first row
 #pragma unroll
                 for (int i = 0; i < kColIpt; ++i) {
-                    e[i].f = m[i] >> 31;
-                    e[i].v[0] = wv[i] * xv[c][i];
-                    tot = seg_combine(tot, e[i]);
-                }
-                const SegVal<1> inc = wave_inclusive_scan(tot);
-                SegVal<1> run = seg_combine(run_carry[c], wave_shift_right(inc));
-#pragma unroll
-                for (int i = 0; i < kColIpt; ++i) {
-                    run = seg_combine(run, e[i]);
+                    const double ux = uv[i] * xv[c][i];
+                    run = (m[i] >> 31) ? ux : fma(av[i], run, ux);
                     if ((m[i] & kCountMask) && live[c]) {
-                        const double zv = run.v[0] * qv[i];   // sqrt(d) xbar
+                        const double zv = run * qv[i];   // sqrt(d) xbar
                         d2[c] = fma(zv, zv, d2[c]);
                         store_z<ZT>(&z[(int64_t)(j0 + c) * ldz + gi[i]], zv, zs[c]);
                     }
                 }
-                run_carry[c] = seg_combine(run_carry[c], lane63_seg(inc));
+                const double tb = readlane63(bb[c]);
+                cb[c] = tf ? tb : fma(ta, cb[c], tb);
             }
         }
     }
@@ -360,132 +397,134 @@ __global__ __launch_bounds__(kRowBlock) void colreduce_kernel(const double *part
     }
 }
 
-// ------------------------------------------------------------------ row scans (forward / reverse)
+// ------------------------------------------------------------------ row scans
 //
-// Segmented +scan of one FP64 value per row over all ld rows, in tiles of
-// `tile` rows: (1) each workgroup folds its tile into one aggregate, (2) one
-// workgroup scans the aggregates into the carry entering every tile, (3) each
-// workgroup rescans its tile from its carry.  REV scans from the last row
-// backwards, a segment then starting at the last row of each stratum.
+// Segmented scans over all ld rows in tiles of `tile` rows: (1) each workgroup
+// folds its tile into one aggregate, (2) one workgroup scans the aggregates
+// into the value entering every tile, (3) each workgroup rescans its tile from
+// there.  The element type and its operator come from affscan.hpp; a loader
+// gives the element at scan position k and a writer stores the inclusive value.
 
 constexpr int kScanThreads = 256, kScanWaves = kScanThreads / kWave;
 
-template <bool REV>
-__device__ __forceinline__ uint32_t scan_head(const uint32_t *meta, int64_t n, int64_t k)
+template <class Op, class Ld>
+__global__ __launch_bounds__(kScanThreads) void tscan_agg_kernel(Ld ldr, int64_t tile, typename Op::E *agg)
 {
-    if (k == 0) return 1u;
-    if (!REV) return (meta[k] & kHeadBit) ? 1u : 0u;
-    return (meta[n - k] & kHeadBit) ? 1u : 0u;   // row n-1-k is a stratum's last row
-}
-
-template <bool REV>
-__global__ __launch_bounds__(kScanThreads) void tileagg_kernel(const double *a, const uint32_t *meta, int64_t n,
-                                                                 int64_t tile, double *aggv, uint32_t *aggf)
-{
-    __shared__ SegVal<1> wtot[kScanWaves];
+    using E = typename Op::E;
+    __shared__ E wtot[kScanWaves];
     const int t = blockIdx.x;
     const int64_t per = tile / kScanThreads;
     const int64_t k0 = (int64_t)t * tile + (int64_t)threadIdx.x * per;
-    SegVal<1> f = seg_identity<1>();
-    for (int64_t i = 0; i < per; ++i) {
-        const int64_t k = k0 + i;
-        SegVal<1> e;
-        e.f = scan_head<REV>(meta, n, k);
-        e.v[0] = a[REV ? n - 1 - k : k];
-        f = seg_combine(f, e);
-    }
-    SegVal<1> total;
-    (void)block_exclusive_scan<1, kScanWaves>(f, wtot, total);
-    if (threadIdx.x == 0) {
-        aggv[t] = total.v[0];
-        aggf[t] = total.f;
-    }
+    E f = Op::id();
+    for (int64_t i = 0; i < per; ++i) f = Op::combine(f, ldr(k0 + i));
+    E total;
+    (void)block_exclusive_e<Op, kScanWaves>(f, wtot, total);
+    if (threadIdx.x == 0) agg[t] = total;
 }
 
-// carry[t] = the running segment sum entering tile t (one workgroup)
-__global__ __launch_bounds__(1024) void tilecarry_kernel(const double *aggv, const uint32_t *aggf, int ntiles,
-                                                         double *carry)
+template <class Op>
+__global__ __launch_bounds__(1024) void tscan_carry_kernel(const typename Op::E *agg, int ntiles,
+                                                           typename Op::E *carry)
 {
-    __shared__ SegVal<1> wtot[1024 / kWave];
+    using E = typename Op::E;
+    __shared__ E wtot[1024 / kWave];
     const int per = (ntiles + 1023) / 1024;
     const int t0 = threadIdx.x * per;
-    SegVal<1> f = seg_identity<1>();
+    E f = Op::id();
+    for (int i = 0; i < per; ++i)
+        if (t0 + i < ntiles) f = Op::combine(f, agg[t0 + i]);
+    E total;
+    E run = block_exclusive_e<Op, 1024 / kWave>(f, wtot, total);
     for (int i = 0; i < per; ++i) {
         const int t = t0 + i;
         if (t < ntiles) {
-            SegVal<1> e;
-            e.f = aggf[t];
-            e.v[0] = aggv[t];
-            f = seg_combine(f, e);
-        }
-    }
-    SegVal<1> total;
-    SegVal<1> run = block_exclusive_scan<1, 1024 / kWave>(f, wtot, total);
-    for (int i = 0; i < per; ++i) {
-        const int t = t0 + i;
-        if (t < ntiles) {
-            carry[t] = run.v[0];
-            SegVal<1> e;
-            e.f = aggf[t];
-            e.v[0] = aggv[t];
-            run = seg_combine(run, e);
+            carry[t] = run;
+            run = Op::combine(run, agg[t]);
         }
     }
 }
 
-template <bool REV>
-__global__ __launch_bounds__(kScanThreads) void tileapply_kernel(const double *a, const uint32_t *meta, double *out,
-                                                                   int64_t n, int64_t tile, const double *carry)
+template <class Op, class Ld, class Wr>
+__global__ __launch_bounds__(kScanThreads) void tscan_apply_kernel(Ld ldr, Wr wr, int64_t tile,
+                                                                   const typename Op::E *carry)
 {
-    __shared__ SegVal<1> wtot[kScanWaves];
+    using E = typename Op::E;
+    __shared__ E wtot[kScanWaves];
     const int t = blockIdx.x;
     const int64_t per = tile / kScanThreads;
     const int64_t k0 = (int64_t)t * tile + (int64_t)threadIdx.x * per;
-    SegVal<1> f = seg_identity<1>();
+    E f = Op::id();
+    for (int64_t i = 0; i < per; ++i) f = Op::combine(f, ldr(k0 + i));
+    E total;
+    const E exc = block_exclusive_e<Op, kScanWaves>(f, wtot, total);
+    E run = Op::combine(carry[t], exc);
     for (int64_t i = 0; i < per; ++i) {
-        const int64_t k = k0 + i;
-        SegVal<1> e;
-        e.f = scan_head<REV>(meta, n, k);
-        e.v[0] = a[REV ? n - 1 - k : k];
-        f = seg_combine(f, e);
+        run = Op::combine(run, ldr(k0 + i));
+        wr(k0 + i, run);
     }
-    SegVal<1> total;
-    const SegVal<1> exc = block_exclusive_scan<1, kScanWaves>(f, wtot, total);
-    SegVal<1> run = seg_identity<1>();
-    run.v[0] = carry[t];
-    run = seg_combine(run, exc);
-    for (int64_t i = 0; i < per; ++i) {
-        const int64_t k = k0 + i;
-        SegVal<1> e;
-        e.f = scan_head<REV>(meta, n, k);
-        e.v[0] = a[REV ? n - 1 - k : k];
-        run = seg_combine(run, e);
-        out[REV ? n - 1 - k : k] = run.v[0];
+}
+
+// running maximum of eta within each stratum (forward)
+struct MaxLoad {
+    const double *eta;
+    const uint32_t *meta;
+    __device__ MaxE operator()(int64_t k) const { return MaxE{(meta[k] & kHeadBit) ? 1u : 0u, eta[k]}; }
+};
+struct MaxWrite {
+    double *m;
+    __device__ void operator()(int64_t k, const MaxE &e) const { m[k] = e.m; }
+};
+
+// S0' (forward): S0'_r = alpha_r S0'_{r-1} + u_r
+struct S0Load {
+    const double *alpha, *u;
+    const uint32_t *meta;
+    __device__ AffE operator()(int64_t k) const { return AffE{(meta[k] & kHeadBit) ? 1u : 0u, alpha[k], u[k]}; }
+};
+struct BWrite {
+    double *out;
+    __device__ void operator()(int64_t k, const AffE &e) const { out[k] = e.b; }
+};
+
+// R (reverse, scan position k = row n-1-k): R_r = h'_r + alpha_{r+1} R_{r+1},
+// a segment starting at each stratum's last row
+struct RLoad {
+    const double *alpha, *h;
+    const uint32_t *meta;
+    int64_t n;
+    __device__ AffE operator()(int64_t k) const
+    {
+        const int64_t r = n - 1 - k;
+        const bool start = k == 0 || (meta[r + 1] & kHeadBit);
+        return AffE{start ? 1u : 0u, start ? 1.0 : alpha[r + 1], h[r]};
     }
+};
+struct RWrite {
+    double *out;
+    int64_t n;
+    __device__ void operator()(int64_t k, const AffE &e) const { out[n - 1 - k] = e.b; }
+};
+
+template <class Op, class Ld, class Wr>
+int tile_scan(Ld ldr, Wr wr, int64_t n, int64_t tile, void *scratch, size_t scratch_bytes, hipStream_t stream)
+{
+    using E = typename Op::E;
+    if (tile <= 0 || tile % kScanThreads != 0 || n % tile != 0) return -5;
+    const int ntiles = (int)(n / tile);
+    if (sizeof(E) * 2 * (size_t)ntiles > scratch_bytes) return -5;
+    E *agg = static_cast<E *>(scratch);
+    E *carry = agg + ntiles;
+    tscan_agg_kernel<Op, Ld><<<ntiles, kScanThreads, 0, stream>>>(ldr, tile, agg);
+    tscan_carry_kernel<Op><<<1, 1024, 0, stream>>>(agg, ntiles, carry);
+    tscan_apply_kernel<Op, Ld, Wr><<<ntiles, kScanThreads, 0, stream>>>(ldr, wr, tile, carry);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 }  // namespace
 
 // ------------------------------------------------------------------ host launchers
 
-int rowscan(const double *a, const uint32_t *meta, double *out, int64_t n, int64_t tile, bool reverse,
-            void *scratch, size_t scratch_bytes, hipStream_t stream)
-{
-    if (tile <= 0 || tile % kScanThreads != 0 || n % tile != 0) return -5;
-    const int ntiles = (int)(n / tile);
-    if (rowscan_scratch_bytes(ntiles) > scratch_bytes) return -5;
-    double *aggv = static_cast<double *>(scratch);
-    double *carry = aggv + ntiles;
-    uint32_t *aggf = reinterpret_cast<uint32_t *>(carry + ntiles);
-    if (reverse) tileagg_kernel<true><<<ntiles, kScanThreads, 0, stream>>>(a, meta, n, tile, aggv, aggf);
-    else tileagg_kernel<false><<<ntiles, kScanThreads, 0, stream>>>(a, meta, n, tile, aggv, aggf);
-    tilecarry_kernel<<<1, 1024, 0, stream>>>(aggv, aggf, ntiles, carry);
-    if (reverse) tileapply_kernel<true><<<ntiles, kScanThreads, 0, stream>>>(a, meta, out, n, tile, carry);
-    else tileapply_kernel<false><<<ntiles, kScanThreads, 0, stream>>>(a, meta, out, n, tile, carry);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
-}
-
-size_t rowscan_scratch_bytes(int ntiles) { return (sizeof(double) * 2 + sizeof(uint32_t)) * (size_t)ntiles + 256; }
+size_t rowscan_scratch_bytes(int ntiles) { return sizeof(AffE) * 2 * (size_t)ntiles + 256; }
 
 int full_eval_launch(const FullEvalArgs &A, hipStream_t stream)
 {
@@ -494,25 +533,29 @@ int full_eval_launch(const FullEvalArgs &A, hipStream_t stream)
     if (nb > A.max_blocks) return -5;
     hipError_t e = hipMemsetAsync(A.flags, 0, sizeof(unsigned), stream);
     if (e != hipSuccess) return -3;
-    eta_kernel<<<nb, kRowBlock, 0, stream>>>(A.x, ld, A.p, A.beta, A.meta, A.eta, A.blockbuf);
-    max_kernel<<<1, kRowBlock, 0, stream>>>(A.blockbuf, nb, A.scal);
-    weight_kernel<<<nb, kRowBlock, 0, stream>>>(A.eta, A.scal, ld, A.w);
-    int rc = rowscan(A.w, A.meta, A.s0, ld, A.tile, false, A.scan_scratch, A.scan_scratch_bytes, stream);
+    eta_kernel<<<nb, kRowBlock, 0, stream>>>(A.x, ld, A.p, A.beta, A.eta);
+    int rc = tile_scan<MaxOp>(MaxLoad{A.eta, A.meta}, MaxWrite{A.m}, ld, A.tile, A.scan_scratch,
+                              A.scan_scratch_bytes, stream);
     if (rc) return rc;
-    hazard_kernel<<<nb, kRowBlock, 0, stream>>>(A.s0, A.eta, A.meta, A.scal, ld, A.h, A.zq, A.blockbuf, A.flags);
-    rc = rowscan(A.h, A.meta, A.lam, ld, A.tile, true, A.scan_scratch, A.scan_scratch_bytes, stream);
+    prep_kernel<<<nb, kRowBlock, 0, stream>>>(A.eta, A.m, A.meta, ld, A.alpha, A.w);
+    rc = tile_scan<AffOp>(S0Load{A.alpha, A.w, A.meta}, BWrite{A.s0}, ld, A.tile, A.scan_scratch,
+                          A.scan_scratch_bytes, stream);
     if (rc) return rc;
-    rowweight_kernel<<<nb, kRowBlock, 0, stream>>>(A.w, A.lam, A.meta, ld, A.a, A.b);
+    hazard_kernel<<<nb, kRowBlock, 0, stream>>>(A.s0, A.eta, A.m, A.meta, ld, A.h, A.zq, A.blockbuf, A.flags);
+    rc = tile_scan<AffOp>(RLoad{A.alpha, A.h, A.meta, ld}, RWrite{A.lam, ld}, ld, A.tile, A.scan_scratch,
+                          A.scan_scratch_bytes, stream);
+    if (rc) return rc;
+    rowweight_kernel<<<nb, kRowBlock, 0, stream>>>(A.w, A.lam, ld, A.b);
     if (A.n_agg > 0) {
         colagg_kernel<<<(A.n_agg * A.p + kColWaves - 1) / kColWaves, kWave * kColWaves, 0, stream>>>(
-            A.x, ld, A.p, A.w, A.tile, A.agg_tiles, A.n_agg, A.lasthead, A.agg);
+            A.x, ld, A.p, A.alpha, A.w, A.meta, A.tile, A.agg_tiles, A.n_agg, A.lasthead, A.agg);
         colcarry_kernel<<<(A.p + 255) / 256, 256, 0, stream>>>(A.p, A.ntiles, A.tile_carry, A.lasthead, A.agg,
                                                                A.carry);
     }
     const int grid = 8 * ((A.ntiles + 7) / 8) * ((A.p + kColWaves * kColBlock - 1) / (kColWaves * kColBlock));
 #define COXMI_COLPASS(ZT, XB)                                                                                  \
     colpass_kernel<ZT, XB><<<grid, kWave * kColWaves, 0, stream>>>(                                            \
-        A.x, ld, A.p, A.tile, A.ntiles, A.w, A.zq, A.b, A.meta, A.gidx, A.tile_carry, A.carry, A.ldz,          \
+        A.x, ld, A.p, A.tile, A.ntiles, A.alpha, A.w, A.zq, A.b, A.meta, A.gidx, A.tile_carry, A.carry, A.ldz, \
         A.zscale, static_cast<ZT *>(A.z), A.colpart)
     if (!A.want_xbar) COXMI_COLPASS(double, false);
     else if (A.ztype == kZF64) COXMI_COLPASS(double, true);

@@ -75,12 +75,12 @@ int newton_setup(cox_handle *h)
     const size_t zb = ztype_bytes(h->opt.x_precision);
     hipError_t e;
     if ((e = dalloc(&s.gidx, sizeof(int32_t) * ld)) != hipSuccess ||
-        (e = dalloc(&s.rows, sizeof(double) * 8 * ld)) != hipSuccess ||
+        (e = dalloc(&s.rows, sizeof(double) * 9 * ld)) != hipSuccess ||
         (e = dalloc(&s.blockbuf, sizeof(double) * s.max_blocks)) != hipSuccess ||
         (e = dalloc(&s.tile_carry, (size_t)s.ntiles)) != hipSuccess ||
         (e = dalloc(&s.lasthead, sizeof(int32_t) * s.ntiles)) != hipSuccess ||
         (e = dalloc(&s.agg_tiles, sizeof(int32_t) * std::max(1, s.n_agg))) != hipSuccess ||
-        (e = dalloc(&s.agg, sizeof(double) * (size_t)s.ntiles * p)) != hipSuccess ||
+        (e = dalloc(&s.agg, sizeof(double) * 2 * (size_t)s.ntiles * p)) != hipSuccess ||
         (e = dalloc(&s.carry, sizeof(double) * (size_t)s.ntiles * p)) != hipSuccess ||
         (e = dalloc(&s.colpart, sizeof(double) * 3 * (size_t)s.ntiles * p)) != hipSuccess ||
         (e = dalloc(&s.vec, sizeof(double) * (5 * (size_t)p + kScalSlots))) != hipSuccess ||
@@ -174,7 +174,8 @@ int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
     A.h = nrow(s, ld, 3);
     A.lam = nrow(s, ld, 4);
     A.zq = nrow(s, ld, 7);
-    A.a = nrow(s, ld, 5);
+    A.m = nrow(s, ld, 8);
+    A.alpha = nrow(s, ld, 5);
     A.b = nrow(s, ld, 6);
     A.blockbuf = s.blockbuf;
     A.tile = s.tile;

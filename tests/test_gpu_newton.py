@@ -291,3 +291,28 @@ def test_newton_fp8_heavy_tailed():
     _say(f"  iters={info['iters']} evals={info['coord_evals']} rel err {err:.3e} profile {prof}")
     assert info["status"] == coxmi.COX_OK
     assert err <= 1e-10
+
+
+def test_full_evaluation_extreme_linear_predictor():
+    """Rows whose X beta is 900 or more above the rest of their stratum: a single
+    exponent shift would underflow every other row's weight; the running-maximum
+    recurrences keep all risk-set sums in range.  Against the oracle, whose scan
+    carries a running maximum as well."""
+    rng = np.random.default_rng(41)
+    n, p, K = 6000, 4, 60
+    X = rng.standard_normal((n, p))
+    hot = rng.choice(n, size=12, replace=False)
+    X[hot, 0] = rng.choice([-300.0, 300.0], size=12)
+    t = rng.exponential(1.0, n)
+    e = (rng.random(n) < 0.6).astype(np.uint8)
+    st = (np.arange(n) % K).astype(np.int32)
+    beta = np.array([3.0, -2.0, 1.0, 0.5])
+    d = synth.CoxData(X=np.asfortranarray(X), time=t, event=e, stratum=st, beta_true=beta, gamma=0.0, name="extreme")
+    _say("evaluate_full with |X beta| up to 900")
+    fe = _oracle_eval(d, beta)
+    for prec in (coxmi.COX_F64, coxmi.COX_BF16):
+        with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE, x_precision=prec) as m:
+            obj, g, hd, info = m.evaluate_full(beta)
+        _check_first_order(d, obj, g, hd, fe)
+        lim = 1e-11 if prec == coxmi.COX_F64 else 3.5 * U_BF16 + 64 * 2.0 ** -24
+        assert np.all(np.abs(info - fe.info) <= lim * _scale(fe) + 1e-300)
