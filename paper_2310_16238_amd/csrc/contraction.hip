@@ -421,15 +421,17 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_kernel(const uint
 // the weights, rounded to BF16), then every wave runs its tile pairs' MFMAs
 // from LDS.  The next chunk's global loads are issued into registers before
 // the current chunk's MFMAs.  Same partial layout as syrk_bf16_kernel.
-constexpr int kLdsKC = 128, kLdsStride = kLdsKC + 8, kLdsMaxTiles = 8;
-constexpr int kLdsPieces = kLdsKC / 8;                                  // 16-byte pieces per row
-constexpr int kLdsPerThread = kLdsMaxTiles * kMT * kLdsPieces / (64 * kSyrkBfWaves);   // 16
+// KC rows per chunk: 128 for up to 8 row tiles, 64 for up to 16 (the LDS then
+// holds 16 tiles x 32 rows x 72 BF16, twice with weights: 147 KB).
+constexpr int kLdsMaxTiles = 16;
 
-template <bool WEIGHT>
+template <bool WEIGHT, int KC>
 __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_lds_kernel(const uint16_t *u, int64_t ldu, int p,
                                                                           const double *c, int64_t K, int64_t kchunk,
                                                                           float *part)
 {
+    constexpr int kLdsKC = KC, kLdsStride = KC + 8, kLdsPieces = KC / 8;
+    constexpr int kLdsPerThread = (KC == 128 ? 8 : 16) * kMT * kLdsPieces / (64 * kSyrkBfWaves);   // 16
     extern __shared__ uint16_t sh[];   // [nt*32][kLdsStride] plain, then weighted (WEIGHT)
     __shared__ float cw[kLdsKC];
     const int nt = (p + kMT - 1) / kMT;
@@ -757,27 +759,32 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
     if (K16 > ldu) return -1;
     float *fpart = reinterpret_cast<float *>(part);
     const int nt = (p + kMT - 1) / kMT;
-    const int64_t K64 = (K + kLdsKC - 1) / kLdsKC * kLdsKC;
+    const int KC = nt <= 8 ? 128 : 64;
+    const int64_t K64 = (K + KC - 1) / KC * KC;
     if (nt <= kLdsMaxTiles && K64 <= ldu && ldu % 8 == 0) {
         int64_t kchunk = (K64 + splits - 1) / splits;
-        kchunk = (kchunk + kLdsKC - 1) / kLdsKC * kLdsKC;
-        const size_t lds = sizeof(uint16_t) * (size_t)nt * kMT * kLdsStride * (c ? 2 : 1);
+        kchunk = (kchunk + KC - 1) / KC * KC;
+        const size_t lds = sizeof(uint16_t) * (size_t)nt * kMT * (KC + 8) * (c ? 2 : 1);
         static bool attr = false;
         if (!attr) {
-            const size_t most = sizeof(uint16_t) * (size_t)kLdsMaxTiles * kMT * kLdsStride * 2;
-            if (hipFuncSetAttribute(reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<true>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess ||
-                hipFuncSetAttribute(reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<false>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
-                return -3;
+            const size_t most = sizeof(uint16_t) * (size_t)16 * kMT * (64 + 8) * 2;   // the largest of both shapes
+            const void *fns[] = {reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<true, 128>),
+                                 reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<false, 128>),
+                                 reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<true, 64>),
+                                 reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<false, 64>)};
+            for (const void *fn : fns)
+                if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
+                    return -3;
             attr = true;
         }
-        if (c)
-            syrk_bf16_lds_kernel<true><<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64,
-                                                                                                 kchunk, fpart);
-        else
-            syrk_bf16_lds_kernel<false><<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64,
-                                                                                                  kchunk, fpart);
+        const dim3 grid(splits, ngroups);
+        if (KC == 128) {
+            if (c) syrk_bf16_lds_kernel<true, 128><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64, kchunk, fpart);
+            else syrk_bf16_lds_kernel<false, 128><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64, kchunk, fpart);
+        } else {
+            if (c) syrk_bf16_lds_kernel<true, 64><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64, kchunk, fpart);
+            else syrk_bf16_lds_kernel<false, 64><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64, kchunk, fpart);
+        }
     } else {
         int64_t kchunk = (K16 + splits - 1) / splits;
         kchunk = (kchunk + 15) / 16 * 16;
