@@ -22,6 +22,8 @@ constexpr int kEtaRows = 256;     // rows per work item of the X beta kernel
 constexpr int kXRange = 4096;     // rows per K range of the X' diag(b) X contraction
 constexpr int kZRange = 4096;     // event groups per K range of the Z'Z contraction
 constexpr int kTile = 32;         // edge of a contraction tile (one MFMA block)
+constexpr int kScanTile = 4096;   // rows of a scan tile: a fit whose strata all fit one tile is laid
+                                  // out so that every scan tile starts with a stratum head
 
 // FitState.flags
 enum : int {
@@ -60,8 +62,12 @@ struct FitDesc {
     double *L;              // [p][p] Cholesky factor (row-major, lower)
     float *part;            // [(nxr + nzr) * npairs][32 * 32] contraction partials
     double *tilemax;        // [ntile]
+    double *tpart;          // [ntc][2] per scan tile: objective part, range flag
+    double *cpart;          // [ntc][p][3] per scan tile and column: score, the two diagonal parts
     FitState *st;
     int64_t n, ld, ldz;
+    int64_t tile;           // rows per scan tile (ld = ntc * tile)
+    int ntc;                // scan tiles
     int p, G;               // columns, event groups
     int nxr, nzr;           // K ranges of the two products (nzr = 0 without events)
     int npairs, ntile;      // tile pairs of the upper triangle; X beta work items
@@ -73,7 +79,7 @@ struct FitDesc {
 // Launchers (return a hipError_t value).  Work-item arrays are device memory.
 int launch_admit(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_eta(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
-int launch_rows(const FitDesc *fits, const int *slots, int nslots, hipStream_t s);
+int launch_rows(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_cols(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_syrk(const FitDesc *fits, const int4 *items, int nitems, hipStream_t s);
 int launch_step(const FitDesc *fits, const int *slots, int nslots, int max_p, hipStream_t s);

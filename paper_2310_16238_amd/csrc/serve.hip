@@ -2,12 +2,13 @@
 //
 // One Newton iteration of every resident fit is five launches:
 //   eta   (fit, 256-row tile)  X beta in FP64 and the tile's max of X beta
-//   rows  (fit)                w = exp(X beta - c), forward segmented scan of w
+//   rows  (fit, scan tile)     w = exp(X beta - c), forward segmented scan of w
 //                              (S0), d/S0 and (d/S0)/sqrt(d) at group ends and the
 //                              objective, reverse
 //                              segmented scan of d/S0 (Lambda), a = w Lambda - delta,
 //                              b = w Lambda
-//   cols  (fit, column)        one wave: forward segmented scan of w x_j (S1),
+//   cols  (fit, scan tile, column)
+//                              one wave: forward segmented scan of w x_j (S1),
 //                              xbar = S1/S0 at group ends, z = sqrt(d) xbar,
 //                              score X'a, diagonal (X o X)'b - sum d xbar^2
 //   syrk  (fit, tile pair, K range, product)
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(kEtaRows) void eta_kernel(const FitDesc *fits, cons
             if (bj != 0.0) e = fma(F.x[(int64_t)j * F.ld + r], bj, e);
         }
         F.eta[r] = e;
-        if (r < F.n) mx = e;
+        if (!(F.meta[r] & kPadBit)) mx = e;
     }
     mx = wave_max(mx);
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mx;
@@ -109,31 +110,40 @@ __device__ __forceinline__ double block_max_rows(double v, double *red)
     return s;
 }
 
-__global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, const int *slots)
+// One workgroup per (fit, scan tile): every scan tile starts with a stratum
+// head (or is the fit's only tile), so its scans need no carry.  The tile's
+// objective part and range flag go to tpart; the step kernel adds them up.
+__global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, const int2 *items)
 {
     __shared__ SegVal<1> wtot[kRowWaves];
     __shared__ double red[kRowWaves];
-    const FitDesc F = fits[slots[blockIdx.x]];
+    const int2 it = items[blockIdx.x];
+    const FitDesc F = fits[it.x];
     const int t = threadIdx.x;
-    const int64_t n = F.n;
+    const int64_t r_begin = (int64_t)it.y * F.tile;
+    const int64_t r_end = r_begin + F.tile < F.ld ? r_begin + F.tile : F.ld;
+    const int64_t len = r_end - r_begin;
 
     double c = -INFINITY;
     for (int i = t; i < F.ntile; i += kRowThreads) c = fmax(c, F.tilemax[i]);
     c = block_max_rows(c, red);
+    if (!(c > -INFINITY)) c = 0.0;   // a fit of padding rows only cannot occur; guard the shift anyway
 
     // forward: S0 = segmented scan of w; at group ends d/S0 and d (log S0 + c); -eta at events
     double obj = 0.0;
     unsigned bad = 0u;
     SegVal<1> carry = seg_identity<1>();
-    for (int64_t base = 0; base < n; base += kRowTile) {
+    for (int64_t base = 0; base < len; base += kRowTile) {
         SegVal<1> e[kRowIpt];
         SegVal<1> tagg = seg_identity<1>();
 #pragma unroll
         for (int i = 0; i < kRowIpt; ++i) {
-            const int64_t r = base + (int64_t)t * kRowIpt + i;
-            if (r < n) {
-                e[i].f = F.meta[r] >> 31;
-                e[i].v[0] = exp(F.eta[r] - c);
+            const int64_t k = base + (int64_t)t * kRowIpt + i;
+            if (k < len) {
+                const int64_t r = r_begin + k;
+                const uint32_t mw = F.meta[r];
+                e[i].f = (k == 0) ? 1u : (mw >> 31);
+                e[i].v[0] = (mw & kPadBit) ? 0.0 : exp(F.eta[r] - c);   // padding rows carry no weight
             } else {
                 e[i] = seg_identity<1>();
             }
@@ -144,9 +154,10 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, 
         SegVal<1> run = seg_combine(carry, exc);
 #pragma unroll
         for (int i = 0; i < kRowIpt; ++i) {
-            const int64_t r = base + (int64_t)t * kRowIpt + i;
+            const int64_t k = base + (int64_t)t * kRowIpt + i;
             run = seg_combine(run, e[i]);
-            if (r < n) {
+            if (k < len) {
+                const int64_t r = r_begin + k;
                 const uint32_t m = F.meta[r];
                 const uint32_t d = m & kCountMask;
                 F.w[r] = e[i].v[0];
@@ -164,19 +175,19 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, 
             }
         }
         carry = seg_combine(carry, btot);
-        __syncthreads();   // wtot is rewritten by the next tile; w / s0 / hz visible to the reverse pass
+        __syncthreads();   // wtot is rewritten by the next chunk; w / hz visible to the reverse pass
     }
 
     // reverse: Lambda = segmented scan of d/S0 from each stratum's last row backwards
     carry = seg_identity<1>();
-    for (int64_t base = 0; base < n; base += kRowTile) {
+    for (int64_t base = 0; base < len; base += kRowTile) {
         SegVal<1> e[kRowIpt];
         SegVal<1> tagg = seg_identity<1>();
 #pragma unroll
         for (int i = 0; i < kRowIpt; ++i) {
-            const int64_t k = base + (int64_t)t * kRowIpt + i;   // scan position; row n-1-k
-            if (k < n) {
-                const int64_t r = n - 1 - k;
+            const int64_t k = base + (int64_t)t * kRowIpt + i;   // scan position; row r_end-1-k
+            if (k < len) {
+                const int64_t r = r_end - 1 - k;
                 e[i].f = (k == 0 || (F.meta[r + 1] & kHeadBit)) ? 1u : 0u;
                 e[i].v[0] = F.hz[r];
             } else {
@@ -191,8 +202,8 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, 
         for (int i = 0; i < kRowIpt; ++i) {
             const int64_t k = base + (int64_t)t * kRowIpt + i;
             run = seg_combine(run, e[i]);
-            if (k < n) {
-                const int64_t r = n - 1 - k;
+            if (k < len) {
+                const int64_t r = r_end - 1 - k;
                 const double wl = F.w[r] * run.v[0];
                 F.b[r] = wl;
                 F.a[r] = wl - ((F.meta[r] & kEventBit) ? 1.0 : 0.0);
@@ -201,15 +212,11 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, 
         carry = seg_combine(carry, btot);
         __syncthreads();
     }
-    for (int64_t r = n + t; r < F.ld; r += kRowThreads) {
-        F.a[r] = 0.0;
-        F.b[r] = 0.0;
-    }
     obj = block_sum_rows(obj, red);
     const double anybad = block_max_rows(bad ? 1.0 : 0.0, red);
     if (t == 0) {
-        F.st->obj_eval = obj;
-        F.st->range = anybad > 0.0 ? 1u : 0u;
+        F.tpart[2 * it.y] = obj;
+        F.tpart[2 * it.y + 1] = anybad;
     }
 }
 
@@ -225,13 +232,14 @@ __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *
     if (item >= nitems) return;   // whole wave; no workgroup barrier below
     const int2 it = items[item];
     const FitDesc F = fits[it.x];
-    const int j = it.y;
-    const int64_t n = F.n;
+    const int tt = it.y >> 10, j = it.y & 1023;   // (scan tile, column)
+    const int64_t r_begin = (int64_t)tt * F.tile;
+    const int64_t n = r_begin + F.tile < F.ld ? r_begin + F.tile : F.ld;
     const double *xj = F.x + (int64_t)j * F.ld;
     float *zj = F.z + (int64_t)j * F.ldz;
     double g = 0.0, d1 = 0.0, d2 = 0.0;
     SegVal<1> carry = seg_identity<1>();
-    for (int64_t base = 0; base < n; base += kColChunk) {
+    for (int64_t base = r_begin; base < n; base += kColChunk) {
         const int64_t r0 = base + (int64_t)lane * kColIpt;
         SegVal<1> e[kColIpt];
         uint32_t m[kColIpt];
@@ -270,9 +278,10 @@ __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *
     d1 = wave_sum(d1);
     d2 = wave_sum(d2);
     if (lane == 0) {
-        F.grad[j] = g;
-        F.diag1[j] = d1;
-        F.diag2[j] = d2;
+        double *o = F.cpart + ((int64_t)tt * F.p + j) * 3;
+        o[0] = g;
+        o[1] = d1;
+        o[2] = d2;
     }
 }
 
@@ -365,6 +374,29 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     double *A = lds;
     double *y = lds + (int64_t)p * p;
 
+    // per-column sums of the scan-tile partials, and the objective, in tile order
+    for (int j = t; j < p; j += kStepThreads) {
+        double sg = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int q = 0; q < F.ntc; ++q) {
+            const double *o = F.cpart + ((int64_t)q * p + j) * 3;
+            sg += o[0];
+            s1 += o[1];
+            s2 += o[2];
+        }
+        F.grad[j] = sg;
+        F.diag1[j] = s1;
+        F.diag2[j] = s2;
+    }
+    if (t == 0) {
+        double o = 0.0, bad = 0.0;
+        for (int q = 0; q < F.ntc; ++q) {
+            o += F.tpart[2 * q];
+            bad = fmax(bad, F.tpart[2 * q + 1]);
+        }
+        st->obj_eval = o;
+        st->range = bad > 0.0 ? 1u : 0u;
+    }
+    __syncthreads();
     if (t == 0) {
         st->evals += 1;
         int action = 2;   // 0 stop, 1 halve, 2 step
@@ -533,9 +565,9 @@ int launch_eta(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s
     return (int)hipGetLastError();
 }
 
-int launch_rows(const FitDesc *fits, const int *slots, int nslots, hipStream_t s)
+int launch_rows(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s)
 {
-    if (nslots > 0) rows_kernel<<<nslots, kRowThreads, 0, s>>>(fits, slots);
+    if (nitems > 0) rows_kernel<<<nitems, kRowThreads, 0, s>>>(fits, items);
     return (int)hipGetLastError();
 }
 

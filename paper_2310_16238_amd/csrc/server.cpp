@@ -100,20 +100,55 @@ private:
 
 // Where each piece of one fit lives inside its arena block (byte offsets).
 struct FitLayout {
-    int64_t n = 0, ld = 0, ldz = 0;
-    int p = 0, G = 0, nxr = 0, nzr = 0, npairs = 0, ntile = 0;
+    int64_t n = 0, ld = 0, ldz = 0, tile = 0;
+    int p = 0, G = 0, nxr = 0, nzr = 0, npairs = 0, ntile = 0, ntc = 0;
     size_t x = 0, meta = 0, gidx = 0, upload = 0;   // [x | meta | gidx] is uploaded in one copy
     size_t xf = 0, rows = 0, z = 0, beta = 0, prev = 0, zero_end = 0;
-    size_t vec = 0, free_col = 0, L = 0, part = 0, tilemax = 0, total = 0;
+    size_t vec = 0, free_col = 0, L = 0, part = 0, tilemax = 0, tpart = 0, cpart = 0, total = 0;
 };
 
-FitLayout plan(int64_t n, int p, int64_t G)
+// Device rows of a request: when the fit is longer than one scan tile and every
+// stratum fits in one, strata are kept inside scan tiles (padding rows fill the
+// gaps); otherwise the fit is one scan tile.  pos[i] = device row of canonical
+// row i; returns the padded row count and the scan tile length.
+int64_t place_rows(const std::vector<uint32_t> &meta, std::vector<int64_t> &pos, int64_t *tile)
+{
+    const int64_t n = (int64_t)meta.size();
+    pos.resize((size_t)n);
+    int64_t longest = 0, start = 0;
+    for (int64_t i = 1; i <= n; ++i)
+        if (i == n || (meta[i] & kHeadBit)) {
+            longest = std::max(longest, i - start);
+            start = i;
+        }
+    if (n <= kScanTile || longest > kScanTile) {
+        for (int64_t i = 0; i < n; ++i) pos[i] = i;
+        *tile = (int64_t)round_up((size_t)n, kRowPad);
+        return *tile;
+    }
+    int64_t cur = 0, i = 0;
+    while (i < n) {
+        int64_t e = i + 1;
+        while (e < n && !(meta[e] & kHeadBit)) ++e;
+        const int64_t m = e - i, room = kScanTile - (cur % kScanTile);
+        if (m > room) cur += room;
+        for (int64_t k = 0; k < m; ++k) pos[i + k] = cur + k;
+        cur += m;
+        i = e;
+    }
+    *tile = kScanTile;
+    return (int64_t)round_up((size_t)cur, kScanTile);
+}
+
+FitLayout plan(int64_t n, int64_t ld, int64_t tile, int p, int64_t G)
 {
     FitLayout L;
     L.n = n;
     L.p = p;
     L.G = (int)G;
-    L.ld = (int64_t)round_up((size_t)n, kRowPad);
+    L.ld = ld;
+    L.tile = tile;
+    L.ntc = (int)(ld / tile);
     L.ldz = (int64_t)round_up((size_t)std::max<int64_t>(G, 1), kRowPad);
     const int nt = (p + kTile - 1) / kTile;
     L.npairs = nt * (nt + 1) / 2;
@@ -141,6 +176,8 @@ FitLayout plan(int64_t n, int p, int64_t G)
     L.L = take(sizeof(double) * (size_t)p * p);
     L.part = take(sizeof(float) * (size_t)(L.nxr + L.nzr) * L.npairs * kTile * kTile);
     L.tilemax = take(sizeof(double) * L.ntile);
+    L.tpart = take(sizeof(double) * 2 * L.ntc);
+    L.cpart = take(sizeof(double) * 3 * (size_t)L.ntc * p);
     L.total = o;
     return L;
 }
@@ -195,7 +232,7 @@ struct cox_server {
     struct List {
         char *h = nullptr, *d = nullptr;
         size_t cap = 0;
-    } l_admit, l_eta, l_slots, l_cols, l_syrk;
+    } l_admit, l_eta, l_slots, l_cols, l_syrk, l_rows;
 
     std::vector<Slot> slots;
 
@@ -257,32 +294,34 @@ void fail_request_locked(cox_server *s, const Request &q, int code, double t)
 
 // ------------------------------------------------------------------ prep pool
 
-void write_image(const Request &q, const std::vector<int64_t> &perm, const std::vector<uint32_t> &meta, char *dst)
+void write_image(const Request &q, const std::vector<int64_t> &perm, const std::vector<uint32_t> &meta,
+                 const std::vector<int64_t> &pos, char *dst)
 {
     const FitLayout &L = q.lay;
     double *x = reinterpret_cast<double *>(dst + L.x);
     uint32_t *mw = reinterpret_cast<uint32_t *>(dst + L.meta);
     int32_t *gi = reinterpret_cast<int32_t *>(dst + L.gidx);
+    // padding rows: one-row strata without events, X = 0
+    for (int64_t i = 0; i < L.ld; ++i) {
+        mw[i] = kHeadBit | kPadBit;
+        gi[i] = -1;
+    }
     for (int64_t j = 0; j < q.p; ++j) {
         double *col = x + j * L.ld;
         const double *src = q.x + j * q.ldx;
-        for (int64_t i = 0; i < q.n; ++i) col[i] = src[perm[i]];
-        for (int64_t i = q.n; i < L.ld; ++i) col[i] = 0.0;
+        std::memset(col, 0, sizeof(double) * L.ld);
+        for (int64_t i = 0; i < q.n; ++i) col[pos[i]] = src[perm[i]];
     }
     int32_t g = 0;
     for (int64_t i = 0; i < q.n; ++i) {
-        mw[i] = meta[i];
-        gi[i] = (meta[i] & kCountMask) ? g++ : -1;
-    }
-    for (int64_t i = q.n; i < L.ld; ++i) {
-        mw[i] = kHeadBit | kPadBit;
-        gi[i] = -1;
+        mw[pos[i]] = meta[i];
+        gi[pos[i]] = (meta[i] & kCountMask) ? g++ : -1;
     }
 }
 
 void prep_loop(cox_server *s)
 {
-    std::vector<int64_t> perm;
+    std::vector<int64_t> perm, pos;
     std::vector<uint32_t> meta;
     for (;;) {
         std::unique_ptr<Request> q;
@@ -296,7 +335,9 @@ void prep_loop(cox_server *s)
         canonical_order(q->n, q->time, q->event, q->stratum, perm, meta);
         int64_t G = 0;
         for (int64_t i = 0; i < q->n; ++i) G += (meta[i] & kCountMask) ? 1 : 0;
-        q->lay = plan(q->n, (int)q->p, G);
+        int64_t tile = 0;
+        const int64_t ld = place_rows(meta, pos, &tile);
+        q->lay = plan(q->n, ld, tile, (int)q->p, G);
         {
             std::unique_lock<std::mutex> lk(s->mu);
             if (q->lay.total > s->arena_alloc.capacity() || q->lay.upload > s->stage_alloc.capacity()) {
@@ -306,7 +347,7 @@ void prep_loop(cox_server *s)
             s->cv_stage.wait(lk, [s, &q] { return s->stop || s->stage_alloc.alloc(q->lay.upload, &q->stage_off); });
             if (s->stop) return;
         }
-        write_image(*q, perm, meta, s->staging + q->stage_off);
+        write_image(*q, perm, meta, pos, s->staging + q->stage_off);
         {
             std::lock_guard<std::mutex> g(s->mu);
             s->ready_q.push_back(std::move(q));
@@ -362,8 +403,12 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off, int slot)
     F.L = reinterpret_cast<double *>(B + L.L);
     F.part = reinterpret_cast<float *>(B + L.part);
     F.tilemax = reinterpret_cast<double *>(B + L.tilemax);
+    F.tpart = reinterpret_cast<double *>(B + L.tpart);
+    F.cpart = reinterpret_cast<double *>(B + L.cpart);
     F.st = s->d_state + slot;
     F.n = L.n;
+    F.tile = L.tile;
+    F.ntc = L.ntc;
     F.ld = L.ld;
     F.ldz = L.ldz;
     F.p = L.p;
@@ -392,7 +437,9 @@ bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_
            in(F.eta, 8 * ld) && in(F.b, 8 * ld) && in(F.z, 4 * p * (size_t)L.ldz) && in(F.beta, 8 * p) &&
            in(F.prev, 8 * p) && in(F.grad, 8 * p) && in(F.diag2, 8 * p) && in(F.free_col, p) &&
            in(F.L, 8 * p * p) && in(F.part, 4 * (size_t)(L.nxr + L.nzr) * L.npairs * kTile * kTile) &&
-           in(F.tilemax, 8 * (size_t)L.ntile) && F.st == s->d_state + slot && F.p == L.p && F.ld == L.ld &&
+           in(F.tilemax, 8 * (size_t)L.ntile) && in(F.tpart, 16 * (size_t)L.ntc) &&
+           in(F.cpart, 24 * (size_t)L.ntc * p) && F.tile > 0 && F.ntc >= 1 && F.tile * F.ntc == F.ld &&
+           F.st == s->d_state + slot && F.p == L.p && F.ld == L.ld &&
            F.n <= F.ld && F.ld % kRowPad == 0 && F.ldz % kRowPad == 0 && F.G <= F.ldz && F.p >= 1 &&
            F.p <= kMaxP && F.ntile * (int64_t)kEtaRows >= F.ld;
 }
@@ -493,28 +540,34 @@ bool run_round(cox_server *s, WorkerState &ws, std::string &err)
     const bool launched = !act.empty();
     double t_launch = s->now();
     if (launched) {
-        size_t n_eta = 0, n_cols = 0, n_syrk = 0;
+        size_t n_eta = 0, n_cols = 0, n_syrk = 0, n_rows = 0;
         for (int sl : act) {
             const FitLayout &L = s->slots[sl].req->lay;
             n_eta += L.ntile;
-            n_cols += L.p;
+            n_rows += L.ntc;
+            n_cols += (size_t)L.ntc * L.p;
             if (!s->slots[sl].frozen) n_syrk += (size_t)L.npairs * (L.nxr + L.nzr);
         }
         if (!ensure_list(s->l_eta, sizeof(int2) * n_eta, err) || !ensure_list(s->l_cols, sizeof(int2) * n_cols, err) ||
             !ensure_list(s->l_syrk, sizeof(int4) * std::max<size_t>(n_syrk, 1), err) ||
-            !ensure_list(s->l_slots, sizeof(int) * act.size(), err))
+            !ensure_list(s->l_slots, sizeof(int) * act.size(), err) ||
+            !ensure_list(s->l_rows, sizeof(int2) * n_rows, err))
             return false;
+        int2 *rws = reinterpret_cast<int2 *>(s->l_rows.h);
         int2 *eta = reinterpret_cast<int2 *>(s->l_eta.h);
         int2 *cols = reinterpret_cast<int2 *>(s->l_cols.h);
         int4 *syrk = reinterpret_cast<int4 *>(s->l_syrk.h);
         int *sl_list = reinterpret_cast<int *>(s->l_slots.h);
-        size_t ke = 0, kc = 0, ks = 0;
+        size_t ke = 0, kc = 0, ks = 0, kr = 0;
         for (size_t a = 0; a < act.size(); ++a) {
             const int sl = act[a];
             const FitLayout &L = s->slots[sl].req->lay;
             sl_list[a] = sl;
             for (int t = 0; t < L.ntile; ++t) eta[ke++] = make_int2(sl, t);
-            for (int j = 0; j < L.p; ++j) cols[kc++] = make_int2(sl, j);
+            for (int t = 0; t < L.ntc; ++t) {
+                rws[kr++] = make_int2(sl, t);
+                for (int j = 0; j < L.p; ++j) cols[kc++] = make_int2(sl, (t << 10) | j);
+            }
             if (!s->slots[sl].frozen)
                 for (int pr = 0; pr < L.npairs; ++pr) {
                     for (int r = 0; r < L.nxr; ++r) syrk[ks++] = make_int4(sl, pr, r, 0);
@@ -530,9 +583,11 @@ bool run_round(cox_server *s, WorkerState &ws, std::string &err)
                    "lists");
         WCHECK(hipMemcpyAsync(s->l_slots.d, s->l_slots.h, sizeof(int) * act.size(), hipMemcpyHostToDevice, s->compute),
                "lists");
+        WCHECK(hipMemcpyAsync(s->l_rows.d, s->l_rows.h, sizeof(int2) * kr, hipMemcpyHostToDevice, s->compute), "lists");
         const int *dsl = reinterpret_cast<const int *>(s->l_slots.d);
         WCHECK((hipError_t)launch_eta(s->d_desc, reinterpret_cast<const int2 *>(s->l_eta.d), (int)ke, s->compute), "eta");
-        WCHECK((hipError_t)launch_rows(s->d_desc, dsl, (int)act.size(), s->compute), "rows");
+        WCHECK((hipError_t)launch_rows(s->d_desc, reinterpret_cast<const int2 *>(s->l_rows.d), (int)kr, s->compute),
+               "rows");
         WCHECK((hipError_t)launch_cols(s->d_desc, reinterpret_cast<const int2 *>(s->l_cols.d), (int)kc, s->compute),
                "cols");
         if (ks)
@@ -663,7 +718,7 @@ void free_server(cox_server *s)
     if (s->h_desc) (void)hipHostFree(s->h_desc);
     if (s->h_state) (void)hipHostFree(s->h_state);
     if (s->h_beta) (void)hipHostFree(s->h_beta);
-    for (cox_server::List *l : {&s->l_admit, &s->l_eta, &s->l_slots, &s->l_cols, &s->l_syrk}) {
+    for (cox_server::List *l : {&s->l_admit, &s->l_eta, &s->l_slots, &s->l_cols, &s->l_syrk, &s->l_rows}) {
         if (l->h) (void)hipHostFree(l->h);
         if (l->d) (void)hipFree(l->d);
     }
