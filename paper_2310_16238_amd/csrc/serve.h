@@ -19,8 +19,9 @@ namespace serve {
 constexpr int kMaxP = 128;        // columns of a served fit (its Cholesky factor lives in LDS)
 constexpr int kRowPad = 64;       // rows are padded to a multiple of this
 constexpr int kEtaRows = 256;     // rows per work item of the X beta kernel
-constexpr int kXRange = 4096;     // rows per K range of the X' diag(b) X contraction
+constexpr int kXRange = 4096;     // rows per K range of the X' diag(b) X contraction (4 waves of 1024)
 constexpr int kZRange = 4096;     // event groups per K range of the Z'Z contraction
+constexpr int kColBlock = 4;      // columns per wave of the column pass
 constexpr int kTile = 32;         // edge of a contraction tile (one MFMA block)
 constexpr int kScanTile = 4096;   // rows of a scan tile: a fit whose strata all fit one tile is laid
                                   // out so that every scan tile starts with a stratum head
@@ -55,11 +56,11 @@ struct FitDesc {
     float *xf;              // [p][ld] FP32 copy for the contraction
     const uint32_t *meta;   // [ld] row words (padding rows: head | pad)
     const int32_t *gidx;    // [ld] event-group index at group ends, else -1
-    double *eta, *w, *zq, *hz, *a, *b;   // [ld] row vectors (zq = (d/S0)/sqrt(d) at group ends)
+    double *eta, *w, *zq, *hz, *b;   // [ld] row vectors (zq = (d/S0)/sqrt(d) at group ends, b = w Lambda)
     float *z;               // [p][ldz] sqrt(d_g) xbar_g
     double *beta, *prev, *grad, *diag1, *diag2;   // [p]
     uint8_t *free_col;      // [p]
-    double *L;              // [p][p] Cholesky factor (row-major, lower)
+    double *L;              // [p][p] information matrix (info kernel), then its Cholesky factor (row-major, lower)
     float *part;            // [(nxr + nzr) * npairs][32 * 32] contraction partials
     double *tilemax;        // [ntile]
     double *tpart;          // [ntc][2] per scan tile: objective part, range flag
@@ -76,12 +77,18 @@ struct FitDesc {
     int freeze;             // 1: keep the factor once steps are small (reduced-precision contraction)
 };
 
+static_assert(sizeof(FitDesc) % 8 == 0, "descriptors are copied in 8-byte words");
+
 // Launchers (return a hipError_t value).  Work-item arrays are device memory.
-int launch_admit(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
+// admit: `joining` holds the descriptors of the fits that join (copied to
+// fits[slots[k]] by the kernel); items are (k, 256-row tile).
+int launch_admit(FitDesc *fits, const FitDesc *joining, const int *slots, const int2 *items, int nitems,
+                 hipStream_t s);
 int launch_eta(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_rows(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_cols(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_syrk(const FitDesc *fits, const int4 *items, int nitems, hipStream_t s);
+int launch_info(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_step(const FitDesc *fits, const int *slots, int nslots, int max_p, hipStream_t s);
 
 }  // namespace serve

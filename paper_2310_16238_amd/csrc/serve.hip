@@ -1,21 +1,23 @@
 // serve.hip -- batched kernels of the fit server (gfx950).
 //
-// One Newton iteration of every resident fit is five launches:
+// Fits join through `admit` (descriptor, FP32 copy of X, cleared state).  One
+// Newton iteration of every resident fit is six launches:
 //   eta   (fit, 256-row tile)  X beta in FP64 and the tile's max of X beta
 //   rows  (fit, scan tile)     w = exp(X beta - c), forward segmented scan of w
 //                              (S0), d/S0 and (d/S0)/sqrt(d) at group ends and the
 //                              objective, reverse
 //                              segmented scan of d/S0 (Lambda), a = w Lambda - delta,
 //                              b = w Lambda
-//   cols  (fit, scan tile, column)
+//   cols  (fit, scan tile, 4 columns)
 //                              one wave: forward segmented scan of w x_j (S1),
 //                              xbar = S1/S0 at group ends, z = sqrt(d) xbar,
 //                              score X'a, diagonal (X o X)'b - sum d xbar^2
 //   syrk  (fit, tile pair, K range, product)
-//                              one wave: a 32 x 32 tile of X' diag(b) X or Z'Z on
-//                              the matrix cores (v_mfma_f32_32x32x2f32, FP32)
-//   step  (fit)                the information matrix from the partials (FP64),
-//                              Cholesky in LDS, the Newton step and the fit's
+//                              four waves: a 32 x 32 tile of X' diag(b) X or Z'Z
+//                              on the matrix cores (v_mfma_f32_32x32x2f32, FP32)
+//   info  (fit, tile pair)     the K-range partials summed in FP64 in range order:
+//                              the information matrix
+//   step  (fit)                Cholesky in LDS, the Newton step and the fit's
 //                              state machine (halving, freezing, convergence)
 // The sums follow Eqs. strat_l, strat_g and strat_h with the order of the sums
 // over events and risk sets exchanged (the Lambda form).
@@ -47,13 +49,30 @@ __device__ __forceinline__ double wave_max(double v)
 
 // ------------------------------------------------------------------ admit: FP32 copy of X
 
-__global__ __launch_bounds__(256) void admit_kernel(const FitDesc *fits, const int2 *items)
+// Item (k, t): rows [256 t, 256 t + 256) of joining fit k.  The items of a fit
+// also clear its z (grid-stride over the fit's items); item 0 installs the
+// descriptor in the fit's slot and clears beta, the previous beta and the state.
+__global__ __launch_bounds__(256) void admit_kernel(FitDesc *fits, const FitDesc *joining, const int *slots,
+                                                    const int2 *items)
 {
     const int2 it = items[blockIdx.x];
-    const FitDesc F = fits[it.x];
-    const int64_t r = (int64_t)it.y * 256 + threadIdx.x;
-    if (r >= F.ld) return;
-    for (int j = 0; j < F.p; ++j) F.xf[(int64_t)j * F.ld + r] = (float)F.x[(int64_t)j * F.ld + r];
+    const FitDesc &F = joining[it.x];
+    const int x = threadIdx.x;
+    const int64_t r = (int64_t)it.y * 256 + x;
+    if (r < F.ld)
+        for (int j = 0; j < F.p; ++j) F.xf[(int64_t)j * F.ld + r] = (float)F.x[(int64_t)j * F.ld + r];
+    const int64_t nz = (int64_t)F.p * F.ldz, stride = (int64_t)F.ntile * 256;
+    for (int64_t e = (int64_t)it.y * 256 + x; e < nz; e += stride) F.z[e] = 0.0f;
+    if (it.y == 0) {
+        if (x < F.p) {
+            F.beta[x] = 0.0;
+            F.prev[x] = 0.0;
+        }
+        if (x < (int)(sizeof(FitState) / 4)) reinterpret_cast<uint32_t *>(F.st)[x] = 0u;
+        uint64_t *dst = reinterpret_cast<uint64_t *>(fits + slots[it.x]);
+        const uint64_t *src = reinterpret_cast<const uint64_t *>(&F);
+        if (x < (int)(sizeof(FitDesc) / 8)) dst[x] = src[x];
+    }
 }
 
 // ------------------------------------------------------------------ eta
@@ -66,11 +85,18 @@ __global__ __launch_bounds__(kEtaRows) void eta_kernel(const FitDesc *fits, cons
     const int64_t r = (int64_t)it.y * kEtaRows + threadIdx.x;
     double mx = -INFINITY;
     if (r < F.ld) {
+        // every column, in order (X is finite, so a zero coefficient adds a zero)
+        const double *xr = F.x + r;
         double e = 0.0;
-        for (int j = 0; j < F.p; ++j) {
-            const double bj = F.beta[j];
-            if (bj != 0.0) e = fma(F.x[(int64_t)j * F.ld + r], bj, e);
+        int j = 0;
+        for (; j + 8 <= F.p; j += 8) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = xr[(int64_t)(j + q) * F.ld];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) e = fma(v[q], F.beta[j + q], e);
         }
+        for (; j < F.p; ++j) e = fma(xr[(int64_t)j * F.ld], F.beta[j], e);
         F.eta[r] = e;
         if (!(F.meta[r] & kPadBit)) mx = e;
     }
@@ -204,9 +230,7 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, 
             run = seg_combine(run, e[i]);
             if (k < len) {
                 const int64_t r = r_end - 1 - k;
-                const double wl = F.w[r] * run.v[0];
-                F.b[r] = wl;
-                F.a[r] = wl - ((F.meta[r] & kEventBit) ? 1.0 : 0.0);
+                F.b[r] = F.w[r] * run.v[0];
             }
         }
         carry = seg_combine(carry, btot);
@@ -224,64 +248,116 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, 
 
 constexpr int kColWaves = 4, kColIpt = 4, kColChunk = kWave * kColIpt;
 
+__device__ __forceinline__ void load4(const double *p, double *v)
+{
+    const double2 lo = *reinterpret_cast<const double2 *>(p);
+    const double2 hi = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = lo.x;
+    v[1] = lo.y;
+    v[2] = hi.x;
+    v[3] = hi.y;
+}
+
+// One wave per (fit, scan tile, block of kColBlock columns): the row vectors
+// (w, b, zq, row words, group indices) are loaded once per chunk for all the
+// block's columns, whose scans share one flag.  Lanes own 4 consecutive rows
+// (scan tiles and the padded row count are multiples of 64, so a lane's rows
+// are all in the tile or all past it).
 __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *fits, const int2 *items, int nitems)
 {
+    constexpr int CB = kColBlock;
     const int lane = threadIdx.x & (kWave - 1);
     // the item index is the same in all lanes of a wave
     const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kColWaves + threadIdx.x / kWave);
     if (item >= nitems) return;   // whole wave; no workgroup barrier below
     const int2 it = items[item];
     const FitDesc F = fits[it.x];
-    const int tt = it.y >> 10, j = it.y & 1023;   // (scan tile, column)
+    const int tt = it.y >> 10, j0 = it.y & 1023;   // (scan tile, first column of the block)
     const int64_t r_begin = (int64_t)tt * F.tile;
-    const int64_t n = r_begin + F.tile < F.ld ? r_begin + F.tile : F.ld;
-    const double *xj = F.x + (int64_t)j * F.ld;
-    float *zj = F.z + (int64_t)j * F.ldz;
-    double g = 0.0, d1 = 0.0, d2 = 0.0;
-    SegVal<1> carry = seg_identity<1>();
-    for (int64_t base = r_begin; base < n; base += kColChunk) {
+    const int64_t r_end = r_begin + F.tile < F.ld ? r_begin + F.tile : F.ld;
+    const double *xc[CB];
+    bool live[CB];
+    double g[CB], d1[CB], d2[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        live[c] = j0 + c < F.p;
+        xc[c] = F.x + (int64_t)(live[c] ? j0 + c : j0) * F.ld;
+        g[c] = d1[c] = d2[c] = 0.0;
+    }
+    SegVal<CB> carry = seg_identity<CB>();
+    for (int64_t base = r_begin; base < r_end; base += kColChunk) {
         const int64_t r0 = base + (int64_t)lane * kColIpt;
-        SegVal<1> e[kColIpt];
+        const bool in = r0 < r_end;
+        double xv[CB][kColIpt], wv[kColIpt], bv[kColIpt], qv[kColIpt];
         uint32_t m[kColIpt];
-        SegVal<1> tot = seg_identity<1>();
+        int32_t gi[kColIpt];
+        if (in) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c) load4(xc[c] + r0, xv[c]);
+            load4(F.w + r0, wv);
+            load4(F.b + r0, bv);
+            load4(F.zq + r0, qv);
+            const uint4 mm = *reinterpret_cast<const uint4 *>(F.meta + r0);
+            const int4 gg = *reinterpret_cast<const int4 *>(F.gidx + r0);
+            m[0] = mm.x;
+            m[1] = mm.y;
+            m[2] = mm.z;
+            m[3] = mm.w;
+            gi[0] = gg.x;
+            gi[1] = gg.y;
+            gi[2] = gg.z;
+            gi[3] = gg.w;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kColIpt; ++i) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c) xv[c][i] = 0.0;
+                wv[i] = bv[i] = qv[i] = 0.0;
+                m[i] = 0u;
+                gi[i] = 0;
+            }
+        }
+        SegVal<CB> e[kColIpt];
+        SegVal<CB> tot = seg_identity<CB>();
 #pragma unroll
         for (int i = 0; i < kColIpt; ++i) {
-            const int64_t r = r0 + i;
-            if (r < n) {
-                m[i] = F.meta[r];
-                const double xv = xj[r];
-                e[i].f = m[i] >> 31;
-                e[i].v[0] = F.w[r] * xv;
-                g = fma(xv, F.a[r], g);
-                d1 = fma(xv * xv, F.b[r], d1);
-            } else {
-                m[i] = 0u;
-                e[i] = seg_identity<1>();
+            const double aw = bv[i] - ((m[i] & kEventBit) ? 1.0 : 0.0);   // w Lambda - delta
+            e[i].f = m[i] >> 31;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                g[c] = fma(xv[c][i], aw, g[c]);
+                d1[c] = fma(xv[c][i] * xv[c][i], bv[i], d1[c]);
+                e[i].v[c] = wv[i] * xv[c][i];
             }
             tot = seg_combine(tot, e[i]);
         }
-        const SegVal<1> inc = wave_inclusive_scan(tot);
-        SegVal<1> run = seg_combine(carry, wave_shift_right(inc));
+        const SegVal<CB> inc = wave_inclusive_scan(tot);
+        SegVal<CB> run = seg_combine(carry, wave_shift_right(inc));
 #pragma unroll
         for (int i = 0; i < kColIpt; ++i) {
             run = seg_combine(run, e[i]);
             if (m[i] & kCountMask) {
-                const int64_t r = r0 + i;
-                const double zv = run.v[0] * F.zq[r];   // sqrt(d) xbar
-                d2 = fma(zv, zv, d2);
-                zj[F.gidx[r]] = (float)zv;
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    const double zv = run.v[c] * qv[i];   // sqrt(d) xbar
+                    if (live[c]) {
+                        d2[c] = fma(zv, zv, d2[c]);
+                        F.z[(int64_t)(j0 + c) * F.ldz + gi[i]] = (float)zv;
+                    }
+                }
             }
         }
         carry = seg_combine(carry, lane63_seg(inc));
     }
-    g = wave_sum(g);
-    d1 = wave_sum(d1);
-    d2 = wave_sum(d2);
-    if (lane == 0) {
-        double *o = F.cpart + ((int64_t)tt * F.p + j) * 3;
-        o[0] = g;
-        o[1] = d1;
-        o[2] = d2;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        const double gc = wave_sum(g[c]), s1 = wave_sum(d1[c]), s2 = wave_sum(d2[c]);
+        if (lane == 0 && live[c]) {
+            double *o = F.cpart + ((int64_t)tt * F.p + j0 + c) * 3;
+            o[0] = gc;
+            o[1] = s1;
+            o[2] = s2;
+        }
     }
 }
 
@@ -308,12 +384,15 @@ __device__ __forceinline__ int pair_index(int ti, int tj, int nt)
 
 constexpr int kSyrkWaves = 4;
 
-__global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc *fits, const int4 *items, int nitems)
+// One workgroup per (fit, tile pair, K range, product): wave v takes the v-th
+// quarter of the K range, and the four accumulators are added in wave order.
+// Rows of X (event groups of Z) come in steps of 8 -- 4 consecutive per half-wave,
+// as float4 -- with the next step's operands loaded before this step's products.
+__global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc *fits, const int4 *items)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kSyrkWaves + threadIdx.x / kWave);
-    if (item >= nitems) return;   // whole wave
-    const int4 it = items[item];
+    __shared__ float red[kSyrkWaves - 1][16][kWave];
+    const int lane = threadIdx.x & (kWave - 1), v = threadIdx.x / kWave;
+    const int4 it = items[blockIdx.x];
     const FitDesc F = fits[it.x];
     const int nt = tile_count(F.p);
     int ti, tj;
@@ -321,33 +400,63 @@ __global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc 
     const bool zpart = it.w != 0;
     const float *u = zpart ? F.z : F.xf;
     const int64_t ldu = zpart ? F.ldz : F.ld;
-    const int64_t k0 = (int64_t)it.z * (zpart ? kZRange : kXRange);
-    const int64_t kend = k0 + (zpart ? kZRange : kXRange);
-    const int64_t k1 = kend < ldu ? kend : ldu;
+    const int64_t range = zpart ? kZRange : kXRange, quarter = range / kSyrkWaves;
+    const int64_t k0 = (int64_t)it.z * range + v * quarter;
+    const int64_t k1 = k0 + quarter < ldu ? k0 + quarter : ldu;   // ldu is a multiple of 64: steps of 8 fit
     const double *c = zpart ? nullptr : F.b;
     const int ra = ti * kTile + (lane & 31), rb = tj * kTile + (lane & 31);
+    const bool la = ra < F.p, lb = rb < F.p;
     const int kofs = 4 * (lane >> 5);
-    const float *ua = u + (int64_t)(ra < F.p ? ra : 0) * ldu;
-    const float *ub = u + (int64_t)(rb < F.p ? rb : 0) * ldu;
+    const float *ua = u + (int64_t)(la ? ra : 0) * ldu + kofs;
+    const float *ub = u + (int64_t)(lb ? rb : 0) * ldu + kofs;
+    const double *cc = c ? c + kofs : nullptr;
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    float4 an = make_float4(0.f, 0.f, 0.f, 0.f), bn = an;
+    double2 cl = make_double2(1.0, 1.0), ch = cl;
+    if (k0 < k1) {
+        an = *reinterpret_cast<const float4 *>(ua + k0);
+        bn = *reinterpret_cast<const float4 *>(ub + k0);
+        if (cc) {
+            cl = *reinterpret_cast<const double2 *>(cc + k0);
+            ch = *reinterpret_cast<const double2 *>(cc + k0 + 2);
+        }
+    }
     for (int64_t k = k0; k < k1; k += 8) {
-        const int64_t kk = k + kofs;
-        float4 av = *reinterpret_cast<const float4 *>(ua + kk);
-        float4 bv = *reinterpret_cast<const float4 *>(ub + kk);
-        if (ra >= F.p) av = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (rb >= F.p) bv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (c) {
-            av.x *= (float)c[kk];
-            av.y *= (float)c[kk + 1];
-            av.z *= (float)c[kk + 2];
-            av.w *= (float)c[kk + 3];
+        float4 av = an, bv = bn;
+        const double2 l = cl, h = ch;
+        if (k + 8 < k1) {
+            an = *reinterpret_cast<const float4 *>(ua + k + 8);
+            bn = *reinterpret_cast<const float4 *>(ub + k + 8);
+            if (cc) {
+                cl = *reinterpret_cast<const double2 *>(cc + k + 8);
+                ch = *reinterpret_cast<const double2 *>(cc + k + 10);
+            }
+        }
+        if (!la) av = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (!lb) bv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (cc) {
+            av.x *= (float)l.x;
+            av.y *= (float)l.y;
+            av.z *= (float)h.x;
+            av.w *= (float)h.y;
         }
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.x, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv.y, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, bv.z, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, bv.w, acc, 0, 0, 0);
+    }
+    if (v > 0) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) red[v - 1][i][lane] = acc[i];
+    }
+    __syncthreads();
+    if (v != 0) return;
+#pragma unroll
+    for (int w = 0; w < kSyrkWaves - 1; ++w) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] += red[w][i][lane];
     }
     const int slot = zpart ? F.nxr + it.z : it.z;
     float *out = F.part + ((int64_t)slot * F.npairs + it.y) * (kTile * kTile);
@@ -355,6 +464,49 @@ __global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc 
     for (int i = 0; i < 16; ++i) {
         const int m = 8 * (i / 4) + 4 * (lane >> 5) + (i % 4), nn = lane & 31;
         out[m * kTile + nn] = acc[i];
+    }
+}
+
+// ------------------------------------------------------------------ info
+
+// One workgroup per (fit, tile pair): entry (m, n) of the pair's 32 x 32 block
+// of I = X' diag(b) X - Z'Z is the FP64 sum of its K-range partials in range
+// order, written to both triangles of F.L (entries below the diagonal of a
+// diagonal block are taken from above it).
+__global__ __launch_bounds__(256) void info_kernel(const FitDesc *fits, const int2 *items)
+{
+    const int2 it = items[blockIdx.x];
+    const FitDesc F = fits[it.x];
+    const int nt = tile_count(F.p), p = F.p;
+    int ti, tj;
+    pair_tiles(it.y, nt, ti, tj);
+    const int e0 = threadIdx.x * 4;   // entries e0 .. e0 + 3: one row m, columns n .. n + 3
+    double sx[4] = {0.0, 0.0, 0.0, 0.0}, sz[4] = {0.0, 0.0, 0.0, 0.0};
+    const float *base = F.part + (int64_t)it.y * (kTile * kTile) + e0;
+    const int64_t step = (int64_t)F.npairs * (kTile * kTile);
+    for (int r = 0; r < F.nxr; ++r) {
+        const float4 q = *reinterpret_cast<const float4 *>(base + r * step);
+        sx[0] += (double)q.x;
+        sx[1] += (double)q.y;
+        sx[2] += (double)q.z;
+        sx[3] += (double)q.w;
+    }
+    for (int r = 0; r < F.nzr; ++r) {
+        const float4 q = *reinterpret_cast<const float4 *>(base + (F.nxr + r) * step);
+        sz[0] += (double)q.x;
+        sz[1] += (double)q.y;
+        sz[2] += (double)q.z;
+        sz[3] += (double)q.w;
+    }
+    const int m = e0 / kTile, i = ti * kTile + m;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int n = (e0 % kTile) + q, j = tj * kTile + n;
+        if (i < p && j < p && (ti < tj || m <= n)) {
+            const double val = sx[q] - sz[q];
+            F.L[(int64_t)i * p + j] = val;
+            F.L[(int64_t)j * p + i] = val;
+        }
     }
 }
 
@@ -366,8 +518,8 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
 {
     extern __shared__ double lds[];   // A[p * p], y[p]
     __shared__ int s_action, s_bad, s_frozen;
+    __shared__ uint8_t s_free[kMaxP];
     __shared__ double s_red[kStepThreads / kWave];
-    __shared__ double s_piv;
     const FitDesc F = fits[slots[blockIdx.x]];
     FitState *st = F.st;
     const int t = threadIdx.x, p = F.p;
@@ -429,79 +581,84 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
         __syncthreads();
     }
     const bool frozen = s_frozen != 0;
+    const int wv = t / kWave, lane = t & (kWave - 1);
+    constexpr int kWaves = kStepThreads / kWave;
+    for (int j = t; j < p; j += kStepThreads) s_free[j] = F.free_col[j];
+    __syncthreads();
     if (!frozen) {
-        // I = X' diag(b) X - Z'Z from the upper-triangle tiles, partials summed in FP64 in range order
-        const int nt = tile_count(p);
-        for (int e = t; e < p * p; e += kStepThreads) {
-            const int i = e / p, j = e % p;
-            if (j < i) continue;
-            const int ti = i / kTile, tj = j / kTile;
-            const int pair = pair_index(ti, tj, nt);
-            const int off = (i % kTile) * kTile + (j % kTile);
-            double sx = 0.0, sz = 0.0;
-            for (int r = 0; r < F.nxr; ++r) sx += (double)F.part[((int64_t)r * F.npairs + pair) * (kTile * kTile) + off];
-            for (int r = 0; r < F.nzr; ++r)
-                sz += (double)F.part[((int64_t)(F.nxr + r) * F.npairs + pair) * (kTile * kTile) + off];
-            double v = sx - sz;
-            if (!F.free_col[i] || !F.free_col[j]) v = (i == j) ? 1.0 : 0.0;
-            A[i * p + j] = v;
-            A[j * p + i] = v;
-        }
-        __syncthreads();
-        // right-looking Cholesky, lower triangle
-        for (int k = 0; k < p; ++k) {
-            if (t == 0) {
-                double d = A[k * p + k];
-                if (!(d > 0.0)) {
-                    s_bad = 1;
-                    d = 1.0;
-                }
-                s_piv = sqrt(d);
-                A[k * p + k] = s_piv;
+        // the information matrix (info kernel); rows and columns not free become unit rows
+        for (int i = wv; i < p; i += kWaves)
+            for (int j = lane; j < p; j += kWave) {
+                double v = F.L[(int64_t)i * p + j];
+                if (!s_free[i] || !s_free[j]) v = (i == j) ? 1.0 : 0.0;
+                A[i * p + j] = v;
             }
-            __syncthreads();
-            const double piv = s_piv;
+        __syncthreads();
+        // right-looking Cholesky of the lower triangle: per column, scale it by the
+        // pivot, then update the trailing triangle (row i by one wave, lanes over j)
+        for (int k = 0; k < p; ++k) {
+            double d = A[k * p + k];
+            const bool ok = d > 0.0;
+            if (!ok) d = 1.0;
+            const double piv = sqrt(d);
             for (int i = k + 1 + t; i < p; i += kStepThreads) A[i * p + k] /= piv;
             __syncthreads();
-            const int m = p - k - 1;
-            for (int e = t; e < m * m; e += kStepThreads) {
-                const int i = k + 1 + e / m, j = k + 1 + e % m;
-                if (j <= i) A[i * p + j] -= A[i * p + k] * A[j * p + k];
+            if (t == 0) {
+                A[k * p + k] = piv;
+                if (!ok) s_bad = 1;
+            }
+            for (int i = k + 1 + wv; i < p; i += kWaves) {
+                const double lik = A[i * p + k];
+                for (int j = k + 1 + lane; j <= i; j += kWave) A[i * p + j] -= lik * A[j * p + k];
             }
             __syncthreads();
         }
-        for (int e = t; e < p * p; e += kStepThreads) F.L[e] = A[e];
+        for (int i = wv; i < p; i += kWaves)
+            for (int j = lane; j < p; j += kWave) F.L[(int64_t)i * p + j] = A[i * p + j];
     } else {
-        for (int e = t; e < p * p; e += kStepThreads) A[e] = F.L[e];
+        for (int i = wv; i < p; i += kWaves)
+            for (int j = lane; j < p; j += kWave) A[i * p + j] = F.L[(int64_t)i * p + j];
     }
     // score on the free columns; kkt = max |score|
     double kk = 0.0;
     for (int j = t; j < p; j += kStepThreads) {
-        const double gj = F.free_col[j] ? F.grad[j] : 0.0;
+        const double gj = s_free[j] ? F.grad[j] : 0.0;
         y[j] = -gj;
         kk = fmax(kk, fabs(gj));
     }
     kk = wave_max(kk);
-    if ((t & (kWave - 1)) == 0) s_red[t / kWave] = kk;
+    if (lane == 0) s_red[wv] = kk;
     __syncthreads();
-    // L y = -g, then L' dx = y
-    for (int k = 0; k < p; ++k) {
-        if (t == 0) y[k] /= A[k * p + k];
-        __syncthreads();
-        const double yk = y[k];
-        for (int i = k + 1 + t; i < p; i += kStepThreads) y[i] -= A[i * p + k] * yk;
-        __syncthreads();
+    // L y = -g, then L' dx = y, by wave 0: lane l holds entries l and l + 64
+    if (wv == 0) {
+        double y0 = lane < p ? y[lane] : 0.0, y1 = lane + kWave < p ? y[lane + kWave] : 0.0;
+        for (int k = 0; k < p; ++k) {
+            const double own = k < kWave ? y0 : y1;
+            const double yk = __shfl(own, k & (kWave - 1), kWave) / A[k * p + k];
+            if (lane == (k & (kWave - 1))) {
+                if (k < kWave) y0 = yk;
+                else y1 = yk;
+            }
+            if (lane > k && lane < p) y0 -= A[lane * p + k] * yk;
+            if (lane + kWave > k && lane + kWave < p) y1 -= A[(lane + kWave) * p + k] * yk;
+        }
+        for (int k = p - 1; k >= 0; --k) {
+            const double own = k < kWave ? y0 : y1;
+            const double xk = __shfl(own, k & (kWave - 1), kWave) / A[k * p + k];
+            if (lane == (k & (kWave - 1))) {
+                if (k < kWave) y0 = xk;
+                else y1 = xk;
+            }
+            if (lane < k) y0 -= A[k * p + lane] * xk;
+            if (lane + kWave < k) y1 -= A[k * p + lane + kWave] * xk;
+        }
+        if (lane < p) y[lane] = y0;
+        if (lane + kWave < p) y[lane + kWave] = y1;
     }
-    for (int k = p - 1; k >= 0; --k) {
-        if (t == 0) y[k] /= A[k * p + k];
-        __syncthreads();
-        const double xk = y[k];
-        for (int i = t; i < k; i += kStepThreads) y[i] -= A[k * p + i] * xk;
-        __syncthreads();
-    }
+    __syncthreads();
     double smax = 0.0, bmax = 0.0;
     for (int j = t; j < p; j += kStepThreads) {
-        const double dx = F.free_col[j] ? y[j] : 0.0;
+        const double dx = s_free[j] ? y[j] : 0.0;
         const double b0 = F.beta[j];
         const double b1 = b0 + dx;
         F.prev[j] = b0;
@@ -526,7 +683,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
         }
         int flags = st->flags | kHaveFree;
         int pinned = 0;
-        for (int j = 0; j < p; ++j) pinned += F.free_col[j] ? 0 : 1;
+        for (int j = 0; j < p; ++j) pinned += s_free[j] ? 0 : 1;
         st->n_pinned = pinned;
         st->kkt = kkt;
         st->obj = st->obj_eval;
@@ -553,9 +710,10 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
 
 }  // namespace
 
-int launch_admit(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s)
+int launch_admit(FitDesc *fits, const FitDesc *joining, const int *slots, const int2 *items, int nitems,
+                 hipStream_t s)
 {
-    if (nitems > 0) admit_kernel<<<nitems, 256, 0, s>>>(fits, items);
+    if (nitems > 0) admit_kernel<<<nitems, 256, 0, s>>>(fits, joining, slots, items);
     return (int)hipGetLastError();
 }
 
@@ -579,8 +737,13 @@ int launch_cols(const FitDesc *fits, const int2 *items, int nitems, hipStream_t 
 
 int launch_syrk(const FitDesc *fits, const int4 *items, int nitems, hipStream_t s)
 {
-    if (nitems > 0)
-        syrk_kernel<<<(nitems + kSyrkWaves - 1) / kSyrkWaves, kWave * kSyrkWaves, 0, s>>>(fits, items, nitems);
+    if (nitems > 0) syrk_kernel<<<nitems, kWave * kSyrkWaves, 0, s>>>(fits, items);
+    return (int)hipGetLastError();
+}
+
+int launch_info(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s)
+{
+    if (nitems > 0) info_kernel<<<nitems, 256, 0, s>>>(fits, items);
     return (int)hipGetLastError();
 }
 

@@ -103,7 +103,7 @@ struct FitLayout {
     int64_t n = 0, ld = 0, ldz = 0, tile = 0;
     int p = 0, G = 0, nxr = 0, nzr = 0, npairs = 0, ntile = 0, ntc = 0;
     size_t x = 0, meta = 0, gidx = 0, upload = 0;   // [x | meta | gidx] is uploaded in one copy
-    size_t xf = 0, rows = 0, z = 0, beta = 0, prev = 0, zero_end = 0;
+    size_t xf = 0, rows = 0, z = 0, beta = 0, prev = 0;
     size_t vec = 0, free_col = 0, L = 0, part = 0, tilemax = 0, tpart = 0, cpart = 0, total = 0;
 };
 
@@ -166,11 +166,10 @@ FitLayout plan(int64_t n, int64_t ld, int64_t tile, int p, int64_t G)
     L.gidx = take(sizeof(int32_t) * (size_t)L.ld);
     L.upload = o;
     L.xf = take(sizeof(float) * (size_t)p * L.ld);
-    L.rows = take(sizeof(double) * 6 * (size_t)L.ld);
+    L.rows = take(sizeof(double) * 5 * (size_t)L.ld);
     L.z = take(sizeof(float) * (size_t)p * L.ldz);   // zeroed at admission, with beta and prev
     L.beta = take(sizeof(double) * p);
     L.prev = take(sizeof(double) * p);
-    L.zero_end = o;
     L.vec = take(sizeof(double) * 3 * p);
     L.free_col = take((size_t)p);
     L.L = take(sizeof(double) * (size_t)p * p);
@@ -232,7 +231,7 @@ struct cox_server {
     struct List {
         char *h = nullptr, *d = nullptr;
         size_t cap = 0;
-    } l_admit, l_eta, l_slots, l_cols, l_syrk, l_rows;
+    } l_round;   // one block per round: joining descriptors and every work list
 
     std::vector<Slot> slots;
 
@@ -390,8 +389,7 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off, int slot)
     F.w = rows + L.ld;
     F.zq = rows + 2 * L.ld;
     F.hz = rows + 3 * L.ld;
-    F.a = rows + 4 * L.ld;
-    F.b = rows + 5 * L.ld;
+    F.b = rows + 4 * L.ld;
     F.z = reinterpret_cast<float *>(B + L.z);
     F.beta = reinterpret_cast<double *>(B + L.beta);
     F.prev = reinterpret_cast<double *>(B + L.prev);
@@ -434,11 +432,12 @@ bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_
     };
     const size_t p = (size_t)L.p, ld = (size_t)L.ld;
     return in(F.x, 8 * p * ld) && in(F.xf, 4 * p * ld) && in(F.meta, 4 * ld) && in(F.gidx, 4 * ld) &&
-           in(F.eta, 8 * ld) && in(F.b, 8 * ld) && in(F.z, 4 * p * (size_t)L.ldz) && in(F.beta, 8 * p) &&
+           in(F.eta, 8 * ld) && in(F.w, 8 * ld) && in(F.zq, 8 * ld) && in(F.hz, 8 * ld) && in(F.b, 8 * ld) && in(F.z, 4 * p * (size_t)L.ldz) && in(F.beta, 8 * p) &&
            in(F.prev, 8 * p) && in(F.grad, 8 * p) && in(F.diag2, 8 * p) && in(F.free_col, p) &&
            in(F.L, 8 * p * p) && in(F.part, 4 * (size_t)(L.nxr + L.nzr) * L.npairs * kTile * kTile) &&
            in(F.tilemax, 8 * (size_t)L.ntile) && in(F.tpart, 16 * (size_t)L.ntc) &&
-           in(F.cpart, 24 * (size_t)L.ntc * p) && F.tile > 0 && F.ntc >= 1 && F.tile * F.ntc == F.ld &&
+           in(F.cpart, 24 * (size_t)L.ntc * p) && F.tile > 0 && F.tile % kRowPad == 0 && F.ntc >= 1 &&
+           F.tile * F.ntc == F.ld &&
            F.st == s->d_state + slot && F.p == L.p && F.ld == L.ld &&
            F.n <= F.ld && F.ld % kRowPad == 0 && F.ldz % kRowPad == 0 && F.G <= F.ldz && F.p >= 1 &&
            F.p <= kMaxP && F.ntile * (int64_t)kEtaRows >= F.ld;
@@ -498,12 +497,9 @@ bool admit_ready(cox_server *s, WorkerState &ws, std::string &err)
             err = "internal error: a fit descriptor points outside its block";
             return false;
         }
+        // the descriptor is installed, and z, beta and the state cleared, by the admit kernel
         WCHECK(hipMemcpyAsync(B, s->staging + q.stage_off, q.lay.upload, hipMemcpyHostToDevice, s->copy),
                "uploading a fit");
-        WCHECK(hipMemsetAsync(B + q.lay.z, 0, q.lay.zero_end - q.lay.z, s->copy), "clearing a fit");
-        WCHECK(hipMemcpyAsync(s->d_desc + slot, s->h_desc + slot, sizeof(FitDesc), hipMemcpyHostToDevice, s->copy),
-               "uploading a descriptor");
-        WCHECK(hipMemsetAsync(s->d_state + slot, 0, sizeof(FitState), s->copy), "clearing a fit state");
         S.req = std::move(tk.second);
         ws.uploading.push_back(slot);
     }
@@ -512,88 +508,113 @@ bool admit_ready(cox_server *s, WorkerState &ws, std::string &err)
     return true;
 }
 
+// Carves the round block into typed arrays at 16-byte aligned offsets.
+struct Packer {
+    size_t used = 0;
+    template <class T>
+    size_t take(size_t count)
+    {
+        const size_t at = used;
+        used = round_up(used + sizeof(T) * count, 16);
+        return at;
+    }
+};
+
 bool run_round(cox_server *s, WorkerState &ws, std::string &err)
 {
-    // 1. fits uploaded in the previous round join: FP32 copy of X
+    // fits uploaded in the previous round join this round
     std::vector<int> joining;
     if (ws.copy_pending) {
         WCHECK(hipStreamWaitEvent(s->compute, ws.copy_ev, 0), "ordering the upload");
         joining.swap(ws.uploading);
         ws.copy_pending = false;
-        size_t nitems = 0;
-        for (int sl : joining) nitems += (size_t)s->slots[sl].req->lay.ntile;
-        if (!ensure_list(s->l_admit, sizeof(int2) * std::max<size_t>(nitems, 1), err)) return false;
-        int2 *it = reinterpret_cast<int2 *>(s->l_admit.h);
-        size_t k = 0;
-        for (int sl : joining)
-            for (int t = 0; t < s->slots[sl].req->lay.ntile; ++t) it[k++] = make_int2(sl, t);
-        WCHECK(hipMemcpyAsync(s->l_admit.d, s->l_admit.h, sizeof(int2) * k, hipMemcpyHostToDevice, s->compute),
-               "admit list");
-        WCHECK((hipError_t)launch_admit(s->d_desc, reinterpret_cast<const int2 *>(s->l_admit.d), (int)k, s->compute),
-               "admit kernel");
-        for (int sl : joining) s->slots[sl].active = true;
     }
-    // 2. one Newton iteration of every active fit
     std::vector<int> act;
     for (int i = 0; i < (int)s->slots.size(); ++i)
-        if (s->slots[i].used && s->slots[i].active) act.push_back(i);
+        if (s->slots[i].used && (s->slots[i].active || std::find(joining.begin(), joining.end(), i) != joining.end()))
+            act.push_back(i);
+    for (int sl : joining) s->slots[sl].active = true;
     const bool launched = !act.empty();
     double t_launch = s->now();
     if (launched) {
-        size_t n_eta = 0, n_cols = 0, n_syrk = 0, n_rows = 0;
+        // sizes of the lists
+        size_t n_admit = 0, n_eta = 0, n_rows = 0, n_cols = 0, n_syrk = 0, n_info = 0;
+        for (int sl : joining) n_admit += (size_t)s->slots[sl].req->lay.ntile;
         for (int sl : act) {
             const FitLayout &L = s->slots[sl].req->lay;
             n_eta += L.ntile;
             n_rows += L.ntc;
-            n_cols += (size_t)L.ntc * L.p;
-            if (!s->slots[sl].frozen) n_syrk += (size_t)L.npairs * (L.nxr + L.nzr);
+            n_cols += (size_t)L.ntc * ((L.p + kColBlock - 1) / kColBlock);
+            if (!s->slots[sl].frozen) {
+                n_syrk += (size_t)L.npairs * (L.nxr + L.nzr);
+                n_info += L.npairs;
+            }
         }
-        if (!ensure_list(s->l_eta, sizeof(int2) * n_eta, err) || !ensure_list(s->l_cols, sizeof(int2) * n_cols, err) ||
-            !ensure_list(s->l_syrk, sizeof(int4) * std::max<size_t>(n_syrk, 1), err) ||
-            !ensure_list(s->l_slots, sizeof(int) * act.size(), err) ||
-            !ensure_list(s->l_rows, sizeof(int2) * n_rows, err))
-            return false;
-        int2 *rws = reinterpret_cast<int2 *>(s->l_rows.h);
-        int2 *eta = reinterpret_cast<int2 *>(s->l_eta.h);
-        int2 *cols = reinterpret_cast<int2 *>(s->l_cols.h);
-        int4 *syrk = reinterpret_cast<int4 *>(s->l_syrk.h);
-        int *sl_list = reinterpret_cast<int *>(s->l_slots.h);
-        size_t ke = 0, kc = 0, ks = 0, kr = 0;
+        Packer pk;
+        const size_t o_jd = pk.take<FitDesc>(joining.size()), o_js = pk.take<int>(joining.size());
+        const size_t o_admit = pk.take<int2>(n_admit), o_eta = pk.take<int2>(n_eta), o_rows = pk.take<int2>(n_rows);
+        const size_t o_cols = pk.take<int2>(n_cols), o_syrk = pk.take<int4>(n_syrk), o_info = pk.take<int2>(n_info);
+        const size_t o_slots = pk.take<int>(act.size());
+        if (!ensure_list(s->l_round, pk.used, err)) return false;
+        char *H = s->l_round.h, *D = s->l_round.d;
+        FitDesc *jd = reinterpret_cast<FitDesc *>(H + o_jd);
+        int *js = reinterpret_cast<int *>(H + o_js);
+        int2 *adm = reinterpret_cast<int2 *>(H + o_admit);
+        int2 *eta = reinterpret_cast<int2 *>(H + o_eta);
+        int2 *rws = reinterpret_cast<int2 *>(H + o_rows);
+        int2 *cols = reinterpret_cast<int2 *>(H + o_cols);
+        int4 *syrk = reinterpret_cast<int4 *>(H + o_syrk);
+        int2 *info = reinterpret_cast<int2 *>(H + o_info);
+        int *sl_list = reinterpret_cast<int *>(H + o_slots);
+        size_t ka = 0, ke = 0, kr = 0, kc = 0, ks = 0, ki = 0;
+        for (size_t k = 0; k < joining.size(); ++k) {
+            const int sl = joining[k];
+            jd[k] = s->h_desc[sl];
+            js[k] = sl;
+            for (int t = 0; t < s->slots[sl].req->lay.ntile; ++t) adm[ka++] = make_int2((int)k, t);
+        }
+        int max_p = 1;
         for (size_t a = 0; a < act.size(); ++a) {
             const int sl = act[a];
             const FitLayout &L = s->slots[sl].req->lay;
             sl_list[a] = sl;
+            max_p = std::max(max_p, L.p);
             for (int t = 0; t < L.ntile; ++t) eta[ke++] = make_int2(sl, t);
             for (int t = 0; t < L.ntc; ++t) {
                 rws[kr++] = make_int2(sl, t);
-                for (int j = 0; j < L.p; ++j) cols[kc++] = make_int2(sl, (t << 10) | j);
+                for (int j = 0; j < L.p; j += kColBlock) cols[kc++] = make_int2(sl, (t << 10) | j);
             }
             if (!s->slots[sl].frozen)
                 for (int pr = 0; pr < L.npairs; ++pr) {
+                    info[ki++] = make_int2(sl, pr);
                     for (int r = 0; r < L.nxr; ++r) syrk[ks++] = make_int4(sl, pr, r, 0);
                     for (int r = 0; r < L.nzr; ++r) syrk[ks++] = make_int4(sl, pr, r, 1);
                 }
         }
-        int max_p = 1;
-        for (int sl : act) max_p = std::max(max_p, s->slots[sl].req->lay.p);
-        WCHECK(hipMemcpyAsync(s->l_eta.d, s->l_eta.h, sizeof(int2) * ke, hipMemcpyHostToDevice, s->compute), "lists");
-        WCHECK(hipMemcpyAsync(s->l_cols.d, s->l_cols.h, sizeof(int2) * kc, hipMemcpyHostToDevice, s->compute), "lists");
-        if (ks)
-            WCHECK(hipMemcpyAsync(s->l_syrk.d, s->l_syrk.h, sizeof(int4) * ks, hipMemcpyHostToDevice, s->compute),
-                   "lists");
-        WCHECK(hipMemcpyAsync(s->l_slots.d, s->l_slots.h, sizeof(int) * act.size(), hipMemcpyHostToDevice, s->compute),
-               "lists");
-        WCHECK(hipMemcpyAsync(s->l_rows.d, s->l_rows.h, sizeof(int2) * kr, hipMemcpyHostToDevice, s->compute), "lists");
-        const int *dsl = reinterpret_cast<const int *>(s->l_slots.d);
-        WCHECK((hipError_t)launch_eta(s->d_desc, reinterpret_cast<const int2 *>(s->l_eta.d), (int)ke, s->compute), "eta");
-        WCHECK((hipError_t)launch_rows(s->d_desc, reinterpret_cast<const int2 *>(s->l_rows.d), (int)kr, s->compute),
+        if (ka != n_admit || ke != n_eta || kr != n_rows || kc != n_cols || ks != n_syrk || ki != n_info) {
+            err = "internal error: work list sizes";
+            return false;
+        }
+        WCHECK(hipMemcpyAsync(D, H, pk.used, hipMemcpyHostToDevice, s->compute), "work lists");
+        if (ka)
+            WCHECK((hipError_t)launch_admit(s->d_desc, reinterpret_cast<const FitDesc *>(D + o_jd),
+                                            reinterpret_cast<const int *>(D + o_js),
+                                            reinterpret_cast<const int2 *>(D + o_admit), (int)ka, s->compute),
+                   "admit kernel");
+        WCHECK((hipError_t)launch_eta(s->d_desc, reinterpret_cast<const int2 *>(D + o_eta), (int)ke, s->compute), "eta");
+        WCHECK((hipError_t)launch_rows(s->d_desc, reinterpret_cast<const int2 *>(D + o_rows), (int)kr, s->compute),
                "rows");
-        WCHECK((hipError_t)launch_cols(s->d_desc, reinterpret_cast<const int2 *>(s->l_cols.d), (int)kc, s->compute),
+        WCHECK((hipError_t)launch_cols(s->d_desc, reinterpret_cast<const int2 *>(D + o_cols), (int)kc, s->compute),
                "cols");
-        if (ks)
-            WCHECK((hipError_t)launch_syrk(s->d_desc, reinterpret_cast<const int4 *>(s->l_syrk.d), (int)ks, s->compute),
+        if (ks) {
+            WCHECK((hipError_t)launch_syrk(s->d_desc, reinterpret_cast<const int4 *>(D + o_syrk), (int)ks, s->compute),
                    "syrk");
-        WCHECK((hipError_t)launch_step(s->d_desc, dsl, (int)act.size(), max_p, s->compute), "step");
+            WCHECK((hipError_t)launch_info(s->d_desc, reinterpret_cast<const int2 *>(D + o_info), (int)ki, s->compute),
+                   "info");
+        }
+        WCHECK((hipError_t)launch_step(s->d_desc, reinterpret_cast<const int *>(D + o_slots), (int)act.size(), max_p,
+                                       s->compute),
+               "step");
         const int hi = act.back() + 1;   // act is in slot order
         WCHECK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(FitState) * hi, hipMemcpyDeviceToHost, s->compute),
                "reading fit states");
@@ -718,7 +739,7 @@ void free_server(cox_server *s)
     if (s->h_desc) (void)hipHostFree(s->h_desc);
     if (s->h_state) (void)hipHostFree(s->h_state);
     if (s->h_beta) (void)hipHostFree(s->h_beta);
-    for (cox_server::List *l : {&s->l_admit, &s->l_eta, &s->l_slots, &s->l_cols, &s->l_syrk, &s->l_rows}) {
+    for (cox_server::List *l : {&s->l_round}) {
         if (l->h) (void)hipHostFree(l->h);
         if (l->d) (void)hipFree(l->d);
     }
