@@ -259,9 +259,18 @@ typedef struct {
     double now_s;           /* the server's clock */
 } cox_server_counters;
 
-/* cox_server_submit flag: do not copy the inputs; the caller keeps x, time,
- * event and stratum valid and unchanged until the ticket's result is ready */
+/* cox_server_submit flags.
+ * COX_SUBMIT_BORROW: do not copy the inputs; the caller keeps x, time, event
+ *   and stratum valid and unchanged until the ticket's result is ready.
+ * COX_SUBMIT_DEVICE: the four pointers are device memory of the server's
+ *   device, already written (the stream that wrote them synchronised).  They
+ *   are read in place -- borrowed as above, whatever the other flag says: the
+ *   keys (time, event, stratum) are copied to the host for the canonical
+ *   order, and the fit's rows of x are gathered into the server's arena on the
+ *   device when the fit is admitted, so x crosses no host link.  Keys that fail
+ *   the checks of cox_init complete the request with status COX_EINVAL. */
 #define COX_SUBMIT_BORROW 1
+#define COX_SUBMIT_DEVICE 2
 
 void cox_server_default_options(cox_server_options *o);
 
@@ -272,8 +281,9 @@ void cox_server_default_options(cox_server_options *o);
 int cox_server_create(cox_server **out, const cox_server_options *o);
 
 /* Queue one fit; returns at once with its ticket (tickets start at 1).
- *   d     : host data as for cox_init (stratum may be NULL)
- *   flags : 0 (inputs copied) or COX_SUBMIT_BORROW
+ *   d     : data as for cox_init (stratum may be NULL): host memory, or device
+ *           memory with COX_SUBMIT_DEVICE
+ *   flags : 0 (inputs copied), COX_SUBMIT_BORROW and/or COX_SUBMIT_DEVICE
  * Errors: COX_EINVAL (the checks of cox_init), COX_EUNSUPPORTED (p > 128),
  * or the server's fatal device error.  A request whose device footprint
  * exceeds hbm_budget (or staging_bytes) completes with status COX_EUNSUPPORTED. */

@@ -95,6 +95,7 @@ class cox_server_counters(ctypes.Structure):
 
 
 COX_SUBMIT_BORROW = 1
+COX_SUBMIT_DEVICE = 2
 
 _lib = None
 
@@ -375,6 +376,31 @@ class CoxServer:
             msg = lib().cox_server_last_error(self.h)
             raise CoxError(rc, msg.decode() if msg else "")
         return rc
+
+    def submit_device(self, X, time, event, stratum=None) -> int:
+        """Submit device-resident data (torch tensors on the server's device):
+        X float64 n x p with unit row stride (column-major, e.g. a transposed
+        contiguous p x n tensor), time float64, event uint8, stratum int32 or
+        None.  The tensors are read in place and kept referenced until the
+        result is collected; the caller synchronises the stream that wrote them."""
+        import torch
+        n, p = X.shape
+        if X.dtype != torch.float64 or not X.is_cuda or X.stride(0) != 1 or X.stride(1) < n:
+            raise ValueError("X must be a float64 CUDA tensor with unit row stride")
+        checks = [(time, torch.float64), (event, torch.uint8)] + ([(stratum, torch.int32)] if stratum is not None else [])
+        for t, dt in checks:
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+                raise ValueError("time / event / stratum must be contiguous CUDA tensors of n float64 / uint8 / int32")
+        d = cox_data(n=n, p=p, x=ctypes.cast(X.data_ptr(), ctypes.POINTER(ctypes.c_double)), ldx=X.stride(1),
+                     time=ctypes.cast(time.data_ptr(), ctypes.POINTER(ctypes.c_double)),
+                     event=ctypes.cast(event.data_ptr(), ctypes.POINTER(ctypes.c_uint8)))
+        if stratum is not None:
+            d.stratum = ctypes.cast(stratum.data_ptr(), ctypes.POINTER(ctypes.c_int32))
+        t = ctypes.c_uint64()
+        self._check(lib().cox_server_submit(self.h, ctypes.byref(d), COX_SUBMIT_DEVICE, ctypes.byref(t)))
+        self._keep[t.value] = [X, time, event, stratum]
+        self._p[t.value] = p
+        return t.value
 
     def submit(self, X, time, event, stratum=None, borrow=True) -> int:
         X = np.asfortranarray(X, dtype=np.float64)

@@ -52,7 +52,10 @@ struct alignas(16) FitState {
 
 // Everything a kernel needs to know about one resident fit (device pointers).
 struct FitDesc {
-    const double *x;        // [p][ld] FP64, canonical rows, padding rows zero
+    double *x;              // [p][ld] FP64, canonical rows, padding rows zero
+    const double *xs;       // device-resident request: the caller's X (column-major, leading dimension ldxs),
+    const int32_t *src;     //   gathered into x at admission: row r of x is row src[r] of xs (-1: padding);
+    int64_t ldxs;           //   xs = nullptr when X came up with the request's image
     float *xf;              // [p][ld] FP32 copy for the contraction
     const uint32_t *meta;   // [ld] row words (padding rows: head | pad)
     const int32_t *gidx;    // [ld] event-group index at group ends, else -1

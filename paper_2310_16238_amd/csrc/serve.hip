@@ -49,7 +49,8 @@ __device__ __forceinline__ double wave_max(double v)
 
 // ------------------------------------------------------------------ admit: FP32 copy of X
 
-// Item (k, t): rows [256 t, 256 t + 256) of joining fit k.  The items of a fit
+// Item (k, t): rows [256 t, 256 t + 256) of joining fit k (X gathered from the
+// caller's device memory for a device-resident request; the FP32 copy).  The items of a fit
 // also clear its z (grid-stride over the fit's items); item 0 installs the
 // descriptor in the fit's slot and clears beta, the previous beta and the state.
 __global__ __launch_bounds__(256) void admit_kernel(FitDesc *fits, const FitDesc *joining, const int *slots,
@@ -59,8 +60,19 @@ __global__ __launch_bounds__(256) void admit_kernel(FitDesc *fits, const FitDesc
     const FitDesc &F = joining[it.x];
     const int x = threadIdx.x;
     const int64_t r = (int64_t)it.y * 256 + x;
-    if (r < F.ld)
-        for (int j = 0; j < F.p; ++j) F.xf[(int64_t)j * F.ld + r] = (float)F.x[(int64_t)j * F.ld + r];
+    if (r < F.ld) {
+        if (F.xs) {
+            // device-resident request: gather the canonical rows from the caller's X
+            const int32_t sr = F.src[r];
+            for (int j = 0; j < F.p; ++j) {
+                const double v = sr >= 0 ? F.xs[(int64_t)j * F.ldxs + sr] : 0.0;
+                F.x[(int64_t)j * F.ld + r] = v;
+                F.xf[(int64_t)j * F.ld + r] = (float)v;
+            }
+        } else {
+            for (int j = 0; j < F.p; ++j) F.xf[(int64_t)j * F.ld + r] = (float)F.x[(int64_t)j * F.ld + r];
+        }
+    }
     const int64_t nz = (int64_t)F.p * F.ldz, stride = (int64_t)F.ntile * 256;
     for (int64_t e = (int64_t)it.y * 256 + x; e < nz; e += stride) F.z[e] = 0.0f;
     if (it.y == 0) {

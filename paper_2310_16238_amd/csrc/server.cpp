@@ -102,7 +102,9 @@ private:
 struct FitLayout {
     int64_t n = 0, ld = 0, ldz = 0, tile = 0;
     int p = 0, G = 0, nxr = 0, nzr = 0, npairs = 0, ntile = 0, ntc = 0;
-    size_t x = 0, meta = 0, gidx = 0, upload = 0;   // [x | meta | gidx] is uploaded in one copy
+    bool device = false;                            // X is gathered from the caller's device memory
+    size_t meta = 0, gidx = 0, src = 0, x = 0, upload = 0;   // [0, upload) is uploaded in one copy:
+                                                    // meta, gidx, then X (host request) or src (device)
     size_t xf = 0, rows = 0, z = 0, beta = 0, prev = 0;
     size_t vec = 0, free_col = 0, L = 0, part = 0, tilemax = 0, tpart = 0, cpart = 0, total = 0;
 };
@@ -140,9 +142,10 @@ int64_t place_rows(const std::vector<uint32_t> &meta, std::vector<int64_t> &pos,
     return (int64_t)round_up((size_t)cur, kScanTile);
 }
 
-FitLayout plan(int64_t n, int64_t ld, int64_t tile, int p, int64_t G)
+FitLayout plan(int64_t n, int64_t ld, int64_t tile, int p, int64_t G, bool device)
 {
     FitLayout L;
+    L.device = device;
     L.n = n;
     L.p = p;
     L.G = (int)G;
@@ -161,10 +164,16 @@ FitLayout plan(int64_t n, int64_t ld, int64_t tile, int p, int64_t G)
         o = round_up(o + bytes, kAlign);
         return at;
     };
-    L.x = take(sizeof(double) * (size_t)p * L.ld);
     L.meta = take(sizeof(uint32_t) * (size_t)L.ld);
     L.gidx = take(sizeof(int32_t) * (size_t)L.ld);
-    L.upload = o;
+    if (device) {
+        L.src = take(sizeof(int32_t) * (size_t)L.ld);
+        L.upload = o;
+        L.x = take(sizeof(double) * (size_t)p * L.ld);
+    } else {
+        L.x = take(sizeof(double) * (size_t)p * L.ld);
+        L.upload = o;
+    }
     L.xf = take(sizeof(float) * (size_t)p * L.ld);
     L.rows = take(sizeof(double) * 5 * (size_t)L.ld);
     L.z = take(sizeof(float) * (size_t)p * L.ldz);   // zeroed at admission, with beta and prev
@@ -183,6 +192,7 @@ FitLayout plan(int64_t n, int64_t ld, int64_t tile, int p, int64_t G)
 
 struct Request {
     uint64_t ticket = 0;
+    bool device = false;   // x (and, until the prep thread copies them, the keys) in device memory
     int64_t n = 0, p = 0, ldx = 0;
     const double *x = nullptr, *time = nullptr;
     const uint8_t *event = nullptr;
@@ -297,7 +307,6 @@ void write_image(const Request &q, const std::vector<int64_t> &perm, const std::
                  const std::vector<int64_t> &pos, char *dst)
 {
     const FitLayout &L = q.lay;
-    double *x = reinterpret_cast<double *>(dst + L.x);
     uint32_t *mw = reinterpret_cast<uint32_t *>(dst + L.meta);
     int32_t *gi = reinterpret_cast<int32_t *>(dst + L.gidx);
     // padding rows: one-row strata without events, X = 0
@@ -305,11 +314,19 @@ void write_image(const Request &q, const std::vector<int64_t> &perm, const std::
         mw[i] = kHeadBit | kPadBit;
         gi[i] = -1;
     }
-    for (int64_t j = 0; j < q.p; ++j) {
-        double *col = x + j * L.ld;
-        const double *src = q.x + j * q.ldx;
-        std::memset(col, 0, sizeof(double) * L.ld);
-        for (int64_t i = 0; i < q.n; ++i) col[pos[i]] = src[perm[i]];
+    if (L.device) {
+        // the admit kernel gathers X: device row pos[i] is the caller's row perm[i]
+        int32_t *sr = reinterpret_cast<int32_t *>(dst + L.src);
+        for (int64_t i = 0; i < L.ld; ++i) sr[i] = -1;
+        for (int64_t i = 0; i < q.n; ++i) sr[pos[i]] = (int32_t)perm[i];
+    } else {
+        double *x = reinterpret_cast<double *>(dst + L.x);
+        for (int64_t j = 0; j < q.p; ++j) {
+            double *col = x + j * L.ld;
+            const double *src = q.x + j * q.ldx;
+            std::memset(col, 0, sizeof(double) * L.ld);
+            for (int64_t i = 0; i < q.n; ++i) col[pos[i]] = src[perm[i]];
+        }
     }
     int32_t g = 0;
     for (int64_t i = 0; i < q.n; ++i) {
@@ -318,10 +335,44 @@ void write_image(const Request &q, const std::vector<int64_t> &perm, const std::
     }
 }
 
+// Keys of a device-resident request (times, events, strata) are copied to the
+// host for the canonical order; X stays where it is.  Returns an error message.
+const char *fetch_keys(cox_server *s, Request &q, hipStream_t &st)
+{
+    if (!st) {
+        if (hipSetDevice(s->device) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            st = nullptr;
+            return "creating a stream for device-resident keys";
+        }
+    }
+    const size_t n = (size_t)q.n;
+    q.own_t.resize(n);
+    q.own_e.resize(n);
+    if (q.stratum) q.own_s.resize(n);
+    if (hipMemcpyAsync(q.own_t.data(), q.time, sizeof(double) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(q.own_e.data(), q.event, n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        (q.stratum &&
+         hipMemcpyAsync(q.own_s.data(), q.stratum, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st) != hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return "copying device-resident keys";
+    q.time = q.own_t.data();
+    q.event = q.own_e.data();
+    q.stratum = q.stratum ? q.own_s.data() : nullptr;
+    return check_data(q.n, q.p, q.ldx, q.x, q.time, q.event);
+}
+
 void prep_loop(cox_server *s)
 {
     std::vector<int64_t> perm, pos;
     std::vector<uint32_t> meta;
+    hipStream_t key_stream = nullptr;
+    struct StreamGuard {
+        hipStream_t &st;
+        ~StreamGuard()
+        {
+            if (st) (void)hipStreamDestroy(st);
+        }
+    } guard{key_stream};
     for (;;) {
         std::unique_ptr<Request> q;
         {
@@ -331,12 +382,20 @@ void prep_loop(cox_server *s)
             q = std::move(s->prep_q.front());
             s->prep_q.pop_front();
         }
+        if (q->device) {
+            if (const char *bad = fetch_keys(s, *q, key_stream)) {
+                (void)bad;
+                std::lock_guard<std::mutex> g(s->mu);
+                fail_request_locked(s, *q, COX_EINVAL, s->now());
+                continue;
+            }
+        }
         canonical_order(q->n, q->time, q->event, q->stratum, perm, meta);
         int64_t G = 0;
         for (int64_t i = 0; i < q->n; ++i) G += (meta[i] & kCountMask) ? 1 : 0;
         int64_t tile = 0;
         const int64_t ld = place_rows(meta, pos, &tile);
-        q->lay = plan(q->n, ld, tile, (int)q->p, G);
+        q->lay = plan(q->n, ld, tile, (int)q->p, G, q->device);
         {
             std::unique_lock<std::mutex> lk(s->mu);
             if (q->lay.total > s->arena_alloc.capacity() || q->lay.upload > s->stage_alloc.capacity()) {
@@ -380,7 +439,12 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off, int slot)
     const FitLayout &L = q.lay;
     char *B = s->arena + off;
     FitDesc F{};
-    F.x = reinterpret_cast<const double *>(B + L.x);
+    F.x = reinterpret_cast<double *>(B + L.x);
+    if (L.device) {
+        F.xs = q.x;
+        F.ldxs = q.ldx;
+        F.src = reinterpret_cast<const int32_t *>(B + L.src);
+    }
     F.xf = reinterpret_cast<float *>(B + L.xf);
     F.meta = reinterpret_cast<const uint32_t *>(B + L.meta);
     F.gidx = reinterpret_cast<const int32_t *>(B + L.gidx);
@@ -436,7 +500,7 @@ bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_
            in(F.prev, 8 * p) && in(F.grad, 8 * p) && in(F.diag2, 8 * p) && in(F.free_col, p) &&
            in(F.L, 8 * p * p) && in(F.part, 4 * (size_t)(L.nxr + L.nzr) * L.npairs * kTile * kTile) &&
            in(F.tilemax, 8 * (size_t)L.ntile) && in(F.tpart, 16 * (size_t)L.ntc) &&
-           in(F.cpart, 24 * (size_t)L.ntc * p) && F.tile > 0 && F.tile % kRowPad == 0 && F.ntc >= 1 &&
+           in(F.cpart, 24 * (size_t)L.ntc * p) && (!L.device || (in(F.src, 4 * ld) && F.xs && F.ldxs >= L.n)) && F.tile > 0 && F.tile % kRowPad == 0 && F.ntc >= 1 &&
            F.tile * F.ntc == F.ld &&
            F.st == s->d_state + slot && F.p == L.p && F.ld == L.ld &&
            F.n <= F.ld && F.ld % kRowPad == 0 && F.ldz % kRowPad == 0 && F.G <= F.ldz && F.p >= 1 &&
@@ -827,13 +891,40 @@ extern "C" int cox_server_submit(cox_server *s, const cox_data *d, int flags, ui
 {
     if (!s) return COX_EINVAL;
     if (!d || !ticket) return srv_fail(s, COX_EINVAL, "data and ticket are required");
-    if (flags & ~COX_SUBMIT_BORROW) return srv_fail(s, COX_EINVAL, "unknown submit flags");
-    if (const char *bad = check_data(d->n, d->p, d->ldx, d->x, d->time, d->event)) return srv_fail(s, COX_EINVAL, bad);
+    if (flags & ~(COX_SUBMIT_BORROW | COX_SUBMIT_DEVICE)) return srv_fail(s, COX_EINVAL, "unknown submit flags");
+    const bool dev = (flags & COX_SUBMIT_DEVICE) != 0;
+    if (dev) {
+        // shape and placement now; the keys are checked once the prep thread has them
+        if (d->n < 1 || d->p < 1 || d->ldx < d->n || d->n > (int64_t)kCountMask)
+            return srv_fail(s, COX_EINVAL, "need n >= 1, p >= 1, ldx >= n, n < 2^29");
+        const void *ptrs[4] = {d->x, d->time, d->event, d->stratum};
+        for (int k = 0; k < 4; ++k) {
+            if (!ptrs[k]) {
+                if (k == 3) continue;
+                return srv_fail(s, COX_EINVAL, "x, time and event are required");
+            }
+            hipPointerAttribute_t a{};
+            if (hipPointerGetAttributes(&a, ptrs[k]) != hipSuccess ||
+                (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) || a.device != s->device) {
+                (void)hipGetLastError();
+                return srv_fail(s, COX_EINVAL, "COX_SUBMIT_DEVICE needs device memory of the server's device");
+            }
+        }
+    } else if (const char *bad = check_data(d->n, d->p, d->ldx, d->x, d->time, d->event)) {
+        return srv_fail(s, COX_EINVAL, bad);
+    }
     if (d->p > kMaxP) return srv_fail(s, COX_EUNSUPPORTED, "the server fits at most 128 columns");
     std::unique_ptr<Request> q(new Request());
     q->n = d->n;
     q->p = d->p;
-    if (flags & COX_SUBMIT_BORROW) {
+    if (dev) {
+        q->device = true;
+        q->x = d->x;
+        q->ldx = d->ldx;
+        q->time = d->time;
+        q->event = d->event;
+        q->stratum = d->stratum;
+    } else if (flags & COX_SUBMIT_BORROW) {
         q->x = d->x;
         q->ldx = d->ldx;
         q->time = d->time;

@@ -170,3 +170,57 @@ def test_server_edge_cases():
             srv._p[tickets[0]] = 1
             srv.poll(tickets[0])
         assert ei.value.code == coxmi.COX_EINVAL
+
+
+def _on_device(d):
+    return (torch.from_numpy(np.ascontiguousarray(d.X.T)).cuda().t(),
+            torch.from_numpy(np.ascontiguousarray(d.time)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(d.event, dtype=np.uint8)).cuda(),
+            None if d.stratum is None else torch.from_numpy(np.ascontiguousarray(d.stratum, dtype=np.int32)).cuda())
+
+
+def test_device_resident_requests_match_host_requests():
+    # single-tile fits, stratum-aligned multi-tile fits, and one with a stratum longer than a scan tile
+    reqs = _requests(6, seed=19, n_range=(500, 30_000), p_range=(3, 90))
+    reqs.append(synth.make("iid", 9_000, 7, 1, 23, intercept=True))
+    dev = [_on_device(d) for d in reqs]
+    torch.cuda.synchronize()
+    with coxmi.CoxServer(prep_threads=3) as srv:
+        th = [srv.submit(d.X, d.time, d.event, d.stratum) for d in reqs]
+        td = [srv.submit_device(*t) for t in dev]
+        assert srv.drain(timeout=100.0)
+        rh = [srv.poll(t) for t in th]
+        rd = [srv.poll(t) for t in td]
+    for d, a, b in zip(reqs, rh, rd):
+        _say(f"  {d.name}: n={d.n} p={d.p} iters={b[1]['iters']}")
+        assert np.array_equal(a[0], b[0]), d.name   # the same canonical image, gathered on the device
+        assert a[1]["iters"] == b[1]["iters"]
+        _check_against_oracle(d, b[0], b[1])
+
+
+def test_device_submission_errors():
+    import ctypes
+    rng = np.random.default_rng(29)
+    n, p = 200, 3
+    X = torch.from_numpy(rng.standard_normal((p, n))).cuda().t()
+    t_bad = torch.from_numpy(rng.random(n)).cuda()
+    t_bad[7] = float("nan")
+    e = torch.from_numpy((rng.random(n) < 0.5).astype(np.uint8)).cuda()
+    torch.cuda.synchronize()
+    with coxmi.CoxServer(prep_threads=1) as srv:
+        # invalid keys are found by the prep thread: the request completes with COX_EINVAL
+        tk = srv.submit_device(X, t_bad, e)
+        assert srv.wait(tk, timeout=30.0)
+        assert srv.poll(tk)[1]["status"] == coxmi.COX_EINVAL
+        # host memory under COX_SUBMIT_DEVICE is refused at submit
+        Xh = np.asfortranarray(rng.standard_normal((n, p)))
+        th = rng.random(n)
+        eh = np.ones(n, np.uint8)
+        dd = coxmi.cox_data(n=n, p=p, x=Xh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ldx=n,
+                            time=th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            event=eh.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        t = ctypes.c_uint64()
+        rc = coxmi.lib().cox_server_submit(srv.h, ctypes.byref(dd), coxmi.COX_SUBMIT_DEVICE, ctypes.byref(t))
+        assert rc == coxmi.COX_EINVAL
+        with pytest.raises(ValueError):
+            srv.submit_device(X.contiguous(), t_bad, e)   # row-major X
