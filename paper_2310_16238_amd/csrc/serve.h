@@ -60,6 +60,7 @@ struct FitDesc {
     const uint32_t *meta;   // [ld] row words (padding rows: head | pad)
     const int32_t *gidx;    // [ld] event-group index at group ends, else -1
     double *eta, *w, *zq, *hz, *b;   // [ld] row vectors (zq = (d/S0)/sqrt(d) at group ends, b = w Lambda)
+    float *bf;              // [ld] b rounded to FP32: the contraction's weights
     float *z;               // [p][ldz] sqrt(d_g) xbar_g
     double *beta, *prev, *grad, *diag1, *diag2;   // [p]
     uint8_t *free_col;      // [p]

@@ -64,10 +64,17 @@ __global__ __launch_bounds__(256) void admit_kernel(FitDesc *fits, const FitDesc
         if (F.xs) {
             // device-resident request: gather the canonical rows from the caller's X
             const int32_t sr = F.src[r];
-            for (int j = 0; j < F.p; ++j) {
-                const double v = sr >= 0 ? F.xs[(int64_t)j * F.ldxs + sr] : 0.0;
-                F.x[(int64_t)j * F.ld + r] = v;
-                F.xf[(int64_t)j * F.ld + r] = (float)v;
+            for (int j0 = 0; j0 < F.p; j0 += 8) {   // 8 loads in flight per thread
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    v[q] = (j0 + q < F.p && sr >= 0) ? F.xs[(int64_t)(j0 + q) * F.ldxs + sr] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (j0 + q < F.p) {
+                        F.x[(int64_t)(j0 + q) * F.ld + r] = v[q];
+                        F.xf[(int64_t)(j0 + q) * F.ld + r] = (float)v[q];
+                    }
             }
         } else {
             for (int j = 0; j < F.p; ++j) F.xf[(int64_t)j * F.ld + r] = (float)F.x[(int64_t)j * F.ld + r];
@@ -242,7 +249,9 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, 
             run = seg_combine(run, e[i]);
             if (k < len) {
                 const int64_t r = r_end - 1 - k;
-                F.b[r] = F.w[r] * run.v[0];
+                const double bw = F.w[r] * run.v[0];
+                F.b[r] = bw;
+                F.bf[r] = (float)bw;
             }
         }
         carry = seg_combine(carry, btot);
@@ -398,8 +407,9 @@ constexpr int kSyrkWaves = 4;
 
 // One workgroup per (fit, tile pair, K range, product): wave v takes the v-th
 // quarter of the K range, and the four accumulators are added in wave order.
-// Rows of X (event groups of Z) come in steps of 8 -- 4 consecutive per half-wave,
-// as float4 -- with the next step's operands loaded before this step's products.
+// Rows of X (event groups of Z) come in steps of 32 -- 16 consecutive per
+// half-wave, as float4s -- with the next step's operands loaded before this
+// step's 16 products.
 __global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc *fits, const int4 *items)
 {
     __shared__ float red[kSyrkWaves - 1][16][kWave];
@@ -414,50 +424,60 @@ __global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc 
     const int64_t ldu = zpart ? F.ldz : F.ld;
     const int64_t range = zpart ? kZRange : kXRange, quarter = range / kSyrkWaves;
     const int64_t k0 = (int64_t)it.z * range + v * quarter;
-    const int64_t k1 = k0 + quarter < ldu ? k0 + quarter : ldu;   // ldu is a multiple of 64: steps of 8 fit
-    const double *c = zpart ? nullptr : F.b;
+    // k0 is a multiple of 64 and ldu a multiple of 64: steps of 32 fit exactly
+    const int64_t k1 = k0 + quarter < ldu ? k0 + quarter : ldu;
     const int ra = ti * kTile + (lane & 31), rb = tj * kTile + (lane & 31);
     const bool la = ra < F.p, lb = rb < F.p;
-    const int kofs = 4 * (lane >> 5);
-    const float *ua = u + (int64_t)(la ? ra : 0) * ldu + kofs;
-    const float *ub = u + (int64_t)(lb ? rb : 0) * ldu + kofs;
-    const double *cc = c ? c + kofs : nullptr;
+    const int kofs = 16 * (lane >> 5);
+    const float4 *ua = reinterpret_cast<const float4 *>(u + (int64_t)(la ? ra : 0) * ldu + kofs);
+    const float4 *ub = reinterpret_cast<const float4 *>(u + (int64_t)(lb ? rb : 0) * ldu + kofs);
+    const float4 *uc = zpart ? nullptr : reinterpret_cast<const float4 *>(F.bf + kofs);
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-    float4 an = make_float4(0.f, 0.f, 0.f, 0.f), bn = an;
-    double2 cl = make_double2(1.0, 1.0), ch = cl;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 an[4], bn[4], cn[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) an[q] = bn[q] = cn[q] = zero4;
     if (k0 < k1) {
-        an = *reinterpret_cast<const float4 *>(ua + k0);
-        bn = *reinterpret_cast<const float4 *>(ub + k0);
-        if (cc) {
-            cl = *reinterpret_cast<const double2 *>(cc + k0);
-            ch = *reinterpret_cast<const double2 *>(cc + k0 + 2);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            an[q] = ua[k0 / 4 + q];
+            bn[q] = ub[k0 / 4 + q];
+            if (uc) cn[q] = uc[k0 / 4 + q];
         }
     }
-    for (int64_t k = k0; k < k1; k += 8) {
-        float4 av = an, bv = bn;
-        const double2 l = cl, h = ch;
-        if (k + 8 < k1) {
-            an = *reinterpret_cast<const float4 *>(ua + k + 8);
-            bn = *reinterpret_cast<const float4 *>(ub + k + 8);
-            if (cc) {
-                cl = *reinterpret_cast<const double2 *>(cc + k + 8);
-                ch = *reinterpret_cast<const double2 *>(cc + k + 10);
+    for (int64_t k = k0; k < k1; k += 32) {
+        float4 av[4], bv[4], cv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            av[q] = an[q];
+            bv[q] = bn[q];
+            cv[q] = cn[q];
+        }
+        if (k + 32 < k1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                an[q] = ua[(k + 32) / 4 + q];
+                bn[q] = ub[(k + 32) / 4 + q];
+                if (uc) cn[q] = uc[(k + 32) / 4 + q];
             }
         }
-        if (!la) av = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (!lb) bv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (cc) {
-            av.x *= (float)l.x;
-            av.y *= (float)l.y;
-            av.z *= (float)h.x;
-            av.w *= (float)h.y;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!la) av[q] = zero4;
+            if (!lb) bv[q] = zero4;
+            if (uc) {
+                av[q].x *= cv[q].x;
+                av[q].y *= cv[q].y;
+                av[q].z *= cv[q].z;
+                av[q].w *= cv[q].w;
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].x, bv[q].x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].y, bv[q].y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].z, bv[q].z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].w, bv[q].w, acc, 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bv.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, bv.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.z, bv.z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av.w, bv.w, acc, 0, 0, 0);
     }
     if (v > 0) {
 #pragma unroll
@@ -606,25 +626,58 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
                 A[i * p + j] = v;
             }
         __syncthreads();
-        // right-looking Cholesky of the lower triangle: per column, scale it by the
-        // pivot, then update the trailing triangle (row i by one wave, lanes over j)
+        // right-looking Cholesky of the lower triangle, one barrier per column.
+        // Thread (ty, tx) owns the entries (i, j) with i = ty, j = tx (mod 16).  At
+        // column k every thread reads the pivot and the column's entries in its rows
+        // and in its columns, scales them itself, and updates its entries of the
+        // trailing triangle.  The scaled column is stored after the next barrier
+        // (by the threads with tx = 0, the pivot by thread 0), when nothing reads it.
+        constexpr int kOwn = kMaxP / 16;
+        const int ty = t >> 4, tx = t & 15;
+        double keep[kOwn];
+        double keep_piv = 1.0;
+#pragma unroll
+        for (int a = 0; a < kOwn; ++a) keep[a] = 0.0;
         for (int k = 0; k < p; ++k) {
+            if (k > 0) {   // column k - 1
+                if (tx == 0) {
+#pragma unroll
+                    for (int a = 0; a < kOwn; ++a) {
+                        const int i = ty + 16 * a;
+                        if (i > k - 1 && i < p) A[i * p + k - 1] = keep[a];
+                    }
+                }
+                if (t == 0) A[(k - 1) * p + k - 1] = keep_piv;
+            }
             double d = A[k * p + k];
             const bool ok = d > 0.0;
             if (!ok) d = 1.0;
             const double piv = sqrt(d);
-            for (int i = k + 1 + t; i < p; i += kStepThreads) A[i * p + k] /= piv;
-            __syncthreads();
-            if (t == 0) {
-                A[k * p + k] = piv;
-                if (!ok) s_bad = 1;
+            if (t == 0 && !ok) s_bad = 1;
+            double li[kOwn], lj[kOwn];
+#pragma unroll
+            for (int a = 0; a < kOwn; ++a) {
+                const int i = ty + 16 * a, j = tx + 16 * a;
+                li[a] = (i > k && i < p) ? A[i * p + k] / piv : 0.0;
+                lj[a] = (j > k && j < p) ? A[j * p + k] / piv : 0.0;
             }
-            for (int i = k + 1 + wv; i < p; i += kWaves) {
-                const double lik = A[i * p + k];
-                for (int j = k + 1 + lane; j <= i; j += kWave) A[i * p + j] -= lik * A[j * p + k];
+#pragma unroll
+            for (int a = 0; a < kOwn; ++a) {
+                const int i = ty + 16 * a;
+                if (i > k && i < p) {
+#pragma unroll
+                    for (int b = 0; b < kOwn; ++b) {
+                        const int j = tx + 16 * b;
+                        if (j > k && j <= i) A[i * p + j] -= li[a] * lj[b];
+                    }
+                }
+                keep[a] = li[a];
             }
+            keep_piv = piv;
             __syncthreads();
         }
+        if (t == 0) A[(p - 1) * p + p - 1] = keep_piv;   // the last column is its pivot alone
+        __syncthreads();
         for (int i = wv; i < p; i += kWaves)
             for (int j = lane; j < p; j += kWave) F.L[(int64_t)i * p + j] = A[i * p + j];
     } else {

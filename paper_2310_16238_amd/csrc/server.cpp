@@ -105,7 +105,7 @@ struct FitLayout {
     bool device = false;                            // X is gathered from the caller's device memory
     size_t meta = 0, gidx = 0, src = 0, x = 0, upload = 0;   // [0, upload) is uploaded in one copy:
                                                     // meta, gidx, then X (host request) or src (device)
-    size_t xf = 0, rows = 0, z = 0, beta = 0, prev = 0;
+    size_t xf = 0, rows = 0, bf = 0, z = 0, beta = 0, prev = 0;
     size_t vec = 0, free_col = 0, L = 0, part = 0, tilemax = 0, tpart = 0, cpart = 0, total = 0;
 };
 
@@ -176,6 +176,7 @@ FitLayout plan(int64_t n, int64_t ld, int64_t tile, int p, int64_t G, bool devic
     }
     L.xf = take(sizeof(float) * (size_t)p * L.ld);
     L.rows = take(sizeof(double) * 5 * (size_t)L.ld);
+    L.bf = take(sizeof(float) * (size_t)L.ld);
     L.z = take(sizeof(float) * (size_t)p * L.ldz);   // zeroed at admission, with beta and prev
     L.beta = take(sizeof(double) * p);
     L.prev = take(sizeof(double) * p);
@@ -454,6 +455,7 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off, int slot)
     F.zq = rows + 2 * L.ld;
     F.hz = rows + 3 * L.ld;
     F.b = rows + 4 * L.ld;
+    F.bf = reinterpret_cast<float *>(B + L.bf);
     F.z = reinterpret_cast<float *>(B + L.z);
     F.beta = reinterpret_cast<double *>(B + L.beta);
     F.prev = reinterpret_cast<double *>(B + L.prev);
@@ -496,7 +498,7 @@ bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_
     };
     const size_t p = (size_t)L.p, ld = (size_t)L.ld;
     return in(F.x, 8 * p * ld) && in(F.xf, 4 * p * ld) && in(F.meta, 4 * ld) && in(F.gidx, 4 * ld) &&
-           in(F.eta, 8 * ld) && in(F.w, 8 * ld) && in(F.zq, 8 * ld) && in(F.hz, 8 * ld) && in(F.b, 8 * ld) && in(F.z, 4 * p * (size_t)L.ldz) && in(F.beta, 8 * p) &&
+           in(F.eta, 8 * ld) && in(F.w, 8 * ld) && in(F.zq, 8 * ld) && in(F.hz, 8 * ld) && in(F.b, 8 * ld) && in(F.bf, 4 * ld) && in(F.z, 4 * p * (size_t)L.ldz) && in(F.beta, 8 * p) &&
            in(F.prev, 8 * p) && in(F.grad, 8 * p) && in(F.diag2, 8 * p) && in(F.free_col, p) &&
            in(F.L, 8 * p * p) && in(F.part, 4 * (size_t)(L.nxr + L.nzr) * L.npairs * kTile * kTile) &&
            in(F.tilemax, 8 * (size_t)L.ntile) && in(F.tpart, 16 * (size_t)L.ntc) &&
