@@ -548,7 +548,7 @@ constexpr int kStepThreads = 256;
 
 __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits, const int *slots)
 {
-    extern __shared__ double lds[];   // A[p * p], y[p]
+    extern __shared__ double lds[];   // A[p * p], y[p], two column buffers [2][p]
     __shared__ int s_action, s_bad, s_frozen;
     __shared__ uint8_t s_free[kMaxP];
     __shared__ double s_red[kStepThreads / kWave];
@@ -618,38 +618,41 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     for (int j = t; j < p; j += kStepThreads) s_free[j] = F.free_col[j];
     __syncthreads();
     if (!frozen) {
-        // the information matrix (info kernel); rows and columns not free become unit rows
-        for (int i = wv; i < p; i += kWaves)
-            for (int j = lane; j < p; j += kWave) {
-                double v = F.L[(int64_t)i * p + j];
-                if (!s_free[i] || !s_free[j]) v = (i == j) ? 1.0 : 0.0;
-                A[i * p + j] = v;
-            }
-        __syncthreads();
-        // right-looking Cholesky of the lower triangle, one barrier per column.
-        // Thread (ty, tx) owns the entries (i, j) with i = ty, j = tx (mod 16).  At
-        // column k every thread reads the pivot and the column's entries in its rows
-        // and in its columns, scales them itself, and updates its entries of the
-        // trailing triangle.  The scaled column is stored after the next barrier
-        // (by the threads with tx = 0, the pivot by thread 0), when nothing reads it.
+        // Right-looking Cholesky of the information matrix (info kernel; rows and
+        // columns not free become unit rows) with the matrix in registers: thread
+        // (ty, tx) holds the lower-triangle entries (i, j) with i = ty, j = tx
+        // (mod 16).  Per column k, the threads holding column k publish it in LDS
+        // (unscaled; two alternating buffers), and after one barrier every thread
+        // scales the entries it needs by the pivot and updates its own entries.
         constexpr int kOwn = kMaxP / 16;
         const int ty = t >> 4, tx = t & 15;
-        double keep[kOwn];
-        double keep_piv = 1.0;
+        double R[kOwn][kOwn];
 #pragma unroll
-        for (int a = 0; a < kOwn; ++a) keep[a] = 0.0;
+        for (int a = 0; a < kOwn; ++a)
+#pragma unroll
+            for (int b = 0; b < kOwn; ++b) {
+                const int i = ty + 16 * a, j = tx + 16 * b;
+                double v = 0.0;
+                if (i < p && j <= i) {
+                    v = F.L[(int64_t)i * p + j];
+                    if (!s_free[i] || !s_free[j]) v = (i == j) ? 1.0 : 0.0;
+                }
+                R[a][b] = v;
+            }
+        double *cbuf = y + p;   // [2][p]
         for (int k = 0; k < p; ++k) {
-            if (k > 0) {   // column k - 1
-                if (tx == 0) {
+            double *buf = cbuf + (k & 1) * p;
+#pragma unroll
+            for (int b = 0; b < kOwn; ++b)
+                if (tx + 16 * b == k) {
 #pragma unroll
                     for (int a = 0; a < kOwn; ++a) {
                         const int i = ty + 16 * a;
-                        if (i > k - 1 && i < p) A[i * p + k - 1] = keep[a];
+                        if (i >= k && i < p) buf[i] = R[a][b];
                     }
                 }
-                if (t == 0) A[(k - 1) * p + k - 1] = keep_piv;
-            }
-            double d = A[k * p + k];
+            __syncthreads();
+            double d = buf[k];
             const bool ok = d > 0.0;
             if (!ok) d = 1.0;
             const double piv = sqrt(d);
@@ -658,28 +661,29 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
 #pragma unroll
             for (int a = 0; a < kOwn; ++a) {
                 const int i = ty + 16 * a, j = tx + 16 * a;
-                li[a] = (i > k && i < p) ? A[i * p + k] / piv : 0.0;
-                lj[a] = (j > k && j < p) ? A[j * p + k] / piv : 0.0;
+                li[a] = (i > k && i < p) ? buf[i] / piv : 0.0;
+                lj[a] = (j > k && j < p) ? buf[j] / piv : 0.0;
             }
 #pragma unroll
-            for (int a = 0; a < kOwn; ++a) {
-                const int i = ty + 16 * a;
-                if (i > k && i < p) {
+            for (int a = 0; a < kOwn; ++a)
 #pragma unroll
-                    for (int b = 0; b < kOwn; ++b) {
-                        const int j = tx + 16 * b;
-                        if (j > k && j <= i) A[i * p + j] -= li[a] * lj[b];
-                    }
+                for (int b = 0; b < kOwn; ++b) {
+                    const int i = ty + 16 * a, j = tx + 16 * b;
+                    if (j == k && i >= k) R[a][b] = (i == k) ? piv : li[a];   // the factor's column k
+                    else if (j > k && j <= i) R[a][b] = fma(-li[a], lj[b], R[a][b]);
                 }
-                keep[a] = li[a];
-            }
-            keep_piv = piv;
-            __syncthreads();
         }
-        if (t == 0) A[(p - 1) * p + p - 1] = keep_piv;   // the last column is its pivot alone
+#pragma unroll
+        for (int a = 0; a < kOwn; ++a)
+#pragma unroll
+            for (int b = 0; b < kOwn; ++b) {
+                const int i = ty + 16 * a, j = tx + 16 * b;
+                if (i < p && j <= i) {
+                    A[i * p + j] = R[a][b];
+                    F.L[(int64_t)i * p + j] = R[a][b];
+                }
+            }
         __syncthreads();
-        for (int i = wv; i < p; i += kWaves)
-            for (int j = lane; j < p; j += kWave) F.L[(int64_t)i * p + j] = A[i * p + j];
     } else {
         for (int i = wv; i < p; i += kWaves)
             for (int j = lane; j < p; j += kWave) A[i * p + j] = F.L[(int64_t)i * p + j];
@@ -815,10 +819,10 @@ int launch_info(const FitDesc *fits, const int2 *items, int nitems, hipStream_t 
 int launch_step(const FitDesc *fits, const int *slots, int nslots, int max_p, hipStream_t s)
 {
     if (nslots <= 0) return 0;
-    const size_t lds = sizeof(double) * ((size_t)max_p * max_p + max_p);
+    const size_t lds = sizeof(double) * ((size_t)max_p * max_p + 3 * (size_t)max_p);
     static bool attr_set = false;
     if (!attr_set) {
-        const size_t most = sizeof(double) * ((size_t)kMaxP * kMaxP + kMaxP);
+        const size_t most = sizeof(double) * ((size_t)kMaxP * kMaxP + 3 * (size_t)kMaxP);
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)most);
         if (e != hipSuccess) return (int)e;
