@@ -178,6 +178,16 @@ int cox_coordinate(cox_handle *h, const double *beta, int64_t j, double *out);
  */
 int cox_layout(const cox_handle *h, int64_t *perm, uint32_t *meta);
 
+/* The canonical order of Sec. 2.7 on the host, without a handle or a device:
+ * the same perm and meta as cox_layout reports after cox_init of these data
+ * (rows by stratum ascending, time descending, original index ascending;
+ * -0 and +0 are the same time).  time, event, stratum (NULL = one stratum):
+ * host, n entries; perm, meta: host, n entries, written on success.
+ * Errors: COX_EINVAL (n < 1 or > 2^29 - 1, a NULL pointer, a non-finite time,
+ * an event other than 0 or 1), nothing written. */
+int cox_canonical_order(int64_t n, const double *time, const uint8_t *event, const int32_t *stratum,
+                        int64_t *perm, uint32_t *meta);
+
 /* Duration in milliseconds of the last persistent-kernel launch on h, from
  * HIP events recorded on the handle's stream immediately around the launch. */
 int cox_last_kernel_ms(const cox_handle *h, double *ms);

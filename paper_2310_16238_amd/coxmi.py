@@ -110,6 +110,9 @@ SIGNATURES = [
     ("cox_evaluate_full", ctypes.c_int, [_VP, _DP, _DP, _DP, _DP, _DP]),
     ("cox_coordinate", ctypes.c_int, [_VP, _DP, ctypes.c_int64, _DP]),
     ("cox_layout", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32)]),
+    ("cox_canonical_order", ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32)]),
     ("cox_last_kernel_ms", ctypes.c_int, [_VP, _DP]),
     ("cox_last_profile", ctypes.c_int, [_VP, ctypes.POINTER(cox_profile)]),
     ("cox_shape", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -244,6 +247,23 @@ def cox_layout(h):
     meta = np.zeros(n, dtype=np.uint32)
     _check(h, lib().cox_layout(h, perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                meta.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return perm, meta
+
+
+def cox_canonical_order(time, event, stratum=None):
+    """Host canonical order (no device): (perm int64[n], meta uint32[n])."""
+    time = np.ascontiguousarray(time, dtype=np.float64)
+    event = np.ascontiguousarray(event, dtype=np.uint8)
+    n = time.shape[0]
+    st = None if stratum is None else np.ascontiguousarray(stratum, dtype=np.int32)
+    perm = np.zeros(n, dtype=np.int64)
+    meta = np.zeros(n, dtype=np.uint32)
+    rc = lib().cox_canonical_order(n, _dptr(time), event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                   None if st is None else st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   meta.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    if rc != COX_OK:
+        raise CoxError(rc, "cox_canonical_order")
     return perm, meta
 
 

@@ -381,6 +381,21 @@ extern "C" int cox_layout(const cox_handle *h, int64_t *perm, uint32_t *meta)
     return COX_OK;
 }
 
+extern "C" int cox_canonical_order(int64_t n, const double *time, const uint8_t *event, const int32_t *stratum,
+                                   int64_t *perm, uint32_t *meta)
+{
+    if (n < 1 || !perm || !meta) return COX_EINVAL;
+    if (n > (int64_t)kCountMask || !time || !event) return COX_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(time[i]) || event[i] > 1) return COX_EINVAL;
+    std::vector<int64_t> pv;
+    std::vector<uint32_t> mv;
+    canonical_order(n, time, event, stratum, pv, mv);
+    std::memcpy(perm, pv.data(), sizeof(int64_t) * n);
+    std::memcpy(meta, mv.data(), sizeof(uint32_t) * n);
+    return COX_OK;
+}
+
 extern "C" int cox_last_profile(const cox_handle *h, cox_profile *out)
 {
     if (!h || !out) return COX_EINVAL;

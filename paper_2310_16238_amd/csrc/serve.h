@@ -70,6 +70,8 @@ struct FitDesc {
     double *tpart;          // [ntc][2] per scan tile: objective part, range flag
     double *cpart;          // [ntc][p][3] per scan tile and column: score, the two diagonal parts
     FitState *st;
+    FitState *hst;          // host-mapped mirror of *st, written by the step kernel every iteration
+    double *hbeta;          // host-mapped [p]: the estimate, written when the fit is final
     int64_t n, ld, ldz;
     int64_t tile;           // rows per scan tile (ld = ntc * tile)
     int ntc;                // scan tiles

@@ -599,9 +599,14 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     }
     __syncthreads();
     const int action = s_action;
-    if (action == 0) return;
+    if (action == 0) {   // final: the state and the estimate go to the host
+        if (t == 0) *F.hst = *st;
+        for (int j = t; j < p; j += kStepThreads) F.hbeta[j] = F.beta[j];
+        return;
+    }
     if (action == 1) {
         for (int j = t; j < p; j += kStepThreads) F.beta[j] = F.prev[j] + 0.5 * (F.beta[j] - F.prev[j]);
+        if (t == 0) *F.hst = *st;
         return;
     }
     // the columns that move: chosen once, at the first evaluation (g'' > 1e-12 S2-term)
@@ -774,7 +779,12 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
             }
         }
         st->flags = flags;
+        *F.hst = *st;
+        s_action = (flags & kDone) ? 1 : 0;
     }
+    __syncthreads();
+    if (s_action)   // final: every thread sends the entries of beta it wrote
+        for (int j = t; j < p; j += kStepThreads) F.hbeta[j] = F.beta[j];
 }
 
 }  // namespace

@@ -235,14 +235,15 @@ struct cox_server {
     char *staging = nullptr;
     RangeAlloc stage_alloc;
     FitDesc *h_desc = nullptr;
-    FitState *h_state = nullptr;
-    double *h_beta = nullptr;
+    FitState *h_state = nullptr, *dh_state = nullptr;   // host-mapped (and its device address)
+    double *h_beta = nullptr, *dh_beta = nullptr;
 
     // work lists: pinned host copies and device arrays (capacity in bytes)
     struct List {
         char *h = nullptr, *d = nullptr;
         size_t cap = 0;
-    } l_round;   // one block per round: joining descriptors and every work list
+    } l_round,     // one block per round: every work list
+        l_admit[2];   // admission blocks (descriptors, slots, items), alternating
 
     std::vector<Slot> slots;
 
@@ -470,6 +471,8 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off, int slot)
     F.tpart = reinterpret_cast<double *>(B + L.tpart);
     F.cpart = reinterpret_cast<double *>(B + L.cpart);
     F.st = s->d_state + slot;
+    F.hst = s->dh_state + slot;
+    F.hbeta = s->dh_beta + (size_t)slot * kMaxP;
     F.n = L.n;
     F.tile = L.tile;
     F.ntc = L.ntc;
@@ -515,6 +518,7 @@ struct WorkerState {
     std::vector<int> upload_stage_release;
     hipEvent_t copy_ev = nullptr;
     bool copy_pending = false;
+    int admit_buf = 0;
 };
 
 #define WCHECK(expr, what)                      \
@@ -525,6 +529,18 @@ struct WorkerState {
             return false;                       \
         }                                       \
     } while (0)
+
+// Carves the round block into typed arrays at 16-byte aligned offsets.
+struct Packer {
+    size_t used = 0;
+    template <class T>
+    size_t take(size_t count)
+    {
+        const size_t at = used;
+        used = round_up(used + sizeof(T) * count, 16);
+        return at;
+    }
+};
 
 bool admit_ready(cox_server *s, WorkerState &ws, std::string &err)
 {
@@ -563,28 +579,43 @@ bool admit_ready(cox_server *s, WorkerState &ws, std::string &err)
             err = "internal error: a fit descriptor points outside its block";
             return false;
         }
-        // the descriptor is installed, and z, beta and the state cleared, by the admit kernel
         WCHECK(hipMemcpyAsync(B, s->staging + q.stage_off, q.lay.upload, hipMemcpyHostToDevice, s->copy),
                "uploading a fit");
         S.req = std::move(tk.second);
         ws.uploading.push_back(slot);
     }
+    // after the uploads, on the same stream (so beside this round's iteration): the admit
+    // kernel installs the descriptors, clears z, beta and the states, and forms the FP32
+    // copies (gathering X of device-resident requests).  Its block alternates between two
+    // buffers: the one used two admissions ago is free, since the round after that
+    // admission waited for it.
+    size_t n_items = 0;
+    for (auto &tk : taken) n_items += (size_t)s->slots[tk.first].req->lay.ntile;
+    Packer pk;
+    const size_t o_jd = pk.take<FitDesc>(taken.size()), o_js = pk.take<int>(taken.size());
+    const size_t o_it = pk.take<int2>(n_items);
+    cox_server::List &l = s->l_admit[ws.admit_buf];
+    ws.admit_buf ^= 1;
+    if (!ensure_list(l, pk.used, err)) return false;
+    FitDesc *jd = reinterpret_cast<FitDesc *>(l.h + o_jd);
+    int *js = reinterpret_cast<int *>(l.h + o_js);
+    int2 *items = reinterpret_cast<int2 *>(l.h + o_it);
+    size_t ka = 0;
+    for (size_t k = 0; k < taken.size(); ++k) {
+        const int sl = taken[k].first;
+        jd[k] = s->h_desc[sl];
+        js[k] = sl;
+        for (int t = 0; t < s->slots[sl].req->lay.ntile; ++t) items[ka++] = make_int2((int)k, t);
+    }
+    WCHECK(hipMemcpyAsync(l.d, l.h, pk.used, hipMemcpyHostToDevice, s->copy), "admit list");
+    WCHECK((hipError_t)launch_admit(s->d_desc, reinterpret_cast<const FitDesc *>(l.d + o_jd),
+                                    reinterpret_cast<const int *>(l.d + o_js), reinterpret_cast<const int2 *>(l.d + o_it),
+                                    (int)ka, s->copy),
+           "admit kernel");
     WCHECK(hipEventRecord(ws.copy_ev, s->copy), "recording the upload");
     ws.copy_pending = true;
     return true;
 }
-
-// Carves the round block into typed arrays at 16-byte aligned offsets.
-struct Packer {
-    size_t used = 0;
-    template <class T>
-    size_t take(size_t count)
-    {
-        const size_t at = used;
-        used = round_up(used + sizeof(T) * count, 16);
-        return at;
-    }
-};
 
 bool run_round(cox_server *s, WorkerState &ws, std::string &err)
 {
@@ -604,8 +635,7 @@ bool run_round(cox_server *s, WorkerState &ws, std::string &err)
     double t_launch = s->now();
     if (launched) {
         // sizes of the lists
-        size_t n_admit = 0, n_eta = 0, n_rows = 0, n_cols = 0, n_syrk = 0, n_info = 0;
-        for (int sl : joining) n_admit += (size_t)s->slots[sl].req->lay.ntile;
+        size_t n_eta = 0, n_rows = 0, n_cols = 0, n_syrk = 0, n_info = 0;
         for (int sl : act) {
             const FitLayout &L = s->slots[sl].req->lay;
             n_eta += L.ntile;
@@ -617,28 +647,18 @@ bool run_round(cox_server *s, WorkerState &ws, std::string &err)
             }
         }
         Packer pk;
-        const size_t o_jd = pk.take<FitDesc>(joining.size()), o_js = pk.take<int>(joining.size());
-        const size_t o_admit = pk.take<int2>(n_admit), o_eta = pk.take<int2>(n_eta), o_rows = pk.take<int2>(n_rows);
+        const size_t o_eta = pk.take<int2>(n_eta), o_rows = pk.take<int2>(n_rows);
         const size_t o_cols = pk.take<int2>(n_cols), o_syrk = pk.take<int4>(n_syrk), o_info = pk.take<int2>(n_info);
         const size_t o_slots = pk.take<int>(act.size());
         if (!ensure_list(s->l_round, pk.used, err)) return false;
         char *H = s->l_round.h, *D = s->l_round.d;
-        FitDesc *jd = reinterpret_cast<FitDesc *>(H + o_jd);
-        int *js = reinterpret_cast<int *>(H + o_js);
-        int2 *adm = reinterpret_cast<int2 *>(H + o_admit);
         int2 *eta = reinterpret_cast<int2 *>(H + o_eta);
         int2 *rws = reinterpret_cast<int2 *>(H + o_rows);
         int2 *cols = reinterpret_cast<int2 *>(H + o_cols);
         int4 *syrk = reinterpret_cast<int4 *>(H + o_syrk);
         int2 *info = reinterpret_cast<int2 *>(H + o_info);
         int *sl_list = reinterpret_cast<int *>(H + o_slots);
-        size_t ka = 0, ke = 0, kr = 0, kc = 0, ks = 0, ki = 0;
-        for (size_t k = 0; k < joining.size(); ++k) {
-            const int sl = joining[k];
-            jd[k] = s->h_desc[sl];
-            js[k] = sl;
-            for (int t = 0; t < s->slots[sl].req->lay.ntile; ++t) adm[ka++] = make_int2((int)k, t);
-        }
+        size_t ke = 0, kr = 0, kc = 0, ks = 0, ki = 0;
         int max_p = 1;
         for (size_t a = 0; a < act.size(); ++a) {
             const int sl = act[a];
@@ -657,16 +677,11 @@ bool run_round(cox_server *s, WorkerState &ws, std::string &err)
                     for (int r = 0; r < L.nzr; ++r) syrk[ks++] = make_int4(sl, pr, r, 1);
                 }
         }
-        if (ka != n_admit || ke != n_eta || kr != n_rows || kc != n_cols || ks != n_syrk || ki != n_info) {
+        if (ke != n_eta || kr != n_rows || kc != n_cols || ks != n_syrk || ki != n_info) {
             err = "internal error: work list sizes";
             return false;
         }
         WCHECK(hipMemcpyAsync(D, H, pk.used, hipMemcpyHostToDevice, s->compute), "work lists");
-        if (ka)
-            WCHECK((hipError_t)launch_admit(s->d_desc, reinterpret_cast<const FitDesc *>(D + o_jd),
-                                            reinterpret_cast<const int *>(D + o_js),
-                                            reinterpret_cast<const int2 *>(D + o_admit), (int)ka, s->compute),
-                   "admit kernel");
         WCHECK((hipError_t)launch_eta(s->d_desc, reinterpret_cast<const int2 *>(D + o_eta), (int)ke, s->compute), "eta");
         WCHECK((hipError_t)launch_rows(s->d_desc, reinterpret_cast<const int2 *>(D + o_rows), (int)kr, s->compute),
                "rows");
@@ -681,9 +696,7 @@ bool run_round(cox_server *s, WorkerState &ws, std::string &err)
         WCHECK((hipError_t)launch_step(s->d_desc, reinterpret_cast<const int *>(D + o_slots), (int)act.size(), max_p,
                                        s->compute),
                "step");
-        const int hi = act.back() + 1;   // act is in slot order
-        WCHECK(hipMemcpyAsync(s->h_state, s->d_state, sizeof(FitState) * hi, hipMemcpyDeviceToHost, s->compute),
-               "reading fit states");
+        // the step kernel writes each fit's state (and a final estimate) to host-mapped memory
         WCHECK(hipEventRecord(s->iter_ev, s->compute), "recording the iteration");
     }
     // 3. while the GPU iterates: admit what the prep pool has staged (uploads on the copy stream)
@@ -707,13 +720,6 @@ bool run_round(cox_server *s, WorkerState &ws, std::string &err)
         if (st.flags & kDone) done.push_back(sl);
         else s->slots[sl].frozen = (st.flags & kFrozen) != 0;
     }
-    for (int sl : done) {
-        const FitDesc &F = s->h_desc[sl];
-        WCHECK(hipMemcpyAsync(s->h_beta + (size_t)sl * kMaxP, F.beta, sizeof(double) * F.p, hipMemcpyDeviceToHost,
-                              s->compute),
-               "reading an estimate");
-    }
-    if (!done.empty()) WCHECK(hipStreamSynchronize(s->compute), "reading estimates");
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->iterations += 1;
@@ -805,7 +811,7 @@ void free_server(cox_server *s)
     if (s->h_desc) (void)hipHostFree(s->h_desc);
     if (s->h_state) (void)hipHostFree(s->h_state);
     if (s->h_beta) (void)hipHostFree(s->h_beta);
-    for (cox_server::List *l : {&s->l_round}) {
+    for (cox_server::List *l : {&s->l_round, &s->l_admit[0], &s->l_admit[1]}) {
         if (l->h) (void)hipHostFree(l->h);
         if (l->d) (void)hipFree(l->d);
     }
@@ -871,10 +877,13 @@ extern "C" int cox_server_create(cox_server **out, const cox_server_options *o)
             hipSuccess ||
         (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_desc), sizeof(FitDesc) * ns, hipHostMallocDefault)) !=
             hipSuccess ||
-        (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_state), sizeof(FitState) * ns, hipHostMallocDefault)) !=
-            hipSuccess ||
-        (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_beta), sizeof(double) * kMaxP * ns, hipHostMallocDefault)) !=
-            hipSuccess) {
+        // written by the step kernel, read by the worker after each iteration's event
+        (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_state), sizeof(FitState) * ns,
+                           hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_beta), sizeof(double) * kMaxP * ns,
+                           hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->dh_state), s->h_state, 0)) != hipSuccess ||
+        (e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->dh_beta), s->h_beta, 0)) != hipSuccess) {
         g_create_error = std::string("server allocation: ") + hipGetErrorString(e);
         free_server(s.get());
         return e == hipErrorOutOfMemory ? COX_ENOMEM : COX_EDEVICE;
