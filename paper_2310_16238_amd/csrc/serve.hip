@@ -548,9 +548,10 @@ constexpr int kStepThreads = 256;
 
 __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits, const int *slots)
 {
-    extern __shared__ double lds[];   // A[p * p], y[p], two column buffers [2][p]
+    extern __shared__ double lds[];   // A[p * p], y[p]
     __shared__ int s_action, s_bad, s_frozen;
     __shared__ uint8_t s_free[kMaxP];
+    __shared__ __align__(16) double s_col[2][kMaxP];   // Cholesky column buffers
     __shared__ double s_red[kStepThreads / kWave];
     const FitDesc F = fits[slots[blockIdx.x]];
     FitState *st = F.st;
@@ -625,10 +626,13 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     if (!frozen) {
         // Right-looking Cholesky of the information matrix (info kernel; rows and
         // columns not free become unit rows) with the matrix in registers: thread
-        // (ty, tx) holds the lower-triangle entries (i, j) with i = ty, j = tx
-        // (mod 16).  Per column k, the threads holding column k publish it in LDS
-        // (unscaled; two alternating buffers), and after one barrier every thread
-        // scales the entries it needs by the pivot and updates its own entries.
+        // (ty, tx) holds the entries (i, j) with i = ty, j = tx (mod 16).  Per column
+        // k, the 16 threads holding column k publish it in LDS -- zero outside rows
+        // k..p-1, entry i at (i mod 16) * 8 + i / 16 so that a thread's 8 rows (or
+        // columns) are contiguous; two alternating buffers -- and after one barrier
+        // every thread scales what it needs by 1/pivot and updates all its entries
+        // (zeros leave the finished columns as they are; entries above the diagonal
+        // are never read).  The holders then set column k of the factor.
         constexpr int kOwn = kMaxP / 16;
         const int ty = t >> 4, tx = t & 15;
         double R[kOwn][kOwn];
@@ -644,39 +648,59 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
                 }
                 R[a][b] = v;
             }
-        double *cbuf = y + p;   // [2][p]
         for (int k = 0; k < p; ++k) {
-            double *buf = cbuf + (k & 1) * p;
+            double *buf = s_col[k & 1];
+            const int bk = k >> 4;
+            if (tx == (k & 15)) {
+                double v[kOwn];
 #pragma unroll
-            for (int b = 0; b < kOwn; ++b)
-                if (tx + 16 * b == k) {
+                for (int b = 0; b < kOwn; ++b)
+                    if (b == bk) {
 #pragma unroll
-                    for (int a = 0; a < kOwn; ++a) {
-                        const int i = ty + 16 * a;
-                        if (i >= k && i < p) buf[i] = R[a][b];
+                        for (int a = 0; a < kOwn; ++a) {
+                            const int i = ty + 16 * a;
+                            v[a] = (i >= k && i < p) ? R[a][b] : 0.0;
+                        }
                     }
-                }
+                double2 *dst = reinterpret_cast<double2 *>(buf + ty * kOwn);
+#pragma unroll
+                for (int a = 0; a < kOwn; a += 2) dst[a / 2] = make_double2(v[a], v[a + 1]);
+            }
             __syncthreads();
-            double d = buf[k];
+            double d = buf[(k & 15) * kOwn + bk];
             const bool ok = d > 0.0;
             if (!ok) d = 1.0;
-            const double piv = sqrt(d);
+            const double piv = sqrt(d), inv = 1.0 / piv;
             if (t == 0 && !ok) s_bad = 1;
             double li[kOwn], lj[kOwn];
+            const double2 *ri = reinterpret_cast<const double2 *>(buf + ty * kOwn);
+            const double2 *rj = reinterpret_cast<const double2 *>(buf + tx * kOwn);
 #pragma unroll
-            for (int a = 0; a < kOwn; ++a) {
-                const int i = ty + 16 * a, j = tx + 16 * a;
-                li[a] = (i > k && i < p) ? buf[i] / piv : 0.0;
-                lj[a] = (j > k && j < p) ? buf[j] / piv : 0.0;
+            for (int a = 0; a < kOwn; a += 2) {
+                const double2 u = ri[a / 2], w = rj[a / 2];
+                li[a] = u.x * inv;
+                li[a + 1] = u.y * inv;
+                lj[a] = w.x * inv;
+                lj[a + 1] = w.y * inv;
             }
+            // row k and column k take part too (their products land above the
+            // diagonal or in column k, which is set below); finished columns see zeros
 #pragma unroll
             for (int a = 0; a < kOwn; ++a)
 #pragma unroll
-                for (int b = 0; b < kOwn; ++b) {
-                    const int i = ty + 16 * a, j = tx + 16 * b;
-                    if (j == k && i >= k) R[a][b] = (i == k) ? piv : li[a];   // the factor's column k
-                    else if (j > k && j <= i) R[a][b] = fma(-li[a], lj[b], R[a][b]);
-                }
+                for (int b = 0; b < kOwn; ++b) R[a][b] = fma(-li[a], lj[b], R[a][b]);
+            if (tx == (k & 15)) {
+#pragma unroll
+                for (int b = 0; b < kOwn; ++b)
+                    if (b == bk) {
+#pragma unroll
+                        for (int a = 0; a < kOwn; ++a) {
+                            const int i = ty + 16 * a;
+                            if (i == k) R[a][b] = piv;
+                            else if (i > k) R[a][b] = li[a];
+                        }
+                    }
+            }
         }
 #pragma unroll
         for (int a = 0; a < kOwn; ++a)
@@ -829,10 +853,10 @@ int launch_info(const FitDesc *fits, const int2 *items, int nitems, hipStream_t 
 int launch_step(const FitDesc *fits, const int *slots, int nslots, int max_p, hipStream_t s)
 {
     if (nslots <= 0) return 0;
-    const size_t lds = sizeof(double) * ((size_t)max_p * max_p + 3 * (size_t)max_p);
+    const size_t lds = sizeof(double) * ((size_t)max_p * max_p + max_p);
     static bool attr_set = false;
     if (!attr_set) {
-        const size_t most = sizeof(double) * ((size_t)kMaxP * kMaxP + 3 * (size_t)kMaxP);
+        const size_t most = sizeof(double) * ((size_t)kMaxP * kMaxP + kMaxP);
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)most);
         if (e != hipSuccess) return (int)e;

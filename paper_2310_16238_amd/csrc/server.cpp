@@ -507,7 +507,8 @@ bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_
            in(F.tilemax, 8 * (size_t)L.ntile) && in(F.tpart, 16 * (size_t)L.ntc) &&
            in(F.cpart, 24 * (size_t)L.ntc * p) && (!L.device || (in(F.src, 4 * ld) && F.xs && F.ldxs >= L.n)) && F.tile > 0 && F.tile % kRowPad == 0 && F.ntc >= 1 &&
            F.tile * F.ntc == F.ld &&
-           F.st == s->d_state + slot && F.p == L.p && F.ld == L.ld &&
+           F.st == s->d_state + slot && F.hst == s->dh_state + slot && F.hbeta == s->dh_beta + (size_t)slot * kMaxP &&
+           F.p == L.p && F.ld == L.ld &&
            F.n <= F.ld && F.ld % kRowPad == 0 && F.ldz % kRowPad == 0 && F.G <= F.ldz && F.p >= 1 &&
            F.p <= kMaxP && F.ntile * (int64_t)kEtaRows >= F.ld;
 }
