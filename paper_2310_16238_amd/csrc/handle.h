@@ -26,6 +26,7 @@ struct NewtonState {
     double *carry = nullptr;       // [ntiles][p]
     double *colpart = nullptr;     // [ntiles][p][3]
     double *vec = nullptr;         // beta, grad, diag1, diag2, dx (p each), scal (8)
+    double *hvec = nullptr;        // pinned host mirror of vec, then flags and status (one double each)
     unsigned *flags = nullptr;
     int *status = nullptr;
     uint8_t *free_col = nullptr;   // [p]

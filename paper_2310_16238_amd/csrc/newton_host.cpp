@@ -91,7 +91,9 @@ int newton_setup(cox_handle *h)
         (e = dalloc(&s.zscale, sizeof(float) * p)) != hipSuccess ||
         (e = dalloc(&s.syrk_part, s.syrk_part_bytes)) != hipSuccess ||
         (e = dalloc(&s.info, sizeof(double) * (size_t)p * p)) != hipSuccess ||
-        (e = dalloc(&s.scan_scratch, s.scan_scratch_bytes)) != hipSuccess) {
+        (e = dalloc(&s.scan_scratch, s.scan_scratch_bytes)) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void **>(&s.hvec), sizeof(double) * (5 * (size_t)p + kScalSlots + 2),
+                           hipHostMallocDefault)) != hipSuccess) {
         newton_free(h);
         return handle_hip_fail(h, e, "allocating full-evaluation buffers");
     }
@@ -158,7 +160,10 @@ int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
     const int p = (int)h->p;
     double *d_beta = s.vec, *d_grad = s.vec + p, *d_d1 = s.vec + 2 * p, *d_d2 = s.vec + 3 * p;
     double *d_scal = s.vec + 5 * p;
-    hipError_t e = hipMemcpyAsync(d_beta, beta, sizeof(double) * p, hipMemcpyHostToDevice, h->stream);
+    // beta goes up, and the results come back, through the pinned mirror: one
+    // synchronisation per evaluation
+    std::memcpy(s.hvec, beta, sizeof(double) * p);
+    hipError_t e = hipMemcpyAsync(d_beta, s.hvec, sizeof(double) * p, hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) return handle_hip_fail(h, e, "staging beta");
     FullEvalArgs A;
     A.x = h->d_x;
@@ -203,22 +208,24 @@ int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
     int rc = full_eval_launch(A, h->stream);
     if (rc != 0) return handle_fail(h, rc == -5 ? COX_EUNSUPPORTED : COX_EDEVICE, "full evaluation launch");
     (void)hipEventRecord(s.ev[1], h->stream);
-    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return handle_hip_fail(h, e, "full evaluation");
+    // grad, diag1, diag2, dx and scal are contiguous after beta
+    double *hres = s.hvec + p;
+    unsigned *hflags = reinterpret_cast<unsigned *>(s.hvec + 5 * p + kScalSlots);
+    if ((e = hipMemcpyAsync(hres, d_grad, sizeof(double) * (4 * (size_t)p + kScalSlots), hipMemcpyDeviceToHost,
+                            h->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(hflags, s.flags, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+        return handle_hip_fail(h, e, "full evaluation");
+    (void)d_d1;
+    (void)d_d2;
     h->prof.evaluations += 1;
     h->prof.evaluation_ms += elapsed_ms(s.ev[0], s.ev[1]);
-    double scal[2];
-    out.grad.resize(p);
-    out.diag1.resize(p);
-    out.diag2.assign(p, 0.0);
-    if ((e = hipMemcpy(scal, d_scal, sizeof(scal), hipMemcpyDeviceToHost)) != hipSuccess ||
-        (e = hipMemcpy(&out.flags, s.flags, sizeof(unsigned), hipMemcpyDeviceToHost)) != hipSuccess ||
-        (e = hipMemcpy(out.grad.data(), d_grad, sizeof(double) * p, hipMemcpyDeviceToHost)) != hipSuccess ||
-        (e = hipMemcpy(out.diag1.data(), d_d1, sizeof(double) * p, hipMemcpyDeviceToHost)) != hipSuccess)
-        return handle_hip_fail(h, e, "reading the evaluation");
-    if (want_xbar &&
-        (e = hipMemcpy(out.diag2.data(), d_d2, sizeof(double) * p, hipMemcpyDeviceToHost)) != hipSuccess)
-        return handle_hip_fail(h, e, "reading the evaluation");
-    out.objective = scal[1];
+    out.grad.assign(hres, hres + p);
+    out.diag1.assign(hres + p, hres + 2 * p);
+    if (want_xbar) out.diag2.assign(hres + 2 * p, hres + 3 * p);
+    else out.diag2.assign(p, 0.0);
+    out.flags = *hflags;
+    out.objective = hres[4 * p + 1];
     if (out.flags & 1u) return handle_fail(h, COX_ENUMERIC, "a risk-set sum left the FP64 normal range");
     return COX_OK;
 }
@@ -263,6 +270,7 @@ void newton_free(cox_handle *h)
                     s.zscale, s.xlp, s.xscale, s.syrk_part, s.info, s.scan_scratch, s.wscratch};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    if (s.hvec) (void)hipHostFree(s.hvec);
     for (hipEvent_t ev : s.ev)
         if (ev) (void)hipEventDestroy(ev);
     s = NewtonState();
@@ -347,17 +355,20 @@ int newton_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_inf
         if (chol_solve(s.info, p, d_grad, s.free_col, frozen ? 1 : 0, d_dx, s.status, h->stream) != 0)
             return handle_fail(h, COX_EDEVICE, "Cholesky launch");
         (void)hipEventRecord(s.ev[5], h->stream);
-        hipError_t e = hipStreamSynchronize(h->stream);
+        int *hstatus = reinterpret_cast<int *>(s.hvec + 5 * p + kScalSlots + 1);
+        double *hdx = s.hvec + 4 * p;
+        hipError_t e = hipMemcpyAsync(hdx, d_dx, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(hstatus, s.status, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (!frozen) {
             h->prof.contractions += 1;
             h->prof.contraction_ms += elapsed_ms(s.ev[2], s.ev[3]);
         }
         h->prof.solves += 1;
         h->prof.solve_ms += elapsed_ms(s.ev[4], s.ev[5]);
-        int status = 0;
-        if (e == hipSuccess) e = hipMemcpy(&status, s.status, sizeof(int), hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMemcpy(dx.data(), d_dx, sizeof(double) * p, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return handle_hip_fail(h, e, "Cholesky solve");
+        const int status = *hstatus;
+        std::memcpy(dx.data(), hdx, sizeof(double) * p);
         if (status) return handle_fail(h, COX_ENUMERIC, "the information matrix is not positive definite");
         prev = beta;
         obj_prev = ev.objective;
