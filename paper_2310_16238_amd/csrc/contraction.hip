@@ -185,66 +185,108 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(double *A, int p, const
     if (t == 0) status[0] = s_bad;
 }
 
-// Blocked variant for p <= kCholMaxP: 32-column panels factored in LDS, the
-// trailing update in 4 x 4 register blocks, triangular solves by 32-row
-// blocks (one wave solves the diagonal block with lane shuffles).  Same
-// contract as chol_solve_kernel.
-constexpr int kCholNB = 32, kCholThreads = 1024, kCholMaxP = 512;
+// Blocked variant for p <= kCholMaxP, 16-column panels, three barriers each:
+//   1. wave 0 factors the 16 x 16 diagonal block, a row per lane in registers
+//      (each scaled column goes through LDS to the lanes below it);
+//   2. every thread takes one row below the block and solves x L11' = a for it
+//      (L11 read from LDS by all lanes at once), giving the panel L21;
+//   3. all threads update the trailing lower triangle in 4 x 4 register blocks
+//      from L21 (kept in LDS): A22 -= L21 L21'.
+// Triangular solves by 32-row blocks (one wave solves the diagonal block with
+// lane shuffles).  Same contract as chol_solve_kernel.
+constexpr int kCholNB = 32, kCholThreads = 512, kCholMaxP = 512, kPanNB = 16;
 
 __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, int p, const double *g,
                                                                     const uint8_t *free_col, int factored,
                                                                     double *dx, int *status)
 {
-    extern __shared__ double lds[];   // panel [p][kCholNB], then y[p]
-    double *P = lds;
+    // panel L21 [kPanNB][p] (column-major: entry (i, c) at c * p + i), then y at p * kCholNB
+    extern __shared__ double lds[];
+    double *pan = lds;
     double *y = lds + (size_t)p * kCholNB;
-    __shared__ double s_piv;
+    __shared__ double s_l11[kPanNB][kPanNB + 1];   // the factored diagonal block, row-major
+    __shared__ double s_inv[kPanNB];                 // 1 / its diagonal
+    __shared__ double s_col[kPanNB];                 // one scaled column of the block
     __shared__ int s_bad;
     const int t = threadIdx.x;
     const int lane = t & (kWaveC - 1), wv = t / kWaveC;
+    constexpr int kWaves = kCholThreads / kWaveC;
     if (t == 0) s_bad = 0;
     if (!factored) {
-        for (int64_t e = t; e < (int64_t)p * p; e += kCholThreads) {
-            const int i = (int)(e / p), j = (int)(e % p);
-            if (!free_col[i] || !free_col[j]) A[e] = (i == j) ? 1.0 : 0.0;
-        }
+        // rows and columns not free become unit rows
+        for (int i = wv; i < p; i += kWaves)
+            for (int j = lane; j < p; j += kWaveC)
+                if (!free_col[i] || !free_col[j]) A[(int64_t)i * p + j] = (i == j) ? 1.0 : 0.0;
         __syncthreads();
-        for (int k0 = 0; k0 < p; k0 += kCholNB) {
-            const int nb = p - k0 < kCholNB ? p - k0 : kCholNB;
-            const int m = p - k0;
-            for (int e = t; e < m * kCholNB; e += kCholThreads) {
-                const int i = e / kCholNB, c = e % kCholNB;
-                P[e] = (c < nb) ? A[(int64_t)(k0 + i) * p + k0 + c] : 0.0;
+        for (int c0 = 0; c0 < p; c0 += kPanNB) {
+            const int nb = p - c0 < kPanNB ? p - c0 : kPanNB;
+            // 1. diagonal block: lane r holds row c0 + r (entries up to the diagonal)
+            if (wv == 0) {
+                double D[kPanNB];
+#pragma unroll
+                for (int c = 0; c < kPanNB; ++c)
+                    D[c] = (lane < nb && c <= lane) ? A[(int64_t)(c0 + lane) * p + c0 + c] : 0.0;
+#pragma unroll
+                for (int kk = 0; kk < kPanNB; ++kk) {
+                    if (kk < nb) {
+                        double d = __shfl(D[kk], kk, kWaveC);
+                        const bool ok = d > 0.0;
+                        if (!ok) d = 1.0;
+                        const double piv = sqrt(d), inv = 1.0 / piv;
+                        if (lane == 0) {
+                            if (!ok) s_bad = 1;
+                            s_inv[kk] = inv;
+                        }
+                        if (lane == kk) D[kk] = piv;
+                        else if (lane > kk) D[kk] *= inv;
+                        if (lane < kPanNB) s_col[lane] = D[kk];
+                        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                        for (int jj = kk + 1; jj < kPanNB; ++jj)
+                            if (jj < nb && lane >= jj) D[jj] = fma(-D[kk], s_col[jj], D[jj]);
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+                if (lane < nb) {
+#pragma unroll
+                    for (int c = 0; c < kPanNB; ++c)
+                        if (c <= lane) {
+                            s_l11[lane][c] = D[c];
+                            A[(int64_t)(c0 + lane) * p + c0 + c] = D[c];
+                        }
+                }
             }
             __syncthreads();
-            for (int c = 0; c < nb; ++c) {
-                if (t == 0) {
-                    double d = P[c * kCholNB + c];
-                    if (!(d > 0.0)) {
-                        s_bad = 1;
-                        d = 1.0;
+            // 2. the rows below the block: x L11' = a, one row per thread
+            const int r0 = c0 + nb;
+            for (int i = r0 + t; i < p; i += kCholThreads) {
+                double a[kPanNB];
+                const double *row = A + (int64_t)i * p + c0;
+#pragma unroll
+                for (int c = 0; c < kPanNB; ++c) a[c] = c < nb ? row[c] : 0.0;
+#pragma unroll
+                for (int c = 0; c < kPanNB; ++c) {
+                    if (c < nb) {
+                        double v = a[c];
+#pragma unroll
+                        for (int q = 0; q < c; ++q) v = fma(-a[q], s_l11[c][q], v);
+                        a[c] = v * s_inv[c];
                     }
-                    s_piv = sqrt(d);
-                    P[c * kCholNB + c] = s_piv;
+                    // keep the LDS reads of row c + 1 of L11 from being hoisted above this
+                    // point (hoisting all of them would not fit in registers)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                __syncthreads();
-                const double piv = s_piv;
-                for (int i = c + 1 + t; i < m; i += kCholThreads) P[i * kCholNB + c] /= piv;
-                __syncthreads();
-                const int w = nb - c - 1;
-                if (w > 0)
-                    for (int e = t; e < (m - c - 1) * w; e += kCholThreads) {
-                        const int i = c + 1 + e / w, cc = c + 1 + e % w;
-                        if (cc <= i) P[i * kCholNB + cc] -= P[i * kCholNB + c] * P[cc * kCholNB + c];
+                double *wrow = A + (int64_t)i * p + c0;
+#pragma unroll
+                for (int c = 0; c < kPanNB; ++c)
+                    if (c < nb) {
+                        wrow[c] = a[c];
+                        pan[c * p + i] = a[c];
                     }
-                __syncthreads();
             }
-            for (int e = t; e < m * kCholNB; e += kCholThreads) {
-                const int i = e / kCholNB, c = e % kCholNB;
-                if (c < nb && c <= i) A[(int64_t)(k0 + i) * p + k0 + c] = P[e];
-            }
-            // trailing update of the lower triangle: A22 -= P2 P2'
-            const int m2 = m - nb;
+            __syncthreads();
+            // 3. trailing update of the lower triangle: A22 -= L21 L21'
+            const int m2 = p - r0;
             if (m2 > 0) {
                 const int nb4 = (m2 + 3) / 4;
                 const int nblk = nb4 * (nb4 + 1) / 2;
@@ -263,9 +305,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
                         double ai[4], aj[4];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            const int ii = nb + 4 * bi + u, jj = nb + 4 * bj + u;
-                            ai[u] = ii < m ? P[ii * kCholNB + c] : 0.0;
-                            aj[u] = jj < m ? P[jj * kCholNB + c] : 0.0;
+                            const int ii = r0 + 4 * bi + u, jj = r0 + 4 * bj + u;
+                            ai[u] = ii < p ? pan[c * p + ii] : 0.0;
+                            aj[u] = jj < p ? pan[c * p + jj] : 0.0;
                         }
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
@@ -276,7 +318,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
                     for (int u = 0; u < 4; ++u)
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const int i = k0 + nb + 4 * bi + u, j = k0 + nb + 4 * bj + v;
+                            const int i = r0 + 4 * bi + u, j = r0 + 4 * bj + v;
                             if (i < p && j <= i) A[(int64_t)i * p + j] -= acc[u][v];
                         }
                 }
@@ -287,14 +329,23 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
     // solves: L y = -g, then L' x = y (free columns only)
     for (int i = t; i < p; i += kCholThreads) y[i] = free_col[i] ? -g[i] : 0.0;
     __syncthreads();
+    // the diagonal block's entries a lane needs are loaded into registers first
+    // (all loads in flight together), so the sequential steps wait only on shuffles
     for (int k0 = 0; k0 < p; k0 += kCholNB) {
         const int nb = p - k0 < kCholNB ? p - k0 : kCholNB;
         if (wv == 0) {
+            double Lr[kCholNB];   // row k0 + lane of the block (entries up to the diagonal)
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c)
+                Lr[c] = (lane < nb && c <= lane) ? A[(int64_t)(k0 + lane) * p + k0 + c] : 1.0;
             double yi = lane < nb ? y[k0 + lane] : 0.0;
-            for (int c = 0; c < nb; ++c) {
-                if (lane == c) yi /= A[(int64_t)(k0 + c) * p + k0 + c];
-                const double yc = __shfl(yi, c, kWaveC);
-                if (lane > c && lane < nb) yi -= A[(int64_t)(k0 + lane) * p + k0 + c] * yc;
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c) {
+                if (c < nb) {
+                    if (lane == c) yi /= Lr[c];
+                    const double yc = __shfl(yi, c, kWaveC);
+                    if (lane > c && lane < nb) yi = fma(-Lr[c], yc, yi);
+                }
             }
             if (lane < nb) y[k0 + lane] = yi;
         }
@@ -310,11 +361,18 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
     for (int k0 = ((p - 1) / kCholNB) * kCholNB; k0 >= 0; k0 -= kCholNB) {
         const int nb = p - k0 < kCholNB ? p - k0 : kCholNB;
         if (wv == 0) {
+            double Lc[kCholNB];   // column k0 + lane of the block (entries from the diagonal down)
+#pragma unroll
+            for (int c = 0; c < kCholNB; ++c)
+                Lc[c] = (lane < nb && c >= lane && c < nb) ? A[(int64_t)(k0 + c) * p + k0 + lane] : 1.0;
             double xi = lane < nb ? y[k0 + lane] : 0.0;
-            for (int c = nb - 1; c >= 0; --c) {
-                if (lane == c) xi /= A[(int64_t)(k0 + c) * p + k0 + c];
-                const double xc = __shfl(xi, c, kWaveC);
-                if (lane < c) xi -= A[(int64_t)(k0 + c) * p + k0 + lane] * xc;
+#pragma unroll
+            for (int c = kCholNB - 1; c >= 0; --c) {
+                if (c < nb) {
+                    if (lane == c) xi /= Lc[c];
+                    const double xc = __shfl(xi, c, kWaveC);
+                    if (lane < c) xi = fma(-Lc[c], xc, xi);
+                }
             }
             if (lane < nb) y[k0 + lane] = xi;
         }
