@@ -254,31 +254,46 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
         g[c] = d1[c] = d2[c] = 0.0;
         cb[c] = (XBAR && live[c] && tile_carry[t]) ? carry[(int64_t)t * p + j] : 0.0;
     }
-    for (int64_t base = r_begin; base < r_end; base += kColChunk) {
-        const int64_t r0 = base + (int64_t)lane * kColIpt;   // 4 consecutive rows per lane: 16-byte loads
+    // one chunk's loads: 4 consecutive rows per lane (16-byte loads); the next
+    // chunk's loads are issued before this chunk is processed
+    struct Chunk {
         double xv[CB][kColIpt], bv[kColIpt], av[kColIpt], uv[kColIpt], qv[kColIpt];
         uint32_t m[kColIpt];
         int32_t gi[kColIpt];
+    };
+    auto load_chunk = [&](Chunk &k, int64_t r0) {
 #pragma unroll
-        for (int c = 0; c < CB; ++c) load4(xc[c] + r0, xv[c]);
-        load4(b + r0, bv);
-        {
-            const uint4 mm = *reinterpret_cast<const uint4 *>(meta + r0);
-            m[0] = mm.x;
-            m[1] = mm.y;
-            m[2] = mm.z;
-            m[3] = mm.w;
-        }
+        for (int c = 0; c < CB; ++c) load4(xc[c] + r0, k.xv[c]);
+        load4(b + r0, k.bv);
+        const uint4 mm = *reinterpret_cast<const uint4 *>(meta + r0);
+        k.m[0] = mm.x;
+        k.m[1] = mm.y;
+        k.m[2] = mm.z;
+        k.m[3] = mm.w;
         if (XBAR) {
-            load4(alpha + r0, av);
-            load4(u + r0, uv);
-            load4(zq + r0, qv);
+            load4(alpha + r0, k.av);
+            load4(u + r0, k.uv);
+            load4(zq + r0, k.qv);
             const int4 gg = *reinterpret_cast<const int4 *>(gidx + r0);
-            gi[0] = gg.x;
-            gi[1] = gg.y;
-            gi[2] = gg.z;
-            gi[3] = gg.w;
+            k.gi[0] = gg.x;
+            k.gi[1] = gg.y;
+            k.gi[2] = gg.z;
+            k.gi[3] = gg.w;
         }
+    };
+    Chunk cur;
+    load_chunk(cur, r_begin + (int64_t)lane * kColIpt);
+    for (int64_t base = r_begin; base < r_end; base += kColChunk) {
+        Chunk nxt;
+        const bool more = base + kColChunk < r_end;
+        if (more) load_chunk(nxt, base + kColChunk + (int64_t)lane * kColIpt);
+        double(&xv)[CB][kColIpt] = cur.xv;
+        double(&bv)[kColIpt] = cur.bv;
+        double(&av)[kColIpt] = cur.av;
+        double(&uv)[kColIpt] = cur.uv;
+        double(&qv)[kColIpt] = cur.qv;
+        uint32_t(&m)[kColIpt] = cur.m;
+        int32_t(&gi)[kColIpt] = cur.gi;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
 #pragma unroll
@@ -332,6 +347,7 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
                 cb[c] = tf ? tb : fma(ta, cb[c], tb);
             }
         }
+        if (more) cur = nxt;
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
