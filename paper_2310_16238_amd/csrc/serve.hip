@@ -305,39 +305,54 @@ __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *
         xc[c] = F.x + (int64_t)(live[c] ? j0 + c : j0) * F.ld;
         g[c] = d1[c] = d2[c] = 0.0;
     }
-    SegVal<CB> carry = seg_identity<CB>();
-    for (int64_t base = r_begin; base < r_end; base += kColChunk) {
-        const int64_t r0 = base + (int64_t)lane * kColIpt;
-        const bool in = r0 < r_end;
+    // one chunk's loads; the next chunk's loads are issued before this chunk is processed
+    struct Chunk {
         double xv[CB][kColIpt], wv[kColIpt], bv[kColIpt], qv[kColIpt];
         uint32_t m[kColIpt];
         int32_t gi[kColIpt];
-        if (in) {
+    };
+    auto load_chunk = [&](Chunk &k, int64_t r0) {
+        if (r0 < r_end) {
 #pragma unroll
-            for (int c = 0; c < CB; ++c) load4(xc[c] + r0, xv[c]);
-            load4(F.w + r0, wv);
-            load4(F.b + r0, bv);
-            load4(F.zq + r0, qv);
+            for (int c = 0; c < CB; ++c) load4(xc[c] + r0, k.xv[c]);
+            load4(F.w + r0, k.wv);
+            load4(F.b + r0, k.bv);
+            load4(F.zq + r0, k.qv);
             const uint4 mm = *reinterpret_cast<const uint4 *>(F.meta + r0);
             const int4 gg = *reinterpret_cast<const int4 *>(F.gidx + r0);
-            m[0] = mm.x;
-            m[1] = mm.y;
-            m[2] = mm.z;
-            m[3] = mm.w;
-            gi[0] = gg.x;
-            gi[1] = gg.y;
-            gi[2] = gg.z;
-            gi[3] = gg.w;
+            k.m[0] = mm.x;
+            k.m[1] = mm.y;
+            k.m[2] = mm.z;
+            k.m[3] = mm.w;
+            k.gi[0] = gg.x;
+            k.gi[1] = gg.y;
+            k.gi[2] = gg.z;
+            k.gi[3] = gg.w;
         } else {
 #pragma unroll
             for (int i = 0; i < kColIpt; ++i) {
 #pragma unroll
-                for (int c = 0; c < CB; ++c) xv[c][i] = 0.0;
-                wv[i] = bv[i] = qv[i] = 0.0;
-                m[i] = 0u;
-                gi[i] = 0;
+                for (int c = 0; c < CB; ++c) k.xv[c][i] = 0.0;
+                k.wv[i] = k.bv[i] = k.qv[i] = 0.0;
+                k.m[i] = 0u;
+                k.gi[i] = 0;
             }
         }
+    };
+    SegVal<CB> carry = seg_identity<CB>();
+    Chunk cur;
+    load_chunk(cur, r_begin + (int64_t)lane * kColIpt);
+    for (int64_t base = r_begin; base < r_end; base += kColChunk) {
+        const int64_t r0 = base + (int64_t)lane * kColIpt;
+        Chunk nxt;
+        const bool more = base + kColChunk < r_end;
+        if (more) load_chunk(nxt, r0 + kColChunk);
+        double(&xv)[CB][kColIpt] = cur.xv;
+        double(&wv)[kColIpt] = cur.wv;
+        double(&bv)[kColIpt] = cur.bv;
+        double(&qv)[kColIpt] = cur.qv;
+        uint32_t(&m)[kColIpt] = cur.m;
+        int32_t(&gi)[kColIpt] = cur.gi;
         SegVal<CB> e[kColIpt];
         SegVal<CB> tot = seg_identity<CB>();
 #pragma unroll
@@ -369,6 +384,7 @@ __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *
             }
         }
         carry = seg_combine(carry, lane63_seg(inc));
+        if (more) cur = nxt;
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
