@@ -590,18 +590,27 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_lds_kernel(const 
 
 constexpr float kFp8Max = 224.0f;   // below the e4m3 maximum of either encoding
 constexpr int kF8KC = 64, kF8Stride = 80;   // bytes per LDS row (64 + 16 pad)
+constexpr int kF8MaxRows = 800;                // p <= 800 (rows = p rounded up to 32)
 typedef int i32x8v __attribute__((ext_vector_type(8)));
 
-__global__ __launch_bounds__(256) void to_fp8_kernel(const double *x, int64_t ld, const float *xscale, uint8_t *x8)
+// The e4m3 copy is stored in blocks of kF8KC rows of X: block k holds, for each
+// of the prow (= p rounded up to 32) columns in turn, its kF8KC bytes (zero for
+// the padding columns), so the contraction reads each chunk as one contiguous
+// stretch of prow * kF8KC bytes.
+__global__ __launch_bounds__(256) void to_fp8_kernel(const double *x, int64_t ld, int p, int prow,
+                                                     const float *xscale, uint8_t *x8)
 {
     const int j = blockIdx.y;
     const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     if (r >= ld) return;
-    const double inv = 1.0 / (double)xscale[j];
-    const double *src = x + (int64_t)j * ld + r;
-    int v = __builtin_amdgcn_cvt_pk_fp8_f32((float)(src[0] * inv), (float)(src[1] * inv), 0, false);
-    v = __builtin_amdgcn_cvt_pk_fp8_f32((float)(src[2] * inv), (float)(src[3] * inv), v, true);
-    *reinterpret_cast<int *>(x8 + (int64_t)j * ld + r) = v;
+    int v = 0;
+    if (j < p) {
+        const double inv = 1.0 / (double)xscale[j];
+        const double *src = x + (int64_t)j * ld + r;
+        v = __builtin_amdgcn_cvt_pk_fp8_f32((float)(src[0] * inv), (float)(src[1] * inv), 0, false);
+        v = __builtin_amdgcn_cvt_pk_fp8_f32((float)(src[2] * inv), (float)(src[3] * inv), v, true);
+    }
+    *reinterpret_cast<int *>(x8 + ((r / kF8KC) * prow + j) * kF8KC + r % kF8KC) = v;
 }
 
 // wsc[0] = S = 2^ceil(log2(sqrt(max b))) (1 if b is all zero), in two launches
@@ -630,7 +639,9 @@ __global__ __launch_bounds__(256) void wscale_kernel(const double *blockmax, int
     }
 }
 
-__global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_fp8_lds_kernel(const uint8_t *u, int64_t ldu, int p,
+// Two waves per SIMD (registers capped at 256, accumulators included): the
+// products of one chunk overlap the other wave's staging.
+__global__ __launch_bounds__(64 * kSyrkBfWaves, 2) void syrk_fp8_lds_kernel(const uint8_t *u, int p,
                                                                         const double *c, const double *wsc,
                                                                         int64_t K, int64_t kchunk, float *part)
 {
@@ -655,29 +666,54 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_fp8_lds_kernel(const u
         for (int i = 0; i < 16; ++i) acc[q][i] = 0.0f;
     }
     const int rsub = lane & 31, kofs = 32 * (lane >> 5);
-    for (int64_t kc = k0; kc < k1; kc += kF8KC) {
-        if (threadIdx.x < kF8KC) cw[threadIdx.x] = (float)(sqrt(c[kc + threadIdx.x]) * invS);
-        __syncthreads();
-        // rows x 64 bytes: 16-byte pieces, 4 per row; decode, weight, re-encode
-        for (int e = threadIdx.x; e < rows * 4; e += 64 * kSyrkBfWaves) {
-            const int r = e >> 2, piece = e & 3;
+    // the chunk is one contiguous block of rows x 64 bytes (padding rows are zero), read
+    // as 16-byte pieces e = tid + 256 m into registers one chunk ahead
+    constexpr int kPieces = (kF8MaxRows * 4 + 64 * kSyrkBfWaves - 1) / (64 * kSyrkBfWaves);
+    const int npieces = rows * 4;
+    u32x4v reg[kPieces];
+    double creg = 0.0;
+    auto load_chunk = [&](int64_t kc) {
+        const u32x4v *blk = reinterpret_cast<const u32x4v *>(u + (kc / kF8KC) * (int64_t)rows * kF8KC);
+#pragma unroll
+        for (int m = 0; m < kPieces; ++m) {
+            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
             u32x4v v = {0u, 0u, 0u, 0u};
-            if (r < p) {
-                const u32x4v raw = *reinterpret_cast<const u32x4v *>(u + (int64_t)r * ldu + kc + 16 * piece);
+            if (e < npieces) v = blk[e];
+            reg[m] = v;
+        }
+        if (threadIdx.x < kF8KC) creg = c[kc + threadIdx.x];
+    };
+    if (k0 < k1) load_chunk(k0);
+    for (int64_t kc = k0; kc < k1; kc += kF8KC) {
+        if (threadIdx.x < kF8KC) cw[threadIdx.x] = (float)(sqrt(creg) * invS);
+        __syncthreads();
+        // decode, weight, re-encode into LDS; every piece of this thread covers the same
+        // 16 rows of the chunk (piece = tid mod 4), so it needs 16 weights
+        const int piece = threadIdx.x & 3;
+        float wk[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) wk[i] = cw[16 * piece + i];
+#pragma unroll
+        for (int m = 0; m < kPieces; ++m) {
+            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            if (e < npieces) {
+                const u32x4v raw = reg[m];
+                u32x4v v;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
                     const int word = (int)raw[d];
-                    const float *wk = cw + 16 * piece + 4 * d;
-                    int o = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_cvt_f32_fp8(word, 0) * wk[0],
-                                                            __builtin_amdgcn_cvt_f32_fp8(word, 1) * wk[1], 0, false);
-                    o = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_cvt_f32_fp8(word, 2) * wk[2],
-                                                        __builtin_amdgcn_cvt_f32_fp8(word, 3) * wk[3], o, true);
+                    int o = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_cvt_f32_fp8(word, 0) * wk[4 * d],
+                                                            __builtin_amdgcn_cvt_f32_fp8(word, 1) * wk[4 * d + 1], 0,
+                                                            false);
+                    o = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_cvt_f32_fp8(word, 2) * wk[4 * d + 2],
+                                                        __builtin_amdgcn_cvt_f32_fp8(word, 3) * wk[4 * d + 3], o, true);
                     v[d] = (unsigned)o;
                 }
+                *reinterpret_cast<u32x4v *>(sh8 + (e >> 2) * kF8Stride + 16 * piece) = v;
             }
-            *reinterpret_cast<u32x4v *>(sh8 + r * kF8Stride + 16 * piece) = v;
         }
         __syncthreads();
+        if (kc + kF8KC < k1) load_chunk(kc + kF8KC);   // in flight during the products below
 #pragma unroll
         for (int q = 0; q < kTilesPerWave; ++q) {
             if (q < nq) {
@@ -853,11 +889,17 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
+size_t fp8_copy_bytes(int64_t ld, int p)
+{
+    return (size_t)ld * (size_t)((p + kMT - 1) / kMT * kMT);
+}
+
 int make_fp8_copy(const double *x, int64_t ld, int p, uint8_t *x8, float *xscale, float *zscale, hipStream_t stream)
 {
-    if (ld % 4 != 0) return -1;
+    if (ld % kF8KC != 0) return -1;
+    const int prow = (p + kMT - 1) / kMT * kMT;
     colscale_kernel<<<p, 256, 0, stream>>>(x, ld, kFp8Max, xscale, zscale);
-    to_fp8_kernel<<<dim3((unsigned)((ld / 4 + 255) / 256), p), 256, 0, stream>>>(x, ld, xscale, x8);
+    to_fp8_kernel<<<dim3((unsigned)((ld / 4 + 255) / 256), prow), 256, 0, stream>>>(x, ld, p, prow, xscale, x8);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -868,15 +910,24 @@ int syrk_fp8(const uint8_t *u, int64_t ldu, int p, const float *scale, const dou
     const int npairs = nt * (nt + 1) / 2;
     const int ngroups = (npairs + kPairsPerGroup - 1) / kPairsPerGroup;
     const int64_t K64 = (K + kF8KC - 1) / kF8KC * kF8KC;
-    if (K64 > ldu || ldu % 16 != 0 || (size_t)nt * kMT * kF8Stride > 65536) return -1;   // p <= 800
+    if (K64 > ldu || ldu % kF8KC != 0 || nt * kMT > kF8MaxRows) return -1;
     bmax_kernel<<<256, 256, 0, stream>>>(c, K, blockmax);
     wscale_kernel<<<1, 256, 0, stream>>>(blockmax, 256, wsc);
+    // two workgroups per compute unit are resident: size the grid to whole rounds of them
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    const int fit = (4 * cus) / ngroups;
+    if (fit >= 1 && fit < splits) splits = fit;
     int64_t kchunk = (K64 + splits - 1) / splits;
     kchunk = (kchunk + kF8KC - 1) / kF8KC * kF8KC;
     const size_t lds = (size_t)nt * kMT * kF8Stride;
     float *fpart = reinterpret_cast<float *>(part);
-    syrk_fp8_lds_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, wsc, K64, kchunk,
-                                                                                   fpart);
+    syrk_fp8_lds_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, p, c, wsc, K64, kchunk, fpart);
     syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C, wsc);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }

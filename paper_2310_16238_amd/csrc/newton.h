@@ -77,7 +77,11 @@ int make_bf16_copy(const double *x, int64_t ld, int p, void *xlp, float *xscale,
 // C (+)= sign * scale_i scale_j sum_k c_k u_ik u_jk with BF16 u on the matrix cores (FP32 accumulate).
 int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const double *c, int64_t K, int splits,
               double *part, double sign, int accumulate, double *C, hipStream_t stream);
-// e4m3 copy of X with power-of-two column scales (|x / s| <= 224); zscale gets the BF16 scales.
+// Bytes of the blocked e4m3 copy of an ld x p matrix (make_fp8_copy, syrk_fp8).
+size_t fp8_copy_bytes(int64_t ld, int p);
+// e4m3 copy of X with power-of-two column scales (|x / s| <= 224), in blocks of 64 rows
+// (each block: the 64 bytes of every column, p rounded up to 32, in turn; ld a multiple of
+// 64); zscale gets the BF16 scales.
 int make_fp8_copy(const double *x, int64_t ld, int p, uint8_t *x8, float *xscale, float *zscale, hipStream_t stream);
 // C (+)= sign * scale_i scale_j sum_k c_k u_ik u_jk with e4m3 u and sqrt(c) on both operands
 // (blockmax: 256 doubles of scratch; wsc: 1 double receiving the weight scale).

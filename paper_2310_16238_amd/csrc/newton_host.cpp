@@ -115,7 +115,7 @@ int newton_setup(cox_handle *h)
     }
     if (h->opt.x_precision == COX_FP8_E4M3) {
         // e4m3 copy of X with power-of-two column scales (|x / s| <= 224)
-        if ((e = dalloc(&s.xlp, (size_t)p * ld)) != hipSuccess ||
+        if ((e = dalloc(&s.xlp, fp8_copy_bytes(ld, p))) != hipSuccess ||
             (e = dalloc(&s.xscale, sizeof(float) * p)) != hipSuccess ||
             (e = dalloc(&s.wscratch, sizeof(double) * 264)) != hipSuccess) {
             newton_free(h);
