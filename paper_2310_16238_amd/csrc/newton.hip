@@ -423,16 +423,24 @@ __global__ __launch_bounds__(kRowBlock) void colreduce_kernel(const double *part
 
 constexpr int kScanThreads = 256, kScanWaves = kScanThreads / kWave;
 
-template <class Op, class Ld>
+template <class Op, class Ld, int PER>
 __global__ __launch_bounds__(kScanThreads) void tscan_agg_kernel(Ld ldr, int64_t tile, typename Op::E *agg)
 {
     using E = typename Op::E;
     __shared__ E wtot[kScanWaves];
     const int t = blockIdx.x;
-    const int64_t per = tile / kScanThreads;
+    const int64_t per = PER > 0 ? PER : tile / kScanThreads;
     const int64_t k0 = (int64_t)t * tile + (int64_t)threadIdx.x * per;
     E f = Op::id();
-    for (int64_t i = 0; i < per; ++i) f = Op::combine(f, ldr(k0 + i));
+    if constexpr (PER > 0) {
+        E v[PER];   // all of the thread's rows in flight at once
+#pragma unroll
+        for (int i = 0; i < PER; ++i) v[i] = ldr(k0 + i);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) f = Op::combine(f, v[i]);
+    } else {
+        for (int64_t i = 0; i < per; ++i) f = Op::combine(f, ldr(k0 + i));
+    }
     E total;
     (void)block_exclusive_e<Op, kScanWaves>(f, wtot, total);
     if (threadIdx.x == 0) agg[t] = total;
@@ -460,23 +468,40 @@ __global__ __launch_bounds__(1024) void tscan_carry_kernel(const typename Op::E 
     }
 }
 
-template <class Op, class Ld, class Wr>
+template <class Op, class Ld, class Wr, int PER>
 __global__ __launch_bounds__(kScanThreads) void tscan_apply_kernel(Ld ldr, Wr wr, int64_t tile,
                                                                    const typename Op::E *carry)
 {
     using E = typename Op::E;
     __shared__ E wtot[kScanWaves];
     const int t = blockIdx.x;
-    const int64_t per = tile / kScanThreads;
+    const int64_t per = PER > 0 ? PER : tile / kScanThreads;
     const int64_t k0 = (int64_t)t * tile + (int64_t)threadIdx.x * per;
-    E f = Op::id();
-    for (int64_t i = 0; i < per; ++i) f = Op::combine(f, ldr(k0 + i));
-    E total;
-    const E exc = block_exclusive_e<Op, kScanWaves>(f, wtot, total);
-    E run = Op::combine(carry[t], exc);
-    for (int64_t i = 0; i < per; ++i) {
-        run = Op::combine(run, ldr(k0 + i));
-        wr(k0 + i, run);
+    if constexpr (PER > 0) {
+        E v[PER];   // the thread's rows, loaded once, all in flight at once
+#pragma unroll
+        for (int i = 0; i < PER; ++i) v[i] = ldr(k0 + i);
+        E f = Op::id();
+#pragma unroll
+        for (int i = 0; i < PER; ++i) f = Op::combine(f, v[i]);
+        E total;
+        const E exc = block_exclusive_e<Op, kScanWaves>(f, wtot, total);
+        E run = Op::combine(carry[t], exc);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            run = Op::combine(run, v[i]);
+            wr(k0 + i, run);
+        }
+    } else {
+        E f = Op::id();
+        for (int64_t i = 0; i < per; ++i) f = Op::combine(f, ldr(k0 + i));
+        E total;
+        const E exc = block_exclusive_e<Op, kScanWaves>(f, wtot, total);
+        E run = Op::combine(carry[t], exc);
+        for (int64_t i = 0; i < per; ++i) {
+            run = Op::combine(run, ldr(k0 + i));
+            wr(k0 + i, run);
+        }
     }
 }
 
@@ -530,9 +555,21 @@ int tile_scan(Ld ldr, Wr wr, int64_t n, int64_t tile, void *scratch, size_t scra
     if (sizeof(E) * 2 * (size_t)ntiles > scratch_bytes) return -5;
     E *agg = static_cast<E *>(scratch);
     E *carry = agg + ntiles;
-    tscan_agg_kernel<Op, Ld><<<ntiles, kScanThreads, 0, stream>>>(ldr, tile, agg);
-    tscan_carry_kernel<Op><<<1, 1024, 0, stream>>>(agg, ntiles, carry);
-    tscan_apply_kernel<Op, Ld, Wr><<<ntiles, kScanThreads, 0, stream>>>(ldr, wr, tile, carry);
+    // rows per thread as a compile-time count for the tile lengths of the layouts
+    // (4096, 2048, 1024 and 512 rows), so that a thread's loads are all issued together
+    const int64_t per = tile / kScanThreads;
+#define COXMI_TSCAN(P)                                                                                     \
+    do {                                                                                                   \
+        tscan_agg_kernel<Op, Ld, P><<<ntiles, kScanThreads, 0, stream>>>(ldr, tile, agg);                 \
+        tscan_carry_kernel<Op><<<1, 1024, 0, stream>>>(agg, ntiles, carry);                              \
+        tscan_apply_kernel<Op, Ld, Wr, P><<<ntiles, kScanThreads, 0, stream>>>(ldr, wr, tile, carry);    \
+    } while (0)
+    if (per == 16) COXMI_TSCAN(16);
+    else if (per == 8) COXMI_TSCAN(8);
+    else if (per == 4) COXMI_TSCAN(4);
+    else if (per == 2) COXMI_TSCAN(2);
+    else COXMI_TSCAN(0);
+#undef COXMI_TSCAN
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
