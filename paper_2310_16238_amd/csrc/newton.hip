@@ -433,9 +433,12 @@ __global__ __launch_bounds__(kScanThreads) void tscan_agg_kernel(Ld ldr, int64_t
     const int64_t k0 = (int64_t)t * tile + (int64_t)threadIdx.x * per;
     E f = Op::id();
     if constexpr (PER > 0) {
-        E v[PER];   // all of the thread's rows in flight at once
+        E v[PER];   // all of the thread's rows in flight at once, in ascending address order
 #pragma unroll
-        for (int i = 0; i < PER; ++i) v[i] = ldr(k0 + i);
+        for (int q = 0; q < PER; ++q) {
+            const int i = Ld::kReverse ? PER - 1 - q : q;
+            v[i] = ldr(k0 + i);
+        }
 #pragma unroll
         for (int i = 0; i < PER; ++i) f = Op::combine(f, v[i]);
     } else {
@@ -478,9 +481,12 @@ __global__ __launch_bounds__(kScanThreads) void tscan_apply_kernel(Ld ldr, Wr wr
     const int64_t per = PER > 0 ? PER : tile / kScanThreads;
     const int64_t k0 = (int64_t)t * tile + (int64_t)threadIdx.x * per;
     if constexpr (PER > 0) {
-        E v[PER];   // the thread's rows, loaded once, all in flight at once
+        E v[PER];   // the thread's rows, loaded once, all in flight at once, in ascending address order
 #pragma unroll
-        for (int i = 0; i < PER; ++i) v[i] = ldr(k0 + i);
+        for (int q = 0; q < PER; ++q) {
+            const int i = Ld::kReverse ? PER - 1 - q : q;
+            v[i] = ldr(k0 + i);
+        }
         E f = Op::id();
 #pragma unroll
         for (int i = 0; i < PER; ++i) f = Op::combine(f, v[i]);
@@ -507,6 +513,7 @@ __global__ __launch_bounds__(kScanThreads) void tscan_apply_kernel(Ld ldr, Wr wr
 
 // running maximum of eta within each stratum (forward)
 struct MaxLoad {
+    static constexpr bool kReverse = false;   // scan position k is row k
     const double *eta;
     const uint32_t *meta;
     __device__ MaxE operator()(int64_t k) const { return MaxE{(meta[k] & kHeadBit) ? 1u : 0u, eta[k]}; }
@@ -518,6 +525,7 @@ struct MaxWrite {
 
 // S0' (forward): S0'_r = alpha_r S0'_{r-1} + u_r
 struct S0Load {
+    static constexpr bool kReverse = false;
     const double *alpha, *u;
     const uint32_t *meta;
     __device__ AffE operator()(int64_t k) const { return AffE{(meta[k] & kHeadBit) ? 1u : 0u, alpha[k], u[k]}; }
@@ -530,6 +538,7 @@ struct BWrite {
 // R (reverse, scan position k = row n-1-k): R_r = h'_r + alpha_{r+1} R_{r+1},
 // a segment starting at each stratum's last row
 struct RLoad {
+    static constexpr bool kReverse = true;    // scan position k is row n - 1 - k
     const double *alpha, *h;
     const uint32_t *meta;
     int64_t n;
