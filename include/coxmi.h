@@ -188,6 +188,44 @@ int cox_layout(const cox_handle *h, int64_t *perm, uint32_t *meta);
 int cox_canonical_order(int64_t n, const double *time, const uint8_t *event, const int32_t *stratum,
                         int64_t *perm, uint32_t *meta);
 
+/* ---------------------------------------------------------------- time intervals
+ * Secs. 2.2-2.3: a model with piecewise-constant time-varying covariates or
+ * step-function coefficients is a Cox model stratified on time intervals over an
+ * augmented data set.  Given cut points t_1 < ... < t_{K-1} (K = ncuts + 1
+ * intervals [t_{k-1}, t_k), t_0 = -inf, the last interval closed at max Y):
+ *   rows     : (interval k, subject i) for every i with Y_i >= t_{k-1} (a subject
+ *              that left before t_{k-1} is in no risk set of interval k), interval
+ *              by interval, subjects in their original order within one;
+ *   time     : min(Y_i, t_k) (Y_i in the last interval);
+ *   event    : delta_i if Y_i lies in interval k, else 0;
+ *   stratum  : the pair (original stratum, k), numbered s * K + k with s the rank
+ *              of the original label among the distinct labels (one stratum: s = 0);
+ *   columns  : in the original order; a column j with tv_coef[j] = 1 becomes K
+ *              columns, the k-th equal to x_ij on interval k's rows and 0 elsewhere
+ *              (its coefficient beta_jk applies on interval k); other columns keep
+ *              x_ij, or x_by_interval[k][i][j] when given (time-varying covariates).
+ * d         : host data as for cox_init; cuts: host, ncuts strictly increasing
+ *             finite values (ncuts >= 0); tv_coef: host, p flags, or NULL (none);
+ *             x_by_interval: host, K blocks of n x p column-major (leading
+ *             dimension d->ldx), or NULL (x applies on every interval).
+ * out       : receives a library-owned result; release it with
+ *             cox_intervals_release.  Its `data` is ready for cox_init (which copies
+ *             it); the maps give the origin of every augmented row and column.
+ * Errors: COX_EINVAL (the checks of cox_init, bad cuts, more than 2^31 - 1
+ * augmented rows or strata), COX_ENOMEM. */
+typedef struct {
+    cox_data data;                 /* the augmented data set (library-owned host arrays) */
+    int intervals;                 /* K */
+    const int64_t *row_subject;    /* [data.n]: original row of each augmented row */
+    const int32_t *row_interval;   /* [data.n]: its interval, 0..K-1 */
+    const int32_t *col_source;     /* [data.p]: original column of each augmented column */
+    const int32_t *col_interval;   /* [data.p]: its interval for a step coefficient, -1 otherwise */
+} cox_intervals;
+
+int cox_split_intervals(const cox_data *d, int ncuts, const double *cuts, const uint8_t *tv_coef,
+                        const double *x_by_interval, cox_intervals **out);
+void cox_intervals_release(cox_intervals *s);
+
 /* Duration in milliseconds of the last persistent-kernel launch on h, from
  * HIP events recorded on the handle's stream immediately around the launch. */
 int cox_last_kernel_ms(const cox_handle *h, double *ms);

@@ -385,3 +385,94 @@ def fit_newton(X, time, event, stratum=None, *, beta0=None, tol=1e-14, max_iter=
             break
     return FitResult(beta=beta, converged=converged, iters=it, objective=ev.objective,
                      last_step=step_max, grad=ev.grad)
+
+
+# ============================================================== time intervals (Secs. 2.2-2.3)
+
+def split_intervals(X, time, event, stratum=None, cuts=(), tv_coef=None, X_by_interval=None,
+                    keep_all_rows: bool = False) -> dict:
+    """The augmented data set of Secs. 2.2-2.3, built from their definitions.
+
+    Intervals I_k = [t_{k-1}, t_k), k = 0..K-1 with K = len(cuts) + 1, t_{-1} = -inf and
+    the last interval unbounded above (it holds max Y).  For interval k and subject i:
+    Y_ki = min(Y_i, t_k), delta_ki = delta_i [Y_i in I_k], stratum (rank of s_i) * K + k,
+    covariates x_ki (X_by_interval[k][i] if given, else x_i), with every column j that has
+    a step-function coefficient (Sec. 2.3) replaced by K columns, the k-th equal to x_kij on
+    interval k's rows and zero elsewhere.
+
+    The paper's augmented matrix has all K N rows (interval-major).  A row with
+    Y_i < t_{k-1} carries no event and its time is below every event time of its stratum,
+    so it is in no risk set: it contributes nothing to Eq. time_cov_strat_l, and the
+    result drops it unless keep_all_rows.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    n, p = X.shape
+    Y = np.asarray(time, dtype=np.float64)
+    d = np.asarray(event).astype(np.uint8)
+    cuts = np.asarray(cuts, dtype=np.float64)
+    K = cuts.shape[0] + 1
+    bounds = np.concatenate([[-np.inf], cuts, [np.inf]])
+    if stratum is None:
+        srank = np.zeros(n, dtype=np.int64)
+    else:
+        _, srank = np.unique(np.asarray(stratum), return_inverse=True)
+    tv = np.zeros(p, dtype=bool) if tv_coef is None else np.asarray(tv_coef).astype(bool)
+
+    # columns of X^(aug): (source column, interval or -1)
+    cols = []
+    for j in range(p):
+        if tv[j]:
+            cols += [(j, k) for k in range(K)]
+        else:
+            cols.append((j, -1))
+
+    rows_x, rows_t, rows_d, rows_s, rows_i, rows_k = [], [], [], [], [], []
+    for k in range(K):
+        lo, hi = bounds[k], bounds[k + 1]
+        xk = X if X_by_interval is None else np.asarray(X_by_interval[k], dtype=np.float64)
+        for i in range(n):
+            if not keep_all_rows and not (Y[i] >= lo):
+                continue
+            in_k = (Y[i] >= lo) and (Y[i] < hi)
+            rows_t.append(min(Y[i], hi))
+            rows_d.append(d[i] if in_k else 0)
+            rows_s.append(srank[i] * K + k)
+            rows_i.append(i)
+            rows_k.append(k)
+            rows_x.append([xk[i, j] if (kc < 0 or kc == k) else 0.0 for j, kc in cols])
+    pa = len(cols)
+    return {
+        "X": np.asarray(rows_x, dtype=np.float64).reshape(len(rows_t), pa),
+        "time": np.asarray(rows_t, dtype=np.float64),
+        "event": np.asarray(rows_d, dtype=np.uint8),
+        "stratum": np.asarray(rows_s, dtype=np.int32),
+        "row_subject": np.asarray(rows_i, dtype=np.int64),
+        "row_interval": np.asarray(rows_k, dtype=np.int32),
+        "col_source": np.asarray([c[0] for c in cols], dtype=np.int32),
+        "col_interval": np.asarray([c[1] for c in cols], dtype=np.int32),
+        "intervals": K,
+    }
+
+
+def neg_loglik_time_varying_brute(X_by_interval, time, event, stratum, cuts, beta_of_interval) -> float:
+    """-log of Eq. time_cov_l with piecewise-constant covariates and coefficients, by definition.
+
+    For an event at Y_i in interval I_k, every r in R(Y_i) (same stratum, Y_r >= Y_i)
+    contributes exp(x_r(Y_i)' beta(Y_i)) with x_r(Y_i) = X_by_interval[k][r] and
+    beta(Y_i) = beta_of_interval[k]: the covariate path of Sec. 2.2 and the step
+    coefficients of Sec. 2.3 (Eq. time_coef_l) read at the event time.
+    """
+    Y = np.asarray(time, dtype=np.float64)
+    cuts = np.asarray(cuts, dtype=np.float64)
+    n = Y.shape[0]
+    st = np.zeros(n, dtype=np.int64) if stratum is None else np.asarray(stratum)
+    total = 0.0
+    for i in range(n):
+        if not event[i]:
+            continue
+        k = int(np.searchsorted(cuts, Y[i], side="right"))   # number of cuts <= Y_i
+        xk = np.asarray(X_by_interval[k], dtype=np.float64)
+        b = np.asarray(beta_of_interval[k], dtype=np.float64)
+        R = (st == st[i]) & (Y >= Y[i])
+        total -= xk[i] @ b - np.log(np.sum(np.exp(xk[R] @ b)))
+    return float(total)

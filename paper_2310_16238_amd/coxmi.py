@@ -46,6 +46,12 @@ class cox_data(ctypes.Structure):
                 ("stratum", ctypes.POINTER(ctypes.c_int32))]
 
 
+class cox_intervals(ctypes.Structure):
+    _fields_ = [("data", cox_data), ("intervals", ctypes.c_int),
+                ("row_subject", ctypes.POINTER(ctypes.c_int64)), ("row_interval", ctypes.POINTER(ctypes.c_int32)),
+                ("col_source", ctypes.POINTER(ctypes.c_int32)), ("col_interval", ctypes.POINTER(ctypes.c_int32))]
+
+
 class cox_options(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("penalize", ctypes.POINTER(ctypes.c_uint8)),
                 ("mode", ctypes.c_int), ("x_precision", ctypes.c_int), ("ties", ctypes.c_int),
@@ -110,6 +116,10 @@ SIGNATURES = [
     ("cox_evaluate_full", ctypes.c_int, [_VP, _DP, _DP, _DP, _DP, _DP]),
     ("cox_coordinate", ctypes.c_int, [_VP, _DP, ctypes.c_int64, _DP]),
     ("cox_layout", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32)]),
+    ("cox_split_intervals", ctypes.c_int, [ctypes.POINTER(cox_data), ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.POINTER(cox_intervals))]),
+    ("cox_intervals_release", None, [ctypes.POINTER(cox_intervals)]),
     ("cox_canonical_order", ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32)]),
@@ -265,6 +275,53 @@ def cox_canonical_order(time, event, stratum=None):
     if rc != COX_OK:
         raise CoxError(rc, "cox_canonical_order")
     return perm, meta
+
+
+def split_intervals(X, time, event, stratum=None, cuts=(), tv_coef=None, X_by_interval=None):
+    """Secs. 2.2-2.3 augmentation (cox_split_intervals): returns a dict with the augmented
+    X (n_aug, p_aug), time, event, stratum, and the maps row_subject, row_interval,
+    col_source, col_interval (numpy copies; the library's result is released)."""
+    X = np.asfortranarray(X, dtype=np.float64)
+    n, p = X.shape
+    time = np.ascontiguousarray(time, dtype=np.float64)
+    event = np.ascontiguousarray(event, dtype=np.uint8)
+    d = cox_data(n=n, p=p, x=_dptr(X), ldx=n, time=_dptr(time),
+                 event=event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    keep = [X, time, event]
+    if stratum is not None:
+        st = np.ascontiguousarray(stratum, dtype=np.int32)
+        keep.append(st)
+        d.stratum = st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    cuts = np.ascontiguousarray(cuts, dtype=np.float64)
+    tv = None if tv_coef is None else np.ascontiguousarray(tv_coef, dtype=np.uint8)
+    xk = None
+    if X_by_interval is not None:
+        xk = np.ascontiguousarray(np.stack([np.asfortranarray(b, dtype=np.float64).T for b in X_by_interval]))
+        if xk.shape != (len(cuts) + 1, p, n):
+            raise ValueError("X_by_interval needs one n x p block per interval")
+    out = ctypes.POINTER(cox_intervals)()
+    rc = lib().cox_split_intervals(ctypes.byref(d), len(cuts), _dptr(cuts) if len(cuts) else None,
+                                   None if tv is None else tv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                   None if xk is None else _dptr(xk), ctypes.byref(out))
+    if rc != COX_OK:
+        raise CoxError(rc, "cox_split_intervals")
+    try:
+        r = out.contents
+        na, pa = r.data.n, r.data.p
+        res = {
+            "X": np.ctypeslib.as_array(r.data.x, shape=(pa * na,)).reshape(pa, na).T.copy(order="F"),
+            "time": np.ctypeslib.as_array(r.data.time, shape=(na,)).copy(),
+            "event": np.ctypeslib.as_array(r.data.event, shape=(na,)).copy(),
+            "stratum": np.ctypeslib.as_array(r.data.stratum, shape=(na,)).copy(),
+            "row_subject": np.ctypeslib.as_array(r.row_subject, shape=(na,)).copy(),
+            "row_interval": np.ctypeslib.as_array(r.row_interval, shape=(na,)).copy(),
+            "col_source": np.ctypeslib.as_array(r.col_source, shape=(pa,)).copy(),
+            "col_interval": np.ctypeslib.as_array(r.col_interval, shape=(pa,)).copy(),
+            "intervals": int(r.intervals),
+        }
+    finally:
+        lib().cox_intervals_release(out)
+    return res
 
 
 def cox_shape(h):
