@@ -389,6 +389,15 @@ def fit_newton(X, time, event, stratum=None, *, beta0=None, tol=1e-14, max_iter=
 
 # ============================================================== time intervals (Secs. 2.2-2.3)
 
+def augmented_columns(tv_coef, K: int):
+    """Columns of X^(aug) (Sec. 2.3): (source column, interval) pairs, interval -1 for a
+    column with a time-fixed coefficient; a step-coefficient column j gives (j, 0..K-1)."""
+    cols = []
+    for j, t in enumerate(np.asarray(tv_coef).astype(bool)):
+        cols += [(j, k) for k in range(K)] if t else [(j, -1)]
+    return cols
+
+
 def split_intervals(X, time, event, stratum=None, cuts=(), tv_coef=None, X_by_interval=None,
                     keep_all_rows: bool = False) -> dict:
     """The augmented data set of Secs. 2.2-2.3, built from their definitions.
@@ -398,12 +407,13 @@ def split_intervals(X, time, event, stratum=None, cuts=(), tv_coef=None, X_by_in
     Y_ki = min(Y_i, t_k), delta_ki = delta_i [Y_i in I_k], stratum (rank of s_i) * K + k,
     covariates x_ki (X_by_interval[k][i] if given, else x_i), with every column j that has
     a step-function coefficient (Sec. 2.3) replaced by K columns, the k-th equal to x_kij on
-    interval k's rows and zero elsewhere.
+    interval k's rows and zero elsewhere.  Rows are interval-major, subjects in their
+    original order within an interval.
 
-    The paper's augmented matrix has all K N rows (interval-major).  A row with
-    Y_i < t_{k-1} carries no event and its time is below every event time of its stratum,
-    so it is in no risk set: it contributes nothing to Eq. time_cov_strat_l, and the
-    result drops it unless keep_all_rows.
+    The paper's augmented matrix has all K N rows.  A row with Y_i < t_{k-1} carries no
+    event and its time is below every event time of its stratum, so it is in no risk set:
+    it contributes nothing to Eq. time_cov_strat_l, and the result drops it unless
+    keep_all_rows.
     """
     X = np.asarray(X, dtype=np.float64)
     n, p = X.shape
@@ -416,38 +426,28 @@ def split_intervals(X, time, event, stratum=None, cuts=(), tv_coef=None, X_by_in
         srank = np.zeros(n, dtype=np.int64)
     else:
         _, srank = np.unique(np.asarray(stratum), return_inverse=True)
-    tv = np.zeros(p, dtype=bool) if tv_coef is None else np.asarray(tv_coef).astype(bool)
+    cols = augmented_columns(np.zeros(p) if tv_coef is None else tv_coef, K)
 
-    # columns of X^(aug): (source column, interval or -1)
-    cols = []
-    for j in range(p):
-        if tv[j]:
-            cols += [(j, k) for k in range(K)]
-        else:
-            cols.append((j, -1))
-
-    rows_x, rows_t, rows_d, rows_s, rows_i, rows_k = [], [], [], [], [], []
+    parts = []
     for k in range(K):
         lo, hi = bounds[k], bounds[k + 1]
         xk = X if X_by_interval is None else np.asarray(X_by_interval[k], dtype=np.float64)
-        for i in range(n):
-            if not keep_all_rows and not (Y[i] >= lo):
-                continue
-            in_k = (Y[i] >= lo) and (Y[i] < hi)
-            rows_t.append(min(Y[i], hi))
-            rows_d.append(d[i] if in_k else 0)
-            rows_s.append(srank[i] * K + k)
-            rows_i.append(i)
-            rows_k.append(k)
-            rows_x.append([xk[i, j] if (kc < 0 or kc == k) else 0.0 for j, kc in cols])
-    pa = len(cols)
+        rows = np.arange(n) if keep_all_rows else np.flatnonzero(Y >= lo)
+        in_k = (Y[rows] >= lo) & (Y[rows] < hi)
+        Xa = np.zeros((rows.shape[0], len(cols)))
+        for c, (j, kc) in enumerate(cols):
+            if kc < 0 or kc == k:
+                Xa[:, c] = xk[rows, j]
+        parts.append(dict(X=Xa, time=np.minimum(Y[rows], hi), event=np.where(in_k, d[rows], 0),
+                          stratum=srank[rows] * K + k, row_subject=rows, row_interval=np.full(rows.shape[0], k)))
+    cat = {key: np.concatenate([q[key] for q in parts]) for key in parts[0]}
     return {
-        "X": np.asarray(rows_x, dtype=np.float64).reshape(len(rows_t), pa),
-        "time": np.asarray(rows_t, dtype=np.float64),
-        "event": np.asarray(rows_d, dtype=np.uint8),
-        "stratum": np.asarray(rows_s, dtype=np.int32),
-        "row_subject": np.asarray(rows_i, dtype=np.int64),
-        "row_interval": np.asarray(rows_k, dtype=np.int32),
+        "X": np.asfortranarray(cat["X"]),
+        "time": cat["time"].astype(np.float64),
+        "event": cat["event"].astype(np.uint8),
+        "stratum": cat["stratum"].astype(np.int32),
+        "row_subject": cat["row_subject"].astype(np.int64),
+        "row_interval": cat["row_interval"].astype(np.int32),
         "col_source": np.asarray([c[0] for c in cols], dtype=np.int32),
         "col_interval": np.asarray([c[1] for c in cols], dtype=np.int32),
         "intervals": K,

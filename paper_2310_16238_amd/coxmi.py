@@ -279,8 +279,9 @@ def cox_canonical_order(time, event, stratum=None):
 
 def split_intervals(X, time, event, stratum=None, cuts=(), tv_coef=None, X_by_interval=None):
     """Secs. 2.2-2.3 augmentation (cox_split_intervals): returns a dict with the augmented
-    X (n_aug, p_aug), time, event, stratum, and the maps row_subject, row_interval,
-    col_source, col_interval (numpy copies; the library's result is released)."""
+    X (n_aug, p_aug, column-major), time, event, stratum, and the maps row_subject,
+    row_interval, col_source, col_interval.  The arrays are views of the library's result,
+    which is released once none of them is referenced."""
     X = np.asfortranarray(X, dtype=np.float64)
     n, p = X.shape
     time = np.ascontiguousarray(time, dtype=np.float64)
@@ -305,23 +306,39 @@ def split_intervals(X, time, event, stratum=None, cuts=(), tv_coef=None, X_by_in
                                    None if xk is None else _dptr(xk), ctypes.byref(out))
     if rc != COX_OK:
         raise CoxError(rc, "cox_split_intervals")
-    try:
-        r = out.contents
-        na, pa = r.data.n, r.data.p
-        res = {
-            "X": np.ctypeslib.as_array(r.data.x, shape=(pa * na,)).reshape(pa, na).T.copy(order="F"),
-            "time": np.ctypeslib.as_array(r.data.time, shape=(na,)).copy(),
-            "event": np.ctypeslib.as_array(r.data.event, shape=(na,)).copy(),
-            "stratum": np.ctypeslib.as_array(r.data.stratum, shape=(na,)).copy(),
-            "row_subject": np.ctypeslib.as_array(r.row_subject, shape=(na,)).copy(),
-            "row_interval": np.ctypeslib.as_array(r.row_interval, shape=(na,)).copy(),
-            "col_source": np.ctypeslib.as_array(r.col_source, shape=(pa,)).copy(),
-            "col_interval": np.ctypeslib.as_array(r.col_interval, shape=(pa,)).copy(),
-            "intervals": int(r.intervals),
-        }
-    finally:
-        lib().cox_intervals_release(out)
-    return res
+    owner = _IntervalsOwner(out)
+    r = out.contents
+    na, pa = r.data.n, r.data.p
+    return {
+        "X": owner.view(r.data.x, ctypes.c_double, pa * na).reshape(pa, na).T,
+        "time": owner.view(r.data.time, ctypes.c_double, na),
+        "event": owner.view(r.data.event, ctypes.c_uint8, na),
+        "stratum": owner.view(r.data.stratum, ctypes.c_int32, na),
+        "row_subject": owner.view(r.row_subject, ctypes.c_int64, na),
+        "row_interval": owner.view(r.row_interval, ctypes.c_int32, na),
+        "col_source": owner.view(r.col_source, ctypes.c_int32, pa),
+        "col_interval": owner.view(r.col_interval, ctypes.c_int32, pa),
+        "intervals": int(r.intervals),
+    }
+
+
+class _IntervalsOwner:
+    """Holds a cox_intervals result; the numpy views made by view() keep it alive, and it is
+    released (cox_intervals_release) when the last of them goes."""
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+        self.lib = lib()   # held, so that the release works during interpreter shutdown too
+
+    def view(self, p, ctype, count):
+        buf = (ctype * count).from_address(ctypes.cast(p, ctypes.c_void_p).value)
+        buf._owner = self
+        return np.frombuffer(buf, dtype=np.dtype(ctype))
+
+    def __del__(self):
+        if self.ptr:
+            self.lib.cox_intervals_release(self.ptr)
+        self.ptr = None
 
 
 def cox_shape(h):

@@ -5,7 +5,10 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <memory>
 #include <new>
+#include <system_error>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -15,7 +18,8 @@
 namespace {
 
 struct Store {
-    std::vector<double> x, time;
+    std::unique_ptr<double[]> x;    // not zero-filled: every entry is written by the column fill
+    std::vector<double> time;
     std::vector<uint8_t> event;
     std::vector<int32_t> stratum;
     std::vector<int64_t> row_subject;
@@ -109,22 +113,53 @@ extern "C" int cox_split_intervals(const cox_data *d, int ncuts, const double *c
                 r->row_interval[a] = k;
                 ++a;
             }
-        r->x.assign((size_t)(naug * paug), 0.0);
-        for (int64_t c = 0; c < paug; ++c) {
-            const int64_t j = r->col_source[c];
-            const int kc = r->col_interval[c];
-            double *col = r->x.data() + c * naug;
-            for (int64_t b = 0; b < naug; ++b) {
-                const int k = r->row_interval[b];
-                if (kc >= 0 && kc != k) continue;   // a step coefficient's column is zero off its interval
-                const int64_t i = r->row_subject[b];
-                const double *src = x_by_interval ? x_by_interval + (int64_t)k * d->ldx * p : d->x;
-                col[b] = src[j * d->ldx + i];
+        // interval k's rows are the contiguous block [first[k], first[k + 1])
+        std::vector<int64_t> first((size_t)K + 1, 0);
+        for (int64_t b = 0; b < naug; ++b) first[(size_t)r->row_interval[b] + 1]++;
+        for (int k = 0; k < K; ++k) first[(size_t)k + 1] += first[(size_t)k];
+        r->x.reset(new double[(size_t)(naug * paug)]);
+        // columns are independent: fill them on a few threads (each column a gather per interval)
+        auto fill = [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; ++c) {
+                const int64_t j = r->col_source[(size_t)c];
+                const int kc = r->col_interval[(size_t)c];
+                double *col = r->x.get() + c * naug;
+                for (int k = 0; k < K; ++k) {
+                    double *dst = col + first[(size_t)k];
+                    const int64_t len = first[(size_t)k + 1] - first[(size_t)k];
+                    if (kc >= 0 && kc != k) {   // a step coefficient's column is zero off its interval
+                        std::fill(dst, dst + len, 0.0);
+                        continue;
+                    }
+                    const double *src = (x_by_interval ? x_by_interval + (int64_t)k * d->ldx * p : d->x) + j * d->ldx;
+                    const int64_t *subj = r->row_subject.data() + first[(size_t)k];
+                    for (int64_t b = 0; b < len; ++b) dst[b] = src[subj[b]];
+                }
             }
+        };
+        const int64_t work = naug * paug;
+        int nth = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), 16);
+        nth = (int)std::min<int64_t>(nth, std::max<int64_t>(1, work >> 22));
+        nth = (int)std::min<int64_t>(nth, paug);
+        if (nth <= 1) {
+            fill(0, paug);
+        } else {
+            std::vector<std::thread> pool;
+            const int64_t per = (paug + nth - 1) / nth;
+            for (int t = 0; t < nth; ++t) {
+                const int64_t c0 = t * per, c1 = std::min<int64_t>(paug, c0 + per);
+                if (c0 >= c1) continue;
+                try {
+                    pool.emplace_back(fill, c0, c1);
+                } catch (const std::system_error &) {   // no thread to spare: fill this block here
+                    fill(c0, c1);
+                }
+            }
+            for (auto &th : pool) th.join();
         }
         pub.data.n = naug;
         pub.data.p = paug;
-        pub.data.x = r->x.data();
+        pub.data.x = r->x.get();
         pub.data.ldx = naug;
         pub.data.time = r->time.data();
         pub.data.event = r->event.data();

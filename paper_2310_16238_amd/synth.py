@@ -239,3 +239,36 @@ def config_heavy(n: int = 10_000_000, p: int = 500, K: int = 500_000, seed: int 
     N(0, 1) entries at seeded positions (seed 4)."""
     return make("t3", n, p, K, seed, beta_kind="sparse_count", beta_sd=1.0, beta_nonzero=0.1, gamma=0.0,
                 name=f"heavy-n{n}-p{p}-K{K}", progress=progress)
+
+
+def config_step_effect(n: int = 407_828, p: int = 1000, seed: int = 6, cut: float = 10.0,
+                       log_hr=(math.log(2.0), math.log(1.1)), density: float = 0.05,
+                       base_rate: float = 1.0 / 365.0, censor_rate: float = 1.0 / 500.0) -> CoxData:
+    """Sec. 3.3 shape: a treatment whose effect changes at `cut` days after initiation.
+
+    Column 0 is the treatment indicator (half the subjects, the 1:1 matched comparison);
+    columns 1..p-1 are binary baseline covariates with `density` ones and coefficients
+    N(0, 0.25) x Bernoulli(0.2).  The treatment's log hazard ratio is log_hr[0] before the
+    cut and log_hr[1] after it, so the event times come from a piecewise-exponential
+    hazard: with rate a before the cut and b after, T = E / a if E < a cut, else
+    cut + (E - a cut) / b, for E ~ Exp(1).  Censoring C ~ Exp(censor_rate); follow-up
+    in whole days (Y = ceil(min(T, C)), at least 1); one stratum.  beta_true holds the
+    baseline coefficients with the treatment entry 0 (its effect is log_hr).
+    """
+    rng = np.random.default_rng(seed)
+    X = np.empty((n, p), dtype=np.float64, order="F")
+    X[:, 0] = (rng.random(n) < 0.5).astype(np.float64)
+    for j in range(1, p):
+        X[:, j] = (rng.random(n) < density).astype(np.float64)
+    b = rng.normal(0.0, 0.5, size=p) * (rng.random(p) < 0.2)
+    b[0] = 0.0
+    eta = _linear_predictor(X, b)
+    a_rate = base_rate * np.exp(eta + X[:, 0] * log_hr[0])
+    b_rate = base_rate * np.exp(eta + X[:, 0] * log_hr[1])
+    E = rng.exponential(1.0, size=n)
+    T = np.where(E < a_rate * cut, E / a_rate, cut + (E - a_rate * cut) / b_rate)
+    C = rng.exponential(1.0, size=n) / censor_rate
+    event = (T <= C).astype(np.uint8)
+    Y = np.maximum(np.ceil(np.minimum(T, C)), 1.0)
+    return CoxData(X=X, time=Y, event=event, stratum=np.zeros(n, dtype=np.int32), beta_true=b,
+                   gamma=math.sqrt(2.0), name=f"step-effect-n{n}-p{p}-cut{cut:g}")

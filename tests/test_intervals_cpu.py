@@ -147,14 +147,16 @@ def test_oracle_split_pin(name):
 
 # Planted mistakes in a copy of the oracle's split: each must break a pin.
 MUTANTS = {
-    "event_everywhere": ("rows_d.append(d[i] if in_k else 0)", "rows_d.append(d[i])"),
-    "time_not_clipped": ("rows_t.append(min(Y[i], hi))", "rows_t.append(Y[i])"),
-    "strata_merged": ("rows_s.append(srank[i] * K + k)", "rows_s.append(srank[i])"),
-    "strata_collide": ("rows_s.append(srank[i] * K + k)", "rows_s.append(srank[i] + k)"),
-    "step_column_wrong_interval": ("(kc < 0 or kc == k)", "(kc < 0 or kc != k)"),
+    "event_everywhere": ("event=np.where(in_k, d[rows], 0)", "event=d[rows]"),
+    "time_not_clipped": ("time=np.minimum(Y[rows], hi)", "time=Y[rows]"),
+    "strata_merged": ("stratum=srank[rows] * K + k", "stratum=srank[rows]"),
+    "strata_collide": ("stratum=srank[rows] * K + k", "stratum=srank[rows] + k"),
+    "step_column_wrong_interval": ("if kc < 0 or kc == k:", "if kc < 0 or kc != k:"),
     "interval_covariates_ignored": ("xk = X if X_by_interval is None else", "xk = X if True else"),
-    "left_end_open": ("in_k = (Y[i] >= lo) and (Y[i] < hi)", "in_k = (Y[i] > lo) and (Y[i] < hi)"),
-    "right_end_closed": ("in_k = (Y[i] >= lo) and (Y[i] < hi)", "in_k = (Y[i] >= lo) and (Y[i] <= hi)"),
+    "left_end_open": ("in_k = (Y[rows] >= lo) & (Y[rows] < hi)", "in_k = (Y[rows] > lo) & (Y[rows] < hi)"),
+    "right_end_closed": ("in_k = (Y[rows] >= lo) & (Y[rows] < hi)", "in_k = (Y[rows] >= lo) & (Y[rows] <= hi)"),
+    "rows_not_dropped": ("rows = np.arange(n) if keep_all_rows else np.flatnonzero(Y >= lo)",
+                         "rows = np.arange(n)"),
 }
 
 
@@ -162,7 +164,7 @@ def _mutant(name):
     src = inspect.getsource(o.split_intervals)
     old, new = MUTANTS[name]
     assert src.count(old) == 1, name
-    ns = {"np": np}
+    ns = {"np": np, "augmented_columns": o.augmented_columns}
     exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
     return ns["split_intervals"]
 
