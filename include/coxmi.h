@@ -226,6 +226,59 @@ int cox_split_intervals(const cox_data *d, int ncuts, const double *cuts, const 
                         const double *x_by_interval, cox_intervals **out);
 void cox_intervals_release(cox_intervals *s);
 
+/* ---------------------------------------------------------------- resampling, CV, bootstrap
+ * Sec. 2.1 chooses the common l1 weight gamma by cross-validation; Sec. 3.2 adds
+ * bootstrap percentile intervals.  Both refit the model on resampled data sets:
+ * the data set in which original row i of the parent appears count[i] times
+ * (0 drops it; copies are tied subjects under the Breslow rule).
+ *
+ * cox_init_resample: a new handle for that data set, built on the device from
+ * the parent's resident X (a gather; X does not cross PCIe again).  Its rows
+ * are numbered as if the caller had repeated every row count[i] times in
+ * order (cox_layout's perm refers to that numbering), and its canonical order
+ * equals cox_canonical_order of those repeated data.  delta'X_j is summed on
+ * the device (fixed order), so with every count 1 the child equals the parent
+ * up to the rounding of that sum.
+ *   parent : a handle on the current device (not modified; must outlive no child)
+ *   count  : host, parent n entries; their sum in [1, 2^29 - 1]
+ *   o      : options of the child (penalize copied); NULL = the parent's options
+ *            and l1 weights
+ * Errors: COX_EINVAL (NULL pointer, no rows, another device), COX_EUNSUPPORTED
+ * (too many rows, options as for cox_init), COX_ENOMEM, COX_EDEVICE; message via
+ * cox_last_error(NULL). */
+int cox_init_resample(cox_handle **out, const cox_handle *parent, const uint32_t *count, const cox_options *o);
+
+/* Replace h's l1 weights: gamma_j = gamma for penalised columns (penalize: host,
+ * p flags, NULL = all), 0 otherwise.  COX_EINVAL for a negative or non-finite
+ * gamma; COX_EUNSUPPORTED for gamma != 0 on a COX_NEWTON_REFINE handle. */
+int cox_set_penalty(cox_handle *h, double gamma, const uint8_t *penalize);
+
+/* K-fold cross-validation of the l1 weight along a path (Sec. 2.1).  For fold k
+ * the model is fitted (CCD, warm-started along gammas in the given order, from
+ * 0 at gammas[0]) on the rows with fold[i] != k, giving beta_{-k}(gamma), and the
+ * cross-validated log partial likelihood
+ *     cvl[g] = sum_k [ l(beta_{-k}) - l_{-k}(beta_{-k}) ]
+ * is accumulated, l being the log of Eq. strat_l on all rows and l_{-k} on the
+ * training rows (the held-out rows' contribution given the rest).
+ *   h       : COX_CCD handle on the full data (used for l; its options give tol,
+ *             max_iter, precision and stream of the fold fits)
+ *   fold    : host, n entries in [0, nfolds); every fold non-empty and not all rows
+ *   gammas  : host, ngamma finite values >= 0 (a decreasing path warm-starts best)
+ *   penalize: host, p flags or NULL (all columns penalised)
+ *   cvl     : host, ngamma outputs; betas: host [nfolds][ngamma][p] or NULL;
+ *   status  : host [nfolds][ngamma] fit statuses or NULL
+ * Returns COX_OK, COX_NOT_CONVERGED (some fit hit max_iter; outputs filled), or
+ * an error (COX_EUNSUPPORTED for a COX_NEWTON_REFINE handle). */
+int cox_cross_validate(cox_handle *h, int nfolds, const int32_t *fold, int ngamma, const double *gammas,
+                       const uint8_t *penalize, double *cvl, double *betas, int *status);
+
+/* Bootstrap refits (Sec. 3.2): replicate b is the data set with row
+ * multiplicities counts[b * n .. b * n + n - 1] (host; e.g. a multinomial draw
+ * of n rows), fitted with h's options and l1 weights from beta0 (host p, NULL =
+ * 0); betas: host [nrep][p]; status: host [nrep] or NULL.  Percentile intervals
+ * are quantiles of the betas.  Returns COX_OK, COX_NOT_CONVERGED, or an error. */
+int cox_bootstrap(cox_handle *h, int nrep, const uint32_t *counts, const double *beta0, double *betas, int *status);
+
 /* Duration in milliseconds of the last persistent-kernel launch on h, from
  * HIP events recorded on the handle's stream immediately around the launch. */
 int cox_last_kernel_ms(const cox_handle *h, double *ms);

@@ -476,3 +476,75 @@ def neg_loglik_time_varying_brute(X_by_interval, time, event, stratum, cuts, bet
         R = (st == st[i]) & (Y >= Y[i])
         total -= xk[i] @ b - np.log(np.sum(np.exp(xk[R] @ b)))
     return float(total)
+
+
+# ============================================================== resampling, CV, bootstrap (Secs. 2.1, 3.2)
+
+def resample(X, time, event, stratum, count):
+    """The data set in which row i appears count[i] times (copies kept together, rows in
+    their original order): the training rows of a cross-validation fold (counts 0/1) or a
+    bootstrap sample (multinomial counts)."""
+    idx = np.repeat(np.arange(np.asarray(time).shape[0]), np.asarray(count, dtype=np.int64))
+    X = np.asarray(X, dtype=np.float64)
+    return (np.asfortranarray(X[idx]), np.asarray(time, dtype=np.float64)[idx], np.asarray(event)[idx],
+            None if stratum is None else np.asarray(stratum)[idx])
+
+
+def neg_loglik(X, time, event, stratum, beta) -> float:
+    """-log of Eq. strat_l (no penalty) through the scan form."""
+    lay = canonical_layout(time, event, stratum)
+    return full_eval(to_canonical(X, lay), lay, beta, want_info=False).objective
+
+
+def cross_validate(X, time, event, stratum, fold, gammas, penalize=None, tol=1e-13, max_sweeps=1000):
+    """Cross-validated log partial likelihood of the l1 weight (Sec. 2.1 chooses gamma by
+    cross-validation; the criterion is not stated -- this is the one of Verweij and van
+    Houwelingen): for fold k, beta_{-k}(gamma) is the CCD fit on the rows outside fold k,
+    and cvl(gamma) = sum_k [ l(beta_{-k}) - l_{-k}(beta_{-k}) ], l the log partial
+    likelihood on all rows and l_{-k} on the training rows.  Each fold's path starts at 0
+    and is warm-started from the previous gamma.
+    Returns (cvl[ngamma], betas[nfolds, ngamma, p], converged[nfolds, ngamma])."""
+    fold = np.asarray(fold)
+    K = int(fold.max()) + 1
+    G = len(gammas)
+    p = np.asarray(X).shape[1]
+    cvl = np.zeros(G)
+    betas = np.zeros((K, G, p))
+    conv = np.zeros((K, G), dtype=bool)
+    for k in range(K):
+        Xt, tt, et, st = resample(X, time, event, stratum, (fold != k).astype(np.int64))
+        lay = canonical_layout(tt, et, st)
+        Xc = to_canonical(Xt, lay)
+        beta = np.zeros(p)
+        for g, gam in enumerate(gammas):
+            r = fit_ccd(Xt, tt, et, st, gamma=gam, penalize=penalize, beta0=beta, tol=tol,
+                        max_sweeps=max_sweeps, layout=lay, Xc=Xc)
+            beta = r.beta
+            betas[k, g] = beta
+            conv[k, g] = r.converged
+            l_all = -neg_loglik(X, time, event, stratum, beta)
+            l_train = -full_eval(Xc, lay, beta, want_info=False).objective
+            cvl[g] += l_all - l_train
+    return cvl, betas, conv
+
+
+def bootstrap(X, time, event, stratum, counts, gamma=0.0, penalize=None, beta0=None, tol=1e-13, max_sweeps=1000):
+    """Refits on bootstrap samples (Sec. 3.2): replicate b uses the rows with multiplicities
+    counts[b].  Returns (betas[B, p], converged[B])."""
+    counts = np.asarray(counts)
+    p = np.asarray(X).shape[1]
+    betas = np.zeros((counts.shape[0], p))
+    conv = np.zeros(counts.shape[0], dtype=bool)
+    for b in range(counts.shape[0]):
+        Xb, tb, eb, sb = resample(X, time, event, stratum, counts[b])
+        r = fit_ccd(Xb, tb, eb, sb, gamma=gamma, penalize=penalize, beta0=beta0, tol=tol, max_sweeps=max_sweeps)
+        betas[b] = r.beta
+        conv[b] = r.converged
+    return betas, conv
+
+
+def percentile_interval(values, level=0.95):
+    """Percentile interval of bootstrap values (Sec. 3.2): the (1-level)/2 and (1+level)/2
+    empirical quantiles, numpy's default (linear) interpolation."""
+    v = np.asarray(values, dtype=np.float64)
+    return np.quantile(v, (1.0 - level) / 2.0, axis=0), np.quantile(v, (1.0 + level) / 2.0, axis=0)

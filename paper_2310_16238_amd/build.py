@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(CSRC, "_build")
 LIB = os.path.join(PKG, "libcoxmi.so")
 SOURCES = ["ccd_kernel.hip", "newton.hip", "contraction.hip", "serve.hip",
-           "canonical.cpp", "coxmi.cpp", "newton_host.cpp", "server.cpp", "intervals.cpp"]
+           "canonical.cpp", "coxmi.cpp", "newton_host.cpp", "server.cpp", "intervals.cpp", "resample.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -120,6 +120,13 @@ SIGNATURES = [
                                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.POINTER(cox_intervals))]),
     ("cox_intervals_release", None, [ctypes.POINTER(cox_intervals)]),
+    ("cox_init_resample", ctypes.c_int, [ctypes.POINTER(_VP), _VP, ctypes.POINTER(ctypes.c_uint32),
+                                         ctypes.POINTER(cox_options)]),
+    ("cox_set_penalty", ctypes.c_int, [_VP, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8)]),
+    ("cox_cross_validate", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _DP,
+                                          ctypes.POINTER(ctypes.c_uint8), _DP, _DP, ctypes.POINTER(ctypes.c_int)]),
+    ("cox_bootstrap", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), _DP, _DP,
+                                     ctypes.POINTER(ctypes.c_int)]),
     ("cox_canonical_order", ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32)]),
@@ -207,6 +214,83 @@ def cox_init(X, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-1
     rc = lib().cox_init(ctypes.byref(h), ctypes.byref(d), ctypes.byref(o))
     _check(None, rc)
     return h.value
+
+
+def _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep):
+    o = cox_default_options()
+    o.gamma = float(gamma)
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.mode = int(mode)
+    o.x_precision = int(x_precision)
+    if penalize is not None:
+        pen = np.ascontiguousarray(penalize, dtype=np.uint8)
+        keep.append(pen)
+        o.penalize = pen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    if stream is not None:
+        o.stream = ctypes.c_void_p(int(stream))
+    return o
+
+
+def cox_init_resample(parent, count, *, inherit=True, gamma=0.0, penalize=None, tol=1e-12, max_iter=1000,
+                      stream=None, mode=COX_CCD, x_precision=COX_F64):
+    """A handle on the data set in which row i of the parent's data appears count[i] times,
+    gathered on the device from the parent's X.  inherit=True keeps the parent's options
+    and l1 weights (the keyword options are then ignored)."""
+    n, _, _ = cox_shape(parent)
+    cnt = np.ascontiguousarray(count, dtype=np.uint32)
+    if cnt.shape != (n,):
+        raise ValueError(f"count needs {n} entries")
+    keep = [cnt]
+    o = None if inherit else _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep)
+    h = ctypes.c_void_p()
+    rc = lib().cox_init_resample(ctypes.byref(h), parent, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                 None if o is None else ctypes.byref(o))
+    _check(None, rc)
+    return h.value
+
+
+def cox_set_penalty(h, gamma, penalize=None):
+    pen = None if penalize is None else np.ascontiguousarray(penalize, dtype=np.uint8)
+    rc = lib().cox_set_penalty(h, float(gamma), None if pen is None else pen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    _check(h, rc)
+
+
+def cox_cross_validate(h, fold, gammas, penalize=None, nfolds=None):
+    """Cross-validated log partial likelihood along `gammas` (cox_cross_validate).
+    Returns (cvl[ngamma], betas[nfolds, ngamma, p], status[nfolds, ngamma])."""
+    n, p, _ = cox_shape(h)
+    fold = np.ascontiguousarray(fold, dtype=np.int32)
+    if fold.shape != (n,):
+        raise ValueError(f"fold needs {n} entries")
+    K = int(fold.max()) + 1 if nfolds is None else int(nfolds)
+    gam = np.ascontiguousarray(gammas, dtype=np.float64)
+    pen = None if penalize is None else np.ascontiguousarray(penalize, dtype=np.uint8)
+    cvl = np.zeros(gam.shape[0])
+    betas = np.zeros((K, gam.shape[0], p))
+    status = np.zeros((K, gam.shape[0]), dtype=np.int32)
+    rc = lib().cox_cross_validate(h, K, fold.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), gam.shape[0], _dptr(gam),
+                                  None if pen is None else pen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                  _dptr(cvl), _dptr(betas), status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    _check(h, rc, ok=(COX_OK, COX_NOT_CONVERGED))
+    return cvl, betas, status
+
+
+def cox_bootstrap(h, counts, beta0=None):
+    """Refits on the row multiplicities counts[b] (cox_bootstrap).  Returns (betas[B, p], status[B])."""
+    n, p, _ = cox_shape(h)
+    cnt = np.ascontiguousarray(counts, dtype=np.uint32)
+    if cnt.ndim != 2 or cnt.shape[1] != n:
+        raise ValueError(f"counts needs shape (B, {n})")
+    B = cnt.shape[0]
+    b0 = None if beta0 is None else np.ascontiguousarray(beta0, dtype=np.float64)
+    betas = np.zeros((B, p))
+    status = np.zeros(B, dtype=np.int32)
+    rc = lib().cox_bootstrap(h, B, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                             None if b0 is None else _dptr(b0), _dptr(betas),
+                             status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    _check(h, rc, ok=(COX_OK, COX_NOT_CONVERGED))
+    return betas, status
 
 
 def cox_fit(h, beta0=None, p=None):
@@ -398,6 +482,21 @@ class CoxModel:
 
     def layout(self):
         return cox_layout(self.h)
+
+    def resample(self, count, **opts):
+        """A CoxModel on the data set with row multiplicities `count` (see cox_init_resample)."""
+        m = CoxModel.__new__(CoxModel)
+        m.h = cox_init_resample(self.h, count, inherit=not opts, **opts)
+        return m
+
+    def set_penalty(self, gamma, penalize=None):
+        cox_set_penalty(self.h, gamma, penalize)
+
+    def cross_validate(self, fold, gammas, penalize=None, nfolds=None):
+        return cox_cross_validate(self.h, fold, gammas, penalize, nfolds)
+
+    def bootstrap(self, counts, beta0=None):
+        return cox_bootstrap(self.h, counts, beta0)
 
     def kernel_ms(self):
         return cox_last_kernel_ms(self.h)

@@ -146,6 +146,77 @@ static void tile_layout(const std::vector<uint32_t> &meta, LaunchShape &shape, s
     shape.ld = (int64_t)shape.grid * kNewtonTile;
 }
 
+// Device buffers of a handle whose layout (shape, pos) is set.
+static hipError_t alloc_device(cox_handle *h)
+{
+    const int64_t ld = h->shape.ld, p = h->p;
+    hipError_t e;
+    if ((e = hipMalloc(&h->d_x, sizeof(double) * (size_t)ld * p)) != hipSuccess ||
+        (e = hipMalloc(&h->d_meta, sizeof(uint32_t) * (size_t)ld)) != hipSuccess ||
+        (e = hipMalloc(&h->d_vec, sizeof(double) * (size_t)(6 * p + kResultSlots + 64))) != hipSuccess ||
+        (e = hipMalloc(&h->d_sync, sync_scratch_bytes(h->shape.ipt ? h->shape.grid : 1))) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+// Row words at the layout positions; padding rows are single-row strata without events.
+static hipError_t upload_meta(cox_handle *h)
+{
+    const int64_t ld = h->shape.ld;
+    std::vector<uint32_t> mpad(ld, kHeadBit | kPadBit);
+    for (int64_t i = 0; i < h->n; ++i) mpad[h->pos[i]] = h->meta[i];
+    return hipMemcpy(h->d_meta, mpad.data(), sizeof(uint32_t) * ld, hipMemcpyHostToDevice);
+}
+
+// l1 weights, the exponential's table and the timing events.
+static hipError_t upload_tables(cox_handle *h)
+{
+    hipError_t e = hipMemcpy(h->gam(), h->gamma.data(), sizeof(double) * h->p, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        // 2^(j/64), j = 0..63, rounded to nearest from extended precision (table of the device exp)
+        double tab[64];
+        for (int j = 0; j < 64; ++j) tab[j] = (double)std::exp2l((long double)j / 64.0L);
+        e = hipMemcpy(h->exp_tab(), tab, sizeof(tab), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipEventCreate(&h->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&h->ev1);
+    return e;
+}
+
+// Options common to cox_init and cox_init_resample; 0 or a COX_* code with msg set.
+static int check_options(const cox_options &opt, std::string &msg)
+{
+    if (opt.mode != COX_CCD && opt.mode != COX_NEWTON_REFINE) { msg = "unknown mode"; return COX_EINVAL; }
+    if (opt.x_precision != COX_F64 && opt.x_precision != COX_BF16 && opt.x_precision != COX_FP8_E4M3) {
+        msg = "x_precision must be COX_F64, COX_BF16 or COX_FP8_E4M3";
+        return COX_EUNSUPPORTED;
+    }
+    if (opt.x_precision == COX_FP8_E4M3 && opt.mode != COX_NEWTON_REFINE) {
+        msg = "COX_FP8_E4M3 applies to COX_NEWTON_REFINE fits";
+        return COX_EUNSUPPORTED;
+    }
+    if (opt.mode == COX_NEWTON_REFINE && opt.gamma != 0.0) {
+        msg = "COX_NEWTON_REFINE fits the unpenalised model (gamma = 0)";
+        return COX_EUNSUPPORTED;
+    }
+    if (opt.ties != COX_BRESLOW) { msg = "only COX_BRESLOW ties"; return COX_EUNSUPPORTED; }
+    if (!(opt.gamma >= 0.0) || !std::isfinite(opt.gamma)) { msg = "gamma must be finite and >= 0"; return COX_EINVAL; }
+    if (!(opt.tol >= 0.0)) { msg = "tol must be >= 0"; return COX_EINVAL; }
+    if (opt.max_iter < 1) { msg = "max_iter must be >= 1"; return COX_EINVAL; }
+    return 0;
+}
+
+// Launch layout for h->meta (sets shape and pos); Newton fits fall back to the tile layout.
+static int layout_for(cox_handle *h, std::string &err)
+{
+    int rc = choose_layout(h->meta, (int)h->p, h->shape, h->pos, err);
+    if (rc == COX_EUNSUPPORTED && h->opt.mode == COX_NEWTON_REFINE) {
+        tile_layout(h->meta, h->shape, h->pos);
+        rc = 0;
+    }
+    return rc;
+}
+
 extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *o)
 {
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
@@ -158,17 +229,10 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     cox_options opt;
     if (o) opt = *o;
     else cox_default_options(&opt);
-    if (opt.mode != COX_CCD && opt.mode != COX_NEWTON_REFINE) return fail(nullptr, COX_EINVAL, "unknown mode");
-    if (opt.x_precision != COX_F64 && opt.x_precision != COX_BF16 && opt.x_precision != COX_FP8_E4M3)
-        return fail(nullptr, COX_EUNSUPPORTED, "x_precision must be COX_F64, COX_BF16 or COX_FP8_E4M3");
-    if (opt.x_precision == COX_FP8_E4M3 && opt.mode != COX_NEWTON_REFINE)
-        return fail(nullptr, COX_EUNSUPPORTED, "COX_FP8_E4M3 applies to COX_NEWTON_REFINE fits");
-    if (opt.mode == COX_NEWTON_REFINE && opt.gamma != 0.0)
-        return fail(nullptr, COX_EUNSUPPORTED, "COX_NEWTON_REFINE fits the unpenalised model (gamma = 0)");
-    if (opt.ties != COX_BRESLOW) return fail(nullptr, COX_EUNSUPPORTED, "only COX_BRESLOW ties");
-    if (!(opt.gamma >= 0.0) || !std::isfinite(opt.gamma)) return fail(nullptr, COX_EINVAL, "gamma must be finite and >= 0");
-    if (!(opt.tol >= 0.0)) return fail(nullptr, COX_EINVAL, "tol must be >= 0");
-    if (opt.max_iter < 1) return fail(nullptr, COX_EINVAL, "max_iter must be >= 1");
+    {
+        std::string msg;
+        if (const int rc = check_options(opt, msg)) return fail(nullptr, rc, msg);
+    }
 
     cox_handle *h = new cox_handle();
     h->n = n;
@@ -186,32 +250,20 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
         for (int64_t j = 0; j < p; ++j) h->gamma[j] = o->penalize[j] ? opt.gamma : 0.0;
 
     std::string err;
-    int rc = choose_layout(h->meta, (int)p, h->shape, h->pos, err);
-    if (rc == COX_EUNSUPPORTED && opt.mode == COX_NEWTON_REFINE) {
-        tile_layout(h->meta, h->shape, h->pos);
-        rc = 0;
-    }
+    const int rc = layout_for(h, err);
     if (rc != 0) {
         delete h;
         return fail(nullptr, rc, err);
     }
     const int64_t ld = h->shape.ld;
 
-    hipError_t e;
-    if ((e = hipMalloc(&h->d_x, sizeof(double) * (size_t)ld * p)) != hipSuccess ||
-        (e = hipMalloc(&h->d_meta, sizeof(uint32_t) * (size_t)ld)) != hipSuccess ||
-        (e = hipMalloc(&h->d_vec, sizeof(double) * (size_t)(6 * p + kResultSlots + 64))) != hipSuccess ||
-        (e = hipMalloc(&h->d_sync, sync_scratch_bytes(h->shape.ipt ? h->shape.grid : 1))) != hipSuccess) {
+    hipError_t e = alloc_device(h);
+    if (e != hipSuccess) {
         free_device(h);
         delete h;
         return hip_fail(nullptr, e, "device allocation");
     }
-    // row words; padding rows are single-row strata without events
-    {
-        std::vector<uint32_t> mpad(ld, kHeadBit | kPadBit);
-        for (int64_t i = 0; i < n; ++i) mpad[h->pos[i]] = h->meta[i];
-        e = hipMemcpy(h->d_meta, mpad.data(), sizeof(uint32_t) * ld, hipMemcpyHostToDevice);
-    }
+    e = upload_meta(h);
     // X in canonical order at the layout positions, column by column, and q_j = delta'X_j
     std::vector<double> col(ld, 0.0), q(p, 0.0);
     for (int64_t j = 0; j < p && e == hipSuccess; ++j) {
@@ -227,21 +279,149 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
         e = hipMemcpy(h->d_x + j * ld, col.data(), sizeof(double) * ld, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemcpy(h->q(), q.data(), sizeof(double) * p, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(h->gam(), h->gamma.data(), sizeof(double) * p, hipMemcpyHostToDevice);
-    if (e == hipSuccess) {
-        // 2^(j/64), j = 0..63, rounded to nearest from extended precision (table of the device exp)
-        double tab[64];
-        for (int j = 0; j < 64; ++j) tab[j] = (double)std::exp2l((long double)j / 64.0L);
-        e = hipMemcpy(h->exp_tab(), tab, sizeof(tab), hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess) e = hipEventCreate(&h->ev0);
-    if (e == hipSuccess) e = hipEventCreate(&h->ev1);
+    if (e == hipSuccess) e = upload_tables(h);
     if (e != hipSuccess) {
         free_device(h);
         delete h;
         return hip_fail(nullptr, e, "device upload");
     }
     *out = h;
+    return COX_OK;
+}
+
+// Canonical rows of the data set in which original row i appears count[i] times
+// (copies numbered consecutively, original rows in order), derived from the
+// parent's canonical order without sorting: copies of one row are adjacent and
+// keep the parent's order.  The parent marks the last row of every tie group
+// with events; the rows between two such marks are tie groups without events
+// followed by that group, so the group's events are all the range's events and
+// the child's mark goes on the last copy in the range.
+static void resampled_order(const cox_handle *parent, const uint32_t *count, std::vector<int64_t> &perm,
+                            std::vector<uint32_t> &meta, std::vector<int64_t> &from)
+{
+    const int64_t n = parent->n;
+    std::vector<int64_t> first((size_t)n + 1, 0);   // first copy of original row i
+    for (int64_t i = 0; i < n; ++i) first[(size_t)i + 1] = first[(size_t)i] + count[i];
+    perm.clear();
+    meta.clear();
+    from.clear();
+    bool head_pending = false;
+    int64_t range_first = 0;    // first child row of the current range
+    uint64_t range_events = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        const uint32_t w = parent->meta[(size_t)c];
+        if (w & kHeadBit) {
+            head_pending = true;
+            range_first = (int64_t)perm.size();
+            range_events = 0;
+        }
+        const int64_t i = parent->perm[(size_t)c];
+        const bool ev = (w & kEventBit) != 0u;
+        for (uint32_t k = 0; k < count[i]; ++k) {
+            perm.push_back(first[(size_t)i] + k);
+            meta.push_back((head_pending ? kHeadBit : 0u) | (ev ? kEventBit : 0u));
+            from.push_back(c);
+            head_pending = false;
+        }
+        if (ev) range_events += count[i];
+        if (w & kCountMask) {
+            if ((int64_t)perm.size() > range_first && range_events > 0)
+                meta.back() |= (uint32_t)range_events;
+            range_first = (int64_t)perm.size();
+            range_events = 0;
+        }
+    }
+}
+
+extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, const uint32_t *count,
+                                 const cox_options *o)
+{
+    if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!parent || !count) return fail(nullptr, COX_EINVAL, "parent and count are required");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != parent->device) return fail(nullptr, COX_EINVAL, "the parent handle lives on another device");
+    uint64_t total = 0;
+    for (int64_t i = 0; i < parent->n; ++i) total += count[i];
+    if (total < 1) return fail(nullptr, COX_EINVAL, "the resampled data set has no rows");
+    if (total > (uint64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "the resampled data set exceeds 2^29 - 1 rows");
+    cox_options opt;
+    if (o) opt = *o;
+    else opt = parent->opt;
+    {
+        std::string msg;
+        if (const int rc = check_options(opt, msg)) return fail(nullptr, rc, msg);
+    }
+    cox_handle *h = new cox_handle();
+    h->n = (int64_t)total;
+    h->p = parent->p;
+    h->opt = opt;
+    h->opt.penalize = nullptr;
+    h->stream = static_cast<hipStream_t>(opt.stream);
+    h->device = parent->device;
+    std::vector<int64_t> from;
+    resampled_order(parent, count, h->perm, h->meta, from);
+    if (o) {
+        h->gamma.assign((size_t)h->p, opt.gamma);
+        if (o->penalize)
+            for (int64_t j = 0; j < h->p; ++j) h->gamma[(size_t)j] = o->penalize[j] ? opt.gamma : 0.0;
+    } else {
+        h->gamma = parent->gamma;
+    }
+    std::string err;
+    const int rc = layout_for(h, err);
+    if (rc != 0) {
+        delete h;
+        return fail(nullptr, rc, err);
+    }
+    const int64_t ld = h->shape.ld;
+    if (parent->shape.ld > (int64_t)INT32_MAX) {
+        delete h;
+        return fail(nullptr, COX_EUNSUPPORTED, "parent layout too long for 32-bit row indices");
+    }
+    // device row of the child -> device row of the parent (-1: padding)
+    std::vector<int32_t> src((size_t)ld, -1);
+    for (int64_t k = 0; k < h->n; ++k) src[(size_t)h->pos[(size_t)k]] = (int32_t)parent->pos[(size_t)from[(size_t)k]];
+    hipError_t e = alloc_device(h);
+    int32_t *d_src = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&d_src, sizeof(int32_t) * (size_t)ld);
+    if (e != hipSuccess) {
+        if (d_src) (void)hipFree(d_src);
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "device allocation");
+    }
+    e = upload_meta(h);
+    if (e == hipSuccess) e = hipMemcpy(d_src, src.data(), sizeof(int32_t) * (size_t)ld, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = (hipError_t)launch_gather_rows(parent->d_x, parent->shape.ld, d_src, h->d_x, ld, (int)h->p, h->stream);
+    if (e == hipSuccess) e = (hipError_t)launch_event_sums(h->d_x, ld, h->d_meta, h->q(), (int)h->p, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d_src);
+    if (e == hipSuccess) e = upload_tables(h);
+    if (e != hipSuccess) {
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "building the resampled data set");
+    }
+    *out = h;
+    return COX_OK;
+}
+
+extern "C" int cox_set_penalty(cox_handle *h, double gamma, const uint8_t *penalize)
+{
+    if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(h, COX_EINVAL, "gamma must be finite and >= 0");
+    if (h->opt.mode == COX_NEWTON_REFINE && gamma != 0.0)
+        return fail(h, COX_EUNSUPPORTED, "COX_NEWTON_REFINE fits the unpenalised model (gamma = 0)");
+    std::vector<double> g((size_t)h->p, gamma);
+    if (penalize)
+        for (int64_t j = 0; j < h->p; ++j) g[(size_t)j] = penalize[j] ? gamma : 0.0;
+    const hipError_t e = hipMemcpy(h->gam(), g.data(), sizeof(double) * h->p, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(h, e, "uploading the l1 weights");
+    h->gamma.swap(g);
+    h->opt.gamma = gamma;
     return COX_OK;
 }
 
@@ -331,6 +511,94 @@ extern "C" int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox
         info->kkt_inf = kkt;
     }
     return rc;
+}
+
+// -log partial likelihood (Eq. strat_l, no penalty) of h's data at beta.
+static int neg_loglik(cox_handle *h, const double *beta, double *nll)
+{
+    double res[kResultSlots];
+    const int rc = run_kernel(h, kModeEval, 0, 1, beta, res);
+    if (rc != COX_OK) return rc;
+    *nll = res[kResObjective];
+    return COX_OK;
+}
+
+extern "C" int cox_cross_validate(cox_handle *h, int nfolds, const int32_t *fold, int ngamma, const double *gammas,
+                                  const uint8_t *penalize, double *cvl, double *betas, int *status)
+{
+    if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (h->opt.mode != COX_CCD) return fail(h, COX_EUNSUPPORTED, "cross-validation runs l1 fits: the handle must be COX_CCD");
+    if (nfolds < 2 || !fold) return fail(h, COX_EINVAL, "need nfolds >= 2 and a fold for every row");
+    if (ngamma < 1 || !gammas || !cvl) return fail(h, COX_EINVAL, "need ngamma >= 1, gammas and cvl");
+    for (int g = 0; g < ngamma; ++g)
+        if (!(gammas[g] >= 0.0) || !std::isfinite(gammas[g])) return fail(h, COX_EINVAL, "gamma must be finite and >= 0");
+    std::vector<int64_t> size((size_t)nfolds, 0);
+    for (int64_t i = 0; i < h->n; ++i) {
+        if (fold[i] < 0 || fold[i] >= nfolds) return fail(h, COX_EINVAL, "fold index out of range");
+        ++size[(size_t)fold[i]];
+    }
+    for (int k = 0; k < nfolds; ++k)
+        if (size[(size_t)k] == 0 || size[(size_t)k] == h->n) return fail(h, COX_EINVAL, "every fold must hold some rows, and not all");
+    const int64_t p = h->p;
+    std::fill(cvl, cvl + ngamma, 0.0);
+    bool all_converged = true;
+    std::vector<uint32_t> keep((size_t)h->n);
+    std::vector<double> beta((size_t)p), prev((size_t)p);
+    for (int k = 0; k < nfolds; ++k) {
+        for (int64_t i = 0; i < h->n; ++i) keep[(size_t)i] = fold[i] != k ? 1u : 0u;
+        cox_options o = h->opt;
+        o.gamma = gammas[0];
+        o.penalize = penalize;
+        cox_handle *c = nullptr;
+        int rc = cox_init_resample(&c, h, keep.data(), &o);
+        if (rc != COX_OK) return fail(h, rc, std::string("fold training set: ") + cox_last_error(nullptr));
+        std::fill(prev.begin(), prev.end(), 0.0);
+        for (int g = 0; g < ngamma && rc >= 0; ++g) {
+            rc = cox_set_penalty(c, gammas[g], penalize);
+            cox_fit_info info{};
+            if (rc == COX_OK) rc = cox_fit(c, prev.data(), beta.data(), &info);
+            if (rc < 0) break;
+            if (rc != COX_OK) all_converged = false;
+            if (status) status[(size_t)k * ngamma + g] = rc;
+            double nll_train = 0.0, nll_full = 0.0;
+            int rc2 = neg_loglik(c, beta.data(), &nll_train);
+            if (rc2 == COX_OK) rc2 = neg_loglik(h, beta.data(), &nll_full);
+            if (rc2 != COX_OK) {
+                rc = rc2;
+                break;
+            }
+            cvl[g] += nll_train - nll_full;    // l(beta) - l_{-k}(beta), l = log partial likelihood
+            if (betas) std::copy(beta.begin(), beta.end(), betas + ((size_t)k * ngamma + g) * p);
+            prev = beta;
+            rc = COX_OK;
+        }
+        const std::string cerr = rc < 0 ? c->err : std::string();
+        cox_release(c);
+        if (rc < 0) return fail(h, rc, "fold " + std::to_string(k) + ": " + cerr);
+    }
+    return all_converged ? COX_OK : COX_NOT_CONVERGED;
+}
+
+extern "C" int cox_bootstrap(cox_handle *h, int nrep, const uint32_t *counts, const double *beta0, double *betas,
+                             int *status)
+{
+    if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (nrep < 1 || !counts || !betas) return fail(h, COX_EINVAL, "need nrep >= 1, counts and betas");
+    const int64_t n = h->n, p = h->p;
+    bool all_converged = true;
+    for (int b = 0; b < nrep; ++b) {
+        cox_handle *c = nullptr;
+        int rc = cox_init_resample(&c, h, counts + (size_t)b * n, nullptr);
+        if (rc != COX_OK) return fail(h, rc, "replicate " + std::to_string(b) + ": " + cox_last_error(nullptr));
+        cox_fit_info info{};
+        rc = cox_fit(c, beta0, betas + (size_t)b * p, &info);
+        const std::string cerr = rc < 0 ? c->err : std::string();
+        cox_release(c);
+        if (rc < 0) return fail(h, rc, "replicate " + std::to_string(b) + ": " + cerr);
+        if (status) status[b] = rc;
+        if (rc != COX_OK) all_converged = false;
+    }
+    return all_converged ? COX_OK : COX_NOT_CONVERGED;
 }
 
 extern "C" int cox_evaluate(cox_handle *h, const double *beta, double *objective, double *grad,

@@ -66,6 +66,13 @@ void carve_sync_scratch(void *base, int grid, CcdLaunch &L);
 int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream,
                hipEvent_t ev0, hipEvent_t ev1);
 
+// Resampled data sets (resample.hip); return hipError_t values.
+// x_out[j][r] = src[r] >= 0 ? x_in[j][src[r]] : 0 for r < ld_out (src: device, ld_out entries).
+int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, double *x_out, int64_t ld_out, int p,
+                       hipStream_t stream);
+// q[j] = sum of x[j][r] over the rows whose word has the event bit (fixed-order sums).
+int launch_event_sums(const double *x, int64_t ld, const uint32_t *meta, double *q, int p, hipStream_t stream);
+
 // Segmented +scan of n doubles on device memory; returns a COX_* code.
 int segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, hipStream_t stream);
 

@@ -1,0 +1,86 @@
+// resample.hip -- device side of cox_init_resample: a resampled data set (row
+// multiplicities, e.g. the training rows of a cross-validation fold or a
+// bootstrap sample) is built from a handle's device-resident X by a gather,
+// without sending X over PCIe again.
+#include "internal.h"
+
+namespace coxmi {
+
+namespace {
+
+constexpr int kGatherBlock = 256;
+constexpr int kGatherRows = 4;     // rows per thread
+constexpr int kGatherCols = 8;     // columns per workgroup (the source index is loaded once for them)
+
+// x_out[j][r] = src[r] >= 0 ? x_in[j][src[r]] : 0 for r < ld_out, j < p.
+// Grid: (ceil(ld_out / (kGatherBlock * kGatherRows)), ceil(p / kGatherCols)).
+__global__ __launch_bounds__(kGatherBlock) void gather_rows_kernel(const double *__restrict__ x_in, int64_t ld_in,
+                                                                   const int32_t *__restrict__ src,
+                                                                   double *__restrict__ x_out, int64_t ld_out, int p)
+{
+    const int64_t r0 = (int64_t)blockIdx.x * (kGatherBlock * kGatherRows) + threadIdx.x;
+    const int j0 = blockIdx.y * kGatherCols;
+    int32_t s[kGatherRows];
+#pragma unroll
+    for (int k = 0; k < kGatherRows; ++k) {
+        const int64_t r = r0 + (int64_t)k * kGatherBlock;
+        s[k] = r < ld_out ? src[r] : -1;
+    }
+#pragma unroll
+    for (int c = 0; c < kGatherCols; ++c) {
+        const int j = j0 + c;
+        if (j >= p) break;
+        const double *xi = x_in + (int64_t)j * ld_in;
+        double *xo = x_out + (int64_t)j * ld_out;
+#pragma unroll
+        for (int k = 0; k < kGatherRows; ++k) {
+            const int64_t r = r0 + (int64_t)k * kGatherBlock;
+            if (r < ld_out) xo[r] = s[k] >= 0 ? xi[s[k]] : 0.0;
+        }
+    }
+}
+
+constexpr int kQBlock = 256;
+
+// q[j] = sum over rows with the event bit of x[j][r], one workgroup per column;
+// each thread sums a fixed stride of rows and the workgroup folds the thread
+// sums in a fixed tree, so the result does not depend on timing.
+__global__ __launch_bounds__(kQBlock) void event_sums_kernel(const double *__restrict__ x, int64_t ld,
+                                                             const uint32_t *__restrict__ meta, double *__restrict__ q)
+{
+    __shared__ double s[kQBlock];
+    const int j = blockIdx.x;
+    const double *xj = x + (int64_t)j * ld;
+    double acc = 0.0;
+    for (int64_t r = threadIdx.x; r < ld; r += kQBlock)
+        if (meta[r] & kEventBit) acc += xj[r];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int w = kQBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) q[j] = s[0];
+}
+
+}  // namespace
+
+int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, double *x_out, int64_t ld_out, int p,
+                       hipStream_t stream)
+{
+    if (ld_out <= 0 || p <= 0) return (int)hipSuccess;
+    const int64_t per = (int64_t)kGatherBlock * kGatherRows;
+    const dim3 grid((unsigned)((ld_out + per - 1) / per), (unsigned)((p + kGatherCols - 1) / kGatherCols));
+    hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(kGatherBlock), 0, stream, x_in, ld_in, src, x_out, ld_out, p);
+    return (int)hipGetLastError();
+}
+
+int launch_event_sums(const double *x, int64_t ld, const uint32_t *meta, double *q, int p, hipStream_t stream)
+{
+    if (p <= 0) return (int)hipSuccess;
+    hipLaunchKernelGGL(event_sums_kernel, dim3((unsigned)p), dim3(kQBlock), 0, stream, x, ld, meta, q);
+    return (int)hipGetLastError();
+}
+
+}  // namespace coxmi
