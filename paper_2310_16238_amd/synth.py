@@ -272,3 +272,11 @@ def config_step_effect(n: int = 407_828, p: int = 1000, seed: int = 6, cut: floa
     Y = np.maximum(np.ceil(np.minimum(T, C)), 1.0)
     return CoxData(X=X, time=Y, event=event, stratum=np.zeros(n, dtype=np.int32), beta_true=b,
                    gamma=math.sqrt(2.0), name=f"step-effect-n{n}-p{p}-cut{cut:g}")
+
+
+def config_legend(n: int = 946_911, p: int = 1000, K: int = 10, seed: int = 7) -> CoxData:
+    """Sec. 3.2 shape: p binary covariates with 3% ones (the paper's 97% sparsity),
+    coefficients N(0, 0.25) x Bernoulli(0.2), K equal-sized strata (standing in for its
+    propensity-score strata); column 0 plays the unpenalised treatment covariate."""
+    return make("binary", n, p, K, seed, beta_kind="normal", beta_sd=0.5, beta_nonzero=0.2, density=0.03,
+             gamma=math.sqrt(2.0), name=f"legend-n{n}-p{p}-K{K}")

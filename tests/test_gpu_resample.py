@@ -6,8 +6,10 @@ the oracle on the explicitly repeated data.
   dropped tie groups with events);
 * fits and evaluations on it: FP64 tolerances as for every fit (max|gpu - oracle| /
   max|oracle| <= 1e-10, l1 zero pattern exact, objective 1e-11 relative);
-* cross-validated log likelihood: |gpu - oracle| <= 1e-10 sum_k (|l| + |l_{-k}|) at the
-  oracle's beta (each term is a difference of two log likelihoods evaluated in FP64).
+* cross-validated log likelihood: |gpu - oracle| <= 1e-11 sum_k (|l| + |l_{-k}|): each term
+  is a difference of two FP64 log likelihoods (rounding ~1e-13 of their size), and the fold
+  estimates, equal to 1e-10 relative, enter l(beta) to first order through the held-out
+  rows' score, whose size is a small fraction of |l|.
 """
 import numpy as np
 import pytest
@@ -121,8 +123,8 @@ def test_cross_validation_matches_oracle():
     nll_all = orc.neg_loglik(d.X, d.time, d.event, d.stratum, np.zeros(30))
     scale = 2.0 * 5 * abs(nll_all)
     err = float(np.max(np.abs(cvl - rcvl)))
-    _say(f"  cvl {np.round(cvl, 3)}; max |gpu - oracle| {err:.3e} (bound {1e-10 * scale:.3e})")
-    assert err <= 1e-10 * scale
+    _say(f"  cvl {np.round(cvl, 3)}; max |gpu - oracle| {err:.3e} (bound {1e-11 * scale:.3e})")
+    assert err <= 1e-11 * scale
     assert int(np.argmax(cvl)) == int(np.argmax(rcvl))
 
 
