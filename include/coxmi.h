@@ -248,6 +248,29 @@ void cox_intervals_release(cox_intervals *s);
  * cox_last_error(NULL). */
 int cox_init_resample(cox_handle **out, const cox_handle *parent, const uint32_t *count, const cox_options *o);
 
+/* The interval-stratified model of Secs. 2.2-2.3 (step-function coefficients) built on
+ * the device from a handle on the original data, without the augmented X ever
+ * existing on the host or crossing PCIe: rows, strata, times and events are those of
+ * cox_split_intervals (same cuts and tv_coef rules, same row and column order, so
+ * cox_layout's perm numbers its augmented rows), and each augmented column is
+ * gathered from the parent's resident column (zero outside its interval for a step
+ * coefficient).  Covariates that change between intervals need cox_split_intervals.
+ *   parent           : a handle on the current device, built from n rows
+ *   time, event,
+ *   stratum          : host, the n rows the parent was built from (stratum may be NULL);
+ *                      checked against the parent's event pattern
+ *   ncuts, cuts,
+ *   tv_coef          : as for cox_split_intervals (tv_coef: parent p flags or NULL)
+ *   o                : options of the child (penalize indexes the augmented columns);
+ *                      NULL = the parent's options, each augmented column taking its
+ *                      source column's l1 weight
+ * Errors: COX_EINVAL (NULL pointer, bad cuts, data that do not match the parent),
+ * COX_EUNSUPPORTED (more than 2^29 - 1 rows or 4096 columns after the split),
+ * COX_ENOMEM, COX_EDEVICE; message via cox_last_error(NULL). */
+int cox_init_intervals(cox_handle **out, const cox_handle *parent, const double *time, const uint8_t *event,
+                       const int32_t *stratum, int ncuts, const double *cuts, const uint8_t *tv_coef,
+                       const cox_options *o);
+
 /* Replace h's l1 weights: gamma_j = gamma for penalised columns (penalize: host,
  * p flags, NULL = all), 0 otherwise.  COX_EINVAL for a negative or non-finite
  * gamma; COX_EUNSUPPORTED for gamma != 0 on a COX_NEWTON_REFINE handle. */

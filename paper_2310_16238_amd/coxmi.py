@@ -122,6 +122,9 @@ SIGNATURES = [
     ("cox_intervals_release", None, [ctypes.POINTER(cox_intervals)]),
     ("cox_init_resample", ctypes.c_int, [ctypes.POINTER(_VP), _VP, ctypes.POINTER(ctypes.c_uint32),
                                          ctypes.POINTER(cox_options)]),
+    ("cox_init_intervals", ctypes.c_int, [ctypes.POINTER(_VP), _VP, _DP, ctypes.POINTER(ctypes.c_uint8),
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _DP,
+                                          ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(cox_options)]),
     ("cox_set_penalty", ctypes.c_int, [_VP, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8)]),
     ("cox_cross_validate", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _DP,
                                           ctypes.POINTER(ctypes.c_uint8), _DP, _DP, ctypes.POINTER(ctypes.c_int)]),
@@ -246,6 +249,38 @@ def cox_init_resample(parent, count, *, inherit=True, gamma=0.0, penalize=None, 
     h = ctypes.c_void_p()
     rc = lib().cox_init_resample(ctypes.byref(h), parent, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                  None if o is None else ctypes.byref(o))
+    _check(None, rc)
+    return h.value
+
+
+def cox_init_intervals(parent, time, event, stratum=None, cuts=(), tv_coef=None, *, inherit=True, gamma=0.0,
+                       penalize=None, tol=1e-12, max_iter=1000, stream=None, mode=COX_CCD, x_precision=COX_F64):
+    """The interval-stratified model (cox_init_intervals) built on the device from the parent's
+    X; time, event, stratum are the data the parent was built from."""
+    n, p, _ = cox_shape(parent)
+    time = np.ascontiguousarray(time, dtype=np.float64)
+    event = np.ascontiguousarray(event, dtype=np.uint8)
+    if time.shape != (n,) or event.shape != (n,):
+        raise ValueError(f"time and event need {n} entries")
+    keep = [time, event]
+    st = None
+    if stratum is not None:
+        st = np.ascontiguousarray(stratum, dtype=np.int32)
+        keep.append(st)
+    cuts = np.ascontiguousarray(cuts, dtype=np.float64)
+    tv = None
+    if tv_coef is not None:
+        tv = np.ascontiguousarray(tv_coef, dtype=np.uint8)
+        if tv.shape != (p,):
+            raise ValueError(f"tv_coef needs {p} entries")
+    o = None if inherit else _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep)
+    h = ctypes.c_void_p()
+    rc = lib().cox_init_intervals(ctypes.byref(h), parent, _dptr(time),
+                                  event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                  None if st is None else st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  cuts.shape[0], _dptr(cuts) if cuts.shape[0] else None,
+                                  None if tv is None else tv.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                  None if o is None else ctypes.byref(o))
     _check(None, rc)
     return h.value
 
@@ -487,6 +522,12 @@ class CoxModel:
         """A CoxModel on the data set with row multiplicities `count` (see cox_init_resample)."""
         m = CoxModel.__new__(CoxModel)
         m.h = cox_init_resample(self.h, count, inherit=not opts, **opts)
+        return m
+
+    def intervals(self, time, event, stratum=None, cuts=(), tv_coef=None, **opts):
+        """A CoxModel on the interval-stratified data (see cox_init_intervals)."""
+        m = CoxModel.__new__(CoxModel)
+        m.h = cox_init_intervals(self.h, time, event, stratum, cuts, tv_coef, inherit=not opts, **opts)
         return m
 
     def set_penalty(self, gamma, penalize=None):

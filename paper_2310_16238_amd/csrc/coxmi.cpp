@@ -19,6 +19,7 @@
 #include "canonical.h"
 #include "handle.h"
 #include "internal.h"
+#include "intervals.h"
 
 using namespace coxmi;
 
@@ -395,7 +396,8 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
     e = upload_meta(h);
     if (e == hipSuccess) e = hipMemcpy(d_src, src.data(), sizeof(int32_t) * (size_t)ld, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = (hipError_t)launch_gather_rows(parent->d_x, parent->shape.ld, d_src, h->d_x, ld, (int)h->p, h->stream);
+        e = (hipError_t)launch_gather_rows(parent->d_x, parent->shape.ld, d_src, nullptr, nullptr, nullptr, h->d_x, ld,
+                                           (int)h->p, h->stream);
     if (e == hipSuccess) e = (hipError_t)launch_event_sums(h->d_x, ld, h->d_meta, h->q(), (int)h->p, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     (void)hipFree(d_src);
@@ -404,6 +406,107 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
         free_device(h);
         delete h;
         return hip_fail(nullptr, e, "building the resampled data set");
+    }
+    *out = h;
+    return COX_OK;
+}
+
+extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, const double *time,
+                                  const uint8_t *event, const int32_t *stratum, int ncuts, const double *cuts,
+                                  const uint8_t *tv_coef, const cox_options *o)
+{
+    if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!parent) return fail(nullptr, COX_EINVAL, "parent is NULL");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != parent->device) return fail(nullptr, COX_EINVAL, "the parent handle lives on another device");
+    const int64_t n = parent->n, p = parent->p;
+    if (!time || !event) return fail(nullptr, COX_EINVAL, "time and event are required");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(time[i]) || event[i] > 1) return fail(nullptr, COX_EINVAL, "time must be finite, event 0 or 1");
+    for (int64_t c = 0; c < n; ++c)
+        if (((parent->meta[(size_t)c] & kEventBit) != 0u) != (event[parent->perm[(size_t)c]] != 0))
+            return fail(nullptr, COX_EINVAL, "time and event are not the data the parent was built from");
+    cox_options opt;
+    if (o) opt = *o;
+    else opt = parent->opt;
+    {
+        std::string msg;
+        if (const int rc = check_options(opt, msg)) return fail(nullptr, rc, msg);
+    }
+    IntervalRows rows;
+    try {
+        const int rc = interval_rows(n, time, event, stratum, ncuts, cuts, tv_coef, p, rows);
+        if (rc != COX_OK) return fail(nullptr, rc, "bad cuts, or too many augmented rows or strata");
+    } catch (const std::bad_alloc &) {
+        return fail(nullptr, COX_ENOMEM, "host memory for the augmented rows");
+    }
+    const int64_t naug = (int64_t)rows.time.size(), paug = (int64_t)rows.col_source.size();
+    if (naug > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "more than 2^29 - 1 augmented rows");
+    if (paug > 4096) return fail(nullptr, COX_EUNSUPPORTED, "more than 4096 augmented columns");
+    cox_handle *h = new cox_handle();
+    h->n = naug;
+    h->p = paug;
+    h->opt = opt;
+    h->opt.penalize = nullptr;
+    h->stream = static_cast<hipStream_t>(opt.stream);
+    h->device = parent->device;
+    canonical_order(naug, rows.time.data(), rows.event.data(), rows.stratum.data(), h->perm, h->meta);
+    h->gamma.assign((size_t)paug, opt.gamma);
+    if (o) {
+        if (o->penalize)
+            for (int64_t c = 0; c < paug; ++c) h->gamma[(size_t)c] = o->penalize[c] ? opt.gamma : 0.0;
+    } else {
+        for (int64_t c = 0; c < paug; ++c) h->gamma[(size_t)c] = parent->gamma[(size_t)rows.col_source[(size_t)c]];
+    }
+    std::string err;
+    const int rc = layout_for(h, err);
+    if (rc != 0) {
+        delete h;
+        return fail(nullptr, rc, err);
+    }
+    const int64_t ld = h->shape.ld;
+    if (parent->shape.ld > (int64_t)INT32_MAX) {
+        delete h;
+        return fail(nullptr, COX_EUNSUPPORTED, "parent layout too long for 32-bit row indices");
+    }
+    // maps: [0, ld) source row, [ld, 2 ld) interval of each device row, then column source and interval
+    std::vector<int32_t> maps((size_t)(2 * ld + 2 * paug), -1);
+    {
+        std::vector<int64_t> canon_of((size_t)n);
+        for (int64_t c = 0; c < n; ++c) canon_of[(size_t)parent->perm[(size_t)c]] = c;
+        for (int64_t k = 0; k < naug; ++k) {
+            const int64_t a = h->perm[(size_t)k];
+            const int64_t r = h->pos[(size_t)k];
+            maps[(size_t)r] = (int32_t)parent->pos[(size_t)canon_of[(size_t)rows.row_subject[(size_t)a]]];
+            maps[(size_t)(ld + r)] = rows.row_interval[(size_t)a];
+        }
+        std::copy(rows.col_source.begin(), rows.col_source.end(), maps.begin() + 2 * ld);
+        std::copy(rows.col_interval.begin(), rows.col_interval.end(), maps.begin() + 2 * ld + paug);
+    }
+    hipError_t e = alloc_device(h);
+    int32_t *d_maps = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&d_maps, sizeof(int32_t) * maps.size());
+    if (e != hipSuccess) {
+        if (d_maps) (void)hipFree(d_maps);
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "device allocation");
+    }
+    e = upload_meta(h);
+    if (e == hipSuccess) e = hipMemcpy(d_maps, maps.data(), sizeof(int32_t) * maps.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = (hipError_t)launch_gather_rows(parent->d_x, parent->shape.ld, d_maps, d_maps + ld, d_maps + 2 * ld,
+                                           d_maps + 2 * ld + paug, h->d_x, ld, (int)paug, h->stream);
+    if (e == hipSuccess) e = (hipError_t)launch_event_sums(h->d_x, ld, h->d_meta, h->q(), (int)paug, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(d_maps);
+    if (e == hipSuccess) e = upload_tables(h);
+    if (e != hipSuccess) {
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "building the interval-stratified data set");
     }
     *out = h;
     return COX_OK;

@@ -67,8 +67,11 @@ int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream,
                hipEvent_t ev0, hipEvent_t ev1);
 
 // Resampled data sets (resample.hip); return hipError_t values.
-// x_out[j][r] = src[r] >= 0 ? x_in[j][src[r]] : 0 for r < ld_out (src: device, ld_out entries).
-int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, double *x_out, int64_t ld_out, int p,
+// x_out[j][r] = src[r] >= 0 ? x_in[col_src[j]][src[r]] : 0 for r < ld_out (device arrays: src
+// and rint ld_out entries, col_src and col_int p entries; col_src NULL = identity).  With
+// rint and col_int, column j is also zero where col_int[j] >= 0 and rint[r] != col_int[j].
+int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, const int32_t *rint,
+                       const int32_t *col_src, const int32_t *col_int, double *x_out, int64_t ld_out, int p,
                        hipStream_t stream);
 // q[j] = sum of x[j][r] over the rows whose word has the event bit (fixed-order sums).
 int launch_event_sums(const double *x, int64_t ld, const uint32_t *meta, double *q, int p, hipStream_t stream);

@@ -1,6 +1,7 @@
-// resample.hip -- device side of cox_init_resample: a resampled data set (row
-// multiplicities, e.g. the training rows of a cross-validation fold or a
-// bootstrap sample) is built from a handle's device-resident X by a gather,
+// resample.hip -- device side of cox_init_resample and cox_init_intervals: a
+// resampled data set (row multiplicities, e.g. the training rows of a
+// cross-validation fold or a bootstrap sample) or an interval-stratified one
+// (Secs. 2.2-2.3) is built from a handle's device-resident X by a gather,
 // without sending X over PCIe again.
 #include "internal.h"
 
@@ -12,30 +13,40 @@ constexpr int kGatherBlock = 256;
 constexpr int kGatherRows = 4;     // rows per thread
 constexpr int kGatherCols = 8;     // columns per workgroup (the source index is loaded once for them)
 
-// x_out[j][r] = src[r] >= 0 ? x_in[j][src[r]] : 0 for r < ld_out, j < p.
+// x_out[j][r] = src[r] >= 0 ? x_in[cs(j)][src[r]] : 0 for r < ld_out, j < p, where
+// cs(j) = col_src[j] (identity when col_src is null); with col_int and rint given, a
+// column with col_int[j] >= 0 is also zero on rows whose rint[r] differs (a step
+// coefficient's column outside its interval).
 // Grid: (ceil(ld_out / (kGatherBlock * kGatherRows)), ceil(p / kGatherCols)).
 __global__ __launch_bounds__(kGatherBlock) void gather_rows_kernel(const double *__restrict__ x_in, int64_t ld_in,
                                                                    const int32_t *__restrict__ src,
+                                                                   const int32_t *__restrict__ rint,
+                                                                   const int32_t *__restrict__ col_src,
+                                                                   const int32_t *__restrict__ col_int,
                                                                    double *__restrict__ x_out, int64_t ld_out, int p)
 {
     const int64_t r0 = (int64_t)blockIdx.x * (kGatherBlock * kGatherRows) + threadIdx.x;
     const int j0 = blockIdx.y * kGatherCols;
-    int32_t s[kGatherRows];
+    int32_t s[kGatherRows], ki[kGatherRows];
 #pragma unroll
     for (int k = 0; k < kGatherRows; ++k) {
         const int64_t r = r0 + (int64_t)k * kGatherBlock;
         s[k] = r < ld_out ? src[r] : -1;
+        ki[k] = (rint && r < ld_out) ? rint[r] : -1;
     }
 #pragma unroll
     for (int c = 0; c < kGatherCols; ++c) {
         const int j = j0 + c;
         if (j >= p) break;
-        const double *xi = x_in + (int64_t)j * ld_in;
+        const int js = col_src ? col_src[j] : j;
+        const int jk = col_int ? col_int[j] : -1;
+        const double *xi = x_in + (int64_t)js * ld_in;
         double *xo = x_out + (int64_t)j * ld_out;
 #pragma unroll
         for (int k = 0; k < kGatherRows; ++k) {
             const int64_t r = r0 + (int64_t)k * kGatherBlock;
-            if (r < ld_out) xo[r] = s[k] >= 0 ? xi[s[k]] : 0.0;
+            const bool live = s[k] >= 0 && (jk < 0 || jk == ki[k]);
+            if (r < ld_out) xo[r] = live ? xi[s[k]] : 0.0;
         }
     }
 }
@@ -66,13 +77,15 @@ __global__ __launch_bounds__(kQBlock) void event_sums_kernel(const double *__res
 
 }  // namespace
 
-int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, double *x_out, int64_t ld_out, int p,
+int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, const int32_t *rint,
+                       const int32_t *col_src, const int32_t *col_int, double *x_out, int64_t ld_out, int p,
                        hipStream_t stream)
 {
     if (ld_out <= 0 || p <= 0) return (int)hipSuccess;
     const int64_t per = (int64_t)kGatherBlock * kGatherRows;
     const dim3 grid((unsigned)((ld_out + per - 1) / per), (unsigned)((p + kGatherCols - 1) / kGatherCols));
-    hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(kGatherBlock), 0, stream, x_in, ld_in, src, x_out, ld_out, p);
+    hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(kGatherBlock), 0, stream, x_in, ld_in, src, rint, col_src,
+                       col_int, x_out, ld_out, p);
     return (int)hipGetLastError();
 }
 

@@ -98,3 +98,49 @@ def test_step_effect_l1_fit_matches_oracle():
     err = _rel(beta, ref.beta)
     _say(f"  iters={info['iters']} nonzero={int(np.count_nonzero(beta))} rel err {err:.3e}")
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("strata", [False, True])
+def test_device_mapping_matches_split(strata):
+    """cox_init_intervals (augmented X gathered on the device from the parent's columns) against
+    the host split: identical canonical layout, fits equal to the oracle's on its own split."""
+    d = synth.make("ar1", 20_000, 7, 12, 105, beta_sd=0.4, tie_round=50.0)
+    st = d.stratum if strata else None
+    cuts = [float(q) for q in np.quantile(d.time, [0.3, 0.6])]
+    tv = np.array([1, 0, 0, 1, 0, 0, 0], np.uint8)
+    r = orc.split_intervals(d.X, d.time, d.event, st, cuts, tv_coef=tv)
+    L = orc.canonical_layout(r["time"], r["event"], r["stratum"])
+    pa = r["X"].shape[1]
+    pen = np.ones(pa, np.uint8)
+    pen[r["col_source"] == 0] = 0
+    _say(f"device interval mapping strata={strata}: n_aug={r['X'].shape[0]} p_aug={pa}")
+    with coxmi.CoxModel(d.X, d.time, d.event, st) as m:
+        with m.intervals(d.time, d.event, st, cuts, tv, gamma=1.5, penalize=pen, tol=1e-13) as c:
+            perm, meta = c.layout()
+            np.testing.assert_array_equal(perm, L.perm)
+            np.testing.assert_array_equal(meta, L.meta)
+            beta, info = c.fit()
+            obj, _, _ = c.evaluate(beta)
+        with m.intervals(d.time, d.event, st, cuts, tv, mode=coxmi.COX_NEWTON_REFINE, tol=1e-13) as c:
+            bn, infon = c.fit()
+    ref = orc.fit_ccd(r["X"], r["time"], r["event"], r["stratum"], gamma=1.5, penalize=pen, tol=1e-13)
+    assert ref.converged and info["status"] == coxmi.COX_OK
+    assert np.array_equal(beta == 0.0, ref.beta == 0.0) and _rel(beta, ref.beta) <= 1e-10
+    refn = orc.fit_newton(r["X"], r["time"], r["event"], r["stratum"], tol=1e-14)
+    assert infon["status"] == coxmi.COX_OK and _rel(bn, refn.beta) <= 1e-10
+    _say(f"  ccd rel err {_rel(beta, ref.beta):.3e}, newton rel err {_rel(bn, refn.beta):.3e}")
+
+
+def test_device_mapping_errors():
+    d = synth.make("iid", 3000, 3, 3, 107)
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum) as m:
+        ev = d.event.copy()
+        ev[np.flatnonzero(ev)[0]] = 0
+        with pytest.raises(coxmi.CoxError) as e:
+            m.intervals(d.time, ev, d.stratum, [0.5])
+        assert e.value.code == coxmi.COX_EINVAL
+        with pytest.raises(coxmi.CoxError) as e:
+            m.intervals(d.time, d.event, d.stratum, [2.0, 1.0])
+        assert e.value.code == coxmi.COX_EINVAL
+        with pytest.raises(ValueError):
+            m.intervals(d.time, d.event, d.stratum, [0.5], tv_coef=np.ones(2, np.uint8))
