@@ -120,6 +120,10 @@ SIGNATURES = [
                                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.POINTER(cox_intervals))]),
     ("cox_intervals_release", None, [ctypes.POINTER(cox_intervals)]),
+    ("cox_init_indicator", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), _DP,
+                                          ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(cox_options)]),
     ("cox_init_resample", ctypes.c_int, [ctypes.POINTER(_VP), _VP, ctypes.POINTER(ctypes.c_uint32),
                                          ctypes.POINTER(cox_options)]),
     ("cox_init_intervals", ctypes.c_int, [ctypes.POINTER(_VP), _VP, _DP, ctypes.POINTER(ctypes.c_uint8),
@@ -233,6 +237,33 @@ def _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep):
     if stream is not None:
         o.stream = ctypes.c_void_p(int(stream))
     return o
+
+
+def cox_init_indicator(n, col_ptr, row_idx, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-12,
+                       max_iter=1000, stream=None):
+    """A handle on indicator X given as compressed sparse columns: column j holds 1 at rows
+    row_idx[col_ptr[j]:col_ptr[j + 1]] and 0 elsewhere (cox_init_indicator)."""
+    cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+    ri = np.ascontiguousarray(row_idx, dtype=np.int32)
+    p = cp.shape[0] - 1
+    time = np.ascontiguousarray(time, dtype=np.float64)
+    event = np.ascontiguousarray(event, dtype=np.uint8)
+    if time.shape != (n,) or event.shape != (n,):
+        raise ValueError(f"time and event need {n} entries")
+    keep = [cp, ri, time, event]
+    st = None
+    if stratum is not None:
+        st = np.ascontiguousarray(stratum, dtype=np.int32)
+        keep.append(st)
+    o = _options(gamma, penalize, tol, max_iter, stream, COX_CCD, COX_F64, keep)
+    h = ctypes.c_void_p()
+    rc = lib().cox_init_indicator(ctypes.byref(h), int(n), int(p), cp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  ri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(time),
+                                  event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                  None if st is None else st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                  ctypes.byref(o))
+    _check(None, rc)
+    return h.value
 
 
 def cox_init_resample(parent, count, *, inherit=True, gamma=0.0, penalize=None, tol=1e-12, max_iter=1000,
@@ -502,6 +533,13 @@ class CoxModel:
 
     def __init__(self, X, time, event, stratum=None, **opts):
         self.h = cox_init(X, time, event, stratum, **opts)
+
+    @classmethod
+    def indicator(cls, n, col_ptr, row_idx, time, event, stratum=None, **opts):
+        """A CoxModel on indicator X in compressed sparse columns (see cox_init_indicator)."""
+        m = cls.__new__(cls)
+        m.h = cox_init_indicator(n, col_ptr, row_idx, time, event, stratum, **opts)
+        return m
 
     def fit(self, beta0=None):
         return cox_fit(self.h, beta0)

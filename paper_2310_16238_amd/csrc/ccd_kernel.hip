@@ -35,6 +35,8 @@
 //     A risk-set sum outside [1e-300, 1e300] stops the fit with a flag.
 #include <math.h>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "segscan.hpp"
 
@@ -146,6 +148,34 @@ __device__ __forceinline__ void load_words(uint32_t (&v)[IPT], const uint32_t *p
         for (int i = 0; i < IPT; ++i) v[i] = p[i];
     }
 }
+
+// One column's values at a thread's IPT rows.  Dense: IPT doubles from the
+// column-major X.  Indicator (BITS): one bit per row, a thread's IPT bits in one
+// unit (uint8 for IPT <= 8, uint16 for 16) at xbits[j * ldb + thread]; the value is
+// 0.0 or 1.0, so every product formed with it equals the dense one exactly.
+template <int IPT, bool BITS>
+struct XCol;
+
+template <int IPT>
+struct XCol<IPT, false> {
+    double v[IPT];
+    __device__ __forceinline__ void load(const CcdLaunch &L, int64_t ld, int64_t j, int64_t row0, int64_t)
+    {
+        load_rows<IPT>(v, L.x + j * ld + row0);
+    }
+    __device__ __forceinline__ double operator[](int i) const { return v[i]; }
+};
+
+template <int IPT>
+struct XCol<IPT, true> {
+    using Unit = typename std::conditional<(IPT > 8), uint16_t, uint8_t>::type;
+    uint32_t bits;
+    __device__ __forceinline__ void load(const CcdLaunch &L, int64_t, int64_t j, int64_t, int64_t tg)
+    {
+        bits = static_cast<const Unit *>(L.xbits)[j * L.ldb + tg];
+    }
+    __device__ __forceinline__ double operator[](int i) const { return ((bits >> i) & 1u) ? 1.0 : 0.0; }
+};
 
 __device__ __forceinline__ Partial partial_identity()
 {
@@ -314,7 +344,7 @@ __device__ __forceinline__ bool gather_partials(const PacketArray &part, int G, 
 
 // ------------------------------------------------------------------ the persistent kernel
 
-template <int BLOCK, int IPT>
+template <int BLOCK, int IPT, bool BITS>
 __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 {
     constexpr int NW = BLOCK / kWave;
@@ -339,6 +369,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
     const int64_t ld = (int64_t)G * BLOCK * IPT;
     const int64_t tile0 = (int64_t)b * BLOCK * IPT;
     const int64_t row0 = tile0 + (int64_t)t * IPT;
+    const int64_t tg = (int64_t)b * BLOCK + t;      // the thread's unit in an indicator column
     const bool fit = (L.mode == kModeFit);
 
     double *sbeta = smem_dyn, *strust = smem_dyn + p, *sgamma = smem_dyn + 2 * p;
@@ -360,8 +391,8 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
     for (int j = 0; j < p; ++j) {
         const double bj = L.beta[j];
         if (bj != 0.0) {
-            double xv[IPT];
-            load_rows<IPT>(xv, L.x + (int64_t)j * ld + row0);
+            XCol<IPT, BITS> xv;
+            xv.load(L, ld, j, row0, tg);
 #pragma unroll
             for (int i = 0; i < IPT; ++i) eta[i] = fma(xv[i], bj, eta[i]);
         }
@@ -386,8 +417,8 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 
     const int jfirst = fit ? 0 : L.j0;
     const int jend = fit ? p : L.j1;
-    double xc[IPT];
-    load_rows<IPT>(xc, L.x + (int64_t)jfirst * ld + row0);
+    XCol<IPT, BITS> xc;
+    xc.load(L, ld, jfirst, row0, tg);
 
     // bookkeeping of workgroup 0, thread 0
     int sweeps = 0, pinned = 0, pinned_last = 0;
@@ -398,8 +429,8 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
         for (int j = jfirst; j < jend; ++j) {
             ++epoch;
             const int jn = (j + 1 < jend) ? j + 1 : jfirst;
-            double xn[IPT];
-            load_rows<IPT>(xn, L.x + (int64_t)jn * ld + row0);
+            XCol<IPT, BITS> xn;
+            xn.load(L, ld, jn, row0, tg);
             double qj = 0.0;
             if (t == 0) qj = L.q[j];
             const bool want_obj = (j == jfirst);
@@ -507,8 +538,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 #pragma unroll
                 for (int i = 0; i < IPT; ++i) eta[i] = fma(xc[i], step, eta[i]);
             }
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) xc[i] = xn[i];
+            xc = xn;
             if (flags & (kFlagConverged | kFlagSweepLimit)) {
                 stop = flags;
                 break;
@@ -592,7 +622,7 @@ constexpr int kCcdBlock = kThreads;
 template <int IPT>
 int occupancy_ccd(int p, int *blocks)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, ccd_kernel<kCcdBlock, IPT>, kCcdBlock,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, ccd_kernel<kCcdBlock, IPT, false>, kCcdBlock,
                                                         sizeof(double) * 3 * (size_t)p);
 }
 
@@ -645,12 +675,18 @@ int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream,
     void *args[] = {&arg};
     const size_t smem = sizeof(double) * 3 * (size_t)L.p;
     const void *fn = nullptr;
+    const bool bits = L.xbits != nullptr;
     switch (shape.ipt) {
-    case 1: fn = reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 1>); break;
-    case 2: fn = reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 2>); break;
-    case 4: fn = reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 4>); break;
-    case 8: fn = reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 8>); break;
-    case 16: fn = reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 16>); break;
+    case 1: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 1, true>)
+                      : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 1, false>); break;
+    case 2: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 2, true>)
+                      : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 2, false>); break;
+    case 4: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 4, true>)
+                      : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 4, false>); break;
+    case 8: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 8, true>)
+                      : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 8, false>); break;
+    case 16: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 16, true>)
+                       : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 16, false>); break;
     default: return (int)hipErrorInvalidValue;
     }
     e = hipLaunchCooperativeKernel(fn, dim3(shape.grid), dim3(kCcdBlock), args, (unsigned)smem, stream);

@@ -59,6 +59,8 @@ static void free_device(cox_handle *h)
 {
     newton_free(h);
     if (h->d_x) (void)hipFree(h->d_x);
+    if (h->d_xbits) (void)hipFree(h->d_xbits);
+    h->d_xbits = nullptr;
     if (h->d_meta) (void)hipFree(h->d_meta);
     if (h->d_vec) (void)hipFree(h->d_vec);
     if (h->d_sync) (void)hipFree(h->d_sync);
@@ -147,12 +149,16 @@ static void tile_layout(const std::vector<uint32_t> &meta, LaunchShape &shape, s
     shape.ld = (int64_t)shape.grid * kNewtonTile;
 }
 
-// Device buffers of a handle whose layout (shape, pos) is set.
+// Bytes of one thread's unit of an indicator column (ipt bits).
+static size_t indicator_unit(int ipt) { return ipt > 8 ? 2 : 1; }
+
+// Device buffers of a handle whose layout (shape, pos) is set; dense X unless ldb != 0.
 static hipError_t alloc_device(cox_handle *h)
 {
     const int64_t ld = h->shape.ld, p = h->p;
     hipError_t e;
-    if ((e = hipMalloc(&h->d_x, sizeof(double) * (size_t)ld * p)) != hipSuccess ||
+    if ((h->ldb == 0 && (e = hipMalloc(&h->d_x, sizeof(double) * (size_t)ld * p)) != hipSuccess) ||
+        (h->ldb != 0 && (e = hipMalloc(&h->d_xbits, indicator_unit(h->shape.ipt) * (size_t)h->ldb * p)) != hipSuccess) ||
         (e = hipMalloc(&h->d_meta, sizeof(uint32_t) * (size_t)ld)) != hipSuccess ||
         (e = hipMalloc(&h->d_vec, sizeof(double) * (size_t)(6 * p + kResultSlots + 64))) != hipSuccess ||
         (e = hipMalloc(&h->d_sync, sync_scratch_bytes(h->shape.ipt ? h->shape.grid : 1))) != hipSuccess)
@@ -290,6 +296,99 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     return COX_OK;
 }
 
+extern "C" int cox_init_indicator(cox_handle **out, int64_t n, int64_t p, const int64_t *col_ptr,
+                                  const int32_t *row_idx, const double *time, const uint8_t *event,
+                                  const int32_t *stratum, const cox_options *o)
+{
+    if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || p < 1) return fail(nullptr, COX_EINVAL, "need n >= 1 and p >= 1");
+    if (n > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "n exceeds 2^29 - 1");
+    if (p > 4096) return fail(nullptr, COX_EUNSUPPORTED, "p > 4096 is not supported by the resident kernel");
+    if (!col_ptr || !time || !event) return fail(nullptr, COX_EINVAL, "col_ptr, time and event are required");
+    if (col_ptr[0] != 0) return fail(nullptr, COX_EINVAL, "col_ptr[0] must be 0");
+    for (int64_t j = 0; j < p; ++j)
+        if (col_ptr[j + 1] < col_ptr[j]) return fail(nullptr, COX_EINVAL, "col_ptr must be non-decreasing");
+    const int64_t nnz = col_ptr[p];
+    if (nnz > 0 && !row_idx) return fail(nullptr, COX_EINVAL, "row_idx is required");
+    for (int64_t k = 0; k < nnz; ++k)
+        if (row_idx[k] < 0 || row_idx[k] >= n) return fail(nullptr, COX_EINVAL, "row index out of range");
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(time[i]) || event[i] > 1) return fail(nullptr, COX_EINVAL, "time must be finite, event 0 or 1");
+    cox_options opt;
+    if (o) opt = *o;
+    else cox_default_options(&opt);
+    {
+        std::string msg;
+        if (const int rc = check_options(opt, msg)) return fail(nullptr, rc, msg);
+    }
+    if (opt.mode != COX_CCD || opt.x_precision != COX_F64)
+        return fail(nullptr, COX_EUNSUPPORTED, "indicator X runs COX_CCD fits in COX_F64");
+    cox_handle *h = new cox_handle();
+    h->n = n;
+    h->p = p;
+    h->opt = opt;
+    h->opt.penalize = nullptr;
+    h->stream = static_cast<hipStream_t>(opt.stream);
+    (void)hipGetDevice(&h->device);
+    canonical_order(n, time, event, stratum, h->perm, h->meta);
+    h->gamma.assign((size_t)p, opt.gamma);
+    if (o && o->penalize)
+        for (int64_t j = 0; j < p; ++j) h->gamma[(size_t)j] = o->penalize[j] ? opt.gamma : 0.0;
+    std::string err;
+    const int rc = layout_for(h, err);
+    if (rc != 0) {
+        delete h;
+        return fail(nullptr, rc, err);
+    }
+    const int ipt = h->shape.ipt;
+    h->ldb = h->shape.ld / ipt;    // one unit per thread
+    // bits at the layout positions: row r of the device layout is bit r % ipt of unit r / ipt
+    std::vector<int64_t> dev_row((size_t)n);
+    for (int64_t c = 0; c < n; ++c) dev_row[(size_t)h->perm[(size_t)c]] = h->pos[(size_t)c];
+    const size_t unit = indicator_unit(ipt);
+    std::vector<uint8_t> bits(unit * (size_t)h->ldb * (size_t)p, 0);
+    std::vector<double> q((size_t)p, 0.0);
+    for (int64_t j = 0; j < p; ++j) {
+        double qj = 0.0;
+        for (int64_t k = col_ptr[j]; k < col_ptr[j + 1]; ++k) {
+            const int64_t i = row_idx[k];
+            const int64_t r = dev_row[(size_t)i];
+            const size_t u = (size_t)(j * h->ldb + r / ipt);
+            const uint32_t bit = 1u << (r % ipt);
+            if (unit == 1) {
+                if (bits[u] & bit) continue;    // a repeated index sets the same entry once
+                bits[u] = (uint8_t)(bits[u] | bit);
+            } else {
+                uint16_t w;
+                std::memcpy(&w, &bits[2 * u], 2);
+                if (w & bit) continue;
+                w = (uint16_t)(w | bit);
+                std::memcpy(&bits[2 * u], &w, 2);
+            }
+            if (event[i]) qj += 1.0;
+        }
+        q[(size_t)j] = qj;
+    }
+    hipError_t e = alloc_device(h);
+    if (e != hipSuccess) {
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "device allocation");
+    }
+    e = upload_meta(h);
+    if (e == hipSuccess) e = hipMemcpy(h->d_xbits, bits.data(), bits.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->q(), q.data(), sizeof(double) * p, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = upload_tables(h);
+    if (e != hipSuccess) {
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "device upload");
+    }
+    *out = h;
+    return COX_OK;
+}
+
 // Canonical rows of the data set in which original row i appears count[i] times
 // (copies numbered consecutively, original rows in order), derived from the
 // parent's canonical order without sorting: copies of one row are adjacent and
@@ -340,6 +439,7 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
     *out = nullptr;
     if (!parent || !count) return fail(nullptr, COX_EINVAL, "parent and count are required");
+    if (!parent->d_x) return fail(nullptr, COX_EUNSUPPORTED, "the parent holds indicator X");
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != parent->device) return fail(nullptr, COX_EINVAL, "the parent handle lives on another device");
@@ -418,6 +518,7 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
     *out = nullptr;
     if (!parent) return fail(nullptr, COX_EINVAL, "parent is NULL");
+    if (!parent->d_x) return fail(nullptr, COX_EUNSUPPORTED, "the parent holds indicator X");
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != parent->device) return fail(nullptr, COX_EINVAL, "the parent handle lives on another device");
@@ -543,6 +644,8 @@ static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *bet
     if (e != hipSuccess) return hip_fail(h, e, "staging beta");
     CcdLaunch L;
     L.x = h->d_x;
+    L.xbits = h->d_xbits;
+    L.ldb = h->ldb;
     L.meta = h->d_meta;
     L.q = h->q();
     L.gamma = h->gam();

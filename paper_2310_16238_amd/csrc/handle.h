@@ -48,7 +48,9 @@ struct cox_handle {
     int device = 0;
     coxmi::LaunchShape shape;
     hipStream_t stream = nullptr;
-    double *d_x = nullptr;
+    double *d_x = nullptr;         // dense X [p][ld]; NULL for a handle on indicator X
+    void *d_xbits = nullptr;       // indicator X: [p][ldb] units of ipt bits (uint8, uint16 for ipt 16)
+    int64_t ldb = 0;
     uint32_t *d_meta = nullptr;
     double *d_vec = nullptr;       // q, gamma, beta, g1, g2, m2 (p each), result (8), exp table (64)
     void *d_sync = nullptr;

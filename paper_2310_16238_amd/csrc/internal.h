@@ -33,7 +33,9 @@ int max_resident_groups(int ipt, int p, int *groups, std::string &err);
 
 // Arguments of one persistent launch (device pointers unless noted).
 struct CcdLaunch {
-    const double *x = nullptr;       // [p][ld] canonical rows, padding rows zero
+    const double *x = nullptr;       // [p][ld] canonical rows, padding rows zero (dense X)
+    const void *xbits = nullptr;     // indicator X instead: [p][ldb] units of IPT bits (uint8, uint16 for IPT 16)
+    int64_t ldb = 0;                 // units per indicator column (grid * threads)
     const uint32_t *meta = nullptr;  // [ld]
     const double *q = nullptr;       // [p] delta' X_j
     const double *gamma = nullptr;   // [p] l1 weights

@@ -37,6 +37,10 @@ size_t ztype_bytes(int prec) { return lowp(prec) ? 2 : 8; }
 
 int newton_setup(cox_handle *h)
 {
+    if (!h->d_x)
+        return handle_fail(h, COX_EUNSUPPORTED,
+                           "a handle on indicator X runs the CCD path only (cox_fit in COX_CCD mode, cox_evaluate, "
+                           "cox_coordinate)");
     NewtonState &s = h->nt;
     if (s.ready) return COX_OK;
     const int64_t ld = h->shape.ld, n = h->n;

@@ -1,0 +1,95 @@
+"""Indicator X (one bit per row; Secs. 3.1-3.2 use 3-5% dense indicators) on the GPU.
+
+With x in {0, 1} every product the CCD kernel forms equals the dense one exactly, so a
+handle built from compressed sparse columns must give the same bits as a handle on the
+same X stored dense (fits, evaluations, coordinates), and both meet the oracle at the
+FP64 fit tolerance (max|gpu - oracle| / max|oracle| <= 1e-10, zero pattern exact).
+"""
+import numpy as np
+import pytest
+
+from oracle import cox_oracle as orc
+from paper_2310_16238_amd import coxmi, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    coxmi.lib()
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(1e-300, np.max(np.abs(b))))
+
+
+def _csc(X):
+    cols = [np.flatnonzero(X[:, j]) for j in range(X.shape[1])]
+    ptr = np.zeros(X.shape[1] + 1, np.int64)
+    ptr[1:] = np.cumsum([c.size for c in cols])
+    return ptr, np.concatenate(cols).astype(np.int32)
+
+
+@pytest.mark.parametrize("n,p,K,gamma", [(5000, 12, 1, 1.0), (150_000, 40, 7500, 2.0), (600_000, 30, 1, 0.0),
+                                         (1_200_000, 20, 60_000, 5.0)])
+def test_indicator_equals_dense(n, p, K, gamma):
+    d = synth.make("binary", n, p, K, 200 + K, beta_sd=1.0, beta_nonzero=0.3, density=0.05, tie_round=100.0)
+    d.X[:, 3] = 0.0                       # an empty column (pinned at zero)
+    ptr, idx = _csc(d.X)
+    _say(f"indicator vs dense n={n} p={p} K={K} gamma={gamma} nnz={idx.size}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, gamma=gamma, tol=1e-13) as md, \
+            coxmi.CoxModel.indicator(n, ptr, idx, d.time, d.event, d.stratum, gamma=gamma, tol=1e-13) as mb:
+        assert np.array_equal(md.layout()[0], mb.layout()[0])
+        bd, infod = md.fit()
+        bb, infob = mb.fit()
+        assert np.array_equal(bd, bb) and infod["iters"] == infob["iters"]
+        probe = np.random.default_rng(1).normal(0, 0.2, p)
+        od, gd, hd = md.evaluate(probe)
+        ob, gb, hb = mb.evaluate(probe)
+        assert od == ob and np.array_equal(gd, gb) and np.array_equal(hd, hb)
+        assert np.array_equal(md.coordinate(probe, 5), mb.coordinate(probe, 5))
+    if n <= 150_000:
+        ref = orc.fit_ccd(d.X, d.time, d.event, d.stratum, gamma=gamma, tol=1e-13)
+        assert ref.converged and np.array_equal(bb == 0.0, ref.beta == 0.0)
+        err = _rel(bb, ref.beta)
+        _say(f"  sweeps={infob['iters']} rel err vs oracle {err:.3e}")
+        assert err <= 1e-10
+
+
+def test_indicator_repeated_indices_and_errors():
+    d = synth.make("binary", 4000, 5, 2, 211, density=0.1)
+    ptr, idx = _csc(d.X)
+    # every index listed twice, columns in scrambled order: the same matrix
+    ptr2 = ptr * 2
+    idx2 = np.concatenate([np.random.default_rng(0).permutation(np.repeat(idx[ptr[j]:ptr[j + 1]], 2))
+                           for j in range(5)]).astype(np.int32)
+    with coxmi.CoxModel.indicator(4000, ptr, idx, d.time, d.event, d.stratum, gamma=1.0) as a, \
+            coxmi.CoxModel.indicator(4000, ptr2, idx2, d.time, d.event, d.stratum, gamma=1.0) as b:
+        ba, _ = a.fit()
+        bb, _ = b.fit()
+        assert np.array_equal(ba, bb)
+        with pytest.raises(coxmi.CoxError) as e:
+            a.evaluate_full(np.zeros(5))
+        assert e.value.code == coxmi.COX_EUNSUPPORTED
+        with pytest.raises(coxmi.CoxError) as e:
+            a.resample(np.ones(4000, np.uint32))
+        assert e.value.code == coxmi.COX_EUNSUPPORTED
+    bad = idx.copy()
+    bad[0] = 4000
+    with pytest.raises(coxmi.CoxError) as e:
+        coxmi.CoxModel.indicator(4000, ptr, bad, d.time, d.event, d.stratum)
+    assert e.value.code == coxmi.COX_EINVAL
+    ptr_bad = ptr.copy()
+    ptr_bad[2] = ptr_bad[1] - 1
+    with pytest.raises(coxmi.CoxError) as e:
+        coxmi.CoxModel.indicator(4000, ptr_bad, idx, d.time, d.event, d.stratum)
+    assert e.value.code == coxmi.COX_EINVAL
