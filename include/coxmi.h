@@ -99,7 +99,8 @@ void cox_default_options(cox_options *o);
  *   d   : data; all pointers host memory, read only during the call
  *   o   : options (NULL = defaults); penalize is copied
  * Errors: COX_EINVAL (n < 1, p < 1, ldx < n, NULL x/time/event, non-finite
- * time, event not 0/1), COX_EUNSUPPORTED (p > 4096; in mode COX_CCD, n
+ * time, event not 0/1), COX_EUNSUPPORTED (p > 12288, or p > 4096 in mode
+ * COX_NEWTON_REFINE -- cox_evaluate_full also needs p <= 4096; in mode COX_CCD, n
  * beyond the persistent kernel's register-resident capacity of about
  * CUs x 512 x 16 rows -- a COX_NEWTON_REFINE handle of that size is created,
  * and then supports cox_fit and cox_evaluate_full only; mode COX_NEWTON_REFINE
@@ -234,7 +235,7 @@ void cox_intervals_release(cox_intervals *s);
  * persistent CCD kernel reads a thread's rows of x_j from one byte.  With x in {0, 1}
  * every product the kernel forms is exact, so fits equal those on the same X stored
  * dense, bit for bit.
- *   n, p     : rows and columns (1 <= n <= 2^29 - 1, 1 <= p <= 4096)
+ *   n, p     : rows and columns (1 <= n <= 2^29 - 1, 1 <= p <= 12288)
  *   col_ptr  : host, p + 1 non-decreasing offsets into row_idx, col_ptr[0] = 0
  *   row_idx  : host, col_ptr[p] row indices in [0, n) (order free; repeats count once)
  *   time, event, stratum : as in cox_data
@@ -285,7 +286,8 @@ int cox_init_resample(cox_handle **out, const cox_handle *parent, const uint32_t
  *                      NULL = the parent's options, each augmented column taking its
  *                      source column's l1 weight
  * Errors: COX_EINVAL (NULL pointer, bad cuts, data that do not match the parent),
- * COX_EUNSUPPORTED (more than 2^29 - 1 rows or 4096 columns after the split),
+ * COX_EUNSUPPORTED (more than 2^29 - 1 rows, or more than 12288 columns after the split
+ * (4096 for COX_NEWTON_REFINE)),
  * COX_ENOMEM, COX_EDEVICE; message via cox_last_error(NULL). */
 int cox_init_intervals(cox_handle **out, const cox_handle *parent, const double *time, const uint8_t *event,
                        const int32_t *stratum, int ncuts, const double *cuts, const uint8_t *tv_coef,

@@ -349,7 +349,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 {
     constexpr int NW = BLOCK / kWave;
     static_assert(BLOCK % kWave == 0 && NW <= 16, "block shape");
-    extern __shared__ double smem_dyn[];     // beta, trust, gamma (the same in every workgroup)
+    extern __shared__ double smem_dyn[];     // beta (the same in every workgroup)
     __shared__ SegVal<3> s_wtot[NW];
     __shared__ Partial s_red[NW];        // this workgroup's own reduction
     __shared__ Partial s_gat[NW];        // the gathered records
@@ -372,11 +372,11 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
     const int64_t tg = (int64_t)b * BLOCK + t;      // the thread's unit in an indicator column
     const bool fit = (L.mode == kModeFit);
 
-    double *sbeta = smem_dyn, *strust = smem_dyn + p, *sgamma = smem_dyn + 2 * p;
+    double *sbeta = smem_dyn;
+    double *trust = L.trust + (int64_t)b * p;      // this workgroup's copy of the trust half-widths
     for (int j = t; j < p; j += BLOCK) {
         sbeta[j] = L.beta[j];
-        strust[j] = 1.0;
-        sgamma[j] = L.gamma[j];
+        trust[j] = 1.0;
     }
     if (t == 0) s_abort = 0;
     if (t < 64) s_exptab[t] = L.exp_tab[t];
@@ -431,8 +431,6 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             const int jn = (j + 1 < jend) ? j + 1 : jfirst;
             XCol<IPT, BITS> xn;
             xn.load(L, ld, jn, row0, tg);
-            double qj = 0.0;
-            if (t == 0) qj = L.q[j];
             const bool want_obj = (j == jfirst);
 
             // pass 1: D, N1, N2 of the thread's rows and their fold
@@ -487,6 +485,13 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             const bool extra = want_obj || !fit;
             if (t == 0) publish_partial(part, G, b, v, epoch, extra);
 
+            // the step's per-column inputs: issued here, they arrive while the records are gathered
+            double qj = 0.0, gj = 0.0, trj = 0.0;
+            if (t == 0) {
+                qj = L.q[j];
+                gj = L.gamma[j];
+                trj = trust[j];
+            }
             Partial tot;
             if (!gather_partials<NW>(part, G, epoch, extra, ctl, s_gat, &s_abort, tot)) return;
             if (t == 0) {
@@ -500,12 +505,13 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
                 if (want_obj) {
                     objective = tot.v[kPObj];
                     if (fit)
-                        for (int k = 0; k < p; ++k) objective += sgamma[k] * fabs(sbeta[k]);
+                        for (int k = 0; k < p; ++k) objective += L.gamma[k] * fabs(sbeta[k]);
                 }
                 double step = 0.0;
                 if (fit && !(flags & kFlagNumeric)) {
                     int pin = 0;
-                    step = ccd_step(sbeta[j], g1, g2, m2, sgamma[j], &strust[j], &pin);
+                    step = ccd_step(sbeta[j], g1, g2, m2, gj, &trj, &pin);
+                    trust[j] = trj;
                     sbeta[j] += step;
                     maxstep = fmax(maxstep, fabs(step));
                     pinned += pin;
@@ -623,7 +629,7 @@ template <int IPT>
 int occupancy_ccd(int p, int *blocks)
 {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, ccd_kernel<kCcdBlock, IPT, false>, kCcdBlock,
-                                                        sizeof(double) * 3 * (size_t)p);
+                                                        sizeof(double) * (size_t)p);
 }
 
 int occupancy_for(int ipt, int p, int *blocks)
@@ -673,7 +679,7 @@ int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream,
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return (int)e;
     CcdLaunch arg = L;
     void *args[] = {&arg};
-    const size_t smem = sizeof(double) * 3 * (size_t)L.p;
+    const size_t smem = sizeof(double) * (size_t)L.p;
     const void *fn = nullptr;
     const bool bits = L.xbits != nullptr;
     switch (shape.ipt) {

@@ -60,7 +60,9 @@ static void free_device(cox_handle *h)
     newton_free(h);
     if (h->d_x) (void)hipFree(h->d_x);
     if (h->d_xbits) (void)hipFree(h->d_xbits);
+    if (h->d_trust) (void)hipFree(h->d_trust);
     h->d_xbits = nullptr;
+    h->d_trust = nullptr;
     if (h->d_meta) (void)hipFree(h->d_meta);
     if (h->d_vec) (void)hipFree(h->d_vec);
     if (h->d_sync) (void)hipFree(h->d_sync);
@@ -161,7 +163,8 @@ static hipError_t alloc_device(cox_handle *h)
         (h->ldb != 0 && (e = hipMalloc(&h->d_xbits, indicator_unit(h->shape.ipt) * (size_t)h->ldb * p)) != hipSuccess) ||
         (e = hipMalloc(&h->d_meta, sizeof(uint32_t) * (size_t)ld)) != hipSuccess ||
         (e = hipMalloc(&h->d_vec, sizeof(double) * (size_t)(6 * p + kResultSlots + 64))) != hipSuccess ||
-        (e = hipMalloc(&h->d_sync, sync_scratch_bytes(h->shape.ipt ? h->shape.grid : 1))) != hipSuccess)
+        (e = hipMalloc(&h->d_sync, sync_scratch_bytes(h->shape.ipt ? h->shape.grid : 1))) != hipSuccess ||
+        (h->shape.ipt && (e = hipMalloc(&h->d_trust, sizeof(double) * (size_t)h->shape.grid * p)) != hipSuccess))
         return e;
     return hipSuccess;
 }
@@ -232,7 +235,6 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     const int64_t n = d->n, p = d->p;
     if (n > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "n exceeds 2^29 - 1");
     if (const char *bad = check_data(n, p, d->ldx, d->x, d->time, d->event)) return fail(nullptr, COX_EINVAL, bad);
-    if (p > 4096) return fail(nullptr, COX_EUNSUPPORTED, "p > 4096 is not supported by the resident kernel");
     cox_options opt;
     if (o) opt = *o;
     else cox_default_options(&opt);
@@ -240,6 +242,8 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
         std::string msg;
         if (const int rc = check_options(opt, msg)) return fail(nullptr, rc, msg);
     }
+    if (p > kMaxCcdP || (opt.mode == COX_NEWTON_REFINE && p > kMaxNewtonP))
+        return fail(nullptr, COX_EUNSUPPORTED, "p exceeds 12288 (COX_CCD) or 4096 (COX_NEWTON_REFINE)");
 
     cox_handle *h = new cox_handle();
     h->n = n;
@@ -304,7 +308,7 @@ extern "C" int cox_init_indicator(cox_handle **out, int64_t n, int64_t p, const 
     *out = nullptr;
     if (n < 1 || p < 1) return fail(nullptr, COX_EINVAL, "need n >= 1 and p >= 1");
     if (n > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "n exceeds 2^29 - 1");
-    if (p > 4096) return fail(nullptr, COX_EUNSUPPORTED, "p > 4096 is not supported by the resident kernel");
+    if (p > kMaxCcdP) return fail(nullptr, COX_EUNSUPPORTED, "p > 12288 is not supported by the resident kernel");
     if (!col_ptr || !time || !event) return fail(nullptr, COX_EINVAL, "col_ptr, time and event are required");
     if (col_ptr[0] != 0) return fail(nullptr, COX_EINVAL, "col_ptr[0] must be 0");
     for (int64_t j = 0; j < p; ++j)
@@ -545,7 +549,8 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
     }
     const int64_t naug = (int64_t)rows.time.size(), paug = (int64_t)rows.col_source.size();
     if (naug > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "more than 2^29 - 1 augmented rows");
-    if (paug > 4096) return fail(nullptr, COX_EUNSUPPORTED, "more than 4096 augmented columns");
+    if (paug > kMaxCcdP || (opt.mode == COX_NEWTON_REFINE && paug > kMaxNewtonP))
+        return fail(nullptr, COX_EUNSUPPORTED, "too many augmented columns (12288 for COX_CCD, 4096 for Newton)");
     cox_handle *h = new cox_handle();
     h->n = naug;
     h->p = paug;
@@ -649,6 +654,7 @@ static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *bet
     L.meta = h->d_meta;
     L.q = h->q();
     L.gamma = h->gam();
+    L.trust = h->d_trust;
     L.exp_tab = h->exp_tab();
     L.n = h->n;
     L.p = (int)h->p;

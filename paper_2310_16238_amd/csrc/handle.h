@@ -54,6 +54,7 @@ struct cox_handle {
     uint32_t *d_meta = nullptr;
     double *d_vec = nullptr;       // q, gamma, beta, g1, g2, m2 (p each), result (8), exp table (64)
     void *d_sync = nullptr;
+    double *d_trust = nullptr;     // [grid][p] trust half-widths of the persistent kernel
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     float last_kernel_ms = 0.0f;
     cox_profile prof{};

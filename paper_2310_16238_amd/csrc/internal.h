@@ -16,6 +16,8 @@ constexpr uint32_t kCountMask = 0x1fffffffu;
 
 constexpr int kThreads = 512;           // threads per workgroup of the CCD kernel
 constexpr int kMaxGroups = 256;         // workgroups of one persistent launch (one per compute unit)
+constexpr int64_t kMaxCcdP = 12288;     // columns of the persistent kernel (beta in LDS: 96 KB)
+constexpr int64_t kMaxNewtonP = 4096;   // columns of the Newton / full-evaluation path
 
 enum KernelMode { kModeFit = 0, kModeEval = 1 };
 
@@ -39,6 +41,7 @@ struct CcdLaunch {
     const uint32_t *meta = nullptr;  // [ld]
     const double *q = nullptr;       // [p] delta' X_j
     const double *gamma = nullptr;   // [p] l1 weights
+    double *trust = nullptr;         // [grid][p] trust half-widths, one copy per workgroup
     const double *exp_tab = nullptr; // [64] 2^(j/64)
     int64_t n = 0;                   // real rows (rows n..ld-1 are padding)
     int p = 0;

@@ -37,6 +37,8 @@ size_t ztype_bytes(int prec) { return lowp(prec) ? 2 : 8; }
 
 int newton_setup(cox_handle *h)
 {
+    if (h->p > kMaxNewtonP)
+        return handle_fail(h, COX_EUNSUPPORTED, "the full evaluation and Newton fits support p <= 4096");
     if (!h->d_x)
         return handle_fail(h, COX_EUNSUPPORTED,
                            "a handle on indicator X runs the CCD path only (cox_fit in COX_CCD mode, cox_evaluate, "
