@@ -280,3 +280,47 @@ def config_legend(n: int = 946_911, p: int = 1000, K: int = 10, seed: int = 7) -
     propensity-score strata); column 0 plays the unpenalised treatment covariate."""
     return make("binary", n, p, K, seed, beta_kind="normal", beta_sd=0.5, beta_nonzero=0.2, density=0.03,
              gamma=math.sqrt(2.0), name=f"legend-n{n}-p{p}-K{K}")
+
+
+@dataclasses.dataclass
+class SparseCoxData:
+    """Indicator design in compressed sparse columns: column j is 1 at rows
+    row_idx[col_ptr[j]:col_ptr[j + 1]] (ascending) and 0 elsewhere."""
+    n: int
+    col_ptr: np.ndarray    # (p + 1,) int64
+    row_idx: np.ndarray    # (nnz,) int32
+    time: np.ndarray
+    event: np.ndarray
+    stratum: np.ndarray
+    beta_true: np.ndarray
+    gamma: float
+    name: str
+
+
+def config_legend_sparse(n: int = 946_911, p: int = 9977, K: int = 10, density: float = 0.03,
+                         seed: int = 9) -> SparseCoxData:
+    """Sec. 3.2 at its full width: p indicator covariates with `density` ones (97% sparse),
+    drawn column by column as the gaps between ones (geometric with success probability
+    `density`), coefficients N(0, 0.25) x Bernoulli(0.2) with column 0 (the treatment) at
+    log 0.8; K equal strata; the response model of make()."""
+    rng = np.random.default_rng(seed)
+    cols = []
+    for _ in range(p):
+        gaps = rng.geometric(density, size=int(n * density * 1.2) + 64)
+        pos = np.cumsum(gaps) - 1
+        while pos[-1] < n - 1:       # rare: draw more gaps
+            more = np.cumsum(rng.geometric(density, size=int(n * density * 0.2) + 64)) + pos[-1]
+            pos = np.concatenate([pos, more])
+        cols.append(pos[pos < n].astype(np.int32))
+    col_ptr = np.zeros(p + 1, dtype=np.int64)
+    col_ptr[1:] = np.cumsum([c.size for c in cols])
+    row_idx = np.concatenate(cols)
+    b = rng.normal(0.0, 0.5, size=p) * (rng.random(p) < 0.2)
+    b[0] = math.log(0.8)
+    eta = np.zeros(n)
+    for j in np.flatnonzero(b):
+        eta[cols[j]] += b[j]
+    stratum, lam = _strata(rng, n, K)
+    Y, event = _times(rng, eta, lam[stratum], 0.0)
+    return SparseCoxData(n=n, col_ptr=col_ptr, row_idx=row_idx, time=Y, event=event, stratum=stratum,
+                         beta_true=b, gamma=math.sqrt(2.0), name=f"legend-sparse-n{n}-p{p}-K{K}")
