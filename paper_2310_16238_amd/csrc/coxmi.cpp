@@ -20,6 +20,7 @@
 #include "handle.h"
 #include "internal.h"
 #include "intervals.h"
+#include "resample.h"
 
 using namespace coxmi;
 
@@ -443,7 +444,6 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
     *out = nullptr;
     if (!parent || !count) return fail(nullptr, COX_EINVAL, "parent and count are required");
-    if (!parent->d_x) return fail(nullptr, COX_EUNSUPPORTED, "the parent holds indicator X");
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != parent->device) return fail(nullptr, COX_EINVAL, "the parent handle lives on another device");
@@ -458,6 +458,8 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
         std::string msg;
         if (const int rc = check_options(opt, msg)) return fail(nullptr, rc, msg);
     }
+    if (!parent->d_x && (opt.mode != COX_CCD || opt.x_precision != COX_F64))
+        return fail(nullptr, COX_EUNSUPPORTED, "indicator X runs COX_CCD fits in COX_F64");
     cox_handle *h = new cox_handle();
     h->n = (int64_t)total;
     h->p = parent->p;
@@ -485,6 +487,13 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
         delete h;
         return fail(nullptr, COX_EUNSUPPORTED, "parent layout too long for 32-bit row indices");
     }
+    if (!parent->d_x) {
+        if (h->shape.ipt == 0) {
+            delete h;
+            return fail(nullptr, COX_EUNSUPPORTED, "indicator X needs the persistent kernel's layout");
+        }
+        h->ldb = ld / h->shape.ipt;
+    }
     // device row of the child -> device row of the parent (-1: padding)
     std::vector<int32_t> src((size_t)ld, -1);
     for (int64_t k = 0; k < h->n; ++k) src[(size_t)h->pos[(size_t)k]] = (int32_t)parent->pos[(size_t)from[(size_t)k]];
@@ -499,10 +508,17 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
     }
     e = upload_meta(h);
     if (e == hipSuccess) e = hipMemcpy(d_src, src.data(), sizeof(int32_t) * (size_t)ld, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
+    if (e == hipSuccess && parent->d_x) {
         e = (hipError_t)launch_gather_rows(parent->d_x, parent->shape.ld, d_src, nullptr, nullptr, nullptr, h->d_x, ld,
                                            (int)h->p, h->stream);
-    if (e == hipSuccess) e = (hipError_t)launch_event_sums(h->d_x, ld, h->d_meta, h->q(), (int)h->p, h->stream);
+        if (e == hipSuccess) e = (hipError_t)launch_event_sums(h->d_x, ld, h->d_meta, h->q(), (int)h->p, h->stream);
+    } else if (e == hipSuccess) {
+        e = (hipError_t)launch_gather_bits(parent->d_xbits, parent->ldb, parent->shape.ipt, d_src, h->d_xbits, h->ldb,
+                                           h->shape.ipt, (int)h->p, h->stream);
+        if (e == hipSuccess)
+            e = (hipError_t)launch_event_sums_bits(h->d_xbits, h->ldb, h->shape.ipt, h->d_meta, h->q(), (int)h->p,
+                                                   h->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     (void)hipFree(d_src);
     if (e == hipSuccess) e = upload_tables(h);

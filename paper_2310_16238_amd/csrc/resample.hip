@@ -4,6 +4,7 @@
 // (Secs. 2.2-2.3) is built from a handle's device-resident X by a gather,
 // without sending X over PCIe again.
 #include "internal.h"
+#include "resample.h"
 
 namespace coxmi {
 
@@ -75,6 +76,55 @@ __global__ __launch_bounds__(kQBlock) void event_sums_kernel(const double *__res
     if (threadIdx.x == 0) q[j] = s[0];
 }
 
+// Indicator columns: child unit u of column j (ipt_out bits, unit of us_out bytes) takes
+// bit i from the parent's row src[u * ipt_out + i] (bit (s % ipt_in) of the parent's unit
+// s / ipt_in, units of us_in bytes, little-endian).  Grid: (ceil(ldb_out / 256), p).
+__global__ __launch_bounds__(256) void gather_bits_kernel(const uint8_t *__restrict__ b_in, int64_t ldb_in, int ipt_in,
+                                                          int us_in, const int32_t *__restrict__ src,
+                                                          uint8_t *__restrict__ b_out, int64_t ldb_out, int ipt_out,
+                                                          int us_out)
+{
+    const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (u >= ldb_out) return;
+    const int64_t j = blockIdx.y;
+    uint32_t v = 0u;
+    for (int i = 0; i < ipt_out; ++i) {
+        const int32_t s = src[u * ipt_out + i];
+        if (s < 0) continue;
+        const int bit = s % ipt_in;
+        const uint8_t byte = b_in[(j * ldb_in + s / ipt_in) * us_in + bit / 8];
+        v |= (uint32_t)((byte >> (bit % 8)) & 1u) << i;
+    }
+    uint8_t *o = b_out + (j * ldb_out + u) * us_out;
+    o[0] = (uint8_t)(v & 0xffu);
+    if (us_out == 2) o[1] = (uint8_t)(v >> 8);
+}
+
+// q[j] = number of rows with the event bit whose indicator bit is set (fixed-order sums).
+__global__ __launch_bounds__(kQBlock) void event_sums_bits_kernel(const uint8_t *__restrict__ bits, int64_t ldb,
+                                                                  int ipt, int us, const uint32_t *__restrict__ meta,
+                                                                  double *__restrict__ q)
+{
+    __shared__ double s[kQBlock];
+    const int64_t j = blockIdx.x;
+    const int64_t ld = ldb * ipt;
+    double acc = 0.0;
+    for (int64_t r = threadIdx.x; r < ld; r += kQBlock) {
+        if (!(meta[r] & kEventBit)) continue;
+        const int bit = (int)(r % ipt);
+        const uint8_t byte = bits[(j * ldb + r / ipt) * us + bit / 8];
+        if ((byte >> (bit % 8)) & 1u) acc += 1.0;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int w = kQBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) q[j] = s[0];
+}
+
 }  // namespace
 
 int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, const int32_t *rint,
@@ -86,6 +136,26 @@ int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, co
     const dim3 grid((unsigned)((ld_out + per - 1) / per), (unsigned)((p + kGatherCols - 1) / kGatherCols));
     hipLaunchKernelGGL(gather_rows_kernel, grid, dim3(kGatherBlock), 0, stream, x_in, ld_in, src, rint, col_src,
                        col_int, x_out, ld_out, p);
+    return (int)hipGetLastError();
+}
+
+int launch_gather_bits(const void *b_in, int64_t ldb_in, int ipt_in, const int32_t *src, void *b_out, int64_t ldb_out,
+                       int ipt_out, int p, hipStream_t stream)
+{
+    if (ldb_out <= 0 || p <= 0) return (int)hipSuccess;
+    const dim3 grid((unsigned)((ldb_out + 255) / 256), (unsigned)p);
+    hipLaunchKernelGGL(gather_bits_kernel, grid, dim3(256), 0, stream, static_cast<const uint8_t *>(b_in), ldb_in,
+                       ipt_in, ipt_in > 8 ? 2 : 1, src, static_cast<uint8_t *>(b_out), ldb_out, ipt_out,
+                       ipt_out > 8 ? 2 : 1);
+    return (int)hipGetLastError();
+}
+
+int launch_event_sums_bits(const void *bits, int64_t ldb, int ipt, const uint32_t *meta, double *q, int p,
+                           hipStream_t stream)
+{
+    if (p <= 0) return (int)hipSuccess;
+    hipLaunchKernelGGL(event_sums_bits_kernel, dim3((unsigned)p), dim3(kQBlock), 0, stream,
+                       static_cast<const uint8_t *>(bits), ldb, ipt, ipt > 8 ? 2 : 1, meta, q);
     return (int)hipGetLastError();
 }
 

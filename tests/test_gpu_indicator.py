@@ -81,7 +81,7 @@ def test_indicator_repeated_indices_and_errors():
             a.evaluate_full(np.zeros(5))
         assert e.value.code == coxmi.COX_EUNSUPPORTED
         with pytest.raises(coxmi.CoxError) as e:
-            a.resample(np.ones(4000, np.uint32))
+            a.intervals(d.time, d.event, d.stratum, [0.5])
         assert e.value.code == coxmi.COX_EUNSUPPORTED
     bad = idx.copy()
     bad[0] = 4000
@@ -121,3 +121,36 @@ def test_wide_indicator_beyond_4096_columns():
         worst = max(worst, r / E)
     _say(f"  sweeps={infob['iters']} nonzero={nz.size} l1 optimality residual / E = {worst:.2e}")
     assert worst <= 1e-10
+
+
+@pytest.mark.parametrize("n,K", [(20_000, 40), (1_100_000, 11)])
+def test_indicator_resample_cv_bootstrap_equal_dense(n, K):
+    """Resampled handles of an indicator parent (bits gathered on the device) give the same bits
+    as those of a dense parent: a fold fit, the cross-validated likelihood and bootstrap refits;
+    n = 1.1e6 takes 16 rows per thread in the parent and 8 in a fold."""
+    p = 12
+    d = synth.make("binary", n, p, K, 215 + K, beta_sd=1.0, beta_nonzero=0.4, density=0.05, tie_round=100.0)
+    ptr, idx = _csc(d.X)
+    rng = np.random.default_rng(5)
+    fold = rng.integers(0, 4, n).astype(np.int32)
+    counts = np.stack([rng.multinomial(n, np.full(n, 1.0 / n)) for _ in range(2)]).astype(np.uint32)
+    gammas = [50.0, 10.0, 2.0]
+    _say(f"indicator resampling n={n} K={K}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, gamma=3.0, tol=1e-12) as md, \
+            coxmi.CoxModel.indicator(n, ptr, idx, d.time, d.event, d.stratum, gamma=3.0, tol=1e-12) as mb:
+        keep = (fold != 1).astype(np.uint32)
+        with md.resample(keep) as cd, mb.resample(keep) as cb:
+            assert np.array_equal(cd.layout()[1], cb.layout()[1])
+            bd, _ = cd.fit()
+            bb, _ = cb.fit()
+            assert np.array_equal(bd, bb)
+        cvd, betd, _ = md.cross_validate(fold, gammas)
+        cvb, betb, _ = mb.cross_validate(fold, gammas)
+        assert np.array_equal(cvd, cvb) and np.array_equal(betd, betb)
+        btd, _ = md.bootstrap(counts)
+        btb, _ = mb.bootstrap(counts)
+        assert np.array_equal(btd, btb)
+    if n <= 20_000:
+        Xr, tr, er, sr = orc.resample(d.X, d.time, d.event, d.stratum, keep)
+        ref = orc.fit_ccd(Xr, tr, er, sr, gamma=3.0, tol=1e-12)
+        assert np.array_equal(bb == 0.0, ref.beta == 0.0) and _rel(bb, ref.beta) <= 1e-10
