@@ -240,9 +240,10 @@ void cox_intervals_release(cox_intervals *s);
  *   row_idx  : host, col_ptr[p] row indices in [0, n) (order free; repeats count once)
  *   time, event, stratum : as in cox_data
  *   o        : options (mode COX_CCD, x_precision COX_F64; NULL = defaults)
- * The handle runs cox_fit (COX_CCD), cox_evaluate, cox_coordinate, cox_set_penalty and
- * the bookkeeping calls; cox_evaluate_full, Newton fits and resampling return
- * COX_EUNSUPPORTED.  Errors: COX_EINVAL (bad arrays), COX_EUNSUPPORTED (sizes, options,
+ * The handle runs cox_fit (COX_CCD), cox_evaluate, cox_coordinate, cox_set_penalty,
+ * cox_init_resample (the bits are gathered on the device), cox_cross_validate,
+ * cox_bootstrap and the bookkeeping calls; cox_evaluate_full, Newton fits and
+ * cox_init_intervals return COX_EUNSUPPORTED.  Errors: COX_EINVAL (bad arrays), COX_EUNSUPPORTED (sizes, options,
  * n beyond the resident kernel), COX_ENOMEM, COX_EDEVICE. */
 int cox_init_indicator(cox_handle **out, int64_t n, int64_t p, const int64_t *col_ptr, const int32_t *row_idx,
                        const double *time, const uint8_t *event, const int32_t *stratum, const cox_options *o);
