@@ -344,6 +344,15 @@ typedef struct {
 
 int cox_last_profile(const cox_handle *h, cox_profile *out);
 
+/* Breslow estimate of the cumulative baseline hazard at beta (the step function whose
+ * jump at an event time of stratum k is d / sum_{r in R_k} exp(x_r'beta), the sums of
+ * Eq. strat_l): cumhaz[i] = Lambda_0k(Y_i) for original row i in stratum k, the jumps
+ * of its stratum at times <= Y_i.  From one full evaluation (the reverse scan Lambda of
+ * the score X'(w Lambda - delta), with exp(X beta) taken relative to the running maximum
+ * within the stratum and scaled back).  beta: host p; cumhaz: host n.  Needs dense X and
+ * p <= 4096 (else COX_EUNSUPPORTED); COX_ENUMERIC as for cox_evaluate_full. */
+int cox_baseline_hazard(cox_handle *h, const double *beta, double *cumhaz);
+
 /* Number of rows and columns of the handle; the device row stride (>= n). */
 int cox_shape(const cox_handle *h, int64_t *n, int64_t *p, int64_t *ld);
 

@@ -548,3 +548,25 @@ def percentile_interval(values, level=0.95):
     empirical quantiles, numpy's default (linear) interpolation."""
     v = np.asarray(values, dtype=np.float64)
     return np.quantile(v, (1.0 - level) / 2.0, axis=0), np.quantile(v, (1.0 + level) / 2.0, axis=0)
+
+
+# ============================================================== Breslow baseline hazard
+
+def baseline_hazard_brute(X, time, event, stratum, beta) -> np.ndarray:
+    """Breslow cumulative baseline hazard at each row's own time, by definition: for row i in
+    stratum k, the sum over the distinct event times t <= Y_i of stratum k of
+    d(t) / sum_{r in k, Y_r >= t} exp(x_r'beta), d(t) the events at t (the denominators are
+    the risk-set sums of Eq. strat_l)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(time, dtype=np.float64)
+    ev = np.asarray(event).astype(bool)
+    n = Y.shape[0]
+    st = np.zeros(n, dtype=np.int64) if stratum is None else np.asarray(stratum)
+    w = np.exp(X @ np.asarray(beta, dtype=np.float64))
+    out = np.zeros(n)
+    for i in range(n):
+        same = st == st[i]
+        for t in np.unique(Y[same & ev & (Y <= Y[i])]):
+            d = np.count_nonzero(same & ev & (Y == t))
+            out[i] += d / w[same & (Y >= t)].sum()
+    return out

@@ -120,6 +120,7 @@ SIGNATURES = [
                                            ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.POINTER(cox_intervals))]),
     ("cox_intervals_release", None, [ctypes.POINTER(cox_intervals)]),
+    ("cox_baseline_hazard", ctypes.c_int, [_VP, _DP, _DP]),
     ("cox_init_indicator", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int64, ctypes.c_int64,
                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), _DP,
                                           ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
@@ -237,6 +238,15 @@ def _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep):
     if stream is not None:
         o.stream = ctypes.c_void_p(int(stream))
     return o
+
+
+def cox_baseline_hazard(h, beta):
+    """Breslow cumulative baseline hazard at each row's time, in its stratum (cox_baseline_hazard)."""
+    n, _, _ = cox_shape(h)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    out = np.zeros(n)
+    _check(h, lib().cox_baseline_hazard(h, _dptr(b), _dptr(out)))
+    return out
 
 
 def cox_init_indicator(n, col_ptr, row_idx, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-12,
@@ -567,6 +577,9 @@ class CoxModel:
         m = CoxModel.__new__(CoxModel)
         m.h = cox_init_intervals(self.h, time, event, stratum, cuts, tv_coef, inherit=not opts, **opts)
         return m
+
+    def baseline_hazard(self, beta):
+        return cox_baseline_hazard(self.h, beta)
 
     def set_penalty(self, gamma, penalize=None):
         cox_set_penalty(self.h, gamma, penalize)

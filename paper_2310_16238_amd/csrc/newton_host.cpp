@@ -316,6 +316,30 @@ extern "C" int cox_evaluate_full(cox_handle *h, const double *beta, double *obje
     return COX_OK;
 }
 
+extern "C" int cox_baseline_hazard(cox_handle *h, const double *beta, double *cumhaz)
+{
+    if (!h) return handle_fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (!beta || !cumhaz) return handle_fail(h, COX_EINVAL, "beta and cumhaz are required");
+    (void)hipSetDevice(h->device);
+    int rc = newton_setup(h);
+    if (rc != COX_OK) return rc;
+    EvalOut ev;
+    rc = newton_eval(h, beta, false, ev);
+    if (rc != COX_OK) return rc;
+    // R_r = Lambda_r exp(m_r) (the reverse scan of the evaluation), m_r the running maximum of X beta
+    const int64_t ld = h->shape.ld;
+    std::vector<double> R((size_t)ld), m((size_t)ld);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(R.data(), nrow(h->nt, ld, 4), sizeof(double) * ld, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(m.data(), nrow(h->nt, ld, 8), sizeof(double) * ld, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return handle_hip_fail(h, e, "reading the cumulative hazard");
+    for (int64_t c = 0; c < h->n; ++c) {
+        const int64_t r = h->pos[(size_t)c];
+        cumhaz[h->perm[(size_t)c]] = R[(size_t)r] * std::exp(-m[(size_t)r]);
+    }
+    return COX_OK;
+}
+
 int newton_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *info)
 {
     (void)hipSetDevice(h->device);

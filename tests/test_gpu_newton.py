@@ -316,3 +316,33 @@ def test_full_evaluation_extreme_linear_predictor():
         _check_first_order(d, obj, g, hd, fe)
         lim = 1e-11 if prec == coxmi.COX_F64 else 3.5 * U_BF16 + 64 * 2.0 ** -24
         assert np.all(np.abs(info - fe.info) <= lim * _scale(fe) + 1e-300)
+
+
+@pytest.mark.parametrize("n,K,ties", [(3000, 1, False), (4000, 40, True)])
+def test_baseline_hazard_matches_oracle(n, K, ties):
+    """Breslow cumulative baseline hazard from the full evaluation against the oracle's
+    definition (FP64 on both sides: 1e-12 relative, row by row)."""
+    d = synth.make("iid", n, 4, K, 41 + K, beta_sd=0.5, tie_round=50.0 if ties else 0.0)
+    beta = np.array([0.4, -0.3, 0.2, 0.1])
+    _say(f"baseline hazard n={n} K={K} ties={ties}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum) as m:
+        lam = m.baseline_hazard(beta)
+    ref = orc.baseline_hazard_brute(d.X, d.time, d.event, d.stratum, beta)
+    np.testing.assert_allclose(lam, ref, rtol=1e-12, atol=0)
+
+
+def test_baseline_hazard_large_identities():
+    """At N = 1e6 with 5e4 strata: martingale residuals sum to zero in every stratum, and
+    X'(exp(X beta) Lambda_0 - delta) equals the score of cox_evaluate_full."""
+    d = synth.config_ar1()
+    beta = np.random.default_rng(2).normal(0, 0.1, d.X.shape[1])
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE) as m:
+        lam = m.baseline_hazard(beta)
+        _, g, _, _ = m.evaluate_full(beta, want_info=False)
+    w = np.exp(d.X @ beta)
+    res = d.event - w * lam
+    per = np.bincount(d.stratum, weights=res)
+    E = float(d.event.sum())
+    assert np.max(np.abs(per)) <= 1e-10
+    score = d.X.T @ (w * lam - d.event)
+    assert np.max(np.abs(score - g)) <= 1e-10 * E
