@@ -103,8 +103,8 @@ void cox_default_options(cox_options *o);
  * COX_NEWTON_REFINE -- cox_evaluate_full also needs p <= 4096; in mode COX_CCD, n
  * beyond the persistent kernel's register-resident capacity of about
  * CUs x 512 x 16 rows -- a COX_NEWTON_REFINE handle of that size is created,
- * and then supports cox_fit and cox_evaluate_full only; mode COX_NEWTON_REFINE
- * with gamma != 0; an x_precision other than COX_F64 / COX_BF16),
+ * and then supports cox_fit and cox_evaluate_full only; an x_precision other
+ * than COX_F64 / COX_BF16),
  * COX_ENOMEM, COX_EDEVICE.  On error *out is NULL and the
  * message is available through cox_last_error(NULL).
  */
@@ -121,12 +121,17 @@ int cox_init(cox_handle **out, const cox_data *d, const cox_options *o);
  *   beta_out : host, p entries, receives the estimate
  *   info     : host, optional (may be NULL)
  * Degenerate columns (g'' <= 1e-12 * delta'(S[N2]/S[D])) are not moved.
- * With mode COX_NEWTON_REFINE (gamma must be 0, else COX_EUNSUPPORTED): Newton steps
- * beta -= I^{-1} grad with I from cox_evaluate_full's contraction in
- * x_precision, factored by an FP64 Cholesky on the device; once a step is
- * below 1e-3 * max(1, max|beta|) the factor is kept and only the FP64
- * gradient is recomputed (iterative refinement), until the step is below
- * tol * max(1, max|beta|).  A step that raises the objective is halved.
+ * With mode COX_NEWTON_REFINE: Newton steps beta -= I^{-1} grad with I from
+ * cox_evaluate_full's contraction in x_precision, factored by an FP64 Cholesky
+ * on the device; once a step is below 1e-3 * max(1, max|beta|) the factor is
+ * kept and only the FP64 gradient is recomputed (iterative refinement), until
+ * the step is below tol * max(1, max|beta|).  A step that raises the objective
+ * is halved.  With l1 weights (gamma != 0) the steps are proximal Newton steps:
+ * the quadratic model g'D + D'ID/2 plus the l1 term is minimised by coordinate
+ * descent with soft thresholding on the host (I copied from the device), and the
+ * penalised objective decides the halving; the fixed point meets the l1
+ * optimality conditions on the FP64 score, so a reduced-precision I (kept once
+ * steps are small) still gives the FP64 optimum.
  * Returns COX_OK, COX_NOT_CONVERGED (max_iter sweeps done; beta_out filled),
  * COX_ENUMERIC (an event's risk-set sum under- or overflowed FP64 after the
  * global shift of X beta), COX_EDEVICE.

@@ -206,10 +206,6 @@ static int check_options(const cox_options &opt, std::string &msg)
         msg = "COX_FP8_E4M3 applies to COX_NEWTON_REFINE fits";
         return COX_EUNSUPPORTED;
     }
-    if (opt.mode == COX_NEWTON_REFINE && opt.gamma != 0.0) {
-        msg = "COX_NEWTON_REFINE fits the unpenalised model (gamma = 0)";
-        return COX_EUNSUPPORTED;
-    }
     if (opt.ties != COX_BRESLOW) { msg = "only COX_BRESLOW ties"; return COX_EUNSUPPORTED; }
     if (!(opt.gamma >= 0.0) || !std::isfinite(opt.gamma)) { msg = "gamma must be finite and >= 0"; return COX_EINVAL; }
     if (!(opt.tol >= 0.0)) { msg = "tol must be >= 0"; return COX_EINVAL; }
@@ -638,8 +634,6 @@ extern "C" int cox_set_penalty(cox_handle *h, double gamma, const uint8_t *penal
 {
     if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
     if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(h, COX_EINVAL, "gamma must be finite and >= 0");
-    if (h->opt.mode == COX_NEWTON_REFINE && gamma != 0.0)
-        return fail(h, COX_EUNSUPPORTED, "COX_NEWTON_REFINE fits the unpenalised model (gamma = 0)");
     std::vector<double> g((size_t)h->p, gamma);
     if (penalize)
         for (int64_t j = 0; j < h->p; ++j) g[(size_t)j] = penalize[j] ? gamma : 0.0;

@@ -340,8 +340,148 @@ extern "C" int cox_baseline_hazard(cox_handle *h, const double *beta, double *cu
     return COX_OK;
 }
 
+// Proximal Newton for the l1-penalised fit: each step minimises the quadratic model
+//   g'D + D'HD/2 + sum_j gamma_j |beta_j + D_j|
+// (FP64 score g, information H in x_precision) by cyclic coordinate descent with soft
+// thresholding on the host; a step that raises the penalised objective is halved.  A fixed
+// point (D = 0) satisfies the l1 optimality conditions on the FP64 score whatever the
+// precision of H, so a reduced-precision H, kept once steps are small, still reaches the
+// FP64 optimum.
+static int newton_fit_l1(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *info)
+{
+    NewtonState &s = h->nt;
+    const int p = (int)h->p;
+    const std::vector<double> &gam = h->gamma;
+    std::vector<double> beta(p, 0.0), prev(p, 0.0), D(p, 0.0), HD(p, 0.0), H((size_t)p * p, 0.0);
+    if (beta0) std::memcpy(beta.data(), beta0, sizeof(double) * p);
+    std::vector<uint8_t> freec(p, 1);
+    bool frozen = false, have_free = false, have_h = false, converged = false;
+    double obj_prev = INFINITY, last_step = 0.0, objective = 0.0;
+    int iters = 0, evals = 0, halvings = 0;
+    auto penalty = [&](const std::vector<double> &b) {
+        double v = 0.0;
+        for (int j = 0; j < p; ++j) v += gam[j] * std::fabs(b[j]);
+        return v;
+    };
+    EvalOut ev;
+    while (iters < h->opt.max_iter) {
+        int rc = newton_eval(h, beta.data(), !frozen || !have_free, ev);
+        ++evals;
+        if (rc != COX_OK) return rc;
+        if (!have_free) {
+            bool moved = false;
+            for (int j = 0; j < p; ++j) {
+                const double hd = ev.diag1[j] - ev.diag2[j];
+                freec[j] = (hd > 1e-12 * std::fabs(ev.diag1[j]) && std::isfinite(hd)) ? 1 : 0;
+                if (!freec[j] && beta[j] != 0.0) {
+                    beta[j] = 0.0;
+                    moved = true;
+                }
+            }
+            have_free = true;
+            if (moved) continue;   // re-evaluate at the start point with the pinned columns at zero
+        }
+        const double F = ev.objective + penalty(beta);
+        if (F > obj_prev + 1e-12 * std::fabs(obj_prev) && halvings < 40) {
+            for (int j = 0; j < p; ++j) beta[j] = prev[j] + 0.5 * (beta[j] - prev[j]);
+            ++halvings;
+            continue;
+        }
+        halvings = 0;
+        objective = F;
+        if (!frozen || !have_h) {
+            rc = newton_info(h);
+            if (rc != COX_OK) return rc;
+            hipError_t e = hipStreamSynchronize(h->stream);
+            if (e == hipSuccess) e = hipMemcpy(H.data(), s.info, sizeof(double) * H.size(), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return handle_hip_fail(h, e, "information matrix");
+            h->prof.contractions += 1;
+            h->prof.contraction_ms += elapsed_ms(s.ev[2], s.ev[3]);
+            have_h = true;
+        }
+        // coordinate descent on the model; HD = H D is kept up to date
+        std::fill(D.begin(), D.end(), 0.0);
+        std::fill(HD.begin(), HD.end(), 0.0);
+        double bmax = 1.0;
+        for (int j = 0; j < p; ++j) bmax = std::max(bmax, std::fabs(beta[j]));
+        for (int sweep = 0; sweep < 1000; ++sweep) {
+            double change = 0.0;
+            for (int j = 0; j < p; ++j) {
+                if (!freec[j]) continue;
+                const double a = H[(size_t)j * p + j];
+                if (!(a > 0.0)) continue;
+                const double b = ev.grad[j] + HD[j] - a * D[j];      // model slope at D with D_j removed
+                const double u = a * beta[j] - b;
+                const double z = u > gam[j] ? (u - gam[j]) / a : (u < -gam[j] ? (u + gam[j]) / a : 0.0);
+                const double dn = z - beta[j];
+                const double delta = dn - D[j];
+                if (delta != 0.0) {
+                    D[j] = dn;
+                    const double *col = H.data() + (size_t)j * p;   // symmetric: row j = column j
+                    for (int k = 0; k < p; ++k) HD[k] += col[k] * delta;
+                    change = std::max(change, std::fabs(delta));
+                }
+            }
+            if (change <= 1e-3 * h->opt.tol * bmax) break;
+        }
+        prev = beta;
+        obj_prev = F;
+        double step = 0.0;
+        for (int j = 0; j < p; ++j) {
+            const double nb = beta[j] + D[j];   // exactly 0 where the model's soft threshold gave 0
+            beta[j] = nb == 0.0 ? 0.0 : nb;
+            step = std::max(step, std::fabs(D[j]));
+        }
+        bmax = 1.0;
+        for (int j = 0; j < p; ++j) bmax = std::max(bmax, std::fabs(beta[j]));
+        ++iters;
+        last_step = step;
+        if (step <= h->opt.tol * bmax) {
+            converged = true;
+            break;
+        }
+        if (!frozen && h->opt.x_precision != COX_F64 && step <= 1e-3 * bmax) frozen = true;
+    }
+    std::memcpy(beta_out, beta.data(), sizeof(double) * p);
+    const int rc = converged ? COX_OK : COX_NOT_CONVERGED;
+    if (info) {
+        info->status = rc;
+        info->iters = iters;
+        info->coord_evals = evals;
+        info->objective = objective;
+        info->last_step = last_step;
+        int pinned = 0;
+        double kkt = 0.0;
+        for (int j = 0; j < p; ++j) {
+            if (!freec[j]) {
+                ++pinned;
+                continue;
+            }
+            const double g = ev.grad[j], b = beta_out[j];
+            const double r = gam[j] <= 0.0 ? std::fabs(g)
+                                           : (b != 0.0 ? std::fabs(g + (b > 0 ? gam[j] : -gam[j]))
+                                                       : std::max(std::fabs(g) - gam[j], 0.0));
+            kkt = std::max(kkt, r);
+        }
+        info->n_pinned = pinned;
+        info->kkt_inf = kkt;
+    }
+    return rc;
+}
+
 int newton_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *info)
 {
+    {
+        bool penalised = false;
+        for (double g : h->gamma) penalised = penalised || g != 0.0;
+        if (penalised) {
+            (void)hipSetDevice(h->device);
+            const int rc0 = newton_setup(h);
+            if (rc0 != COX_OK) return rc0;
+            h->prof = cox_profile{};
+            return newton_fit_l1(h, beta0, beta_out, info);
+        }
+    }
     (void)hipSetDevice(h->device);
     int rc = newton_setup(h);
     if (rc != COX_OK) return rc;
