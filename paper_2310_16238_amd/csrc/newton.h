@@ -9,6 +9,9 @@
 
 namespace coxmi {
 
+// Columns of the FP8 contraction (its tiles of one workgroup hold all p rows).
+constexpr int64_t kMaxFp8P = 800;
+
 // ------------------------------------------------------------------ full evaluation (newton.hip)
 
 enum ZType { kZF64 = 0, kZF32 = 1, kZBF16 = 2 };

@@ -211,6 +211,10 @@ def test_newton_fit_mixed_precision_full_size():
 
 def test_newton_options_rejected():
     d = synth.config_small(n=500, K=1)
+    wide = np.random.default_rng(0).normal(size=(500, 801))
+    with pytest.raises(coxmi.CoxError) as e:
+        coxmi.cox_init(wide, d.time, d.event, mode=coxmi.COX_NEWTON_REFINE, x_precision=coxmi.COX_FP8_E4M3)
+    assert e.value.code == coxmi.COX_EUNSUPPORTED
     for prec in (coxmi.COX_F32, coxmi.COX_FP8_E4M3):
         with pytest.raises(coxmi.CoxError) as e:
             coxmi.cox_init(d.X, d.time, d.event, x_precision=prec)
