@@ -578,6 +578,142 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_lds_kernel(const 
     }
 }
 
+// Wide X (more than kLdsMaxTiles row tiles): the tile pairs are cut into blocks of
+// kBlkTiles x kBlkTiles pairs (row block I, column block J >= I), and a workgroup stages
+// only the 2 kBlkTiles row tiles its block touches (kBlkTiles on the diagonal), so the
+// LDS holds 8 tiles x 32 rows x (KC + 8) BF16, twice with weights: 139 KB at KC = 128.
+// Waves take kBlkPairsPerWave pairs of the block; same partial layout as the kernels above.
+constexpr int kBlkTiles = 4;
+constexpr int kBlkPairsPerWave = kBlkTiles * kBlkTiles / kSyrkBfWaves;   // 4
+
+__host__ __device__ __forceinline__ int pair_index(int ti, int tj, int nt)
+{
+    return ti * nt - ti * (ti - 1) / 2 + (tj - ti);   // row-major upper triangle, ti <= tj
+}
+
+template <bool WEIGHT, int KC>
+__global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_blk_kernel(const uint16_t *u, int64_t ldu, int p,
+                                                                          const double *c, int64_t K, int64_t kchunk,
+                                                                          float *part)
+{
+    constexpr int kStride = KC + 8, kPieces = KC / 8;
+    constexpr int kRows = 2 * kBlkTiles * kMT;                                // staged rows (off-diagonal block)
+    constexpr int kPerThread = kRows * kPieces / (64 * kSyrkBfWaves);      // 16 at KC = 128
+    extern __shared__ uint16_t sh[];   // [kRows][kStride] plain, then weighted (WEIGHT)
+    __shared__ float cw[KC];
+    uint16_t *plain = sh;
+    uint16_t *wtd = sh + (size_t)kRows * kStride;
+    const int nt = (p + kMT - 1) / kMT;
+    const int nb = (nt + kBlkTiles - 1) / kBlkTiles;
+    const int npairs = nt * (nt + 1) / 2;
+    int I, J;
+    tile_pair(blockIdx.y, nb, I, J);
+    const bool diag = I == J;
+    const int nst = diag ? kBlkTiles : 2 * kBlkTiles;     // staged tiles
+    const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+    const int s = blockIdx.x;
+    const int64_t k0 = (int64_t)s * kchunk;
+    const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+    // this wave's pairs: local tiles (la, lb) of the staged rows, global pair index, valid flag
+    int la[kBlkPairsPerWave], lb[kBlkPairsPerWave], gp[kBlkPairsPerWave];
+    bool ok[kBlkPairsPerWave];
+    f32x16 acc[kBlkPairsPerWave];
+#pragma unroll
+    for (int q = 0; q < kBlkPairsPerWave; ++q) {
+        const int idx = w * kBlkPairsPerWave + q;
+        int a, b;
+        if (diag) {
+            tile_pair(idx < kBlkTiles * (kBlkTiles + 1) / 2 ? idx : 0, kBlkTiles, a, b);
+            ok[q] = idx < kBlkTiles * (kBlkTiles + 1) / 2;
+            la[q] = a;
+            lb[q] = b;
+        } else {
+            a = idx / kBlkTiles;
+            b = idx % kBlkTiles;
+            ok[q] = true;
+            la[q] = a;
+            lb[q] = kBlkTiles + b;
+        }
+        const int ti = I * kBlkTiles + a, tj = J * kBlkTiles + b;
+        ok[q] = ok[q] && ti < nt && tj < nt;
+        gp[q] = ok[q] ? pair_index(ti, tj, nt) : 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[q][i] = 0.0f;
+    }
+    const int rsub = lane & 31, ksub = 8 * (lane >> 5);
+    const int npieces = nst * kMT * kPieces;
+    u32x4v reg[kPerThread];
+    float creg = 0.0f;
+    auto global_row = [&](int lr) {
+        const int lt = lr / kMT;
+        const int gt = lt < kBlkTiles ? I * kBlkTiles + lt : J * kBlkTiles + (lt - kBlkTiles);
+        return gt * kMT + lr % kMT;
+    };
+    auto load_chunk = [&](int64_t kc) {
+#pragma unroll
+        for (int m = 0; m < kPerThread; ++m) {
+            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            const int lr = e / kPieces, piece = e % kPieces;
+            u32x4v v = {0u, 0u, 0u, 0u};
+            if (e < npieces) {
+                const int r = global_row(lr);
+                if (r < p) v = *reinterpret_cast<const u32x4v *>(u + (int64_t)r * ldu + kc + 8 * piece);
+            }
+            reg[m] = v;
+        }
+        if (WEIGHT && threadIdx.x < KC) creg = (float)c[kc + threadIdx.x];
+    };
+    if (k0 < k1) load_chunk(k0);
+    for (int64_t kc = k0; kc < k1; kc += KC) {
+        if (WEIGHT && threadIdx.x < KC) cw[threadIdx.x] = creg;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kPerThread; ++m) {
+            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            if (e < npieces) {
+                const int lr = e / kPieces, piece = e % kPieces;
+                *reinterpret_cast<u32x4v *>(plain + lr * kStride + 8 * piece) = reg[m];
+                if (WEIGHT) {
+                    const bf16x8 x = __builtin_bit_cast(bf16x8, reg[m]);
+                    bf16x8 y;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) y[i] = (__bf16)((float)x[i] * cw[8 * piece + i]);
+                    *reinterpret_cast<u32x4v *>(wtd + lr * kStride + 8 * piece) = __builtin_bit_cast(u32x4v, y);
+                }
+            }
+        }
+        __syncthreads();
+        if (kc + KC < k1) load_chunk(kc + KC);   // in flight during the MFMAs below
+        const uint16_t *asrc = WEIGHT ? wtd : plain;
+#pragma unroll
+        for (int sub = 0; sub < KC / 16; ++sub) {
+            const int kk = 16 * sub + ksub;
+#pragma unroll
+            for (int q = 0; q < kBlkPairsPerWave; ++q) {
+                if (ok[q]) {
+                    const bf16x8 a = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const u32x4v *>(asrc + (la[q] * kMT + rsub) * kStride + kk));
+                    const bf16x8 b = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const u32x4v *>(plain + (lb[q] * kMT + rsub) * kStride + kk));
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();   // the next chunk rewrites the LDS tiles
+    }
+#pragma unroll
+    for (int q = 0; q < kBlkPairsPerWave; ++q) {
+        if (ok[q]) {
+            float *out = part + ((int64_t)s * npairs + gp[q]) * (kMT * kMT);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = 8 * (i / 4) + 4 * (lane / 32) + (i % 4), n = lane % 32;
+                out[m * kMT + n] = acc[q][i];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ FP8 (e4m3) on the matrix cores
 //
 // X is stored as e4m3 with a power-of-two scale per column (|x / s| <= 224).
@@ -878,6 +1014,38 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
         } else {
             if (c) syrk_bf16_lds_kernel<true, 64><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64, kchunk, fpart);
             else syrk_bf16_lds_kernel<false, 64><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, K64, kchunk, fpart);
+        }
+    } else if (nt > kLdsMaxTiles && ldu % 8 == 0 && (K + 63) / 64 * 64 <= ldu) {
+        // wide X: blocks of tile pairs, each staging only its row blocks
+        const int BKC = (K + 127) / 128 * 128 <= ldu ? 128 : 64;
+        const int64_t KB = (K + BKC - 1) / BKC * BKC;
+        const int nb = (nt + kBlkTiles - 1) / kBlkTiles;
+        const int nblocks = nb * (nb + 1) / 2;
+        int bsplits = splits;
+        if (bsplits * (int64_t)nblocks > 16384) bsplits = 16384 / nblocks > 1 ? 16384 / nblocks : 1;
+        int64_t kchunk = (KB + bsplits - 1) / bsplits;
+        kchunk = (kchunk + BKC - 1) / BKC * BKC;
+        const size_t lds = sizeof(uint16_t) * (size_t)2 * kBlkTiles * kMT * (BKC + 8) * (c ? 2 : 1);
+        static bool battr = false;
+        if (!battr) {
+            const size_t most = sizeof(uint16_t) * (size_t)2 * kBlkTiles * kMT * (128 + 8) * 2;
+            const void *fns[] = {reinterpret_cast<const void *>(&syrk_bf16_blk_kernel<true, 128>),
+                                 reinterpret_cast<const void *>(&syrk_bf16_blk_kernel<false, 128>),
+                                 reinterpret_cast<const void *>(&syrk_bf16_blk_kernel<true, 64>),
+                                 reinterpret_cast<const void *>(&syrk_bf16_blk_kernel<false, 64>)};
+            for (const void *fn : fns)
+                if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
+                    return -3;
+            battr = true;
+        }
+        splits = bsplits;   // the reduce below sums the slices this launch writes
+        const dim3 grid(bsplits, nblocks);
+        if (BKC == 128) {
+            if (c) syrk_bf16_blk_kernel<true, 128><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
+            else syrk_bf16_blk_kernel<false, 128><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
+        } else {
+            if (c) syrk_bf16_blk_kernel<true, 64><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
+            else syrk_bf16_blk_kernel<false, 64><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
         }
     } else {
         int64_t kchunk = (K16 + splits - 1) / splits;

@@ -380,3 +380,26 @@ def test_newton_l1_fit(name, make, prec):
     err = _rel(beta, ref.beta)
     _say(f"  steps={info['iters']} nonzero={int(np.count_nonzero(beta))} rel err {err:.3e} kkt {info['kkt_inf']:.2e}")
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("n,p,K", [(20_011, 600, 13), (12_003, 1000, 1)])
+def test_information_bf16_wide_within_bound(n, p, K):
+    """More than 16 row tiles (P > 512): the blocked contraction, where each workgroup stages only
+    the two row blocks of its tile pairs.  Same bound as the narrow case; the two-factor design
+    makes every entry comparable to the diagonal, so a misplaced block would show."""
+    d = _mixed(n, p, K, 5)
+    beta = _beta_probe(d)
+    _say(f"evaluate_full BF16 wide n={n} p={p}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, x_precision=coxmi.COX_BF16) as m:
+        obj, g, hd, info = m.evaluate_full(beta)
+    fe = _oracle_eval(d, beta)
+    _check_first_order(d, obj, g, hd, fe)
+    r = _scale(fe)
+    k = math.ceil(d.n / 128) + 16
+    bound = (3.5 * U_BF16 + k * 2.0 ** -24) * r
+    err = np.abs(info - fe.info)
+    worst = float(np.max(err / r))
+    _say(f"  max |err| / r = {worst:.3e} (bound {3.5 * U_BF16 + k * 2.0 ** -24:.3e})")
+    assert np.all(err <= bound), worst
+    assert np.array_equal(info, info.T)
+    assert float(np.median(err / r)) <= 0.1 * 3.5 * U_BF16
