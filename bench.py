@@ -718,6 +718,62 @@ def run_legend(args):
     print(json.dumps(out), flush=True)
 
 
+def run_bootstrap(args):
+    """Bootstrap refits of an unpenalised model (Sec. 3.2's percentile intervals) as independent
+    requests to the fit server (each replicate's rows gathered on the device and submitted in
+    place), against the same refits one after another on a Newton handle (cox_bootstrap).
+    N=20,000 rows, P=20, K=200 strata; the two agree replicate by replicate."""
+    import numpy as np
+    import torch
+    from paper_2310_16238_amd import coxmi, synth
+
+    torch.cuda.set_device(0)
+    n, p, K, B = 20_000, 20, 200, args.bootstrap_reps
+    d = synth.make("iid", n, p, K, 43, beta_sd=0.5, tie_round=100.0)
+    rng = np.random.default_rng(44)
+    counts = np.stack([rng.multinomial(n, np.full(n, 1.0 / n)) for _ in range(B)]).astype(np.uint32)
+    Xt = torch.from_numpy(np.ascontiguousarray(d.X.T)).cuda()
+    tt = torch.from_numpy(np.ascontiguousarray(d.time)).cuda()
+    et = torch.from_numpy(np.ascontiguousarray(d.event, dtype=np.uint8)).cuda()
+    st = torch.from_numpy(np.ascontiguousarray(d.stratum, dtype=np.int32)).cuda()
+    reps = []
+    for b in range(B):
+        idx = torch.from_numpy(np.repeat(np.arange(n), counts[b])).cuda()
+        reps.append((Xt.index_select(1, idx).t(), tt.index_select(0, idx).contiguous(),
+                     et.index_select(0, idx).contiguous(), st.index_select(0, idx).contiguous()))
+    torch.cuda.synchronize()
+    log(f"{B} bootstrap replicates of N={n} P={p} K={K} gathered on the device")
+    with coxmi.CoxServer(prep_threads=args.prep_threads) as srv:
+        t0 = time.perf_counter()
+        tickets = [srv.submit_device(*r) for r in reps]
+        assert srv.drain(timeout=600.0)
+        serve_s = time.perf_counter() - t0
+        served = [srv.poll(t) for t in tickets]
+    seq = min(B, 32)
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE, tol=1e-13) as m:
+        m.bootstrap(counts[:1])   # warm
+        t0 = time.perf_counter()
+        betas, status = m.bootstrap(counts[:seq])
+        seq_s = time.perf_counter() - t0
+    diff = max(float(np.max(np.abs(served[b][0] - betas[b])) / np.max(np.abs(betas[b]))) for b in range(seq))
+    ok = all(r[1]["status"] == 0 for r in served) and bool(np.all(status == 0))
+    hr = np.exp(np.array([r[0][1] for r in served]))
+    log(f"server: {B} refits in {serve_s:.2f} s ({B / serve_s:.0f} fits/s); one after another: {seq} refits in "
+        f"{seq_s:.2f} s ({seq / seq_s:.0f} fits/s); max rel diff {diff:.1e}; statuses ok {ok}; "
+        f"95% BPI of exp(beta_1) [{np.quantile(hr, 0.025):.4f}, {np.quantile(hr, 0.975):.4f}]")
+    out = {
+        "metric": METRIC, "value": B / serve_s, "unit": "fits/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * serve_s,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 contraction, f64 score and solve", "data": "synthetic",
+        "config": {"workload": f"{B} bootstrap refits (unpenalised) of N={n} P={p} K={K} through the fit server, "
+                               f"replicates gathered on the device, seed 43"},
+        "sequential_fits_per_s": seq / seq_s, "speedup": (B / serve_s) / (seq / seq_s),
+        "max_rel_diff_vs_sequential": diff, "statuses_ok": ok, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_heavy(args):
     """Large heavy-tailed Newton fit: N=1e7, P=500 Student-t(3), 50 nonzero coefficients,
     K=5e5 -- FP8 e4m3 information matrix + FP64 refinement against the FP64 Newton path.
@@ -870,6 +926,7 @@ def main():
     ap.add_argument("--paper-p", type=int, default=1000, help="paper: columns")
     ap.add_argument("--paper-newton", action="store_true",
                     help="paper: also fit by proximal Newton with BF16 (and, for P <= 800, FP8) information")
+    ap.add_argument("--bootstrap-reps", type=int, default=512, help="bootstrap: replicates")
     ap.add_argument("--sparse-n", type=int, default=946_911, help="sparse: rows")
     ap.add_argument("--sparse-p", type=int, default=9977, help="sparse: indicator columns")
     ap.add_argument("--cv-n", type=int, default=946_911, help="cv: rows")
@@ -878,12 +935,13 @@ def main():
     ap.add_argument("--bootstrap", type=int, default=20, help="cv: bootstrap refits")
     ap.add_argument("--intervals-n", type=int, default=407_828, help="intervals: subjects")
     ap.add_argument("--intervals-p", type=int, default=1000, help="intervals: columns before the split")
-    ap.add_argument("--workload", choices=["ccd", "serve", "mixed", "heavy", "paper", "intervals", "cv", "sparse", "legend"], default="ccd",
+    ap.add_argument("--workload", choices=["ccd", "serve", "mixed", "heavy", "paper", "intervals", "cv", "sparse", "legend", "bootstrap"], default="ccd",
                     help="ccd: the CCD fit of the N=1e6 P=50 workload (default); serve: the serving stream; "
                          "mixed: BF16 + FP64-refinement Newton fits at N=1e6 P=200; heavy: FP8 Newton at N=1e7 P=500; "
                          "paper: the Sec. 3.1 l1 CCD fit; intervals: a step-effect model split into interval strata; "
                          "cv: cross-validation over an l1 path plus bootstrap refits; sparse: the full-width "
-                         "Sec. 3.2 fit on indicator X; legend: the full-width Sec. 3.2 analysis (CV, refit, bootstrap)")
+                         "Sec. 3.2 fit on indicator X; legend: the full-width Sec. 3.2 analysis (CV, refit, bootstrap); "
+                         "bootstrap: unpenalised bootstrap refits through the fit server")
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--plain-sample", type=int, default=32, help="serve: requests timed on the plain FP64 path")
     ap.add_argument("--poisson-seconds", type=float, default=30.0, help="serve: length of the Poisson run")
@@ -910,6 +968,9 @@ def main():
         return
     if args.workload == "heavy":
         run_heavy(args)
+        return
+    if args.workload == "bootstrap":
+        run_bootstrap(args)
         return
     if args.workload == "legend":
         run_legend(args)

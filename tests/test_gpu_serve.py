@@ -224,3 +224,40 @@ def test_device_submission_errors():
         assert rc == coxmi.COX_EINVAL
         with pytest.raises(ValueError):
             srv.submit_device(X.contiguous(), t_bad, e)   # row-major X
+
+
+def test_bootstrap_through_the_server():
+    """Bootstrap refits of an unpenalised model as independent server requests (each replicate's
+    rows gathered on the device and submitted in place) against cox_bootstrap on a Newton handle
+    and the oracle: every replicate's optimum to 1e-10."""
+    d = synth.make("iid", 5_000, 8, 20, 37, beta_sd=0.5, tie_round=100.0)
+    n = d.time.shape[0]
+    rng = np.random.default_rng(41)
+    B = 48
+    counts = np.stack([rng.multinomial(n, np.full(n, 1.0 / n)) for _ in range(B)]).astype(np.uint32)
+    Xt = torch.from_numpy(np.ascontiguousarray(d.X.T)).cuda()          # p x n: columns contiguous
+    tt = torch.from_numpy(np.ascontiguousarray(d.time)).cuda()
+    et = torch.from_numpy(np.ascontiguousarray(d.event, dtype=np.uint8)).cuda()
+    st = torch.from_numpy(np.ascontiguousarray(d.stratum, dtype=np.int32)).cuda()
+    reps = []
+    for b in range(B):
+        idx = torch.from_numpy(np.repeat(np.arange(n), counts[b])).cuda()
+        reps.append((Xt.index_select(1, idx).t(), tt.index_select(0, idx).contiguous(),
+                     et.index_select(0, idx).contiguous(), st.index_select(0, idx).contiguous()))
+    torch.cuda.synchronize()
+    _say(f"bootstrap through the server: {B} replicates of n={n} p=8")
+    with coxmi.CoxServer(prep_threads=4) as srv:
+        tickets = [srv.submit_device(*r) for r in reps]
+        assert srv.drain(timeout=120.0)
+        served = [srv.poll(t) for t in tickets]
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE, tol=1e-13) as m:
+        betas, status = m.bootstrap(counts)
+    assert np.all(status == coxmi.COX_OK)
+    for b in range(B):
+        beta_s, info_s = served[b][0], served[b][1]
+        assert info_s["status"] == coxmi.COX_OK
+        assert np.max(np.abs(beta_s - betas[b])) <= 1e-10 * np.max(np.abs(betas[b])), b
+    for b in (0, B - 1):
+        Xr, tr, er, sr = orc.resample(d.X, d.time, d.event, d.stratum, counts[b])
+        ref = orc.fit_newton(Xr, tr, er, sr, tol=1e-14)
+        assert np.max(np.abs(betas[b] - ref.beta)) <= 1e-10 * np.max(np.abs(ref.beta))
