@@ -401,11 +401,13 @@ static int newton_fit_l1(cox_handle *h, const double *beta0, double *beta_out, c
             h->prof.contraction_ms += elapsed_ms(s.ev[2], s.ev[3]);
             have_h = true;
         }
-        // coordinate descent on the model; HD = H D is kept up to date
+        // coordinate descent on the model; HD = H D is kept up to date.  The model is solved to
+        // a thousandth of the last outer step (inexact early on), and to 1e-3 tol at the end
         std::fill(D.begin(), D.end(), 0.0);
         std::fill(HD.begin(), HD.end(), 0.0);
         double bmax = 1.0;
         for (int j = 0; j < p; ++j) bmax = std::max(bmax, std::fabs(beta[j]));
+        const double inner_tol = std::max(1e-3 * h->opt.tol * bmax, iters ? 1e-3 * last_step : 1e-3 * bmax);
         for (int sweep = 0; sweep < 1000; ++sweep) {
             double change = 0.0;
             for (int j = 0; j < p; ++j) {
@@ -424,7 +426,7 @@ static int newton_fit_l1(cox_handle *h, const double *beta0, double *beta_out, c
                     change = std::max(change, std::fabs(delta));
                 }
             }
-            if (change <= 1e-3 * h->opt.tol * bmax) break;
+            if (change <= inner_tol) break;
         }
         prev = beta;
         obj_prev = F;
