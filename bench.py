@@ -448,9 +448,16 @@ def run_cv(args):
     pen = np.ones(p, np.uint8)
     pen[0] = 0
     t0 = time.perf_counter()
-    m = coxmi.CoxModel(d.X, d.time, d.event, d.stratum, gamma=0.0, penalize=pen, tol=1e-12)
+    if args.cv_newton:   # proximal Newton fits with a BF16 information matrix
+        m = coxmi.CoxModel(d.X, d.time, d.event, d.stratum, gamma=0.0, penalize=pen, tol=1e-12,
+                           mode=coxmi.COX_NEWTON_REFINE, x_precision=coxmi.COX_BF16, max_iter=300)
+    else:
+        m = coxmi.CoxModel(d.X, d.time, d.event, d.stratum, gamma=0.0, penalize=pen, tol=1e-12)
     log(f"cox_init {time.perf_counter() - t0:.1f} s")
-    _, g0, _ = m.evaluate(np.zeros(p))
+    if args.cv_newton:
+        _, g0, _, _ = m.evaluate_full(np.zeros(p), want_info=False)
+    else:
+        _, g0, _ = m.evaluate(np.zeros(p))
     gmax = float(np.max(np.abs(g0[pen == 1])))
     gammas = gmax * np.array([0.5, 0.2, 0.1, 0.05, 0.02, 0.01, 0.003, 0.001])
     rng = np.random.default_rng(8)
@@ -519,7 +526,9 @@ def run_cv(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"Sec. 3.2 analysis shape: N={n} rows, P={p} binary covariates (3% ones), K={K} strata; "
                                f"{F}-fold CV over {len(gammas)} l1 weights (column 0 unpenalised), refit at the chosen "
-                               f"weight, {B} bootstrap refits; CCD to 1e-12, FP64, seed 7"},
+                               f"weight, {B} bootstrap refits; "
+                               + ("proximal Newton with BF16 information" if args.cv_newton else "CCD, FP64")
+                               + ", to 1e-12, seed 7"},
         "cv_s": cv_s, "refit_s": fit_s, "bootstrap_s": boot_s, "fits": fits,
         "gammas": [float(g) for g in gammas], "cvl": [float(c) for c in cvl], "chosen": gi,
         "treatment_hr": math.exp(beta_star[0]), "treatment_bpi95": [float(lo), float(hi)],
@@ -932,6 +941,7 @@ def main():
     ap.add_argument("--cv-n", type=int, default=946_911, help="cv: rows")
     ap.add_argument("--cv-p", type=int, default=1000, help="cv: columns")
     ap.add_argument("--cv-folds", type=int, default=10, help="cv: folds")
+    ap.add_argument("--cv-newton", action="store_true", help="cv: proximal Newton fits (BF16 information)")
     ap.add_argument("--bootstrap", type=int, default=20, help="cv: bootstrap refits")
     ap.add_argument("--intervals-n", type=int, default=407_828, help="intervals: subjects")
     ap.add_argument("--intervals-p", type=int, default=1000, help="intervals: columns before the split")

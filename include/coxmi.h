@@ -312,15 +312,16 @@ int cox_set_penalty(cox_handle *h, double gamma, const uint8_t *penalize);
  *     cvl[g] = sum_k [ l(beta_{-k}) - l_{-k}(beta_{-k}) ]
  * is accumulated, l being the log of Eq. strat_l on all rows and l_{-k} on the
  * training rows (the held-out rows' contribution given the rest).
- *   h       : COX_CCD handle on the full data (used for l; its options give tol,
- *             max_iter, precision and stream of the fold fits)
+ *   h       : handle on the full data (used for l; its options give the mode --
+ *             COX_CCD, or COX_NEWTON_REFINE for proximal Newton fits --, tol, max_iter,
+ *             precision and stream of the fold fits)
  *   fold    : host, n entries in [0, nfolds); every fold non-empty and not all rows
  *   gammas  : host, ngamma finite values >= 0 (a decreasing path warm-starts best)
  *   penalize: host, p flags or NULL (all columns penalised)
  *   cvl     : host, ngamma outputs; betas: host [nfolds][ngamma][p] or NULL;
  *   status  : host [nfolds][ngamma] fit statuses or NULL
  * Returns COX_OK, COX_NOT_CONVERGED (some fit hit max_iter; outputs filled), or
- * an error (COX_EUNSUPPORTED for a COX_NEWTON_REFINE handle). */
+ * an error. */
 int cox_cross_validate(cox_handle *h, int nfolds, const int32_t *fold, int ngamma, const double *gammas,
                        const uint8_t *penalize, double *cvl, double *betas, int *status);
 

@@ -738,9 +738,19 @@ extern "C" int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox
     return rc;
 }
 
-// -log partial likelihood (Eq. strat_l, no penalty) of h's data at beta.
+// -log partial likelihood (Eq. strat_l, no penalty) of h's data at beta: the persistent
+// kernel's evaluation of one coordinate, or the full evaluation on a Newton handle.
 static int neg_loglik(cox_handle *h, const double *beta, double *nll)
 {
+    if (h->opt.mode == COX_NEWTON_REFINE) {
+        double obj = 0.0;
+        const int rc = cox_evaluate_full(h, beta, &obj, nullptr, nullptr, nullptr);
+        if (rc != COX_OK) return rc;
+        double pen = 0.0;
+        for (int64_t j = 0; j < h->p; ++j) pen += h->gamma[(size_t)j] * std::fabs(beta[j]);
+        *nll = obj - pen;
+        return COX_OK;
+    }
     double res[kResultSlots];
     const int rc = run_kernel(h, kModeEval, 0, 1, beta, res);
     if (rc != COX_OK) return rc;
@@ -752,7 +762,6 @@ extern "C" int cox_cross_validate(cox_handle *h, int nfolds, const int32_t *fold
                                   const uint8_t *penalize, double *cvl, double *betas, int *status)
 {
     if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
-    if (h->opt.mode != COX_CCD) return fail(h, COX_EUNSUPPORTED, "cross-validation runs l1 fits: the handle must be COX_CCD");
     if (nfolds < 2 || !fold) return fail(h, COX_EINVAL, "need nfolds >= 2 and a fold for every row");
     if (ngamma < 1 || !gammas || !cvl) return fail(h, COX_EINVAL, "need ngamma >= 1, gammas and cvl");
     for (int g = 0; g < ngamma; ++g)

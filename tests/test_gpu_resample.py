@@ -165,7 +165,27 @@ def test_resample_and_cv_errors():
         with pytest.raises(coxmi.CoxError) as e:
             m.set_penalty(-1.0)
         assert e.value.code == coxmi.COX_EINVAL
-    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE) as m:
-        with pytest.raises(coxmi.CoxError) as e:
-            m.cross_validate(np.arange(n, dtype=np.int32) % 2, [1.0])
-        assert e.value.code == coxmi.COX_EUNSUPPORTED
+
+
+def test_cross_validation_newton_bf16_matches_oracle():
+    """The same cross-validation with proximal Newton fits and a BF16 information matrix: the
+    fold optima are the same, so the criterion and the estimates match the oracle's CCD path."""
+    d = synth.make("binary", 30_000, 20, 10, 31, beta_sd=1.0, beta_nonzero=0.3, density=0.1, tie_round=50.0)
+    fold = np.random.default_rng(13).integers(0, 4, d.time.shape[0]).astype(np.int32)
+    gammas = np.array([40.0, 10.0, 2.0])
+    pen = np.ones(20, np.uint8)
+    pen[0] = 0
+    _say("cross-validation by proximal Newton (BF16): 4 folds x 3 gammas, n=30000 p=20")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE,
+                        x_precision=coxmi.COX_BF16, tol=1e-13, max_iter=300) as m:
+        cvl, betas, status = m.cross_validate(fold, gammas, pen)
+    rcvl, rbetas, rconv = orc.cross_validate(d.X, d.time, d.event, d.stratum, fold, gammas, pen, tol=1e-14)
+    assert rconv.all() and np.all(status == coxmi.COX_OK)
+    for k in range(4):
+        for g in range(len(gammas)):
+            assert np.array_equal(betas[k, g] == 0.0, rbetas[k, g] == 0.0), (k, g)
+            assert _rel(betas[k, g], rbetas[k, g]) <= 1e-10, (k, g)
+    nll_all = orc.neg_loglik(d.X, d.time, d.event, d.stratum, np.zeros(20))
+    err = float(np.max(np.abs(cvl - rcvl)))
+    _say(f"  max |gpu - oracle| {err:.3e}")
+    assert err <= 1e-11 * 2.0 * 4 * abs(nll_all)
