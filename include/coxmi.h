@@ -41,7 +41,7 @@ extern "C" {
 #define COX_ENOMEM (-2)   /* device or host allocation failed */
 #define COX_EDEVICE (-3)  /* HIP runtime error or a device-side synchronisation time-out */
 #define COX_ENUMERIC (-4) /* a risk-set sum left the normal FP64 range (see cox_fit) */
-#define COX_EUNSUPPORTED (-5) /* option or size this build does not support */
+#define COX_EUNSUPPORTED (-5) /* option or size the library does not support */
 
 /* ---------------------------------------------------------------- options */
 /* optimiser: cyclic coordinate descent (Sec. 2.4), or Newton steps on the full

@@ -1,4 +1,4 @@
-// Host-only driver for the sanitizer test: exercises the library's host code
+// Host-only program for the sanitizer test: exercises the library's host code
 // (input checks, canonical order, interval split) on random and edge-case
 // inputs, checking the canonical order against a plain sort.  Built with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_host_sanitizers_cpu.py.

@@ -1,6 +1,6 @@
 """The library's host-only code (canonical order, interval split) built with g++ under
 AddressSanitizer and UndefinedBehaviorSanitizer and run on random and edge-case inputs,
-the canonical order checked against a plain sort (tests/host/sanitize_driver.cpp)."""
+the canonical order checked against a plain sort (tests/host/sanitize_host.cpp)."""
 import os
 import shutil
 import subprocess
@@ -13,11 +13,11 @@ CSRC = os.path.join(ROOT, "paper_2310_16238_amd", "csrc")
 
 @pytest.mark.skipif(shutil.which("g++") is None or not os.path.isdir("/opt/rocm/include"), reason="needs g++ and HIP headers")
 def test_host_code_under_sanitizers(tmp_path):
-    exe = str(tmp_path / "sanitize_driver")
+    exe = str(tmp_path / "sanitize_host")
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=undefined", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
            "-I", CSRC, "-I", "/opt/rocm/include",
-           os.path.join(ROOT, "tests", "host", "sanitize_driver.cpp"), os.path.join(CSRC, "canonical.cpp"),
+           os.path.join(ROOT, "tests", "host", "sanitize_host.cpp"), os.path.join(CSRC, "canonical.cpp"),
            os.path.join(CSRC, "intervals.cpp"), "-lpthread", "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True, text=True, timeout=300)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
