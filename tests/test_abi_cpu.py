@@ -111,3 +111,57 @@ def test_server_default_options():
     o = coxmi.cox_server_default_options()
     assert o.x_precision == coxmi.COX_F32 and o.tol == 1e-12 and o.max_iter == 100
     assert o.hbm_budget == 8 << 30 and o.staging_bytes == 1 << 30 and o.device == -1
+
+
+def test_new_entry_points_reject_bad_inputs_before_the_device():
+    L = coxmi.lib()
+    out = ctypes.c_void_p()
+    cnt = np.ones(4, np.uint32)
+    # resampling, intervals, penalties, CV, bootstrap, baseline hazard: NULL handles and outputs
+    assert L.cox_init_resample(None, None, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), None) == coxmi.COX_EINVAL
+    assert L.cox_init_resample(ctypes.byref(out), None, None, None) == coxmi.COX_EINVAL and out.value is None
+    t = np.array([1.0, 2.0]); e = np.array([1, 0], np.uint8)
+    assert L.cox_init_intervals(ctypes.byref(out), None, coxmi._dptr(t), e.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                None, 0, None, None, None) == coxmi.COX_EINVAL
+    assert L.cox_set_penalty(None, 1.0, None) == coxmi.COX_EINVAL
+    assert L.cox_cross_validate(None, 2, None, 1, None, None, None, None, None) == coxmi.COX_EINVAL
+    assert L.cox_bootstrap(None, 1, None, None, None, None) == coxmi.COX_EINVAL
+    b = np.zeros(1)
+    assert L.cox_baseline_hazard(None, coxmi._dptr(b), coxmi._dptr(b)) == coxmi.COX_EINVAL
+
+
+@pytest.mark.parametrize("case", ["col_ptr_start", "col_ptr_decreasing", "row_out_of_range", "nan_time",
+                                  "event_2", "p_too_large", "newton_mode"])
+def test_indicator_init_rejects_bad_inputs(case):
+    n, p = 5, 2
+    ptr = np.array([0, 2, 3], np.int64)
+    idx = np.array([0, 3, 4], np.int32)
+    time = np.linspace(1.0, 2.0, n)
+    event = np.array([1, 0, 1, 1, 0], np.uint8)
+    kw = {}
+    code = coxmi.COX_EINVAL
+    if case == "col_ptr_start":
+        ptr = np.array([1, 2, 3], np.int64)
+    elif case == "col_ptr_decreasing":
+        ptr = np.array([0, 3, 2], np.int64)
+    elif case == "row_out_of_range":
+        idx = np.array([0, 3, 5], np.int32)
+    elif case == "nan_time":
+        time[2] = math.nan
+    elif case == "event_2":
+        event[1] = 2
+    elif case == "p_too_large":
+        ptr = np.zeros(12290, np.int64)
+        code = coxmi.COX_EUNSUPPORTED
+    elif case == "newton_mode":
+        code = coxmi.COX_EUNSUPPORTED
+    o = coxmi.cox_default_options()
+    if case == "newton_mode":
+        o.mode = coxmi.COX_NEWTON_REFINE
+    out = ctypes.c_void_p()
+    rc = coxmi.lib().cox_init_indicator(ctypes.byref(out), n, ptr.shape[0] - 1,
+                                        ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), coxmi._dptr(time),
+                                        event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), None, ctypes.byref(o))
+    assert rc == code and out.value is None
+    assert coxmi.lib().cox_last_error(None)
