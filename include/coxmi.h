@@ -100,8 +100,7 @@ void cox_default_options(cox_options *o);
  *   o   : options (NULL = defaults); penalize is copied
  * Errors: COX_EINVAL (n < 1, p < 1, ldx < n, NULL x/time/event, non-finite
  * time, event not 0/1), COX_EUNSUPPORTED (p > 12288, or p > 4096 in mode
- * COX_NEWTON_REFINE -- cox_evaluate_full also needs p <= 4096; p > 800 with
- * COX_FP8_E4M3; in mode COX_CCD, n
+ * COX_NEWTON_REFINE -- cox_evaluate_full also needs p <= 4096; in mode COX_CCD, n
  * beyond the persistent kernel's register-resident capacity of about
  * CUs x 512 x 16 rows -- a COX_NEWTON_REFINE handle of that size is created,
  * and then supports cox_fit and cox_evaluate_full only; an x_precision other

@@ -879,6 +879,133 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, 2) void syrk_fp8_lds_kernel(cons
     }
 }
 
+// Wide X in FP8 (more than kF8MaxRows rows): blocks of kBlkTiles x kBlkTiles tile pairs as in
+// syrk_bf16_blk_kernel; a workgroup stages only the row tiles of its block (8 tiles x 32 rows
+// x 80 bytes of LDS) with the same decode / weight / re-encode as syrk_fp8_lds_kernel.
+__global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_fp8_blk_kernel(const uint8_t *u, int p, const double *c,
+                                                                         const double *wsc, int64_t K, int64_t kchunk,
+                                                                         float *part)
+{
+    constexpr int kRows = 2 * kBlkTiles * kMT;                                   // staged rows
+    constexpr int kPieces = kRows * 4 / (64 * kSyrkBfWaves);                    // 4 per thread
+    __shared__ uint8_t sh8[kRows * kF8Stride];
+    __shared__ float cw[kF8KC];
+    const int nt = (p + kMT - 1) / kMT;
+    const int rows = nt * kMT;
+    const int nb = (nt + kBlkTiles - 1) / kBlkTiles;
+    const int npairs = nt * (nt + 1) / 2;
+    int I, J;
+    tile_pair(blockIdx.y, nb, I, J);
+    const bool diag = I == J;
+    const int nst = diag ? kBlkTiles : 2 * kBlkTiles;
+    const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+    const int s = blockIdx.x;
+    const int64_t k0 = (int64_t)s * kchunk;
+    const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+    const double invS = 1.0 / wsc[0];
+    int la[kBlkPairsPerWave], lb[kBlkPairsPerWave], gp[kBlkPairsPerWave];
+    bool ok[kBlkPairsPerWave];
+    f32x16 acc[kBlkPairsPerWave];
+#pragma unroll
+    for (int q = 0; q < kBlkPairsPerWave; ++q) {
+        const int idx = w * kBlkPairsPerWave + q;
+        int a, b;
+        if (diag) {
+            ok[q] = idx < kBlkTiles * (kBlkTiles + 1) / 2;
+            tile_pair(ok[q] ? idx : 0, kBlkTiles, a, b);
+            la[q] = a;
+            lb[q] = b;
+        } else {
+            a = idx / kBlkTiles;
+            b = idx % kBlkTiles;
+            ok[q] = true;
+            la[q] = a;
+            lb[q] = kBlkTiles + b;
+        }
+        const int ti = I * kBlkTiles + a, tj = J * kBlkTiles + b;
+        ok[q] = ok[q] && ti < nt && tj < nt;
+        gp[q] = ok[q] ? pair_index(ti, tj, nt) : 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[q][i] = 0.0f;
+    }
+    const int rsub = lane & 31, kofs = 32 * (lane >> 5);
+    const int npieces = nst * kMT * 4;
+    u32x4v reg[kPieces];
+    double creg = 0.0;
+    auto load_chunk = [&](int64_t kc) {
+        const uint8_t *blk = u + (kc / kF8KC) * (int64_t)rows * kF8KC;
+#pragma unroll
+        for (int m = 0; m < kPieces; ++m) {
+            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            u32x4v v = {0u, 0u, 0u, 0u};
+            if (e < npieces) {
+                const int lr = e >> 2, lt = lr / kMT;
+                const int gt = lt < kBlkTiles ? I * kBlkTiles + lt : J * kBlkTiles + (lt - kBlkTiles);
+                if (gt < nt)
+                    v = *reinterpret_cast<const u32x4v *>(blk + (int64_t)(gt * kMT + lr % kMT) * kF8KC + 16 * (e & 3));
+            }
+            reg[m] = v;
+        }
+        if (threadIdx.x < kF8KC) creg = c[kc + threadIdx.x];
+    };
+    if (k0 < k1) load_chunk(k0);
+    for (int64_t kc = k0; kc < k1; kc += kF8KC) {
+        if (threadIdx.x < kF8KC) cw[threadIdx.x] = (float)(sqrt(creg) * invS);
+        __syncthreads();
+        const int piece = threadIdx.x & 3;
+        float wk[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) wk[i] = cw[16 * piece + i];
+#pragma unroll
+        for (int m = 0; m < kPieces; ++m) {
+            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            if (e < npieces) {
+                const u32x4v raw = reg[m];
+                u32x4v v;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int word = (int)raw[d];
+                    int o = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_cvt_f32_fp8(word, 0) * wk[4 * d],
+                                                            __builtin_amdgcn_cvt_f32_fp8(word, 1) * wk[4 * d + 1], 0,
+                                                            false);
+                    o = __builtin_amdgcn_cvt_pk_fp8_f32(__builtin_amdgcn_cvt_f32_fp8(word, 2) * wk[4 * d + 2],
+                                                        __builtin_amdgcn_cvt_f32_fp8(word, 3) * wk[4 * d + 3], o, true);
+                    v[d] = (unsigned)o;
+                }
+                *reinterpret_cast<u32x4v *>(sh8 + (e >> 2) * kF8Stride + 16 * piece) = v;
+            }
+        }
+        __syncthreads();
+        if (kc + kF8KC < k1) load_chunk(kc + kF8KC);   // in flight during the products below
+#pragma unroll
+        for (int q = 0; q < kBlkPairsPerWave; ++q) {
+            if (ok[q]) {
+                const uint8_t *pa = sh8 + (la[q] * kMT + rsub) * kF8Stride + kofs;
+                const uint8_t *pb = sh8 + (lb[q] * kMT + rsub) * kF8Stride + kofs;
+                const u32x4v a0 = *reinterpret_cast<const u32x4v *>(pa), a1 = *reinterpret_cast<const u32x4v *>(pa + 16);
+                const u32x4v b0 = *reinterpret_cast<const u32x4v *>(pb), b1 = *reinterpret_cast<const u32x4v *>(pb + 16);
+                const i32x8v av = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3],
+                                   (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+                const i32x8v bv = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3],
+                                   (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+                acc[q] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[q], 0, 0, 0, 127, 0, 127);
+            }
+        }
+        __syncthreads();   // the next chunk rewrites the LDS tiles
+    }
+#pragma unroll
+    for (int q = 0; q < kBlkPairsPerWave; ++q) {
+        if (ok[q]) {
+            float *out = part + ((int64_t)s * npairs + gp[q]) * (kMT * kMT);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = 8 * (i / 4) + 4 * (lane / 32) + (i % 4), n = lane % 32;
+                out[m * kMT + n] = acc[q][i];
+            }
+        }
+    }
+}
+
 // C (+)= sign * scale_i * scale_j * sum over ranges of the partial tiles (FP64).
 // Grid (npairs, 16): each workgroup takes 64 entries of one tile; its four
 // waves sum the splits q = w, w + 4, ... in order, then the four sums are
@@ -1078,9 +1205,23 @@ int syrk_fp8(const uint8_t *u, int64_t ldu, int p, const float *scale, const dou
     const int npairs = nt * (nt + 1) / 2;
     const int ngroups = (npairs + kPairsPerGroup - 1) / kPairsPerGroup;
     const int64_t K64 = (K + kF8KC - 1) / kF8KC * kF8KC;
-    if (K64 > ldu || ldu % kF8KC != 0 || nt * kMT > kF8MaxRows) return -1;
+    if (K64 > ldu || ldu % kF8KC != 0) return -1;
     bmax_kernel<<<256, 256, 0, stream>>>(c, K, blockmax);
     wscale_kernel<<<1, 256, 0, stream>>>(blockmax, 256, wsc);
+    if (nt * kMT > kF8MaxRows) {
+        // wide X: blocks of tile pairs, each staging only its row blocks
+        const int nb = (nt + kBlkTiles - 1) / kBlkTiles;
+        const int nblocks = nb * (nb + 1) / 2;
+        int bsplits = splits;
+        if (bsplits * (int64_t)nblocks > 16384) bsplits = 16384 / nblocks > 1 ? 16384 / nblocks : 1;
+        int64_t kchunk = (K64 + bsplits - 1) / bsplits;
+        kchunk = (kchunk + kF8KC - 1) / kF8KC * kF8KC;
+        float *fpart = reinterpret_cast<float *>(part);
+        syrk_fp8_blk_kernel<<<dim3(bsplits, nblocks), 64 * kSyrkBfWaves, 0, stream>>>(u, p, c, wsc, K64, kchunk, fpart);
+        syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 256, 0, stream>>>(fpart, p, bsplits, scale, sign, accumulate, C,
+                                                                     wsc);
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+    }
     // two workgroups per compute unit are resident: size the grid to whole rounds of them
     static int cus = 0;
     if (cus == 0) {

@@ -243,7 +243,7 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     if (p > kMaxCcdP || (opt.mode == COX_NEWTON_REFINE && p > kMaxNewtonP))
         return fail(nullptr, COX_EUNSUPPORTED, "p exceeds 12288 (COX_CCD) or 4096 (COX_NEWTON_REFINE)");
     if (opt.x_precision == COX_FP8_E4M3 && p > kMaxFp8P)
-        return fail(nullptr, COX_EUNSUPPORTED, "the FP8 contraction supports p <= 800");
+        return fail(nullptr, COX_EUNSUPPORTED, "the FP8 contraction supports p <= 4096");
 
     cox_handle *h = new cox_handle();
     h->n = n;

@@ -9,8 +9,9 @@
 
 namespace coxmi {
 
-// Columns of the FP8 contraction (its tiles of one workgroup hold all p rows).
-constexpr int64_t kMaxFp8P = 800;
+// Columns of the FP8 contraction (up to 800 every workgroup stages all p rows, beyond that
+// blocks of tile pairs stage only their own rows): the Newton path's limit.
+constexpr int64_t kMaxFp8P = 4096;
 
 // ------------------------------------------------------------------ full evaluation (newton.hip)
 

@@ -40,7 +40,7 @@ int newton_setup(cox_handle *h)
     if (h->p > kMaxNewtonP)
         return handle_fail(h, COX_EUNSUPPORTED, "the full evaluation and Newton fits support p <= 4096");
     if (h->opt.x_precision == COX_FP8_E4M3 && h->p > kMaxFp8P)
-        return handle_fail(h, COX_EUNSUPPORTED, "the FP8 contraction supports p <= 800");
+        return handle_fail(h, COX_EUNSUPPORTED, "the FP8 contraction supports p <= 4096");
     if (!h->d_x)
         return handle_fail(h, COX_EUNSUPPORTED,
                            "a handle on indicator X runs the CCD path only (cox_fit in COX_CCD mode, cox_evaluate, "

@@ -211,7 +211,7 @@ def test_newton_fit_mixed_precision_full_size():
 
 def test_newton_options_rejected():
     d = synth.config_small(n=500, K=1)
-    wide = np.random.default_rng(0).normal(size=(500, 801))
+    wide = np.random.default_rng(0).normal(size=(500, 4097))
     with pytest.raises(coxmi.CoxError) as e:
         coxmi.cox_init(wide, d.time, d.event, mode=coxmi.COX_NEWTON_REFINE, x_precision=coxmi.COX_FP8_E4M3)
     assert e.value.code == coxmi.COX_EUNSUPPORTED
@@ -403,3 +403,26 @@ def test_information_bf16_wide_within_bound(n, p, K):
     assert np.all(err <= bound), worst
     assert np.array_equal(info, info.T)
     assert float(np.median(err / r)) <= 0.1 * 3.5 * U_BF16
+
+
+@pytest.mark.parametrize("n,p,K", [(20_011, 900, 13), (12_003, 1000, 1)])
+def test_information_fp8_wide_within_bound(n, p, K):
+    """More than 800 columns in FP8: the blocked kernel (each workgroup stages only the row
+    blocks of its tile pairs); the FP8 bound of the narrow case."""
+    d = _mixed(n, p, K, 6)
+    beta = _beta_probe(d)
+    _say(f"evaluate_full FP8 wide n={n} p={p}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE,
+                        x_precision=coxmi.COX_FP8_E4M3) as m:
+        obj, g, hd, info = m.evaluate_full(beta)
+    fe = _oracle_eval(d, beta)
+    _check_first_order(d, obj, g, hd, fe)
+    r = _scale(fe)
+    k = math.ceil(d.n / 128) + 16
+    lim = 4.5 * U_FP8 + 3.5 * U_BF16 + k * 2.0 ** -24
+    err = np.abs(info - fe.info)
+    worst = float(np.max(err / r))
+    _say(f"  max |err| / r = {worst:.3e} (bound {lim:.3e}), median {float(np.median(err / r)):.2e}")
+    assert np.all(err <= lim * r), worst
+    assert np.array_equal(info, info.T)
+    assert float(np.median(err / r)) <= 0.1 * lim
