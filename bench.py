@@ -783,6 +783,40 @@ def run_bootstrap(args):
     print(json.dumps(out), flush=True)
 
 
+def run_strata_sweep(args):
+    """Sec. 2.7 / Sec. 3.1: with the segmented scan the work per coordinate does not depend on how
+    the rows are cut into strata.  N=1e6 rows, P=10 AR(1) columns, the same data cut into K = 1 ..
+    N/2 strata; time per coordinate of the persistent kernel (a fixed 20-sweep evaluation run, so
+    every K does the same number of coordinates)."""
+    import numpy as np
+    import torch
+    from paper_2310_16238_amd import coxmi, synth
+
+    torch.cuda.set_device(0)
+    n, p = 1_000_000, 10
+    res = {}
+    for K in (1, 10, 1_000, 50_000, 250_000, 500_000):
+        d = synth.make("ar1", n, p, K, 50, beta_sd=0.3)
+        with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, gamma=1.0, tol=0.0, max_iter=20) as m:
+            m.fit()   # warm
+            kms = []
+            for _ in range(3):
+                _, info = m.fit()
+                kms.append(m.kernel_ms())
+        us = 1e3 * float(np.median(kms)) / (20 * p)
+        res[K] = us
+        log(f"K={K}: {us:.2f} us per coordinate ({info['iters']} sweeps)")
+    vals = list(res.values())
+    out = {
+        "metric": "us per coordinate evaluation across strata counts", "value": max(vals) / min(vals),
+        "unit": "max/min ratio", "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": None,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"N={n}, P={p} AR(1), the same rows cut into K strata, 20 CCD sweeps, seed 50"},
+        "us_per_coordinate": {str(k): v for k, v in res.items()}, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_heavy(args):
     """Large heavy-tailed Newton fit: N=1e7, P=500 Student-t(3), 50 nonzero coefficients,
     K=5e5 -- FP8 e4m3 information matrix + FP64 refinement against the FP64 Newton path.
@@ -945,13 +979,15 @@ def main():
     ap.add_argument("--bootstrap", type=int, default=20, help="cv: bootstrap refits")
     ap.add_argument("--intervals-n", type=int, default=407_828, help="intervals: subjects")
     ap.add_argument("--intervals-p", type=int, default=1000, help="intervals: columns before the split")
-    ap.add_argument("--workload", choices=["ccd", "serve", "mixed", "heavy", "paper", "intervals", "cv", "sparse", "legend", "bootstrap"], default="ccd",
+    ap.add_argument("--workload", choices=["ccd", "serve", "mixed", "heavy", "paper", "intervals", "cv", "sparse", "legend", "bootstrap",
+                             "strata-sweep"], default="ccd",
                     help="ccd: the CCD fit of the N=1e6 P=50 workload (default); serve: the serving stream; "
                          "mixed: BF16 + FP64-refinement Newton fits at N=1e6 P=200; heavy: FP8 Newton at N=1e7 P=500; "
                          "paper: the Sec. 3.1 l1 CCD fit; intervals: a step-effect model split into interval strata; "
                          "cv: cross-validation over an l1 path plus bootstrap refits; sparse: the full-width "
                          "Sec. 3.2 fit on indicator X; legend: the full-width Sec. 3.2 analysis (CV, refit, bootstrap); "
-                         "bootstrap: unpenalised bootstrap refits through the fit server")
+                         "bootstrap: unpenalised bootstrap refits through the fit server; strata-sweep: time per "
+                         "coordinate across strata counts")
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--plain-sample", type=int, default=32, help="serve: requests timed on the plain FP64 path")
     ap.add_argument("--poisson-seconds", type=float, default=30.0, help="serve: length of the Poisson run")
@@ -978,6 +1014,9 @@ def main():
         return
     if args.workload == "heavy":
         run_heavy(args)
+        return
+    if args.workload == "strata-sweep":
+        run_strata_sweep(args)
         return
     if args.workload == "bootstrap":
         run_bootstrap(args)
