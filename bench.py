@@ -817,6 +817,50 @@ def run_strata_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def run_peaks(args):
+    """Measured reference points for the roofline, beside the published peaks: HBM bandwidth of a
+    plain device copy (1 GiB each way) and the matrix-core rate of large contiguous BF16 and FP32
+    products through the vendor library (torch.matmul), timed with HIP events."""
+    import torch
+
+    torch.cuda.set_device(0)
+    out = {}
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 10 * 2 * x.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    out["copy_GBps"] = gbs
+    log(f"device copy: {gbs:.0f} GB/s (read + write) of {HBM_PEAK_GBS:.0f} published")
+    del x, y
+    for dt, name, peak in [(torch.bfloat16, "bf16", MFMA_PEAK_TFLOPS["bf16"]), (torch.float32, "fp32", 157.3)]:
+        n = 8192
+        a = torch.randn(n, n, device="cuda").to(dt).contiguous()
+        b = torch.randn(n, n, device="cuda").to(dt).contiguous()
+        for _ in range(3):
+            torch.matmul(a, b)
+        e0.record()
+        for _ in range(10):
+            torch.matmul(a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        tf = 10 * 2 * n ** 3 / (e0.elapsed_time(e1) / 1e3) / 1e12
+        out[f"matmul_{name}_TFLOPs"] = tf
+        log(f"matmul {name} {n}^3: {tf:.0f} TFLOP/s of {peak:.0f} published")
+    rec = {"metric": "measured reference peaks", "value": out["copy_GBps"], "unit": "GB/s", "n_gpus": 1,
+           "steps": 10, "warmup": 3, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 copy; bf16 and fp32 products", "data": "synthetic",
+           "config": {"workload": "1 GiB device copy; 8192^3 matrix products"}, "measured": out,
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(rec), flush=True)
+
+
 def run_heavy(args):
     """Large heavy-tailed Newton fit: N=1e7, P=500 Student-t(3), 50 nonzero coefficients,
     K=5e5 -- FP8 e4m3 information matrix + FP64 refinement against the FP64 Newton path.
@@ -980,14 +1024,14 @@ def main():
     ap.add_argument("--intervals-n", type=int, default=407_828, help="intervals: subjects")
     ap.add_argument("--intervals-p", type=int, default=1000, help="intervals: columns before the split")
     ap.add_argument("--workload", choices=["ccd", "serve", "mixed", "heavy", "paper", "intervals", "cv", "sparse", "legend", "bootstrap",
-                             "strata-sweep"], default="ccd",
+                             "strata-sweep", "peaks"], default="ccd",
                     help="ccd: the CCD fit of the N=1e6 P=50 workload (default); serve: the serving stream; "
                          "mixed: BF16 + FP64-refinement Newton fits at N=1e6 P=200; heavy: FP8 Newton at N=1e7 P=500; "
                          "paper: the Sec. 3.1 l1 CCD fit; intervals: a step-effect model split into interval strata; "
                          "cv: cross-validation over an l1 path plus bootstrap refits; sparse: the full-width "
                          "Sec. 3.2 fit on indicator X; legend: the full-width Sec. 3.2 analysis (CV, refit, bootstrap); "
                          "bootstrap: unpenalised bootstrap refits through the fit server; strata-sweep: time per "
-                         "coordinate across strata counts")
+                         "coordinate across strata counts; peaks: measured copy bandwidth and matrix-core rates")
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--plain-sample", type=int, default=32, help="serve: requests timed on the plain FP64 path")
     ap.add_argument("--poisson-seconds", type=float, default=30.0, help="serve: length of the Poisson run")
@@ -1014,6 +1058,9 @@ def main():
         return
     if args.workload == "heavy":
         run_heavy(args)
+        return
+    if args.workload == "peaks":
+        run_peaks(args)
         return
     if args.workload == "strata-sweep":
         run_strata_sweep(args)
