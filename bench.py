@@ -793,17 +793,22 @@ def run_strata_sweep(args):
     from paper_2310_16238_amd import coxmi, synth
 
     torch.cuda.set_device(0)
-    n, p = 1_000_000, 10
+    paper = args.sweep_design == "paper"
+    n, p, sweeps = (1_000_000, 1000, 2) if paper else (1_000_000, 10, 20)
     res = {}
-    for K in (1, 10, 1_000, 50_000, 250_000, 500_000):
-        d = synth.make("ar1", n, p, K, 50, beta_sd=0.3)
-        with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, gamma=1.0, tol=0.0, max_iter=20) as m:
+    for K in ((1, 10, 1_000, 50_000, 500_000) if paper else (1, 10, 1_000, 50_000, 250_000, 500_000)):
+        if paper:   # the Sec. 3.1 design: binary X with 5% ones, beta ~ N(0,1) x Bernoulli(0.2)
+            d = synth.config_paper(n=n, p=p, K=K)
+        else:
+            d = synth.make("ar1", n, p, K, 50, beta_sd=0.3)
+        with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, gamma=1.0, tol=0.0, max_iter=sweeps) as m:
             m.fit()   # warm
             kms = []
             for _ in range(3):
                 _, info = m.fit()
                 kms.append(m.kernel_ms())
-        us = 1e3 * float(np.median(kms)) / (20 * p)
+        del d
+        us = 1e3 * float(np.median(kms)) / (sweeps * p)
         res[K] = us
         log(f"K={K}: {us:.2f} us per coordinate ({info['iters']} sweeps)")
     vals = list(res.values())
@@ -811,7 +816,9 @@ def run_strata_sweep(args):
         "metric": "us per coordinate evaluation across strata counts", "value": max(vals) / min(vals),
         "unit": "max/min ratio", "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": None,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"N={n}, P={p} AR(1), the same rows cut into K strata, 20 CCD sweeps, seed 50"},
+        "config": {"workload": (f"N={n}, P={p} binary (5% ones, the Sec. 3.1 design), K strata, {sweeps} CCD sweeps, "
+                                f"seed 5") if paper else
+                               f"N={n}, P={p} AR(1), the same rows cut into K strata, {sweeps} CCD sweeps, seed 50"},
         "us_per_coordinate": {str(k): v for k, v in res.items()}, "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -1014,6 +1021,8 @@ def main():
     ap.add_argument("--paper-newton", action="store_true",
                     help="paper: also fit by proximal Newton with BF16 and FP8 information matrices")
     ap.add_argument("--bootstrap-reps", type=int, default=512, help="bootstrap: replicates")
+    ap.add_argument("--sweep-design", choices=["ar1", "paper"], default="ar1",
+                    help="strata-sweep: AR(1) P=10, or the Sec. 3.1 binary design at P=1000")
     ap.add_argument("--sparse-n", type=int, default=946_911, help="sparse: rows")
     ap.add_argument("--sparse-p", type=int, default=9977, help="sparse: indicator columns")
     ap.add_argument("--cv-n", type=int, default=946_911, help="cv: rows")
