@@ -246,9 +246,9 @@ void cox_intervals_release(cox_intervals *s);
  *   time, event, stratum : as in cox_data
  *   o        : options (mode COX_CCD, x_precision COX_F64; NULL = defaults)
  * The handle runs cox_fit (COX_CCD), cox_evaluate, cox_coordinate, cox_set_penalty,
- * cox_init_resample (the bits are gathered on the device), cox_cross_validate,
- * cox_bootstrap and the bookkeeping calls; cox_evaluate_full, Newton fits and
- * cox_init_intervals return COX_EUNSUPPORTED.  Errors: COX_EINVAL (bad arrays), COX_EUNSUPPORTED (sizes, options,
+ * cox_init_resample and cox_init_intervals (the bits are gathered on the device; the
+ * children hold indicator X too), cox_cross_validate, cox_bootstrap and the bookkeeping
+ * calls; cox_evaluate_full, cox_baseline_hazard and Newton fits return COX_EUNSUPPORTED.  Errors: COX_EINVAL (bad arrays), COX_EUNSUPPORTED (sizes, options,
  * n beyond the resident kernel), COX_ENOMEM, COX_EDEVICE. */
 int cox_init_indicator(cox_handle **out, int64_t n, int64_t p, const int64_t *col_ptr, const int32_t *row_idx,
                        const double *time, const uint8_t *event, const int32_t *stratum, const cox_options *o);
@@ -281,7 +281,8 @@ int cox_init_resample(cox_handle **out, const cox_handle *parent, const uint32_t
  * cox_split_intervals (same cuts and tv_coef rules, same row and column order, so
  * cox_layout's perm numbers its augmented rows), and each augmented column is
  * gathered from the parent's resident column (zero outside its interval for a step
- * coefficient).  Covariates that change between intervals need cox_split_intervals.
+ * coefficient; a parent on indicator X gives an indicator child, COX_CCD in FP64).
+ * Covariates that change between intervals need cox_split_intervals.
  *   parent           : a handle on the current device, built from n rows
  *   time, event,
  *   stratum          : host, the n rows the parent was built from (stratum may be NULL);

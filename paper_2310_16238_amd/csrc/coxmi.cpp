@@ -512,8 +512,8 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
                                            (int)h->p, h->stream);
         if (e == hipSuccess) e = (hipError_t)launch_event_sums(h->d_x, ld, h->d_meta, h->q(), (int)h->p, h->stream);
     } else if (e == hipSuccess) {
-        e = (hipError_t)launch_gather_bits(parent->d_xbits, parent->ldb, parent->shape.ipt, d_src, h->d_xbits, h->ldb,
-                                           h->shape.ipt, (int)h->p, h->stream);
+        e = (hipError_t)launch_gather_bits(parent->d_xbits, parent->ldb, parent->shape.ipt, d_src, nullptr, nullptr,
+                                           nullptr, h->d_xbits, h->ldb, h->shape.ipt, (int)h->p, h->stream);
         if (e == hipSuccess)
             e = (hipError_t)launch_event_sums_bits(h->d_xbits, h->ldb, h->shape.ipt, h->d_meta, h->q(), (int)h->p,
                                                    h->stream);
@@ -537,7 +537,6 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
     *out = nullptr;
     if (!parent) return fail(nullptr, COX_EINVAL, "parent is NULL");
-    if (!parent->d_x) return fail(nullptr, COX_EUNSUPPORTED, "the parent holds indicator X");
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != parent->device) return fail(nullptr, COX_EINVAL, "the parent handle lives on another device");
@@ -555,6 +554,8 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
         std::string msg;
         if (const int rc = check_options(opt, msg)) return fail(nullptr, rc, msg);
     }
+    if (!parent->d_x && (opt.mode != COX_CCD || opt.x_precision != COX_F64))
+        return fail(nullptr, COX_EUNSUPPORTED, "indicator X runs COX_CCD fits in COX_F64");
     IntervalRows rows;
     try {
         const int rc = interval_rows(n, time, event, stratum, ncuts, cuts, tv_coef, p, rows);
@@ -592,6 +593,13 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
         delete h;
         return fail(nullptr, COX_EUNSUPPORTED, "parent layout too long for 32-bit row indices");
     }
+    if (!parent->d_x) {
+        if (h->shape.ipt == 0) {
+            delete h;
+            return fail(nullptr, COX_EUNSUPPORTED, "indicator X needs the persistent kernel's layout");
+        }
+        h->ldb = ld / h->shape.ipt;
+    }
     // maps: [0, ld) source row, [ld, 2 ld) interval of each device row, then column source and interval
     std::vector<int32_t> maps((size_t)(2 * ld + 2 * paug), -1);
     {
@@ -617,10 +625,18 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
     }
     e = upload_meta(h);
     if (e == hipSuccess) e = hipMemcpy(d_maps, maps.data(), sizeof(int32_t) * maps.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
+    if (e == hipSuccess && parent->d_x) {
         e = (hipError_t)launch_gather_rows(parent->d_x, parent->shape.ld, d_maps, d_maps + ld, d_maps + 2 * ld,
                                            d_maps + 2 * ld + paug, h->d_x, ld, (int)paug, h->stream);
-    if (e == hipSuccess) e = (hipError_t)launch_event_sums(h->d_x, ld, h->d_meta, h->q(), (int)paug, h->stream);
+        if (e == hipSuccess) e = (hipError_t)launch_event_sums(h->d_x, ld, h->d_meta, h->q(), (int)paug, h->stream);
+    } else if (e == hipSuccess) {
+        e = (hipError_t)launch_gather_bits(parent->d_xbits, parent->ldb, parent->shape.ipt, d_maps, d_maps + ld,
+                                           d_maps + 2 * ld, d_maps + 2 * ld + paug, h->d_xbits, h->ldb, h->shape.ipt,
+                                           (int)paug, h->stream);
+        if (e == hipSuccess)
+            e = (hipError_t)launch_event_sums_bits(h->d_xbits, h->ldb, h->shape.ipt, h->d_meta, h->q(), (int)paug,
+                                                   h->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     (void)hipFree(d_maps);
     if (e == hipSuccess) e = upload_tables(h);

@@ -79,20 +79,29 @@ __global__ __launch_bounds__(kQBlock) void event_sums_kernel(const double *__res
 // Indicator columns: child unit u of column j (ipt_out bits, unit of us_out bytes) takes
 // bit i from the parent's row src[u * ipt_out + i] (bit (s % ipt_in) of the parent's unit
 // s / ipt_in, units of us_in bytes, little-endian).  Grid: (ceil(ldb_out / 256), p).
+// With rint / col_src / col_int (device, may be NULL), column j takes the parent's column
+// col_src[j] and, when col_int[j] >= 0, only the rows whose rint equals it (a step coefficient).
 __global__ __launch_bounds__(256) void gather_bits_kernel(const uint8_t *__restrict__ b_in, int64_t ldb_in, int ipt_in,
                                                           int us_in, const int32_t *__restrict__ src,
+                                                          const int32_t *__restrict__ rint,
+                                                          const int32_t *__restrict__ col_src,
+                                                          const int32_t *__restrict__ col_int,
                                                           uint8_t *__restrict__ b_out, int64_t ldb_out, int ipt_out,
                                                           int us_out)
 {
     const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (u >= ldb_out) return;
     const int64_t j = blockIdx.y;
+    const int64_t js = col_src ? col_src[j] : j;
+    const int jk = col_int ? col_int[j] : -1;
     uint32_t v = 0u;
     for (int i = 0; i < ipt_out; ++i) {
-        const int32_t s = src[u * ipt_out + i];
+        const int64_t r = u * ipt_out + i;
+        const int32_t s = src[r];
         if (s < 0) continue;
+        if (jk >= 0 && rint[r] != jk) continue;
         const int bit = s % ipt_in;
-        const uint8_t byte = b_in[(j * ldb_in + s / ipt_in) * us_in + bit / 8];
+        const uint8_t byte = b_in[(js * ldb_in + s / ipt_in) * us_in + bit / 8];
         v |= (uint32_t)((byte >> (bit % 8)) & 1u) << i;
     }
     uint8_t *o = b_out + (j * ldb_out + u) * us_out;
@@ -139,14 +148,15 @@ int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, co
     return (int)hipGetLastError();
 }
 
-int launch_gather_bits(const void *b_in, int64_t ldb_in, int ipt_in, const int32_t *src, void *b_out, int64_t ldb_out,
-                       int ipt_out, int p, hipStream_t stream)
+int launch_gather_bits(const void *b_in, int64_t ldb_in, int ipt_in, const int32_t *src, const int32_t *rint,
+                       const int32_t *col_src, const int32_t *col_int, void *b_out, int64_t ldb_out, int ipt_out, int p,
+                       hipStream_t stream)
 {
     if (ldb_out <= 0 || p <= 0) return (int)hipSuccess;
     const dim3 grid((unsigned)((ldb_out + 255) / 256), (unsigned)p);
     hipLaunchKernelGGL(gather_bits_kernel, grid, dim3(256), 0, stream, static_cast<const uint8_t *>(b_in), ldb_in,
-                       ipt_in, ipt_in > 8 ? 2 : 1, src, static_cast<uint8_t *>(b_out), ldb_out, ipt_out,
-                       ipt_out > 8 ? 2 : 1);
+                       ipt_in, ipt_in > 8 ? 2 : 1, src, rint, col_src, col_int, static_cast<uint8_t *>(b_out), ldb_out,
+                       ipt_out, ipt_out > 8 ? 2 : 1);
     return (int)hipGetLastError();
 }
 

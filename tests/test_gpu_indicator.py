@@ -81,7 +81,10 @@ def test_indicator_repeated_indices_and_errors():
             a.evaluate_full(np.zeros(5))
         assert e.value.code == coxmi.COX_EUNSUPPORTED
         with pytest.raises(coxmi.CoxError) as e:
-            a.intervals(d.time, d.event, d.stratum, [0.5])
+            a.baseline_hazard(np.zeros(5))
+        assert e.value.code == coxmi.COX_EUNSUPPORTED
+        with pytest.raises(coxmi.CoxError) as e:
+            a.intervals(d.time, d.event, d.stratum, [0.5], mode=coxmi.COX_NEWTON_REFINE)
         assert e.value.code == coxmi.COX_EUNSUPPORTED
     bad = idx.copy()
     bad[0] = 4000
@@ -154,3 +157,32 @@ def test_indicator_resample_cv_bootstrap_equal_dense(n, K):
         Xr, tr, er, sr = orc.resample(d.X, d.time, d.event, d.stratum, keep)
         ref = orc.fit_ccd(Xr, tr, er, sr, gamma=3.0, tol=1e-12)
         assert np.array_equal(bb == 0.0, ref.beta == 0.0) and _rel(bb, ref.beta) <= 1e-10
+
+
+def test_indicator_intervals_equal_dense():
+    """The interval-stratified model (Secs. 2.2-2.3, step coefficients on two columns) built on
+    the device from an indicator parent equals the one built from a dense parent, bit for bit,
+    and meets the oracle's fit of its own split."""
+    n, p = 40_000, 16
+    d = synth.make("binary", n, p, 8, 221, beta_sd=1.0, beta_nonzero=0.4, density=0.08, tie_round=50.0)
+    d.X[:, 0] = (np.random.default_rng(3).random(n) < 0.5).astype(np.float64)    # a treatment indicator
+    ptr, idx = _csc(d.X)
+    cuts = [float(np.quantile(d.time, 0.2)), float(np.quantile(d.time, 0.6))]
+    tv = np.zeros(p, np.uint8)
+    tv[[0, 5]] = 1
+    r = orc.split_intervals(d.X, d.time, d.event, d.stratum, cuts, tv_coef=tv)
+    pa = r["X"].shape[1]
+    pen = np.ones(pa, np.uint8)
+    pen[r["col_source"] == 0] = 0
+    _say(f"indicator intervals n={n} p={p} -> n_aug={r['X'].shape[0]} p_aug={pa}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum) as md, \
+            coxmi.CoxModel.indicator(n, ptr, idx, d.time, d.event, d.stratum) as mb:
+        with md.intervals(d.time, d.event, d.stratum, cuts, tv, gamma=2.0, penalize=pen, tol=1e-13) as cd, \
+                mb.intervals(d.time, d.event, d.stratum, cuts, tv, gamma=2.0, penalize=pen, tol=1e-13) as cb:
+            assert np.array_equal(cd.layout()[0], cb.layout()[0]) and np.array_equal(cd.layout()[1], cb.layout()[1])
+            bd, _ = cd.fit()
+            bb, info = cb.fit()
+    assert np.array_equal(bd, bb)
+    ref = orc.fit_ccd(r["X"], r["time"], r["event"], r["stratum"], gamma=2.0, penalize=pen, tol=1e-13)
+    assert ref.converged and info["status"] == coxmi.COX_OK
+    assert np.array_equal(bb == 0.0, ref.beta == 0.0) and _rel(bb, ref.beta) <= 1e-10
