@@ -324,3 +324,44 @@ def config_legend_sparse(n: int = 946_911, p: int = 9977, K: int = 10, density: 
     Y, event = _times(rng, eta, lam[stratum], 0.0)
     return SparseCoxData(n=n, col_ptr=col_ptr, row_idx=row_idx, time=Y, event=event, stratum=stratum,
                          beta_true=b, gamma=math.sqrt(2.0), name=f"legend-sparse-n{n}-p{p}-K{K}")
+
+
+def config_cough_sparse(n: int = 407_828, p: int = 9666, density: float = 0.03, cut: float = 10.0,
+                        log_hr=(math.log(2.0), math.log(1.1)), seed: int = 11) -> SparseCoxData:
+    """Sec. 3.3 at its full width on indicator X: column 0 a treatment indicator (half the
+    subjects) whose log hazard ratio is log_hr[0] before `cut` days and log_hr[1] after,
+    columns 1..p-1 indicators with `density` ones (drawn as geometric gaps), coefficients
+    N(0, 0.01) x Bernoulli(0.2) (so the baseline covariates' linear predictor has sd ~0.8, and
+    few subjects leave before the cut); piecewise-exponential event times (baseline rate 1/365 per
+    day), censoring Exp(1/500), whole days; one stratum.  beta_true[0] = 0 (the treatment
+    effect is log_hr)."""
+    rng = np.random.default_rng(seed)
+    cols = [np.flatnonzero(rng.random(n) < 0.5).astype(np.int32)]
+    for _ in range(1, p):
+        gaps = rng.geometric(density, size=int(n * density * 1.2) + 64)
+        pos = np.cumsum(gaps) - 1
+        while pos[-1] < n - 1:
+            more = np.cumsum(rng.geometric(density, size=int(n * density * 0.2) + 64)) + pos[-1]
+            pos = np.concatenate([pos, more])
+        cols.append(pos[pos < n].astype(np.int32))
+    col_ptr = np.zeros(p + 1, dtype=np.int64)
+    col_ptr[1:] = np.cumsum([c.size for c in cols])
+    row_idx = np.concatenate(cols)
+    b = rng.normal(0.0, 0.1, size=p) * (rng.random(p) < 0.2)
+    b[0] = 0.0
+    eta = np.zeros(n)
+    for j in np.flatnonzero(b):
+        eta[cols[j]] += b[j]
+    treat = np.zeros(n)
+    treat[cols[0]] = 1.0
+    base = 1.0 / 365.0
+    a_rate = base * np.exp(eta + treat * log_hr[0])
+    b_rate = base * np.exp(eta + treat * log_hr[1])
+    E = rng.exponential(1.0, size=n)
+    T = np.where(E < a_rate * cut, E / a_rate, cut + (E - a_rate * cut) / b_rate)
+    C = rng.exponential(1.0, size=n) * 500.0
+    event = (T <= C).astype(np.uint8)
+    Y = np.maximum(np.ceil(np.minimum(T, C)), 1.0)
+    return SparseCoxData(n=n, col_ptr=col_ptr, row_idx=row_idx, time=Y, event=event,
+                         stratum=np.zeros(n, dtype=np.int32), beta_true=b, gamma=math.sqrt(2.0),
+                         name=f"cough-sparse-n{n}-p{p}")
