@@ -315,7 +315,9 @@ int cox_set_penalty(cox_handle *h, double gamma, const uint8_t *penalize);
  *   h       : handle on the full data (used for l; its options give the mode --
  *             COX_CCD, or COX_NEWTON_REFINE for proximal Newton fits --, tol, max_iter,
  *             precision and stream of the fold fits)
- *   fold    : host, n entries in [0, nfolds); every fold non-empty and not all rows
+ *   fold    : host, n entries in [0, nfolds); every fold non-empty and not all rows.  On
+ *             an interval-stratified handle (cox_init_intervals, cox_split_intervals) give
+ *             all rows of one subject the same fold, so that a subject is held out whole
  *   gammas  : host, ngamma finite values >= 0 (a decreasing path warm-starts best)
  *   penalize: host, p flags or NULL (all columns penalised)
  *   cvl     : host, ngamma outputs; betas: host [nfolds][ngamma][p] or NULL;
