@@ -57,18 +57,22 @@ typedef struct cox_handle cox_handle; /* opaque; owns all device state of one da
 typedef struct {
     int64_t n;               /* rows (observations), >= 1 */
     int64_t p;               /* columns (covariates), >= 1 */
-    const double *x;         /* host, column-major n x p, leading dimension ldx >= n */
+    const double *x;         /* column-major n x p, leading dimension ldx >= n */
     int64_t ldx;
-    const double *time;      /* host, n observed times Y (finite) */
-    const uint8_t *event;    /* host, n event indicators delta in {0, 1} */
-    const int32_t *stratum;  /* host, n stratum labels (any int32 values); NULL = one stratum */
+    const double *time;      /* n observed times Y (finite) */
+    const uint8_t *event;    /* n event indicators delta in {0, 1} */
+    const int32_t *stratum;  /* n stratum labels (any int32 values); NULL = one stratum */
+    int on_device;           /* 0: the four arrays are host memory; 1: device memory of the
+                                current device (e.g. torch tensors), see cox_init */
 } cox_data;
 
 typedef struct {
     double gamma;             /* l1 strength gamma >= 0 (Sec. 2.1); 0 = unpenalised */
     const uint8_t *penalize;  /* host, p flags: 1 = column penalised; NULL = all columns */
     int mode;                 /* COX_CCD or COX_NEWTON_REFINE */
-    int x_precision;          /* contraction precision: COX_F64 or COX_BF16 (F32/FP8: COX_EUNSUPPORTED) */
+    int x_precision;          /* contraction precision: COX_F64 or COX_BF16; COX_FP8_E4M3 in mode
+                                 COX_NEWTON_REFINE only (p <= 4096); COX_F32: COX_EUNSUPPORTED
+                                 (the fit server's precision) */
     int ties;                 /* COX_BRESLOW */
     double tol;               /* stop when the largest |step| of a CCD sweep or Newton step <= tol * max(1, max|beta|) */
     int max_iter;             /* maximum number of CCD sweeps or Newton iterations */
@@ -94,17 +98,25 @@ void cox_default_options(cox_options *o);
  * strata).  Validates the inputs, sorts rows by (stratum ascending, time
  * descending, original index ascending) (Sec. 2.7), marks stratum heads and
  * tie groups, copies X into device memory in that order, and precomputes
- * delta'X_j for every column (first term of Eq. strat_g).
+ * delta'X_j for every column (first term of Eq. strat_g; summed on the device in
+ * a fixed order, so both sources of X below give the same handle bit for bit).
  *   out : receives the handle (set to NULL on error)
- *   d   : data; all pointers host memory, read only during the call
+ *   d   : data, read only during the call.  d->on_device = 0: host arrays.
+ *         d->on_device = 1: device memory of the current device, read after the
+ *         work already queued on o->stream (the caller orders any other producer
+ *         stream before the call); the keys (time, event, stratum) are copied to the
+ *         host for the canonical order, X is gathered into that order on the device
+ *         (only a 4-byte source index per row crosses PCIe).  Each array must lie
+ *         inside one allocation (x: ldx * (p - 1) + n doubles), else COX_EINVAL.
  *   o   : options (NULL = defaults); penalize is copied
  * Errors: COX_EINVAL (n < 1, p < 1, ldx < n, NULL x/time/event, non-finite
- * time, event not 0/1), COX_EUNSUPPORTED (p > 12288, or p > 4096 in mode
+ * time, event not 0/1, on_device arrays not in device memory of the current
+ * device), COX_EUNSUPPORTED (p > 12288, or p > 4096 in mode
  * COX_NEWTON_REFINE -- cox_evaluate_full also needs p <= 4096; in mode COX_CCD, n
  * beyond the persistent kernel's register-resident capacity of about
  * CUs x 512 x 16 rows -- a COX_NEWTON_REFINE handle of that size is created,
- * and then supports cox_fit and cox_evaluate_full only; an x_precision other
- * than COX_F64 / COX_BF16),
+ * and then supports cox_fit and cox_evaluate_full only; x_precision COX_F32, or
+ * COX_FP8_E4M3 outside mode COX_NEWTON_REFINE),
  * COX_ENOMEM, COX_EDEVICE.  On error *out is NULL and the
  * message is available through cox_last_error(NULL).
  */
@@ -159,8 +171,9 @@ int cox_evaluate(cox_handle *h, const double *beta, double *objective, double *g
  * over X per product).  Outputs (host, any may be NULL): objective (-log L of
  * Eq. strat_l plus the l1 penalty), grad (p), hess_diag (p), info (p x p,
  * row-major, symmetric).  objective, grad and hess_diag are FP64; info is
- * formed in the handle's x_precision (FP64, or BF16 on the matrix cores with
- * FP32 accumulation) and returned as FP64.
+ * formed in the handle's x_precision (FP64; BF16, or FP8 e4m3 for a
+ * COX_NEWTON_REFINE handle, on the matrix cores with FP32 accumulation) and
+ * returned as FP64.
  */
 int cox_evaluate_full(cox_handle *h, const double *beta, double *objective, double *grad, double *hess_diag,
                       double *info);
@@ -302,7 +315,8 @@ int cox_init_intervals(cox_handle **out, const cox_handle *parent, const double 
 
 /* Replace h's l1 weights: gamma_j = gamma for penalised columns (penalize: host,
  * p flags, NULL = all), 0 otherwise.  COX_EINVAL for a negative or non-finite
- * gamma; COX_EUNSUPPORTED for gamma != 0 on a COX_NEWTON_REFINE handle. */
+ * gamma.  On a COX_NEWTON_REFINE handle nonzero weights make cox_fit take proximal
+ * Newton steps (see cox_fit). */
 int cox_set_penalty(cox_handle *h, double gamma, const uint8_t *penalize);
 
 /* K-fold cross-validation of the l1 weight along a path (Sec. 2.1).  For fold k
@@ -447,7 +461,8 @@ int cox_server_create(cox_server **out, const cox_server_options *o);
 
 /* Queue one fit; returns at once with its ticket (tickets start at 1).
  *   d     : data as for cox_init (stratum may be NULL): host memory, or device
- *           memory with COX_SUBMIT_DEVICE
+ *           memory with COX_SUBMIT_DEVICE (d->on_device = 1 means the same); each
+ *           device array must lie inside one allocation, as for cox_init
  *   flags : 0 (inputs copied), COX_SUBMIT_BORROW and/or COX_SUBMIT_DEVICE
  * Errors: COX_EINVAL (the checks of cox_init), COX_EUNSUPPORTED (p > 128),
  * or the server's fatal device error.  A request whose device footprint

@@ -43,7 +43,7 @@ class cox_data(ctypes.Structure):
                 ("x", ctypes.POINTER(ctypes.c_double)), ("ldx", ctypes.c_int64),
                 ("time", ctypes.POINTER(ctypes.c_double)),
                 ("event", ctypes.POINTER(ctypes.c_uint8)),
-                ("stratum", ctypes.POINTER(ctypes.c_int32))]
+                ("stratum", ctypes.POINTER(ctypes.c_int32)), ("on_device", ctypes.c_int)]
 
 
 class cox_intervals(ctypes.Structure):
@@ -218,6 +218,40 @@ def cox_init(X, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-1
         o.penalize = pen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     if stream is not None:
         o.stream = ctypes.c_void_p(int(stream))
+    h = ctypes.c_void_p()
+    rc = lib().cox_init(ctypes.byref(h), ctypes.byref(d), ctypes.byref(o))
+    _check(None, rc)
+    return h.value
+
+
+def _device_data(X, time, event, stratum):
+    """cox_data over device-resident torch tensors (checked here for shape and dtype only;
+    the library checks that every array lies in device memory)."""
+    import torch
+    n, p = X.shape
+    if X.dtype != torch.float64 or not X.is_cuda or X.stride(0) != 1 or X.stride(1) < n:
+        raise ValueError("X must be a float64 CUDA tensor with unit row stride (column-major)")
+    checks = [(time, torch.float64), (event, torch.uint8)] + ([(stratum, torch.int32)] if stratum is not None else [])
+    for t, dt in checks:
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("time / event / stratum must be contiguous CUDA tensors of n float64 / uint8 / int32")
+    d = cox_data(n=n, p=p, x=ctypes.cast(X.data_ptr(), _DP), ldx=X.stride(1),
+                 time=ctypes.cast(time.data_ptr(), _DP),
+                 event=ctypes.cast(event.data_ptr(), ctypes.POINTER(ctypes.c_uint8)), on_device=1)
+    if stratum is not None:
+        d.stratum = ctypes.cast(stratum.data_ptr(), ctypes.POINTER(ctypes.c_int32))
+    return d
+
+
+def cox_init_device(X, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-12, max_iter=1000,
+                    stream=None, mode=COX_CCD, x_precision=COX_F64):
+    """cox_init on device-resident data: X a float64 CUDA tensor with unit row stride
+    (column-major, e.g. the transpose of a contiguous p x n tensor), time float64, event
+    uint8, stratum int32 or None (contiguous CUDA tensors).  The library reads them after
+    the work queued on `stream` (default: the default stream); order other producers first."""
+    d = _device_data(X, time, event, stratum)
+    keep = []
+    o = _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep)
     h = ctypes.c_void_p()
     rc = lib().cox_init(ctypes.byref(h), ctypes.byref(d), ctypes.byref(o))
     _check(None, rc)
@@ -545,6 +579,13 @@ class CoxModel:
         self.h = cox_init(X, time, event, stratum, **opts)
 
     @classmethod
+    def from_device(cls, X, time, event, stratum=None, **opts):
+        """A CoxModel on device-resident torch tensors (see cox_init_device)."""
+        m = cls.__new__(cls)
+        m.h = cox_init_device(X, time, event, stratum, **opts)
+        return m
+
+    @classmethod
     def indicator(cls, n, col_ptr, row_idx, time, event, stratum=None, **opts):
         """A CoxModel on indicator X in compressed sparse columns (see cox_init_indicator)."""
         m = cls.__new__(cls)
@@ -668,19 +709,8 @@ class CoxServer:
         contiguous p x n tensor), time float64, event uint8, stratum int32 or
         None.  The tensors are read in place and kept referenced until the
         result is collected; the caller synchronises the stream that wrote them."""
-        import torch
         n, p = X.shape
-        if X.dtype != torch.float64 or not X.is_cuda or X.stride(0) != 1 or X.stride(1) < n:
-            raise ValueError("X must be a float64 CUDA tensor with unit row stride")
-        checks = [(time, torch.float64), (event, torch.uint8)] + ([(stratum, torch.int32)] if stratum is not None else [])
-        for t, dt in checks:
-            if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
-                raise ValueError("time / event / stratum must be contiguous CUDA tensors of n float64 / uint8 / int32")
-        d = cox_data(n=n, p=p, x=ctypes.cast(X.data_ptr(), ctypes.POINTER(ctypes.c_double)), ldx=X.stride(1),
-                     time=ctypes.cast(time.data_ptr(), ctypes.POINTER(ctypes.c_double)),
-                     event=ctypes.cast(event.data_ptr(), ctypes.POINTER(ctypes.c_uint8)))
-        if stratum is not None:
-            d.stratum = ctypes.cast(stratum.data_ptr(), ctypes.POINTER(ctypes.c_int32))
+        d = _device_data(X, time, event, stratum)
         t = ctypes.c_uint64()
         self._check(lib().cox_server_submit(self.h, ctypes.byref(d), COX_SUBMIT_DEVICE, ctypes.byref(t)))
         self._keep[t.value] = [X, time, event, stratum]

@@ -225,6 +225,57 @@ static int layout_for(cox_handle *h, std::string &err)
     return rc;
 }
 
+bool coxmi::device_range_ok(const void *ptr, size_t bytes, int device)
+{
+    if (!ptr) return false;
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess ||
+        (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) || a.device != device) {
+        (void)hipGetLastError();
+        return false;
+    }
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void *>(ptr)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const char *b = static_cast<const char *>(base), *q = static_cast<const char *>(ptr);
+    if (q < b || (size_t)(q - b) > size) return false;
+    return bytes <= size - (size_t)(q - b);
+}
+
+// Host copies of device-resident keys (time, event, stratum), read on `stream` after the
+// work already queued there.  Returns nullptr or a message.
+static const char *copy_keys(const cox_data *d, hipStream_t stream, std::vector<double> &time,
+                             std::vector<uint8_t> &event, std::vector<int32_t> &stratum)
+{
+    const int64_t n = d->n, p = d->p;
+    if (n < 1 || p < 1) return "need n >= 1 and p >= 1";
+    if (d->ldx < n) return "ldx < n";
+    if (!d->x || !d->time || !d->event) return "x, time and event are required";
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "cannot query the current device";
+    const size_t xbytes = sizeof(double) * ((size_t)d->ldx * (size_t)(p - 1) + (size_t)n);
+    if (!device_range_ok(d->x, xbytes, dev) || !device_range_ok(d->time, sizeof(double) * (size_t)n, dev) ||
+        !device_range_ok(d->event, (size_t)n, dev) ||
+        (d->stratum && !device_range_ok(d->stratum, sizeof(int32_t) * (size_t)n, dev)))
+        return "on_device data must lie in device memory of the current device (x: ldx * (p - 1) + n doubles)";
+    time.resize((size_t)n);
+    event.resize((size_t)n);
+    if (d->stratum) stratum.resize((size_t)n);
+    hipError_t e = hipMemcpyAsync(time.data(), d->time, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(event.data(), d->event, (size_t)n, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess && d->stratum)
+        e = hipMemcpyAsync(stratum.data(), d->stratum, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return "copying the device-resident keys failed";
+    }
+    return nullptr;
+}
+
 extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *o)
 {
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
@@ -232,7 +283,6 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     if (!d) return fail(nullptr, COX_EINVAL, "data is NULL");
     const int64_t n = d->n, p = d->p;
     if (n > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "n exceeds 2^29 - 1");
-    if (const char *bad = check_data(n, p, d->ldx, d->x, d->time, d->event)) return fail(nullptr, COX_EINVAL, bad);
     cox_options opt;
     if (o) opt = *o;
     else cox_default_options(&opt);
@@ -240,6 +290,21 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
         std::string msg;
         if (const int rc = check_options(opt, msg)) return fail(nullptr, rc, msg);
     }
+    // the keys on the host: the caller's arrays, or copies of device-resident ones
+    const double *time = d->time;
+    const uint8_t *event = d->event;
+    const int32_t *stratum = d->stratum;
+    std::vector<double> time_h;
+    std::vector<uint8_t> event_h;
+    std::vector<int32_t> stratum_h;
+    if (d->on_device) {
+        if (const char *bad = copy_keys(d, static_cast<hipStream_t>(opt.stream), time_h, event_h, stratum_h))
+            return fail(nullptr, COX_EINVAL, bad);
+        time = time_h.data();
+        event = event_h.data();
+        stratum = d->stratum ? stratum_h.data() : nullptr;
+    }
+    if (const char *bad = check_data(n, p, d->ldx, d->x, time, event)) return fail(nullptr, COX_EINVAL, bad);
     if (p > kMaxCcdP || (opt.mode == COX_NEWTON_REFINE && p > kMaxNewtonP))
         return fail(nullptr, COX_EUNSUPPORTED, "p exceeds 12288 (COX_CCD) or 4096 (COX_NEWTON_REFINE)");
     if (opt.x_precision == COX_FP8_E4M3 && p > kMaxFp8P)
@@ -254,7 +319,7 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
     (void)hipGetDevice(&h->device);
 
     // canonical order: stratum ascending, time descending, original index ascending
-    canonical_order(n, d->time, d->event, d->stratum, h->perm, h->meta);
+    canonical_order(n, time, event, stratum, h->perm, h->meta);
 
     h->gamma.assign(p, opt.gamma);
     if (o && o->penalize)
@@ -275,21 +340,31 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
         return hip_fail(nullptr, e, "device allocation");
     }
     e = upload_meta(h);
-    // X in canonical order at the layout positions, column by column, and q_j = delta'X_j
-    std::vector<double> col(ld, 0.0), q(p, 0.0);
-    for (int64_t j = 0; j < p && e == hipSuccess; ++j) {
-        const double *xj = d->x + j * d->ldx;
-        double qj = 0.0;
-        for (int64_t i = 0; i < n; ++i) {
-            const int64_t r = h->perm[i];
-            const double v = xj[r];
-            col[h->pos[i]] = v;
-            if (d->event[r]) qj += v;
+    if (d->on_device) {
+        // X gathered on the device into canonical order at the layout positions: only the
+        // 4-byte source row of each device row crosses PCIe
+        std::vector<int32_t> src((size_t)ld, -1);
+        for (int64_t i = 0; i < n; ++i) src[(size_t)h->pos[i]] = (int32_t)h->perm[i];
+        int32_t *d_src = nullptr;
+        if (e == hipSuccess) e = hipMalloc(&d_src, sizeof(int32_t) * (size_t)ld);
+        if (e == hipSuccess) e = hipMemcpy(d_src, src.data(), sizeof(int32_t) * (size_t)ld, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = (hipError_t)launch_gather_rows(d->x, d->ldx, d_src, nullptr, nullptr, nullptr, h->d_x, ld, (int)p,
+                                               h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (d_src) (void)hipFree(d_src);
+    } else {
+        // X in canonical order at the layout positions, column by column
+        std::vector<double> col(ld, 0.0);
+        for (int64_t j = 0; j < p && e == hipSuccess; ++j) {
+            const double *xj = d->x + j * d->ldx;
+            for (int64_t i = 0; i < n; ++i) col[h->pos[i]] = xj[h->perm[i]];
+            e = hipMemcpy(h->d_x + j * ld, col.data(), sizeof(double) * ld, hipMemcpyHostToDevice);
         }
-        q[j] = qj;
-        e = hipMemcpy(h->d_x + j * ld, col.data(), sizeof(double) * ld, hipMemcpyHostToDevice);
     }
-    if (e == hipSuccess) e = hipMemcpy(h->q(), q.data(), sizeof(double) * p, hipMemcpyHostToDevice);
+    // q_j = delta'X_j, summed on the device in a fixed order (the same for either source of X)
+    if (e == hipSuccess) e = (hipError_t)launch_event_sums(h->d_x, ld, h->d_meta, h->q(), (int)p, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e == hipSuccess) e = upload_tables(h);
     if (e != hipSuccess) {
         free_device(h);
@@ -530,6 +605,37 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
     return COX_OK;
 }
 
+// Checks that (time, event, stratum) are the keys the parent's canonical order was built
+// from: in the parent's order, the events match, each parent stratum carries one label
+// (labels increasing from stratum to stratum), times do not increase within a stratum, and
+// the tie groups with events -- runs of equal times -- end where the parent's row words say,
+// with the same event counts.  O(n); returns nullptr or a message.
+static const char *same_keys_as_parent(const cox_handle *parent, const double *time, const uint8_t *event,
+                                       const int32_t *stratum)
+{
+    const int64_t n = parent->n;
+    uint32_t group_events = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        const uint32_t w = parent->meta[(size_t)c];
+        const int64_t r = parent->perm[(size_t)c];
+        if (((w & kEventBit) != 0u) != (event[r] != 0)) return "event is not the data the parent was built from";
+        if (c > 0) {
+            const int64_t rp = parent->perm[(size_t)(c - 1)];
+            const int32_t sp = stratum ? stratum[rp] : 0, sc = stratum ? stratum[r] : 0;
+            if ((w & kHeadBit) ? !(sc > sp) : (sc != sp)) return "stratum is not the data the parent was built from";
+            if (!(w & kHeadBit) && time[r] > time[rp]) return "time is not the data the parent was built from";
+        } else if (!(w & kHeadBit)) {
+            return "the parent's layout has no head row";
+        }
+        group_events += event[r] ? 1u : 0u;
+        const bool last = c + 1 == n || (parent->meta[(size_t)(c + 1)] & kHeadBit) != 0u ||
+                          time[parent->perm[(size_t)(c + 1)]] != time[r];
+        if ((w & kCountMask) != (last ? group_events : 0u)) return "time is not the data the parent was built from";
+        if (last) group_events = 0;
+    }
+    return nullptr;
+}
+
 extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, const double *time,
                                   const uint8_t *event, const int32_t *stratum, int ncuts, const double *cuts,
                                   const uint8_t *tv_coef, const cox_options *o)
@@ -544,9 +650,8 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
     if (!time || !event) return fail(nullptr, COX_EINVAL, "time and event are required");
     for (int64_t i = 0; i < n; ++i)
         if (!std::isfinite(time[i]) || event[i] > 1) return fail(nullptr, COX_EINVAL, "time must be finite, event 0 or 1");
-    for (int64_t c = 0; c < n; ++c)
-        if (((parent->meta[(size_t)c] & kEventBit) != 0u) != (event[parent->perm[(size_t)c]] != 0))
-            return fail(nullptr, COX_EINVAL, "time and event are not the data the parent was built from");
+    if (const char *bad = same_keys_as_parent(parent, time, event, stratum))
+        return fail(nullptr, COX_EINVAL, bad);
     cox_options opt;
     if (o) opt = *o;
     else opt = parent->opt;

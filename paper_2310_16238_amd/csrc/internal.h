@@ -81,6 +81,10 @@ int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, co
 // q[j] = sum of x[j][r] over the rows whose word has the event bit (fixed-order sums).
 int launch_event_sums(const double *x, int64_t ld, const uint32_t *meta, double *q, int p, hipStream_t stream);
 
+// True when [ptr, ptr + bytes) lies inside one device (or managed) allocation of `device`
+// (host code; clears the HIP error state when the pointer is not device memory).
+bool device_range_ok(const void *ptr, size_t bytes, int device);
+
 // Segmented +scan of n doubles on device memory; returns a COX_* code.
 int segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, hipStream_t stream);
 

@@ -904,23 +904,23 @@ extern "C" int cox_server_submit(cox_server *s, const cox_data *d, int flags, ui
     if (!s) return COX_EINVAL;
     if (!d || !ticket) return srv_fail(s, COX_EINVAL, "data and ticket are required");
     if (flags & ~(COX_SUBMIT_BORROW | COX_SUBMIT_DEVICE)) return srv_fail(s, COX_EINVAL, "unknown submit flags");
-    const bool dev = (flags & COX_SUBMIT_DEVICE) != 0;
+    const bool dev = (flags & COX_SUBMIT_DEVICE) != 0 || d->on_device;
     if (dev) {
         // shape and placement now; the keys are checked once the prep thread has them
         if (d->n < 1 || d->p < 1 || d->ldx < d->n || d->n > (int64_t)kCountMask)
             return srv_fail(s, COX_EINVAL, "need n >= 1, p >= 1, ldx >= n, n < 2^29");
         const void *ptrs[4] = {d->x, d->time, d->event, d->stratum};
+        const size_t n = (size_t)d->n;
+        const size_t bytes[4] = {sizeof(double) * ((size_t)d->ldx * (size_t)(d->p - 1) + n), sizeof(double) * n, n,
+                                 sizeof(int32_t) * n};
         for (int k = 0; k < 4; ++k) {
             if (!ptrs[k]) {
                 if (k == 3) continue;
                 return srv_fail(s, COX_EINVAL, "x, time and event are required");
             }
-            hipPointerAttribute_t a{};
-            if (hipPointerGetAttributes(&a, ptrs[k]) != hipSuccess ||
-                (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) || a.device != s->device) {
-                (void)hipGetLastError();
-                return srv_fail(s, COX_EINVAL, "COX_SUBMIT_DEVICE needs device memory of the server's device");
-            }
+            if (!device_range_ok(ptrs[k], bytes[k], s->device))
+                return srv_fail(s, COX_EINVAL, "COX_SUBMIT_DEVICE needs device memory of the server's device, "
+                                               "each array inside one allocation");
         }
     } else if (const char *bad = check_data(d->n, d->p, d->ldx, d->x, d->time, d->event)) {
         return srv_fail(s, COX_EINVAL, bad);

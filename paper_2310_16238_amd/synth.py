@@ -128,7 +128,17 @@ def _linear_predictor(X, beta):
     return eta
 
 
-def _times(rng, eta, lam_row, tie_round):
+def _times(rng, eta, lam_row, tie_round, log_time=False):
+    if log_time:
+        # On the log scale: log T = log E - log lambda - eta and log C = log E' - log lambda
+        # never overflow, whatever the range of eta (exp(eta) would for |eta| > 709).  The
+        # returned time is log Y, a strictly increasing function of Y: the partial
+        # likelihood depends on the times only through their order within a stratum.
+        log_lam = np.log(lam_row)
+        logT = np.log(rng.exponential(1.0, size=eta.shape[0])) - log_lam - eta
+        logC = np.log(rng.exponential(1.0, size=eta.shape[0])) - log_lam
+        event = (logT <= logC).astype(np.uint8)
+        return np.minimum(logT, logC).astype(np.float64), event
     rate_t = lam_row * np.exp(eta)
     T = rng.exponential(1.0, size=eta.shape[0]) / rate_t
     C = rng.exponential(1.0, size=eta.shape[0]) / lam_row
@@ -143,9 +153,10 @@ def _times(rng, eta, lam_row, tie_round):
 def make(design: str, n: int, p: int, K: int, seed: int, *, beta=None,
          beta_kind: str = "normal", beta_sd: float = 0.5, beta_nonzero: float = 1.0,
          intercept: bool = False, density: float = 0.05, tie_round: float = 0.0,
-         gamma: float = 0.0, name: str = "", progress=None) -> CoxData:
+         gamma: float = 0.0, name: str = "", progress=None, log_time: bool = False) -> CoxData:
     """Draw one workload.  See the module docstring for the model and order.
-    `progress(j, p)`, if given, is called after each column of the t3 design is drawn."""
+    `progress(j, p)`, if given, is called after each column of the t3 design is drawn.
+    With `log_time` the returned times are log Y (drawn on the log scale, see _times)."""
     if n < 1 or p < 1 or K < 1 or K > n:
         raise ValueError("need n >= 1, p >= 1, 1 <= K <= n")
     rng = np.random.default_rng(seed)
@@ -176,7 +187,7 @@ def make(design: str, n: int, p: int, K: int, seed: int, *, beta=None,
         raise ValueError(f"unknown beta_kind {beta_kind!r}")
     stratum, lam = _strata(rng, n, K)
     eta = _linear_predictor(X, b)
-    Y, event = _times(rng, eta, lam[stratum], tie_round)
+    Y, event = _times(rng, eta, lam[stratum], tie_round, log_time)
     return CoxData(X=X, time=Y, event=event, stratum=stratum, beta_true=b,
                    gamma=float(gamma), name=name or f"{design}-n{n}-p{p}-K{K}-s{seed}")
 
@@ -236,9 +247,10 @@ def arrival_times(count: int, rate: float, seed: int = 3) -> np.ndarray:
 
 def config_heavy(n: int = 10_000_000, p: int = 500, K: int = 500_000, seed: int = 4, progress=None) -> CoxData:
     """Student-t(3) columns scaled to unit variance, beta_true with round(0.1 p) nonzero
-    N(0, 1) entries at seeded positions (seed 4)."""
+    N(0, 1) entries at seeded positions (seed 4).  X beta_true spreads beyond the range of
+    exp() in FP64, so the times are drawn on the log scale and returned as log Y."""
     return make("t3", n, p, K, seed, beta_kind="sparse_count", beta_sd=1.0, beta_nonzero=0.1, gamma=0.0,
-                name=f"heavy-n{n}-p{p}-K{K}", progress=progress)
+                name=f"heavy-n{n}-p{p}-K{K}", progress=progress, log_time=True)
 
 
 def config_step_effect(n: int = 407_828, p: int = 1000, seed: int = 6, cut: float = 10.0,

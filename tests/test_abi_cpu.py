@@ -84,6 +84,20 @@ def test_init_rejects_bad_shapes():
     assert lib.cox_init(None, ctypes.byref(d), None) == coxmi.COX_EINVAL
 
 
+def test_init_on_device_rejects_host_arrays():
+    """on_device = 1 with host arrays: rejected by the pointer checks, before any copy."""
+    lib = coxmi.lib()
+    X, t, e = _data()
+    dp = ctypes.POINTER(ctypes.c_double)
+    Xf = np.asfortranarray(X)
+    d = coxmi.cox_data(n=20, p=3, ldx=20, x=Xf.ctypes.data_as(dp), time=t.ctypes.data_as(dp),
+                       event=e.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), on_device=1)
+    h = ctypes.c_void_p()
+    assert lib.cox_init(ctypes.byref(h), ctypes.byref(d), None) == coxmi.COX_EINVAL
+    assert not h.value
+    assert coxmi.cox_last_error(None)
+
+
 def test_null_handle_calls_are_errors():
     lib = coxmi.lib()
     b = np.zeros(3)

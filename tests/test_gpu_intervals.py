@@ -142,5 +142,22 @@ def test_device_mapping_errors():
         with pytest.raises(coxmi.CoxError) as e:
             m.intervals(d.time, d.event, d.stratum, [2.0, 1.0])
         assert e.value.code == coxmi.COX_EINVAL
+        # keys other than the parent's: permuted times, a merged tie group, other strata
+        rng = np.random.default_rng(3)
+        bad_time = [rng.permutation(d.time), d.time.copy()]
+        perm, meta = m.layout()
+        c = next(c for c in range(d.n - 1) if d.event[perm[c]] and d.event[perm[c + 1]] and not meta[c + 1] >> 31)
+        bad_time[1][perm[c + 1]] = d.time[perm[c]]     # two events of one stratum merged into a tie group
+        for t in bad_time:
+            with pytest.raises(coxmi.CoxError) as e:
+                m.intervals(t, d.event, d.stratum, [0.5])
+            assert e.value.code == coxmi.COX_EINVAL
+        for st in [None, (d.stratum + 1) % 3, np.where(np.arange(d.n) == 5, d.stratum + 7, d.stratum)]:
+            with pytest.raises(coxmi.CoxError) as e:
+                m.intervals(d.time, d.event, None if st is None else st.astype(np.int32), [0.5])
+            assert e.value.code == coxmi.COX_EINVAL
+        # relabelled strata in the same order are the same strata
+        with m.intervals(d.time, d.event, (d.stratum * 5 + 2).astype(np.int32), [0.5]) as c:
+            assert coxmi.cox_shape(c.h)[0] >= d.n
         with pytest.raises(ValueError):
             m.intervals(d.time, d.event, d.stratum, [0.5], tv_coef=np.ones(2, np.uint8))

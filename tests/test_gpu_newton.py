@@ -294,6 +294,60 @@ def test_newton_fp8_heavy_tailed():
     assert err <= 1e-10
 
 
+@pytest.fixture(scope="module")
+def heavy_tile():
+    """The heavy-tailed workload past the persistent kernel's register capacity (256 CUs x
+    512 x 16 rows): N = 2.5e6 Student-t(3) rows, P = 64, 6 nonzero N(0,1) coefficients,
+    K = N/20 strata -- the handle takes the 4096-row tile layout, as at N = 1e7."""
+    return synth.config_heavy(n=2_500_000, p=64, K=125_000)
+
+
+def test_information_fp8_tile_layout_within_bound(heavy_tile):
+    """FP8 e4m3 information matrix on a tile-layout handle, element by element within the
+    FP8 bound of the module docstring (the contraction's K ranges hold at most
+    ceil(N / 128) + 16 rows here too)."""
+    d = heavy_tile
+    beta = d.beta_true * 0.9
+    _say(f"evaluate_full FP8 tile layout n={d.n} p={d.p}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE,
+                        x_precision=coxmi.COX_FP8_E4M3) as m:
+        n, p, ld = coxmi.cox_shape(m.h)
+        assert ld % 4096 == 0 and ld >= n > 256 * 512 * 16
+        obj, g, hd, info = m.evaluate_full(beta)
+    fe = _oracle_eval(d, beta)
+    _check_first_order(d, obj, g, hd, fe)
+    r = _scale(fe)
+    k = math.ceil(d.n / 128) + 16
+    lim = 4.5 * U_FP8 + 3.5 * U_BF16 + k * 2.0 ** -24
+    err = np.abs(info - fe.info)
+    worst = float(np.max(err / r))
+    _say(f"  max |err| / r = {worst:.3e} (bound {lim:.3e}), median {float(np.median(err / r)):.2e}")
+    assert np.all(err <= lim * r), worst
+    assert np.array_equal(info, info.T)
+    assert float(np.median(err / r)) <= 0.1 * lim
+
+
+def test_newton_fp8_beyond_the_resident_kernel(heavy_tile):
+    """The large heavy-tailed configuration's own path at a size the oracle fits in seconds:
+    FP8 information matrix on the tile layout + FP64 score and refinement, against the
+    oracle's FP64 Newton optimum (1e-10 relative on beta)."""
+    d = heavy_tile
+    _say(f"newton fit FP8 tile layout n={d.n} p={d.p} K=1.25e5")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE,
+                        x_precision=coxmi.COX_FP8_E4M3, tol=1e-13, max_iter=200) as m:
+        n, p, ld = coxmi.cox_shape(m.h)
+        assert ld % 4096 == 0 and ld >= n
+        beta, info = m.fit()
+        prof = m.profile()
+    ref = orc.fit_newton(d.X, d.time, d.event, d.stratum, tol=1e-14)
+    assert ref.converged
+    err = _rel(beta, ref.beta)
+    _say(f"  iters={info['iters']} evals={info['coord_evals']} rel err {err:.3e} profile {prof}")
+    assert info["status"] == coxmi.COX_OK
+    assert err <= 1e-10
+    assert abs(info["objective"] - ref.objective) <= 1e-11 * max(float(d.event.sum()), abs(ref.objective))
+
+
 def test_full_evaluation_extreme_linear_predictor():
     """Rows whose X beta is 900 or more above the rest of their stratum: a single
     exponent shift would underflow every other row's weight; the running-maximum
