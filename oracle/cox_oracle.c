@@ -121,6 +121,65 @@ void orc_coord_terms(int64_t n, const double *xj, const double *eta, const uint8
     free(S);
 }
 
+/* ------------------------------------------------------------------ Efron's ties */
+
+/*
+ * Efron's approximation for tied event times (B. Efron, "The efficiency of Cox's
+ * likelihood function for censored data", JASA 72, 1977), a variant the paper does not
+ * discuss.  A tie group g with d events D_g and risk set R_g (the rows of the stratum
+ * with Y_r >= Y_g) contributes
+ *     -sum_{i in D_g} eta_i + sum_{l=0}^{d-1} log(S0_g - (l/d) E0_g)
+ * to -log L, with S0_g = sum_{r in R_g} w_r and E0_g = sum_{i in D_g} w_i: the l-th of
+ * the tied events keeps only (1 - l/d) of the tied events' weight in its risk set.  The
+ * derivatives in beta_j use the same sums with w x_j (S1, E1) and w x_j^2 (S2, E2):
+ *     g'  = -sum_D x_j + sum_l (S1 - a_l E1) / (S0 - a_l E0)
+ *     g'' =  sum_l [ (S2 - a_l E2) / (S0 - a_l E0) - ((S1 - a_l E1) / (S0 - a_l E0))^2 ]
+ * with a_l = l/d.  A group with one event (d = 1) is Breslow's term exactly.
+ * Same outputs as orc_coord_terms; the E sums are taken at the group's shift m.
+ */
+void orc_coord_terms_efron(int64_t n, const double *xj, const double *eta, const uint8_t *head,
+                           const uint8_t *event, const int64_t *gend, double *out)
+{
+    orc_state *S = (orc_state *)malloc(sizeof(orc_state) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        orc_state e = orc_row(i == 0 ? 1 : head[i], eta[i], xj[i]);
+        S[i] = (i == 0) ? e : orc_state_op(S[i - 1], e);
+    }
+    double sx = 0, se = 0, t1 = 0, t2 = 0, t3 = 0, lsum = 0;
+    int64_t i = 0;
+    while (i < n) {
+        const int64_t e = gend[i];          /* rows i..e form one tie group */
+        const orc_state *g = &S[e];
+        int nd = 0;
+        double e0 = 0, e1 = 0, e2 = 0;
+        for (int64_t r = i; r <= e; ++r) {
+            if (!event[r]) continue;
+            double w = exp(eta[r] - g->m);
+            ++nd;
+            e0 += w;
+            e1 += w * xj[r];
+            e2 += w * xj[r] * xj[r];
+            sx += xj[r];
+            se += eta[r];
+        }
+        for (int l = 0; l < nd; ++l) {
+            double a = (double)l / (double)nd;
+            double A = g->s0 - a * e0;
+            double r1 = (g->s1 - a * e1) / A;
+            t1 += r1;
+            t2 += (g->s2 - a * e2) / A;
+            t3 += r1 * r1;
+            lsum += log(A) + g->m;
+        }
+        i = e + 1;
+    }
+    out[0] = t1 - sx;
+    out[1] = t2 - t3;
+    out[2] = lsum - se;
+    out[3] = t2;
+    free(S);
+}
+
 /* ------------------------------------------------------------------ CCD (Sec. 2.4) */
 
 /* Coordinates whose curvature is numerically zero (a ones column, a column
@@ -177,9 +236,22 @@ double orc_ccd_step(double beta, double g1, double g2, double h1, double gamma, 
  *   grad  : out, g' of the last evaluation of each coordinate (may be NULL)
  *   info  : out[0] = sweeps, out[1] = last max |step|, out[2] = objective at exit
  */
+int orc_ccd_fit_ties(int64_t n, int64_t p, const double *X, int64_t ldx, const uint8_t *head,
+                     const uint8_t *event, const int64_t *gend, const double *gamma, double tol,
+                     int max_sweeps, double *beta, double *grad, double *info, int efron);
+
 int orc_ccd_fit(int64_t n, int64_t p, const double *X, int64_t ldx, const uint8_t *head,
                 const uint8_t *event, const int64_t *gend, const double *gamma, double tol,
                 int max_sweeps, double *beta, double *grad, double *info)
+{
+    return orc_ccd_fit_ties(n, p, X, ldx, head, event, gend, gamma, tol, max_sweeps, beta, grad, info, 0);
+}
+
+/* The same descent with each coordinate's terms from orc_coord_terms (efron = 0, the
+ * risk sets of Eq. strat_l) or orc_coord_terms_efron (efron = 1). */
+int orc_ccd_fit_ties(int64_t n, int64_t p, const double *X, int64_t ldx, const uint8_t *head,
+                     const uint8_t *event, const int64_t *gend, const double *gamma, double tol,
+                     int max_sweeps, double *beta, double *grad, double *info, int efron)
 {
     double *eta = (double *)calloc((size_t)n, sizeof(double));
     double *trust = (double *)malloc(sizeof(double) * (size_t)p);
@@ -195,7 +267,8 @@ int orc_ccd_fit(int64_t n, int64_t p, const double *X, int64_t ldx, const uint8_
         for (int64_t j = 0; j < p; ++j) {
             double t[4];
             const double *xj = X + j * ldx;
-            orc_coord_terms(n, xj, eta, head, event, gend, t);
+            if (efron) orc_coord_terms_efron(n, xj, eta, head, event, gend, t);
+            else orc_coord_terms(n, xj, eta, head, event, gend, t);
             if (grad) grad[j] = t[0];
             obj = t[2];
             double s = orc_ccd_step(beta[j], t[0], t[1], t[3], gamma ? gamma[j] : 0.0, &trust[j]);
@@ -301,5 +374,117 @@ int64_t orc_group_sums(int64_t n, int64_t p, const double *X, int64_t ldx, const
     free(lh);
     free(s2);
     free(s1);
+    return G;
+}
+
+/*
+ * Efron's form of the group sums (see orc_coord_terms_efron).  For every tie group g
+ * holding events, at its shift m_g (the running maximum of eta over R_g):
+ *   S0g[g], S1g[g*p + j], S2dg[g*p + j]  the risk-set sums of w, w x_j, w x_j^2
+ *   E0g[g], E1g[g*p + j], E2dg[g*p + j]  the same sums over the group's events only
+ *   dg[g], mg[g]                         event count and shift
+ * and per row wl[r] = w_r c_r with w_r = exp(eta_r), where
+ *   c_r = sum over the event groups g of r's stratum with Y_g <= Y_r of h_g
+ *         - delta_r k_{g(r)},   h_g = sum_l 1/A_{g,l},  k_g = sum_l (l/d_g)/A_{g,l},
+ *   A_{g,l} = S0_g - (l/d_g) E0_g (unshifted):
+ * exchanging the sums, sum_g sum_l (S2_g - a_l E2_g)/A_{g,l} = sum_r w_r c_r x_r x_r'.
+ * log h and log k are accumulated with the shifts, so no exp() overflows.  Returns the
+ * number of event groups.
+ */
+int64_t orc_group_sums_efron(int64_t n, int64_t p, const double *X, int64_t ldx, const double *eta,
+                             const uint8_t *head, const uint8_t *event, const int64_t *gend,
+                             double *S0g, double *S1g, double *S2dg, double *E0g, double *E1g,
+                             double *E2dg, double *dg, double *mg, double *wl)
+{
+    double *q1 = (double *)calloc((size_t)p, sizeof(double));
+    double *q2 = (double *)calloc((size_t)p, sizeof(double));
+    double *lh = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1)); /* log h_g per row of g */
+    double *lk = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1)); /* log k_g per row of g */
+    double s0 = 0.0, m = -INFINITY;
+    int64_t G = 0;
+    int64_t i = 0;
+    while (i < n) {
+        int64_t e = gend[i];
+        int nd = 0;
+        for (int64_t r = i; r <= e; ++r) {
+            if (head[r] || r == 0) {
+                s0 = 0.0;
+                m = -INFINITY;
+                memset(q1, 0, sizeof(double) * (size_t)p);
+                memset(q2, 0, sizeof(double) * (size_t)p);
+            }
+            if (eta[r] > m) {
+                double sc = (m == -INFINITY) ? 0.0 : exp(m - eta[r]);
+                s0 *= sc;
+                for (int64_t j = 0; j < p; ++j) { q1[j] *= sc; q2[j] *= sc; }
+                m = eta[r];
+            }
+            double w = exp(eta[r] - m);
+            s0 += w;
+            for (int64_t j = 0; j < p; ++j) {
+                double x = X[j * ldx + r];
+                q1[j] += w * x;
+                q2[j] += w * x * x;
+            }
+            nd += event[r] ? 1 : 0;
+        }
+        if (nd > 0) {
+            double e0 = 0.0;
+            double *e1 = E1g + G * p, *e2 = E2dg + G * p;
+            for (int64_t j = 0; j < p; ++j) { e1[j] = 0.0; e2[j] = 0.0; }
+            for (int64_t r = i; r <= e; ++r) {
+                if (!event[r]) continue;
+                double w = exp(eta[r] - m);
+                e0 += w;
+                for (int64_t j = 0; j < p; ++j) {
+                    double x = X[j * ldx + r];
+                    e1[j] += w * x;
+                    e2[j] += w * x * x;
+                }
+            }
+            double h = 0.0, k = 0.0;
+            for (int l = 0; l < nd; ++l) {
+                double a = (double)l / (double)nd;
+                double A = s0 - a * e0;
+                h += 1.0 / A;
+                k += a / A;
+            }
+            S0g[G] = s0;
+            E0g[G] = e0;
+            memcpy(S1g + G * p, q1, sizeof(double) * (size_t)p);
+            memcpy(S2dg + G * p, q2, sizeof(double) * (size_t)p);
+            dg[G] = nd;
+            mg[G] = m;
+            for (int64_t r = i; r <= e; ++r) {
+                lh[r] = log(h) - m;
+                lk[r] = k > 0.0 ? log(k) - m : -INFINITY;
+            }
+            ++G;
+        } else {
+            for (int64_t r = i; r <= e; ++r) { lh[r] = -INFINITY; lk[r] = -INFINITY; }
+        }
+        i = e + 1;
+    }
+    double lacc = -INFINITY;
+    for (int64_t r = n - 1; r >= 0; ) {
+        int64_t e = r, s = r;
+        while (s > 0 && gend[s - 1] == e) --s;
+        double t = lh[e];
+        if (t != -INFINITY) {
+            double M = lacc > t ? lacc : t;
+            lacc = M + log(exp(lacc - M) + exp(t - M));
+        }
+        for (int64_t q = s; q <= e; ++q) {
+            double v = (lacc == -INFINITY) ? 0.0 : exp(eta[q] + lacc);
+            if (event[q] && lk[e] != -INFINITY) v -= exp(eta[q] + lk[e]);
+            wl[q] = v;
+        }
+        if (head[s]) lacc = -INFINITY;
+        r = s - 1;
+    }
+    free(lk);
+    free(lh);
+    free(q2);
+    free(q1);
     return G;
 }

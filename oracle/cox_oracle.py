@@ -67,6 +67,14 @@ def load_library(path: str):
     lib.orc_group_sums.argtypes = [i64, i64, dp, i64, dp, u8p, u8p, i64p,
                                    dp, dp, dp, dp, dp, dp]
     lib.orc_group_sums.restype = i64
+    lib.orc_coord_terms_efron.argtypes = [i64, dp, dp, u8p, u8p, i64p, dp]
+    lib.orc_coord_terms_efron.restype = None
+    lib.orc_ccd_fit_ties.argtypes = [i64, i64, dp, i64, u8p, u8p, i64p, dp, ctypes.c_double,
+                                     ctypes.c_int, dp, dp, dp, ctypes.c_int]
+    lib.orc_ccd_fit_ties.restype = ctypes.c_int
+    lib.orc_group_sums_efron.argtypes = [i64, i64, dp, i64, dp, u8p, u8p, i64p,
+                                         dp, dp, dp, dp, dp, dp, dp, dp, dp]
+    lib.orc_group_sums_efron.restype = i64
     return lib
 
 
@@ -228,20 +236,97 @@ def info_brute(X, time, event, stratum, beta) -> np.ndarray:
     return H
 
 
+# ------------------------------------------------ Efron's approximation for ties (brute force)
+#
+# Efron (JASA 72, 1977): a tie group g of stratum k at time t with d events D_g and risk
+# set R_g = {r in stratum k : Y_r >= t} contributes
+#     -sum_{i in D_g} eta_i + sum_{l=0}^{d-1} log( sum_{R_g} w_r - (l/d) sum_{D_g} w_i )
+# to -log L (w = exp(eta)).  The paper's risk sets (Eq. strat_l) give Breslow's form,
+# where every tied event sees all of R_g; Efron's removes an increasing share of the tied
+# events' weight.  With one event per group both are the same.
+
+def _event_groups(time, event, stratum):
+    """For each (stratum, time) that holds an event: masks of R_g and D_g."""
+    time = np.asarray(time, dtype=np.float64)
+    event = np.asarray(event)
+    n = time.shape[0]
+    stratum = np.zeros(n, dtype=np.int64) if stratum is None else np.asarray(stratum)
+    keys = sorted({(int(stratum[i]), float(time[i])) for i in range(n) if event[i]})
+    for s_, t_ in keys:
+        same = stratum == s_
+        yield same & (time >= t_), same & (time == t_) & (event != 0)
+
+
+def neg_loglik_efron_brute(X, time, event, stratum, beta) -> float:
+    """-log L with Efron's tie correction, by explicit loops over tie groups and their events."""
+    X = np.asarray(X, dtype=np.float64)
+    eta = X @ np.asarray(beta, dtype=np.float64)
+    w = np.exp(eta)
+    total = 0.0
+    for R, D in _event_groups(time, event, stratum):
+        d = int(D.sum())
+        S0, E0 = w[R].sum(), w[D].sum()
+        total -= eta[D].sum()
+        for l in range(d):
+            total += np.log(S0 - (l / d) * E0)
+    return float(total)
+
+
+def grad_efron_brute(X, time, event, stratum, beta) -> np.ndarray:
+    """Gradient of neg_loglik_efron_brute: -sum_D x + sum_l (S1 - a_l E1) / (S0 - a_l E0)."""
+    X = np.asarray(X, dtype=np.float64)
+    w = np.exp(X @ np.asarray(beta, dtype=np.float64))
+    g = np.zeros(X.shape[1])
+    for R, D in _event_groups(time, event, stratum):
+        d = int(D.sum())
+        S0, S1 = w[R].sum(), w[R] @ X[R]
+        E0, E1 = w[D].sum(), w[D] @ X[D]
+        g -= X[D].sum(axis=0)
+        for l in range(d):
+            a = l / d
+            g += (S1 - a * E1) / (S0 - a * E0)
+    return g
+
+
+def info_efron_brute(X, time, event, stratum, beta) -> np.ndarray:
+    """Hessian of neg_loglik_efron_brute: sum_l [(S2 - a_l E2)/A_l - m_l m_l'], m_l = (S1 - a_l E1)/A_l."""
+    X = np.asarray(X, dtype=np.float64)
+    w = np.exp(X @ np.asarray(beta, dtype=np.float64))
+    H = np.zeros((X.shape[1], X.shape[1]))
+    for R, D in _event_groups(time, event, stratum):
+        d = int(D.sum())
+        S0, S1, S2 = w[R].sum(), w[R] @ X[R], (X[R].T * w[R]) @ X[R]
+        E0, E1, E2 = w[D].sum(), w[D] @ X[D], (X[D].T * w[D]) @ X[D]
+        for l in range(d):
+            a = l / d
+            A = S0 - a * E0
+            m = (S1 - a * E1) / A
+            H += (S2 - a * E2) / A - np.outer(m, m)
+    return H
+
+
 # ============================================================== scan form (C)
 
-def coord_terms(Xc, layout: Layout, j: int, eta) -> dict:
+def _ties_flag(ties: str) -> int:
+    if ties not in ("breslow", "efron"):
+        raise ValueError("ties must be 'breslow' or 'efron'")
+    return int(ties == "efron")
+
+
+def coord_terms(Xc, layout: Layout, j: int, eta, ties: str = "breslow") -> dict:
     """g'(beta_j), g''(beta_j), objective and second-moment term for column j.
 
     Xc is the design in canonical order (see to_canonical); eta = Xc @ beta.
-    Follows Eqs. parallel_g / parallel_h with the segmented scans of Sec. 2.6.
+    Follows Eqs. parallel_g / parallel_h with the segmented scans of Sec. 2.6;
+    ties="efron" takes Efron's tie correction (orc_coord_terms_efron).
     """
     xj = np.ascontiguousarray(Xc[:, j], dtype=np.float64)
     eta = np.ascontiguousarray(eta, dtype=np.float64)
     out = np.zeros(4)
-    _c().orc_coord_terms(xj.shape[0], _p(xj, ctypes.c_double), _p(eta, ctypes.c_double),
-                         _p(layout.head, ctypes.c_uint8), _p(layout.event, ctypes.c_uint8),
-                         _p(layout.gend, ctypes.c_int64), _p(out, ctypes.c_double))
+    fn = _c().orc_coord_terms_efron if _ties_flag(ties) else _c().orc_coord_terms
+    fn(xj.shape[0], _p(xj, ctypes.c_double), _p(eta, ctypes.c_double),
+       _p(layout.head, ctypes.c_uint8), _p(layout.event, ctypes.c_uint8),
+       _p(layout.gend, ctypes.c_int64), _p(out, ctypes.c_double))
     return {"grad": out[0], "hess": out[1], "obj": out[2], "m2": out[3]}
 
 
@@ -270,8 +355,11 @@ def _gamma_vec(p, gamma, penalize):
 
 
 def fit_ccd(X, time, event, stratum=None, *, gamma=0.0, penalize=None, beta0=None,
-            tol=1e-12, max_sweeps=1000, layout: Layout | None = None, Xc=None) -> FitResult:
-    """Cyclic coordinate descent of Sec. 2.4 on -log L + sum_j gamma_j |beta_j| (C oracle)."""
+            tol=1e-12, max_sweeps=1000, layout: Layout | None = None, Xc=None,
+            ties: str = "breslow") -> FitResult:
+    """Cyclic coordinate descent of Sec. 2.4 on -log L + sum_j gamma_j |beta_j| (C oracle);
+    ties="efron" descends Efron's -log L instead."""
+    efron = _ties_flag(ties)
     layout = layout or canonical_layout(time, event, stratum)
     Xc = to_canonical(X, layout) if Xc is None else Xc
     n, p = Xc.shape
@@ -279,11 +367,11 @@ def fit_ccd(X, time, event, stratum=None, *, gamma=0.0, penalize=None, beta0=Non
     grad = np.zeros(p)
     info = np.zeros(3)
     gam = _gamma_vec(p, gamma, penalize)
-    rc = _c().orc_ccd_fit(n, p, _p(Xc, ctypes.c_double), n, _p(layout.head, ctypes.c_uint8),
-                          _p(layout.event, ctypes.c_uint8), _p(layout.gend, ctypes.c_int64),
-                          _p(gam, ctypes.c_double), float(tol), int(max_sweeps),
-                          _p(beta, ctypes.c_double), _p(grad, ctypes.c_double),
-                          _p(info, ctypes.c_double))
+    rc = _c().orc_ccd_fit_ties(n, p, _p(Xc, ctypes.c_double), n, _p(layout.head, ctypes.c_uint8),
+                               _p(layout.event, ctypes.c_uint8), _p(layout.gend, ctypes.c_int64),
+                               _p(gam, ctypes.c_double), float(tol), int(max_sweeps),
+                               _p(beta, ctypes.c_double), _p(grad, ctypes.c_double),
+                               _p(info, ctypes.c_double), efron)
     return FitResult(beta=beta, converged=(rc == 0), iters=int(info[0]), objective=float(info[2]),
                      last_step=float(info[1]), grad=grad)
 
@@ -298,7 +386,49 @@ class FullEval:
     info_second: np.ndarray | None = None   # sum_g d_g xbar_g xbar_g'
 
 
-def full_eval(Xc, layout: Layout, beta, want_info: bool = True) -> FullEval:
+def full_eval_efron(Xc, layout: Layout, beta, want_info: bool = True) -> FullEval:
+    """full_eval with Efron's tie correction (see orc_coord_terms_efron).
+
+    objective = -delta' eta + sum_g sum_l log A_{g,l},  A_{g,l} = S0_g - a_l E0_g, a_l = l/d_g
+    gradient  = -X' delta + sum_g sum_l (S1_g - a_l E1_g) / A_{g,l}
+    diag      = sum_g sum_l [(S2_g - a_l E2_g) / A_{g,l} - ((S1_g - a_l E1_g) / A_{g,l})^2]
+    Hessian   = X' diag(w c) X - Z'Z, the rows of Z being m_{g,l} = (S1_g - a_l E1_g) / A_{g,l}
+    for every group g and l < d_g (one row per event), w c from orc_group_sums_efron.
+    """
+    Xc = np.asfortranarray(Xc, dtype=np.float64)
+    n, p = Xc.shape
+    beta = np.asarray(beta, dtype=np.float64)
+    eta = np.ascontiguousarray(Xc @ beta)
+    G = int(np.count_nonzero(layout.dcount))
+    S0 = np.zeros(G); S1 = np.zeros((G, p)); S2 = np.zeros((G, p))
+    E0 = np.zeros(G); E1 = np.zeros((G, p)); E2 = np.zeros((G, p))
+    d = np.zeros(G); m = np.zeros(G); wl = np.zeros(n)
+    dp = ctypes.c_double
+    g_out = _c().orc_group_sums_efron(n, p, _p(Xc, dp), n, _p(eta, dp), _p(layout.head, ctypes.c_uint8),
+                                      _p(layout.event, ctypes.c_uint8), _p(layout.gend, ctypes.c_int64),
+                                      _p(S0, dp), _p(S1, dp), _p(S2, dp), _p(E0, dp), _p(E1, dp), _p(E2, dp),
+                                      _p(d, dp), _p(m, dp), _p(wl, dp))
+    assert g_out == G
+    ev = layout.event.astype(np.float64)
+    dn = d.astype(np.int64)
+    # one row per event: group index and a_l = l / d_g
+    gi = np.repeat(np.arange(G), dn)
+    a = np.concatenate([np.arange(k) / k for k in dn]) if G else np.zeros(0)
+    A = S0[gi] - a * E0[gi]
+    M1 = (S1[gi] - a[:, None] * E1[gi]) / A[:, None]
+    M2 = (S2[gi] - a[:, None] * E2[gi]) / A[:, None]
+    obj = float(-(ev @ eta) + np.sum(np.log(A) + m[gi]))
+    grad = -(Xc.T @ ev) + M1.sum(axis=0)
+    hdiag = (M2 - M1 * M1).sum(axis=0)
+    info = first = second = None
+    if want_info:
+        first = (Xc.T * wl) @ Xc
+        second = M1.T @ M1
+        info = first - second
+    return FullEval(objective=obj, grad=grad, hess_diag=hdiag, info=info, info_first=first, info_second=second)
+
+
+def full_eval(Xc, layout: Layout, beta, want_info: bool = True, ties: str = "breslow") -> FullEval:
     """Objective, full gradient, diag Hessian and (optionally) the full Hessian at beta.
 
     gradient  = -X' delta + sum_g d_g S1_g / S0_g                     (Eq. strat_g, all j)
@@ -307,7 +437,10 @@ def full_eval(Xc, layout: Layout, beta, want_info: bool = True) -> FullEval:
     where g runs over tie groups with d_g events, S*_g are risk-set sums at the
     group end, xbar_g = S1_g / S0_g and Lambda_r = sum_{g: Y_g <= Y_r} d_g / S0_g
     (same stratum): sum_g d_g S2_g / S0_g = sum_r w_r Lambda_r x_r x_r'.
+    ties="efron" gives full_eval_efron.
     """
+    if _ties_flag(ties):
+        return full_eval_efron(Xc, layout, beta, want_info)
     Xc = np.asfortranarray(Xc, dtype=np.float64)
     n, p = Xc.shape
     beta = np.asarray(beta, dtype=np.float64)
@@ -334,7 +467,7 @@ def full_eval(Xc, layout: Layout, beta, want_info: bool = True) -> FullEval:
     return FullEval(objective=obj, grad=grad, hess_diag=hdiag, info=info, info_first=first, info_second=second)
 
 
-def degenerate_columns(Xc, layout: Layout, beta=None) -> np.ndarray:
+def degenerate_columns(Xc, layout: Layout, beta=None, ties: str = "breslow") -> np.ndarray:
     """Columns with numerically zero curvature (g'' <= 1e-12 * second-moment term)."""
     Xc = np.asfortranarray(Xc, dtype=np.float64)
     n, p = Xc.shape
@@ -342,26 +475,26 @@ def degenerate_columns(Xc, layout: Layout, beta=None) -> np.ndarray:
     eta = Xc @ beta
     out = np.zeros(p, dtype=bool)
     for j in range(p):
-        t = coord_terms(Xc, layout, j, eta)
+        t = coord_terms(Xc, layout, j, eta, ties)
         out[j] = not (t["hess"] > 1e-12 * abs(t["m2"]))
     return out
 
 
 def fit_newton(X, time, event, stratum=None, *, beta0=None, tol=1e-14, max_iter=100,
-               layout: Layout | None = None, Xc=None) -> FitResult:
+               layout: Layout | None = None, Xc=None, ties: str = "breslow") -> FitResult:
     """Unpenalised optimum by Newton's method on the full Hessian (numpy Cholesky).
 
     Degenerate columns (a ones column, which cancels from every ratio in
     Eq. strat_l) are held at zero.  Step halving guards the first iterations.
-    Stops when max|step| <= tol * max(1, max|beta|).
+    Stops when max|step| <= tol * max(1, max|beta|).  ties="efron": Efron's -log L.
     """
     layout = layout or canonical_layout(time, event, stratum)
     Xc = to_canonical(X, layout) if Xc is None else Xc
     n, p = Xc.shape
     beta = np.zeros(p) if beta0 is None else np.array(beta0, dtype=np.float64)
-    free = ~degenerate_columns(Xc, layout)
+    free = ~degenerate_columns(Xc, layout, ties=ties)
     beta[~free] = 0.0
-    ev = full_eval(Xc, layout, beta)
+    ev = full_eval(Xc, layout, beta, ties=ties)
     it = 0
     step_max = np.inf
     converged = False
@@ -373,7 +506,7 @@ def fit_newton(X, time, event, stratum=None, *, beta0=None, tol=1e-14, max_iter=
         step[free] = -np.linalg.solve(L.T, np.linalg.solve(L, ev.grad[free]))
         t = 1.0
         while True:
-            cand = full_eval(Xc, layout, beta + t * step)
+            cand = full_eval(Xc, layout, beta + t * step, ties=ties)
             if cand.objective <= ev.objective + 1e-12 * abs(ev.objective) or t < 1e-6:
                 break
             t *= 0.5

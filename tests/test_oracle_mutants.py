@@ -32,6 +32,14 @@ MUTANTS = {
     "trust_never_grows": ("*trust = t2 > half ? t2 : half;", "*trust = half;"),
     "l1_wrong_side": ("} else if (g1 + gamma < 0.0) {", "} else if (g1 - gamma < 0.0) {"),
     "newton_sign": ("step = -g1 / g2;", "step = g1 / g2;"),
+    # Efron's tie correction
+    "efron_denominator_uncorrected": ("double A = g->s0 - a * e0;", "double A = g->s0;"),
+    "efron_numerator_uncorrected": ("double r1 = (g->s1 - a * e1) / A;", "double r1 = g->s1 / A;"),
+    "efron_objective_uncorrected": ("lsum += log(A) + g->m;", "lsum += log(g->s0) + g->m;"),
+    "efron_share_over_all_rows": ("            if (!event[r]) continue;\n            double w = exp(eta[r] - g->m);",
+                                  "            double w = exp(eta[r] - g->m);"),
+    "efron_k_wrong": ("k += a / A;", "k += 1.0 / A;"),
+    "efron_no_event_term_in_weights": ("if (event[q] && lk[e] != -INFINITY) v -= exp(eta[q] + lk[e]);", ";"),
 }
 
 
@@ -86,6 +94,34 @@ def _pins():
     check("ccd_vs_newton", lambda: cd.converged and np.max(np.abs(cd.beta - nw.beta)) < 1e-9)
     gb = o.grad_brute(ds.X, ds.time, ds.event, ds.stratum, cd.beta)
     check("ccd_zero_score", lambda: np.max(np.abs(gb)) < 1e-8)
+    # Efron's correction: toy 3 closed forms and the brute-force definition on tied data
+    X3 = np.array(t["toy3.x"])[:, None]
+    t3, e3 = np.array(t["toy3.time"]), np.array(t["toy3.event"], dtype=np.uint8)
+    L3 = o.canonical_layout(t3, e3)
+    X3c = o.to_canonical(X3, L3)
+    ce = o.coord_terms(X3c, L3, 0, np.zeros(4), "efron")
+    fe3 = o.full_eval(X3c, L3, [0.0], ties="efron")
+    check("efron_toy3_grad", lambda: abs(ce["grad"] - t["toy3.efron.grad0"][0]) < 1e-14
+          and abs(fe3.grad[0] - t["toy3.efron.grad0"][0]) < 1e-14)
+    check("efron_toy3_hess", lambda: abs(ce["hess"] - t["toy3.efron.hess0"][0]) < 1e-14
+          and abs(fe3.info[0, 0] - t["toy3.efron.hess0"][0]) < 1e-14)
+    check("efron_toy3_obj", lambda: abs(ce["obj"] - t["toy3.efron.negloglik0"][0]) < 1e-14
+          and abs(fe3.objective - t["toy3.efron.negloglik0"][0]) < 1e-14)
+    de = synth.make("iid", 150, 3, 5, 7, beta_sd=0.7, tie_round=5.0)
+    Le = o.canonical_layout(de.time, de.event, de.stratum)
+    fee = o.full_eval(o.to_canonical(de.X, Le), Le, beta, ties="efron")
+    tole = 1e-11 * de.event.sum()
+    check("efron_brute_info", lambda: np.allclose(fee.info, o.info_efron_brute(de.X, de.time, de.event, de.stratum,
+                                                                                beta), atol=tole))
+    check("efron_brute_grad", lambda: np.allclose(fee.grad, o.grad_efron_brute(de.X, de.time, de.event, de.stratum,
+                                                                                beta), atol=tole))
+    Xec = o.to_canonical(de.X, Le)
+    etae = Xec @ beta
+    ge = o.grad_efron_brute(de.X, de.time, de.event, de.stratum, beta)
+    oe = o.neg_loglik_efron_brute(de.X, de.time, de.event, de.stratum, beta)
+    check("efron_brute_coord", lambda: all(
+        abs(o.coord_terms(Xec, Le, j, etae, "efron")["grad"] - ge[j]) < tole
+        and abs(o.coord_terms(Xec, Le, j, etae, "efron")["obj"] - oe) < tole for j in range(3)))
     gam = 5.0
     # a weak fourth column so that the l1 optimum has an exact zero (dead zone |g'| <= gamma)
     X4 = np.asfortranarray(np.column_stack([d.X, 0.02 * np.random.default_rng(2).standard_normal(d.n)]))
