@@ -390,6 +390,19 @@ int cox_shape(const cox_handle *h, int64_t *n, int64_t *p, int64_t *ld);
  */
 int cox_segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, void *stream);
 
+/*
+ * cox_segscan_f64 for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, scan and results, but the scan's synchronisation words live in a fixed
+ * 4,352-byte array of the library's device memory (one copy per GPU, held until the
+ * process ends) instead of a per-call allocation.  A fill kernel on `stream` clears
+ * the array before each scan.  Calls no hipMalloc, hipFree or other allocating
+ * routine.  Limit: n <= CUs x 1024 x 16 rows (4,194,304 on 256 compute units), else
+ * COX_EUNSUPPORTED (as for cox_segscan_f64).  Calls that overlap on one GPU (other
+ * streams or threads) share the array and race: the caller serialises them.
+ */
+int cox_segscan_f64_noalloc(const double *a, const uint8_t *head, double *b, int64_t n, void *stream);
+
 /* Free the handle and all device memory it owns.  NULL is a no-op. */
 void cox_release(cox_handle *h);
 

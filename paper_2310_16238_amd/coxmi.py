@@ -143,6 +143,7 @@ SIGNATURES = [
     ("cox_shape", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64)]),
     ("cox_segscan_f64", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
+    ("cox_segscan_f64_noalloc", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, _VP]),
     ("cox_release", None, [_VP]),
     ("cox_last_error", ctypes.c_char_p, [_VP]),
     ("cox_server_default_options", None, [ctypes.POINTER(cox_server_options)]),
@@ -559,6 +560,15 @@ def cox_segscan_f64(a_ptr: int, head_ptr: int, b_ptr: int, n: int, stream=None) 
                                int(n), None if stream is None else ctypes.c_void_p(int(stream)))
     if rc != COX_OK:
         raise CoxError(rc, "cox_segscan_f64 failed")
+    return rc
+
+
+def cox_segscan_f64_noalloc(a_ptr: int, head_ptr: int, b_ptr: int, n: int, stream=None) -> int:
+    """cox_segscan_f64 without device allocation (library-owned scratch); raises on error."""
+    rc = lib().cox_segscan_f64_noalloc(ctypes.c_void_p(a_ptr), ctypes.c_void_p(head_ptr), ctypes.c_void_p(b_ptr),
+                                       int(n), None if stream is None else ctypes.c_void_p(int(stream)))
+    if rc != COX_OK:
+        raise CoxError(rc, "cox_segscan_f64_noalloc failed")
     return rc
 
 

@@ -35,6 +35,7 @@
 //     A risk-set sum outside [1e-300, 1e300] stops the fit with a flag.
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -744,6 +745,98 @@ int segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, hipS
     if (e != hipSuccess || aborted) rc = -3;
     (void)hipFree(scratch);
     return rc;
+}
+
+// ------------------------------------------------------------------ the scan without allocation
+
+// Synchronisation words of segscan_f64_noalloc: the control block and one aggregate
+// packet per workgroup (at most kMaxGroups), in library-owned device memory that
+// exists once per GPU for the life of the process.  Host code never uses this name
+// as an address: its per-device address comes from hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchBytes = 256 + sizeof(Packet) * kMaxGroups;
+static_assert(sizeof(SyncCtl) <= 256, "control block");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return -3;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return -3;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+// Zero `words` 32-bit words (a fill kernel rather than a memset node, so the call can
+// sit in captured work).
+__global__ __launch_bounds__(256) void zero_words_kernel(uint32_t *p, int words)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < words) p[i] = 0u;
+}
+
+}  // namespace
+
+int segscan_f64_noalloc(const double *a, const uint8_t *head, double *b, int64_t n, hipStream_t stream)
+{
+    if (n < 0 || (n > 0 && (!a || !head || !b))) return -1;
+    if (n == 0) return 0;
+    int cus = 0;
+    if (device_cus(&cus) != (int)hipSuccess || cus <= 0) return -3;
+    const int ipts[] = {1, 2, 4, 8, 16};
+    int ipt = 0;
+    int64_t grid = 0;
+    for (int c : ipts) {
+        grid = (n + (int64_t)kScanBlock * c - 1) / ((int64_t)kScanBlock * c);
+        if (grid <= cus && grid <= kMaxGroups) {
+            ipt = c;
+            break;
+        }
+    }
+    if (!ipt) return -5;
+    void *base = nullptr;
+    if (scratch_address(&base) != 0) return -3;
+    const size_t bytes = up256(sizeof(SyncCtl)) + up256(sizeof(Packet) * (size_t)grid);
+    if (bytes > kNoAllocScratchBytes) return -5;
+    char *cb = static_cast<char *>(base);
+    SyncCtl *ctl = reinterpret_cast<SyncCtl *>(cb);
+    Packet *agg = reinterpret_cast<Packet *>(cb + up256(sizeof(SyncCtl)));
+    // the previous call's packets carry the same epoch: clear them before this scan reads any
+    const int words = (int)(bytes / sizeof(uint32_t));
+    hipLaunchKernelGGL(zero_words_kernel, dim3((words + 255) / 256), dim3(256), 0, stream,
+                       reinterpret_cast<uint32_t *>(base), words);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        void *args[] = {(void *)&a, (void *)&head, (void *)&b, (void *)&n, (void *)&agg, (void *)&ctl};
+        const void *fn = nullptr;
+        switch (ipt) {
+        case 1: fn = reinterpret_cast<const void *>(&segscan_kernel<1>); break;
+        case 2: fn = reinterpret_cast<const void *>(&segscan_kernel<2>); break;
+        case 4: fn = reinterpret_cast<const void *>(&segscan_kernel<4>); break;
+        case 8: fn = reinterpret_cast<const void *>(&segscan_kernel<8>); break;
+        default: fn = reinterpret_cast<const void *>(&segscan_kernel<16>); break;
+        }
+        e = hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(kScanBlock), args, 0, stream);
+    }
+    uint32_t aborted = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&aborted, &ctl->abort, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    return (e != hipSuccess || aborted) ? -3 : 0;
 }
 
 }  // namespace coxmi

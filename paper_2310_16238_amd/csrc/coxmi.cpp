@@ -1048,6 +1048,12 @@ extern "C" int cox_segscan_f64(const double *a, const uint8_t *head, double *b, 
     return segscan_f64(a, head, b, n, static_cast<hipStream_t>(stream));
 }
 
+extern "C" int cox_segscan_f64_noalloc(const double *a, const uint8_t *head, double *b, int64_t n, void *stream)
+{
+    if (n > 0x7fffffffLL) return COX_EUNSUPPORTED;
+    return segscan_f64_noalloc(a, head, b, n, static_cast<hipStream_t>(stream));
+}
+
 extern "C" void cox_release(cox_handle *h)
 {
     if (!h) return;

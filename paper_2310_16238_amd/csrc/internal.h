@@ -87,6 +87,9 @@ bool device_range_ok(const void *ptr, size_t bytes, int device);
 
 // Segmented +scan of n doubles on device memory; returns a COX_* code.
 int segscan_f64(const double *a, const uint8_t *head, double *b, int64_t n, hipStream_t stream);
+// The same scan with its synchronisation words in a fixed library-owned device array
+// (no allocation); calls that overlap on one device race on that array.
+int segscan_f64_noalloc(const double *a, const uint8_t *head, double *b, int64_t n, hipStream_t stream);
 
 // Result slots written by the persistent kernel.
 enum ResultSlot {
