@@ -7,8 +7,10 @@ first call raises RuntimeError; there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -104,6 +106,20 @@ COX_SUBMIT_BORROW = 1
 COX_SUBMIT_DEVICE = 2
 
 _lib = None
+
+# Handles and servers still open when the interpreter exits are released before its
+# teardown starts, while the HIP runtime is whole (a release from a finalizer during
+# teardown can run after the runtime's own exit handlers).
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 # (name, restype, argtypes) of every entry point in include/coxmi.h
 _VP = ctypes.c_void_p
@@ -587,12 +603,14 @@ class CoxModel:
 
     def __init__(self, X, time, event, stratum=None, **opts):
         self.h = cox_init(X, time, event, stratum, **opts)
+        _live.add(self)
 
     @classmethod
     def from_device(cls, X, time, event, stratum=None, **opts):
         """A CoxModel on device-resident torch tensors (see cox_init_device)."""
         m = cls.__new__(cls)
         m.h = cox_init_device(X, time, event, stratum, **opts)
+        _live.add(m)
         return m
 
     @classmethod
@@ -600,6 +618,7 @@ class CoxModel:
         """A CoxModel on indicator X in compressed sparse columns (see cox_init_indicator)."""
         m = cls.__new__(cls)
         m.h = cox_init_indicator(n, col_ptr, row_idx, time, event, stratum, **opts)
+        _live.add(m)
         return m
 
     def fit(self, beta0=None):
@@ -621,12 +640,14 @@ class CoxModel:
         """A CoxModel on the data set with row multiplicities `count` (see cox_init_resample)."""
         m = CoxModel.__new__(CoxModel)
         m.h = cox_init_resample(self.h, count, inherit=not opts, **opts)
+        _live.add(m)
         return m
 
     def intervals(self, time, event, stratum=None, cuts=(), tv_coef=None, **opts):
         """A CoxModel on the interval-stratified data (see cox_init_intervals)."""
         m = CoxModel.__new__(CoxModel)
         m.h = cox_init_intervals(self.h, time, event, stratum, cuts, tv_coef, inherit=not opts, **opts)
+        _live.add(m)
         return m
 
     def baseline_hazard(self, beta):
@@ -706,6 +727,7 @@ class CoxServer:
         self.h = h.value
         self._keep = {}
         self._p = {}
+        _live.add(self)
 
     def _check(self, rc, ok=(COX_OK,)):
         if rc not in ok:
