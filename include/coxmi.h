@@ -50,7 +50,11 @@ enum { COX_CCD = 0, COX_NEWTON_REFINE = 1 };
 /* storage precision of X for the information-matrix contraction (the
  * gradient and objective are always formed in FP64) */
 enum { COX_F64 = 0, COX_F32 = 1, COX_BF16 = 2, COX_FP8_E4M3 = 3 };
-enum { COX_BRESLOW = 0 };             /* tie handling (see above) */
+/* tie handling: COX_BRESLOW takes the risk sets of Eq. strat_l literally (see above);
+ * COX_EFRON is Efron's (1977) approximation, which the paper does not discuss: the l-th of
+ * the d tied events of a group sees its risk set less l/d of the tied events' own weight
+ * (sums S - (l/d) E, l = 0..d-1).  The two agree when no event times are tied. */
+enum { COX_BRESLOW = 0, COX_EFRON = 1 };
 
 typedef struct cox_handle cox_handle; /* opaque; owns all device state of one data set */
 
@@ -73,7 +77,7 @@ typedef struct {
     int x_precision;          /* contraction precision: COX_F64 or COX_BF16; COX_FP8_E4M3 in mode
                                  COX_NEWTON_REFINE only (p <= 4096); COX_F32: COX_EUNSUPPORTED
                                  (the fit server's precision) */
-    int ties;                 /* COX_BRESLOW */
+    int ties;                 /* COX_BRESLOW or COX_EFRON */
     double tol;               /* stop when the largest |step| of a CCD sweep or Newton step <= tol * max(1, max|beta|) */
     int max_iter;             /* maximum number of CCD sweeps or Newton iterations */
     void *stream;             /* hipStream_t to issue work on; NULL = default stream */

@@ -29,6 +29,7 @@ COX_F32 = 1
 COX_BF16 = 2
 COX_FP8_E4M3 = 3
 COX_BRESLOW = 0
+COX_EFRON = 1
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcoxmi.so")
 
@@ -209,7 +210,7 @@ def cox_default_options() -> cox_options:
 
 
 def cox_init(X, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-12, max_iter=1000,
-             stream=None, mode=COX_CCD, x_precision=COX_F64):
+             stream=None, mode=COX_CCD, x_precision=COX_F64, ties=COX_BRESLOW):
     """Create a handle.  X: (n, p) float64 (any order), time float64[n], event 0/1[n],
     stratum int32[n] or None.  Returns an opaque handle (int)."""
     X = np.asfortranarray(X, dtype=np.float64)
@@ -229,6 +230,7 @@ def cox_init(X, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-1
     o.max_iter = int(max_iter)
     o.mode = int(mode)
     o.x_precision = int(x_precision)
+    o.ties = int(ties)
     if penalize is not None:
         pen = np.ascontiguousarray(penalize, dtype=np.uint8)
         keep.append(pen)
@@ -261,27 +263,28 @@ def _device_data(X, time, event, stratum):
 
 
 def cox_init_device(X, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-12, max_iter=1000,
-                    stream=None, mode=COX_CCD, x_precision=COX_F64):
+                    stream=None, mode=COX_CCD, x_precision=COX_F64, ties=COX_BRESLOW):
     """cox_init on device-resident data: X a float64 CUDA tensor with unit row stride
     (column-major, e.g. the transpose of a contiguous p x n tensor), time float64, event
     uint8, stratum int32 or None (contiguous CUDA tensors).  The library reads them after
     the work queued on `stream` (default: the default stream); order other producers first."""
     d = _device_data(X, time, event, stratum)
     keep = []
-    o = _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep)
+    o = _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep, ties)
     h = ctypes.c_void_p()
     rc = lib().cox_init(ctypes.byref(h), ctypes.byref(d), ctypes.byref(o))
     _check(None, rc)
     return h.value
 
 
-def _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep):
+def _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep, ties=COX_BRESLOW):
     o = cox_default_options()
     o.gamma = float(gamma)
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.mode = int(mode)
     o.x_precision = int(x_precision)
+    o.ties = int(ties)
     if penalize is not None:
         pen = np.ascontiguousarray(penalize, dtype=np.uint8)
         keep.append(pen)
@@ -301,7 +304,7 @@ def cox_baseline_hazard(h, beta):
 
 
 def cox_init_indicator(n, col_ptr, row_idx, time, event, stratum=None, *, gamma=0.0, penalize=None, tol=1e-12,
-                       max_iter=1000, stream=None):
+                       max_iter=1000, stream=None, ties=COX_BRESLOW):
     """A handle on indicator X given as compressed sparse columns: column j holds 1 at rows
     row_idx[col_ptr[j]:col_ptr[j + 1]] and 0 elsewhere (cox_init_indicator)."""
     cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
@@ -316,7 +319,7 @@ def cox_init_indicator(n, col_ptr, row_idx, time, event, stratum=None, *, gamma=
     if stratum is not None:
         st = np.ascontiguousarray(stratum, dtype=np.int32)
         keep.append(st)
-    o = _options(gamma, penalize, tol, max_iter, stream, COX_CCD, COX_F64, keep)
+    o = _options(gamma, penalize, tol, max_iter, stream, COX_CCD, COX_F64, keep, ties)
     h = ctypes.c_void_p()
     rc = lib().cox_init_indicator(ctypes.byref(h), int(n), int(p), cp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                   ri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(time),
@@ -328,7 +331,7 @@ def cox_init_indicator(n, col_ptr, row_idx, time, event, stratum=None, *, gamma=
 
 
 def cox_init_resample(parent, count, *, inherit=True, gamma=0.0, penalize=None, tol=1e-12, max_iter=1000,
-                      stream=None, mode=COX_CCD, x_precision=COX_F64):
+                      stream=None, mode=COX_CCD, x_precision=COX_F64, ties=COX_BRESLOW):
     """A handle on the data set in which row i of the parent's data appears count[i] times,
     gathered on the device from the parent's X.  inherit=True keeps the parent's options
     and l1 weights (the keyword options are then ignored)."""
@@ -337,7 +340,7 @@ def cox_init_resample(parent, count, *, inherit=True, gamma=0.0, penalize=None, 
     if cnt.shape != (n,):
         raise ValueError(f"count needs {n} entries")
     keep = [cnt]
-    o = None if inherit else _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep)
+    o = None if inherit else _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep, ties)
     h = ctypes.c_void_p()
     rc = lib().cox_init_resample(ctypes.byref(h), parent, cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                  None if o is None else ctypes.byref(o))
@@ -346,7 +349,8 @@ def cox_init_resample(parent, count, *, inherit=True, gamma=0.0, penalize=None, 
 
 
 def cox_init_intervals(parent, time, event, stratum=None, cuts=(), tv_coef=None, *, inherit=True, gamma=0.0,
-                       penalize=None, tol=1e-12, max_iter=1000, stream=None, mode=COX_CCD, x_precision=COX_F64):
+                       penalize=None, tol=1e-12, max_iter=1000, stream=None, mode=COX_CCD, x_precision=COX_F64,
+                       ties=COX_BRESLOW):
     """The interval-stratified model (cox_init_intervals) built on the device from the parent's
     X; time, event, stratum are the data the parent was built from."""
     n, p, _ = cox_shape(parent)
@@ -365,7 +369,7 @@ def cox_init_intervals(parent, time, event, stratum=None, cuts=(), tv_coef=None,
         tv = np.ascontiguousarray(tv_coef, dtype=np.uint8)
         if tv.shape != (p,):
             raise ValueError(f"tv_coef needs {p} entries")
-    o = None if inherit else _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep)
+    o = None if inherit else _options(gamma, penalize, tol, max_iter, stream, mode, x_precision, keep, ties)
     h = ctypes.c_void_p()
     rc = lib().cox_init_intervals(ctypes.byref(h), parent, _dptr(time),
                                   event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),

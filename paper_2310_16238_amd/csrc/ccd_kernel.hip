@@ -25,11 +25,11 @@
 //     never runs.
 //   * Per-coordinate sums are reduced per workgroup (DPP + LDS) and published
 //     as epoch-tagged packets (two per workgroup, double-buffered by epoch
-//     parity).  Every workgroup gathers all of them -- one thread per
-//     workgroup, all in flight at once -- reduces them in a fixed order and
-//     takes the same scalar CCD step, so one memory round trip after the
-//     last workgroup publishes, everyone can move on.  Results are
-//     bit-reproducible.
+//     parity).  In every workgroup one wave gathers all of them -- four
+//     workgroups' records per lane, all in flight at once -- reduces them in a
+//     fixed order and takes the same scalar CCD step, which one barrier hands
+//     to the other waves: one memory round trip after the last workgroup
+//     publishes, everyone can move on.  Results are bit-reproducible.
 //   * exp() uses one global shift c (the largest X beta of the previous
 //     coordinate); ratios are shift-invariant and the objective adds c back.
 //     A risk-set sum outside [1e-300, 1e300] stops the fit with a flag.
@@ -69,9 +69,12 @@ size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
 }  // namespace
 
+// Tile aggregates of the look-back: up to 6 packets per workgroup (Efron's scan element).
+constexpr int kAggPackets = 6;
+
 size_t sync_scratch_bytes(int grid)
 {
-    return up256(sizeof(SyncCtl)) + up256(sizeof(Packet) * 3 * (size_t)grid) +
+    return up256(sizeof(SyncCtl)) + up256(sizeof(Packet) * kAggPackets * (size_t)grid) +
            up256(sizeof(Packet) * kRecPackets * 2 * (size_t)grid);
 }
 
@@ -81,7 +84,7 @@ void carve_sync_scratch(void *base, int grid, CcdLaunch &L)
     L.ctl = c;
     c += up256(sizeof(SyncCtl));
     L.agg = c;
-    c += up256(sizeof(Packet) * 3 * (size_t)grid);
+    c += up256(sizeof(Packet) * kAggPackets * (size_t)grid);
     L.part = c;
     L.res = nullptr;
 }
@@ -293,79 +296,229 @@ __device__ __forceinline__ double ccd_step(double beta, double g1, double g2, do
     return s;
 }
 
-// Every workgroup gathers the records of all G <= 256 workgroups for
-// `epoch`: thread q waits for workgroup q's record (all in flight at once),
-// each wave reduces its 64 records in lane order and every thread folds the
-// wave totals in wave order -- a fixed order, so all workgroups obtain the
-// same bits regardless of arrival times.  Called by every thread; returns
-// false (uniformly) on abort.
-template <int NW>
-__device__ __forceinline__ bool gather_partials(const PacketArray &part, int G, uint32_t epoch, bool extra,
-                                                SyncCtl *ctl, Partial *red, int *abort_flag, Partial &total)
+// One wave gathers the records of all G <= 256 workgroups for `epoch`: lane L
+// waits for the records of workgroups L, L + 64, L + 128, L + 192 (every packet of
+// every pending record in flight at once, re-polled together until all carry the
+// epoch), folds them in that order, and the wave reduces the lane totals in a
+// fixed DPP order -- so every workgroup obtains the same bits regardless of
+// arrival times.  Every lane of the wave receives the total.  Returns false
+// (uniformly) once a wait has timed out or another workgroup aborted.  Packets
+// first .. first + NP - 1 of each record are polled.
+constexpr int kGatherPer = kMaxGroups / kWave;
+
+template <int NP>
+__device__ __forceinline__ bool poll_records(const PacketArray &part, int G, uint32_t epoch, SyncCtl *ctl,
+                                             u32x4 (&r)[kGatherPer][NP], int first = 0)
 {
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int q = threadIdx.x;
-    Partial x = partial_identity();
-    if (q < G) {
-        const uint32_t slot = (uint32_t)(kRecPackets * ((epoch & 1u) * (uint32_t)G + (uint32_t)q));
-        bool ok;
-        u32x4 r[4];
-        if (extra) {
-            ok = packets_wait<4>(part, slot, epoch, ctl, r);
-        } else {
-            u32x4 r2[2];
-            ok = packets_wait<2>(part, slot, epoch, ctl, r2);
-            r[0] = r2[0];
-            r[1] = r2[1];
-            r[2] = r2[0];
-            r[3] = r2[0];
+    const int lane = threadIdx.x & (kWave - 1);
+    bool done[kGatherPer];
+    uint32_t slot[kGatherPer];
+#pragma unroll
+    for (int k = 0; k < kGatherPer; ++k) {
+        const int q = lane + kWave * k;
+        done[k] = q >= G;
+        slot[k] = (uint32_t)(kRecPackets * ((epoch & 1u) * (uint32_t)G + (uint32_t)q) + first);
+    }
+    WaitBudget wb;
+    bool ok = true;
+    for (;;) {
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k)
+            if (!done[k])
+#pragma unroll
+                for (int pk = 0; pk < NP; ++pk) r[k][pk] = packet_get(part, slot[k] + pk);
+        bool all = true;
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k) {
+            if (!done[k]) {
+                bool fresh = true;
+#pragma unroll
+                for (int pk = 0; pk < NP; ++pk) fresh = fresh && r[k][pk].z == epoch;
+                done[k] = fresh;
+                all = all && fresh;
+            }
         }
-        if (ok) {
-            x.v[kPC1] = packet_value(r[0]);
-            x.v[kPEtaMax] = (double)__uint_as_float(r[0].w);
-            x.v[kPC2] = packet_value(r[1]);
-            const float m2 = __uint_as_float(r[1].w);
-            x.v[kPM2] = extra ? packet_value(r[3]) : (double)m2;
-            x.err = (m2 == m2) ? 0u : 1u;
-            x.v[kPObj] = extra ? packet_value(r[2]) : 0.0;
-        } else {
-            *abort_flag = 1;
+        if (all) break;
+        if (!wb.keep_waiting(ctl)) {
+            ok = false;
+            break;
         }
     }
-    const Partial wr = wave_reduce_partial(x);
-    if (lane == kWave - 1) red[w] = wr;
-    __syncthreads();
-    if (*abort_flag) return false;
-    Partial tot = red[0];
+    return __builtin_amdgcn_ballot_w64(!ok) == 0;
+}
+
+__device__ __forceinline__ Partial broadcast_lane63(const Partial &x)
+{
+    Partial r;
 #pragma unroll
-    for (int k = 1; k < NW; ++k) partial_combine(tot, red[k]);
-    total = tot;
+    for (int k = 0; k < kPN; ++k) r.v[k] = lane63_f64(x.v[k]);
+    r.err = (uint32_t)__builtin_amdgcn_readlane((int)x.err, 63);
+    return r;
+}
+
+__device__ __forceinline__ bool gather_wave(const PacketArray &part, int G, uint32_t epoch, bool extra,
+                                            SyncCtl *ctl, Partial &total)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    Partial x = partial_identity();
+    {
+        u32x4 r[kGatherPer][2];
+        if (!poll_records<2>(part, G, epoch, ctl, r)) return false;
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k) {
+            if (lane + kWave * k < G) {
+                Partial y;
+                y.v[kPC1] = packet_value(r[k][0]);
+                y.v[kPEtaMax] = (double)__uint_as_float(r[k][0].w);
+                y.v[kPC2] = packet_value(r[k][1]);
+                const float m2 = __uint_as_float(r[k][1].w);
+                y.err = (m2 == m2) ? 0u : 1u;
+                y.v[kPM2] = (double)m2;
+                y.v[kPObj] = 0.0;
+                partial_combine(x, y);
+            }
+        }
+    }
+    if (extra) {
+        // the objective and the exact second moment (written with the two above): a second,
+        // short poll on the first coordinate of a sweep and in evaluations only
+        u32x4 r[kGatherPer][2];
+        if (!poll_records<2>(part, G, epoch, ctl, r, 2)) return false;
+        double obj = 0.0, m2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k) {
+            if (lane + kWave * k < G) {
+                obj += packet_value(r[k][0]);
+                m2 += packet_value(r[k][1]);
+            }
+        }
+        x.v[kPObj] = obj;
+        x.v[kPM2] = m2;
+    }
+    total = broadcast_lane63(wave_reduce_partial(x));
     return true;
+}
+
+// Tie-group terms of one row, added to v (Sec. 2.4 derivatives).  S = (S0, S1, S2): the
+// inclusive risk-set sums at the row; d: the events of the tie group ending at the row (0 when
+// the row ends no group with events, and then nothing is added).
+//   Breslow (the risk sets of Eq. strat_l taken literally): every tied event sees S,
+//     so the group adds d S1/S0, d (S2/S0 - (S1/S0)^2), d S2/S0, d (log S0 + c).  Evaluated
+//     on every row without branches (d = 0 adds zeros; S0 is replaced by 1 there so that
+//     no infinity enters).
+//   Efron (1977): E = (E0, E1, E2), the same sums over the group's own events; the l-th
+//     of its d events sees S - (l/d) E, l = 0..d-1 (d = 1 is Breslow's term exactly).
+template <bool EFRON, bool WANT_OBJ>
+__device__ __forceinline__ void group_terms(Partial &v, uint32_t d, const double (&S)[3], const double (&E)[3],
+                                            double c)
+{
+    const double s0 = S[0];
+    if constexpr (!EFRON) {
+        const bool end = d != 0u;
+        if (end && (!(s0 >= 1e-300) || !(s0 <= 1e300))) v.err = 1u;
+        const double sg = end ? s0 : 1.0;
+        const double inv = recip(sg);
+        const double r1 = S[1] * inv, r2 = S[2] * inv;
+        const double dd = (double)d;
+        v.v[kPC1] = fma(dd, r1, v.v[kPC1]);
+        v.v[kPC2] = fma(dd, fma(-r1, r1, r2), v.v[kPC2]);
+        v.v[kPM2] = fma(dd, r2, v.v[kPM2]);
+        if constexpr (WANT_OBJ) v.v[kPObj] = fma(dd, log(sg) + c, v.v[kPObj]);
+    } else {
+        if (d == 0u) return;
+        if (!(s0 >= 1e-300) || !(s0 <= 1e300)) v.err = 1u;
+        const double dd = (double)d;
+        for (uint32_t l = 0; l < d; ++l) {
+            const double a = (double)l / dd;
+            const double A = s0 - a * E[0];
+            const double inv = recip(A);
+            const double r1 = (S[1] - a * E[1]) * inv, r2 = (S[2] - a * E[2]) * inv;
+            v.v[kPC1] += r1;
+            v.v[kPC2] += r2 - r1 * r1;
+            v.v[kPM2] += r2;
+            if constexpr (WANT_OBJ) v.v[kPObj] += log(A) + c;
+        }
+    }
+}
+
+// Scan element of one row.  Components 0..2: (D, N1, N2) restarting at stratum heads
+// (flag bit 0).  Efron adds components 3..5: the same values on event rows only, restarting
+// after every row that ends a tie group with events (flag bit 1; such a row contributes 0
+// itself, so the running value before it plus its own values are its group's event sums).
+// An event-free stretch adds nothing, so these sums need no restart at stratum heads.
+template <bool EFRON>
+using RowVal = SegVal<EFRON ? 6 : 3, 3>;
+
+template <bool EFRON>
+__device__ __forceinline__ RowVal<EFRON> row_value(uint32_t m, double w, double x)
+{
+    RowVal<EFRON> r;
+    r.f = m >> 31;
+    r.v[0] = w;
+    r.v[1] = x * w;
+    r.v[2] = x * r.v[1];
+    if constexpr (EFRON) {
+        const bool end = (m & kCountMask) != 0u, ev = (m & kEventBit) != 0u;
+        r.f |= end ? 2u : 0u;
+        const bool keep = ev && !end;
+        r.v[3] = keep ? r.v[0] : 0.0;
+        r.v[4] = keep ? r.v[1] : 0.0;
+        r.v[5] = keep ? r.v[2] : 0.0;
+    }
+    return r;
+}
+
+// Pass 2 over a thread's rows: the inclusive prefixes from the thread's exclusive prefix
+// `run`, the group-end terms, the largest X beta over real rows, and (WANT_OBJ, the first
+// coordinate of a sweep) the objective's parts.
+template <int IPT, bool BITS, bool EFRON, bool WANT_OBJ>
+__device__ __forceinline__ Partial pass2(RowVal<EFRON> run, const uint32_t (&meta)[IPT], const double (&wv)[IPT],
+                                         const XCol<IPT, BITS> &xc, const double (&eta)[IPT], double c)
+{
+    Partial v = partial_identity();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+        const RowVal<EFRON> r = row_value<EFRON>(meta[i], wv[i], xc[i]);
+        double E[3] = {0.0, 0.0, 0.0};
+        if constexpr (EFRON) {
+            // this row's group's event sums: the running value before it plus its own share
+            const bool ev = (meta[i] & kEventBit) != 0u;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) E[k] = run.v[3 + k] + (ev ? r.v[k] : 0.0);
+        }
+        run = seg_combine(run, r);
+        v.v[kPEtaMax] = (meta[i] & kPadBit) ? v.v[kPEtaMax] : fmax(v.v[kPEtaMax], eta[i]);
+        const double S[3] = {run.v[0], run.v[1], run.v[2]};
+        group_terms<EFRON, WANT_OBJ>(v, meta[i] & kCountMask, S, E, c);
+        if constexpr (WANT_OBJ) v.v[kPObj] -= (meta[i] & kEventBit) ? eta[i] : 0.0;
+    }
+    return v;
 }
 
 // ------------------------------------------------------------------ the persistent kernel
 
-template <int BLOCK, int IPT, bool BITS>
+template <int BLOCK, int IPT, bool BITS, bool EFRON>
 __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 {
     constexpr int NW = BLOCK / kWave;
+    constexpr int KV = EFRON ? 6 : 3;
+    using RV = RowVal<EFRON>;
     static_assert(BLOCK % kWave == 0 && NW <= 16, "block shape");
     extern __shared__ double smem_dyn[];     // beta (the same in every workgroup)
-    __shared__ SegVal<3> s_wtot[NW];
+    __shared__ RV s_wtot[NW];
     __shared__ Partial s_red[NW];        // this workgroup's own reduction
-    __shared__ Partial s_gat[NW];        // the gathered records
-    __shared__ SegVal<3> s_win[kMaxGroups / kWave];
-    __shared__ double s_step, s_shift;
-    __shared__ uint32_t s_flags;
+    __shared__ RV s_win[kMaxGroups / kWave];
     __shared__ int s_abort;
     __shared__ double s_exptab[64];
+    __shared__ double s_step, s_shift;   // wave 0's step and shift for the next coordinate
+    __shared__ uint32_t s_flags;
 
     const int p = L.p;
     const int G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
     const int lane = t & (kWave - 1), w = t / kWave;
-    const bool writer = (b == 0);   // workgroup 0 writes the outputs
+    const bool writer = (b == 0 && t == 0);   // writes the outputs
     SyncCtl *ctl = static_cast<SyncCtl *>(L.ctl);
-    const PacketArray agg = packet_array(L.agg, sizeof(Packet) * 3 * (size_t)G);
+    const PacketArray agg = packet_array(L.agg, sizeof(Packet) * KV * (size_t)G);
     const PacketArray part = packet_array(L.part, sizeof(Packet) * kRecPackets * 2 * (size_t)G);
     const int64_t ld = (int64_t)G * BLOCK * IPT;
     const int64_t tile0 = (int64_t)b * BLOCK * IPT;
@@ -402,6 +555,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 
     // epoch 1: the initial shift, the largest X beta over the real rows
     uint32_t epoch = 1;
+    double c;
     {
         Partial v = partial_identity();
 #pragma unroll
@@ -409,19 +563,27 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             if (!(meta[i] & kPadBit)) v.v[kPEtaMax] = fmax(v.v[kPEtaMax], eta[i]);
         v = block_reduce_partial<NW>(v, s_red);
         if (t == 0) publish_partial(part, G, b, v, epoch, false);
-        Partial tot;
-        if (!gather_partials<NW>(part, G, epoch, false, ctl, s_gat, &s_abort, tot)) return;
-        if (t == 0) s_shift = tot.v[kPEtaMax];
+        if (w == 0) {
+            Partial tot;
+            if (gather_wave(part, G, epoch, false, ctl, tot)) {
+                if (lane == 0) s_shift = tot.v[kPEtaMax];
+            } else if (lane == 0) {
+                s_abort = 1;
+            }
+        }
         __syncthreads();
+        if (s_abort) return;
+        c = s_shift;
     }
-    double c = s_shift;
 
     const int jfirst = fit ? 0 : L.j0;
     const int jend = fit ? p : L.j1;
     XCol<IPT, BITS> xc;
     xc.load(L, ld, jfirst, row0, tg);
 
-    // bookkeeping of workgroup 0, thread 0
+    // Wave 0 keeps the bookkeeping (the same in every lane) and takes the step: its
+    // inputs are read at the start of the coordinate, and lane 0 writes beta_j and the
+    // half-width after the gather, for the next sweep.
     int sweeps = 0, pinned = 0, pinned_last = 0;
     double maxstep = 0.0, last_maxstep = 0.0, objective = 0.0;
     uint32_t stop = 0;
@@ -433,104 +595,81 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             XCol<IPT, BITS> xn;
             xn.load(L, ld, jn, row0, tg);
             const bool want_obj = (j == jfirst);
+            // the step's per-column inputs: issued here, they arrive during the passes
+            const double bj = sbeta[j];
+            const double qj = L.q[j], gj = L.gamma[j];
+            double trj = trust[j];
 
             // pass 1: D, N1, N2 of the thread's rows and their fold
+            RV tagg = seg_identity<KV, 3>();
             double wv[IPT];
-            SegVal<3> tagg = seg_identity<3>();
 #pragma unroll
             for (int i = 0; i < IPT; ++i) {
                 wv[i] = exp_table(eta[i] - c, s_exptab);
-                SegVal<3> r;
-                r.f = meta[i] >> 31;
-                r.v[0] = wv[i];
-                r.v[1] = xc[i] * wv[i];
-                r.v[2] = xc[i] * r.v[1];
-                tagg = seg_combine(tagg, r);
+                tagg = seg_combine(tagg, row_value<EFRON>(meta[i], wv[i], xc[i]));
             }
-            SegVal<3> btot;
-            SegVal<3> exc = block_exclusive_scan<3, NW>(tagg, s_wtot, btot);
-            if (t == 0) publish_aggregate<3>(agg, b, btot, epoch);
+            RV btot;
+            RV exc = block_exclusive_scan<KV, NW, 3>(tagg, s_wtot, btot);
+            if (t == 0) publish_aggregate(agg, b, btot, epoch);
             if (!tile_head) {
-                SegVal<3> carry;
-                if (!look_back<3>(b, epoch, agg, ctl, s_win, &s_abort, carry)) return;
+                RV carry;
+                if (!look_back<KV, 3>(b, epoch, agg, ctl, s_win, &s_abort, carry)) return;
                 exc = seg_combine(carry, exc);
             }
 
             // pass 2: inclusive prefixes at group ends -> per-coordinate sums
-            Partial v = partial_identity();
-            SegVal<3> run = exc;
-#pragma unroll
-            for (int i = 0; i < IPT; ++i) {
-                SegVal<3> r;
-                r.f = meta[i] >> 31;
-                r.v[0] = wv[i];
-                r.v[1] = xc[i] * wv[i];
-                r.v[2] = xc[i] * r.v[1];
-                run = seg_combine(run, r);
-                if (!(meta[i] & kPadBit)) v.v[kPEtaMax] = fmax(v.v[kPEtaMax], eta[i]);
-                const uint32_t d = meta[i] & kCountMask;
-                if (d != 0u) {
-                    const double s0 = run.v[0];
-                    if (!(s0 >= 1e-300) || !(s0 <= 1e300)) v.err = 1u;
-                    const double inv = recip(s0);
-                    const double r1 = run.v[1] * inv, r2 = run.v[2] * inv;
-                    const double dd = (double)d;
-                    v.v[kPC1] += dd * r1;
-                    v.v[kPC2] += dd * (r2 - r1 * r1);
-                    v.v[kPM2] += dd * r2;
-                    if (want_obj) v.v[kPObj] += dd * (log(s0) + c);
-                }
-                if (want_obj && (meta[i] & kEventBit)) v.v[kPObj] -= eta[i];
-            }
+            Partial v = want_obj ? pass2<IPT, BITS, EFRON, true>(exc, meta, wv, xc, eta, c)
+                                 : pass2<IPT, BITS, EFRON, false>(exc, meta, wv, xc, eta, c);
             v = block_reduce_partial<NW>(v, s_red);
             const bool extra = want_obj || !fit;
             if (t == 0) publish_partial(part, G, b, v, epoch, extra);
 
-            // the step's per-column inputs: issued here, they arrive while the records are gathered
-            double qj = 0.0, gj = 0.0, trj = 0.0;
-            if (t == 0) {
-                qj = L.q[j];
-                gj = L.gamma[j];
-                trj = trust[j];
-            }
-            Partial tot;
-            if (!gather_partials<NW>(part, G, epoch, extra, ctl, s_gat, &s_abort, tot)) return;
-            if (t == 0) {
-                uint32_t flags = tot.err ? kFlagNumeric : 0u;
-                const double g1 = -qj + tot.v[kPC1], g2 = tot.v[kPC2], m2 = tot.v[kPM2];
-                if (writer) {
-                    L.g1[j] = g1;
-                    L.g2[j] = g2;
-                    L.m2[j] = m2;
-                }
-                if (want_obj) {
-                    objective = tot.v[kPObj];
-                    if (fit)
-                        for (int k = 0; k < p; ++k) objective += L.gamma[k] * fabs(sbeta[k]);
-                }
-                double step = 0.0;
-                if (fit && !(flags & kFlagNumeric)) {
-                    int pin = 0;
-                    step = ccd_step(sbeta[j], g1, g2, m2, gj, &trj, &pin);
-                    trust[j] = trj;
-                    sbeta[j] += step;
-                    maxstep = fmax(maxstep, fabs(step));
-                    pinned += pin;
-                    if (j == jend - 1) {
-                        ++sweeps;
-                        double bmax = 1.0;
-                        for (int k = 0; k < p; ++k) bmax = fmax(bmax, fabs(sbeta[k]));
-                        if (maxstep <= L.tol * bmax) flags |= kFlagConverged;
-                        else if (sweeps >= L.max_sweeps) flags |= kFlagSweepLimit;
-                        last_maxstep = maxstep;
-                        pinned_last = pinned;
-                        maxstep = 0.0;
-                        pinned = 0;
+            // wave 0 gathers every workgroup's record and takes the step; the others wait for it
+            if (w == 0) {
+                Partial tot;
+                if (!gather_wave(part, G, epoch, extra, ctl, tot)) {
+                    if (lane == 0) s_abort = 1;
+                } else {
+                    uint32_t flags = tot.err ? kFlagNumeric : 0u;
+                    const double g1 = -qj + tot.v[kPC1], g2 = tot.v[kPC2], m2 = tot.v[kPM2];
+                    if (writer) {
+                        L.g1[j] = g1;
+                        L.g2[j] = g2;
+                        L.m2[j] = m2;
+                    }
+                    if (want_obj) {
+                        objective = tot.v[kPObj];
+                        if (fit)
+                            for (int k = 0; k < p; ++k) objective += L.gamma[k] * fabs(sbeta[k]);
+                    }
+                    double step = 0.0;
+                    if (fit && !(flags & kFlagNumeric)) {
+                        int pin = 0;
+                        step = ccd_step(bj, g1, g2, m2, gj, &trj, &pin);
+                        maxstep = fmax(maxstep, fabs(step));
+                        pinned += pin;
+                        if (j == jend - 1) {
+                            ++sweeps;
+                            double bmax = 1.0;
+                            for (int k = 0; k < p; ++k) bmax = fmax(bmax, fabs(k == j ? bj + step : sbeta[k]));
+                            if (maxstep <= L.tol * bmax) flags |= kFlagConverged;
+                            else if (sweeps >= L.max_sweeps) flags |= kFlagSweepLimit;
+                            last_maxstep = maxstep;
+                            pinned_last = pinned;
+                            maxstep = 0.0;
+                            pinned = 0;
+                        }
+                    }
+                    if (lane == 0) {
+                        if (fit && !(flags & kFlagNumeric)) {
+                            trust[j] = trj;
+                            sbeta[j] = bj + step;
+                        }
+                        s_step = step;
+                        s_shift = tot.v[kPEtaMax];
+                        s_flags = flags;
                     }
                 }
-                s_step = step;
-                s_shift = tot.v[kPEtaMax];
-                s_flags = flags;
             }
             __syncthreads();
             if (s_abort) return;
@@ -554,7 +693,8 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
         if (stop || !fit) break;
     }
 
-    if (writer) {
+    if (b == 0) {
+        // wave 0 holds the bookkeeping; beta is in LDS (written before the last barrier)
         if (fit)
             for (int j = t; j < p; j += BLOCK) L.beta[j] = sbeta[j];
         if (t == 0) {
@@ -626,23 +766,51 @@ namespace {
 
 constexpr int kCcdBlock = kThreads;
 
-template <int IPT>
-int occupancy_ccd(int p, int *blocks)
+// Dynamic LDS of one persistent workgroup: beta.
+size_t ccd_smem_bytes(int, int p)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, ccd_kernel<kCcdBlock, IPT, false>, kCcdBlock,
-                                                        sizeof(double) * (size_t)p);
+    return sizeof(double) * (size_t)p;
 }
 
-int occupancy_for(int ipt, int p, int *blocks)
+template <int IPT, bool BITS, bool EFRON>
+const void *ccd_fn()
+{
+    return reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, IPT, BITS, EFRON>);
+}
+
+template <bool BITS, bool EFRON>
+const void *ccd_fn_ipt(int ipt)
 {
     switch (ipt) {
-    case 1: return occupancy_ccd<1>(p, blocks);
-    case 2: return occupancy_ccd<2>(p, blocks);
-    case 4: return occupancy_ccd<4>(p, blocks);
-    case 8: return occupancy_ccd<8>(p, blocks);
-    case 16: return occupancy_ccd<16>(p, blocks);
-    default: return (int)hipErrorInvalidValue;
+    case 1: return ccd_fn<1, BITS, EFRON>();
+    case 2: return ccd_fn<2, BITS, EFRON>();
+    case 4: return ccd_fn<4, BITS, EFRON>();
+    case 8: return ccd_fn<8, BITS, EFRON>();
+    case 16: return ccd_fn<16, BITS, EFRON>();
+    default: return nullptr;
     }
+}
+
+const void *ccd_function(int ipt, bool bits, bool efron)
+{
+    if (bits) return efron ? ccd_fn_ipt<true, true>(ipt) : ccd_fn_ipt<true, false>(ipt);
+    return efron ? ccd_fn_ipt<false, true>(ipt) : ccd_fn_ipt<false, false>(ipt);
+}
+
+// Workgroups of the persistent kernel that fit on one compute unit; every variant
+// (indicator X, Efron) must fit, since a handle may run any of them.
+int occupancy_for(int ipt, int p, int *blocks)
+{
+    *blocks = 1 << 30;
+    for (int v = 0; v < 4; ++v) {
+        const void *fn = ccd_function(ipt, (v & 1) != 0, (v & 2) != 0);
+        if (!fn) return (int)hipErrorInvalidValue;
+        int nb = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kCcdBlock, ccd_smem_bytes(ipt, p));
+        if (e != hipSuccess) return (int)e;
+        *blocks = nb < *blocks ? nb : *blocks;
+    }
+    return (int)hipSuccess;
 }
 
 int device_cus(int *cus)
@@ -680,22 +848,9 @@ int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream,
     if (ev0 && (e = hipEventRecord(ev0, stream)) != hipSuccess) return (int)e;
     CcdLaunch arg = L;
     void *args[] = {&arg};
-    const size_t smem = sizeof(double) * (size_t)L.p;
-    const void *fn = nullptr;
-    const bool bits = L.xbits != nullptr;
-    switch (shape.ipt) {
-    case 1: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 1, true>)
-                      : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 1, false>); break;
-    case 2: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 2, true>)
-                      : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 2, false>); break;
-    case 4: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 4, true>)
-                      : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 4, false>); break;
-    case 8: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 8, true>)
-                      : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 8, false>); break;
-    case 16: fn = bits ? reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 16, true>)
-                       : reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, 16, false>); break;
-    default: return (int)hipErrorInvalidValue;
-    }
+    const size_t smem = ccd_smem_bytes(shape.ipt, L.p);
+    const void *fn = ccd_function(shape.ipt, L.xbits != nullptr, L.efron != 0);
+    if (!fn) return (int)hipErrorInvalidValue;
     e = hipLaunchCooperativeKernel(fn, dim3(shape.grid), dim3(kCcdBlock), args, (unsigned)smem, stream);
     if (e != hipSuccess) return (int)e;
     if (ev1 && (e = hipEventRecord(ev1, stream)) != hipSuccess) return (int)e;

@@ -207,7 +207,7 @@ static int check_options(const cox_options &opt, std::string &msg)
         msg = "COX_FP8_E4M3 applies to COX_NEWTON_REFINE fits";
         return COX_EUNSUPPORTED;
     }
-    if (opt.ties != COX_BRESLOW) { msg = "only COX_BRESLOW ties"; return COX_EUNSUPPORTED; }
+    if (opt.ties != COX_BRESLOW && opt.ties != COX_EFRON) { msg = "ties must be COX_BRESLOW or COX_EFRON"; return COX_EINVAL; }
     if (!(opt.gamma >= 0.0) || !std::isfinite(opt.gamma)) { msg = "gamma must be finite and >= 0"; return COX_EINVAL; }
     if (!(opt.tol >= 0.0)) { msg = "tol must be >= 0"; return COX_EINVAL; }
     if (opt.max_iter < 1) { msg = "max_iter must be >= 1"; return COX_EINVAL; }
@@ -793,6 +793,7 @@ static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *bet
     L.n = h->n;
     L.p = (int)h->p;
     L.mode = mode;
+    L.efron = h->opt.ties == COX_EFRON ? 1 : 0;
     L.j0 = j0;
     L.j1 = j1;
     L.max_sweeps = h->opt.max_iter;

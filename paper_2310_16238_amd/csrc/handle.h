@@ -41,6 +41,20 @@ struct NewtonState {
     void *scan_scratch = nullptr;
     size_t scan_scratch_bytes = 0;
     hipEvent_t ev[6] = {};         // around evaluation, contraction, solve
+    // Efron's tie correction (see newton.hip): groups with two or more events get a second row of Z
+    bool efron = false;
+    int64_t n_multi = 0;           // tie groups with >= 2 events
+    int64_t n_zrows = 0;           // rows of Z in use: n_groups (+ n_multi with Efron)
+    int32_t *gidx2 = nullptr;      // [ld] index of the multi-event group ending at the row, else -1
+    int32_t *gend = nullptr;       // [ld] end row of an event row's tie group, else -1
+    int32_t *me_ptr = nullptr;     // [n_multi + 1] event rows of each multi-event group (me_row ranges)
+    int32_t *me_row = nullptr;     // [me_ptr[n_multi]]
+    int32_t *me_end = nullptr;     // [n_multi] end row of each multi-event group
+    double *me_w = nullptr;        // [me_ptr[n_multi]] exp(eta_r - m_end) of those rows
+    double *s1me = nullptr;        // [n_multi][p] S1' at the multi-event group ends
+    double *erows = nullptr;       // 4 x [ld]: E0', k', l21, l22 at event-group ends
+    double *epart = nullptr;       // [p][eblocks] diagonal parts of the multi-event groups
+    int eblocks = 0;
 };
 
 struct cox_handle {

@@ -46,6 +46,7 @@ struct CcdLaunch {
     int64_t n = 0;                   // real rows (rows n..ld-1 are padding)
     int p = 0;
     int mode = kModeFit;
+    int efron = 0;                   // 1: Efron's tie correction instead of the plain risk sets
     int j0 = 0, j1 = 0;              // evaluation: columns [j0, j1)
     int max_sweeps = 0;
     double tol = 0.0;
@@ -54,7 +55,7 @@ struct CcdLaunch {
     double *g2 = nullptr;            // [p] g''
     double *m2 = nullptr;            // [p] delta'(S[N2]/S[D])
     double *result = nullptr;        // [kResultSlots] see ResultSlot
-    void *agg = nullptr;             // [grid][3] packets: tile aggregates for the look-back
+    void *agg = nullptr;             // [grid][6] packets: tile aggregates for the look-back
     void *part = nullptr;            // [grid][5] packets: per-workgroup partial sums
     void *res = nullptr;             // [2] packets: the step broadcast by workgroup 0
     void *ctl = nullptr;             // control words

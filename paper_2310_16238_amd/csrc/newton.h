@@ -52,6 +52,16 @@ struct FullEvalArgs {
     bool want_xbar = true;            // form xbar, Z and the second diagonal part
     void *scan_scratch = nullptr;     // sync scratch of the row scans
     size_t scan_scratch_bytes = 0;
+    // Efron's tie correction: row vectors [ld] E0' (the group's own event weights, relative to
+    // exp(m)), k', and the Cholesky factor (zq = l11, l21, l22) of sum_l (1, -a_l)(1, -a_l)' / A_l^2;
+    // the multi-event groups (d >= 2) as lists of their event rows (see FullEvalArgs users)
+    bool efron = false;
+    double *e0 = nullptr, *kq = nullptr, *zq2 = nullptr, *zq3 = nullptr;
+    const int32_t *gidx2 = nullptr, *gend = nullptr;
+    const int32_t *me_ptr = nullptr, *me_row = nullptr, *me_end = nullptr;
+    double *me_w = nullptr, *s1me = nullptr, *epart = nullptr;
+    int64_t n_groups = 0, n_multi = 0, n_me_rows = 0;
+    int eblocks = 0;
 };
 
 // Objective, gradient and the two parts of the Hessian diagonal at beta,

@@ -14,6 +14,16 @@
 // X' products, and one per-column scan forms xbar; the information matrix is
 // two symmetric rank-K products (contraction.hip).
 //
+// Efron's tie correction (Efron 1977; the paper's risk sets are Breslow's): the l-th of the
+// d events of group g sees A_l = S0_g - (l/d) E0_g, E the sums over the group's own events.
+// With h_g = sum_l 1/A_l and k_g = sum_l (l/d)/A_l the same exchange of sums gives
+//   gradient     = X'(w o c - delta),  c_r = sum_{g: r in R_g} h_g - delta_r k_{g(r)}
+//   Hessian      = X' diag(w o c) X - sum_g [S1 E1] M_g [S1 E1]',  M_g = sum_l (1, -a_l)(1, -a_l)' / A_l^2
+//   objective    = -delta'eta + sum_g sum_l (log A_l + c)
+// and M_g = L L' (2 x 2 Cholesky) turns each group's term into two rows of Z: l11 S1 + l21 E1
+// and l22 E1.  For d = 1, a_0 = 0 and these are the plain terms (h = 1/S0, one row S1/S0), so
+// E1 is needed only for the groups with two or more events, whose event rows are listed.
+//
 // All kernels here are ordinary launches (no cross-workgroup waits).
 #include <hip/hip_bf16.h>
 #include <math.h>
@@ -120,6 +130,77 @@ __global__ __launch_bounds__(kRowBlock) void rowweight_kernel(const double *u, c
     if (r < ld) b[r] = u[r] * R[r];
 }
 
+// Efron at event-group ends, everything relative to exp(m_r) as above: A'_l = S0' - (l/d) E0',
+// h' = sum_l 1/A'_l, k' = sum_l (l/d)/A'_l, objective sum_l (log A'_l + m), and the factor of
+// M' = sum_l (1, -a_l)(1, -a_l)' / A'_l^2 (l11 in zq, l21, l22); -eta at event rows.
+__global__ __launch_bounds__(kRowBlock) void hazard_efron_kernel(const double *s0, const double *e0, const double *eta,
+                                                                 const double *m, const uint32_t *meta, int64_t ld,
+                                                                 double *h, double *kq, double *zq, double *zq2,
+                                                                 double *zq3, double *blockobj, unsigned *flags)
+{
+    __shared__ double red[kRowBlock / kWave];
+    const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+    double obj = 0.0;
+    if (r < ld) {
+        const uint32_t mw = meta[r];
+        const uint32_t d = mw & kCountMask;
+        double hv = 0.0, kv = 0.0, l11 = 0.0, l21 = 0.0, l22 = 0.0;
+        if (d != 0u) {
+            const double s = s0[r], ev = e0[r], mr = m[r], dd = (double)d;
+            if (!(s >= 0.5) || !(s <= 1e300)) atomicOr(flags, 1u);
+            double m11 = 0.0, m21 = 0.0, m22 = 0.0;
+            for (uint32_t l = 0; l < d; ++l) {
+                const double a = (double)l / dd;
+                const double A = s - a * ev;
+                const double iA = 1.0 / A, iA2 = iA * iA;
+                hv += iA;
+                kv += a * iA;
+                m11 += iA2;
+                m21 -= a * iA2;
+                m22 += a * a * iA2;
+                obj += log(A) + mr;
+            }
+            l11 = sqrt(m11);
+            l21 = m21 / l11;
+            l22 = sqrt(fmax(m22 - l21 * l21, 0.0));
+        }
+        if (mw & kEventBit) obj -= eta[r];
+        h[r] = hv;
+        kq[r] = kv;
+        zq[r] = l11;
+        zq2[r] = l21;
+        zq3[r] = l22;
+    }
+    obj = block_sum(obj, red);
+    if (threadIdx.x == 0) blockobj[blockIdx.x] = obj;
+}
+
+// b = w c = u R - delta exp(eta - m_e) k'_e, e the end row of the row's tie group
+__global__ __launch_bounds__(kRowBlock) void rowweight_efron_kernel(const double *u, const double *R, const double *eta,
+                                                                    const double *m, const double *kq,
+                                                                    const int32_t *gend, int64_t ld, double *b)
+{
+    const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+    if (r < ld) {
+        double v = u[r] * R[r];
+        const int32_t e = gend[r];
+        if (e >= 0) v -= exp(eta[r] - m[e]) * kq[e];
+        b[r] = v;
+    }
+}
+
+// me_w[q] = exp(eta - m_end) of the listed event rows of the multi-event groups
+__global__ __launch_bounds__(kRowBlock) void efron_w_kernel(const double *eta, const double *m, const int32_t *me_ptr,
+                                                            const int32_t *me_row, const int32_t *me_end,
+                                                            int64_t n_multi, double *me_w)
+{
+    const int64_t k = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+    if (k < n_multi) {
+        const double me = m[me_end[k]];
+        for (int32_t q = me_ptr[k]; q < me_ptr[k + 1]; ++q) me_w[q] = exp(eta[me_row[q]] - me);
+    }
+}
+
 template <typename ZT>
 __device__ __forceinline__ void store_z(ZT *p, double v, float inv_scale)
 {
@@ -221,13 +302,16 @@ __device__ __forceinline__ void aff_step(uint32_t &f, double &a, double (&b)[CB]
     f = f | sf;
 }
 
-template <typename ZT, bool XBAR>
+// EFRON: at the end of a group with two or more events S1' goes to s1me (its rows of Z
+// are formed with E1 by efron_z_kernel); the other groups' rows are the plain ones.
+template <typename ZT, bool XBAR, bool EFRON>
 __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double *x, int64_t ld, int p, int64_t tile,
                                                                     int ntiles, const double *alpha, const double *u,
                                                                     const double *zq, const double *b,
                                                                     const uint32_t *meta, const int32_t *gidx,
                                                                     const uint8_t *tile_carry, const double *carry,
-                                                                    int64_t ldz, const float *zscale, ZT *z, double *part)
+                                                                    int64_t ldz, const float *zscale, ZT *z, double *part,
+                                                                    const int32_t *gidx2, double *s1me)
 {
     constexpr int CB = kColBlock;
     const int lane = threadIdx.x & (kWave - 1);
@@ -259,7 +343,7 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
     struct Chunk {
         double xv[CB][kColIpt], bv[kColIpt], av[kColIpt], uv[kColIpt], qv[kColIpt];
         uint32_t m[kColIpt];
-        int32_t gi[kColIpt];
+        int32_t gi[kColIpt], g2[EFRON ? kColIpt : 1];
     };
     auto load_chunk = [&](Chunk &k, int64_t r0) {
 #pragma unroll
@@ -279,6 +363,13 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
             k.gi[1] = gg.y;
             k.gi[2] = gg.z;
             k.gi[3] = gg.w;
+            if constexpr (EFRON) {
+                const int4 g2 = *reinterpret_cast<const int4 *>(gidx2 + r0);
+                k.g2[0] = g2.x;
+                k.g2[1] = g2.y;
+                k.g2[2] = g2.z;
+                k.g2[3] = g2.w;
+            }
         }
     };
     Chunk cur;
@@ -338,9 +429,13 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
                     const double ux = uv[i] * xv[c][i];
                     run = (m[i] >> 31) ? ux : fma(av[i], run, ux);
                     if ((m[i] & kCountMask) && live[c]) {
-                        const double zv = run * qv[i];   // sqrt(d) xbar
-                        d2[c] = fma(zv, zv, d2[c]);
-                        store_z<ZT>(&z[(int64_t)(j0 + c) * ldz + gi[i]], zv, zs[c]);
+                        if (EFRON && cur.g2[EFRON ? i : 0] >= 0) {
+                            s1me[(int64_t)cur.g2[EFRON ? i : 0] * p + j0 + c] = run;
+                        } else {
+                            const double zv = run * qv[i];   // sqrt(d) xbar
+                            d2[c] = fma(zv, zv, d2[c]);
+                            store_z<ZT>(&z[(int64_t)(j0 + c) * ldz + gi[i]], zv, zs[c]);
+                        }
                     }
                 }
                 const double tb = readlane63(bb[c]);
@@ -363,6 +458,55 @@ __global__ __launch_bounds__(kWave * kColWaves) void colpass_kernel(const double
             o[1] = s1;
             o[2] = s2;
         }
+    }
+}
+
+// Rows of Z of the multi-event groups (Efron): for group k and column j = blockIdx.y,
+// E1' = sum over its event rows of exp(eta_r - m_end) x_rj, then z1 = l11 S1' + l21 E1' at the
+// group's own row and z2 = l22 E1' at row n_groups + k; the workgroup's sum of z1^2 + z2^2 goes
+// to epart[j][blockIdx.x] (fixed-order tree).
+template <typename ZT>
+__global__ __launch_bounds__(kRowBlock) void efron_z_kernel(const double *x, int64_t ld, int p, const int32_t *me_ptr,
+                                                            const int32_t *me_row, const int32_t *me_end,
+                                                            const double *me_w, const double *s1me,
+                                                            const double *zq, const double *zq2, const double *zq3,
+                                                            const int32_t *gidx, int64_t n_groups, int64_t n_multi,
+                                                            int64_t ldz, const float *zscale, ZT *z, double *epart,
+                                                            int eblocks)
+{
+    __shared__ double tree[kRowBlock];
+    const int j = blockIdx.y;
+    const int64_t k = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+    double sq = 0.0;
+    if (k < n_multi && j < p) {
+        const double *xj = x + (int64_t)j * ld;
+        double e1 = 0.0;
+        for (int32_t q = me_ptr[k]; q < me_ptr[k + 1]; ++q) e1 = fma(me_w[q], xj[me_row[q]], e1);
+        const int32_t e = me_end[k];
+        const double s1 = s1me[k * p + j];
+        const double z1 = fma(zq[e], s1, zq2[e] * e1), z2 = zq3[e] * e1;
+        const float inv = zscale ? 1.0f / zscale[j] : 1.0f;
+        store_z<ZT>(&z[(int64_t)j * ldz + gidx[e]], z1, inv);
+        store_z<ZT>(&z[(int64_t)j * ldz + n_groups + k], z2, inv);
+        sq = fma(z1, z1, z2 * z2);
+    }
+    tree[threadIdx.x] = sq;
+    __syncthreads();
+    for (int h = kRowBlock / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) tree[threadIdx.x] += tree[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && j < p) epart[(int64_t)j * eblocks + blockIdx.x] = tree[0];
+}
+
+// diag2[j] += the multi-event groups' parts, summed in block order
+__global__ __launch_bounds__(kWave) void efron_d2_kernel(const double *epart, int eblocks, int p, double *diag2)
+{
+    const int j = blockIdx.x * kWave + threadIdx.x;
+    if (j < p) {
+        double s = 0.0;
+        for (int k = 0; k < eblocks; ++k) s += epart[(int64_t)j * eblocks + k];
+        diag2[j] += s;
     }
 }
 
@@ -535,6 +679,21 @@ struct BWrite {
     __device__ void operator()(int64_t k, const AffE &e) const { out[k] = e.b; }
 };
 
+// Efron's E0' (forward): the running sum of u over event rows, restarting at stratum heads and
+// after every row that ends a tie group with events, so at a group end it is the group's own
+// E0 relative to exp(m_end): E0'_r = alpha_r E0'_{r-1} + delta_r u_r
+struct E0Load {
+    static constexpr bool kReverse = false;
+    const double *alpha, *u;
+    const uint32_t *meta;
+    __device__ AffE operator()(int64_t k) const
+    {
+        const uint32_t mk = meta[k];
+        const bool restart = (mk & kHeadBit) || k == 0 || (meta[k - 1] & kCountMask) != 0u;
+        return AffE{restart ? 1u : 0u, alpha[k], (mk & kEventBit) ? u[k] : 0.0};
+    }
+};
+
 // R (reverse, scan position k = row n-1-k): R_r = h'_r + alpha_{r+1} R_{r+1},
 // a segment starting at each stratum's last row
 struct RLoad {
@@ -603,11 +762,22 @@ int full_eval_launch(const FullEvalArgs &A, hipStream_t stream)
     rc = tile_scan<AffOp>(S0Load{A.alpha, A.w, A.meta}, BWrite{A.s0}, ld, A.tile, A.scan_scratch,
                           A.scan_scratch_bytes, stream);
     if (rc) return rc;
-    hazard_kernel<<<nb, kRowBlock, 0, stream>>>(A.s0, A.eta, A.m, A.meta, ld, A.h, A.zq, A.blockbuf, A.flags);
+    if (A.efron) {
+        rc = tile_scan<AffOp>(E0Load{A.alpha, A.w, A.meta}, BWrite{A.e0}, ld, A.tile, A.scan_scratch,
+                              A.scan_scratch_bytes, stream);
+        if (rc) return rc;
+        hazard_efron_kernel<<<nb, kRowBlock, 0, stream>>>(A.s0, A.e0, A.eta, A.m, A.meta, ld, A.h, A.kq, A.zq, A.zq2,
+                                                          A.zq3, A.blockbuf, A.flags);
+    } else {
+        hazard_kernel<<<nb, kRowBlock, 0, stream>>>(A.s0, A.eta, A.m, A.meta, ld, A.h, A.zq, A.blockbuf, A.flags);
+    }
     rc = tile_scan<AffOp>(RLoad{A.alpha, A.h, A.meta, ld}, RWrite{A.lam, ld}, ld, A.tile, A.scan_scratch,
                           A.scan_scratch_bytes, stream);
     if (rc) return rc;
-    rowweight_kernel<<<nb, kRowBlock, 0, stream>>>(A.w, A.lam, ld, A.b);
+    if (A.efron)
+        rowweight_efron_kernel<<<nb, kRowBlock, 0, stream>>>(A.w, A.lam, A.eta, A.m, A.kq, A.gend, ld, A.b);
+    else
+        rowweight_kernel<<<nb, kRowBlock, 0, stream>>>(A.w, A.lam, ld, A.b);
     if (A.n_agg > 0) {
         colagg_kernel<<<(A.n_agg * A.p + kColWaves - 1) / kColWaves, kWave * kColWaves, 0, stream>>>(
             A.x, ld, A.p, A.alpha, A.w, A.meta, A.tile, A.agg_tiles, A.n_agg, A.lasthead, A.agg);
@@ -615,17 +785,39 @@ int full_eval_launch(const FullEvalArgs &A, hipStream_t stream)
                                                                A.carry);
     }
     const int grid = 8 * ((A.ntiles + 7) / 8) * ((A.p + kColWaves * kColBlock - 1) / (kColWaves * kColBlock));
-#define COXMI_COLPASS(ZT, XB)                                                                                  \
-    colpass_kernel<ZT, XB><<<grid, kWave * kColWaves, 0, stream>>>(                                            \
+#define COXMI_COLPASS(ZT, XB, EF)                                                                              \
+    colpass_kernel<ZT, XB, EF><<<grid, kWave * kColWaves, 0, stream>>>(                                        \
         A.x, ld, A.p, A.tile, A.ntiles, A.alpha, A.w, A.zq, A.b, A.meta, A.gidx, A.tile_carry, A.carry, A.ldz, \
-        A.zscale, static_cast<ZT *>(A.z), A.colpart)
-    if (!A.want_xbar) COXMI_COLPASS(double, false);
-    else if (A.ztype == kZF64) COXMI_COLPASS(double, true);
-    else if (A.ztype == kZF32) COXMI_COLPASS(float, true);
-    else COXMI_COLPASS(__hip_bfloat16, true);
+        A.zscale, static_cast<ZT *>(A.z), A.colpart, A.gidx2, A.s1me)
+    const bool ef = A.efron && A.n_multi > 0;
+    if (!A.want_xbar) COXMI_COLPASS(double, false, false);
+    else if (A.ztype == kZF64) {
+        if (ef) COXMI_COLPASS(double, true, true);
+        else COXMI_COLPASS(double, true, false);
+    } else if (A.ztype == kZF32) {
+        COXMI_COLPASS(float, true, false);
+    } else {
+        if (ef) COXMI_COLPASS(__hip_bfloat16, true, true);
+        else COXMI_COLPASS(__hip_bfloat16, true, false);
+    }
 #undef COXMI_COLPASS
     colreduce_kernel<<<A.p + 1, kRowBlock, 0, stream>>>(A.colpart, A.p, A.ntiles, A.grad, A.diag1, A.diag2,
                                                         A.blockbuf, nb, A.scal);
+    if (ef && A.want_xbar) {
+        if (A.ztype == kZF32) return -5;
+        efron_w_kernel<<<(unsigned)((A.n_multi + kRowBlock - 1) / kRowBlock), kRowBlock, 0, stream>>>(
+            A.eta, A.m, A.me_ptr, A.me_row, A.me_end, A.n_multi, A.me_w);
+        const dim3 zg((unsigned)A.eblocks, (unsigned)A.p);
+        if (A.ztype == kZF64)
+            efron_z_kernel<double><<<zg, kRowBlock, 0, stream>>>(
+                A.x, ld, A.p, A.me_ptr, A.me_row, A.me_end, A.me_w, A.s1me, A.zq, A.zq2, A.zq3, A.gidx, A.n_groups,
+                A.n_multi, A.ldz, A.zscale, static_cast<double *>(A.z), A.epart, A.eblocks);
+        else
+            efron_z_kernel<__hip_bfloat16><<<zg, kRowBlock, 0, stream>>>(
+                A.x, ld, A.p, A.me_ptr, A.me_row, A.me_end, A.me_w, A.s1me, A.zq, A.zq2, A.zq3, A.gidx, A.n_groups,
+                A.n_multi, A.ldz, A.zscale, static_cast<__hip_bfloat16 *>(A.z), A.epart, A.eblocks);
+        efron_d2_kernel<<<(A.p + kWave - 1) / kWave, kWave, 0, stream>>>(A.epart, A.eblocks, A.p, A.diag2);
+    }
     e = hipGetLastError();
     return e == hipSuccess ? 0 : -3;
 }

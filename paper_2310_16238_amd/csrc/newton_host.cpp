@@ -57,7 +57,37 @@ int newton_setup(cox_handle *h)
         head[h->pos[i]] = (h->meta[i] & kHeadBit) ? 1 : 0;
     }
     s.n_groups = G;
-    s.ldz = std::max<int64_t>(128, (G + 127) / 128 * 128);   // K chunks of the contraction are 128 rows
+    // Efron: the event rows of every group with two or more events, and for every event row
+    // the end row of its group (a group's events are the event rows after the previous
+    // event-group end of the stratum, up to its own end)
+    s.efron = h->opt.ties == COX_EFRON;
+    std::vector<int32_t> gidx2, gend, me_ptr, me_row, me_end;
+    if (s.efron) {
+        gidx2.assign(ld, -1);
+        gend.assign(ld, -1);
+        me_ptr.push_back(0);
+        std::vector<int32_t> pending;
+        for (int64_t i = 0; i < n; ++i) {
+            if (h->meta[i] & kHeadBit) pending.clear();
+            if (h->meta[i] & kEventBit) pending.push_back((int32_t)h->pos[i]);
+            const uint32_t d = h->meta[i] & kCountMask;
+            if (d == 0u) continue;
+            if (pending.size() != d) return handle_fail(h, COX_EDEVICE, "inconsistent tie groups");
+            const int32_t e = (int32_t)h->pos[i];
+            for (int32_t r : pending) gend[(size_t)r] = e;
+            if (d >= 2u) {
+                gidx2[(size_t)e] = (int32_t)me_end.size();
+                me_end.push_back(e);
+                me_row.insert(me_row.end(), pending.begin(), pending.end());
+                me_ptr.push_back((int32_t)me_row.size());
+            }
+            pending.clear();
+        }
+    }
+    s.n_multi = (int64_t)me_end.size();
+    s.n_zrows = G + s.n_multi;
+    s.eblocks = (int)std::max<int64_t>(1, (s.n_multi + 255) / 256);
+    s.ldz = std::max<int64_t>(128, (s.n_zrows + 127) / 128 * 128);   // K chunks of the contraction are 128 rows
     s.max_blocks = (int)((ld + 255) / 256) + 1;
     // column-pass tiles: the persistent kernel's tiles (ld = grid * tile)
     s.tile = ld / h->shape.grid;
@@ -117,6 +147,27 @@ int newton_setup(cox_handle *h)
     if (e == hipSuccess && s.n_agg)
         e = hipMemcpy(s.agg_tiles, agg_tiles.data(), sizeof(int32_t) * s.n_agg, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(s.z, 0, zb * (size_t)p * s.ldz);
+    if (e == hipSuccess && s.efron) {
+        const size_t nme = std::max<size_t>(1, me_row.size()), nm = (size_t)std::max<int64_t>(1, s.n_multi);
+        if (e == hipSuccess) e = dalloc(&s.gidx2, sizeof(int32_t) * ld);
+        if (e == hipSuccess) e = dalloc(&s.gend, sizeof(int32_t) * ld);
+        if (e == hipSuccess) e = dalloc(&s.me_ptr, sizeof(int32_t) * (nm + 1));
+        if (e == hipSuccess) e = dalloc(&s.me_row, sizeof(int32_t) * nme);
+        if (e == hipSuccess) e = dalloc(&s.me_end, sizeof(int32_t) * nm);
+        if (e == hipSuccess) e = dalloc(&s.me_w, sizeof(double) * nme);
+        if (e == hipSuccess) e = dalloc(&s.s1me, sizeof(double) * nm * p);
+        if (e == hipSuccess) e = dalloc(&s.erows, sizeof(double) * 4 * ld);
+        if (e == hipSuccess) e = dalloc(&s.epart, sizeof(double) * (size_t)s.eblocks * p);
+        if (e == hipSuccess) e = hipMemcpy(s.gidx2, gidx2.data(), sizeof(int32_t) * ld, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(s.gend, gend.data(), sizeof(int32_t) * ld, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(s.me_ptr, me_ptr.data(), sizeof(int32_t) * me_ptr.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !me_row.empty())
+            e = hipMemcpy(s.me_row, me_row.data(), sizeof(int32_t) * me_row.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !me_end.empty())
+            e = hipMemcpy(s.me_end, me_end.data(), sizeof(int32_t) * me_end.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(s.erows, 0, sizeof(double) * 4 * ld);
+    }
     if (e != hipSuccess) {
         newton_free(h);
         return handle_hip_fail(h, e, "uploading group indices");
@@ -212,6 +263,24 @@ int newton_eval(cox_handle *h, const double *beta, bool want_xbar, EvalOut &out)
     A.want_xbar = want_xbar;
     A.scan_scratch = s.scan_scratch;
     A.scan_scratch_bytes = s.scan_scratch_bytes;
+    if (s.efron) {
+        A.efron = true;
+        A.e0 = s.erows;
+        A.kq = s.erows + ld;
+        A.zq2 = s.erows + 2 * ld;
+        A.zq3 = s.erows + 3 * ld;
+        A.gidx2 = s.gidx2;
+        A.gend = s.gend;
+        A.me_ptr = s.me_ptr;
+        A.me_row = s.me_row;
+        A.me_end = s.me_end;
+        A.me_w = s.me_w;
+        A.s1me = s.s1me;
+        A.epart = s.epart;
+        A.n_groups = s.n_groups;
+        A.n_multi = s.n_multi;
+        A.eblocks = s.eblocks;
+    }
     (void)hipEventRecord(s.ev[0], h->stream);
     int rc = full_eval_launch(A, h->stream);
     if (rc != 0) return handle_fail(h, rc == -5 ? COX_EUNSUPPORTED : COX_EDEVICE, "full evaluation launch");
@@ -254,13 +323,13 @@ int newton_info(cox_handle *h)
         else
             rc = syrk_bf16(static_cast<const uint16_t *>(s.xlp), ld, p, s.xscale, b, ld, kSplitsXBF16, s.syrk_part,
                            1.0, 0, s.info, h->stream);
-        if (rc == 0 && s.n_groups > 0)
-            rc = syrk_bf16(static_cast<const uint16_t *>(s.z), s.ldz, p, s.zscale, nullptr, s.n_groups, kSplitsZBF16,
+        if (rc == 0 && s.n_zrows > 0)
+            rc = syrk_bf16(static_cast<const uint16_t *>(s.z), s.ldz, p, s.zscale, nullptr, s.n_zrows, kSplitsZBF16,
                            s.syrk_part, -1.0, 1, s.info, h->stream);
     } else {
         rc = syrk_f64(h->d_x, ld, p, b, ld, kSplitsXF64, s.syrk_part, 1.0, 0, s.info, h->stream);
-        if (rc == 0 && s.n_groups > 0)
-            rc = syrk_f64(static_cast<const double *>(s.z), s.ldz, p, nullptr, s.n_groups, kSplitsZF64, s.syrk_part,
+        if (rc == 0 && s.n_zrows > 0)
+            rc = syrk_f64(static_cast<const double *>(s.z), s.ldz, p, nullptr, s.n_zrows, kSplitsZF64, s.syrk_part,
                           -1.0, 1, s.info, h->stream);
     }
     if (rc != 0) return handle_fail(h, COX_EDEVICE, "information-matrix contraction launch");
@@ -275,7 +344,8 @@ void newton_free(cox_handle *h)
     NewtonState &s = h->nt;
     void *ptrs[] = {s.gidx, s.rows, s.blockbuf, s.tile_carry, s.lasthead, s.agg_tiles, s.agg, s.carry,
                     s.colpart, s.vec, s.flags, s.status, s.free_col, s.z,
-                    s.zscale, s.xlp, s.xscale, s.syrk_part, s.info, s.scan_scratch, s.wscratch};
+                    s.zscale, s.xlp, s.xscale, s.syrk_part, s.info, s.scan_scratch, s.wscratch,
+                    s.gidx2, s.gend, s.me_ptr, s.me_row, s.me_end, s.me_w, s.s1me, s.erows, s.epart};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (s.hvec) (void)hipHostFree(s.hvec);
@@ -322,6 +392,8 @@ extern "C" int cox_baseline_hazard(cox_handle *h, const double *beta, double *cu
 {
     if (!h) return handle_fail(nullptr, COX_EINVAL, "handle is NULL");
     if (!beta || !cumhaz) return handle_fail(h, COX_EINVAL, "beta and cumhaz are required");
+    if (h->opt.ties == COX_EFRON)
+        return handle_fail(h, COX_EUNSUPPORTED, "the baseline hazard is the Breslow estimator (COX_BRESLOW handles)");
     (void)hipSetDevice(h->device);
     int rc = newton_setup(h);
     if (rc != COX_OK) return rc;

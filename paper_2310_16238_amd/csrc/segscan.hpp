@@ -30,16 +30,20 @@ namespace coxmi {
 
 constexpr int kWave = 64;
 
-template <int K>
+// Components 0..KS-1 restart at elements whose flag has bit 0 set, components KS..K-1
+// at elements whose flag has bit 1 set: two segmented scans with different segment
+// boundaries carried in one element.  With KS = K it is one scan, restarting at any
+// nonzero flag.  Each is the flag-value operator above, so the pair is associative too.
+template <int K, int KS = K>
 struct SegVal {
     uint32_t f;
     double v[K];
 };
 
-template <int K>
-__device__ __forceinline__ SegVal<K> seg_identity()
+template <int K, int KS = K>
+__device__ __forceinline__ SegVal<K, KS> seg_identity()
 {
-    SegVal<K> r;
+    SegVal<K, KS> r;
     r.f = 0u;
 #pragma unroll
     for (int k = 0; k < K; ++k) r.v[k] = 0.0;
@@ -47,13 +51,21 @@ __device__ __forceinline__ SegVal<K> seg_identity()
 }
 
 // a is the earlier (left) element, b the later one.
-template <int K>
-__device__ __forceinline__ SegVal<K> seg_combine(const SegVal<K> &a, const SegVal<K> &b)
+template <int K, int KS>
+__device__ __forceinline__ SegVal<K, KS> seg_combine(const SegVal<K, KS> &a, const SegVal<K, KS> &b)
 {
-    SegVal<K> r;
+    SegVal<K, KS> r;
     r.f = a.f | b.f;
+    if constexpr (KS == K) {
+        // one scan: any flag bit restarts.  a * keep + b with keep = 0 or 1 is b or a + b
+        // exactly (one rounding, as the sum), for finite a: one FMA per component
+        const double keep = b.f ? 0.0 : 1.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) r.v[k] = b.f ? b.v[k] : a.v[k] + b.v[k];
+        for (int k = 0; k < K; ++k) r.v[k] = fma(a.v[k], keep, b.v[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) r.v[k] = (b.f & (k < KS ? 1u : 2u)) ? b.v[k] : a.v[k] + b.v[k];
+    }
     return r;
 }
 
@@ -74,10 +86,10 @@ __device__ __forceinline__ uint32_t dpp_u32(uint32_t x)
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xF, false);
 }
 
-template <int CTRL, int ROWS, int K>
-__device__ __forceinline__ SegVal<K> dpp_seg(const SegVal<K> &x)
+template <int CTRL, int ROWS, int K, int KS>
+__device__ __forceinline__ SegVal<K, KS> dpp_seg(const SegVal<K, KS> &x)
 {
-    SegVal<K> r;
+    SegVal<K, KS> r;
     r.f = dpp_u32<CTRL, ROWS>(x.f);
 #pragma unroll
     for (int k = 0; k < K; ++k) r.v[k] = dpp_f64<CTRL, ROWS>(x.v[k]);
@@ -86,8 +98,8 @@ __device__ __forceinline__ SegVal<K> dpp_seg(const SegVal<K> &x)
 
 // Inclusive segmented scan across the 64 lanes (lane order = row order).
 // All 64 lanes must be active.
-template <int K>
-__device__ __forceinline__ SegVal<K> wave_inclusive_scan(SegVal<K> x)
+template <int K, int KS>
+__device__ __forceinline__ SegVal<K, KS> wave_inclusive_scan(SegVal<K, KS> x)
 {
     x = seg_combine(dpp_seg<0x111, 0xF>(x), x);
     x = seg_combine(dpp_seg<0x112, 0xF>(x), x);
@@ -99,10 +111,10 @@ __device__ __forceinline__ SegVal<K> wave_inclusive_scan(SegVal<K> x)
 }
 
 // Lane i receives lane i-1's value; lane 0 receives the identity.
-template <int K>
-__device__ __forceinline__ SegVal<K> wave_shift_right(const SegVal<K> &x)
+template <int K, int KS>
+__device__ __forceinline__ SegVal<K, KS> wave_shift_right(const SegVal<K, KS> &x)
 {
-    return dpp_seg<0x138, 0xF, K>(x);
+    return dpp_seg<0x138, 0xF, K, KS>(x);
 }
 
 __device__ __forceinline__ double lane63_f64(double x)
@@ -113,10 +125,10 @@ __device__ __forceinline__ double lane63_f64(double x)
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-template <int K>
-__device__ __forceinline__ SegVal<K> lane63_seg(const SegVal<K> &x)
+template <int K, int KS>
+__device__ __forceinline__ SegVal<K, KS> lane63_seg(const SegVal<K, KS> &x)
 {
-    SegVal<K> r;
+    SegVal<K, KS> r;
     r.f = (uint32_t)__builtin_amdgcn_readlane((int)x.f, 63);
 #pragma unroll
     for (int k = 0; k < K; ++k) r.v[k] = lane63_f64(x.v[k]);
@@ -127,19 +139,20 @@ __device__ __forceinline__ SegVal<K> lane63_seg(const SegVal<K> &x)
 // Returns the thread's exclusive prefix; `total` receives the workgroup's
 // total in every thread.  One barrier.  `wtot` is LDS of NW elements that
 // must not be rewritten before a later barrier.
-template <int K, int NW>
-__device__ __forceinline__ SegVal<K> block_exclusive_scan(const SegVal<K> &x, SegVal<K> *wtot, SegVal<K> &total)
+template <int K, int NW, int KS = K>
+__device__ __forceinline__ SegVal<K, KS> block_exclusive_scan(const SegVal<K, KS> &x, SegVal<K, KS> *wtot,
+                                                              SegVal<K, KS> &total)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    const SegVal<K> inc = wave_inclusive_scan(x);
-    const SegVal<K> exc = wave_shift_right(inc);
+    const SegVal<K, KS> inc = wave_inclusive_scan(x);
+    const SegVal<K, KS> exc = wave_shift_right(inc);
     if (lane == kWave - 1) wtot[w] = inc;
     __syncthreads();
-    SegVal<K> pre = seg_identity<K>(), tot = seg_identity<K>();
+    SegVal<K, KS> pre = seg_identity<K, KS>(), tot = seg_identity<K, KS>();
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
-        const SegVal<K> t = wtot[k];
+        const SegVal<K, KS> t = wtot[k];
         if (k < w) pre = seg_combine(pre, t);
         tot = seg_combine(tot, t);
     }
@@ -259,8 +272,8 @@ __device__ __forceinline__ bool packets_wait(const PacketArray &a, uint32_t inde
 // ------------------------------------------------------------------ look-back
 
 // Publish a tile aggregate as K packets at index K*b: (v0, epoch, f), (v1, epoch), ...
-template <int K>
-__device__ __forceinline__ void publish_aggregate(const PacketArray &agg, int b, const SegVal<K> &a, uint32_t epoch)
+template <int K, int KS>
+__device__ __forceinline__ void publish_aggregate(const PacketArray &agg, int b, const SegVal<K, KS> &a, uint32_t epoch)
 {
 #pragma unroll
     for (int k = 0; k < K; ++k) packet_put(agg, (uint32_t)(K * b + k), a.v[k], epoch, k == 0 ? a.f : 0u);
@@ -274,15 +287,15 @@ __device__ __forceinline__ void publish_aggregate(const PacketArray &agg, int b,
 // win[k]; after one barrier every thread folds the windows from the
 // farthest to the nearest.  Heads inside a window cut the carry as the
 // operator requires.  Returns false (uniformly) on abort.
-template <int K>
+template <int K, int KS = K>
 __device__ __forceinline__ bool look_back(int b, uint32_t epoch, const PacketArray &agg, SyncCtl *ctl,
-                                          SegVal<K> *win, int *abort_flag, SegVal<K> &carry)
+                                          SegVal<K, KS> *win, int *abort_flag, SegVal<K, KS> &carry)
 {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int nwin = (b + kWave - 1) / kWave;
     if (w < nwin) {
         const int q = b - kWave * (w + 1) + lane;
-        SegVal<K> x = seg_identity<K>();
+        SegVal<K, KS> x = seg_identity<K, KS>();
         bool ok = true;
         if (q >= 0) {
             u32x4 r[K];
@@ -294,12 +307,12 @@ __device__ __forceinline__ bool look_back(int b, uint32_t epoch, const PacketArr
             }
         }
         if (!ok) *abort_flag = 1;
-        const SegVal<K> inc = wave_inclusive_scan(x);
+        const SegVal<K, KS> inc = wave_inclusive_scan(x);
         if (lane == kWave - 1) win[w] = inc;
     }
     __syncthreads();
     if (*abort_flag) return false;
-    carry = seg_identity<K>();
+    carry = seg_identity<K, KS>();
     for (int k = nwin - 1; k >= 0; --k) carry = seg_combine(carry, win[k]);
     return true;
 }

@@ -45,7 +45,7 @@ def _data(n=20, p=3):
     return rng.standard_normal((n, p)), rng.exponential(1.0, n), (rng.random(n) < 0.5).astype(np.uint8)
 
 
-@pytest.mark.parametrize("case", ["nan_time", "inf_time", "event2", "gamma_neg", "tol_neg", "maxit0"])
+@pytest.mark.parametrize("case", ["nan_time", "inf_time", "event2", "gamma_neg", "tol_neg", "maxit0", "ties"])
 def test_init_rejects_bad_inputs(case):
     X, t, e = _data()
     kw = {}
@@ -61,6 +61,8 @@ def test_init_rejects_bad_inputs(case):
         kw["tol"] = -1e-3
     elif case == "maxit0":
         kw["max_iter"] = 0
+    elif case == "ties":
+        kw["ties"] = 7            # neither COX_BRESLOW nor COX_EFRON
     with pytest.raises(coxmi.CoxError) as ei:
         coxmi.cox_init(X, t, e, **kw)
     assert ei.value.code == coxmi.COX_EINVAL
