@@ -497,7 +497,9 @@ __device__ __forceinline__ Partial pass2(RowVal<EFRON> run, const uint32_t (&met
 
 // ------------------------------------------------------------------ the persistent kernel
 
-template <int BLOCK, int IPT, bool BITS, bool EFRON>
+// WAVE: the layout puts every stratum inside one wave's rows, so a wave's first row is a
+// stratum head and its scan needs nothing from the other waves: no workgroup scan, no barrier.
+template <int BLOCK, int IPT, bool BITS, bool EFRON, bool WAVE>
 __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 {
     constexpr int NW = BLOCK / kWave;
@@ -608,13 +610,18 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
                 wv[i] = exp_table(eta[i] - c, s_exptab);
                 tagg = seg_combine(tagg, row_value<EFRON>(meta[i], wv[i], xc[i]));
             }
-            RV btot;
-            RV exc = block_exclusive_scan<KV, NW, 3>(tagg, s_wtot, btot);
-            if (t == 0) publish_aggregate(agg, b, btot, epoch);
-            if (!tile_head) {
-                RV carry;
-                if (!look_back<KV, 3>(b, epoch, agg, ctl, s_win, &s_abort, carry)) return;
-                exc = seg_combine(carry, exc);
+            RV exc;
+            if constexpr (WAVE) {
+                exc = wave_shift_right(wave_inclusive_scan(tagg));
+            } else {
+                RV btot;
+                exc = block_exclusive_scan<KV, NW, 3>(tagg, s_wtot, btot);
+                if (t == 0) publish_aggregate(agg, b, btot, epoch);
+                if (!tile_head) {
+                    RV carry;
+                    if (!look_back<KV, 3>(b, epoch, agg, ctl, s_win, &s_abort, carry)) return;
+                    exc = seg_combine(carry, exc);
+                }
             }
 
             // pass 2: inclusive prefixes at group ends -> per-coordinate sums
@@ -772,38 +779,44 @@ size_t ccd_smem_bytes(int, int p)
     return sizeof(double) * (size_t)p;
 }
 
-template <int IPT, bool BITS, bool EFRON>
+template <int IPT, bool BITS, bool EFRON, bool WAVE>
 const void *ccd_fn()
 {
-    return reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, IPT, BITS, EFRON>);
+    return reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, IPT, BITS, EFRON, WAVE>);
 }
 
-template <bool BITS, bool EFRON>
+template <bool BITS, bool EFRON, bool WAVE>
 const void *ccd_fn_ipt(int ipt)
 {
     switch (ipt) {
-    case 1: return ccd_fn<1, BITS, EFRON>();
-    case 2: return ccd_fn<2, BITS, EFRON>();
-    case 4: return ccd_fn<4, BITS, EFRON>();
-    case 8: return ccd_fn<8, BITS, EFRON>();
-    case 16: return ccd_fn<16, BITS, EFRON>();
+    case 1: return ccd_fn<1, BITS, EFRON, WAVE>();
+    case 2: return ccd_fn<2, BITS, EFRON, WAVE>();
+    case 4: return ccd_fn<4, BITS, EFRON, WAVE>();
+    case 8: return ccd_fn<8, BITS, EFRON, WAVE>();
+    case 16: return ccd_fn<16, BITS, EFRON, WAVE>();
     default: return nullptr;
     }
 }
 
-const void *ccd_function(int ipt, bool bits, bool efron)
+template <bool WAVE>
+const void *ccd_function_w(int ipt, bool bits, bool efron)
 {
-    if (bits) return efron ? ccd_fn_ipt<true, true>(ipt) : ccd_fn_ipt<true, false>(ipt);
-    return efron ? ccd_fn_ipt<false, true>(ipt) : ccd_fn_ipt<false, false>(ipt);
+    if (bits) return efron ? ccd_fn_ipt<true, true, WAVE>(ipt) : ccd_fn_ipt<true, false, WAVE>(ipt);
+    return efron ? ccd_fn_ipt<false, true, WAVE>(ipt) : ccd_fn_ipt<false, false, WAVE>(ipt);
+}
+
+const void *ccd_function(int ipt, bool bits, bool efron, bool wave)
+{
+    return wave ? ccd_function_w<true>(ipt, bits, efron) : ccd_function_w<false>(ipt, bits, efron);
 }
 
 // Workgroups of the persistent kernel that fit on one compute unit; every variant
-// (indicator X, Efron) must fit, since a handle may run any of them.
+// (indicator X, Efron, wave-aligned layout) must fit, since a handle may run any of them.
 int occupancy_for(int ipt, int p, int *blocks)
 {
     *blocks = 1 << 30;
-    for (int v = 0; v < 4; ++v) {
-        const void *fn = ccd_function(ipt, (v & 1) != 0, (v & 2) != 0);
+    for (int v = 0; v < 8; ++v) {
+        const void *fn = ccd_function(ipt, (v & 1) != 0, (v & 2) != 0, (v & 4) != 0);
         if (!fn) return (int)hipErrorInvalidValue;
         int nb = 0;
         const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kCcdBlock, ccd_smem_bytes(ipt, p));
@@ -849,7 +862,7 @@ int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream,
     CcdLaunch arg = L;
     void *args[] = {&arg};
     const size_t smem = ccd_smem_bytes(shape.ipt, L.p);
-    const void *fn = ccd_function(shape.ipt, L.xbits != nullptr, L.efron != 0);
+    const void *fn = ccd_function(shape.ipt, L.xbits != nullptr, L.efron != 0, shape.wave);
     if (!fn) return (int)hipErrorInvalidValue;
     e = hipLaunchCooperativeKernel(fn, dim3(shape.grid), dim3(kCcdBlock), args, (unsigned)smem, stream);
     if (e != hipSuccess) return (int)e;

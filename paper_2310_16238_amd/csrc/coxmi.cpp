@@ -100,18 +100,39 @@ static int64_t aligned_positions(const std::vector<uint32_t> &meta, int64_t R, s
 
 // Rows per thread, workgroups and device row positions for the persistent
 // kernel: the fewest rows per thread whose workgroup count fits one per
-// compute unit, preferring the stratum-aligned layout.
+// compute unit, preferring a layout in which no stratum crosses a wave's rows
+// (then every wave's scan is its own, with no carry between waves), then one in
+// which no stratum that fits a workgroup tile crosses a tile boundary.
 static int choose_layout(const std::vector<uint32_t> &meta, int p, LaunchShape &shape,
                          std::vector<int64_t> &pos, std::string &err)
 {
     const int64_t n = (int64_t)meta.size();
     pos.assign(n, 0);
+    shape.wave = false;
+    int64_t longest = 0;   // the longest stratum
+    for (int64_t i = 0; i < n;) {
+        int64_t e = i + 1;
+        while (e < n && !(meta[e] & kHeadBit)) ++e;
+        longest = std::max(longest, e - i);
+        i = e;
+    }
     const int ipts[] = {1, 2, 4, 8, 16};
     for (int ipt : ipts) {
         int groups = 0;
         if (max_resident_groups(ipt, p, &groups, err) != 0) return COX_EDEVICE;
         if (groups < 1) continue;
-        const int64_t R = (int64_t)kThreads * ipt;
+        const int64_t R = (int64_t)kThreads * ipt, Rw = (int64_t)kWaveRows * ipt;
+        if (longest <= Rw) {
+            const int64_t lw = aligned_positions(meta, Rw, nullptr);
+            if ((lw + R - 1) / R <= groups) {
+                aligned_positions(meta, Rw, &pos);
+                shape.ipt = ipt;
+                shape.grid = (int)((lw + R - 1) / R);
+                shape.ld = (int64_t)shape.grid * R;
+                shape.wave = true;
+                return 0;
+            }
+        }
         const int64_t la = aligned_positions(meta, R, nullptr);
         if ((la + R - 1) / R <= groups) {
             aligned_positions(meta, R, &pos);
@@ -149,6 +170,7 @@ static void tile_layout(const std::vector<uint32_t> &meta, LaunchShape &shape, s
     }
     const int64_t rows = la <= n + n / 8 ? la : n;
     shape.ipt = 0;
+    shape.wave = false;
     shape.grid = (int)((rows + kNewtonTile - 1) / kNewtonTile);
     shape.ld = (int64_t)shape.grid * kNewtonTile;
 }
@@ -794,6 +816,7 @@ static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *bet
     L.p = (int)h->p;
     L.mode = mode;
     L.efron = h->opt.ties == COX_EFRON ? 1 : 0;
+    L.wave = h->shape.wave ? 1 : 0;
     L.j0 = j0;
     L.j1 = j1;
     L.max_sweeps = h->opt.max_iter;

@@ -15,6 +15,7 @@ constexpr uint32_t kPadBit = 0x20000000u;     // device layout only: a padding r
 constexpr uint32_t kCountMask = 0x1fffffffu;
 
 constexpr int kThreads = 512;           // threads per workgroup of the CCD kernel
+constexpr int kWaveRows = 64;           // threads per wave: a wave owns kWaveRows * ipt consecutive rows
 constexpr int kMaxGroups = 256;         // workgroups of one persistent launch (one per compute unit)
 constexpr int64_t kMaxCcdP = 12288;     // columns of the persistent kernel (beta in LDS: 96 KB)
 constexpr int64_t kMaxNewtonP = 4096;   // columns of the Newton / full-evaluation path
@@ -27,6 +28,7 @@ struct LaunchShape {
     int ipt = 0;
     int grid = 0;
     int64_t ld = 0;
+    bool wave = false;   // every stratum lies within one wave's rows (kWaveRows(ipt)): wave-local scans
 };
 
 // Workgroups that fit on the device at once for the persistent kernel with
@@ -47,6 +49,7 @@ struct CcdLaunch {
     int p = 0;
     int mode = kModeFit;
     int efron = 0;                   // 1: Efron's tie correction instead of the plain risk sets
+    int wave = 0;                    // 1: the layout is wave-aligned (LaunchShape::wave)
     int j0 = 0, j1 = 0;              // evaluation: columns [j0, j1)
     int max_sweeps = 0;
     double tol = 0.0;

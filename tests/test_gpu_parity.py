@@ -137,6 +137,39 @@ def test_tile_boundary_strata():
     np.testing.assert_allclose(h, fe.hess_diag, atol=tol, rtol=0)
 
 
+def test_wave_aligned_layout_edges():
+    """Strata of at most one wave's rows (64 at one row per thread): the layout pads them to
+    wave boundaries and every wave scans on its own.  Sizes include exactly 64, 63, 65-free
+    runs of 1-row strata and strata that would otherwise straddle a wave or tile boundary."""
+    rng = np.random.default_rng(17)
+    sizes = []
+    pattern = [64, 1, 63, 2, 64, 30, 50, 64, 1, 1, 1, 33, 64, 40, 24, 64]
+    while sum(sizes) < 20_000:
+        sizes.extend(pattern)
+    n = sum(sizes)
+    stratum = np.repeat(np.arange(len(sizes), dtype=np.int32), sizes)
+    perm = rng.permutation(n)
+    stratum = stratum[perm]
+    X = np.asfortranarray(rng.standard_normal((n, 4)))
+    time = np.floor(rng.exponential(1.0, n) * 50) / 50       # ties
+    event = (rng.random(n) < 0.6).astype(np.uint8)
+    beta = np.array([0.4, -0.3, 0.2, 0.1])
+    L = orc.canonical_layout(time, event, stratum)
+    Xc = orc.to_canonical(X, L)
+    fe = orc.full_eval(Xc, L, beta, want_info=False)
+    tol = 1e-11 * max(1.0, float(event.sum()))
+    _say(f"wave-aligned layout n={n} strata={len(sizes)}")
+    with coxmi.CoxModel(X, time, event, stratum) as m:
+        obj, g, h = m.evaluate(beta)
+        assert coxmi.cox_shape(m.h)[2] > n   # padded
+        b, info = m.fit()
+    assert abs(obj - fe.objective) <= 1e-11 * max(event.sum(), abs(fe.objective))
+    np.testing.assert_allclose(g, fe.grad, atol=tol, rtol=0)
+    np.testing.assert_allclose(h, fe.hess_diag, atol=tol, rtol=0)
+    ref = orc.fit_newton(X, time, event, stratum, tol=1e-14)
+    assert info["status"] == coxmi.COX_OK and _rel(b, ref.beta) <= 1e-10
+
+
 # ------------------------------------------------------------------ fits
 
 @pytest.mark.parametrize("K", [1, 10, 500, 5000])
