@@ -97,6 +97,88 @@ __global__ __launch_bounds__(kSyrkThreads) void syrk_f64_kernel(const double *u,
         for (int bb = 0; bb < 4; ++bb) out[(ty * 4 + a) * kTile + tx * 4 + bb] = acc[a][bb];
 }
 
+// FP64 on the matrix cores (v_mfma_f64_16x16x4_f64), for p <= 256: per K chunk of kF64KC
+// rows the workgroup stages every row of u once in LDS (FP64, as stored); its 8 waves own
+// the 16 x 16 blocks (bi <= bj) of the upper triangle in turn (block q to wave q mod 8) and
+// run them from LDS, the A operand multiplied by c_k as it is read.  An MFMA step takes
+// 4 K values: lane l supplies A[bi*16 + l%16][k + l/16] and B[bj*16 + l%16][k + l/16] and
+// holds D[l/16 + 4 r][l%16], r = 0..3, of its block (rows interleaved by 4).  The partials go to the 64 x 64
+// tile-pair layout of syrk_f64_kernel (blocks below the diagonal of a diagonal tile are
+// never written, and syrk_reduce_kernel never reads them).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kF64Waves = 8, kF64KC = 32, kF64MaxBlk = 16;   // 16 blocks of 16 rows: p <= 256
+constexpr int kF64PerWave = (kF64MaxBlk * (kF64MaxBlk + 1) / 2 + kF64Waves - 1) / kF64Waves;   // 17
+
+__global__ __launch_bounds__(64 * kF64Waves, 1) void syrk_f64_mfma_kernel(const double *u, int64_t ldu, int p,
+                                                                         const double *c, int64_t K,
+                                                                         int64_t kchunk, double *part)
+{
+    __shared__ double xs[kF64MaxBlk * 16][kF64KC + 1];
+    __shared__ double cs[kF64KC];
+    const int nb = (p + 15) / 16;
+    const int nblk = nb * (nb + 1) / 2;
+    const int nt = (p + kTile - 1) / kTile;
+    const int npairs = nt * (nt + 1) / 2;
+    const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
+    const int s = blockIdx.x;
+    const int64_t k0 = (int64_t)s * kchunk;
+    const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+    int bi[kF64PerWave], bj[kF64PerWave];
+    f64x4 acc[kF64PerWave];
+#pragma unroll
+    for (int m = 0; m < kF64PerWave; ++m) {
+        const int q = w + kF64Waves * m;
+        int i = 0, rem = q < nblk ? q : 0;
+        while (rem >= nb - i) {
+            rem -= nb - i;
+            ++i;
+        }
+        bi[m] = i;
+        bj[m] = i + rem;
+        acc[m] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+    const int rows = nb * 16;
+    const int r16 = lane & 15, kq = lane >> 4;
+    for (int64_t kc = k0; kc < k1; kc += kF64KC) {
+        // stage rows x kF64KC (zero beyond p and beyond k1)
+        for (int e = threadIdx.x; e < rows * kF64KC; e += 64 * kF64Waves) {
+            const int r = e / kF64KC, kk = e % kF64KC;
+            const int64_t kr = kc + kk;
+            xs[r][kk] = (r < p && kr < k1) ? u[(int64_t)r * ldu + kr] : 0.0;
+        }
+        if (threadIdx.x < kF64KC) cs[threadIdx.x] = (c && kc + threadIdx.x < k1) ? c[kc + threadIdx.x] : 1.0;
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kF64KC; ks += 4) {
+            const int kk = ks + kq;
+            const double ck = cs[kk];
+#pragma unroll
+            for (int m = 0; m < kF64PerWave; ++m) {
+                if (w + kF64Waves * m < nblk) {
+                    const double a = xs[bi[m] * 16 + r16][kk] * ck;
+                    const double b = xs[bj[m] * 16 + r16][kk];
+                    acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[m], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();   // the next chunk rewrites the staged rows
+    }
+#pragma unroll
+    for (int m = 0; m < kF64PerWave; ++m) {
+        if (w + kF64Waves * m < nblk) {
+            const int ti = bi[m] / 4, tj = bj[m] / 4;
+            const int pair = ti * nt - ti * (ti - 1) / 2 + (tj - ti);
+            double *out = part + ((int64_t)s * npairs + pair) * (kTile * kTile);
+            const int col = (bj[m] % 4) * 16 + r16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = (bi[m] % 4) * 16 + kq + 4 * r;
+                out[row * kTile + col] = acc[m][r];
+            }
+        }
+    }
+}
+
 // C (p x p, row-major, symmetric) = sign * sum over splits (in order) of the
 // partial tiles, added to C when accumulate != 0.
 __global__ __launch_bounds__(kSyrkThreads) void syrk_reduce_kernel(const double *part, int p, int S, double sign,
@@ -483,13 +565,16 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_kernel(const uint
 // holds 16 tiles x 32 rows x 72 BF16, twice with weights: 147 KB).
 constexpr int kLdsMaxTiles = 16;
 
-template <bool WEIGHT, int KC>
-__global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_lds_kernel(const uint16_t *u, int64_t ldu, int p,
-                                                                          const double *c, int64_t K, int64_t kchunk,
-                                                                          float *part)
+// MAXT: the most row tiles the launch may have (the LDS holds MAXT x 32 rows); OCC: the
+// workgroups per compute unit the register budget is cut for (two let one workgroup's
+// loads overlap the other's matrix-core work).
+template <bool WEIGHT, int KC, int MAXT = (KC == 128 ? 8 : 16), int OCC = 1>
+__global__ __launch_bounds__(64 * kSyrkBfWaves, OCC) void syrk_bf16_lds_kernel(const uint16_t *u, int64_t ldu, int p,
+                                                                               const double *c, int64_t K,
+                                                                               int64_t kchunk, float *part)
 {
     constexpr int kLdsKC = KC, kLdsStride = KC + 8, kLdsPieces = KC / 8;
-    constexpr int kLdsPerThread = (KC == 128 ? 8 : 16) * kMT * kLdsPieces / (64 * kSyrkBfWaves);   // 16
+    constexpr int kLdsPerThread = MAXT * kMT * kLdsPieces / (64 * kSyrkBfWaves);
     extern __shared__ uint16_t sh[];   // [nt*32][kLdsStride] plain, then weighted (WEIGHT)
     __shared__ float cw[kLdsKC];
     const int nt = (p + kMT - 1) / kMT;
@@ -1092,6 +1177,15 @@ int syrk_f64(const double *u, int64_t ldu, int p, const double *c, int64_t K, in
     const int nt = (p + kTile - 1) / kTile;
     const int npairs = nt * (nt + 1) / 2;
     int64_t kchunk = (K + splits - 1) / splits;
+    if (p <= kF64MaxBlk * 16) {
+        // matrix cores, every row of u staged once per K chunk; 2 * splits workgroups
+        const int s2 = 2 * splits;
+        kchunk = (K + s2 - 1) / s2;
+        kchunk = (kchunk + kF64KC - 1) / kF64KC * kF64KC;
+        syrk_f64_mfma_kernel<<<s2, 64 * kF64Waves, 0, stream>>>(u, ldu, p, c, K, kchunk, part);
+        syrk_reduce_kernel<<<npairs, kSyrkThreads, 0, stream>>>(part, p, s2, sign, accumulate, C);
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+    }
     kchunk = (kchunk + kKc - 1) / kKc * kKc;
     syrk_f64_kernel<<<dim3(npairs, splits), kSyrkThreads, 0, stream>>>(u, ldu, p, c, K, kchunk, part);
     syrk_reduce_kernel<<<npairs, kSyrkThreads, 0, stream>>>(part, p, splits, sign, accumulate, C);
@@ -1118,7 +1212,28 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
     const int nt = (p + kMT - 1) / kMT;
     const int KC = nt <= 8 ? 128 : 64;
     const int64_t K64 = (K + KC - 1) / KC * KC;
-    if (nt <= kLdsMaxTiles && K64 <= ldu && ldu % 8 == 0) {
+    if (nt <= 8 && (K + 63) / 64 * 64 <= ldu && ldu % 8 == 0) {
+        // two workgroups per compute unit, 64-row chunks (64.5 KB of LDS each with the weighted copy)
+        const int64_t KB = (K + 63) / 64 * 64;
+        const int s2 = 2 * splits;
+        int64_t kchunk = (KB + s2 - 1) / s2;
+        kchunk = (kchunk + 63) / 64 * 64;
+        const size_t lds = sizeof(uint16_t) * (size_t)nt * kMT * (64 + 8) * (c ? 2 : 1);
+        static bool attr2 = false;
+        if (!attr2) {
+            const size_t most = sizeof(uint16_t) * (size_t)8 * kMT * (64 + 8) * 2;
+            const void *fns[] = {reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<true, 64, 8, 2>),
+                                 reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<false, 64, 8, 2>)};
+            for (const void *fn : fns)
+                if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
+                    return -3;
+            attr2 = true;
+        }
+        splits = s2;   // the reduce below sums the slices this launch writes
+        const dim3 grid(s2, ngroups);
+        if (c) syrk_bf16_lds_kernel<true, 64, 8, 2><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
+        else syrk_bf16_lds_kernel<false, 64, 8, 2><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
+    } else if (nt <= kLdsMaxTiles && K64 <= ldu && ldu % 8 == 0) {
         int64_t kchunk = (K64 + splits - 1) / splits;
         kchunk = (kchunk + KC - 1) / KC * KC;
         const size_t lds = sizeof(uint16_t) * (size_t)nt * kMT * (KC + 8) * (c ? 2 : 1);

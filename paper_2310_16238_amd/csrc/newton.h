@@ -82,13 +82,17 @@ size_t syrk_partial_bytes(int p, int splits);
 size_t syrk_bf16_partial_bytes(int p, int splits);
 
 // K splits of the contractions: X' diag(b) X and Z'Z, FP64 and BF16.
-constexpr int kSplitsXF64 = 128, kSplitsZF64 = 64, kSplitsXBF16 = 256, kSplitsZBF16 = 256;
-// C (+)= sign * sum_k c_k u_k u_k' in FP64 (u: [p][ldu]; c NULL means 1).
+constexpr int kSplitsXF64 = 128, kSplitsZF64 = 128, kSplitsXBF16 = 256, kSplitsZBF16 = 256;
+// C (+)= sign * sum_k c_k u_k u_k' in FP64 (u: [p][ldu]; c NULL means 1).  `part` must hold
+// syrk_partial_bytes(p, 2 * splits) for p <= 256, where the matrix cores take 2 * splits K slices
+// (syrk_partial_bytes(p, splits) beyond).
 int syrk_f64(const double *u, int64_t ldu, int p, const double *c, int64_t K, int splits, double *part,
              double sign, int accumulate, double *C, hipStream_t stream);
 // BF16 copy of X with power-of-two column scales (zscale receives the same scales).
 int make_bf16_copy(const double *x, int64_t ld, int p, void *xlp, float *xscale, float *zscale, hipStream_t stream);
 // C (+)= sign * scale_i scale_j sum_k c_k u_ik u_jk with BF16 u on the matrix cores (FP32 accumulate).
+// `part` must hold syrk_bf16_partial_bytes(p, 2 * splits): up to 256 columns the K range is cut
+// into 2 * splits slices (two workgroups per compute unit).
 int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const double *c, int64_t K, int splits,
               double *part, double sign, int accumulate, double *C, hipStream_t stream);
 // Bytes of the blocked e4m3 copy of an ld x p matrix (make_fp8_copy, syrk_fp8).

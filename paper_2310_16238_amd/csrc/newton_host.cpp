@@ -106,9 +106,10 @@ int newton_setup(cox_handle *h)
         if (tile_carry[t + 1]) agg_tiles.push_back(t);
     s.n_agg = (int)agg_tiles.size();
     s.syrk_part_bytes = lowp(h->opt.x_precision)
-                            ? std::max({syrk_bf16_partial_bytes(p, kSplitsXBF16), syrk_bf16_partial_bytes(p, kSplitsXFP8),
-                                        syrk_bf16_partial_bytes(p, kSplitsZBF16)})
-                            : std::max(syrk_partial_bytes(p, kSplitsXF64), syrk_partial_bytes(p, kSplitsZF64));
+                            ? std::max({syrk_bf16_partial_bytes(p, 2 * kSplitsXBF16), syrk_bf16_partial_bytes(p, kSplitsXFP8),
+                                        syrk_bf16_partial_bytes(p, 2 * kSplitsZBF16)})
+                            : std::max(syrk_partial_bytes(p, (p <= 256 ? 2 : 1) * kSplitsXF64),
+                                       syrk_partial_bytes(p, (p <= 256 ? 2 : 1) * kSplitsZF64));
     s.scan_scratch_bytes = rowscan_scratch_bytes(s.ntiles);
     const size_t zb = ztype_bytes(h->opt.x_precision);
     hipError_t e;

@@ -567,7 +567,6 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     extern __shared__ double lds[];   // A[p * p], y[p]
     __shared__ int s_action, s_bad, s_frozen;
     __shared__ uint8_t s_free[kMaxP];
-    __shared__ __align__(16) double s_col[2][kMaxP];   // Cholesky column buffers
     __shared__ double s_red[kStepThreads / kWave];
     const FitDesc F = fits[slots[blockIdx.x]];
     FitState *st = F.st;
@@ -640,94 +639,106 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     for (int j = t; j < p; j += kStepThreads) s_free[j] = F.free_col[j];
     __syncthreads();
     if (!frozen) {
-        // Right-looking Cholesky of the information matrix (info kernel; rows and
-        // columns not free become unit rows) with the matrix in registers: thread
-        // (ty, tx) holds the entries (i, j) with i = ty, j = tx (mod 16).  Per column
-        // k, the 16 threads holding column k publish it in LDS -- zero outside rows
-        // k..p-1, entry i at (i mod 16) * 8 + i / 16 so that a thread's 8 rows (or
-        // columns) are contiguous; two alternating buffers -- and after one barrier
-        // every thread scales what it needs by 1/pivot and updates all its entries
-        // (zeros leave the finished columns as they are; entries above the diagonal
-        // are never read).  The holders then set column k of the factor.
-        constexpr int kOwn = kMaxP / 16;
-        const int ty = t >> 4, tx = t & 15;
-        double R[kOwn][kOwn];
-#pragma unroll
-        for (int a = 0; a < kOwn; ++a)
-#pragma unroll
-            for (int b = 0; b < kOwn; ++b) {
-                const int i = ty + 16 * a, j = tx + 16 * b;
-                double v = 0.0;
-                if (i < p && j <= i) {
-                    v = F.L[(int64_t)i * p + j];
-                    if (!s_free[i] || !s_free[j]) v = (i == j) ? 1.0 : 0.0;
-                }
-                R[a][b] = v;
+        // Blocked right-looking Cholesky of the information matrix (info kernel; rows and
+        // columns not free become unit rows) in LDS, lower triangle, panels of 16 columns:
+        // wave 0 factors the diagonal block (lane r holds its row r, columns passed by
+        // shuffles), every thread solves rows below it against that block, and the threads
+        // update the trailing triangle in 4 x 4 tiles -- three barriers per panel.
+        constexpr int NB = 16;
+        for (int i = wv; i < p; i += kWaves)
+            for (int j = lane; j <= i; j += kWave) {
+                double v = F.L[(int64_t)i * p + j];
+                if (!s_free[i] || !s_free[j]) v = (i == j) ? 1.0 : 0.0;
+                A[i * p + j] = v;
             }
-        for (int k = 0; k < p; ++k) {
-            double *buf = s_col[k & 1];
-            const int bk = k >> 4;
-            if (tx == (k & 15)) {
-                double v[kOwn];
+        __syncthreads();
+        for (int k0 = 0; k0 < p; k0 += NB) {
+            const int kb = p - k0 < NB ? p - k0 : NB;
+            if (wv == 0) {
+                double r[NB];
 #pragma unroll
-                for (int b = 0; b < kOwn; ++b)
-                    if (b == bk) {
+                for (int c = 0; c < NB; ++c) r[c] = (lane < kb && c <= lane) ? A[(k0 + lane) * p + k0 + c] : 0.0;
 #pragma unroll
-                        for (int a = 0; a < kOwn; ++a) {
-                            const int i = ty + 16 * a;
-                            v[a] = (i >= k && i < p) ? R[a][b] : 0.0;
+                for (int c = 0; c < NB; ++c) {
+                    if (c < kb) {
+                        double d = __shfl(r[c], c, kWave);
+                        const bool ok = d > 0.0;
+                        if (!ok) {
+                            d = 1.0;
+                            if (lane == 0) s_bad = 1;
+                        }
+                        const double piv = sqrt(d), inv = 1.0 / piv;
+                        r[c] = lane == c ? piv : (lane > c ? r[c] * inv : r[c]);
+                        const double lc = r[c];   // L[k0 + lane][k0 + c] below the pivot
+#pragma unroll
+                        for (int cc = c + 1; cc < NB; ++cc) {
+                            const double lcc = __shfl(lc, cc, kWave);   // L[k0 + cc][k0 + c]
+                            if (cc < kb && lane >= cc) r[cc] = fma(-lc, lcc, r[cc]);
                         }
                     }
-                double2 *dst = reinterpret_cast<double2 *>(buf + ty * kOwn);
+                }
 #pragma unroll
-                for (int a = 0; a < kOwn; a += 2) dst[a / 2] = make_double2(v[a], v[a + 1]);
+                for (int c = 0; c < NB; ++c)
+                    if (lane < kb && c <= lane) A[(k0 + lane) * p + k0 + c] = r[c];
             }
             __syncthreads();
-            double d = buf[(k & 15) * kOwn + bk];
-            const bool ok = d > 0.0;
-            if (!ok) d = 1.0;
-            const double piv = sqrt(d), inv = 1.0 / piv;
-            if (t == 0 && !ok) s_bad = 1;
-            double li[kOwn], lj[kOwn];
-            const double2 *ri = reinterpret_cast<const double2 *>(buf + ty * kOwn);
-            const double2 *rj = reinterpret_cast<const double2 *>(buf + tx * kOwn);
+            // rows below the block: x L_kk' = A[i][k0 .. k0 + kb)
+            for (int i = k0 + kb + t; i < p; i += kStepThreads) {
+                double x[NB];
 #pragma unroll
-            for (int a = 0; a < kOwn; a += 2) {
-                const double2 u = ri[a / 2], w = rj[a / 2];
-                li[a] = u.x * inv;
-                li[a + 1] = u.y * inv;
-                lj[a] = w.x * inv;
-                lj[a + 1] = w.y * inv;
+                for (int c = 0; c < NB; ++c) x[c] = c < kb ? A[i * p + k0 + c] : 0.0;
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    if (c < kb) {
+                        double v = x[c];
+#pragma unroll
+                        for (int cc = 0; cc < c; ++cc) v = fma(-x[cc], A[(k0 + c) * p + k0 + cc], v);
+                        x[c] = v / A[(k0 + c) * p + k0 + c];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    if (c < kb) A[i * p + k0 + c] = x[c];
             }
-            // row k and column k take part too (their products land above the
-            // diagonal or in column k, which is set below); finished columns see zeros
+            __syncthreads();
+            // trailing triangle rows/columns m0 .. p-1, 4 x 4 tiles (ti >= tj)
+            const int m0 = k0 + kb, mt = (p - m0 + 3) / 4;
+            const int ntile = mt * (mt + 1) / 2;
+            for (int q = t; q < ntile; q += kStepThreads) {
+                int ti = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+                while (ti * (ti + 1) / 2 > q) --ti;
+                while ((ti + 1) * (ti + 2) / 2 <= q) ++ti;
+                const int tj = q - ti * (ti + 1) / 2;
+                const int i0 = m0 + 4 * ti, j0 = m0 + 4 * tj;
+                double acc[4][4];
 #pragma unroll
-            for (int a = 0; a < kOwn; ++a)
+                for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int b = 0; b < kOwn; ++b) R[a][b] = fma(-li[a], lj[b], R[a][b]);
-            if (tx == (k & 15)) {
+                    for (int s2 = 0; s2 < 4; ++s2) acc[r][s2] = 0.0;
+                for (int c = 0; c < kb; ++c) {
+                    double av[4], bv[4];
 #pragma unroll
-                for (int b = 0; b < kOwn; ++b)
-                    if (b == bk) {
+                    for (int r = 0; r < 4; ++r) {
+                        av[r] = i0 + r < p ? A[(i0 + r) * p + k0 + c] : 0.0;
+                        bv[r] = j0 + r < p ? A[(j0 + r) * p + k0 + c] : 0.0;
+                    }
 #pragma unroll
-                        for (int a = 0; a < kOwn; ++a) {
-                            const int i = ty + 16 * a;
-                            if (i == k) R[a][b] = piv;
-                            else if (i > k) R[a][b] = li[a];
-                        }
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int s2 = 0; s2 < 4; ++s2) acc[r][s2] = fma(av[r], bv[s2], acc[r][s2]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int s2 = 0; s2 < 4; ++s2) {
+                        const int i = i0 + r, j = j0 + s2;
+                        if (i < p && j <= i) A[i * p + j] -= acc[r][s2];
                     }
             }
+            __syncthreads();
         }
-#pragma unroll
-        for (int a = 0; a < kOwn; ++a)
-#pragma unroll
-            for (int b = 0; b < kOwn; ++b) {
-                const int i = ty + 16 * a, j = tx + 16 * b;
-                if (i < p && j <= i) {
-                    A[i * p + j] = R[a][b];
-                    F.L[(int64_t)i * p + j] = R[a][b];
-                }
-            }
+        for (int i = wv; i < p; i += kWaves)
+            for (int j = lane; j <= i; j += kWave) F.L[(int64_t)i * p + j] = A[i * p + j];
         __syncthreads();
     } else {
         for (int i = wv; i < p; i += kWaves)
