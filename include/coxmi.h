@@ -334,8 +334,9 @@ int cox_set_penalty(cox_handle *h, double gamma, const uint8_t *penalize);
  *             COX_CCD, or COX_NEWTON_REFINE for proximal Newton fits --, tol, max_iter,
  *             precision and stream of the fold fits)
  *   fold    : host, n entries in [0, nfolds); every fold non-empty and not all rows.  On
- *             an interval-stratified handle (cox_init_intervals, cox_split_intervals) give
- *             all rows of one subject the same fold, so that a subject is held out whole
+ *             a handle from cox_init_intervals all rows of one subject must share a fold
+ *             (a subject is held out whole; else COX_EINVAL); on rows split by
+ *             cox_split_intervals and passed to cox_init, the caller keeps subjects whole
  *   gammas  : host, ngamma finite values >= 0 (a decreasing path warm-starts best)
  *   penalize: host, p flags or NULL (all columns penalised)
  *   cvl     : host, ngamma outputs; betas: host [nfolds][ngamma][p] or NULL;

@@ -772,6 +772,7 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
         delete h;
         return hip_fail(nullptr, e, "building the interval-stratified data set");
     }
+    h->subject = std::move(rows.row_subject);
     *out = h;
     return COX_OK;
 }
@@ -918,6 +919,17 @@ extern "C" int cox_cross_validate(cox_handle *h, int nfolds, const int32_t *fold
     }
     for (int k = 0; k < nfolds; ++k)
         if (size[(size_t)k] == 0 || size[(size_t)k] == h->n) return fail(h, COX_EINVAL, "every fold must hold some rows, and not all");
+    if (!h->subject.empty()) {
+        // interval-stratified rows: a subject's rows are held out together
+        int64_t ns = 0;
+        for (int64_t s : h->subject) ns = std::max(ns, s + 1);
+        std::vector<int32_t> of((size_t)ns, -1);
+        for (int64_t i = 0; i < h->n; ++i) {
+            int32_t &f = of[(size_t)h->subject[(size_t)i]];
+            if (f < 0) f = fold[i];
+            else if (f != fold[i]) return fail(h, COX_EINVAL, "rows of one subject fall in different folds");
+        }
+    }
     const int64_t p = h->p;
     std::fill(cvl, cvl + ngamma, 0.0);
     bool all_converged = true;

@@ -76,6 +76,7 @@ struct cox_handle {
     std::vector<uint32_t> meta;    // canonical row words
     std::vector<int64_t> pos;      // canonical row -> row of the device layout
     std::vector<double> gamma;
+    std::vector<int64_t> subject;  // cox_init_intervals: subject (row of the parent) of each row; else empty
     cox_options opt{};
     std::string err;
     NewtonState nt;

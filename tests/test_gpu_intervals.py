@@ -159,5 +159,21 @@ def test_device_mapping_errors():
         # relabelled strata in the same order are the same strata
         with m.intervals(d.time, d.event, (d.stratum * 5 + 2).astype(np.int32), [0.5]) as c:
             assert coxmi.cox_shape(c.h)[0] >= d.n
+        # cross-validation folds on interval rows: a subject split across folds is refused,
+        # per-subject folds are accepted
+        cuts = [float(np.quantile(d.time, 0.5))]
+        r = orc.split_intervals(d.X, d.time, d.event, d.stratum, cuts)
+        fold_subj = np.arange(d.n, dtype=np.int32) % 3
+        with m.intervals(d.time, d.event, d.stratum, cuts, tol=1e-10) as c:
+            naug = coxmi.cox_shape(c.h)[0]
+            assert naug == r["X"].shape[0] > d.n
+            split = fold_subj[r["row_subject"]].copy()
+            a = int(np.flatnonzero(r["row_interval"] == 1)[0])
+            split[a] = (split[a] + 1) % 3
+            with pytest.raises(coxmi.CoxError) as e:
+                c.cross_validate(split, [0.0], nfolds=3)
+            assert e.value.code == coxmi.COX_EINVAL
+            cvl, _, status = c.cross_validate(fold_subj[r["row_subject"]], [0.0], nfolds=3)
+            assert np.isfinite(cvl[0]) and np.all(status == coxmi.COX_OK)
         with pytest.raises(ValueError):
             m.intervals(d.time, d.event, d.stratum, [0.5], tv_coef=np.ones(2, np.uint8))
