@@ -40,6 +40,26 @@ __device__ __forceinline__ void tile_pair(int pair, int nt, int &ti, int &tj)
     tj = i + rem;
 }
 
+// (K range, group) of a workgroup of a (splits, groups) grid.  Workgroups go to the 8 XCDs in
+// turn by linear id; when splits is a multiple of 8 the ids are renumbered so that every group
+// of one K range runs on one XCD at nearly the same time, and the rows of the range that each
+// of them stages are read from HBM once and from that XCD's L2 after.  Only the assignment of
+// work to workgroups changes, not the work.
+__device__ __forceinline__ void split_group(int &split, int &group)
+{
+    const int nsplit = gridDim.x, ngroup = gridDim.y;
+    if (ngroup == 1 || nsplit % 8 != 0) {
+        split = blockIdx.x;
+        group = blockIdx.y;
+        return;
+    }
+    const int L = blockIdx.x + nsplit * blockIdx.y;
+    const int x = L % 8, r = L / 8;
+    split = x + 8 * (r / ngroup);
+    group = r % ngroup;
+}
+
+
 __global__ __launch_bounds__(kSyrkThreads) void syrk_f64_kernel(const double *u, int64_t ldu, int p,
                                                                 const double *c, int64_t K, int64_t kchunk,
                                                                 double *part)
@@ -179,31 +199,42 @@ __global__ __launch_bounds__(64 * kF64Waves, 1) void syrk_f64_mfma_kernel(const 
     }
 }
 
-// C (p x p, row-major, symmetric) = sign * sum over splits (in order) of the
-// partial tiles, added to C when accumulate != 0.
-__global__ __launch_bounds__(kSyrkThreads) void syrk_reduce_kernel(const double *part, int p, int S, double sign,
-                                                                   int accumulate, double *C)
+// C (p x p, row-major, symmetric) = sign * sum over splits of the partial tiles, added to C
+// when accumulate != 0.  Grid (npairs, 64): a workgroup takes 64 entries of one 64 x 64 tile;
+// its 16 waves sum the splits q = w, w + 16, ... in order and the 16 sums are added in wave
+// order (a fixed order: results do not vary run to run).  Entries below the diagonal of a
+// diagonal tile are neither read nor written.
+constexpr int kRedWaves = 16;
+
+__global__ __launch_bounds__(64 * kRedWaves) void syrk_reduce_kernel(const double *part, int p, int S, double sign,
+                                                                     int accumulate, double *C)
 {
+    __shared__ double red[kRedWaves][64];
     const int nt = (p + kTile - 1) / kTile;
     const int npairs = nt * (nt + 1) / 2;
     const int pair = blockIdx.x;
     int ti, tj;
     tile_pair(pair, nt, ti, tj);
-    for (int e = threadIdx.x; e < kTile * kTile; e += kSyrkThreads) {
-        const int a = e / kTile, bb = e % kTile;
-        const int i = ti * kTile + a, j = tj * kTile + bb;
-        if (i >= p || j >= p) continue;
-        if (ti == tj && j < i) continue;     // the diagonal tile: upper half only
-        double s = 0.0;
-        for (int q = 0; q < S; ++q) s += part[((int64_t)q * npairs + pair) * (kTile * kTile) + e];
-        s *= sign;
-        if (accumulate) {
-            C[(int64_t)i * p + j] += s;
-            if (i != j) C[(int64_t)j * p + i] += s;
-        } else {
-            C[(int64_t)i * p + j] = s;
-            if (i != j) C[(int64_t)j * p + i] = s;
-        }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = blockIdx.y * 64 + lane;
+    const int a = e / kTile, bb = e % kTile;
+    const int i = ti * kTile + a, j = tj * kTile + bb;
+    const bool live = i < p && j < p && !(ti == tj && j < i);
+    double s = 0.0;
+    if (live)
+        for (int q = w; q < S; q += kRedWaves) s += part[((int64_t)q * npairs + pair) * (kTile * kTile) + e];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w != 0 || !live) return;
+    s = red[0][lane];
+    for (int v = 1; v < kRedWaves; ++v) s += red[v][lane];
+    s *= sign;
+    if (accumulate) {
+        C[(int64_t)i * p + j] += s;
+        if (i != j) C[(int64_t)j * p + i] += s;
+    } else {
+        C[(int64_t)i * p + j] = s;
+        if (i != j) C[(int64_t)j * p + i] = s;
     }
 }
 
@@ -517,8 +548,9 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_kernel(const uint
     const int nt = (p + kMT - 1) / kMT;
     const int npairs = nt * (nt + 1) / 2;
     const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
-    const int s = blockIdx.x;
-    const int pair0 = blockIdx.y * kPairsPerGroup + w * kTilesPerWave;
+    int s, grp;
+    split_group(s, grp);
+    const int pair0 = grp * kPairsPerGroup + w * kTilesPerWave;
     const int64_t k0 = (int64_t)s * kchunk;
     const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
     int ti[kTilesPerWave], tj[kTilesPerWave];
@@ -565,16 +597,19 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_kernel(const uint
 // holds 16 tiles x 32 rows x 72 BF16, twice with weights: 147 KB).
 constexpr int kLdsMaxTiles = 16;
 
-// MAXT: the most row tiles the launch may have (the LDS holds MAXT x 32 rows); OCC: the
-// workgroups per compute unit the register budget is cut for (two let one workgroup's
-// loads overlap the other's matrix-core work).
-template <bool WEIGHT, int KC, int MAXT = (KC == 128 ? 8 : 16), int OCC = 1>
-__global__ __launch_bounds__(64 * kSyrkBfWaves, OCC) void syrk_bf16_lds_kernel(const uint16_t *u, int64_t ldu, int p,
+// MAXT: the most row tiles the launch may have (the LDS holds MAXT x 32 rows); OCC: the waves
+// per SIMD the register budget is cut for (with NWV waves of TPW tile pairs each: two
+// workgroups of 8 waves per compute unit need 4, so one workgroup's loads overlap the
+// other's matrix-core work).
+template <bool WEIGHT, int KC, int MAXT = (KC == 128 ? 8 : 16), int OCC = 1, int NWV = kSyrkBfWaves,
+          int TPW = kTilesPerWave>
+__global__ __launch_bounds__(64 * NWV, OCC) void syrk_bf16_lds_kernel(const uint16_t *u, int64_t ldu, int p,
                                                                                const double *c, int64_t K,
                                                                                int64_t kchunk, float *part)
 {
     constexpr int kLdsKC = KC, kLdsStride = KC + 8, kLdsPieces = KC / 8;
-    constexpr int kLdsPerThread = MAXT * kMT * kLdsPieces / (64 * kSyrkBfWaves);
+    static_assert(NWV * TPW == kPairsPerGroup, "a group holds kPairsPerGroup tile pairs");
+    constexpr int kLdsPerThread = (MAXT * kMT * kLdsPieces + 64 * NWV - 1) / (64 * NWV);
     extern __shared__ uint16_t sh[];   // [nt*32][kLdsStride] plain, then weighted (WEIGHT)
     __shared__ float cw[kLdsKC];
     const int nt = (p + kMT - 1) / kMT;
@@ -583,28 +618,33 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, OCC) void syrk_bf16_lds_kernel(c
     uint16_t *wtd = sh + (size_t)rows * kLdsStride;
     const int npairs = nt * (nt + 1) / 2;
     const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
-    const int s = blockIdx.x;
-    const int pair0 = blockIdx.y * kPairsPerGroup + w * kTilesPerWave;
-    const int nq = npairs - pair0 < kTilesPerWave ? (npairs - pair0 > 0 ? npairs - pair0 : 0) : kTilesPerWave;
+    int s, grp;
+    split_group(s, grp);
+    const int pair0 = grp * kPairsPerGroup + w * TPW;
+    const int nq = npairs - pair0 < TPW ? (npairs - pair0 > 0 ? npairs - pair0 : 0) : TPW;
     const int64_t k0 = (int64_t)s * kchunk;
     const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
-    int ti[kTilesPerWave], tj[kTilesPerWave];
-    f32x16 acc[kTilesPerWave];
+    const int rsub = lane & 31, ksub = 8 * (lane >> 5);
+    // LDS offsets of this lane's A (weighted) and B (plain) rows for each tile pair, packed
+    // 16 bits each (at most 16 x 32 rows of kLdsStride elements: < 2^16)
+    uint32_t offs[TPW];
+    f32x16 acc[TPW];
 #pragma unroll
-    for (int q = 0; q < kTilesPerWave; ++q) {
-        tile_pair(pair0 + q < npairs ? pair0 + q : 0, nt, ti[q], tj[q]);
+    for (int q = 0; q < TPW; ++q) {
+        int ti, tj;
+        tile_pair(pair0 + q < npairs ? pair0 + q : 0, nt, ti, tj);
+        offs[q] = (uint32_t)((ti * kMT + rsub) * kLdsStride) | ((uint32_t)((tj * kMT + rsub) * kLdsStride) << 16);
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[q][i] = 0.0f;
     }
-    const int rsub = lane & 31, ksub = 8 * (lane >> 5);
     const int npieces = rows * kLdsPieces;
-    // prefetch registers: this thread's pieces e = tid + 256 m
+    // prefetch registers: this thread's pieces e = tid + 256 m, one chunk ahead
     u32x4v reg[kLdsPerThread];
     float creg = 0.0f;
     auto load_chunk = [&](int64_t kc) {
 #pragma unroll
         for (int m = 0; m < kLdsPerThread; ++m) {
-            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            const int e = threadIdx.x + 64 * NWV * m;
             const int r = e / kLdsPieces, piece = e % kLdsPieces;
             u32x4v v = {0u, 0u, 0u, 0u};
             if (e < npieces && r < p) v = *reinterpret_cast<const u32x4v *>(u + (int64_t)r * ldu + kc + 8 * piece);
@@ -618,7 +658,7 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, OCC) void syrk_bf16_lds_kernel(c
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < kLdsPerThread; ++m) {
-            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            const int e = threadIdx.x + 64 * NWV * m;
             if (e < npieces) {
                 const int r = e / kLdsPieces, piece = e % kLdsPieces;
                 *reinterpret_cast<u32x4v *>(plain + r * kLdsStride + 8 * piece) = reg[m];
@@ -637,13 +677,17 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, OCC) void syrk_bf16_lds_kernel(c
 #pragma unroll
         for (int sub = 0; sub < kLdsKC / 16; ++sub) {
             const int kk = 16 * sub + ksub;
+            // a wave's pairs run along rows of the upper triangle: the A fragment (row tile ti)
+            // is read from LDS only when ti changes
+            bf16x8 a;
 #pragma unroll
-            for (int q = 0; q < kTilesPerWave; ++q) {
+            for (int q = 0; q < TPW; ++q) {
                 if (q < nq) {
-                    const bf16x8 a = __builtin_bit_cast(
-                        bf16x8, *reinterpret_cast<const u32x4v *>(asrc + (ti[q] * kMT + rsub) * kLdsStride + kk));
+                    if (q == 0 || (offs[q] & 0xffffu) != (offs[q - 1] & 0xffffu))
+                        a = __builtin_bit_cast(bf16x8,
+                                               *reinterpret_cast<const u32x4v *>(asrc + (offs[q] & 0xffffu) + kk));
                     const bf16x8 b = __builtin_bit_cast(
-                        bf16x8, *reinterpret_cast<const u32x4v *>(plain + (tj[q] * kMT + rsub) * kLdsStride + kk));
+                        bf16x8, *reinterpret_cast<const u32x4v *>(plain + (offs[q] >> 16) + kk));
                     acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[q], 0, 0, 0);
                 }
             }
@@ -651,7 +695,7 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, OCC) void syrk_bf16_lds_kernel(c
         __syncthreads();   // the next chunk rewrites the LDS tiles
     }
 #pragma unroll
-    for (int q = 0; q < kTilesPerWave; ++q) {
+    for (int q = 0; q < TPW; ++q) {
         if (q < nq) {
             float *out = part + ((int64_t)s * npairs + pair0 + q) * (kMT * kMT);
 #pragma unroll
@@ -692,11 +736,12 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_bf16_blk_kernel(const 
     const int nb = (nt + kBlkTiles - 1) / kBlkTiles;
     const int npairs = nt * (nt + 1) / 2;
     int I, J;
-    tile_pair(blockIdx.y, nb, I, J);
+    int s, grp;
+    split_group(s, grp);
+    tile_pair(grp, nb, I, J);
     const bool diag = I == J;
     const int nst = diag ? kBlkTiles : 2 * kBlkTiles;     // staged tiles
     const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
-    const int s = blockIdx.x;
     const int64_t k0 = (int64_t)s * kchunk;
     const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
     // this wave's pairs: local tiles (la, lb) of the staged rows, global pair index, valid flag
@@ -862,7 +907,10 @@ __global__ __launch_bounds__(256) void wscale_kernel(const double *blockmax, int
 
 // Two waves per SIMD (registers capped at 256, accumulators included): the
 // products of one chunk overlap the other wave's staging.
-__global__ __launch_bounds__(64 * kSyrkBfWaves, 2) void syrk_fp8_lds_kernel(const uint8_t *u, int p,
+// MAXR: the most staged rows (p rounded up to 32) the launch may have; it sizes the prefetch
+// registers.  NWV waves of TPW tile pairs each, registers cut for two workgroups per compute unit.
+template <int MAXR, int NWV = kSyrkBfWaves, int TPW = kTilesPerWave>
+__global__ __launch_bounds__(64 * NWV, NWV / 2) void syrk_fp8_lds_kernel(const uint8_t *u, int p,
                                                                         const double *c, const double *wsc,
                                                                         int64_t K, int64_t kchunk, float *part)
 {
@@ -872,24 +920,31 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, 2) void syrk_fp8_lds_kernel(cons
     const int rows = nt * kMT;
     const int npairs = nt * (nt + 1) / 2;
     const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
-    const int s = blockIdx.x;
-    const int pair0 = blockIdx.y * kPairsPerGroup + w * kTilesPerWave;
-    const int nq = npairs - pair0 < kTilesPerWave ? (npairs - pair0 > 0 ? npairs - pair0 : 0) : kTilesPerWave;
+    int s, grp;
+    split_group(s, grp);
+    const int pair0 = grp * kPairsPerGroup + w * TPW;
+    const int nq = npairs - pair0 < TPW ? (npairs - pair0 > 0 ? npairs - pair0 : 0) : TPW;
     const int64_t k0 = (int64_t)s * kchunk;
     const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
     const double invS = 1.0 / wsc[0];
-    int ti[kTilesPerWave], tj[kTilesPerWave];
-    f32x16 acc[kTilesPerWave];
+    const int rsub = lane & 31, kofs = 32 * (lane >> 5);
+    // LDS byte offsets of this lane's A and B rows for each tile pair, packed 16 bits each
+    // (at most kF8MaxRows rows of kF8Stride bytes: < 2^16)
+    uint32_t offs[TPW];
+    f32x16 acc[TPW];
 #pragma unroll
-    for (int q = 0; q < kTilesPerWave; ++q) {
-        tile_pair(pair0 + q < npairs ? pair0 + q : 0, nt, ti[q], tj[q]);
+    for (int q = 0; q < TPW; ++q) {
+        int ti, tj;
+        tile_pair(pair0 + q < npairs ? pair0 + q : 0, nt, ti, tj);
+        offs[q] = (uint32_t)((ti * kMT + rsub) * kF8Stride + kofs) |
+                  ((uint32_t)((tj * kMT + rsub) * kF8Stride + kofs) << 16);
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[q][i] = 0.0f;
     }
-    const int rsub = lane & 31, kofs = 32 * (lane >> 5);
     // the chunk is one contiguous block of rows x 64 bytes (padding rows are zero), read
     // as 16-byte pieces e = tid + 256 m into registers one chunk ahead
-    constexpr int kPieces = (kF8MaxRows * 4 + 64 * kSyrkBfWaves - 1) / (64 * kSyrkBfWaves);
+    static_assert(NWV * TPW == kPairsPerGroup, "a group holds kPairsPerGroup tile pairs");
+    constexpr int kPieces = (MAXR * 4 + 64 * NWV - 1) / (64 * NWV);
     const int npieces = rows * 4;
     u32x4v reg[kPieces];
     double creg = 0.0;
@@ -897,7 +952,7 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, 2) void syrk_fp8_lds_kernel(cons
         const u32x4v *blk = reinterpret_cast<const u32x4v *>(u + (kc / kF8KC) * (int64_t)rows * kF8KC);
 #pragma unroll
         for (int m = 0; m < kPieces; ++m) {
-            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            const int e = threadIdx.x + 64 * NWV * m;
             u32x4v v = {0u, 0u, 0u, 0u};
             if (e < npieces) v = blk[e];
             reg[m] = v;
@@ -911,12 +966,10 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, 2) void syrk_fp8_lds_kernel(cons
         // decode, weight, re-encode into LDS; every piece of this thread covers the same
         // 16 rows of the chunk (piece = tid mod 4), so it needs 16 weights
         const int piece = threadIdx.x & 3;
-        float wk[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) wk[i] = cw[16 * piece + i];
+        const float *wk = cw + 16 * piece;
 #pragma unroll
         for (int m = 0; m < kPieces; ++m) {
-            const int e = threadIdx.x + 64 * kSyrkBfWaves * m;
+            const int e = threadIdx.x + 64 * NWV * m;
             if (e < npieces) {
                 const u32x4v raw = reg[m];
                 u32x4v v;
@@ -935,15 +988,21 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, 2) void syrk_fp8_lds_kernel(cons
         }
         __syncthreads();
         if (kc + kF8KC < k1) load_chunk(kc + kF8KC);   // in flight during the products below
+        // a wave's pairs run along rows of the upper triangle: the A fragment (row tile ti) is
+        // read from LDS only when ti changes
+        i32x8v av;
 #pragma unroll
-        for (int q = 0; q < kTilesPerWave; ++q) {
+        for (int q = 0; q < TPW; ++q) {
             if (q < nq) {
-                const uint8_t *pa = sh8 + (ti[q] * kMT + rsub) * kF8Stride + kofs;
-                const uint8_t *pb = sh8 + (tj[q] * kMT + rsub) * kF8Stride + kofs;
-                const u32x4v a0 = *reinterpret_cast<const u32x4v *>(pa), a1 = *reinterpret_cast<const u32x4v *>(pa + 16);
+                if (q == 0 || (offs[q] & 0xffffu) != (offs[q - 1] & 0xffffu)) {
+                    const uint8_t *pa = sh8 + (offs[q] & 0xffffu);
+                    const u32x4v a0 = *reinterpret_cast<const u32x4v *>(pa);
+                    const u32x4v a1 = *reinterpret_cast<const u32x4v *>(pa + 16);
+                    av = i32x8v{(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3],
+                                (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+                }
+                const uint8_t *pb = sh8 + (offs[q] >> 16);
                 const u32x4v b0 = *reinterpret_cast<const u32x4v *>(pb), b1 = *reinterpret_cast<const u32x4v *>(pb + 16);
-                const i32x8v av = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3],
-                                   (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
                 const i32x8v bv = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3],
                                    (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
                 acc[q] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, acc[q], 0, 0, 0, 127, 0, 127);
@@ -952,7 +1011,7 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves, 2) void syrk_fp8_lds_kernel(cons
         __syncthreads();   // the next chunk rewrites the LDS tiles
     }
 #pragma unroll
-    for (int q = 0; q < kTilesPerWave; ++q) {
+    for (int q = 0; q < TPW; ++q) {
         if (q < nq) {
             float *out = part + ((int64_t)s * npairs + pair0 + q) * (kMT * kMT);
 #pragma unroll
@@ -980,11 +1039,12 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_fp8_blk_kernel(const u
     const int nb = (nt + kBlkTiles - 1) / kBlkTiles;
     const int npairs = nt * (nt + 1) / 2;
     int I, J;
-    tile_pair(blockIdx.y, nb, I, J);
+    int s, grp;
+    split_group(s, grp);
+    tile_pair(grp, nb, I, J);
     const bool diag = I == J;
     const int nst = diag ? kBlkTiles : 2 * kBlkTiles;
     const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
-    const int s = blockIdx.x;
     const int64_t k0 = (int64_t)s * kchunk;
     const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
     const double invS = 1.0 / wsc[0];
@@ -1092,14 +1152,14 @@ __global__ __launch_bounds__(64 * kSyrkBfWaves) void syrk_fp8_blk_kernel(const u
 }
 
 // C (+)= sign * scale_i * scale_j * sum over ranges of the partial tiles (FP64).
-// Grid (npairs, 16): each workgroup takes 64 entries of one tile; its four
-// waves sum the splits q = w, w + 4, ... in order, then the four sums are
+// Grid (npairs, 16): each workgroup takes 64 entries of one tile; its 16
+// waves sum the splits q = w, w + 16, ... in order, then the 16 sums are
 // added in wave order (a fixed order, so results do not vary run to run).
-__global__ __launch_bounds__(256) void syrk_bf16_reduce_kernel(const float *part, int p, int S, const float *scale,
-                                                               double sign, int accumulate, double *C,
-                                                               const double *wsc)
+__global__ __launch_bounds__(64 * kRedWaves) void syrk_bf16_reduce_kernel(const float *part, int p, int S,
+                                                                          const float *scale, double sign,
+                                                                          int accumulate, double *C, const double *wsc)
 {
-    __shared__ double red[4][64];
+    __shared__ double red[kRedWaves][64];
     const int nt = (p + kMT - 1) / kMT;
     const int npairs = nt * (nt + 1) / 2;
     const int pair = blockIdx.x;
@@ -1108,11 +1168,12 @@ __global__ __launch_bounds__(256) void syrk_bf16_reduce_kernel(const float *part
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int e = blockIdx.y * 64 + lane;
     double s = 0.0;
-    for (int q = w; q < S; q += 4) s += (double)part[((int64_t)q * npairs + pair) * (kMT * kMT) + e];
+    for (int q = w; q < S; q += kRedWaves) s += (double)part[((int64_t)q * npairs + pair) * (kMT * kMT) + e];
     red[w][lane] = s;
     __syncthreads();
     if (w != 0) return;
-    s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    s = red[0][lane];
+    for (int v = 1; v < kRedWaves; ++v) s += red[v][lane];
     const int a = e / kMT, bb = e % kMT;
     const int i = ti * kMT + a, j = tj * kMT + bb;
     if (i >= p || j >= p) return;
@@ -1178,17 +1239,23 @@ int syrk_f64(const double *u, int64_t ldu, int p, const double *c, int64_t K, in
     const int npairs = nt * (nt + 1) / 2;
     int64_t kchunk = (K + splits - 1) / splits;
     if (p <= kF64MaxBlk * 16) {
-        // matrix cores, every row of u staged once per K chunk; 2 * splits workgroups
-        const int s2 = 2 * splits;
+        // matrix cores, every row of u staged once per K chunk
+        // 2 * splits workgroups, fewer when K is short (at least 4 chunks each): the reduction
+        // reads every split's tiles
+        int s2 = 2 * splits;
+        const int64_t most = (K + 4 * kF64KC - 1) / (4 * kF64KC);
+        if (most < s2) s2 = most > 1 ? (int)most : 1;
         kchunk = (K + s2 - 1) / s2;
         kchunk = (kchunk + kF64KC - 1) / kF64KC * kF64KC;
         syrk_f64_mfma_kernel<<<s2, 64 * kF64Waves, 0, stream>>>(u, ldu, p, c, K, kchunk, part);
-        syrk_reduce_kernel<<<npairs, kSyrkThreads, 0, stream>>>(part, p, s2, sign, accumulate, C);
+        syrk_reduce_kernel<<<dim3(npairs, kTile * kTile / 64), 64 * kRedWaves, 0, stream>>>(part, p, s2, sign,
+                                                                                           accumulate, C);
         return hipGetLastError() == hipSuccess ? 0 : -3;
     }
     kchunk = (kchunk + kKc - 1) / kKc * kKc;
     syrk_f64_kernel<<<dim3(npairs, splits), kSyrkThreads, 0, stream>>>(u, ldu, p, c, K, kchunk, part);
-    syrk_reduce_kernel<<<npairs, kSyrkThreads, 0, stream>>>(part, p, splits, sign, accumulate, C);
+    syrk_reduce_kernel<<<dim3(npairs, kTile * kTile / 64), 64 * kRedWaves, 0, stream>>>(part, p, splits, sign,
+                                                                                       accumulate, C);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -1222,8 +1289,8 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
         static bool attr2 = false;
         if (!attr2) {
             const size_t most = sizeof(uint16_t) * (size_t)8 * kMT * (64 + 8) * 2;
-            const void *fns[] = {reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<true, 64, 8, 2>),
-                                 reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<false, 64, 8, 2>)};
+            const void *fns[] = {reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<true, 64, 8, 4, 8, 4>),
+                                 reinterpret_cast<const void *>(&syrk_bf16_lds_kernel<false, 64, 8, 4, 8, 4>)};
             for (const void *fn : fns)
                 if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)most) != hipSuccess)
                     return -3;
@@ -1231,8 +1298,8 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
         }
         splits = s2;   // the reduce below sums the slices this launch writes
         const dim3 grid(s2, ngroups);
-        if (c) syrk_bf16_lds_kernel<true, 64, 8, 2><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
-        else syrk_bf16_lds_kernel<false, 64, 8, 2><<<grid, 64 * kSyrkBfWaves, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
+        if (c) syrk_bf16_lds_kernel<true, 64, 8, 4, 8, 4><<<grid, 64 * 8, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
+        else syrk_bf16_lds_kernel<false, 64, 8, 4, 8, 4><<<grid, 64 * 8, lds, stream>>>(u, ldu, p, c, KB, kchunk, fpart);
     } else if (nt <= kLdsMaxTiles && K64 <= ldu && ldu % 8 == 0) {
         int64_t kchunk = (K64 + splits - 1) / splits;
         kchunk = (kchunk + KC - 1) / KC * KC;
@@ -1294,7 +1361,7 @@ int syrk_bf16(const uint16_t *u, int64_t ldu, int p, const float *scale, const d
         kchunk = (kchunk + 15) / 16 * 16;
         syrk_bf16_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, 0, stream>>>(u, ldu, p, c, K16, kchunk, fpart);
     }
-    syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C,
+    syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 64 * kRedWaves, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C,
                                                                  nullptr);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
@@ -1333,7 +1400,7 @@ int syrk_fp8(const uint8_t *u, int64_t ldu, int p, const float *scale, const dou
         kchunk = (kchunk + kF8KC - 1) / kF8KC * kF8KC;
         float *fpart = reinterpret_cast<float *>(part);
         syrk_fp8_blk_kernel<<<dim3(bsplits, nblocks), 64 * kSyrkBfWaves, 0, stream>>>(u, p, c, wsc, K64, kchunk, fpart);
-        syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 256, 0, stream>>>(fpart, p, bsplits, scale, sign, accumulate, C,
+        syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 64 * kRedWaves, 0, stream>>>(fpart, p, bsplits, scale, sign, accumulate, C,
                                                                      wsc);
         return hipGetLastError() == hipSuccess ? 0 : -3;
     }
@@ -1345,14 +1412,122 @@ int syrk_fp8(const uint8_t *u, int64_t ldu, int p, const float *scale, const dou
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
     }
-    const int fit = (4 * cus) / ngroups;
+    int fit = (4 * cus) / ngroups;
+    if (fit >= 8) fit = fit / 8 * 8;   // whole groups of 8 K ranges: one XCD runs all groups of a range
     if (fit >= 1 && fit < splits) splits = fit;
     int64_t kchunk = (K64 + splits - 1) / splits;
     kchunk = (kchunk + kF8KC - 1) / kF8KC * kF8KC;
     const size_t lds = (size_t)nt * kMT * kF8Stride;
     float *fpart = reinterpret_cast<float *>(part);
-    syrk_fp8_lds_kernel<<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, p, c, wsc, K64, kchunk, fpart);
-    syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 256, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C, wsc);
+    if (nt * kMT <= 512)
+        syrk_fp8_lds_kernel<512><<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, p, c, wsc, K64, kchunk,
+                                                                                          fpart);
+    else
+        syrk_fp8_lds_kernel<kF8MaxRows><<<dim3(splits, ngroups), 64 * kSyrkBfWaves, lds, stream>>>(u, p, c, wsc, K64,
+                                                                                                 kchunk, fpart);
+    syrk_bf16_reduce_kernel<<<dim3(npairs, 16), 64 * kRedWaves, 0, stream>>>(fpart, p, splits, scale, sign, accumulate, C, wsc);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+// Proximal Newton's model solve: cyclic coordinate descent with soft thresholding (the l1
+// rule of Sec. 2.4, applied to the quadratic model of the objective)
+//   min_D  g'D + D'HD/2 + sum_j gamma_j |beta_j + D_j|
+// in one wave.  Every lane takes the same scalar decision for coordinate j from inputs
+// broadcast out of LDS; lane l keeps HD[k] (k = l mod 64) up to date from row j of the
+// symmetric H when D_j moves.  Row j+1's first kProxPre * 64 entries are loaded into
+// registers while coordinate j is decided.  Coordinates not free, or with H_jj <= 0 or not
+// finite, stay at 0.  Stops after the first sweep whose largest |change| is <= tol, or after
+// max_sweeps sweeps.
+constexpr int kProxChunk = 1024;   // coordinates whose inputs are staged in LDS at a time
+constexpr int kProxPre = 16;       // prefetched entries of a row per lane (1024 columns)
+
+__global__ __launch_bounds__(64) void prox_cd_kernel(const double *H, int p, const double *g, const double *beta,
+                                                     const double *gam, const uint8_t *free_col, double tol,
+                                                     int max_sweeps, double *D, int *sweeps_out)
+{
+    extern __shared__ double sm[];   // HD[p], Dv[p]
+    double *HD = sm, *Dv = sm + p;
+    __shared__ double cg[kProxChunk], cb[kProxChunk], cgam[kProxChunk], ca[kProxChunk];
+    const int lane = threadIdx.x;
+    for (int k = lane; k < p; k += 64) {
+        HD[k] = 0.0;
+        Dv[k] = 0.0;
+    }
+    double nxt[kProxPre];
+    auto load_row = [&](int j) {
+        const double *row = H + (size_t)j * p;
+#pragma unroll
+        for (int m = 0; m < kProxPre; ++m) {
+            const int k = lane + 64 * m;
+            nxt[m] = k < p ? row[k] : 0.0;
+        }
+    };
+    int sweep = 0;
+    while (sweep < max_sweeps) {
+        ++sweep;
+        double change = 0.0;
+        for (int j0 = 0; j0 < p; j0 += kProxChunk) {
+            const int jn = p - j0 < kProxChunk ? p - j0 : kProxChunk;
+            __syncthreads();
+            for (int i = lane; i < jn; i += 64) {
+                const int j = j0 + i;
+                const double a = H[(size_t)j * p + j];
+                cg[i] = g[j];
+                cb[i] = beta[j];
+                cgam[i] = gam[j];
+                ca[i] = (free_col[j] && a > 0.0 && a < INFINITY) ? a : 0.0;
+            }
+            load_row(j0);
+            __syncthreads();
+            for (int i = 0; i < jn; ++i) {
+                const int j = j0 + i;
+                double cur[kProxPre];
+#pragma unroll
+                for (int m = 0; m < kProxPre; ++m) cur[m] = nxt[m];
+                if (i + 1 < jn) load_row(j + 1);
+                const double a = ca[i];
+                if (a == 0.0) continue;
+                const double bj = cb[i], gm = cgam[i], dj = Dv[j];
+                const double b = cg[i] + HD[j] - a * dj;   // the model's slope at D with D_j removed
+                const double u = a * bj - b;
+                const double z = u > gm ? (u - gm) / a : (u < -gm ? (u + gm) / a : 0.0);
+                const double dn = z - bj;
+                const double delta = dn - dj;
+                if (delta != 0.0) {
+                    __syncthreads();   // every lane has read Dv[j] and HD[j]
+                    if (lane == 0) Dv[j] = dn;
+#pragma unroll
+                    for (int m = 0; m < kProxPre; ++m) {
+                        const int k = lane + 64 * m;
+                        if (k < p) HD[k] += cur[m] * delta;
+                    }
+                    for (int k = lane + 64 * kProxPre; k < p; k += 64) HD[k] += H[(size_t)j * p + k] * delta;
+                    change = fmax(change, fabs(delta));
+                    __syncthreads();   // HD and Dv written before the next coordinate reads them
+                }
+            }
+        }
+        if (change <= tol) break;
+    }
+    __syncthreads();
+    for (int k = lane; k < p; k += 64) D[k] = Dv[k];
+    if (lane == 0) *sweeps_out = sweep;
+}
+
+int prox_model_solve(const double *H, int p, const double *g, const double *beta, const double *gam,
+                     const uint8_t *free_col, double tol, int max_sweeps, double *D, int *sweeps, hipStream_t stream)
+{
+    if (p < 1 || p > 4096) return -1;
+    const size_t lds = sizeof(double) * 2 * (size_t)p;
+    static bool attr = false;
+    if (!attr) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&prox_cd_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(double) * 2 * 4096)) !=
+            hipSuccess)
+            return -3;
+        attr = true;
+    }
+    prox_cd_kernel<<<1, 64, lds, stream>>>(H, p, g, beta, gam, free_col, tol, max_sweeps, D, sweeps);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

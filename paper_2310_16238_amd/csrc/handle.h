@@ -55,6 +55,7 @@ struct NewtonState {
     double *erows = nullptr;       // 4 x [ld]: E0', k', l21, l22 at event-group ends
     double *epart = nullptr;       // [p][eblocks] diagonal parts of the multi-event groups
     int eblocks = 0;
+    double *prox = nullptr;        // proximal Newton: g, beta, gamma, D (p each), then the sweep count
 };
 
 struct cox_handle {

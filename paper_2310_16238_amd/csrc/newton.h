@@ -110,4 +110,11 @@ constexpr int kSplitsXFP8 = 256;
 int chol_solve(double *A, int p, const double *g, const uint8_t *free_col, int factored, double *dx, int *status,
                hipStream_t stream);
 
+// Proximal Newton's model solve on the device (one wave): D minimising
+// g'D + D'HD/2 + sum_j gam_j |beta_j + D_j| by cyclic coordinate descent with soft thresholding,
+// free columns only (H: p x p symmetric; g, beta, gam: p; D: p out; sweeps: 1 int out).
+// Stops after a sweep whose largest change is <= tol, or after max_sweeps.  p <= 4096.
+int prox_model_solve(const double *H, int p, const double *g, const double *beta, const double *gam,
+                     const uint8_t *free_col, double tol, int max_sweeps, double *D, int *sweeps, hipStream_t stream);
+
 }  // namespace coxmi

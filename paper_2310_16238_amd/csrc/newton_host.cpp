@@ -346,7 +346,7 @@ void newton_free(cox_handle *h)
     void *ptrs[] = {s.gidx, s.rows, s.blockbuf, s.tile_carry, s.lasthead, s.agg_tiles, s.agg, s.carry,
                     s.colpart, s.vec, s.flags, s.status, s.free_col, s.z,
                     s.zscale, s.xlp, s.xscale, s.syrk_part, s.info, s.scan_scratch, s.wscratch,
-                    s.gidx2, s.gend, s.me_ptr, s.me_row, s.me_end, s.me_w, s.s1me, s.erows, s.epart};
+                    s.gidx2, s.gend, s.me_ptr, s.me_row, s.me_end, s.me_w, s.s1me, s.erows, s.epart, s.prox};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (s.hvec) (void)hipHostFree(s.hvec);
@@ -418,7 +418,8 @@ extern "C" int cox_baseline_hazard(cox_handle *h, const double *beta, double *cu
 // Proximal Newton for the l1-penalised fit: each step minimises the quadratic model
 //   g'D + D'HD/2 + sum_j gamma_j |beta_j + D_j|
 // (FP64 score g, information H in x_precision) by cyclic coordinate descent with soft
-// thresholding on the host; a step that raises the penalised objective is halved.  A fixed
+// thresholding on the device (prox_model_solve: H stays where the contraction left it; only
+// g, beta and D cross to and from the host); a step that raises the penalised objective is halved.  A fixed
 // point (D = 0) satisfies the l1 optimality conditions on the FP64 score whatever the
 // precision of H, so a reduced-precision H, kept once steps are small, still reaches the
 // FP64 optimum.
@@ -427,7 +428,20 @@ static int newton_fit_l1(cox_handle *h, const double *beta0, double *beta_out, c
     NewtonState &s = h->nt;
     const int p = (int)h->p;
     const std::vector<double> &gam = h->gamma;
-    std::vector<double> beta(p, 0.0), prev(p, 0.0), D(p, 0.0), HD(p, 0.0), H((size_t)p * p, 0.0);
+    std::vector<double> beta(p, 0.0), prev(p, 0.0), D(p, 0.0);
+    if (!s.prox) {
+        const hipError_t e = hipMalloc(&s.prox, sizeof(double) * (4 * (size_t)p + 1));
+        if (e != hipSuccess) {
+            s.prox = nullptr;
+            return handle_hip_fail(h, e, "proximal Newton buffers");
+        }
+    }
+    double *d_g = s.prox, *d_beta = s.prox + p, *d_gam = s.prox + 2 * p, *d_D = s.prox + 3 * p;
+    int *d_sweeps = reinterpret_cast<int *>(s.prox + 4 * p);
+    {
+        const hipError_t e = hipMemcpy(d_gam, gam.data(), sizeof(double) * p, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return handle_hip_fail(h, e, "l1 weights");
+    }
     if (beta0) std::memcpy(beta.data(), beta0, sizeof(double) * p);
     std::vector<uint8_t> freec(p, 1);
     bool frozen = false, have_free = false, have_h = false, converged = false;
@@ -454,6 +468,8 @@ static int newton_fit_l1(cox_handle *h, const double *beta0, double *beta_out, c
                 }
             }
             have_free = true;
+            const hipError_t e = hipMemcpy(s.free_col, freec.data(), (size_t)p, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return handle_hip_fail(h, e, "free columns");
             if (moved) continue;   // re-evaluate at the start point with the pinned columns at zero
         }
         const double F = ev.objective + penalty(beta);
@@ -467,39 +483,33 @@ static int newton_fit_l1(cox_handle *h, const double *beta0, double *beta_out, c
         if (!frozen || !have_h) {
             rc = newton_info(h);
             if (rc != COX_OK) return rc;
-            hipError_t e = hipStreamSynchronize(h->stream);
-            if (e == hipSuccess) e = hipMemcpy(H.data(), s.info, sizeof(double) * H.size(), hipMemcpyDeviceToHost);
+            const hipError_t e = hipStreamSynchronize(h->stream);
             if (e != hipSuccess) return handle_hip_fail(h, e, "information matrix");
             h->prof.contractions += 1;
             h->prof.contraction_ms += elapsed_ms(s.ev[2], s.ev[3]);
             have_h = true;
         }
-        // coordinate descent on the model; HD = H D is kept up to date.  The model is solved to
-        // a thousandth of the last outer step (inexact early on), and to 1e-3 tol at the end
-        std::fill(D.begin(), D.end(), 0.0);
-        std::fill(HD.begin(), HD.end(), 0.0);
+        // coordinate descent on the model (device).  The model is solved to a thousandth of the
+        // last outer step (inexact early on), and to 1e-3 tol at the end
         double bmax = 1.0;
         for (int j = 0; j < p; ++j) bmax = std::max(bmax, std::fabs(beta[j]));
         const double inner_tol = std::max(1e-3 * h->opt.tol * bmax, iters ? 1e-3 * last_step : 1e-3 * bmax);
-        for (int sweep = 0; sweep < 1000; ++sweep) {
-            double change = 0.0;
-            for (int j = 0; j < p; ++j) {
-                if (!freec[j]) continue;
-                const double a = H[(size_t)j * p + j];
-                if (!(a > 0.0)) continue;
-                const double b = ev.grad[j] + HD[j] - a * D[j];      // model slope at D with D_j removed
-                const double u = a * beta[j] - b;
-                const double z = u > gam[j] ? (u - gam[j]) / a : (u < -gam[j] ? (u + gam[j]) / a : 0.0);
-                const double dn = z - beta[j];
-                const double delta = dn - D[j];
-                if (delta != 0.0) {
-                    D[j] = dn;
-                    const double *col = H.data() + (size_t)j * p;   // symmetric: row j = column j
-                    for (int k = 0; k < p; ++k) HD[k] += col[k] * delta;
-                    change = std::max(change, std::fabs(delta));
-                }
-            }
-            if (change <= inner_tol) break;
+        {
+            hipError_t e = hipMemcpyAsync(d_g, ev.grad.data(), sizeof(double) * p, hipMemcpyHostToDevice, h->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_beta, beta.data(), sizeof(double) * p, hipMemcpyHostToDevice, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(s.ev[4], h->stream);
+            if (e == hipSuccess &&
+                prox_model_solve(s.info, p, d_g, d_beta, d_gam, s.free_col, inner_tol, 1000, d_D, d_sweeps,
+                                 h->stream) != 0)
+                e = hipErrorLaunchFailure;
+            if (e == hipSuccess) e = hipEventRecord(s.ev[5], h->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(D.data(), d_D, sizeof(double) * p, hipMemcpyDeviceToHost, h->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) return handle_hip_fail(h, e, "proximal model solve");
+            h->prof.solves += 1;
+            h->prof.solve_ms += elapsed_ms(s.ev[4], s.ev[5]);
         }
         prev = beta;
         obj_prev = F;

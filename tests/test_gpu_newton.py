@@ -436,6 +436,30 @@ def test_newton_l1_fit(name, make, prec):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("prec", [coxmi.COX_F64, coxmi.COX_BF16], ids=["f64", "bf16"])
+def test_newton_l1_fit_wide(prec):
+    """Proximal Newton with more columns than one LDS chunk of the device model solve (1024
+    coordinates) and than its prefetched row (1024 entries per row): chunked staging and the
+    streamed row tail; the oracle's CCD optimum to 1e-10 and the same zero pattern."""
+    d = synth.config_ar1(n=8_000, p=1_100, K=40)
+    p = d.X.shape[1]
+    pen = np.ones(p, np.uint8)
+    pen[0] = 0
+    L = orc.canonical_layout(d.time, d.event, d.stratum)
+    g0 = orc.full_eval(orc.to_canonical(d.X, L), L, np.zeros(p), want_info=False).grad
+    gamma = 0.3 * float(np.max(np.abs(g0[1:])))
+    _say(f"newton l1 fit wide p={p} prec={prec} gamma={gamma:.2f}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE, x_precision=prec,
+                        gamma=gamma, penalize=pen, tol=1e-13, max_iter=300) as m:
+        beta, info = m.fit()
+    ref = orc.fit_ccd(d.X, d.time, d.event, d.stratum, gamma=gamma, penalize=pen, tol=1e-14, max_sweeps=5000)
+    assert ref.converged and info["status"] == coxmi.COX_OK, info
+    assert np.array_equal(beta == 0.0, ref.beta == 0.0)
+    err = _rel(beta, ref.beta)
+    _say(f"  steps={info['iters']} nonzero={int(np.count_nonzero(beta))} rel err {err:.3e}")
+    assert err <= 1e-10
+
+
 @pytest.mark.parametrize("n,p,K", [(20_011, 600, 13), (12_003, 1000, 1)])
 def test_information_bf16_wide_within_bound(n, p, K):
     """More than 16 row tiles (P > 512): the blocked contraction, where each workgroup stages only
