@@ -47,14 +47,15 @@ def log(msg):
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ccd_kernel_ar1_n1e6_p50_K5e4.md")
 KERNEL_SOURCES = ["ccd_kernel.hip", "segscan.hpp", "internal.h"]
+CONTRACTION_PROFILE = os.path.join(ROOT, "profiles", "newton_counters_n1e6_p200.md")
 
 
-def recorded_traffic():
-    """HBM bytes per launch from the committed counter summary, or None when the
-    kernel sources no longer hash to the value the counters were taken on."""
+def recorded_field(profile=TRAFFIC_PROFILE, sources=KERNEL_SOURCES, field="traffic_bytes_per_launch"):
+    """A figure from a committed counter summary (HBM bytes per launch by default), or None
+    when the kernel sources no longer hash to the value the counters were taken on."""
     import hashlib
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(profile) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
@@ -64,15 +65,19 @@ def recorded_traffic():
         if sep and key and " " not in key:
             fields[key] = val.strip()
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2310_16238_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if fields.get("kernel_sources_sha256") != h.hexdigest():
         return None
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[field])
     except (KeyError, ValueError):
         return None
+
+
+def recorded_traffic():
+    return recorded_field()
 
 
 def cpu_baseline(d, sweeps=20):
@@ -1214,7 +1219,9 @@ def mixed_leg(args, steps, warmup):
         "speedup_vs_plain": runs["bf16"]["fits_per_s"] / runs["f64"]["fits_per_s"],
         "runs": runs,
         "roofline": {"bound": "mfma", "achieved": flops / contr_s / 1e12, "peak": MFMA_PEAK_TFLOPS["bf16"],
-                     "unit": "TFLOP/s", "frac": flops / contr_s / 1e12 / MFMA_PEAK_TFLOPS["bf16"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": flops / contr_s / 1e12 / MFMA_PEAK_TFLOPS["bf16"],
+                     "traffic": recorded_field(CONTRACTION_PROFILE, ["contraction.hip"]),
+                     "mfma_busy": recorded_field(CONTRACTION_PROFILE, ["contraction.hip"], "mfma_busy"),
                      "kernel": "BF16 information contraction (X' diag(b) X and Z'Z)",
                      "algorithmic_flops_per_launch": flops},
         "evaluation_roofline": {"bound": "hbm", "achieved": eval_bytes / eval_s / 1e9, "peak": HBM_PEAK_GBS,

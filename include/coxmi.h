@@ -416,8 +416,9 @@ const char *cox_last_error(const cox_handle *h);
 
 /* ------------------------------------------------------------------ fit server
  *
- * Continuous batching of many independent, unpenalised stratified Cox fits
- * of uneven size (Eq. strat_l per request, gamma = 0).  Each request is put
+ * Continuous batching of many independent stratified Cox fits of uneven size
+ * (Eq. strat_l per request; unpenalised, or with l1 weights through
+ * cox_server_submit_fit).  Each request is put
  * in the canonical order of Sec. 2.7 by a host thread pool and admitted to
  * the device as soon as a slot is free and its footprint fits in the
  * server's device budget; every resident fit then takes one Newton step per
@@ -486,6 +487,39 @@ int cox_server_create(cox_server **out, const cox_server_options *o);
  * or the server's fatal device error.  A request whose device footprint
  * exceeds hbm_budget (or staging_bytes) completes with status COX_EUNSUPPORTED. */
 int cox_server_submit(cox_server *s, const cox_data *d, int flags, uint64_t *ticket);
+
+/* Per-request options of cox_server_submit_fit. */
+typedef struct {
+    double gamma;             /* l1 weight (Sec. 2.1, R5): 0 = unpenalised */
+    const uint8_t *penalize;  /* host, p flags or NULL (every column penalised when gamma > 0) */
+    const double *beta0;      /* host, p start values (original column order) or NULL (zeros) */
+} cox_fit_request;
+
+/* cox_server_submit with per-request options: an l1-penalised fit (gamma > 0) takes
+ * proximal Newton steps, as on a COX_NEWTON_REFINE handle: the quadratic model with the
+ * FP64 score and the FP32 information matrix, minimised by cyclic coordinate descent with
+ * soft thresholding (the l1 rule of Sec. 2.4) on the device, a step that raises the
+ * penalised objective halved; info->objective is the penalised objective and kkt_inf the
+ * largest violation of the l1 optimality conditions.  beta0 starts the fit elsewhere than
+ * at zero (a warm start along a path of weights).  r = NULL is cox_server_submit.
+ * Errors: those of cox_server_submit, COX_EINVAL (gamma < 0 or not finite, beta0 not finite). */
+int cox_server_submit_fit(cox_server *s, const cox_data *d, int flags, const cox_fit_request *r, uint64_t *ticket);
+
+/* cox_cross_validate with the fold fits batched through a fit server (Sec. 3.2's 10-fold
+ * l1 path as many small independent fits): for each weight in turn the nfolds training-set
+ * fits are submitted together (cox_server_submit_fit: proximal Newton steps, FP32
+ * information matrix, FP64 score), each warm-started from its fold's fit at the previous
+ * weight; the criterion is cox_cross_validate's, from FP64 evaluations on h and on a
+ * training-set handle per fold.
+ *   h   : handle made by cox_init from d (not an interval or resampled handle)
+ *   srv : the server (p <= 128); its tol and max_iter rule the fold fits
+ *   d   : the same data in host memory
+ * Other arguments and outputs as cox_cross_validate.  Errors: those of
+ * cox_cross_validate, COX_EINVAL (srv or d missing, d on the device or not h's shape),
+ * the server's (COX_EUNSUPPORTED for p > 128). */
+int cox_cross_validate_served(cox_handle *h, cox_server *srv, const cox_data *d, int nfolds, const int32_t *fold,
+                              int ngamma, const double *gammas, const uint8_t *penalize, double *cvl, double *betas,
+                              int *status);
 
 /* Collect a result: returns COX_OK and fills beta_out (p doubles, original
  * column order), info (status COX_OK, COX_NOT_CONVERGED, COX_ENUMERIC, ...;

@@ -93,6 +93,11 @@ class cox_request_times(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class cox_fit_request(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("penalize", ctypes.POINTER(ctypes.c_uint8)),
+                ("beta0", ctypes.POINTER(ctypes.c_double))]
+
+
 class cox_server_counters(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("iterations", ctypes.c_int64),
                 ("resident_now", ctypes.c_int64), ("resident_peak", ctypes.c_int64),
@@ -150,6 +155,9 @@ SIGNATURES = [
     ("cox_set_penalty", ctypes.c_int, [_VP, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8)]),
     ("cox_cross_validate", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _DP,
                                           ctypes.POINTER(ctypes.c_uint8), _DP, _DP, ctypes.POINTER(ctypes.c_int)]),
+    ("cox_cross_validate_served", ctypes.c_int, [_VP, _VP, ctypes.POINTER(cox_data), ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_int32), ctypes.c_int, _DP,
+                                                 ctypes.POINTER(ctypes.c_uint8), _DP, _DP, ctypes.POINTER(ctypes.c_int)]),
     ("cox_bootstrap", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), _DP, _DP,
                                      ctypes.POINTER(ctypes.c_int)]),
     ("cox_canonical_order", ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
@@ -167,6 +175,8 @@ SIGNATURES = [
     ("cox_server_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(cox_server_options)]),
     ("cox_server_submit", ctypes.c_int, [_VP, ctypes.POINTER(cox_data), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_uint64)]),
+    ("cox_server_submit_fit", ctypes.c_int, [_VP, ctypes.POINTER(cox_data), ctypes.c_int,
+                                             ctypes.POINTER(cox_fit_request), ctypes.POINTER(ctypes.c_uint64)]),
     ("cox_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, _DP, ctypes.POINTER(cox_fit_info),
                                        ctypes.POINTER(cox_request_times)]),
     ("cox_server_wait", ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_double]),
@@ -403,6 +413,36 @@ def cox_cross_validate(h, fold, gammas, penalize=None, nfolds=None):
     rc = lib().cox_cross_validate(h, K, fold.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), gam.shape[0], _dptr(gam),
                                   None if pen is None else pen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                   _dptr(cvl), _dptr(betas), status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    _check(h, rc, ok=(COX_OK, COX_NOT_CONVERGED))
+    return cvl, betas, status
+
+
+def cox_cross_validate_served(h, server, X, time, event, stratum, fold, gammas, penalize=None, nfolds=None):
+    """cox_cross_validate with the fold fits batched through `server` (a CoxServer); X, time,
+    event, stratum: the host data h was made from (cox_cross_validate_served)."""
+    n, p, _ = cox_shape(h)
+    X = np.asfortranarray(X, dtype=np.float64)
+    time = np.ascontiguousarray(time, dtype=np.float64)
+    event = np.ascontiguousarray(event, dtype=np.uint8)
+    d = cox_data(n=X.shape[0], p=X.shape[1], x=_dptr(X), ldx=X.shape[0], time=_dptr(time),
+                 event=event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    st = None
+    if stratum is not None:
+        st = np.ascontiguousarray(stratum, dtype=np.int32)
+        d.stratum = st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    fold = np.ascontiguousarray(fold, dtype=np.int32)
+    if fold.shape != (n,):
+        raise ValueError(f"fold needs {n} entries")
+    K = int(fold.max()) + 1 if nfolds is None else int(nfolds)
+    gam = np.ascontiguousarray(gammas, dtype=np.float64)
+    pen = None if penalize is None else np.ascontiguousarray(penalize, dtype=np.uint8)
+    cvl = np.zeros(gam.shape[0])
+    betas = np.zeros((K, gam.shape[0], p))
+    status = np.zeros((K, gam.shape[0]), dtype=np.int32)
+    rc = lib().cox_cross_validate_served(h, server.h, ctypes.byref(d), K,
+                                         fold.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), gam.shape[0],
+                                         _dptr(gam), None if pen is None else pen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                         _dptr(cvl), _dptr(betas), status.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     _check(h, rc, ok=(COX_OK, COX_NOT_CONVERGED))
     return cvl, betas, status
 
@@ -663,6 +703,9 @@ class CoxModel:
     def cross_validate(self, fold, gammas, penalize=None, nfolds=None):
         return cox_cross_validate(self.h, fold, gammas, penalize, nfolds)
 
+    def cross_validate_served(self, server, X, time, event, stratum, fold, gammas, penalize=None, nfolds=None):
+        return cox_cross_validate_served(self.h, server, X, time, event, stratum, fold, gammas, penalize, nfolds)
+
     def bootstrap(self, counts, beta0=None):
         return cox_bootstrap(self.h, counts, beta0)
 
@@ -739,21 +782,53 @@ class CoxServer:
             raise CoxError(rc, msg.decode() if msg else "")
         return rc
 
-    def submit_device(self, X, time, event, stratum=None) -> int:
+    @staticmethod
+    def _request(p, gamma, penalize, beta0):
+        """(cox_fit_request or None, arrays to keep alive) for the per-request options."""
+        if gamma == 0.0 and penalize is None and beta0 is None:
+            return None, []
+        r = cox_fit_request(gamma=float(gamma))
+        keep = []
+        if penalize is not None:
+            pen = np.ascontiguousarray(penalize, dtype=np.uint8)
+            if pen.shape != (p,):
+                raise ValueError(f"penalize needs {p} entries")
+            r.penalize = pen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+            keep.append(pen)
+        if beta0 is not None:
+            b0 = np.ascontiguousarray(beta0, dtype=np.float64)
+            if b0.shape != (p,):
+                raise ValueError(f"beta0 needs {p} entries")
+            r.beta0 = _dptr(b0)
+            keep.append(b0)
+        return r, keep
+
+    def _submit(self, d, flags, p, gamma, penalize, beta0):
+        r, keep = self._request(p, gamma, penalize, beta0)
+        t = ctypes.c_uint64()
+        if r is None:
+            self._check(lib().cox_server_submit(self.h, ctypes.byref(d), flags, ctypes.byref(t)))
+        else:
+            self._check(lib().cox_server_submit_fit(self.h, ctypes.byref(d), flags, ctypes.byref(r), ctypes.byref(t)))
+        del keep   # the request options are copied by the call
+        return t.value
+
+    def submit_device(self, X, time, event, stratum=None, gamma=0.0, penalize=None, beta0=None) -> int:
         """Submit device-resident data (torch tensors on the server's device):
         X float64 n x p with unit row stride (column-major, e.g. a transposed
         contiguous p x n tensor), time float64, event uint8, stratum int32 or
         None.  The tensors are read in place and kept referenced until the
-        result is collected; the caller synchronises the stream that wrote them."""
+        result is collected; the caller synchronises the stream that wrote them.
+        gamma, penalize, beta0: l1 weight, penalised columns and start point
+        (cox_server_submit_fit)."""
         n, p = X.shape
         d = _device_data(X, time, event, stratum)
-        t = ctypes.c_uint64()
-        self._check(lib().cox_server_submit(self.h, ctypes.byref(d), COX_SUBMIT_DEVICE, ctypes.byref(t)))
-        self._keep[t.value] = [X, time, event, stratum]
-        self._p[t.value] = p
-        return t.value
+        t = self._submit(d, COX_SUBMIT_DEVICE, p, gamma, penalize, beta0)
+        self._keep[t] = [X, time, event, stratum]
+        self._p[t] = p
+        return t
 
-    def submit(self, X, time, event, stratum=None, borrow=True) -> int:
+    def submit(self, X, time, event, stratum=None, borrow=True, gamma=0.0, penalize=None, beta0=None) -> int:
         X = np.asfortranarray(X, dtype=np.float64)
         n, p = X.shape
         time = np.ascontiguousarray(time, dtype=np.float64)
@@ -765,13 +840,11 @@ class CoxServer:
             st = np.ascontiguousarray(stratum, dtype=np.int32)
             keep.append(st)
             d.stratum = st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-        t = ctypes.c_uint64()
-        self._check(lib().cox_server_submit(self.h, ctypes.byref(d), COX_SUBMIT_BORROW if borrow else 0,
-                                            ctypes.byref(t)))
+        t = self._submit(d, COX_SUBMIT_BORROW if borrow else 0, p, gamma, penalize, beta0)
         if borrow:
-            self._keep[t.value] = keep
-        self._p[t.value] = p
-        return t.value
+            self._keep[t] = keep
+        self._p[t] = p
+        return t
 
     def poll(self, ticket):
         p = self._p[ticket]

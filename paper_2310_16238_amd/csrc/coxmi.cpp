@@ -904,10 +904,10 @@ static int neg_loglik(cox_handle *h, const double *beta, double *nll)
     return COX_OK;
 }
 
-extern "C" int cox_cross_validate(cox_handle *h, int nfolds, const int32_t *fold, int ngamma, const double *gammas,
-                                  const uint8_t *penalize, double *cvl, double *betas, int *status)
+// The argument checks of a cross-validation; 0 or a COX_* code with the message set on h.
+static int check_folds(cox_handle *h, int nfolds, const int32_t *fold, int ngamma, const double *gammas,
+                       const double *cvl)
 {
-    if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
     if (nfolds < 2 || !fold) return fail(h, COX_EINVAL, "need nfolds >= 2 and a fold for every row");
     if (ngamma < 1 || !gammas || !cvl) return fail(h, COX_EINVAL, "need ngamma >= 1, gammas and cvl");
     for (int g = 0; g < ngamma; ++g)
@@ -930,6 +930,14 @@ extern "C" int cox_cross_validate(cox_handle *h, int nfolds, const int32_t *fold
             else if (f != fold[i]) return fail(h, COX_EINVAL, "rows of one subject fall in different folds");
         }
     }
+    return COX_OK;
+}
+
+extern "C" int cox_cross_validate(cox_handle *h, int nfolds, const int32_t *fold, int ngamma, const double *gammas,
+                                  const uint8_t *penalize, double *cvl, double *betas, int *status)
+{
+    if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (const int rc = check_folds(h, nfolds, fold, ngamma, gammas, cvl)) return rc;
     const int64_t p = h->p;
     std::fill(cvl, cvl + ngamma, 0.0);
     bool all_converged = true;
@@ -967,6 +975,107 @@ extern "C" int cox_cross_validate(cox_handle *h, int nfolds, const int32_t *fold
         cox_release(c);
         if (rc < 0) return fail(h, rc, "fold " + std::to_string(k) + ": " + cerr);
     }
+    return all_converged ? COX_OK : COX_NOT_CONVERGED;
+}
+
+extern "C" int cox_cross_validate_served(cox_handle *h, cox_server *srv, const cox_data *d, int nfolds,
+                                         const int32_t *fold, int ngamma, const double *gammas,
+                                         const uint8_t *penalize, double *cvl, double *betas, int *status)
+{
+    if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
+    if (!srv || !d) return fail(h, COX_EINVAL, "server and data are required");
+    if (d->on_device) return fail(h, COX_EINVAL, "the fold requests are built from host data");
+    if (d->n != h->n || d->p != h->p || !h->subject.empty())
+        return fail(h, COX_EINVAL, "d must be the data the handle was made from by cox_init");
+    if (const char *bad = check_data(d->n, d->p, d->ldx, d->x, d->time, d->event)) return fail(h, COX_EINVAL, bad);
+    if (const int rc = check_folds(h, nfolds, fold, ngamma, gammas, cvl)) return rc;
+    const int64_t n = h->n, p = h->p;
+    // each fold's training rows, copied once (column-major X, keys)
+    struct Train {
+        int64_t n = 0;
+        std::vector<double> x, t;
+        std::vector<uint8_t> e;
+        std::vector<int32_t> st;
+        cox_data data{};
+    };
+    std::vector<Train> tr((size_t)nfolds);
+    for (int k = 0; k < nfolds; ++k) {
+        Train &T = tr[(size_t)k];
+        for (int64_t i = 0; i < n; ++i) T.n += fold[i] != k ? 1 : 0;
+        T.x.resize((size_t)(T.n * p));
+        T.t.resize((size_t)T.n);
+        T.e.resize((size_t)T.n);
+        if (d->stratum) T.st.resize((size_t)T.n);
+        int64_t r = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (fold[i] == k) continue;
+            for (int64_t j = 0; j < p; ++j) T.x[(size_t)(j * T.n + r)] = d->x[j * d->ldx + i];
+            T.t[(size_t)r] = d->time[i];
+            T.e[(size_t)r] = d->event[i];
+            if (d->stratum) T.st[(size_t)r] = d->stratum[i];
+            ++r;
+        }
+        T.data.n = T.n;
+        T.data.p = p;
+        T.data.x = T.x.data();
+        T.data.ldx = T.n;
+        T.data.time = T.t.data();
+        T.data.event = T.e.data();
+        T.data.stratum = d->stratum ? T.st.data() : nullptr;
+    }
+    // the fits: every fold at one weight in one batch, warm-started from the previous weight's fits
+    std::vector<double> all((size_t)nfolds * ngamma * p, 0.0);
+    std::vector<int> stat((size_t)nfolds * ngamma, COX_OK);
+    std::vector<uint64_t> tickets((size_t)nfolds);
+    for (int g = 0; g < ngamma; ++g) {
+        for (int k = 0; k < nfolds; ++k) {
+            cox_fit_request r{};
+            r.gamma = gammas[g];
+            r.penalize = penalize;
+            r.beta0 = g > 0 ? all.data() + ((size_t)k * ngamma + g - 1) * p : nullptr;
+            const int rc = cox_server_submit_fit(srv, &tr[(size_t)k].data, COX_SUBMIT_BORROW, &r, &tickets[(size_t)k]);
+            if (rc != COX_OK) return fail(h, rc, std::string("fold request: ") + cox_server_last_error(srv));
+        }
+        for (int k = 0; k < nfolds; ++k) {
+            int rc = cox_server_wait(srv, tickets[(size_t)k], -1.0);
+            cox_fit_info info{};
+            if (rc == COX_OK)
+                rc = cox_server_poll(srv, tickets[(size_t)k], all.data() + ((size_t)k * ngamma + g) * p, &info, nullptr);
+            if (rc != COX_OK) return fail(h, rc, std::string("fold fit: ") + cox_server_last_error(srv));
+            if (info.status < 0) return fail(h, info.status, "fold " + std::to_string(k) + " fit failed");
+            stat[(size_t)k * ngamma + g] = info.status;
+        }
+    }
+    // the criterion: l(beta_{-k}) - l_{-k}(beta_{-k}) from the full handle and a training handle per fold
+    std::fill(cvl, cvl + ngamma, 0.0);
+    std::vector<uint32_t> keep((size_t)n);
+    bool all_converged = true;
+    for (int k = 0; k < nfolds; ++k) {
+        for (int64_t i = 0; i < n; ++i) keep[(size_t)i] = fold[i] != k ? 1u : 0u;
+        cox_options o = h->opt;
+        o.mode = COX_CCD;
+        o.x_precision = COX_F64;
+        o.gamma = 0.0;
+        o.penalize = nullptr;
+        cox_handle *c = nullptr;
+        int rc = cox_init_resample(&c, h, keep.data(), &o);
+        if (rc != COX_OK) return fail(h, rc, std::string("fold training set: ") + cox_last_error(nullptr));
+        for (int g = 0; g < ngamma && rc == COX_OK; ++g) {
+            const double *beta = all.data() + ((size_t)k * ngamma + g) * p;
+            double nll_train = 0.0, nll_full = 0.0;
+            rc = neg_loglik(c, beta, &nll_train);
+            if (rc == COX_OK) rc = neg_loglik(h, beta, &nll_full);
+            if (rc == COX_OK) cvl[g] += nll_train - nll_full;
+        }
+        const std::string cerr = rc != COX_OK ? c->err : std::string();
+        cox_release(c);
+        if (rc != COX_OK) return fail(h, rc, "fold " + std::to_string(k) + ": " + cerr);
+    }
+    for (size_t q = 0; q < stat.size(); ++q) {
+        if (stat[q] != COX_OK) all_converged = false;
+        if (status) status[q] = stat[q];
+    }
+    if (betas) std::copy(all.begin(), all.end(), betas);
     return all_converged ? COX_OK : COX_NOT_CONVERGED;
 }
 

@@ -39,7 +39,8 @@ struct alignas(16) FitState {
     double obj;         // objective at the last accepted point
     double obj_prev;    // objective where the last accepted step started
     double last_step;   // max |step| of the last accepted step
-    double kkt;         // max |score| over the free columns at the last evaluation
+    double kkt;         // max |score| over the free columns at the last evaluation (with l1 weights:
+                        // the largest violation of the l1 optimality conditions there)
     int iters;          // accepted Newton steps
     int evals;          // evaluations (accepted steps + halvings)
     int halvings;       // consecutive halvings of the current step
@@ -78,9 +79,11 @@ struct FitDesc {
     int p, G;               // columns, event groups
     int nxr, nzr;           // K ranges of the two products (nzr = 0 without events)
     int npairs, ntile;      // tile pairs of the upper triangle; X beta work items
+    const double *gam;      // [p] l1 weights (0 for unpenalised columns); nullptr: an unpenalised fit
+    const double *beta0;    // [p] start point; nullptr: zeros
     double tol;
     int max_iter;
-    int freeze;             // 1: keep the factor once steps are small (reduced-precision contraction)
+    int freeze;             // 1: keep the factor (with l1: the information matrix) once steps are small
 };
 
 static_assert(sizeof(FitDesc) % 8 == 0, "descriptors are copied in 8-byte words");

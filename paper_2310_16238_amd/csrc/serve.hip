@@ -84,8 +84,9 @@ __global__ __launch_bounds__(256) void admit_kernel(FitDesc *fits, const FitDesc
     for (int64_t e = (int64_t)it.y * 256 + x; e < nz; e += stride) F.z[e] = 0.0f;
     if (it.y == 0) {
         if (x < F.p) {
-            F.beta[x] = 0.0;
-            F.prev[x] = 0.0;
+            const double b0 = F.beta0 ? F.beta0[x] : 0.0;
+            F.beta[x] = b0;
+            F.prev[x] = b0;
         }
         if (x < (int)(sizeof(FitState) / 4)) reinterpret_cast<uint32_t *>(F.st)[x] = 0u;
         uint64_t *dst = reinterpret_cast<uint64_t *>(fits + slots[it.x]);
@@ -562,6 +563,81 @@ __global__ __launch_bounds__(256) void info_kernel(const FitDesc *fits, const in
 
 constexpr int kStepThreads = 256;
 
+// The step of an l1-penalised fit (proximal Newton): the quadratic model
+//   g'D + D'HD/2 + sum_j gamma_j |beta_j + D_j|
+// (FP64 score g, information H from the info kernel, kept once frozen) minimised by cyclic
+// coordinate descent with soft thresholding (the l1 rule of Sec. 2.4) over the free columns,
+// by wave 0 with H in LDS: lane l keeps (HD)_l and (HD)_{l+64} and D_l, D_{l+64} in registers,
+// and every lane takes the same decision for coordinate j from values it reads or receives by
+// shuffle.  The model is solved to a thousandth of the last step (or of max(1, |beta|) at the
+// first), at least to 1e-3 tol.  D goes to y; s_red[w] receives the largest violation of the
+// l1 optimality conditions at the current point (wave w's columns).
+__device__ void prox_step(const FitDesc &F, double *A, double *y, const uint8_t *s_free, double *s_red, int t,
+                          int wv, int lane)
+{
+    __shared__ double s_g[kMaxP], s_b[kMaxP], s_gm[kMaxP], s_a[kMaxP];
+    const int p = F.p;
+    constexpr int kWaves = kStepThreads / kWave;
+    for (int i = wv; i < p; i += kWaves)
+        for (int j = lane; j < p; j += kWave)
+            A[i * p + j] = i >= j ? F.L[(int64_t)i * p + j] : F.L[(int64_t)j * p + i];   // lower triangle, mirrored
+    double viol = 0.0, bmax = 1.0;
+    for (int j = t; j < p; j += kStepThreads) {
+        const double g = F.grad[j], b = F.beta[j], gm = F.gam[j], a = F.L[(int64_t)j * p + j];
+        s_g[j] = g;
+        s_b[j] = b;
+        s_gm[j] = gm;
+        s_a[j] = (s_free[j] && a > 0.0) ? a : 0.0;   // 0: the coordinate stays
+        bmax = fmax(bmax, fabs(b));
+        if (!s_free[j]) continue;
+        const double r = gm <= 0.0 ? fabs(g) : (b != 0.0 ? fabs(g + (b > 0.0 ? gm : -gm)) : fmax(fabs(g) - gm, 0.0));
+        viol = fmax(viol, r);
+    }
+    viol = wave_max(viol);
+    bmax = wave_max(bmax);
+    __shared__ double s_bm[kStepThreads / kWave];
+    if (lane == 0) {
+        s_red[wv] = viol;
+        s_bm[wv] = bmax;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        const FitState *st = F.st;
+        double bm = 1.0;
+        for (int k = 0; k < kWaves; ++k) bm = fmax(bm, s_bm[k]);
+        const double tol = fmax(1e-3 * F.tol * bm, st->iters ? 1e-3 * st->last_step : 1e-3 * bm);
+        double hd0 = 0.0, hd1 = 0.0, d0 = 0.0, d1 = 0.0;
+        for (int sweep = 0; sweep < 1000; ++sweep) {
+            double change = 0.0;
+            for (int j = 0; j < p; ++j) {
+                const double a = s_a[j];
+                if (a == 0.0) continue;
+                const int src = j & (kWave - 1);
+                const double hj = __shfl(j < kWave ? hd0 : hd1, src, kWave);
+                const double dj = __shfl(j < kWave ? d0 : d1, src, kWave);
+                const double bj = s_b[j], gm = s_gm[j];
+                const double bb = s_g[j] + hj - a * dj;   // the model's slope at D with D_j removed
+                const double u = a * bj - bb;
+                const double z = u > gm ? (u - gm) / a : (u < -gm ? (u + gm) / a : 0.0);
+                const double dn = z - bj;
+                const double delta = dn - dj;
+                if (delta != 0.0) {
+                    if (lane == src) {
+                        if (j < kWave) d0 = dn;
+                        else d1 = dn;
+                    }
+                    if (lane < p) hd0 = fma(A[j * p + lane], delta, hd0);
+                    if (lane + kWave < p) hd1 = fma(A[j * p + lane + kWave], delta, hd1);
+                    change = fmax(change, fabs(delta));
+                }
+            }
+            if (change <= tol) break;
+        }
+        if (lane < p) y[lane] = d0;
+        if (lane + kWave < p) y[lane + kWave] = d1;
+    }
+}
+
 __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits, const int *slots)
 {
     extern __shared__ double lds[];   // A[p * p], y[p]
@@ -574,7 +650,8 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     double *A = lds;
     double *y = lds + (int64_t)p * p;
 
-    // per-column sums of the scan-tile partials, and the objective, in tile order
+    // per-column sums of the scan-tile partials, and the objective, in tile order; with l1
+    // weights the objective includes sum_j gamma_j |beta_j| (summed by wave 0 in column order)
     for (int j = t; j < p; j += kStepThreads) {
         double sg = 0.0, s1 = 0.0, s2 = 0.0;
         for (int q = 0; q < F.ntc; ++q) {
@@ -593,6 +670,8 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
             o += F.tpart[2 * q];
             bad = fmax(bad, F.tpart[2 * q + 1]);
         }
+        if (F.gam)
+            for (int j = 0; j < p; ++j) o += F.gam[j] * fabs(F.beta[j]);
         st->obj_eval = o;
         st->range = bad > 0.0 ? 1u : 0u;
     }
@@ -627,18 +706,36 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     }
     // the columns that move: chosen once, at the first evaluation (g'' > 1e-12 S2-term)
     if (!(st->flags & kHaveFree)) {
+        __shared__ int s_moved;
+        if (t == 0) s_moved = 0;
+        __syncthreads();
         for (int j = t; j < p; j += kStepThreads) {
             const double hd = F.diag1[j] - F.diag2[j];
-            F.free_col[j] = (hd > 1e-12 * fabs(F.diag1[j]) && isfinite(hd)) ? 1 : 0;
+            const bool fr = hd > 1e-12 * fabs(F.diag1[j]) && isfinite(hd);
+            F.free_col[j] = fr ? 1 : 0;
+            if (F.gam && !fr && F.beta[j] != 0.0) {   // l1 fits hold such columns at zero
+                F.beta[j] = 0.0;
+                F.prev[j] = 0.0;
+                s_moved = 1;
+            }
         }
         __syncthreads();
+        if (s_moved) {   // evaluate again at the start point with those columns at zero
+            if (t == 0) {
+                st->flags |= kHaveFree;
+                *F.hst = *st;
+            }
+            return;
+        }
     }
     const bool frozen = s_frozen != 0;
     const int wv = t / kWave, lane = t & (kWave - 1);
     constexpr int kWaves = kStepThreads / kWave;
     for (int j = t; j < p; j += kStepThreads) s_free[j] = F.free_col[j];
     __syncthreads();
-    if (!frozen) {
+    if (F.gam) {
+        prox_step(F, A, y, s_free, s_red, t, wv, lane);
+    } else if (!frozen) {
         // Blocked right-looking Cholesky of the information matrix (info kernel; rows and
         // columns not free become unit rows) in LDS, lower triangle, panels of 16 columns:
         // wave 0 factors the diagonal block (lane r holds its row r, columns passed by
@@ -744,41 +841,43 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
         for (int i = wv; i < p; i += kWaves)
             for (int j = lane; j < p; j += kWave) A[i * p + j] = F.L[(int64_t)i * p + j];
     }
-    // score on the free columns; kkt = max |score|
-    double kk = 0.0;
-    for (int j = t; j < p; j += kStepThreads) {
-        const double gj = s_free[j] ? F.grad[j] : 0.0;
-        y[j] = -gj;
-        kk = fmax(kk, fabs(gj));
-    }
-    kk = wave_max(kk);
-    if (lane == 0) s_red[wv] = kk;
-    __syncthreads();
-    // L y = -g, then L' dx = y, by wave 0: lane l holds entries l and l + 64
-    if (wv == 0) {
-        double y0 = lane < p ? y[lane] : 0.0, y1 = lane + kWave < p ? y[lane + kWave] : 0.0;
-        for (int k = 0; k < p; ++k) {
-            const double own = k < kWave ? y0 : y1;
-            const double yk = __shfl(own, k & (kWave - 1), kWave) / A[k * p + k];
-            if (lane == (k & (kWave - 1))) {
-                if (k < kWave) y0 = yk;
-                else y1 = yk;
-            }
-            if (lane > k && lane < p) y0 -= A[lane * p + k] * yk;
-            if (lane + kWave > k && lane + kWave < p) y1 -= A[(lane + kWave) * p + k] * yk;
+    if (!F.gam) {
+        // score on the free columns; kkt = max |score|
+        double kk = 0.0;
+        for (int j = t; j < p; j += kStepThreads) {
+            const double gj = s_free[j] ? F.grad[j] : 0.0;
+            y[j] = -gj;
+            kk = fmax(kk, fabs(gj));
         }
-        for (int k = p - 1; k >= 0; --k) {
-            const double own = k < kWave ? y0 : y1;
-            const double xk = __shfl(own, k & (kWave - 1), kWave) / A[k * p + k];
-            if (lane == (k & (kWave - 1))) {
-                if (k < kWave) y0 = xk;
-                else y1 = xk;
+        kk = wave_max(kk);
+        if (lane == 0) s_red[wv] = kk;
+        __syncthreads();
+        // L y = -g, then L' dx = y, by wave 0: lane l holds entries l and l + 64
+        if (wv == 0) {
+            double y0 = lane < p ? y[lane] : 0.0, y1 = lane + kWave < p ? y[lane + kWave] : 0.0;
+            for (int k = 0; k < p; ++k) {
+                const double own = k < kWave ? y0 : y1;
+                const double yk = __shfl(own, k & (kWave - 1), kWave) / A[k * p + k];
+                if (lane == (k & (kWave - 1))) {
+                    if (k < kWave) y0 = yk;
+                    else y1 = yk;
+                }
+                if (lane > k && lane < p) y0 -= A[lane * p + k] * yk;
+                if (lane + kWave > k && lane + kWave < p) y1 -= A[(lane + kWave) * p + k] * yk;
             }
-            if (lane < k) y0 -= A[k * p + lane] * xk;
-            if (lane + kWave < k) y1 -= A[k * p + lane + kWave] * xk;
+            for (int k = p - 1; k >= 0; --k) {
+                const double own = k < kWave ? y0 : y1;
+                const double xk = __shfl(own, k & (kWave - 1), kWave) / A[k * p + k];
+                if (lane == (k & (kWave - 1))) {
+                    if (k < kWave) y0 = xk;
+                    else y1 = xk;
+                }
+                if (lane < k) y0 -= A[k * p + lane] * xk;
+                if (lane + kWave < k) y1 -= A[k * p + lane + kWave] * xk;
+            }
+            if (lane < p) y[lane] = y0;
+            if (lane + kWave < p) y[lane + kWave] = y1;
         }
-        if (lane < p) y[lane] = y0;
-        if (lane + kWave < p) y[lane + kWave] = y1;
     }
     __syncthreads();
     double smax = 0.0, bmax = 0.0;

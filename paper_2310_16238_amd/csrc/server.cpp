@@ -103,8 +103,10 @@ struct FitLayout {
     int64_t n = 0, ld = 0, ldz = 0, tile = 0;
     int p = 0, G = 0, nxr = 0, nzr = 0, npairs = 0, ntile = 0, ntc = 0;
     bool device = false;                            // X is gathered from the caller's device memory
-    size_t meta = 0, gidx = 0, src = 0, x = 0, upload = 0;   // [0, upload) is uploaded in one copy:
-                                                    // meta, gidx, then X (host request) or src (device)
+    size_t meta = 0, gidx = 0, gam = 0, beta0 = 0, src = 0, x = 0, upload = 0;
+                                                    // [0, upload) is uploaded in one copy: meta, gidx, the
+                                                    // l1 weights and start point (p each), then X (host
+                                                    // request) or src (device)
     size_t xf = 0, rows = 0, bf = 0, z = 0, beta = 0, prev = 0;
     size_t vec = 0, free_col = 0, L = 0, part = 0, tilemax = 0, tpart = 0, cpart = 0, total = 0;
 };
@@ -166,6 +168,8 @@ FitLayout plan(int64_t n, int64_t ld, int64_t tile, int p, int64_t G, bool devic
     };
     L.meta = take(sizeof(uint32_t) * (size_t)L.ld);
     L.gidx = take(sizeof(int32_t) * (size_t)L.ld);
+    L.gam = take(sizeof(double) * p);
+    L.beta0 = take(sizeof(double) * p);
     if (device) {
         L.src = take(sizeof(int32_t) * (size_t)L.ld);
         L.upload = o;
@@ -201,6 +205,8 @@ struct Request {
     std::vector<double> own_x, own_t;
     std::vector<uint8_t> own_e;
     std::vector<int32_t> own_s;
+    std::vector<double> gam;     // [p] l1 weights; empty: an unpenalised fit
+    std::vector<double> beta0;   // [p] start point; empty: zeros
     double t_submit = 0.0;
     FitLayout lay;
     size_t stage_off = 0;
@@ -334,6 +340,11 @@ void write_image(const Request &q, const std::vector<int64_t> &perm, const std::
     for (int64_t i = 0; i < q.n; ++i) {
         mw[pos[i]] = meta[i];
         gi[pos[i]] = (meta[i] & kCountMask) ? g++ : -1;
+    }
+    double *gw = reinterpret_cast<double *>(dst + L.gam), *b0 = reinterpret_cast<double *>(dst + L.beta0);
+    for (int64_t j = 0; j < q.p; ++j) {
+        gw[j] = q.gam.empty() ? 0.0 : q.gam[(size_t)j];
+        b0[j] = q.beta0.empty() ? 0.0 : q.beta0[(size_t)j];
     }
 }
 
@@ -484,6 +495,8 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off, int slot)
     F.nzr = L.nzr;
     F.npairs = L.npairs;
     F.ntile = L.ntile;
+    F.gam = q.gam.empty() ? nullptr : reinterpret_cast<const double *>(B + L.gam);
+    F.beta0 = q.beta0.empty() ? nullptr : reinterpret_cast<const double *>(B + L.beta0);
     F.tol = s->opt.tol;
     F.max_iter = s->opt.max_iter;
     F.freeze = 1;
@@ -505,7 +518,8 @@ bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_
            in(F.prev, 8 * p) && in(F.grad, 8 * p) && in(F.diag2, 8 * p) && in(F.free_col, p) &&
            in(F.L, 8 * p * p) && in(F.part, 4 * (size_t)(L.nxr + L.nzr) * L.npairs * kTile * kTile) &&
            in(F.tilemax, 8 * (size_t)L.ntile) && in(F.tpart, 16 * (size_t)L.ntc) &&
-           in(F.cpart, 24 * (size_t)L.ntc * p) && (!L.device || (in(F.src, 4 * ld) && F.xs && F.ldxs >= L.n)) && F.tile > 0 && F.tile % kRowPad == 0 && F.ntc >= 1 &&
+           in(F.cpart, 24 * (size_t)L.ntc * p) && (!F.gam || in(F.gam, 8 * p)) && (!F.beta0 || in(F.beta0, 8 * p)) &&
+           (!L.device || (in(F.src, 4 * ld) && F.xs && F.ldxs >= L.n)) && F.tile > 0 && F.tile % kRowPad == 0 && F.ntc >= 1 &&
            F.tile * F.ntc == F.ld &&
            F.st == s->d_state + slot && F.hst == s->dh_state + slot && F.hbeta == s->dh_beta + (size_t)slot * kMaxP &&
            F.p == L.p && F.ld == L.ld &&
@@ -899,10 +913,16 @@ extern "C" int cox_server_create(cox_server **out, const cox_server_options *o)
     return COX_OK;
 }
 
-extern "C" int cox_server_submit(cox_server *s, const cox_data *d, int flags, uint64_t *ticket)
+static int submit_impl(cox_server *s, const cox_data *d, int flags, const cox_fit_request *r, uint64_t *ticket)
 {
     if (!s) return COX_EINVAL;
     if (!d || !ticket) return srv_fail(s, COX_EINVAL, "data and ticket are required");
+    if (r) {
+        if (!(r->gamma >= 0.0) || !std::isfinite(r->gamma)) return srv_fail(s, COX_EINVAL, "gamma must be finite and >= 0");
+        if (r->beta0)
+            for (int64_t j = 0; j < d->p; ++j)
+                if (!std::isfinite(r->beta0[j])) return srv_fail(s, COX_EINVAL, "beta0 must be finite");
+    }
     if (flags & ~(COX_SUBMIT_BORROW | COX_SUBMIT_DEVICE)) return srv_fail(s, COX_EINVAL, "unknown submit flags");
     const bool dev = (flags & COX_SUBMIT_DEVICE) != 0 || d->on_device;
     if (dev) {
@@ -929,6 +949,12 @@ extern "C" int cox_server_submit(cox_server *s, const cox_data *d, int flags, ui
     std::unique_ptr<Request> q(new Request());
     q->n = d->n;
     q->p = d->p;
+    if (r && r->gamma > 0.0) {
+        q->gam.assign((size_t)d->p, r->gamma);
+        if (r->penalize)
+            for (int64_t j = 0; j < d->p; ++j) q->gam[(size_t)j] = r->penalize[j] ? r->gamma : 0.0;
+    }
+    if (r && r->beta0) q->beta0.assign(r->beta0, r->beta0 + d->p);
     if (dev) {
         q->device = true;
         q->x = d->x;
@@ -972,6 +998,17 @@ extern "C" int cox_server_submit(cox_server *s, const cox_data *d, int flags, ui
     }
     s->cv_prep.notify_one();
     return COX_OK;
+}
+
+extern "C" int cox_server_submit(cox_server *s, const cox_data *d, int flags, uint64_t *ticket)
+{
+    return submit_impl(s, d, flags, nullptr, ticket);
+}
+
+extern "C" int cox_server_submit_fit(cox_server *s, const cox_data *d, int flags, const cox_fit_request *r,
+                                     uint64_t *ticket)
+{
+    return submit_impl(s, d, flags, r, ticket);
 }
 
 extern "C" int cox_server_poll(cox_server *s, uint64_t ticket, double *beta_out, cox_fit_info *info,

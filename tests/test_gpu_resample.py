@@ -128,6 +128,39 @@ def test_cross_validation_matches_oracle():
     assert int(np.argmax(cvl)) == int(np.argmax(rcvl))
 
 
+def test_cross_validation_through_the_server():
+    """The same l1 path with the fold fits batched through a fit server (every fold of one weight
+    in one batch, warm-started from the previous weight): fold estimates at the oracle's to 1e-10
+    with the same zero patterns, and the criterion within the same bound as above."""
+    d = synth.make("binary", 40_000, 30, 20, 25, beta_sd=1.0, beta_nonzero=0.3, density=0.1, tie_round=50.0)
+    fold = np.random.default_rng(9).integers(0, 5, d.time.shape[0]).astype(np.int32)
+    gammas = np.array([60.0, 20.0, 6.0, 2.0, 0.5])
+    pen = np.ones(30, np.uint8)
+    pen[0] = 0
+    _say("cross-validation through the server: 5 folds x 5 gammas, n=40000 p=30")
+    with coxmi.CoxServer(hbm_budget=1 << 30, staging_bytes=256 << 20, prep_threads=4) as srv:
+        with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, tol=1e-13) as m:
+            cvl, betas, status = m.cross_validate_served(srv, d.X, d.time, d.event, d.stratum, fold, gammas, pen)
+            with pytest.raises(coxmi.CoxError) as e:   # data of another shape than the handle's
+                m.cross_validate_served(srv, d.X[:, :5], d.time, d.event, d.stratum, fold, gammas, pen[:5])
+            assert e.value.code == coxmi.COX_EINVAL
+    rcvl, rbetas, rconv = orc.cross_validate(d.X, d.time, d.event, d.stratum, fold, gammas, pen, tol=1e-13)
+    assert rconv.all() and np.all(status == coxmi.COX_OK)
+    worst = 0.0
+    for k in range(5):
+        for g in range(len(gammas)):
+            assert np.array_equal(betas[k, g] == 0.0, rbetas[k, g] == 0.0), (k, g)
+            err = _rel(betas[k, g], rbetas[k, g])
+            assert err <= 1e-10, (k, g, err)
+            worst = max(worst, err)
+    nll_all = orc.neg_loglik(d.X, d.time, d.event, d.stratum, np.zeros(30))
+    scale = 2.0 * 5 * abs(nll_all)
+    err = float(np.max(np.abs(cvl - rcvl)))
+    _say(f"  worst fold rel err {worst:.2e}; max |cvl - oracle| {err:.3e} (bound {1e-11 * scale:.3e})")
+    assert err <= 1e-11 * scale
+    assert int(np.argmax(cvl)) == int(np.argmax(rcvl))
+
+
 def test_bootstrap_matches_oracle():
     d = synth.make("iid", 15_000, 8, 15, 27, beta_sd=0.5, tie_round=100.0)
     n = d.time.shape[0]

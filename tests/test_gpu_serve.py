@@ -261,3 +261,61 @@ def test_bootstrap_through_the_server():
         Xr, tr, er, sr = orc.resample(d.X, d.time, d.event, d.stratum, counts[b])
         ref = orc.fit_newton(Xr, tr, er, sr, tol=1e-14)
         assert np.max(np.abs(betas[b] - ref.beta)) <= 1e-10 * np.max(np.abs(ref.beta))
+
+
+def _l1_weight(d, share=0.2):
+    L = orc.canonical_layout(d.time, d.event, d.stratum)
+    g0 = orc.full_eval(orc.to_canonical(d.X, L), L, np.zeros(d.p), want_info=False).grad
+    return share * float(np.max(np.abs(g0[1:])))
+
+
+def test_l1_fits_through_the_server():
+    """l1-penalised requests (cox_server_submit_fit: proximal Newton steps, the quadratic model
+    solved on the device) served beside unpenalised ones: every penalised fit at the oracle's
+    CCD optimum of the same objective to 1e-10 with the same zero pattern, the unpenalised
+    ones at the oracle's Newton fit; a warm start from another weight's solution reaches the
+    same optimum as a cold start."""
+    reqs = _requests(8, seed=11, n_range=(500, 8_000), p_range=(4, 40))
+    gam = [_l1_weight(d) for d in reqs]
+    _say(f"l1 through the server: {len(reqs)} requests, p in [{min(d.p for d in reqs)}, {max(d.p for d in reqs)}]")
+    with coxmi.CoxServer(hbm_budget=1 << 30, staging_bytes=256 << 20, prep_threads=4) as srv:
+        t_l1 = [srv.submit(d.X, d.time, d.event, d.stratum, gamma=g) for d, g in zip(reqs, gam)]
+        t_plain = [srv.submit(d.X, d.time, d.event, d.stratum) for d in reqs[:3]]
+        assert srv.drain(timeout=120.0)
+        l1 = [srv.poll(t) for t in t_l1]
+        plain = [srv.poll(t) for t in t_plain]
+        t_warm = [srv.submit(d.X, d.time, d.event, d.stratum, gamma=0.5 * g, beta0=r[0])
+                  for d, g, r in zip(reqs, gam, l1)]
+        t_cold = [srv.submit(d.X, d.time, d.event, d.stratum, gamma=0.5 * g) for d, g in zip(reqs, gam)]
+        assert srv.drain(timeout=120.0)
+        warm = [srv.poll(t) for t in t_warm]
+        cold = [srv.poll(t) for t in t_cold]
+    worst = 0.0
+    for k, d in enumerate(reqs):
+        for g, (beta, info, _) in ((gam[k], l1[k]), (0.5 * gam[k], warm[k]), (0.5 * gam[k], cold[k])):
+            ref = orc.fit_ccd(d.X, d.time, d.event, d.stratum, gamma=g, tol=1e-14, max_sweeps=5000)
+            assert ref.converged and info["status"] == coxmi.COX_OK, (d.name, info)
+            assert np.array_equal(beta == 0.0, ref.beta == 0.0), d.name
+            err = _rel(beta, ref.beta)
+            assert err <= 1e-10, (d.name, g, err)
+            L = orc.canonical_layout(d.time, d.event, d.stratum)
+            fobj = orc.full_eval(orc.to_canonical(d.X, L), L, ref.beta, want_info=False).objective
+            fobj += g * float(np.sum(np.abs(ref.beta)))   # the penalised objective at the optimum
+            assert abs(info["objective"] - fobj) <= 1e-10 * abs(fobj), (d.name, info["objective"], fobj)
+            assert info["kkt_inf"] <= 1e-6 * max(1.0, float(d.event.sum())), (d.name, info["kkt_inf"])
+            worst = max(worst, err)
+        assert np.count_nonzero(l1[k][0]) < d.p - 1, d.name   # the weight leaves some columns at zero
+    for k in range(3):
+        _check_against_oracle(reqs[k], plain[k][0], plain[k][1])
+    _say(f"  worst rel err {worst:.2e}")
+
+
+def test_l1_submission_errors():
+    d = _requests(1, seed=12, n_range=(500, 600), p_range=(3, 3))[0]
+    with coxmi.CoxServer(hbm_budget=1 << 28, staging_bytes=64 << 20, prep_threads=1) as srv:
+        for bad in (dict(gamma=-1.0), dict(gamma=float("nan")), dict(gamma=1.0, beta0=np.array([0.0, np.nan, 0.0]))):
+            with pytest.raises(coxmi.CoxError) as e:
+                srv.submit(d.X, d.time, d.event, d.stratum, **bad)
+            assert e.value.code == coxmi.COX_EINVAL
+        with pytest.raises(ValueError):
+            srv.submit(d.X, d.time, d.event, d.stratum, gamma=1.0, penalize=np.ones(2, np.uint8))
