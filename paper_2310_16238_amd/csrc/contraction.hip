@@ -117,37 +117,43 @@ __global__ __launch_bounds__(kSyrkThreads) void syrk_f64_kernel(const double *u,
         for (int bb = 0; bb < 4; ++bb) out[(ty * 4 + a) * kTile + tx * 4 + bb] = acc[a][bb];
 }
 
-// FP64 on the matrix cores (v_mfma_f64_16x16x4_f64), for p <= 256: per K chunk of kF64KC
+// FP64 on the matrix cores (v_mfma_f64_16x16x4_f64), for p <= 512: per K chunk of kF64KC
 // rows the workgroup stages every row of u once in LDS (FP64, as stored); its 8 waves own
-// the 16 x 16 blocks (bi <= bj) of the upper triangle in turn (block q to wave q mod 8) and
-// run them from LDS, the A operand multiplied by c_k as it is read.  An MFMA step takes
-// 4 K values: lane l supplies A[bi*16 + l%16][k + l/16] and B[bj*16 + l%16][k + l/16] and
-// holds D[l/16 + 4 r][l%16], r = 0..3, of its block (rows interleaved by 4).  The partials go to the 64 x 64
-// tile-pair layout of syrk_f64_kernel (blocks below the diagonal of a diagonal tile are
-// never written, and syrk_reduce_kernel never reads them).
+// 16 x 16 blocks (bi <= bj) of the upper triangle in turn (block q of the workgroup's group
+// to wave q mod 8) and run them from LDS, the A operand multiplied by c_k as it is read.  A
+// group holds up to kF64Group blocks (p <= 256: all of them; beyond, the groups of one K range
+// run on one XCD, see split_group).  An MFMA step takes 4 K values: lane l supplies
+// A[bi*16 + l%16][k + l/16] and B[bj*16 + l%16][k + l/16] and holds D[l/16 + 4 r][l%16],
+// r = 0..3, of its block (rows interleaved by 4).  The partials go to the 64 x 64 tile-pair
+// layout of syrk_f64_kernel (blocks below the diagonal of a diagonal tile are never
+// written, and syrk_reduce_kernel never reads them).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-constexpr int kF64Waves = 8, kF64KC = 32, kF64MaxBlk = 16;   // 16 blocks of 16 rows: p <= 256
-constexpr int kF64PerWave = (kF64MaxBlk * (kF64MaxBlk + 1) / 2 + kF64Waves - 1) / kF64Waves;   // 17
+constexpr int kF64Waves = 8, kF64KC = 32;
+constexpr int kF64PerWave = 17, kF64Group = kF64Waves * kF64PerWave;   // 136 = all blocks at p <= 256
 
+// MAXB: the most 16-row blocks (16: p <= 256, staged rows 256 x 33 doubles; 32: p <= 512, 135 KB)
+template <int MAXB>
 __global__ __launch_bounds__(64 * kF64Waves, 1) void syrk_f64_mfma_kernel(const double *u, int64_t ldu, int p,
                                                                          const double *c, int64_t K,
                                                                          int64_t kchunk, double *part)
 {
-    __shared__ double xs[kF64MaxBlk * 16][kF64KC + 1];
+    __shared__ double xs[MAXB * 16][kF64KC + 1];
     __shared__ double cs[kF64KC];
     const int nb = (p + 15) / 16;
     const int nblk = nb * (nb + 1) / 2;
     const int nt = (p + kTile - 1) / kTile;
     const int npairs = nt * (nt + 1) / 2;
     const int lane = threadIdx.x & 63, w = threadIdx.x / 64;
-    const int s = blockIdx.x;
+    int s, grp;
+    split_group(s, grp);
+    const int q0 = grp * kF64Group;
     const int64_t k0 = (int64_t)s * kchunk;
     const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
     int bi[kF64PerWave], bj[kF64PerWave];
     f64x4 acc[kF64PerWave];
 #pragma unroll
     for (int m = 0; m < kF64PerWave; ++m) {
-        const int q = w + kF64Waves * m;
+        const int q = q0 + w + kF64Waves * m;
         int i = 0, rem = q < nblk ? q : 0;
         while (rem >= nb - i) {
             rem -= nb - i;
@@ -174,7 +180,7 @@ __global__ __launch_bounds__(64 * kF64Waves, 1) void syrk_f64_mfma_kernel(const 
             const double ck = cs[kk];
 #pragma unroll
             for (int m = 0; m < kF64PerWave; ++m) {
-                if (w + kF64Waves * m < nblk) {
+                if (q0 + w + kF64Waves * m < nblk) {
                     const double a = xs[bi[m] * 16 + r16][kk] * ck;
                     const double b = xs[bj[m] * 16 + r16][kk];
                     acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[m], 0, 0, 0);
@@ -185,7 +191,7 @@ __global__ __launch_bounds__(64 * kF64Waves, 1) void syrk_f64_mfma_kernel(const 
     }
 #pragma unroll
     for (int m = 0; m < kF64PerWave; ++m) {
-        if (w + kF64Waves * m < nblk) {
+        if (q0 + w + kF64Waves * m < nblk) {
             const int ti = bi[m] / 4, tj = bj[m] / 4;
             const int pair = ti * nt - ti * (ti - 1) / 2 + (tj - ti);
             double *out = part + ((int64_t)s * npairs + pair) * (kTile * kTile);
@@ -1238,16 +1244,19 @@ int syrk_f64(const double *u, int64_t ldu, int p, const double *c, int64_t K, in
     const int nt = (p + kTile - 1) / kTile;
     const int npairs = nt * (nt + 1) / 2;
     int64_t kchunk = (K + splits - 1) / splits;
-    if (p <= kF64MaxBlk * 16) {
-        // matrix cores, every row of u staged once per K chunk
-        // 2 * splits workgroups, fewer when K is short (at least 4 chunks each): the reduction
-        // reads every split's tiles
-        int s2 = 2 * splits;
+    if (p <= 512) {
+        // matrix cores, every row of u staged once per K chunk: 2 * splits K ranges at p <= 256
+        // (one group of blocks), splits ranges of 4 groups beyond; fewer ranges when K is short
+        // (at least 4 chunks each), the reduction reading every range's tiles
+        const int nb = (p + 15) / 16, ngroups = (nb * (nb + 1) / 2 + kF64Group - 1) / kF64Group;
+        int s2 = p <= 256 ? 2 * splits : splits;
         const int64_t most = (K + 4 * kF64KC - 1) / (4 * kF64KC);
         if (most < s2) s2 = most > 1 ? (int)most : 1;
+        if (ngroups > 1 && s2 >= 8) s2 = s2 / 8 * 8;   // whole groups of 8 ranges: one XCD runs all groups of a range
         kchunk = (K + s2 - 1) / s2;
         kchunk = (kchunk + kF64KC - 1) / kF64KC * kF64KC;
-        syrk_f64_mfma_kernel<<<s2, 64 * kF64Waves, 0, stream>>>(u, ldu, p, c, K, kchunk, part);
+        if (p <= 256) syrk_f64_mfma_kernel<16><<<dim3(s2, ngroups), 64 * kF64Waves, 0, stream>>>(u, ldu, p, c, K, kchunk, part);
+        else syrk_f64_mfma_kernel<32><<<dim3(s2, ngroups), 64 * kF64Waves, 0, stream>>>(u, ldu, p, c, K, kchunk, part);
         syrk_reduce_kernel<<<dim3(npairs, kTile * kTile / 64), 64 * kRedWaves, 0, stream>>>(part, p, s2, sign,
                                                                                            accumulate, C);
         return hipGetLastError() == hipSuccess ? 0 : -3;

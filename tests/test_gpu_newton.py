@@ -127,6 +127,24 @@ def test_full_evaluation_f64(name, make):
     assert np.all(np.abs(np.diag(info) - hd) <= _first_order_tols(d.X, float(d.event.sum()))[1])
 
 
+@pytest.mark.parametrize("n,p,K", [(20_011, 300, 13), (12_003, 512, 1), (9_001, 257, 40)])
+def test_full_evaluation_f64_wide(n, p, K):
+    """FP64 information beyond 256 columns on the matrix cores: several groups of 16 x 16 blocks
+    per K range (each staging every row of its chunk), at the 512-column limit and one column
+    past a block; the same bound as the narrow FP64 case."""
+    d = _mixed(n, p, K, 7)
+    beta = _beta_probe(d)
+    _say(f"evaluate_full F64 wide n={n} p={p}")
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, mode=coxmi.COX_NEWTON_REFINE) as m:
+        obj, g, hd, info = m.evaluate_full(beta)
+    fe = _oracle_eval(d, beta)
+    _check_first_order(d, obj, g, hd, fe)
+    r = _scale(fe)
+    err = np.abs(info - fe.info)
+    assert np.all(err <= 1e-11 * r), float(np.max(err / r))
+    assert np.array_equal(info, info.T)
+
+
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_information_bf16_within_bound(name, make):
     d = make()
