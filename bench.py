@@ -648,15 +648,22 @@ def run_sparse(args):
     nnz = int(d.row_idx.size)
     pen = np.ones(p, np.uint8)
     pen[0] = 0
+    vals = None
+    if args.sparse_values:   # general sparse X: the same pattern with N(0, 1/4) values (seeded)
+        vals = np.random.default_rng(19).normal(0.0, 0.5, nnz)
     t0 = time.perf_counter()
-    m = coxmi.CoxModel.indicator(n, d.col_ptr, d.row_idx, d.time, d.event, d.stratum, gamma=0.0, penalize=pen,
-                                 tol=1e-12)
+    if vals is None:
+        m = coxmi.CoxModel.indicator(n, d.col_ptr, d.row_idx, d.time, d.event, d.stratum, gamma=0.0,
+                                     penalize=pen, tol=1e-12)
+    else:
+        m = coxmi.CoxModel.sparse(n, d.col_ptr, d.row_idx, vals, d.time, d.event, d.stratum, gamma=0.0,
+                                  penalize=pen, tol=1e-12)
     init_s = time.perf_counter() - t0
     _, g0, _ = m.evaluate(np.zeros(p))
     gmax = float(np.max(np.abs(g0[pen == 1])))
     gamma = 0.02 * gmax
     m.set_penalty(gamma, pen)
-    log(f"cox_init_indicator {init_s:.1f} s ({nnz} ones); gamma = 0.02 gamma_max = {gamma:.2f}")
+    log(f"cox_init ({'indicator' if vals is None else 'sparse'} X) {init_s:.1f} s ({nnz} nonzeros); gamma = 0.02 gamma_max = {gamma:.2f}")
     beta, info = m.fit()   # warm
     torch.cuda.synchronize()
     lat, kms = [], []
@@ -674,37 +681,46 @@ def run_sparse(args):
     from oracle import cox_oracle as orc
     lay = orc.canonical_layout(d.time, d.event, d.stratum)
     eta = np.zeros(n)
+
+    def colvals(j):
+        seg = slice(d.col_ptr[j], d.col_ptr[j + 1])
+        return 1.0 if vals is None else vals[seg]
+
     for j in nzb:
-        eta[d.row_idx[d.col_ptr[j]:d.col_ptr[j + 1]]] += beta[j]
+        eta[d.row_idx[d.col_ptr[j]:d.col_ptr[j + 1]]] += beta[j] * colvals(j)
     eta = np.ascontiguousarray(eta[lay.perm])
     E = float(d.event.sum())
     cols = sorted(set([0] + list(nzb[:4]) + list(np.flatnonzero(beta == 0.0)[:4]) + [p - 1]))
     worst = 0.0
     for j in cols:
         xj = np.zeros((n, 1))
-        xj[d.row_idx[d.col_ptr[j]:d.col_ptr[j + 1]], 0] = 1.0
+        xj[d.row_idx[d.col_ptr[j]:d.col_ptr[j + 1]], 0] = colvals(j)
         g = orc.coord_terms(orc.to_canonical(xj, lay), lay, 0, eta)["grad"]
         gj = gamma * pen[j]
         r = abs(g) if gj == 0.0 else (abs(g + gj * np.sign(beta[j])) if beta[j] != 0.0 else max(abs(g) - gj, 0.0))
         worst = max(worst, r / E)
     log(f"oracle l1 optimality residual on columns {cols}: max / E = {worst:.2e}")
     kernel_s = float(np.median(kms)) / 1e3
-    bytes_per_launch = n / 8.0 * evals + 4.0 * n
+    # per coordinate: the column's bits, and with values its nonzeros (average nnz / p) and wave offsets
+    per_coord = n / 8.0 + (0.0 if vals is None else 8.0 * nnz / p + 4.0 * n / 512.0)
+    bytes_per_launch = per_coord * evals + 4.0 * n
     achieved = bytes_per_launch / kernel_s / 1e9
     out = {
         "metric": METRIC, "value": n * evals / T, "unit": "obs-evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * T,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (indicator X, 1 bit per row)", "data": "synthetic",
-        "config": {"workload": f"Sec. 3.2 at full width: N={n} rows, P={p} indicator covariates (3% ones, {nnz} "
-                               f"ones), K=10 strata, l1 CCD fit to 1e-12 at gamma = 0.02 gamma_max, column 0 "
-                               f"unpenalised, seed 9"},
+        "dtype": "f64 (indicator X, 1 bit per row)" if vals is None else "f64 (sparse X: bits + FP64 values)",
+        "data": "synthetic",
+        "config": {"workload": f"Sec. 3.2 at full width: N={n} rows, P={p} "
+                               + ("indicator covariates" if vals is None else "sparse covariates with N(0, 1/4) values")
+                               + f" (3% nonzero, {nnz} nonzeros), K=10 strata, l1 CCD fit to 1e-12 at gamma = 0.02 "
+                               f"gamma_max, column 0 unpenalised, seed 9"},
         "fit_s": T, "init_s": init_s, "sweeps": int(info["iters"]), "nonzero": int(nzb.size),
         "us_per_coordinate": 1e6 * kernel_s / max(evals, 1), "oracle_l1_residual_over_E": worst,
         "paper_context": "the paper's LEGEND-HTN data have this shape (946,911 x 9,977, 97% sparse)",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "ccd_kernel (persistent, indicator X)",
+                     "kernel": "ccd_kernel (persistent, " + ("indicator" if vals is None else "sparse") + " X)",
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": None,
     }
@@ -1287,6 +1303,8 @@ def main():
     ap.add_argument("--cough-cv", type=int, default=0, help="cough: folds of a cross-validation (0: none)")
     ap.add_argument("--sparse-n", type=int, default=946_911, help="sparse: rows")
     ap.add_argument("--sparse-p", type=int, default=9977, help="sparse: indicator columns")
+    ap.add_argument("--sparse-values", action="store_true",
+                    help="sparse: general sparse X (the same pattern with N(0, 1/4) values, cox_init_sparse)")
     ap.add_argument("--cv-n", type=int, default=946_911, help="cv: rows")
     ap.add_argument("--cv-p", type=int, default=1000, help="cv: columns")
     ap.add_argument("--cv-folds", type=int, default=10, help="cv: folds")

@@ -91,6 +91,11 @@ typedef struct {
     double kkt_inf;           /* max_j of the l1 KKT residual from the last sweep's gradients */
     double last_step;         /* largest |step| of the last sweep */
     int n_pinned;             /* columns skipped as degenerate (g'' numerically 0) in the last sweep */
+    int fallback;             /* 1: a COX_CCD fit whose X beta left the range one shift per fit can hold in
+                                 FP64 (the persistent kernel's exp(x'beta - c)) was finished by (proximal)
+                                 Newton steps on the full evaluation, whose running-maximum scans hold any
+                                 range -- the same optimum; iters and coord_evals then count Newton steps
+                                 and full evaluations */
 } cox_fit_info;
 
 /* Fill *o with defaults: gamma 0, all columns penalised, COX_CCD, COX_F64,
@@ -144,13 +149,17 @@ int cox_init(cox_handle **out, const cox_data *d, const cox_options *o);
  * the step is below tol * max(1, max|beta|).  A step that raises the objective
  * is halved.  With l1 weights (gamma != 0) the steps are proximal Newton steps:
  * the quadratic model g'D + D'ID/2 plus the l1 term is minimised by coordinate
- * descent with soft thresholding on the host (I copied from the device), and the
- * penalised objective decides the halving; the fixed point meets the l1
+ * descent with soft thresholding on the device (one wave, I where the contraction
+ * left it), and the penalised objective decides the halving; the fixed point meets the l1
  * optimality conditions on the FP64 score, so a reduced-precision I (kept once
  * steps are small) still gives the FP64 optimum.
+ * In mode COX_CCD, when an event's risk-set sum under- or overflows FP64 after the
+ * persistent kernel's single shift of X beta, the fit is finished by (proximal)
+ * Newton steps on the full evaluation, whose running-maximum scans hold any range
+ * (the same optimum; info->fallback = 1).
  * Returns COX_OK, COX_NOT_CONVERGED (max_iter sweeps done; beta_out filled),
- * COX_ENUMERIC (an event's risk-set sum under- or overflowed FP64 after the
- * global shift of X beta), COX_EDEVICE.
+ * COX_ENUMERIC (out of range on a handle of indicator X, which has no full
+ * evaluation, or in the full evaluation itself), COX_EDEVICE.
  */
 int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *info);
 
@@ -160,7 +169,8 @@ int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox_fit_info *
  * the unpenalised part (Eq. strat_g, grad: host p, may be NULL) and the
  * diagonal of its Hessian (Eq. strat_h, hess_diag: host p, may be NULL).
  * Each column is one segmented-scan evaluation, as inside a CCD sweep but
- * without moving beta.
+ * without moving beta.  Beyond the single shift's FP64 range the values come from
+ * cox_evaluate_full (dense X; indicator X returns COX_ENUMERIC).
  */
 int cox_evaluate(cox_handle *h, const double *beta, double *objective, double *grad,
                  double *hess_diag);
@@ -269,6 +279,30 @@ void cox_intervals_release(cox_intervals *s);
  * n beyond the resident kernel), COX_ENOMEM, COX_EDEVICE. */
 int cox_init_indicator(cox_handle **out, int64_t n, int64_t p, const int64_t *col_ptr, const int32_t *row_idx,
                        const double *time, const uint8_t *event, const int32_t *stratum, const cox_options *o);
+
+/* ---------------------------------------------------------------- sparse X
+ * General sparse covariates (Sec. 2.7: the kernels need the nonzeros of x_j only), given
+ * as compressed sparse columns with values.  The handle stores the indicator bits of the
+ * nonzero rows (as cox_init_indicator) and the nonzero values in device-row order, with
+ * per-wave offsets; the persistent CCD kernel reads a thread's bits, finds its values by
+ * a prefix sum of bit counts across the wave, and forms every product from the values
+ * themselves, so fits equal those on the same X stored dense, bit for bit.  Storage:
+ * n/8 bytes per column + 8 bytes per nonzero (+ 4 bytes per 64 threads' rows per column).
+ *   n, p     : rows and columns (1 <= n <= 2^29 - 1, 1 <= p <= 12288)
+ *   col_ptr  : host, p + 1 non-decreasing offsets into row_idx and values, col_ptr[0] = 0
+ *   row_idx  : host, col_ptr[p] row indices in [0, n), distinct within a column (order free)
+ *   values   : host, col_ptr[p] finite values (explicit zeros are dropped)
+ *   time, event, stratum : as in cox_data
+ *   o        : options (mode COX_CCD, x_precision COX_F64; NULL = defaults)
+ * The handle runs cox_fit (COX_CCD), cox_evaluate, cox_coordinate, cox_set_penalty and the
+ * bookkeeping calls; cox_init_resample, cox_init_intervals (and so cross-validation and
+ * bootstrap), cox_evaluate_full, cox_baseline_hazard and Newton fits return
+ * COX_EUNSUPPORTED, as does the range fallback of cox_fit (COX_ENUMERIC stays).
+ * Errors: COX_EINVAL (bad arrays, a repeated row in a column), COX_EUNSUPPORTED (sizes,
+ * options, n beyond the resident kernel), COX_ENOMEM, COX_EDEVICE. */
+int cox_init_sparse(cox_handle **out, int64_t n, int64_t p, const int64_t *col_ptr, const int32_t *row_idx,
+                    const double *values, const double *time, const uint8_t *event, const int32_t *stratum,
+                    const cox_options *o);
 
 /* ---------------------------------------------------------------- resampling, CV, bootstrap
  * Sec. 2.1 chooses the common l1 weight gamma by cross-validation; Sec. 3.2 adds

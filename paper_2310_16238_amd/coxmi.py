@@ -64,7 +64,7 @@ class cox_options(ctypes.Structure):
 class cox_fit_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("coord_evals", ctypes.c_int64),
                 ("objective", ctypes.c_double), ("kkt_inf", ctypes.c_double),
-                ("last_step", ctypes.c_double), ("n_pinned", ctypes.c_int)]
+                ("last_step", ctypes.c_double), ("n_pinned", ctypes.c_int), ("fallback", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -147,6 +147,10 @@ SIGNATURES = [
                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), _DP,
                                           ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(cox_options)]),
+    ("cox_init_sparse", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), _DP, _DP,
+                                       ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(cox_options)]),
     ("cox_init_resample", ctypes.c_int, [ctypes.POINTER(_VP), _VP, ctypes.POINTER(ctypes.c_uint32),
                                          ctypes.POINTER(cox_options)]),
     ("cox_init_intervals", ctypes.c_int, [ctypes.POINTER(_VP), _VP, _DP, ctypes.POINTER(ctypes.c_uint8),
@@ -336,6 +340,37 @@ def cox_init_indicator(n, col_ptr, row_idx, time, event, stratum=None, *, gamma=
                                   event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                   None if st is None else st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                   ctypes.byref(o))
+    _check(None, rc)
+    return h.value
+
+
+def cox_init_sparse(n, col_ptr, row_idx, values, time, event, stratum=None, *, gamma=0.0, penalize=None,
+                    tol=1e-12, max_iter=1000, stream=None, ties=COX_BRESLOW):
+    """A handle on sparse X given as compressed sparse columns with values: column j holds
+    values[col_ptr[j]:col_ptr[j + 1]] at rows row_idx[col_ptr[j]:col_ptr[j + 1]] and 0
+    elsewhere (cox_init_sparse)."""
+    cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+    ri = np.ascontiguousarray(row_idx, dtype=np.int32)
+    va = np.ascontiguousarray(values, dtype=np.float64)
+    p = cp.shape[0] - 1
+    if ri.shape != va.shape:
+        raise ValueError("row_idx and values need the same length")
+    time = np.ascontiguousarray(time, dtype=np.float64)
+    event = np.ascontiguousarray(event, dtype=np.uint8)
+    if time.shape != (n,) or event.shape != (n,):
+        raise ValueError(f"time and event need {n} entries")
+    keep = [cp, ri, va, time, event]
+    st = None
+    if stratum is not None:
+        st = np.ascontiguousarray(stratum, dtype=np.int32)
+        keep.append(st)
+    o = _options(gamma, penalize, tol, max_iter, stream, COX_CCD, COX_F64, keep, ties)
+    h = ctypes.c_void_p()
+    rc = lib().cox_init_sparse(ctypes.byref(h), int(n), int(p), cp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               ri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dptr(va), _dptr(time),
+                               event.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                               None if st is None else st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               ctypes.byref(o))
     _check(None, rc)
     return h.value
 
@@ -654,6 +689,14 @@ class CoxModel:
         """A CoxModel on device-resident torch tensors (see cox_init_device)."""
         m = cls.__new__(cls)
         m.h = cox_init_device(X, time, event, stratum, **opts)
+        _live.add(m)
+        return m
+
+    @classmethod
+    def sparse(cls, n, col_ptr, row_idx, values, time, event, stratum=None, **opts):
+        """A CoxModel on sparse X in compressed sparse columns with values (see cox_init_sparse)."""
+        m = cls.__new__(cls)
+        m.h = cox_init_sparse(n, col_ptr, row_idx, values, time, event, stratum, **opts)
         _live.add(m)
         return m
 

@@ -153,15 +153,19 @@ __device__ __forceinline__ void load_words(uint32_t (&v)[IPT], const uint32_t *p
     }
 }
 
-// One column's values at a thread's IPT rows.  Dense: IPT doubles from the
-// column-major X.  Indicator (BITS): one bit per row, a thread's IPT bits in one
-// unit (uint8 for IPT <= 8, uint16 for 16) at xbits[j * ldb + thread]; the value is
-// 0.0 or 1.0, so every product formed with it equals the dense one exactly.
-template <int IPT, bool BITS>
+// One column's values at a thread's IPT rows (XK, the kind of X).  Dense (0): IPT doubles
+// from the column-major X.  Indicator (1): one bit per row, a thread's IPT bits in one unit
+// (uint8 for IPT <= 8, uint16 for 16) at xbits[j * ldb + thread]; the value is 0.0 or 1.0,
+// so every product formed with it equals the dense one exactly.  Sparse values (2): the
+// same bits mark the nonzero rows, whose values lie in row order in xvals from xvoff[j];
+// a wave's first one is at woff[j * nwaves + wave], a lane's after the nonzeros of the
+// lanes below it (a prefix sum of bit counts across the wave) -- the values themselves,
+// so every product again equals the dense one.
+template <int IPT, int XK>
 struct XCol;
 
 template <int IPT>
-struct XCol<IPT, false> {
+struct XCol<IPT, 0> {
     double v[IPT];
     __device__ __forceinline__ void load(const CcdLaunch &L, int64_t ld, int64_t j, int64_t row0, int64_t)
     {
@@ -171,7 +175,7 @@ struct XCol<IPT, false> {
 };
 
 template <int IPT>
-struct XCol<IPT, true> {
+struct XCol<IPT, 1> {
     using Unit = typename std::conditional<(IPT > 8), uint16_t, uint8_t>::type;
     uint32_t bits;
     __device__ __forceinline__ void load(const CcdLaunch &L, int64_t, int64_t j, int64_t, int64_t tg)
@@ -179,6 +183,32 @@ struct XCol<IPT, true> {
         bits = static_cast<const Unit *>(L.xbits)[j * L.ldb + tg];
     }
     __device__ __forceinline__ double operator[](int i) const { return ((bits >> i) & 1u) ? 1.0 : 0.0; }
+};
+
+template <int IPT>
+struct XCol<IPT, 2> {
+    using Unit = typename std::conditional<(IPT > 8), uint16_t, uint8_t>::type;
+    double v[IPT];
+    // called by every lane of the wave (the prefix sum below is across the whole wave)
+    __device__ __forceinline__ void load(const CcdLaunch &L, int64_t, int64_t j, int64_t, int64_t tg)
+    {
+        const uint32_t bits = static_cast<const Unit *>(L.xbits)[j * L.ldb + tg];
+        const int lane = (int)(threadIdx.x & (kWave - 1));
+        const int cnt = __popc(bits);
+        int incl = cnt;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int up = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += up;
+        }
+        const double *src = L.xvals + L.xvoff[j] + L.woff[j * L.nwaves + tg / kWave] + (incl - cnt);
+#pragma unroll
+        for (int i = 0; i < IPT; ++i) {
+            const uint32_t below = bits & ((1u << i) - 1u);
+            v[i] = ((bits >> i) & 1u) ? src[__popc(below)] : 0.0;
+        }
+    }
+    __device__ __forceinline__ double operator[](int i) const { return v[i]; }
 };
 
 __device__ __forceinline__ Partial partial_identity()
@@ -471,9 +501,9 @@ __device__ __forceinline__ RowVal<EFRON> row_value(uint32_t m, double w, double 
 // Pass 2 over a thread's rows: the inclusive prefixes from the thread's exclusive prefix
 // `run`, the group-end terms, the largest X beta over real rows, and (WANT_OBJ, the first
 // coordinate of a sweep) the objective's parts.
-template <int IPT, bool BITS, bool EFRON, bool WANT_OBJ>
+template <int IPT, int XK, bool EFRON, bool WANT_OBJ>
 __device__ __forceinline__ Partial pass2(RowVal<EFRON> run, const uint32_t (&meta)[IPT], const double (&wv)[IPT],
-                                         const XCol<IPT, BITS> &xc, const double (&eta)[IPT], double c)
+                                         const XCol<IPT, XK> &xc, const double (&eta)[IPT], double c)
 {
     Partial v = partial_identity();
 #pragma unroll
@@ -499,7 +529,7 @@ __device__ __forceinline__ Partial pass2(RowVal<EFRON> run, const uint32_t (&met
 
 // WAVE: the layout puts every stratum inside one wave's rows, so a wave's first row is a
 // stratum head and its scan needs nothing from the other waves: no workgroup scan, no barrier.
-template <int BLOCK, int IPT, bool BITS, bool EFRON, bool WAVE>
+template <int BLOCK, int IPT, int XK, bool EFRON, bool WAVE>
 __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 {
     constexpr int NW = BLOCK / kWave;
@@ -547,7 +577,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
     for (int j = 0; j < p; ++j) {
         const double bj = L.beta[j];
         if (bj != 0.0) {
-            XCol<IPT, BITS> xv;
+            XCol<IPT, XK> xv;
             xv.load(L, ld, j, row0, tg);
 #pragma unroll
             for (int i = 0; i < IPT; ++i) eta[i] = fma(xv[i], bj, eta[i]);
@@ -580,7 +610,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
 
     const int jfirst = fit ? 0 : L.j0;
     const int jend = fit ? p : L.j1;
-    XCol<IPT, BITS> xc;
+    XCol<IPT, XK> xc;
     xc.load(L, ld, jfirst, row0, tg);
 
     // Wave 0 keeps the bookkeeping (the same in every lane) and takes the step: its
@@ -594,7 +624,7 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
         for (int j = jfirst; j < jend; ++j) {
             ++epoch;
             const int jn = (j + 1 < jend) ? j + 1 : jfirst;
-            XCol<IPT, BITS> xn;
+            XCol<IPT, XK> xn;
             xn.load(L, ld, jn, row0, tg);
             const bool want_obj = (j == jfirst);
             // the step's per-column inputs: issued here, they arrive during the passes
@@ -625,8 +655,8 @@ __global__ __launch_bounds__(BLOCK) void ccd_kernel(CcdLaunch L)
             }
 
             // pass 2: inclusive prefixes at group ends -> per-coordinate sums
-            Partial v = want_obj ? pass2<IPT, BITS, EFRON, true>(exc, meta, wv, xc, eta, c)
-                                 : pass2<IPT, BITS, EFRON, false>(exc, meta, wv, xc, eta, c);
+            Partial v = want_obj ? pass2<IPT, XK, EFRON, true>(exc, meta, wv, xc, eta, c)
+                                 : pass2<IPT, XK, EFRON, false>(exc, meta, wv, xc, eta, c);
             v = block_reduce_partial<NW>(v, s_red);
             const bool extra = want_obj || !fit;
             if (t == 0) publish_partial(part, G, b, v, epoch, extra);
@@ -779,44 +809,46 @@ size_t ccd_smem_bytes(int, int p)
     return sizeof(double) * (size_t)p;
 }
 
-template <int IPT, bool BITS, bool EFRON, bool WAVE>
+template <int IPT, int XK, bool EFRON, bool WAVE>
 const void *ccd_fn()
 {
-    return reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, IPT, BITS, EFRON, WAVE>);
+    return reinterpret_cast<const void *>(&ccd_kernel<kCcdBlock, IPT, XK, EFRON, WAVE>);
 }
 
-template <bool BITS, bool EFRON, bool WAVE>
+template <int XK, bool EFRON, bool WAVE>
 const void *ccd_fn_ipt(int ipt)
 {
     switch (ipt) {
-    case 1: return ccd_fn<1, BITS, EFRON, WAVE>();
-    case 2: return ccd_fn<2, BITS, EFRON, WAVE>();
-    case 4: return ccd_fn<4, BITS, EFRON, WAVE>();
-    case 8: return ccd_fn<8, BITS, EFRON, WAVE>();
-    case 16: return ccd_fn<16, BITS, EFRON, WAVE>();
+    case 1: return ccd_fn<1, XK, EFRON, WAVE>();
+    case 2: return ccd_fn<2, XK, EFRON, WAVE>();
+    case 4: return ccd_fn<4, XK, EFRON, WAVE>();
+    case 8: return ccd_fn<8, XK, EFRON, WAVE>();
+    case 16: return ccd_fn<16, XK, EFRON, WAVE>();
     default: return nullptr;
     }
 }
 
 template <bool WAVE>
-const void *ccd_function_w(int ipt, bool bits, bool efron)
+const void *ccd_function_w(int ipt, int xk, bool efron)
 {
-    if (bits) return efron ? ccd_fn_ipt<true, true, WAVE>(ipt) : ccd_fn_ipt<true, false, WAVE>(ipt);
-    return efron ? ccd_fn_ipt<false, true, WAVE>(ipt) : ccd_fn_ipt<false, false, WAVE>(ipt);
+    if (xk == 2) return efron ? ccd_fn_ipt<2, true, WAVE>(ipt) : ccd_fn_ipt<2, false, WAVE>(ipt);
+    if (xk == 1) return efron ? ccd_fn_ipt<1, true, WAVE>(ipt) : ccd_fn_ipt<1, false, WAVE>(ipt);
+    return efron ? ccd_fn_ipt<0, true, WAVE>(ipt) : ccd_fn_ipt<0, false, WAVE>(ipt);
 }
 
-const void *ccd_function(int ipt, bool bits, bool efron, bool wave)
+// xk: 0 dense X, 1 indicator X, 2 sparse values (see XCol)
+const void *ccd_function(int ipt, int xk, bool efron, bool wave)
 {
-    return wave ? ccd_function_w<true>(ipt, bits, efron) : ccd_function_w<false>(ipt, bits, efron);
+    return wave ? ccd_function_w<true>(ipt, xk, efron) : ccd_function_w<false>(ipt, xk, efron);
 }
 
 // Workgroups of the persistent kernel that fit on one compute unit; every variant
-// (indicator X, Efron, wave-aligned layout) must fit, since a handle may run any of them.
+// (indicator or sparse X, Efron, wave-aligned layout) must fit, since a handle may run any of them.
 int occupancy_for(int ipt, int p, int *blocks)
 {
     *blocks = 1 << 30;
-    for (int v = 0; v < 8; ++v) {
-        const void *fn = ccd_function(ipt, (v & 1) != 0, (v & 2) != 0, (v & 4) != 0);
+    for (int v = 0; v < 12; ++v) {
+        const void *fn = ccd_function(ipt, v % 3, ((v / 3) & 1) != 0, ((v / 3) & 2) != 0);
         if (!fn) return (int)hipErrorInvalidValue;
         int nb = 0;
         const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kCcdBlock, ccd_smem_bytes(ipt, p));
@@ -862,7 +894,7 @@ int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream,
     CcdLaunch arg = L;
     void *args[] = {&arg};
     const size_t smem = ccd_smem_bytes(shape.ipt, L.p);
-    const void *fn = ccd_function(shape.ipt, L.xbits != nullptr, L.efron != 0, shape.wave);
+    const void *fn = ccd_function(shape.ipt, L.xvals ? 2 : (L.xbits ? 1 : 0), L.efron != 0, shape.wave);
     if (!fn) return (int)hipErrorInvalidValue;
     e = hipLaunchCooperativeKernel(fn, dim3(shape.grid), dim3(kCcdBlock), args, (unsigned)smem, stream);
     if (e != hipSuccess) return (int)e;

@@ -62,8 +62,14 @@ static void free_device(cox_handle *h)
     newton_free(h);
     if (h->d_x) (void)hipFree(h->d_x);
     if (h->d_xbits) (void)hipFree(h->d_xbits);
+    if (h->d_xvals) (void)hipFree(h->d_xvals);
+    if (h->d_xvoff) (void)hipFree(h->d_xvoff);
+    if (h->d_woff) (void)hipFree(h->d_woff);
     if (h->d_trust) (void)hipFree(h->d_trust);
     h->d_xbits = nullptr;
+    h->d_xvals = nullptr;
+    h->d_xvoff = nullptr;
+    h->d_woff = nullptr;
     h->d_trust = nullptr;
     if (h->d_meta) (void)hipFree(h->d_meta);
     if (h->d_vec) (void)hipFree(h->d_vec);
@@ -490,6 +496,143 @@ extern "C" int cox_init_indicator(cox_handle **out, int64_t n, int64_t p, const 
     return COX_OK;
 }
 
+// delta'X_j of one sparse column (device rows ascending, values) in the order of the dense
+// path's event sums (launch_event_sums: thread t of kEventSumThreads adds the event rows
+// r = t (mod kEventSumThreads) in increasing r, then the partials meet in a halving tree), so
+// that a sparse column's sum is bit-identical to the dense column's (its zeros add nothing).
+static double event_sum_device_order(const std::vector<std::pair<int64_t, double>> &col,
+                                     const std::vector<uint8_t> &ev_dev)
+{
+    std::vector<double> acc((size_t)kEventSumThreads, 0.0);
+    for (const auto &e : col)
+        if (ev_dev[(size_t)e.first]) acc[(size_t)(e.first % kEventSumThreads)] += e.second;
+    for (int w = kEventSumThreads / 2; w > 0; w >>= 1)
+        for (int t = 0; t < w; ++t) acc[(size_t)t] += acc[(size_t)(t + w)];
+    return acc[0];
+}
+
+extern "C" int cox_init_sparse(cox_handle **out, int64_t n, int64_t p, const int64_t *col_ptr,
+                               const int32_t *row_idx, const double *values, const double *time,
+                               const uint8_t *event, const int32_t *stratum, const cox_options *o)
+{
+    if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || p < 1) return fail(nullptr, COX_EINVAL, "need n >= 1 and p >= 1");
+    if (n > (int64_t)kCountMask) return fail(nullptr, COX_EUNSUPPORTED, "n exceeds 2^29 - 1");
+    if (p > kMaxCcdP) return fail(nullptr, COX_EUNSUPPORTED, "p > 12288 is not supported by the resident kernel");
+    if (!col_ptr || !time || !event) return fail(nullptr, COX_EINVAL, "col_ptr, time and event are required");
+    if (col_ptr[0] != 0) return fail(nullptr, COX_EINVAL, "col_ptr[0] must be 0");
+    for (int64_t j = 0; j < p; ++j)
+        if (col_ptr[j + 1] < col_ptr[j]) return fail(nullptr, COX_EINVAL, "col_ptr must be non-decreasing");
+    const int64_t nnz = col_ptr[p];
+    if (nnz > 0 && (!row_idx || !values)) return fail(nullptr, COX_EINVAL, "row_idx and values are required");
+    for (int64_t k = 0; k < nnz; ++k) {
+        if (row_idx[k] < 0 || row_idx[k] >= n) return fail(nullptr, COX_EINVAL, "row index out of range");
+        if (!std::isfinite(values[k])) return fail(nullptr, COX_EINVAL, "values must be finite");
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(time[i]) || event[i] > 1) return fail(nullptr, COX_EINVAL, "time must be finite, event 0 or 1");
+    cox_options opt;
+    if (o) opt = *o;
+    else cox_default_options(&opt);
+    {
+        std::string msg;
+        if (const int rc = check_options(opt, msg)) return fail(nullptr, rc, msg);
+    }
+    if (opt.mode != COX_CCD || opt.x_precision != COX_F64)
+        return fail(nullptr, COX_EUNSUPPORTED, "sparse X runs COX_CCD fits in COX_F64");
+    cox_handle *h = new cox_handle();
+    h->n = n;
+    h->p = p;
+    h->opt = opt;
+    h->opt.penalize = nullptr;
+    h->stream = static_cast<hipStream_t>(opt.stream);
+    (void)hipGetDevice(&h->device);
+    canonical_order(n, time, event, stratum, h->perm, h->meta);
+    h->gamma.assign((size_t)p, opt.gamma);
+    if (o && o->penalize)
+        for (int64_t j = 0; j < p; ++j) h->gamma[(size_t)j] = o->penalize[j] ? opt.gamma : 0.0;
+    std::string err;
+    const int rc = layout_for(h, err);
+    if (rc != 0) {
+        delete h;
+        return fail(nullptr, rc, err);
+    }
+    const int ipt = h->shape.ipt;
+    h->ldb = h->shape.ld / ipt;    // one unit per thread
+    const int64_t rows_per_wave = (int64_t)kWaveRows * ipt, nwaves = h->shape.ld / rows_per_wave;
+    std::vector<int64_t> dev_row((size_t)n);
+    for (int64_t c = 0; c < n; ++c) dev_row[(size_t)h->perm[(size_t)c]] = h->pos[(size_t)c];
+    const size_t unit = indicator_unit(ipt);
+    std::vector<uint8_t> bits(unit * (size_t)h->ldb * (size_t)p, 0);
+    std::vector<double> q((size_t)p, 0.0), vals;
+    std::vector<int64_t> voff((size_t)p, 0);
+    std::vector<int32_t> woff((size_t)(p * nwaves), 0);
+    std::vector<std::pair<int64_t, double>> col;
+    std::vector<uint8_t> ev_dev((size_t)h->shape.ld, 0);
+    for (int64_t c = 0; c < n; ++c) ev_dev[(size_t)h->pos[(size_t)c]] = event[h->perm[(size_t)c]];
+    vals.reserve((size_t)nnz);
+    for (int64_t j = 0; j < p; ++j) {
+        // the column's nonzeros in device-row order (explicit zeros dropped)
+        col.clear();
+        for (int64_t k = col_ptr[j]; k < col_ptr[j + 1]; ++k)
+            if (values[k] != 0.0) col.emplace_back(dev_row[(size_t)row_idx[k]], values[k]);
+        std::sort(col.begin(), col.end(),
+                  [](const std::pair<int64_t, double> &a, const std::pair<int64_t, double> &b) { return a.first < b.first; });
+        for (size_t k = 1; k < col.size(); ++k)
+            if (col[k].first == col[k - 1].first) {
+                delete h;
+                return fail(nullptr, COX_EINVAL, "a row index repeats within a column");
+            }
+        voff[(size_t)j] = (int64_t)vals.size();
+        size_t k = 0;
+        for (int64_t w = 0; w < nwaves; ++w) {
+            woff[(size_t)(j * nwaves + w)] = (int32_t)k;
+            while (k < col.size() && col[k].first < (w + 1) * rows_per_wave) ++k;
+        }
+        for (const auto &e : col) {
+            const int64_t r = e.first;
+            const size_t u = (size_t)(j * h->ldb + r / ipt);
+            const uint32_t bit = 1u << (r % ipt);
+            if (unit == 1) {
+                bits[u] = (uint8_t)(bits[u] | bit);
+            } else {
+                uint16_t wd;
+                std::memcpy(&wd, &bits[2 * u], 2);
+                wd = (uint16_t)(wd | bit);
+                std::memcpy(&bits[2 * u], &wd, 2);
+            }
+            vals.push_back(e.second);
+        }
+        q[(size_t)j] = event_sum_device_order(col, ev_dev);
+    }
+    hipError_t e = alloc_device(h);
+    if (e == hipSuccess) e = hipMalloc(&h->d_xvals, sizeof(double) * std::max<size_t>(vals.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&h->d_xvoff, sizeof(int64_t) * (size_t)p);
+    if (e == hipSuccess) e = hipMalloc(&h->d_woff, sizeof(int32_t) * std::max<size_t>(woff.size(), 1));
+    if (e != hipSuccess) {
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "device allocation");
+    }
+    e = upload_meta(h);
+    if (e == hipSuccess) e = hipMemcpy(h->d_xbits, bits.data(), bits.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !vals.empty())
+        e = hipMemcpy(h->d_xvals, vals.data(), sizeof(double) * vals.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->d_xvoff, voff.data(), sizeof(int64_t) * (size_t)p, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !woff.empty())
+        e = hipMemcpy(h->d_woff, woff.data(), sizeof(int32_t) * woff.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(h->q(), q.data(), sizeof(double) * p, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = upload_tables(h);
+    if (e != hipSuccess) {
+        free_device(h);
+        delete h;
+        return hip_fail(nullptr, e, "device upload");
+    }
+    *out = h;
+    return COX_OK;
+}
+
 // Canonical rows of the data set in which original row i appears count[i] times
 // (copies numbered consecutively, original rows in order), derived from the
 // parent's canonical order without sorting: copies of one row are adjacent and
@@ -540,6 +683,8 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
     *out = nullptr;
     if (!parent || !count) return fail(nullptr, COX_EINVAL, "parent and count are required");
+    if (parent->d_xvals)
+        return fail(nullptr, COX_EUNSUPPORTED, "a handle on sparse X (cox_init_sparse) supports cox_fit and cox_evaluate only");
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != parent->device) return fail(nullptr, COX_EINVAL, "the parent handle lives on another device");
@@ -665,6 +810,8 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
     if (!out) return fail(nullptr, COX_EINVAL, "out is NULL");
     *out = nullptr;
     if (!parent) return fail(nullptr, COX_EINVAL, "parent is NULL");
+    if (parent->d_xvals)
+        return fail(nullptr, COX_EUNSUPPORTED, "a handle on sparse X (cox_init_sparse) supports cox_fit and cox_evaluate only");
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != parent->device) return fail(nullptr, COX_EINVAL, "the parent handle lives on another device");
@@ -808,6 +955,10 @@ static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *bet
     L.x = h->d_x;
     L.xbits = h->d_xbits;
     L.ldb = h->ldb;
+    L.xvals = h->d_xvals;
+    L.xvoff = h->d_xvoff;
+    L.woff = h->d_woff;
+    L.nwaves = h->shape.ipt ? h->shape.ld / ((int64_t)kWaveRows * h->shape.ipt) : 0;
     L.meta = h->d_meta;
     L.q = h->q();
     L.gamma = h->gam();
@@ -853,9 +1004,20 @@ extern "C" int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox
     if (beta0)
         for (int64_t j = 0; j < h->p; ++j)
             if (!std::isfinite(beta0[j])) return fail(h, COX_EINVAL, "beta0 is not finite");
+    if (info) info->fallback = 0;
     if (h->opt.mode == COX_NEWTON_REFINE) return newton_fit(h, beta0, beta_out, info);
     double res[kResultSlots];
     int rc = run_kernel(h, kModeFit, 0, (int)h->p, beta0, res);
+    if (rc == COX_ENUMERIC && h->d_x) {
+        // the one shift of the persistent kernel cannot hold exp(X beta) in range: finish on the
+        // full evaluation (running-maximum scans), Newton or proximal Newton steps in FP64
+        const int rc2 = newton_fit(h, beta0, beta_out, info);
+        if (rc2 == COX_OK || rc2 == COX_NOT_CONVERGED) {
+            if (info) info->fallback = 1;
+            return rc2;
+        }
+        return rc2;
+    }
     if (rc != COX_OK && rc != COX_ENUMERIC) return rc;
     hipError_t e = hipMemcpy(beta_out, h->beta(), sizeof(double) * h->p, hipMemcpyDeviceToHost);
     std::vector<double> g(h->p);
@@ -1108,6 +1270,11 @@ extern "C" int cox_evaluate(cox_handle *h, const double *beta, double *objective
     if (!beta) return fail(h, COX_EINVAL, "beta is NULL");
     double res[kResultSlots];
     int rc = run_kernel(h, kModeEval, 0, (int)h->p, beta, res);
+    if (rc == COX_ENUMERIC && h->d_x) {
+        // beyond the one shift's range: the full evaluation (running-maximum scans) gives the
+        // same objective, gradient and diagonal Hessian
+        return cox_evaluate_full(h, beta, objective, grad, hess_diag, nullptr);
+    }
     if (rc != COX_OK) return rc;
     hipError_t e = hipSuccess;
     if (grad) e = hipMemcpy(grad, h->g1(), sizeof(double) * h->p, hipMemcpyDeviceToHost);

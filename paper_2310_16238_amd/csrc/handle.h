@@ -66,6 +66,9 @@ struct cox_handle {
     double *d_x = nullptr;         // dense X [p][ld]; NULL for a handle on indicator X
     void *d_xbits = nullptr;       // indicator X: [p][ldb] units of ipt bits (uint8, uint16 for ipt 16)
     int64_t ldb = 0;
+    double *d_xvals = nullptr;     // sparse X (cox_init_sparse): the values of the rows d_xbits marks
+    int64_t *d_xvoff = nullptr;    // [p] start of each column's values
+    int32_t *d_woff = nullptr;     // [p][ld / (64 ipt)] values of the column before each wave's rows
     uint32_t *d_meta = nullptr;
     double *d_vec = nullptr;       // q, gamma, beta, g1, g2, m2 (p each), result (8), exp table (64)
     void *d_sync = nullptr;

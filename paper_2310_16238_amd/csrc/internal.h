@@ -40,6 +40,10 @@ struct CcdLaunch {
     const double *x = nullptr;       // [p][ld] canonical rows, padding rows zero (dense X)
     const void *xbits = nullptr;     // indicator X instead: [p][ldb] units of IPT bits (uint8, uint16 for IPT 16)
     int64_t ldb = 0;                 // units per indicator column (grid * threads)
+    const double *xvals = nullptr;   // sparse values instead: the nonzeros the bits mark, column by column
+    const int64_t *xvoff = nullptr;  // [p] start of column j in xvals
+    const int32_t *woff = nullptr;   // [p][nwaves] nonzeros of column j before wave w's first row
+    int64_t nwaves = 0;              // waves of the launch (ld / (64 ipt))
     const uint32_t *meta = nullptr;  // [ld]
     const double *q = nullptr;       // [p] delta' X_j
     const double *gamma = nullptr;   // [p] l1 weights
@@ -82,7 +86,9 @@ int launch_ccd(const LaunchShape &shape, const CcdLaunch &L, hipStream_t stream,
 int launch_gather_rows(const double *x_in, int64_t ld_in, const int32_t *src, const int32_t *rint,
                        const int32_t *col_src, const int32_t *col_int, double *x_out, int64_t ld_out, int p,
                        hipStream_t stream);
-// q[j] = sum of x[j][r] over the rows whose word has the event bit (fixed-order sums).
+// q[j] = sum of x[j][r] over the rows whose word has the event bit (fixed-order sums: thread t of
+// kEventSumThreads adds rows r = t (mod kEventSumThreads) in increasing r, then a halving tree).
+constexpr int kEventSumThreads = 256;
 int launch_event_sums(const double *x, int64_t ld, const uint32_t *meta, double *q, int p, hipStream_t stream);
 
 // True when [ptr, ptr + bytes) lies inside one device (or managed) allocation of `device`

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kGatherBlock) void gather_rows_kernel(const double 
     }
 }
 
-constexpr int kQBlock = 256;
+constexpr int kQBlock = kEventSumThreads;
 
 // q[j] = sum over rows with the event bit of x[j][r], one workgroup per column;
 // each thread sums a fixed stride of rows and the workgroup folds the thread

@@ -186,3 +186,74 @@ def test_indicator_intervals_equal_dense():
     ref = orc.fit_ccd(r["X"], r["time"], r["event"], r["stratum"], gamma=2.0, penalize=pen, tol=1e-13)
     assert ref.converged and info["status"] == coxmi.COX_OK
     assert np.array_equal(bb == 0.0, ref.beta == 0.0) and _rel(bb, ref.beta) <= 1e-10
+
+
+def _sparse_values(d, seed):
+    """d.X with its ones replaced by N(0, 1) values (a general sparse design) and its CSC form."""
+    X = d.X.copy()
+    nz = X != 0.0
+    X[nz] = np.random.default_rng(seed).normal(0.0, 1.0, int(nz.sum()))
+    cols = [np.flatnonzero(X[:, j]) for j in range(X.shape[1])]
+    ptr = np.zeros(X.shape[1] + 1, np.int64)
+    ptr[1:] = np.cumsum([c.size for c in cols])
+    idx = np.concatenate(cols).astype(np.int32)
+    vals = np.concatenate([X[c, j] for j, c in enumerate(cols)])
+    return X, ptr, idx, vals
+
+
+@pytest.mark.parametrize("n,p,K,gamma", [(5000, 12, 1, 1.0), (150_000, 40, 7500, 2.0), (300_000, 16, 3, 0.0),
+                                         (600_000, 10, 30_000, 0.5), (1_200_000, 8, 60_000, 5.0)])
+def test_sparse_values_equal_dense(n, p, K, gamma):
+    """General sparse X (cox_init_sparse: the nonzero rows' bits and their values, found by a
+    prefix sum of bit counts across each wave) against the same X stored dense: every product
+    is formed from the same values, so fits, evaluations and coordinates agree bit for bit, at
+    1, 2, 4, 8 and 16 rows per thread; and the oracle's CCD fit to 1e-10."""
+    d = synth.make("binary", n, p, K, 300 + K, beta_sd=0.5, beta_nonzero=0.4, density=0.05, tie_round=100.0)
+    X, ptr, idx, vals = _sparse_values(d, 17)
+    X[:, 2] = 0.0                         # an empty column
+    keep = idx >= 0
+    keep[ptr[2]:ptr[3]] = False
+    ptr2 = ptr.copy()
+    ptr2[3:] -= ptr[3] - ptr[2]
+    idx, vals = idx[keep], vals[keep]
+    perm = np.random.default_rng(3).permutation(ptr2[1])   # column 0's entries in scrambled order
+    idx[:ptr2[1]] = idx[:ptr2[1]][perm]
+    vals[:ptr2[1]] = vals[:ptr2[1]][perm]
+    _say(f"sparse values vs dense n={n} p={p} K={K} gamma={gamma} nnz={idx.size}")
+    with coxmi.CoxModel(X, d.time, d.event, d.stratum, gamma=gamma, tol=1e-13) as md, \
+            coxmi.CoxModel.sparse(n, ptr2, idx, vals, d.time, d.event, d.stratum, gamma=gamma, tol=1e-13) as ms:
+        bd, infod = md.fit()
+        bs, infos = ms.fit()
+        assert np.array_equal(bd, bs) and infod["iters"] == infos["iters"], (infod, infos)
+        probe = np.random.default_rng(1).normal(0, 0.2, p)
+        od, gd, hd = md.evaluate(probe)
+        os_, gs, hs = ms.evaluate(probe)
+        assert od == os_ and np.array_equal(gd, gs) and np.array_equal(hd, hs)
+        assert np.array_equal(md.coordinate(probe, p - 1), ms.coordinate(probe, p - 1))
+    if n <= 150_000:
+        ref = orc.fit_ccd(X, d.time, d.event, d.stratum, gamma=gamma, tol=1e-13)
+        assert ref.converged and np.array_equal(bs == 0.0, ref.beta == 0.0)
+        err = _rel(bs, ref.beta)
+        _say(f"  sweeps={infos['iters']} rel err vs oracle {err:.3e}")
+        assert err <= 1e-10
+
+
+def test_sparse_values_errors():
+    d = synth.make("binary", 4000, 5, 2, 221, density=0.1)
+    X, ptr, idx, vals = _sparse_values(d, 5)
+    bad = idx.copy()
+    bad[1] = bad[0]                       # a repeated row in column 0
+    with pytest.raises(coxmi.CoxError) as e:
+        coxmi.CoxModel.sparse(4000, ptr, bad, vals, d.time, d.event, d.stratum)
+    assert e.value.code == coxmi.COX_EINVAL
+    v2 = vals.copy()
+    v2[0] = np.inf
+    with pytest.raises(coxmi.CoxError) as e:
+        coxmi.CoxModel.sparse(4000, ptr, idx, v2, d.time, d.event, d.stratum)
+    assert e.value.code == coxmi.COX_EINVAL
+    with coxmi.CoxModel.sparse(4000, ptr, idx, vals, d.time, d.event, d.stratum) as m:
+        for call in (lambda: m.evaluate_full(np.zeros(5)), lambda: m.intervals(d.time, d.event, d.stratum, [0.5]),
+                     lambda: m.resample(np.ones(4000, np.uint32))):
+            with pytest.raises(coxmi.CoxError) as e:
+                call()
+            assert e.value.code == coxmi.COX_EUNSUPPORTED

@@ -246,19 +246,44 @@ def test_edge_cases():
         assert abs(obj) <= 1e-12 * n and np.all(np.abs(g) <= 1e-12 * n) and np.all(np.abs(h) <= 1e-12 * n)
 
 
-def test_dynamic_range_error_is_reported():
-    """exp(x'b) far outside FP64 range inside one risk set: the global shift cannot hold it."""
-    n = 64
-    X = np.zeros((n, 1))
-    X[0, 0] = 900.0                      # row 0 sets the global maximum of x'b ...
-    X[1:, 0] = -900.0
-    time = np.linspace(10.0, 1.0, n)
-    time[0] = 0.5                        # ... but has the shortest time, so it is in no other risk set
-    event = np.ones(n, np.uint8)
-    with coxmi.CoxModel(X, time, event) as m:
-        with pytest.raises(coxmi.CoxError) as ei:
-            m.evaluate(np.array([1.0]))
-    assert ei.value.code == coxmi.COX_ENUMERIC
-    # the oracle handles it (running-shift scan) -- documented difference
-    L = orc.canonical_layout(time, event)
-    assert np.isfinite(orc.full_eval(orc.to_canonical(X, L), L, [1.0], want_info=False).objective)
+def test_dynamic_range_falls_back_to_the_full_evaluation():
+    """X beta beyond the range one shift per fit can hold in FP64: a stratum-constant offset of
+    2000 in a column (the partial likelihood ignores it; exp(x'b - c) of the other stratum
+    underflows for any single c).  cox_evaluate then answers from the full evaluation (running-
+    maximum scans) and cox_fit finishes by Newton / proximal Newton steps on it -- the oracle's
+    values and optima (running-shift scans) to the usual bars."""
+    rng = np.random.default_rng(31)
+    n = 3000
+    st = (np.arange(n) % 2).astype(np.int32)
+    z = rng.normal(size=(n, 2))
+    X = z.copy()
+    X[:, 0] += 2000.0 * st
+    lin = z @ np.array([0.6, -0.4])
+    T = rng.exponential(1.0 / np.exp(lin))
+    C = rng.exponential(1.0, n)
+    time = np.minimum(T, C)
+    event = (T <= C).astype(np.uint8)
+    b0 = np.array([0.6, -0.4])
+    with coxmi.CoxModel(X, time, event, st, tol=1e-13) as m:
+        obj, g, hd = m.evaluate(b0)
+        beta, info = m.fit()
+    with coxmi.CoxModel(X, time, event, st, gamma=5.0, tol=1e-13) as m:
+        beta1, info1 = m.fit()
+    L = orc.canonical_layout(time, event, st)
+    fe = orc.full_eval(orc.to_canonical(X, L), L, b0, want_info=False)
+    E = float(event.sum())
+    assert abs(obj - fe.objective) <= 1e-11 * max(E, abs(fe.objective))
+    assert np.max(np.abs(g - fe.grad)) <= 1e-11 * max(1.0, E) * 2000.0
+    assert np.max(np.abs(hd - fe.hess_diag)) <= 1e-11 * max(1.0, E) * 2000.0 ** 2
+    # the offset is constant within strata, so the optima are those of the data without it
+    ref = orc.fit_newton(z, time, event, st, tol=1e-14)
+    assert ref.converged and info["status"] == coxmi.COX_OK and info["fallback"] == 1, info
+    assert np.max(np.abs(beta - ref.beta)) <= 1e-10 * np.max(np.abs(ref.beta))
+    ref1 = orc.fit_ccd(z, time, event, st, gamma=5.0, tol=1e-14, max_sweeps=5000)
+    assert ref1.converged and info1["status"] == coxmi.COX_OK and info1["fallback"] == 1, info1
+    assert np.array_equal(beta1 == 0.0, ref1.beta == 0.0)
+    assert np.max(np.abs(beta1 - ref1.beta)) <= 1e-10 * np.max(np.abs(ref1.beta))
+    # a fit within range takes the persistent kernel
+    with coxmi.CoxModel(z, time, event, st, tol=1e-13) as m:
+        _, info2 = m.fit()
+    assert info2["fallback"] == 0
