@@ -182,7 +182,8 @@ def serve_leg(args):
                 return srv.submit_device(*dev[i])
             d = reqs[i]
             return srv.submit(d.X, d.time, d.event, d.stratum)
-        with coxmi.CoxServer(hbm_budget=args.hbm_gib << 30, prep_threads=args.prep_threads) as srv:
+        with coxmi.CoxServer(hbm_budget=args.hbm_gib << 30, prep_threads=args.prep_threads,
+                             fused_rounds=args.fused_rounds) as srv:
             warm = [submit(srv, i) for i in batch[:4]]
             srv.drain()
             for t in warm:
@@ -203,7 +204,9 @@ def serve_leg(args):
         done = np.array([r[2]["done_s"] for r in res])
         lat = done - sub
         span = float(done.max() - sub.min())
-        stats = {k: st1[k] - st0[k] for k in ("completed", "iterations", "gpu_busy_s")}
+        stats = {k: st1[k] - st0[k] for k in ("completed", "iterations", "gpu_busy_s", "launches")}
+        if args.fused_rounds:
+            stats["phase_s"] = [b - a for a, b in zip(st0["phase_s"], st1["phase_s"])]
         stats.update(resident_peak=st1["resident_peak"], arena_peak=st1["arena_peak"],
                      mean_resident=st1["mean_resident"])
         return res, {"fits_per_s": len(batch) / span, "makespan_s": span,
@@ -274,7 +277,7 @@ def serve_leg(args):
         "config": {"workload": f"serving stream: {R} independent unpenalised fits, n log-uniform in [1e3, 1e5], "
                                "p uniform in 5..100 with a ones column, K = n/100 strata, seed 3; "
                                "request data resident in device memory",
-                   "requests": R, "rows": rows},
+                   "requests": R, "rows": rows, "fused_rounds": args.fused_rounds},
         "plain_fp64_fits_per_s": plain,
         "speedup_vs_plain": {"device_inputs": sat["fits_per_s"] / plain_best_dev,
                              "host_inputs": sat_host["fits_per_s"] / plain_best},
@@ -1327,6 +1330,8 @@ def main():
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--plain-sample", type=int, default=32, help="serve: requests timed on the plain FP64 path")
     ap.add_argument("--poisson-seconds", type=float, default=15.0, help="serve: length of the Poisson run")
+    ap.add_argument("--fused-rounds", type=int, default=0,
+                    help="serve: rounds per persistent launch of the fit server (0: separate launches per round)")
     ap.add_argument("--legs", default="mixed,serve",
                     help="default workload: secondary legs to run after the headline fit (comma-separated: "
                          "mixed = BF16 + refinement Newton at N=1e6 P=200; serve = the serving stream; empty: none)")

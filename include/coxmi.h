@@ -474,6 +474,12 @@ typedef struct {
     double tol;             /* stop when max|step| <= tol * max(1, max|beta|) (default 1e-12) */
     int max_iter;           /* Newton steps per fit (default 100) */
     int device;             /* HIP device ordinal, -1 = the current device */
+    int fused_rounds;       /* 0: every round is six batched launches driven by the host thread;
+                               R in 1..4096: one persistent cooperative launch runs up to R rounds
+                               of every resident fit, its phases separated by grid-wide barriers,
+                               finished fits reported while it runs; it ends early when all its
+                               fits are done or new fits are ready to join.  Results are
+                               bit-identical either way (default 0) */
 } cox_server_options;
 
 typedef struct {
@@ -489,6 +495,10 @@ typedef struct {
     size_t arena_bytes, arena_peak;
     double gpu_busy_s;      /* sum over rounds of launch-to-completion time */
     double now_s;           /* the server's clock */
+    int64_t launches;       /* persistent launches (fused_rounds > 0), else 0 */
+    double phase_s[6];      /* fused_rounds > 0: seconds from one grid barrier to the next, by the
+                               phase it ends (X beta, row scans, column pass, contraction, information
+                               sums, step), summed over launches (workgroup 0's constant-rate clock) */
 } cox_server_counters;
 
 /* cox_server_submit flags.

@@ -83,7 +83,7 @@ class cox_server_options(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("staging_bytes", ctypes.c_size_t),
                 ("max_resident", ctypes.c_int), ("prep_threads", ctypes.c_int),
                 ("x_precision", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("device", ctypes.c_int)]
+                ("device", ctypes.c_int), ("fused_rounds", ctypes.c_int)]
 
 
 class cox_request_times(ctypes.Structure):
@@ -102,10 +102,11 @@ class cox_server_counters(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("iterations", ctypes.c_int64),
                 ("resident_now", ctypes.c_int64), ("resident_peak", ctypes.c_int64),
                 ("mean_resident", ctypes.c_double), ("arena_bytes", ctypes.c_size_t),
-                ("arena_peak", ctypes.c_size_t), ("gpu_busy_s", ctypes.c_double), ("now_s", ctypes.c_double)]
+                ("arena_peak", ctypes.c_size_t), ("gpu_busy_s", ctypes.c_double), ("now_s", ctypes.c_double),
+                ("launches", ctypes.c_int64), ("phase_s", ctypes.c_double * 6)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: (list(getattr(self, k)) if k == "phase_s" else getattr(self, k)) for k, _ in self._fields_}
 
 
 COX_SUBMIT_BORROW = 1
@@ -793,8 +794,10 @@ class CoxServer:
     """
 
     def __init__(self, hbm_budget=None, staging_bytes=None, max_resident=None, prep_threads=None,
-                 tol=None, max_iter=None, device=None):
+                 tol=None, max_iter=None, device=None, fused_rounds=None):
         o = cox_server_default_options()
+        if fused_rounds is not None:
+            o.fused_rounds = int(fused_rounds)
         if hbm_budget is not None:
             o.hbm_budget = int(hbm_budget)
         if staging_bytes is not None:

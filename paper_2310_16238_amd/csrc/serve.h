@@ -100,5 +100,32 @@ int launch_syrk(const FitDesc *fits, const int4 *items, int nitems, hipStream_t 
 int launch_info(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_step(const FitDesc *fits, const int *slots, int nslots, int max_p, hipStream_t s);
 
+// Persistent rounds: one cooperative launch runs up to max_rounds iterations of every fit in
+// the lists, the phases separated by grid-wide barriers; it ends early when every fit has
+// finished or when the host writes a nonzero hold word.  Results equal those of the
+// separate launches above, bit for bit.
+constexpr int kRoundThreads = 512;   // threads of a workgroup of the round kernel
+constexpr int kRoundMaxGrid = 2048;
+
+struct RoundWork {
+    const FitDesc *fits;
+    const int2 *eta, *rows, *cols;   // work items as for the separate launches
+    const int4 *syrk;                // items of the fits not frozen when the launch starts
+    const int2 *info;
+    const int *slots;                // the fits of the launch
+    int ne, nr, nc, ns, ni, nf;
+    int max_rounds;
+    int max_p;                       // largest p among the fits (sizes the step's LDS)
+    const uint32_t *hold;            // host-mapped: nonzero asks the launch to end after the current round
+    void *ctl;                       // device, round_ctl_bytes(), cleared before every launch
+    uint64_t *hout;                  // host-mapped [8]: rounds completed; 1 if a bounded wait timed out;
+                                     // clock ticks (100 MHz) of the six phases, by workgroup 0
+};
+
+size_t round_ctl_bytes();
+// Workgroups of a round launch for fits of at most max_p columns (all resident at once).
+int round_grid(int max_p, int *grid);
+int launch_rounds(const RoundWork &w, int grid, hipStream_t s);
+
 }  // namespace serve
 }  // namespace coxmi

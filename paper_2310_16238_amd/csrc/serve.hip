@@ -97,37 +97,51 @@ __global__ __launch_bounds__(256) void admit_kernel(FitDesc *fits, const FitDesc
 
 // ------------------------------------------------------------------ eta
 
+// The phases of a round are device functions shared by the separate launches
+// below and by the persistent round kernel; a phase body makes the same sums in
+// the same order in both, so a fit's result does not depend on which runs it.
+
+// Item (fit, 256-row tile) of X beta, run by kEtaRows threads (t = 0 .. 255).
+// Every thread of the workgroup calls it the same number of times (the
+// barriers inside); `live` false leaves the item out.
+__device__ __forceinline__ void eta_item(const FitDesc *fits, int2 it, bool live, int t, double *red)
+{
+    double mx = -INFINITY;
+    if (live) {
+        const FitDesc F = fits[it.x];
+        const int64_t r = (int64_t)it.y * kEtaRows + t;
+        if (r < F.ld) {
+            // every column, in order (X is finite, so a zero coefficient adds a zero)
+            const double *xr = F.x + r;
+            double e = 0.0;
+            int j = 0;
+            for (; j + 8 <= F.p; j += 8) {
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = xr[(int64_t)(j + q) * F.ld];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) e = fma(v[q], F.beta[j + q], e);
+            }
+            for (; j < F.p; ++j) e = fma(xr[(int64_t)j * F.ld], F.beta[j], e);
+            F.eta[r] = e;
+            if (!(F.meta[r] & kPadBit)) mx = e;
+        }
+    }
+    mx = wave_max(mx);
+    if ((t & (kWave - 1)) == 0) red[t / kWave] = mx;
+    __syncthreads();
+    if (live && t == 0) {
+        double m = red[0];
+        for (int k = 1; k < kEtaRows / kWave; ++k) m = fmax(m, red[k]);
+        fits[it.x].tilemax[it.y] = m;
+    }
+    __syncthreads();   // red is rewritten by the next item
+}
+
 __global__ __launch_bounds__(kEtaRows) void eta_kernel(const FitDesc *fits, const int2 *items)
 {
     __shared__ double red[kEtaRows / kWave];
-    const int2 it = items[blockIdx.x];
-    const FitDesc F = fits[it.x];
-    const int64_t r = (int64_t)it.y * kEtaRows + threadIdx.x;
-    double mx = -INFINITY;
-    if (r < F.ld) {
-        // every column, in order (X is finite, so a zero coefficient adds a zero)
-        const double *xr = F.x + r;
-        double e = 0.0;
-        int j = 0;
-        for (; j + 8 <= F.p; j += 8) {
-            double v[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = xr[(int64_t)(j + q) * F.ld];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) e = fma(v[q], F.beta[j + q], e);
-        }
-        for (; j < F.p; ++j) e = fma(xr[(int64_t)j * F.ld], F.beta[j], e);
-        F.eta[r] = e;
-        if (!(F.meta[r] & kPadBit)) mx = e;
-    }
-    mx = wave_max(mx);
-    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mx;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = red[0];
-        for (int k = 1; k < kEtaRows / kWave; ++k) m = fmax(m, red[k]);
-        F.tilemax[it.y] = m;
-    }
+    eta_item(fits, items[blockIdx.x], true, threadIdx.x, red);
 }
 
 // ------------------------------------------------------------------ rows
@@ -159,11 +173,11 @@ __device__ __forceinline__ double block_max_rows(double v, double *red)
 // One workgroup per (fit, scan tile): every scan tile starts with a stratum
 // head (or is the fit's only tile), so its scans need no carry.  The tile's
 // objective part and range flag go to tpart; the step kernel adds them up.
-__global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, const int2 *items)
+// Run by kRowThreads threads; the whole workgroup takes the item.
+__device__ __forceinline__ void rows_item(const FitDesc *fits, int2 it)
 {
     __shared__ SegVal<1> wtot[kRowWaves];
     __shared__ double red[kRowWaves];
-    const int2 it = items[blockIdx.x];
     const FitDesc F = fits[it.x];
     const int t = threadIdx.x;
     const int64_t r_begin = (int64_t)it.y * F.tile;
@@ -266,6 +280,11 @@ __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, 
     }
 }
 
+__global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, const int2 *items)
+{
+    rows_item(fits, items[blockIdx.x]);
+}
+
 // ------------------------------------------------------------------ cols
 
 constexpr int kColWaves = 4, kColIpt = 4, kColChunk = kWave * kColIpt;
@@ -285,14 +304,13 @@ __device__ __forceinline__ void load4(const double *p, double *v)
 // block's columns, whose scans share one flag.  Lanes own 4 consecutive rows
 // (scan tiles and the padded row count are multiples of 64, so a lane's rows
 // are all in the tile or all past it).
-__global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *fits, const int2 *items, int nitems)
+// Run by one wave (no workgroup barrier inside).  PF: the next chunk's loads are issued
+// before this chunk is processed (more registers; same arithmetic).
+template <bool PF>
+__device__ __forceinline__ void cols_item(const FitDesc *fits, int2 it)
 {
     constexpr int CB = kColBlock;
     const int lane = threadIdx.x & (kWave - 1);
-    // the item index is the same in all lanes of a wave
-    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kColWaves + threadIdx.x / kWave);
-    if (item >= nitems) return;   // whole wave; no workgroup barrier below
-    const int2 it = items[item];
     const FitDesc F = fits[it.x];
     const int tt = it.y >> 10, j0 = it.y & 1023;   // (scan tile, first column of the block)
     const int64_t r_begin = (int64_t)tt * F.tile;
@@ -347,7 +365,7 @@ __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *
         const int64_t r0 = base + (int64_t)lane * kColIpt;
         Chunk nxt;
         const bool more = base + kColChunk < r_end;
-        if (more) load_chunk(nxt, r0 + kColChunk);
+        if (PF && more) load_chunk(nxt, r0 + kColChunk);
         double(&xv)[CB][kColIpt] = cur.xv;
         double(&wv)[kColIpt] = cur.wv;
         double(&bv)[kColIpt] = cur.bv;
@@ -385,7 +403,8 @@ __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *
             }
         }
         carry = seg_combine(carry, lane63_seg(inc));
-        if (more) cur = nxt;
+        if (PF && more) cur = nxt;
+        else if (!PF && more) load_chunk(cur, r0 + kColChunk);
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
@@ -397,6 +416,14 @@ __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *
             o[2] = s2;
         }
     }
+}
+
+__global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *fits, const int2 *items, int nitems)
+{
+    // the item index is the same in all lanes of a wave
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kColWaves + threadIdx.x / kWave);
+    if (item >= nitems) return;   // whole wave
+    cols_item<true>(fits, items[item]);
 }
 
 // ------------------------------------------------------------------ syrk (FP32 matrix cores)
@@ -422,17 +449,12 @@ __device__ __forceinline__ int pair_index(int ti, int tj, int nt)
 
 constexpr int kSyrkWaves = 4;
 
-// One workgroup per (fit, tile pair, K range, product): wave v takes the v-th
-// quarter of the K range, and the four accumulators are added in wave order.
-// Rows of X (event groups of Z) come in steps of 32 -- 16 consecutive per
-// half-wave, as float4s -- with the next step's operands loaded before this
-// step's 16 products.
-__global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc *fits, const int4 *items)
+// Wave v's product over the v-th quarter of the K range of item (fit, tile
+// pair, K range, product).  Rows of X (event groups of Z) come in steps of 32
+// -- 16 consecutive per half-wave, as float4s -- with the next step's operands
+// loaded before this step's 16 products.
+__device__ __forceinline__ f32x16 syrk_partial(const FitDesc &F, int4 it, int v, int lane)
 {
-    __shared__ float red[kSyrkWaves - 1][16][kWave];
-    const int lane = threadIdx.x & (kWave - 1), v = threadIdx.x / kWave;
-    const int4 it = items[blockIdx.x];
-    const FitDesc F = fits[it.x];
     const int nt = tile_count(F.p);
     int ti, tj;
     pair_tiles(it.y, nt, ti, tj);
@@ -496,18 +518,38 @@ __global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc 
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].w, bv[q].w, acc, 0, 0, 0);
         }
     }
+    return acc;
+}
+
+// Item (fit, tile pair, K range, product), run by kSyrkWaves waves (v = 0 .. 3):
+// the four accumulators are added in wave order through red ([3][16][64]
+// floats).  Every thread of the workgroup calls it the same number of times
+// (the barriers inside); `live` false leaves the item out.
+__device__ __forceinline__ void syrk_item(const FitDesc *fits, int4 it, bool live, int v, int lane, float *red)
+{
+    f32x16 acc;
+    if (live) {
+        acc = syrk_partial(fits[it.x], it, v, lane);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    }
     if (v > 0) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) red[v - 1][i][lane] = acc[i];
+        for (int i = 0; i < 16; ++i) red[((v - 1) * 16 + i) * kWave + lane] = acc[i];
     }
     __syncthreads();
-    if (v != 0) return;
+    if (v == 0) {
 #pragma unroll
-    for (int w = 0; w < kSyrkWaves - 1; ++w) {
+        for (int w = 0; w < kSyrkWaves - 1; ++w) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] += red[w][i][lane];
+            for (int i = 0; i < 16; ++i) acc[i] += red[(w * 16 + i) * kWave + lane];
+        }
     }
-    const int slot = zpart ? F.nxr + it.z : it.z;
+    __syncthreads();   // red is rewritten by the next item
+    if (v != 0 || !live) return;
+    const FitDesc &F = fits[it.x];
+    const int slot = it.w != 0 ? F.nxr + it.z : it.z;
     float *out = F.part + ((int64_t)slot * F.npairs + it.y) * (kTile * kTile);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -516,20 +558,29 @@ __global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc 
     }
 }
 
+constexpr int kSyrkRed = (kSyrkWaves - 1) * 16 * kWave;   // floats of red per item
+
+// One workgroup per item.
+__global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc *fits, const int4 *items)
+{
+    __shared__ float red[kSyrkRed];
+    syrk_item(fits, items[blockIdx.x], true, threadIdx.x / kWave, threadIdx.x & (kWave - 1), red);
+}
+
 // ------------------------------------------------------------------ info
 
 // One workgroup per (fit, tile pair): entry (m, n) of the pair's 32 x 32 block
 // of I = X' diag(b) X - Z'Z is the FP64 sum of its K-range partials in range
 // order, written to both triangles of F.L (entries below the diagonal of a
 // diagonal block are taken from above it).
-__global__ __launch_bounds__(256) void info_kernel(const FitDesc *fits, const int2 *items)
+// Run by 256 threads (t = 0 .. 255); no barrier inside.
+__device__ __forceinline__ void info_item(const FitDesc *fits, int2 it, int t)
 {
-    const int2 it = items[blockIdx.x];
     const FitDesc F = fits[it.x];
     const int nt = tile_count(F.p), p = F.p;
     int ti, tj;
     pair_tiles(it.y, nt, ti, tj);
-    const int e0 = threadIdx.x * 4;   // entries e0 .. e0 + 3: one row m, columns n .. n + 3
+    const int e0 = t * 4;   // entries e0 .. e0 + 3: one row m, columns n .. n + 3
     double sx[4] = {0.0, 0.0, 0.0, 0.0}, sz[4] = {0.0, 0.0, 0.0, 0.0};
     const float *base = F.part + (int64_t)it.y * (kTile * kTile) + e0;
     const int64_t step = (int64_t)F.npairs * (kTile * kTile);
@@ -559,6 +610,11 @@ __global__ __launch_bounds__(256) void info_kernel(const FitDesc *fits, const in
     }
 }
 
+__global__ __launch_bounds__(256) void info_kernel(const FitDesc *fits, const int2 *items)
+{
+    info_item(fits, items[blockIdx.x], threadIdx.x);
+}
+
 // ------------------------------------------------------------------ step
 
 constexpr int kStepThreads = 256;
@@ -572,17 +628,18 @@ constexpr int kStepThreads = 256;
 // shuffle.  The model is solved to a thousandth of the last step (or of max(1, |beta|) at the
 // first), at least to 1e-3 tol.  D goes to y; s_red[w] receives the largest violation of the
 // l1 optimality conditions at the current point (wave w's columns).
+template <int NT>
 __device__ void prox_step(const FitDesc &F, double *A, double *y, const uint8_t *s_free, double *s_red, int t,
                           int wv, int lane)
 {
     __shared__ double s_g[kMaxP], s_b[kMaxP], s_gm[kMaxP], s_a[kMaxP];
     const int p = F.p;
-    constexpr int kWaves = kStepThreads / kWave;
+    constexpr int kWaves = NT / kWave;
     for (int i = wv; i < p; i += kWaves)
         for (int j = lane; j < p; j += kWave)
             A[i * p + j] = i >= j ? F.L[(int64_t)i * p + j] : F.L[(int64_t)j * p + i];   // lower triangle, mirrored
     double viol = 0.0, bmax = 1.0;
-    for (int j = t; j < p; j += kStepThreads) {
+    for (int j = t; j < p; j += NT) {
         const double g = F.grad[j], b = F.beta[j], gm = F.gam[j], a = F.L[(int64_t)j * p + j];
         s_g[j] = g;
         s_b[j] = b;
@@ -595,7 +652,7 @@ __device__ void prox_step(const FitDesc &F, double *A, double *y, const uint8_t 
     }
     viol = wave_max(viol);
     bmax = wave_max(bmax);
-    __shared__ double s_bm[kStepThreads / kWave];
+    __shared__ double s_bm[NT / kWave];
     if (lane == 0) {
         s_red[wv] = viol;
         s_bm[wv] = bmax;
@@ -638,13 +695,44 @@ __device__ void prox_step(const FitDesc &F, double *A, double *y, const uint8_t 
     }
 }
 
-__global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits, const int *slots)
+// The fit's state goes to host-mapped memory with kDone set last, after a system-scope
+// fence: a host that finds kDone while kernels still run reads the rest of the state, and
+// the estimate written before it, complete.
+__device__ __forceinline__ void publish_state(const FitDesc &F, const FitState &st)
 {
-    extern __shared__ double lds[];   // A[p * p], y[p]
+    FitState v = st;
+    const int flags = v.flags;
+    v.flags = flags & ~kDone;
+    *F.hst = v;
+    if (flags & kDone) {
+        __threadfence_system();
+        __hip_atomic_store(&F.hst->flags, flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// Every entry of beta to host-mapped memory (each thread the entries it owns), then the
+// state; ndone (if given) counts the fits that finished.
+template <int NT>
+__device__ __forceinline__ void publish_final(const FitDesc &F, const FitState *st, int t, uint32_t *ndone)
+{
+    for (int j = t; j < F.p; j += NT) F.hbeta[j] = F.beta[j];
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) {
+        publish_state(F, *st);
+        if (ndone) __hip_atomic_fetch_add(ndone, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// One fit's step, run by NT threads (the whole workgroup) with lds = A[p * p], y[p].
+template <int NT>
+__device__ __forceinline__ void step_fit(const FitDesc *fits, int slot, double *lds, uint32_t *ndone)
+{
     __shared__ int s_action, s_bad, s_frozen;
     __shared__ uint8_t s_free[kMaxP];
-    __shared__ double s_red[kStepThreads / kWave];
-    const FitDesc F = fits[slots[blockIdx.x]];
+    __shared__ double s_red[NT / kWave];
+    __syncthreads();   // the shared words of the previous fit have been read
+    const FitDesc F = fits[slot];
     FitState *st = F.st;
     const int t = threadIdx.x, p = F.p;
     double *A = lds;
@@ -652,7 +740,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
 
     // per-column sums of the scan-tile partials, and the objective, in tile order; with l1
     // weights the objective includes sum_j gamma_j |beta_j| (summed by wave 0 in column order)
-    for (int j = t; j < p; j += kStepThreads) {
+    for (int j = t; j < p; j += NT) {
         double sg = 0.0, s1 = 0.0, s2 = 0.0;
         for (int q = 0; q < F.ntc; ++q) {
             const double *o = F.cpart + ((int64_t)q * p + j) * 3;
@@ -694,14 +782,13 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     }
     __syncthreads();
     const int action = s_action;
-    if (action == 0) {   // final: the state and the estimate go to the host
-        if (t == 0) *F.hst = *st;
-        for (int j = t; j < p; j += kStepThreads) F.hbeta[j] = F.beta[j];
+    if (action == 0) {   // final: the estimate and the state go to the host
+        publish_final<NT>(F, st, t, ndone);
         return;
     }
     if (action == 1) {
-        for (int j = t; j < p; j += kStepThreads) F.beta[j] = F.prev[j] + 0.5 * (F.beta[j] - F.prev[j]);
-        if (t == 0) *F.hst = *st;
+        for (int j = t; j < p; j += NT) F.beta[j] = F.prev[j] + 0.5 * (F.beta[j] - F.prev[j]);
+        if (t == 0) publish_state(F, *st);
         return;
     }
     // the columns that move: chosen once, at the first evaluation (g'' > 1e-12 S2-term)
@@ -709,7 +796,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
         __shared__ int s_moved;
         if (t == 0) s_moved = 0;
         __syncthreads();
-        for (int j = t; j < p; j += kStepThreads) {
+        for (int j = t; j < p; j += NT) {
             const double hd = F.diag1[j] - F.diag2[j];
             const bool fr = hd > 1e-12 * fabs(F.diag1[j]) && isfinite(hd);
             F.free_col[j] = fr ? 1 : 0;
@@ -723,18 +810,18 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
         if (s_moved) {   // evaluate again at the start point with those columns at zero
             if (t == 0) {
                 st->flags |= kHaveFree;
-                *F.hst = *st;
+                publish_state(F, *st);
             }
             return;
         }
     }
     const bool frozen = s_frozen != 0;
     const int wv = t / kWave, lane = t & (kWave - 1);
-    constexpr int kWaves = kStepThreads / kWave;
-    for (int j = t; j < p; j += kStepThreads) s_free[j] = F.free_col[j];
+    constexpr int kWaves = NT / kWave;
+    for (int j = t; j < p; j += NT) s_free[j] = F.free_col[j];
     __syncthreads();
     if (F.gam) {
-        prox_step(F, A, y, s_free, s_red, t, wv, lane);
+        prox_step<NT>(F, A, y, s_free, s_red, t, wv, lane);
     } else if (!frozen) {
         // Blocked right-looking Cholesky of the information matrix (info kernel; rows and
         // columns not free become unit rows) in LDS, lower triangle, panels of 16 columns:
@@ -780,7 +867,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
             }
             __syncthreads();
             // rows below the block: x L_kk' = A[i][k0 .. k0 + kb)
-            for (int i = k0 + kb + t; i < p; i += kStepThreads) {
+            for (int i = k0 + kb + t; i < p; i += NT) {
                 double x[NB];
 #pragma unroll
                 for (int c = 0; c < NB; ++c) x[c] = c < kb ? A[i * p + k0 + c] : 0.0;
@@ -801,7 +888,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
             // trailing triangle rows/columns m0 .. p-1, 4 x 4 tiles (ti >= tj)
             const int m0 = k0 + kb, mt = (p - m0 + 3) / 4;
             const int ntile = mt * (mt + 1) / 2;
-            for (int q = t; q < ntile; q += kStepThreads) {
+            for (int q = t; q < ntile; q += NT) {
                 int ti = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
                 while (ti * (ti + 1) / 2 > q) --ti;
                 while ((ti + 1) * (ti + 2) / 2 <= q) ++ti;
@@ -844,7 +931,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     if (!F.gam) {
         // score on the free columns; kkt = max |score|
         double kk = 0.0;
-        for (int j = t; j < p; j += kStepThreads) {
+        for (int j = t; j < p; j += NT) {
             const double gj = s_free[j] ? F.grad[j] : 0.0;
             y[j] = -gj;
             kk = fmax(kk, fabs(gj));
@@ -881,7 +968,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     }
     __syncthreads();
     double smax = 0.0, bmax = 0.0;
-    for (int j = t; j < p; j += kStepThreads) {
+    for (int j = t; j < p; j += NT) {
         const double dx = s_free[j] ? y[j] : 0.0;
         const double b0 = F.beta[j];
         const double b1 = b0 + dx;
@@ -892,7 +979,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     }
     smax = wave_max(smax);
     bmax = wave_max(bmax);
-    __shared__ double s_s[kStepThreads / kWave], s_b[kStepThreads / kWave];
+    __shared__ double s_s[NT / kWave], s_b[NT / kWave];
     if ((t & (kWave - 1)) == 0) {
         s_s[t / kWave] = smax;
         s_b[t / kWave] = bmax;
@@ -900,7 +987,7 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
     __syncthreads();
     if (t == 0) {
         double step = 0.0, bm = 1.0, kkt = 0.0;
-        for (int k = 0; k < kStepThreads / kWave; ++k) {
+        for (int k = 0; k < NT / kWave; ++k) {
             step = fmax(step, s_s[k]);
             bm = fmax(bm, s_b[k]);
             kkt = fmax(kkt, s_red[k]);
@@ -929,12 +1016,216 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits,
             }
         }
         st->flags = flags;
-        *F.hst = *st;
         s_action = (flags & kDone) ? 1 : 0;
     }
     __syncthreads();
-    if (s_action)   // final: every thread sends the entries of beta it wrote
-        for (int j = t; j < p; j += kStepThreads) F.hbeta[j] = F.beta[j];
+    if (s_action) {   // final: every thread sends the entries of beta it wrote, then the state
+        publish_final<NT>(F, st, t, ndone);
+    } else if (t == 0) {
+        publish_state(F, *st);
+    }
+}
+
+__global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits, const int *slots)
+{
+    extern __shared__ double lds[];   // A[p * p], y[p]
+    step_fit<kStepThreads>(fits, slots[blockIdx.x], lds, nullptr);
+}
+
+// ------------------------------------------------------------------ persistent rounds
+
+// Control block of one persistent launch (device memory, cleared before the launch).
+struct RoundCtl {
+    SyncCtl sync;                  // abort word of the bounded waits
+    uint32_t ndone;                // fits that finished during the launch
+    uint32_t hold[2];              // the host's hold word as workgroup 0 read it, by round parity
+    uint32_t pad[61];
+    Packet arrive[kRoundMaxGrid];  // epoch of the last barrier each workgroup reached
+};
+
+// Grid-wide barrier of the persistent round kernel.  Every wave waits for its
+// stores to reach the L2 of its XCD; one thread per workgroup then writes that
+// L2 back (agent-scope fence: the XCDs' L2 caches are kept coherent only
+// through such fences, and one write-back covers the stores of all the
+// workgroup's waves) and publishes its arrival packet; wave 0 of every
+// workgroup polls all arrival packets (a workgroup that has gone on to a later
+// barrier counts as arrived) and fences again before anything written by
+// another workgroup is read.  At the barrier that ends a round every workgroup
+// takes the same decision from the same data: go on while rounds remain, fits
+// remain unfinished (the counter the step phase raises) and the host had not
+// asked for the launch to end when workgroup 0 arrived (its reading of the hold
+// word, stored before its arrival).  Every wait is bounded.  Returns 1 to go
+// on, 0 to stop, -1 when a wait timed out.
+__device__ int round_barrier(const RoundWork &w, RoundCtl *ctl, uint32_t epoch, bool end_of_round, int round,
+                             int *s_word)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int t = threadIdx.x;
+    const PacketArray arrive = packet_array(ctl->arrive, sizeof(Packet) * gridDim.x);
+    if (t == 0) {
+        if (end_of_round && blockIdx.x == 0) {
+            const uint32_t h = __hip_atomic_load(w.hold, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&ctl->hold[round & 1], h != 0u ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        packet_put(arrive, blockIdx.x, 0.0, epoch, 0u);
+    }
+    if (t < kWave) {
+        bool ok = true;
+        for (int k = t; k < (int)gridDim.x && ok; k += kWave) {
+            WaitBudget wb;
+            while (packet_get(arrive, (uint32_t)k).z < epoch)
+                if (!wb.keep_waiting(&ctl->sync)) {
+                    ok = false;
+                    break;
+                }
+        }
+        const bool all_ok = __all(ok ? 1 : 0) != 0;
+        if (t == 0) {
+            int go = -1;
+            if (all_ok) {
+                __threadfence();
+                go = 1;
+                if (end_of_round) {
+                    const uint32_t nd = __hip_atomic_load(&ctl->ndone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t hold = __hip_atomic_load(&ctl->hold[round & 1], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                    go = (round + 1 < w.max_rounds && (int)nd < w.nf && hold == 0u) ? 1 : 0;
+                }
+            }
+            *s_word = go;
+        }
+    }
+    __syncthreads();
+    const int go = *s_word;
+    __syncthreads();   // s_word is rewritten by the next barrier
+    return go;
+}
+
+__device__ __forceinline__ int fit_flags(const FitDesc *fits, int slot) { return fits[slot].st->flags; }
+
+// Persistent round kernel: up to max_rounds Newton iterations of every fit in the work
+// lists, the six phases of a round separated by grid-wide barriers (one cooperative
+// launch; every workgroup resident).  Each phase's items are dealt out over the workgroups
+// first (eta, syrk, info: to half-workgroups of 256 threads; cols: to waves; rows and step:
+// to whole workgroups), so a light phase spreads over many CUs, and run the same bodies as
+// the separate launches, so every fit's sums are the same.  Fits that finish are left out of the later rounds, fits whose information
+// matrix is frozen out of the contraction.  lds: the step's A[p * p], y[p], and during the
+// contraction the two half-workgroups' reduction buffers.
+__global__ __launch_bounds__(kRoundThreads) void round_kernel(RoundWork w)
+{
+    extern __shared__ double lds[];
+    __shared__ double s_eta_red[2][kEtaRows / kWave];
+    __shared__ int s_word;
+    RoundCtl *ctl = static_cast<RoundCtl *>(w.ctl);
+    const int t = threadIdx.x, half = t / 256, th = t & 255, lane = t & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(t / kWave);
+    const int G = gridDim.x, b = blockIdx.x;
+    constexpr int kWaves = kRoundThreads / kWave;
+    uint32_t epoch = 0;
+    int rounds = 0, status = 0;
+    // workgroup 0 times the phases between barrier releases (constant-rate clock)
+    __shared__ uint64_t s_ticks[7];   // six phases, then the last release
+    const bool timer = b == 0 && t == 0;
+    if (timer) {
+        for (int k = 0; k < 6; ++k) s_ticks[k] = 0;
+        s_ticks[6] = wall_clock64();
+    }
+    auto lap = [&](int ph) {
+        if (timer) {
+            const uint64_t now = wall_clock64();
+            s_ticks[ph] += now - s_ticks[6];
+            s_ticks[6] = now;
+        }
+    };
+    for (int round = 0;; ++round) {
+        // X beta: half-workgroup items
+        for (int base = 0; base < w.ne; base += 2 * G) {
+            const int i = __builtin_amdgcn_readfirstlane(base + half * G + b);
+            int2 it = make_int2(0, 0);
+            bool live = false;
+            if (i < w.ne) {
+                it = w.eta[i];
+                live = !(fit_flags(w.fits, it.x) & kDone);
+            }
+            eta_item(w.fits, it, live, th, s_eta_red[half]);
+        }
+        if (round_barrier(w, ctl, ++epoch, false, round, &s_word) < 0) {
+            status = -1;
+            break;
+        }
+        lap(0);
+        // row scans: workgroup items
+        for (int i = b; i < w.nr; i += G) {
+            const int2 it = w.rows[i];
+            if (!(fit_flags(w.fits, it.x) & kDone)) rows_item(w.fits, it);
+        }
+        if (round_barrier(w, ctl, ++epoch, false, round, &s_word) < 0) {
+            status = -1;
+            break;
+        }
+        lap(1);
+        // column pass: wave items
+        for (int i = wv * G + b; i < w.nc; i += kWaves * G) {
+            const int2 it = w.cols[i];
+            if (!(fit_flags(w.fits, it.x) & kDone)) cols_item<false>(w.fits, it);
+        }
+        if (round_barrier(w, ctl, ++epoch, false, round, &s_word) < 0) {
+            status = -1;
+            break;
+        }
+        lap(2);
+        if (w.ns > 0) {
+            // contraction: half-workgroup items
+            float *red = reinterpret_cast<float *>(lds) + half * kSyrkRed;
+            for (int base = 0; base < w.ns; base += 2 * G) {
+                const int i = __builtin_amdgcn_readfirstlane(base + half * G + b);
+                int4 it = make_int4(0, 0, 0, 0);
+                bool live = false;
+                if (i < w.ns) {
+                    it = w.syrk[i];
+                    live = !(fit_flags(w.fits, it.x) & (kDone | kFrozen));
+                }
+                syrk_item(w.fits, it, live, wv & (kSyrkWaves - 1), lane, red);
+            }
+            if (round_barrier(w, ctl, ++epoch, false, round, &s_word) < 0) {
+                status = -1;
+                break;
+            }
+            lap(3);
+            for (int base = 0; base < w.ni; base += 2 * G) {
+                const int i = __builtin_amdgcn_readfirstlane(base + half * G + b);
+                if (i < w.ni) {
+                    const int2 it = w.info[i];
+                    if (!(fit_flags(w.fits, it.x) & (kDone | kFrozen))) info_item(w.fits, it, th);
+                }
+            }
+            if (round_barrier(w, ctl, ++epoch, false, round, &s_word) < 0) {
+                status = -1;
+                break;
+            }
+            lap(4);
+        }
+        // step: workgroup items
+        for (int i = b; i < w.nf; i += G) {
+            const int slot = w.slots[i];
+            if (!(fit_flags(w.fits, slot) & kDone)) step_fit<kRoundThreads>(w.fits, slot, lds, &ctl->ndone);
+        }
+        const int go = round_barrier(w, ctl, ++epoch, true, round, &s_word);
+        if (go < 0) {
+            status = -1;
+            break;
+        }
+        lap(5);
+        rounds = round + 1;
+        if (go == 0) break;
+    }
+    if (b == 0 && t == 0) {
+        w.hout[0] = (uint64_t)rounds;
+        w.hout[1] = status < 0 ? 1u : 0u;
+        for (int k = 0; k < 6; ++k) w.hout[2 + k] = s_ticks[k];
+    }
 }
 
 }  // namespace
@@ -990,6 +1281,46 @@ int launch_step(const FitDesc *fits, const int *slots, int nslots, int max_p, hi
     }
     step_kernel<<<nslots, kStepThreads, lds, s>>>(fits, slots);
     return (int)hipGetLastError();
+}
+
+size_t round_ctl_bytes() { return sizeof(RoundCtl); }
+
+size_t round_lds_bytes(int max_p)
+{
+    const size_t step = sizeof(double) * ((size_t)max_p * max_p + max_p);
+    const size_t red = sizeof(float) * 2 * kSyrkRed;
+    return step > red ? step : red;
+}
+
+int round_grid(int max_p, int *grid)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&round_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)round_lds_bytes(kMaxP));
+        if (e != hipSuccess) return (int)e;
+        attr_set = true;
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&round_kernel),
+                                                         kRoundThreads, round_lds_bytes(max_p));
+    if (e != hipSuccess) return (int)e;
+    const int g = cus * per_cu;
+    *grid = g < kRoundMaxGrid ? g : kRoundMaxGrid;
+    return 0;
+}
+
+int launch_rounds(const RoundWork &w, int grid, hipStream_t s)
+{
+    if (w.nf <= 0 || grid < 1 || grid > kRoundMaxGrid) return (int)hipErrorInvalidValue;
+    RoundWork a = w;
+    void *args[] = {(void *)&a};
+    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&round_kernel), dim3((unsigned)grid),
+                                              dim3(kRoundThreads), args, (unsigned)round_lds_bytes(w.max_p), s);
+    return (int)e;
 }
 
 }  // namespace serve

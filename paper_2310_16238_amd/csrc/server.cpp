@@ -10,7 +10,11 @@
 //   worker      owns the GPU: admits staged requests into free slots of the
 //               device arena while the previous iteration runs (uploads on a
 //               copy stream), runs one batched Newton iteration of every
-//               resident fit, reads the fits' states back, retires finished fits
+//               resident fit, reads the fits' states back, retires finished fits.
+//               With fused_rounds > 0 one persistent launch runs many iterations
+//               (serve.hip, round_kernel); the worker reports fits as they finish
+//               (from host-mapped state), admits while it runs, and asks it to end
+//               after the current iteration when new fits are ready to join
 //
 // Admission is first come, first served, by device footprint: a request is
 // admitted when a slot is free and its block fits in the arena; the fits
@@ -220,6 +224,7 @@ struct Result {
 
 struct Slot {
     bool used = false, active = false, frozen = false;
+    bool reported = false;   // its result went to the caller while the launch still ran
     std::unique_ptr<Request> req;
     size_t arena_off = 0;
     double t_admit = 0.0;
@@ -243,6 +248,10 @@ struct cox_server {
     FitDesc *h_desc = nullptr;
     FitState *h_state = nullptr, *dh_state = nullptr;   // host-mapped (and its device address)
     double *h_beta = nullptr, *dh_beta = nullptr;
+    // persistent rounds: control block, host-mapped hold word and launch results
+    void *d_round_ctl = nullptr;
+    uint64_t *h_round = nullptr, *dh_round = nullptr;   // [0] hold word; [2..9] the launch's results
+    int round_grid_p = -1, round_grid = 0;                // most workgroups for fits of at most round_grid_p columns
 
     // work lists: pinned host copies and device arrays (capacity in bytes)
     struct List {
@@ -265,8 +274,9 @@ struct cox_server {
     std::string err, fatal_msg;
 
     // statistics (worker thread; read under mu)
-    int64_t submitted = 0, completed = 0, iterations = 0, resident_peak = 0;
+    int64_t submitted = 0, completed = 0, iterations = 0, resident_peak = 0, launches = 0;
     double resident_sum = 0.0, gpu_busy_s = 0.0;
+    double phase_s[6] = {0, 0, 0, 0, 0, 0};
 
     std::vector<std::thread> preps;
     std::thread worker;
@@ -577,7 +587,11 @@ bool admit_ready(cox_server *s, WorkerState &ws, std::string &err)
             S.used = true;
             S.active = false;
             S.frozen = false;
+            S.reported = false;
             S.arena_off = off;
+            // the host mirror still holds the previous occupant's final state; no kernel
+            // writes it until this fit's first step
+            std::memset(static_cast<void *>(&s->h_state[slot]), 0, sizeof(FitState));
             S.t_admit = s->now();
             taken.emplace_back(slot, std::move(s->ready_q.front()));
             s->ready_q.pop_front();
@@ -632,135 +646,292 @@ bool admit_ready(cox_server *s, WorkerState &ws, std::string &err)
     return true;
 }
 
-bool run_round(cox_server *s, WorkerState &ws, std::string &err)
+// The result of the fit in slot sl from its host-mapped state and estimate.
+Result make_result(const cox_server *s, int sl, double t_done)
 {
-    // fits uploaded in the previous round join this round
-    std::vector<int> joining;
+    const Slot &S = s->slots[sl];
+    const FitState &st = s->h_state[sl];
+    Result r;
+    r.beta.assign(s->h_beta + (size_t)sl * kMaxP, s->h_beta + (size_t)sl * kMaxP + S.req->p);
+    r.info.status = st.status;
+    r.info.iters = st.iters;
+    r.info.coord_evals = st.evals;
+    r.info.objective = st.obj;
+    r.info.kkt_inf = st.kkt;
+    r.info.last_step = st.last_step;
+    r.info.n_pinned = st.n_pinned;
+    r.times.submit_s = S.req->t_submit;
+    r.times.admit_s = S.t_admit;
+    r.times.done_s = t_done;
+    return r;
+}
+
+// Work lists of one round (or persistent launch) over the fits in `act`, written to the
+// round block and copied to the device on the compute stream.
+struct RoundLists {
+    size_t o_eta = 0, o_rows = 0, o_cols = 0, o_syrk = 0, o_info = 0, o_slots = 0;
+    size_t ke = 0, kr = 0, kc = 0, ks = 0, ki = 0;
+    int max_p = 1;
+};
+
+bool build_lists(cox_server *s, const std::vector<int> &act, RoundLists &R, std::string &err)
+{
+    size_t n_eta = 0, n_rows = 0, n_cols = 0, n_syrk = 0, n_info = 0;
+    for (int sl : act) {
+        const FitLayout &L = s->slots[sl].req->lay;
+        n_eta += L.ntile;
+        n_rows += L.ntc;
+        n_cols += (size_t)L.ntc * ((L.p + kColBlock - 1) / kColBlock);
+        if (!s->slots[sl].frozen) {
+            n_syrk += (size_t)L.npairs * (L.nxr + L.nzr);
+            n_info += L.npairs;
+        }
+    }
+    Packer pk;
+    R.o_eta = pk.take<int2>(n_eta);
+    R.o_rows = pk.take<int2>(n_rows);
+    R.o_cols = pk.take<int2>(n_cols);
+    R.o_syrk = pk.take<int4>(n_syrk);
+    R.o_info = pk.take<int2>(n_info);
+    R.o_slots = pk.take<int>(act.size());
+    if (!ensure_list(s->l_round, pk.used, err)) return false;
+    char *H = s->l_round.h, *D = s->l_round.d;
+    int2 *eta = reinterpret_cast<int2 *>(H + R.o_eta);
+    int2 *rws = reinterpret_cast<int2 *>(H + R.o_rows);
+    int2 *cols = reinterpret_cast<int2 *>(H + R.o_cols);
+    int4 *syrk = reinterpret_cast<int4 *>(H + R.o_syrk);
+    int2 *info = reinterpret_cast<int2 *>(H + R.o_info);
+    int *sl_list = reinterpret_cast<int *>(H + R.o_slots);
+    size_t ke = 0, kr = 0, kc = 0, ks = 0, ki = 0;
+    int max_p = 1;
+    for (size_t a = 0; a < act.size(); ++a) {
+        const int sl = act[a];
+        const FitLayout &L = s->slots[sl].req->lay;
+        sl_list[a] = sl;
+        max_p = std::max(max_p, L.p);
+        for (int t = 0; t < L.ntile; ++t) eta[ke++] = make_int2(sl, t);
+        for (int t = 0; t < L.ntc; ++t) {
+            rws[kr++] = make_int2(sl, t);
+            for (int j = 0; j < L.p; j += kColBlock) cols[kc++] = make_int2(sl, (t << 10) | j);
+        }
+        if (!s->slots[sl].frozen)
+            for (int pr = 0; pr < L.npairs; ++pr) {
+                info[ki++] = make_int2(sl, pr);
+                for (int r = 0; r < L.nxr; ++r) syrk[ks++] = make_int4(sl, pr, r, 0);
+                for (int r = 0; r < L.nzr; ++r) syrk[ks++] = make_int4(sl, pr, r, 1);
+            }
+    }
+    if (ke != n_eta || kr != n_rows || kc != n_cols || ks != n_syrk || ki != n_info) {
+        err = "internal error: work list sizes";
+        return false;
+    }
+    R.ke = ke;
+    R.kr = kr;
+    R.kc = kc;
+    R.ks = ks;
+    R.ki = ki;
+    R.max_p = max_p;
+    WCHECK(hipMemcpyAsync(D, H, pk.used, hipMemcpyHostToDevice, s->compute), "work lists");
+    return true;
+}
+
+// The fits of the next round: those resident and those whose upload was queued in the
+// previous round (the compute stream waits for that upload).
+bool next_round_fits(cox_server *s, WorkerState &ws, std::vector<int> &act, std::vector<int> &joining,
+                     std::string &err)
+{
     if (ws.copy_pending) {
         WCHECK(hipStreamWaitEvent(s->compute, ws.copy_ev, 0), "ordering the upload");
         joining.swap(ws.uploading);
         ws.copy_pending = false;
     }
-    std::vector<int> act;
     for (int i = 0; i < (int)s->slots.size(); ++i)
         if (s->slots[i].used && (s->slots[i].active || std::find(joining.begin(), joining.end(), i) != joining.end()))
             act.push_back(i);
     for (int sl : joining) s->slots[sl].active = true;
-    const bool launched = !act.empty();
-    double t_launch = s->now();
-    if (launched) {
-        // sizes of the lists
-        size_t n_eta = 0, n_rows = 0, n_cols = 0, n_syrk = 0, n_info = 0;
-        for (int sl : act) {
-            const FitLayout &L = s->slots[sl].req->lay;
-            n_eta += L.ntile;
-            n_rows += L.ntc;
-            n_cols += (size_t)L.ntc * ((L.p + kColBlock - 1) / kColBlock);
-            if (!s->slots[sl].frozen) {
-                n_syrk += (size_t)L.npairs * (L.nxr + L.nzr);
-                n_info += L.npairs;
-            }
-        }
-        Packer pk;
-        const size_t o_eta = pk.take<int2>(n_eta), o_rows = pk.take<int2>(n_rows);
-        const size_t o_cols = pk.take<int2>(n_cols), o_syrk = pk.take<int4>(n_syrk), o_info = pk.take<int2>(n_info);
-        const size_t o_slots = pk.take<int>(act.size());
-        if (!ensure_list(s->l_round, pk.used, err)) return false;
-        char *H = s->l_round.h, *D = s->l_round.d;
-        int2 *eta = reinterpret_cast<int2 *>(H + o_eta);
-        int2 *rws = reinterpret_cast<int2 *>(H + o_rows);
-        int2 *cols = reinterpret_cast<int2 *>(H + o_cols);
-        int4 *syrk = reinterpret_cast<int4 *>(H + o_syrk);
-        int2 *info = reinterpret_cast<int2 *>(H + o_info);
-        int *sl_list = reinterpret_cast<int *>(H + o_slots);
-        size_t ke = 0, kr = 0, kc = 0, ks = 0, ki = 0;
-        int max_p = 1;
-        for (size_t a = 0; a < act.size(); ++a) {
-            const int sl = act[a];
-            const FitLayout &L = s->slots[sl].req->lay;
-            sl_list[a] = sl;
-            max_p = std::max(max_p, L.p);
-            for (int t = 0; t < L.ntile; ++t) eta[ke++] = make_int2(sl, t);
-            for (int t = 0; t < L.ntc; ++t) {
-                rws[kr++] = make_int2(sl, t);
-                for (int j = 0; j < L.p; j += kColBlock) cols[kc++] = make_int2(sl, (t << 10) | j);
-            }
-            if (!s->slots[sl].frozen)
-                for (int pr = 0; pr < L.npairs; ++pr) {
-                    info[ki++] = make_int2(sl, pr);
-                    for (int r = 0; r < L.nxr; ++r) syrk[ks++] = make_int4(sl, pr, r, 0);
-                    for (int r = 0; r < L.nzr; ++r) syrk[ks++] = make_int4(sl, pr, r, 1);
-                }
-        }
-        if (ke != n_eta || kr != n_rows || kc != n_cols || ks != n_syrk || ki != n_info) {
-            err = "internal error: work list sizes";
-            return false;
-        }
-        WCHECK(hipMemcpyAsync(D, H, pk.used, hipMemcpyHostToDevice, s->compute), "work lists");
-        WCHECK((hipError_t)launch_eta(s->d_desc, reinterpret_cast<const int2 *>(D + o_eta), (int)ke, s->compute), "eta");
-        WCHECK((hipError_t)launch_rows(s->d_desc, reinterpret_cast<const int2 *>(D + o_rows), (int)kr, s->compute),
-               "rows");
-        WCHECK((hipError_t)launch_cols(s->d_desc, reinterpret_cast<const int2 *>(D + o_cols), (int)kc, s->compute),
-               "cols");
-        if (ks) {
-            WCHECK((hipError_t)launch_syrk(s->d_desc, reinterpret_cast<const int4 *>(D + o_syrk), (int)ks, s->compute),
-                   "syrk");
-            WCHECK((hipError_t)launch_info(s->d_desc, reinterpret_cast<const int2 *>(D + o_info), (int)ki, s->compute),
-                   "info");
-        }
-        WCHECK((hipError_t)launch_step(s->d_desc, reinterpret_cast<const int *>(D + o_slots), (int)act.size(), max_p,
-                                       s->compute),
-               "step");
-        // the step kernel writes each fit's state (and a final estimate) to host-mapped memory
-        WCHECK(hipEventRecord(s->iter_ev, s->compute), "recording the iteration");
-    }
-    // 3. while the GPU iterates: admit what the prep pool has staged (uploads on the copy stream)
-    if (!admit_ready(s, ws, err)) return false;
-    if (!launched) {
-        // nothing resident: the staging of this round's uploads is released next round
-        return true;
-    }
-    WCHECK(hipEventSynchronize(s->iter_ev), "iteration");
-    const double t_done = s->now();
-    // staging of the fits that joined this round has been copied (the compute stream waited on it)
+    return true;
+}
+
+// After a round or a launch: release the staging of the fits that joined, retire the
+// finished fits (reporting those not reported yet), note which factors are frozen.
+void retire_fits(cox_server *s, const std::vector<int> &act, const std::vector<int> &joining, double t_launch,
+                 double t_done, int64_t rounds, double resident_rounds)
+{
     {
         std::lock_guard<std::mutex> g(s->mu);
         for (int sl : joining) s->stage_alloc.release(s->slots[sl].req->stage_off, s->slots[sl].req->lay.upload);
     }
     if (!joining.empty()) s->cv_stage.notify_all();
-    // 4. retire finished fits
     std::vector<int> done;
     for (int sl : act) {
         const FitState &st = s->h_state[sl];
         if (st.flags & kDone) done.push_back(sl);
         else s->slots[sl].frozen = (st.flags & kFrozen) != 0;
     }
+    std::lock_guard<std::mutex> g(s->mu);
+    s->iterations += rounds;
+    s->resident_sum += resident_rounds;
+    s->resident_peak = std::max<int64_t>(s->resident_peak, (int64_t)act.size());
+    s->gpu_busy_s += t_done - t_launch;
+    for (int sl : done) {
+        Slot &S = s->slots[sl];
+        s->arena_alloc.release(S.arena_off, S.req->lay.total);
+        if (!S.reported) finish_locked(s, S.req->ticket, make_result(s, sl, t_done));
+        S = Slot();
+    }
+}
+
+bool run_round(cox_server *s, WorkerState &ws, std::string &err)
+{
+    // fits uploaded in the previous round join this round
+    std::vector<int> joining, act;
+    if (!next_round_fits(s, ws, act, joining, err)) return false;
+    const bool launched = !act.empty();
+    double t_launch = s->now();
+    if (launched) {
+        RoundLists R;
+        if (!build_lists(s, act, R, err)) return false;
+        const char *D = s->l_round.d;
+        WCHECK((hipError_t)launch_eta(s->d_desc, reinterpret_cast<const int2 *>(D + R.o_eta), (int)R.ke, s->compute),
+               "eta");
+        WCHECK((hipError_t)launch_rows(s->d_desc, reinterpret_cast<const int2 *>(D + R.o_rows), (int)R.kr, s->compute),
+               "rows");
+        WCHECK((hipError_t)launch_cols(s->d_desc, reinterpret_cast<const int2 *>(D + R.o_cols), (int)R.kc, s->compute),
+               "cols");
+        if (R.ks) {
+            WCHECK((hipError_t)launch_syrk(s->d_desc, reinterpret_cast<const int4 *>(D + R.o_syrk), (int)R.ks,
+                                           s->compute),
+                   "syrk");
+            WCHECK((hipError_t)launch_info(s->d_desc, reinterpret_cast<const int2 *>(D + R.o_info), (int)R.ki,
+                                           s->compute),
+                   "info");
+        }
+        WCHECK((hipError_t)launch_step(s->d_desc, reinterpret_cast<const int *>(D + R.o_slots), (int)act.size(),
+                                       R.max_p, s->compute),
+               "step");
+        // the step kernel writes each fit's state (and a final estimate) to host-mapped memory
+        WCHECK(hipEventRecord(s->iter_ev, s->compute), "recording the iteration");
+    }
+    // while the GPU iterates: admit what the prep pool has staged (uploads on the copy stream)
+    if (!admit_ready(s, ws, err)) return false;
+    if (!launched) {
+        // nothing resident: the staging of this round's uploads is released next round
+        return true;
+    }
+    WCHECK(hipEventSynchronize(s->iter_ev), "iteration");
+    retire_fits(s, act, joining, t_launch, s->now(), 1, (double)act.size());
+    return true;
+}
+
+// One persistent launch of up to fused_rounds rounds over the resident fits.  While it runs
+// the worker reports fits whose host-mapped state says they are done (the kernel writes
+// the estimate before the final state), admits staged requests once (uploads and the
+// admit kernel on the copy stream), and sets the hold word -- the launch then ends after
+// its current round -- when fits are ready to join or waiting requests could take the
+// place of finished ones.  Slots and arena blocks are released only after the launch.
+bool run_launch_fused(cox_server *s, WorkerState &ws, std::string &err)
+{
+    std::vector<int> joining, act;
+    if (!next_round_fits(s, ws, act, joining, err)) return false;
+    const double t_launch = s->now();
+    if (act.empty()) return admit_ready(s, ws, err);
+    RoundLists R;
+    if (!build_lists(s, act, R, err)) return false;
+    if (R.max_p != s->round_grid_p) {
+        int g = 0;
+        WCHECK((hipError_t)round_grid(R.max_p, &g), "sizing the round launch");
+        if (g < 1) {
+            err = "the round kernel does not fit on the device";
+            return false;
+        }
+        s->round_grid_p = R.max_p;
+        s->round_grid = g;
+    }
+    // workgroups: one per item of the largest phase (items are dealt over workgroups first),
+    // a multiple of the 8 XCDs, at most what fits on the device at once
+    const size_t need = std::max({R.ke, R.kr, R.kc, R.ks, R.ki, act.size()});
+    const int grid = (int)std::min<size_t>((size_t)s->round_grid, std::max<size_t>(8, (need + 7) / 8 * 8));
+    std::vector<int> evals0(act.size());
+    for (size_t a = 0; a < act.size(); ++a) evals0[a] = s->h_state[act[a]].evals;
+    uint32_t *hold = reinterpret_cast<uint32_t *>(s->h_round);
+    __atomic_store_n(hold, 0u, __ATOMIC_SEQ_CST);
+    for (int k = 2; k < 10; ++k) s->h_round[k] = 0u;
+    WCHECK(hipMemsetAsync(s->d_round_ctl, 0, round_ctl_bytes(), s->compute), "clearing the round control block");
+    const char *D = s->l_round.d;
+    RoundWork w{};
+    w.fits = s->d_desc;
+    w.eta = reinterpret_cast<const int2 *>(D + R.o_eta);
+    w.rows = reinterpret_cast<const int2 *>(D + R.o_rows);
+    w.cols = reinterpret_cast<const int2 *>(D + R.o_cols);
+    w.syrk = reinterpret_cast<const int4 *>(D + R.o_syrk);
+    w.info = reinterpret_cast<const int2 *>(D + R.o_info);
+    w.slots = reinterpret_cast<const int *>(D + R.o_slots);
+    w.ne = (int)R.ke;
+    w.nr = (int)R.kr;
+    w.nc = (int)R.kc;
+    w.ns = (int)R.ks;
+    w.ni = (int)R.ki;
+    w.nf = (int)act.size();
+    w.max_rounds = s->opt.fused_rounds;
+    w.max_p = R.max_p;
+    w.hold = reinterpret_cast<const uint32_t *>(s->dh_round);
+    w.ctl = s->d_round_ctl;
+    w.hout = s->dh_round + 2;
+    WCHECK((hipError_t)launch_rounds(w, grid, s->compute), "round kernel");
+    WCHECK(hipEventRecord(s->iter_ev, s->compute), "recording the launch");
+    bool admitted = false, held = false;
+    std::vector<char> seen(act.size(), 0);
+    for (;;) {
+        const hipError_t q = hipEventQuery(s->iter_ev);
+        if (q != hipSuccess && q != hipErrorNotReady) {
+            err = std::string("round kernel: ") + hipGetErrorString(q);
+            return false;
+        }
+        // fits that finished: their estimate and state are complete once kDone is visible
+        std::vector<int> newly;
+        for (size_t a = 0; a < act.size(); ++a)
+            if (!seen[a] && (__atomic_load_n(&s->h_state[act[a]].flags, __ATOMIC_ACQUIRE) & kDone)) {
+                seen[a] = 1;
+                newly.push_back(act[a]);
+            }
+        bool waiting = false;
+        if (!newly.empty() || !held) {
+            std::lock_guard<std::mutex> g(s->mu);
+            const double t = s->now();
+            for (int sl : newly) {
+                finish_locked(s, s->slots[sl].req->ticket, make_result(s, sl, t));
+                s->slots[sl].reported = true;
+            }
+            waiting = !s->ready_q.empty() || s->stop;
+        }
+        if (q == hipSuccess) break;
+        if (!held) {
+            if (waiting && !admitted) {
+                if (!admit_ready(s, ws, err)) return false;
+                admitted = ws.copy_pending;
+            }
+            bool any_done = false;
+            for (char c : seen) any_done |= c != 0;
+            if (admitted || (waiting && any_done)) {
+                __atomic_store_n(hold, 1u, __ATOMIC_SEQ_CST);
+                held = true;
+            }
+        }
+        std::this_thread::yield();
+    }
+    const double t_done = s->now();
+    if (s->h_round[3] != 0u) {
+        err = "round kernel: a grid-wide wait timed out; results are not valid";
+        return false;
+    }
+    double resident_rounds = 0.0;
+    for (size_t a = 0; a < act.size(); ++a) resident_rounds += (double)(s->h_state[act[a]].evals - evals0[a]);
     {
         std::lock_guard<std::mutex> g(s->mu);
-        s->iterations += 1;
-        s->resident_sum += (double)act.size();
-        s->resident_peak = std::max<int64_t>(s->resident_peak, (int64_t)act.size());
-        s->gpu_busy_s += t_done - t_launch;
-        for (int sl : done) {
-            Slot &S = s->slots[sl];
-            const FitState &st = s->h_state[sl];
-            Result r;
-            r.beta.assign(s->h_beta + (size_t)sl * kMaxP, s->h_beta + (size_t)sl * kMaxP + S.req->p);
-            r.info.status = st.status;
-            r.info.iters = st.iters;
-            r.info.coord_evals = st.evals;
-            r.info.objective = st.obj;
-            r.info.kkt_inf = st.kkt;
-            r.info.last_step = st.last_step;
-            r.info.n_pinned = st.n_pinned;
-            r.times.submit_s = S.req->t_submit;
-            r.times.admit_s = S.t_admit;
-            r.times.done_s = t_done;
-            s->arena_alloc.release(S.arena_off, S.req->lay.total);
-            finish_locked(s, S.req->ticket, std::move(r));
-            S = Slot();
-        }
+        s->launches += 1;
+        for (int k = 0; k < 6; ++k) s->phase_s[k] += 1e-8 * (double)s->h_round[4 + k];   // 100 MHz clock
     }
+    retire_fits(s, act, joining, t_launch, t_done, (int64_t)s->h_round[2], resident_rounds);
     return true;
 }
 
@@ -787,7 +958,7 @@ void worker_loop(cox_server *s)
                 break;
             }
         }
-        if (!run_round(s, ws, err)) {
+        if (!(s->opt.fused_rounds > 0 ? run_launch_fused(s, ws, err) : run_round(s, ws, err))) {
             std::lock_guard<std::mutex> g(s->mu);
             s->fatal = COX_EDEVICE;
             s->fatal_msg = err;
@@ -826,6 +997,8 @@ void free_server(cox_server *s)
     if (s->h_desc) (void)hipHostFree(s->h_desc);
     if (s->h_state) (void)hipHostFree(s->h_state);
     if (s->h_beta) (void)hipHostFree(s->h_beta);
+    if (s->d_round_ctl) (void)hipFree(s->d_round_ctl);
+    if (s->h_round) (void)hipHostFree(s->h_round);
     for (cox_server::List *l : {&s->l_round, &s->l_admit[0], &s->l_admit[1]}) {
         if (l->h) (void)hipHostFree(l->h);
         if (l->d) (void)hipFree(l->d);
@@ -849,6 +1022,7 @@ extern "C" void cox_server_default_options(cox_server_options *o)
     o->tol = 1e-12;
     o->max_iter = 100;
     o->device = -1;
+    o->fused_rounds = 0;
 }
 
 extern "C" int cox_server_create(cox_server **out, const cox_server_options *o)
@@ -863,7 +1037,8 @@ extern "C" int cox_server_create(cox_server **out, const cox_server_options *o)
         return COX_EUNSUPPORTED;
     }
     if (opt.hbm_budget < ((size_t)1 << 20) || opt.staging_bytes < ((size_t)1 << 20) || opt.max_resident < 1 ||
-        opt.prep_threads < 1 || !(opt.tol >= 0.0) || opt.max_iter < 1) {
+        opt.prep_threads < 1 || !(opt.tol >= 0.0) || opt.max_iter < 1 || opt.fused_rounds < 0 ||
+        opt.fused_rounds > 4096) {
         g_create_error = "invalid server options";
         return COX_EINVAL;
     }
@@ -898,7 +1073,11 @@ extern "C" int cox_server_create(cox_server **out, const cox_server_options *o)
         (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_beta), sizeof(double) * kMaxP * ns,
                            hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess ||
         (e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->dh_state), s->h_state, 0)) != hipSuccess ||
-        (e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->dh_beta), s->h_beta, 0)) != hipSuccess) {
+        (e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->dh_beta), s->h_beta, 0)) != hipSuccess ||
+        (e = hipMalloc(&s->d_round_ctl, round_ctl_bytes())) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void **>(&s->h_round), 16 * sizeof(uint64_t),
+                           hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostGetDevicePointer(reinterpret_cast<void **>(&s->dh_round), s->h_round, 0)) != hipSuccess) {
         g_create_error = std::string("server allocation: ") + hipGetErrorString(e);
         free_server(s.get());
         return e == hipErrorOutOfMemory ? COX_ENOMEM : COX_EDEVICE;
@@ -1066,6 +1245,8 @@ extern "C" int cox_server_stats(cox_server *s, cox_server_counters *st)
     st->arena_peak = s->arena_alloc.peak();
     st->gpu_busy_s = s->gpu_busy_s;
     st->now_s = s->now();
+    st->launches = s->launches;
+    for (int k = 0; k < 6; ++k) st->phase_s[k] = s->phase_s[k];
     return COX_OK;
 }
 
