@@ -1,7 +1,8 @@
 // serve.hip -- batched kernels of the fit server (gfx950).
 //
 // Fits join through `admit` (descriptor, FP32 copy of X, cleared state).  One
-// Newton iteration of every resident fit is six launches:
+// Newton iteration of every resident fit is six launches (or one phase each of
+// the persistent round kernel at the end of this file):
 //   eta   (fit, 256-row tile)  X beta in FP64 and the tile's max of X beta
 //   rows  (fit, scan tile)     w = exp(X beta - c), forward segmented scan of w
 //                              (S0), d/S0 and (d/S0)/sqrt(d) at group ends and the
@@ -97,6 +98,12 @@ __global__ __launch_bounds__(256) void admit_kernel(FitDesc *fits, const FitDesc
 
 // ------------------------------------------------------------------ eta
 
+// The fit's state flags as the last step left them.  Rounds may be queued before the
+// previous one has finished, so every kernel leaves out the items of fits that have
+// finished (and the contraction those whose information matrix is frozen).
+__device__ __forceinline__ int fit_flags(const FitDesc *fits, int slot) { return fits[slot].st->flags; }
+
+
 // The phases of a round are device functions shared by the separate launches
 // below and by the persistent round kernel; a phase body makes the same sums in
 // the same order in both, so a fit's result does not depend on which runs it.
@@ -141,7 +148,8 @@ __device__ __forceinline__ void eta_item(const FitDesc *fits, int2 it, bool live
 __global__ __launch_bounds__(kEtaRows) void eta_kernel(const FitDesc *fits, const int2 *items)
 {
     __shared__ double red[kEtaRows / kWave];
-    eta_item(fits, items[blockIdx.x], true, threadIdx.x, red);
+    const int2 it = items[blockIdx.x];
+    eta_item(fits, it, !(fit_flags(fits, it.x) & kDone), threadIdx.x, red);
 }
 
 // ------------------------------------------------------------------ rows
@@ -282,7 +290,8 @@ __device__ __forceinline__ void rows_item(const FitDesc *fits, int2 it)
 
 __global__ __launch_bounds__(kRowThreads) void rows_kernel(const FitDesc *fits, const int2 *items)
 {
-    rows_item(fits, items[blockIdx.x]);
+    const int2 it = items[blockIdx.x];
+    if (!(fit_flags(fits, it.x) & kDone)) rows_item(fits, it);
 }
 
 // ------------------------------------------------------------------ cols
@@ -423,7 +432,8 @@ __global__ __launch_bounds__(kWave * kColWaves) void cols_kernel(const FitDesc *
     // the item index is the same in all lanes of a wave
     const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kColWaves + threadIdx.x / kWave);
     if (item >= nitems) return;   // whole wave
-    cols_item<true>(fits, items[item]);
+    const int2 it = items[item];
+    if (!(fit_flags(fits, it.x) & kDone)) cols_item<true>(fits, it);
 }
 
 // ------------------------------------------------------------------ syrk (FP32 matrix cores)
@@ -564,7 +574,9 @@ constexpr int kSyrkRed = (kSyrkWaves - 1) * 16 * kWave;   // floats of red per i
 __global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc *fits, const int4 *items)
 {
     __shared__ float red[kSyrkRed];
-    syrk_item(fits, items[blockIdx.x], true, threadIdx.x / kWave, threadIdx.x & (kWave - 1), red);
+    const int4 it = items[blockIdx.x];
+    if (fit_flags(fits, it.x) & (kDone | kFrozen)) return;   // the whole workgroup
+    syrk_item(fits, it, true, threadIdx.x / kWave, threadIdx.x & (kWave - 1), red);
 }
 
 // ------------------------------------------------------------------ info
@@ -612,7 +624,8 @@ __device__ __forceinline__ void info_item(const FitDesc *fits, int2 it, int t)
 
 __global__ __launch_bounds__(256) void info_kernel(const FitDesc *fits, const int2 *items)
 {
-    info_item(fits, items[blockIdx.x], threadIdx.x);
+    const int2 it = items[blockIdx.x];
+    if (!(fit_flags(fits, it.x) & (kDone | kFrozen))) info_item(fits, it, threadIdx.x);
 }
 
 // ------------------------------------------------------------------ step
@@ -1029,7 +1042,9 @@ __device__ __forceinline__ void step_fit(const FitDesc *fits, int slot, double *
 __global__ __launch_bounds__(kStepThreads) void step_kernel(const FitDesc *fits, const int *slots)
 {
     extern __shared__ double lds[];   // A[p * p], y[p]
-    step_fit<kStepThreads>(fits, slots[blockIdx.x], lds, nullptr);
+    const int slot = slots[blockIdx.x];
+    if (fit_flags(fits, slot) & kDone) return;   // the whole workgroup
+    step_fit<kStepThreads>(fits, slot, lds, nullptr);
 }
 
 // ------------------------------------------------------------------ persistent rounds
@@ -1102,8 +1117,6 @@ __device__ int round_barrier(const RoundWork &w, RoundCtl *ctl, uint32_t epoch, 
     __syncthreads();   // s_word is rewritten by the next barrier
     return go;
 }
-
-__device__ __forceinline__ int fit_flags(const FitDesc *fits, int slot) { return fits[slot].st->flags; }
 
 // Persistent round kernel: up to max_rounds Newton iterations of every fit in the work
 // lists, the six phases of a round separated by grid-wide barriers (one cooperative

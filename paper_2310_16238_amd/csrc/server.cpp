@@ -7,14 +7,15 @@
 //   prep pool   puts each request in canonical order (Sec. 2.7) and writes its
 //               device image (X column-major, row words, group indices) into a
 //               pinned staging area
-//   worker      owns the GPU: admits staged requests into free slots of the
-//               device arena while the previous iteration runs (uploads on a
-//               copy stream), runs one batched Newton iteration of every
-//               resident fit, reads the fits' states back, retires finished fits.
-//               With fused_rounds > 0 one persistent launch runs many iterations
-//               (serve.hip, round_kernel); the worker reports fits as they finish
-//               (from host-mapped state), admits while it runs, and asks it to end
-//               after the current iteration when new fits are ready to join
+//   worker      owns the GPU: builds the work lists of the resident fits and keeps
+//               batched Newton iterations of all of them queued (two ahead; the
+//               kernels leave out fits that have finished), reports fits as they
+//               finish (from host-mapped state), admits staged requests into free
+//               slots of the device arena meanwhile (uploads on a copy stream), and
+//               retires finished fits when it stops queueing on those lists.  With
+//               fused_rounds > 0 one persistent launch runs many iterations instead
+//               (serve.hip, round_kernel), asked to end after its current iteration
+//               when new fits are ready to join
 //
 // Admission is first come, first served, by device footprint: a request is
 // admitted when a slot is free and its block fits in the arena; the fits
@@ -538,10 +539,13 @@ bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_
 }
 
 // Everything the worker does per round; returns false on a device error (message in `err`).
+constexpr int kRoundsAhead = 2;   // rounds queued on the compute stream at once
+
 struct WorkerState {
     std::vector<int> uploading;   // slots whose upload was queued in the previous round
     std::vector<int> upload_stage_release;
     hipEvent_t copy_ev = nullptr;
+    hipEvent_t round_ev[kRoundsAhead] = {};
     bool copy_pending = false;
     int admit_buf = 0;
 };
@@ -781,17 +785,62 @@ void retire_fits(cox_server *s, const std::vector<int> &act, const std::vector<i
     }
 }
 
+// While launched rounds run: report the fits whose host-mapped state says they are done (the
+// step writes the estimate before the final state), admit staged requests once (uploads and
+// the admit kernel on the copy stream), and decide to hold -- run no further rounds on these
+// lists -- when fits are ready to join or waiting requests could take finished fits' places.
+struct Watch {
+    std::vector<char> seen;
+    bool admitted = false, held = false;
+};
+
+bool watch(cox_server *s, WorkerState &ws, const std::vector<int> &act, Watch &W, std::string &err)
+{
+    std::vector<int> newly;
+    for (size_t a = 0; a < act.size(); ++a)
+        if (!W.seen[a] && (__atomic_load_n(&s->h_state[act[a]].flags, __ATOMIC_ACQUIRE) & kDone)) {
+            W.seen[a] = 1;
+            newly.push_back(act[a]);
+        }
+    bool waiting = false;
+    if (!newly.empty() || !W.held) {
+        std::lock_guard<std::mutex> g(s->mu);
+        const double t = s->now();
+        for (int sl : newly) {
+            finish_locked(s, s->slots[sl].req->ticket, make_result(s, sl, t));
+            s->slots[sl].reported = true;
+        }
+        waiting = !s->ready_q.empty() || s->stop;
+    }
+    if (!W.held) {
+        if (waiting && !W.admitted) {
+            if (!admit_ready(s, ws, err)) return false;
+            W.admitted = ws.copy_pending;
+        }
+        bool any_done = false;
+        for (char c : W.seen) any_done |= c != 0;
+        if (W.admitted || (waiting && any_done)) W.held = true;
+    }
+    return true;
+}
+
+// Rounds as separate launches on one set of work lists, kRoundsAhead of them queued at once
+// (the kernels leave out fits that finished in an earlier round), until every fit is done or
+// the watch holds; then the fits are retired and the next call builds new lists.
 bool run_round(cox_server *s, WorkerState &ws, std::string &err)
 {
     // fits uploaded in the previous round join this round
     std::vector<int> joining, act;
     if (!next_round_fits(s, ws, act, joining, err)) return false;
-    const bool launched = !act.empty();
-    double t_launch = s->now();
-    if (launched) {
-        RoundLists R;
-        if (!build_lists(s, act, R, err)) return false;
-        const char *D = s->l_round.d;
+    if (act.empty()) return admit_ready(s, ws, err);   // nothing resident
+    const double t_launch = s->now();
+    RoundLists R;
+    if (!build_lists(s, act, R, err)) return false;
+    std::vector<int> evals0(act.size());
+    for (size_t a = 0; a < act.size(); ++a) evals0[a] = s->h_state[act[a]].evals;
+    const char *D = s->l_round.d;
+    int queued = 0, completed = 0;
+    auto enqueue = [&]() -> bool {
         WCHECK((hipError_t)launch_eta(s->d_desc, reinterpret_cast<const int2 *>(D + R.o_eta), (int)R.ke, s->compute),
                "eta");
         WCHECK((hipError_t)launch_rows(s->d_desc, reinterpret_cast<const int2 *>(D + R.o_rows), (int)R.kr, s->compute),
@@ -806,20 +855,35 @@ bool run_round(cox_server *s, WorkerState &ws, std::string &err)
                                            s->compute),
                    "info");
         }
+        // the step kernel writes each fit's state (and a final estimate) to host-mapped memory
         WCHECK((hipError_t)launch_step(s->d_desc, reinterpret_cast<const int *>(D + R.o_slots), (int)act.size(),
                                        R.max_p, s->compute),
                "step");
-        // the step kernel writes each fit's state (and a final estimate) to host-mapped memory
-        WCHECK(hipEventRecord(s->iter_ev, s->compute), "recording the iteration");
-    }
-    // while the GPU iterates: admit what the prep pool has staged (uploads on the copy stream)
-    if (!admit_ready(s, ws, err)) return false;
-    if (!launched) {
-        // nothing resident: the staging of this round's uploads is released next round
+        WCHECK(hipEventRecord(ws.round_ev[queued % kRoundsAhead], s->compute), "recording a round");
+        queued += 1;
         return true;
+    };
+    if (!enqueue()) return false;
+    Watch W;
+    W.seen.assign(act.size(), 0);
+    while (completed < queued) {
+        if (queued - completed < kRoundsAhead && !W.held) {
+            bool all_done = true;
+            for (char c : W.seen) all_done &= c != 0;
+            if (!all_done && !enqueue()) return false;
+        }
+        const hipError_t q = hipEventQuery(ws.round_ev[completed % kRoundsAhead]);
+        if (q != hipSuccess && q != hipErrorNotReady) {
+            err = std::string("round: ") + hipGetErrorString(q);
+            return false;
+        }
+        if (q == hipSuccess) completed += 1;
+        if (!watch(s, ws, act, W, err)) return false;
+        if (q != hipSuccess) std::this_thread::yield();
     }
-    WCHECK(hipEventSynchronize(s->iter_ev), "iteration");
-    retire_fits(s, act, joining, t_launch, s->now(), 1, (double)act.size());
+    double resident_rounds = 0.0;
+    for (size_t a = 0; a < act.size(); ++a) resident_rounds += (double)(s->h_state[act[a]].evals - evals0[a]);
+    retire_fits(s, act, joining, t_launch, s->now(), completed, resident_rounds);
     return true;
 }
 
@@ -879,44 +943,18 @@ bool run_launch_fused(cox_server *s, WorkerState &ws, std::string &err)
     w.hout = s->dh_round + 2;
     WCHECK((hipError_t)launch_rounds(w, grid, s->compute), "round kernel");
     WCHECK(hipEventRecord(s->iter_ev, s->compute), "recording the launch");
-    bool admitted = false, held = false;
-    std::vector<char> seen(act.size(), 0);
+    Watch W;
+    W.seen.assign(act.size(), 0);
     for (;;) {
         const hipError_t q = hipEventQuery(s->iter_ev);
         if (q != hipSuccess && q != hipErrorNotReady) {
             err = std::string("round kernel: ") + hipGetErrorString(q);
             return false;
         }
-        // fits that finished: their estimate and state are complete once kDone is visible
-        std::vector<int> newly;
-        for (size_t a = 0; a < act.size(); ++a)
-            if (!seen[a] && (__atomic_load_n(&s->h_state[act[a]].flags, __ATOMIC_ACQUIRE) & kDone)) {
-                seen[a] = 1;
-                newly.push_back(act[a]);
-            }
-        bool waiting = false;
-        if (!newly.empty() || !held) {
-            std::lock_guard<std::mutex> g(s->mu);
-            const double t = s->now();
-            for (int sl : newly) {
-                finish_locked(s, s->slots[sl].req->ticket, make_result(s, sl, t));
-                s->slots[sl].reported = true;
-            }
-            waiting = !s->ready_q.empty() || s->stop;
-        }
+        const bool was_held = W.held;
+        if (!watch(s, ws, act, W, err)) return false;
+        if (W.held && !was_held) __atomic_store_n(hold, 1u, __ATOMIC_SEQ_CST);
         if (q == hipSuccess) break;
-        if (!held) {
-            if (waiting && !admitted) {
-                if (!admit_ready(s, ws, err)) return false;
-                admitted = ws.copy_pending;
-            }
-            bool any_done = false;
-            for (char c : seen) any_done |= c != 0;
-            if (admitted || (waiting && any_done)) {
-                __atomic_store_n(hold, 1u, __ATOMIC_SEQ_CST);
-                held = true;
-            }
-        }
         std::this_thread::yield();
     }
     const double t_done = s->now();
@@ -940,7 +978,10 @@ void worker_loop(cox_server *s)
     (void)hipSetDevice(s->device);
     WorkerState ws;
     std::string err;
-    if (hipEventCreateWithFlags(&ws.copy_ev, hipEventDisableTiming) != hipSuccess) {
+    bool ev_ok = hipEventCreateWithFlags(&ws.copy_ev, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < kRoundsAhead && ev_ok; ++k)
+        ev_ok = hipEventCreateWithFlags(&ws.round_ev[k], hipEventDisableTiming) == hipSuccess;
+    if (!ev_ok) {
         std::lock_guard<std::mutex> g(s->mu);
         s->fatal = COX_EDEVICE;
         s->fatal_msg = "creating an event";
@@ -968,6 +1009,8 @@ void worker_loop(cox_server *s)
     (void)hipStreamSynchronize(s->copy);
     (void)hipStreamSynchronize(s->compute);
     if (ws.copy_ev) (void)hipEventDestroy(ws.copy_ev);
+    for (hipEvent_t e : ws.round_ev)
+        if (e) (void)hipEventDestroy(e);
     std::lock_guard<std::mutex> g(s->mu);
     if (s->fatal) {
         // fail everything still outstanding
