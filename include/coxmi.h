@@ -577,7 +577,9 @@ int cox_server_poll(cox_server *s, uint64_t ticket, double *beta_out, cox_fit_in
  * (1; timeout_s < 0 waits for ever) or the server failed (its error code). */
 int cox_server_wait(cox_server *s, uint64_t ticket, double timeout_s);
 
-/* Block until every submitted fit has finished; codes as cox_server_wait. */
+/* Block until every submitted fit has finished and its device slot has been released (a
+ * result can be ready a little before its slot is: fits are reported as soon as their final
+ * state reaches the host); codes as cox_server_wait. */
 int cox_server_drain(cox_server *s, double timeout_s);
 
 int cox_server_stats(cox_server *s, cox_server_counters *st);

@@ -783,6 +783,7 @@ void retire_fits(cox_server *s, const std::vector<int> &act, const std::vector<i
         if (!S.reported) finish_locked(s, S.req->ticket, make_result(s, sl, t_done));
         S = Slot();
     }
+    if (!done.empty()) s->cv_done.notify_all();   // drain waits for the slots too
 }
 
 // While launched rounds run: report the fits whose host-mapped state says they are done (the
@@ -1266,10 +1267,16 @@ extern "C" int cox_server_drain(cox_server *s, double timeout_s)
 {
     if (!s) return COX_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
-    auto ready = [s] { return s->outstanding == 0 || s->fatal != 0; };
+    auto idle = [s] {
+        if (s->outstanding != 0) return false;
+        for (const Slot &S : s->slots)
+            if (S.used) return false;
+        return true;
+    };
+    auto ready = [s, &idle] { return s->fatal != 0 || idle(); };
     if (timeout_s < 0) s->cv_done.wait(lk, ready);
     else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) return 1;
-    return s->outstanding == 0 ? COX_OK : s->fatal;
+    return idle() ? COX_OK : s->fatal;
 }
 
 extern "C" int cox_server_stats(cox_server *s, cox_server_counters *st)
