@@ -135,3 +135,46 @@ def test_fused_rounds_option_checked():
         with pytest.raises(coxmi.CoxError) as e:
             coxmi.CoxServer(fused_rounds=bad)
         assert e.value.code == coxmi.COX_EINVAL
+
+
+def test_fused_edge_cases_and_device_requests():
+    """One row, no events, one column with strata, a stratum longer than a scan tile, and
+    device-resident requests: the persistent rounds give what the separate launches give."""
+    rng = np.random.default_rng(5)
+    cases = [
+        (np.ones((1, 1)), np.array([1.0]), np.array([1], np.uint8), None),
+        (rng.standard_normal((50, 3)), rng.random(50), np.zeros(50, np.uint8), None),
+        (rng.standard_normal((400, 1)), rng.exponential(1.0, 400), (rng.random(400) < 0.5).astype(np.uint8),
+         (np.arange(400) % 4).astype(np.int32)),
+    ]
+    long_stratum = synth.make("iid", 9_000, 7, 1, 23, intercept=True)
+    multi_tile = synth.serving_request(3, seed=25, n_range=(30_000, 30_001), p_range=(20, 20))
+
+    def run(fused):
+        with coxmi.CoxServer(prep_threads=2, fused_rounds=fused) as srv:
+            tk = [srv.submit(*c) for c in cases]
+            for d in (long_stratum, multi_tile):
+                tk.append(srv.submit(d.X, d.time, d.event, d.stratum))
+                dev = (torch.from_numpy(np.ascontiguousarray(d.X.T)).cuda().t(),
+                       torch.from_numpy(np.ascontiguousarray(d.time)).cuda(),
+                       torch.from_numpy(np.ascontiguousarray(d.event, dtype=np.uint8)).cuda(),
+                       None if d.stratum is None else
+                       torch.from_numpy(np.ascontiguousarray(d.stratum, dtype=np.int32)).cuda())
+                torch.cuda.synchronize()
+                tk.append(srv.submit_device(*dev))
+            assert srv.drain(timeout=100.0)
+            return [srv.poll(t) for t in tk]
+
+    ref = run(0)
+    out = run(16)
+    _same(ref, out, "edge")
+    for (X, t, e, s), (beta, info, _) in zip(cases, out):
+        assert info["status"] == coxmi.COX_OK, info
+        if e.sum() == 0 or X.shape[0] == 1:
+            assert np.all(beta == 0.0)
+        else:
+            assert _rel(beta, orc.fit_newton(X, t, e, s, tol=1e-14).beta) <= 1e-10
+    for k, d in enumerate((long_stratum, multi_tile)):
+        host, dev = out[3 + 2 * k], out[4 + 2 * k]
+        assert np.array_equal(host[0], dev[0]), d.name
+        assert _rel(dev[0], orc.fit_newton(d.X, d.time, d.event, d.stratum, tol=1e-14).beta) <= 1e-10
