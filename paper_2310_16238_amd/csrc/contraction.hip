@@ -326,33 +326,16 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
     __shared__ double s_l11[kPanNB][kPanNB + 1];   // the factored diagonal block, row-major
     __shared__ double s_inv[kPanNB];                 // 1 / its diagonal
     __shared__ double s_col[kPanNB];                 // one scaled column of the block
-    __shared__ uint8_t s_free[kCholMaxP];
-    __shared__ int s_fixed[kCholMaxP];               // the columns that are not free
-    __shared__ int s_bad, s_nfixed;
+    __shared__ int s_bad;
     const int t = threadIdx.x;
     const int lane = t & (kWaveC - 1), wv = t / kWaveC;
     constexpr int kWaves = kCholThreads / kWaveC;
-    for (int i = t; i < p; i += kCholThreads) s_free[i] = free_col[i];
     if (t == 0) s_bad = 0;
-    __syncthreads();
     if (!factored) {
-        // rows and columns not free become unit rows (only their entries are written)
-        if (t == 0) {
-            int n = 0;
-            for (int j = 0; j < p; ++j)
-                if (!s_free[j]) s_fixed[n++] = j;
-            s_nfixed = n;
-        }
-        __syncthreads();
-        const int nfix = s_nfixed;
-        for (int q = wv; q < nfix; q += kWaves) {
-            const int i = s_fixed[q];
-            for (int j = lane; j < p; j += kWaveC) A[(int64_t)i * p + j] = (i == j) ? 1.0 : 0.0;
-        }
-        for (int e = t; e < p * nfix; e += kCholThreads) {
-            const int i = e / nfix, j = s_fixed[e % nfix];
-            A[(int64_t)i * p + j] = (i == j) ? 1.0 : 0.0;
-        }
+        // rows and columns not free become unit rows
+        for (int i = wv; i < p; i += kWaves)
+            for (int j = lane; j < p; j += kWaveC)
+                if (!free_col[i] || !free_col[j]) A[(int64_t)i * p + j] = (i == j) ? 1.0 : 0.0;
         __syncthreads();
         for (int c0 = 0; c0 < p; c0 += kPanNB) {
             const int nb = p - c0 < kPanNB ? p - c0 : kPanNB;
@@ -463,7 +446,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
         }
     }
     // solves: L y = -g, then L' x = y (free columns only)
-    for (int i = t; i < p; i += kCholThreads) y[i] = s_free[i] ? -g[i] : 0.0;
+    for (int i = t; i < p; i += kCholThreads) y[i] = free_col[i] ? -g[i] : 0.0;
     __syncthreads();
     // the diagonal block's entries a lane needs are loaded into registers first
     // (all loads in flight together), so the sequential steps wait only on shuffles
@@ -487,15 +470,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
         }
         __syncthreads();
         for (int i = k0 + nb + t; i < p; i += kCholThreads) {
-            // the block's entries of row i are loaded together, then summed in column order
             const double *row = A + (int64_t)i * p + k0;
-            double r[kCholNB];
-#pragma unroll
-            for (int c = 0; c < kCholNB; ++c) r[c] = c < nb ? row[c] : 0.0;
             double s = 0.0;
-#pragma unroll
-            for (int c = 0; c < kCholNB; ++c)
-                if (c < nb) s = fma(r[c], y[k0 + c], s);
+            for (int c = 0; c < nb; ++c) s = fma(row[c], y[k0 + c], s);
             y[i] -= s;
         }
         __syncthreads();
@@ -520,18 +497,13 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
         }
         __syncthreads();
         for (int i = t; i < k0; i += kCholThreads) {
-            double r[kCholNB];
-#pragma unroll
-            for (int c = 0; c < kCholNB; ++c) r[c] = c < nb ? A[(int64_t)(k0 + c) * p + i] : 0.0;
             double s = 0.0;
-#pragma unroll
-            for (int c = 0; c < kCholNB; ++c)
-                if (c < nb) s = fma(r[c], y[k0 + c], s);
+            for (int c = 0; c < nb; ++c) s = fma(A[(int64_t)(k0 + c) * p + i], y[k0 + c], s);
             y[i] -= s;
         }
         __syncthreads();
     }
-    for (int i = t; i < p; i += kCholThreads) dx[i] = s_free[i] ? y[i] : 0.0;
+    for (int i = t; i < p; i += kCholThreads) dx[i] = free_col[i] ? y[i] : 0.0;
     if (t == 0) status[0] = s_bad;
 }
 
