@@ -95,6 +95,32 @@ def cpu_baseline(d, sweeps=20):
             **host_cpu()}
 
 
+def cpu_baseline_newton(d, steps):
+    """Oracle Newton step on all cores: one full FP64 evaluation with the information matrix
+    (risk-set sums in plain C on one thread, X' diag(w Lambda) X and xbar'xbar by numpy's BLAS
+    on every core) of the same data; fits/s assumes `steps` such steps per fit."""
+    import numpy as np
+    from oracle import cox_oracle as orc
+    L = orc.canonical_layout(d.time, d.event, d.stratum)
+    Xc = orc.to_canonical(d.X, L)
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads") or 0) for i in threadpool_info()) or None
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    fe = orc.full_eval(Xc, L, np.zeros(d.p), want_info=True)
+    dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(fe.info))
+    return {"value": 1.0 / (steps * dt), "unit": "fits/s", "cores": threads or host_cpu()["nproc"],
+            "kind": "oracle",
+            "sample": f"one full FP64 evaluation with the information matrix of the same N={d.n} P={d.p} data "
+                      f"({dt:.1f} s: risk-set sums in plain C on one thread, the P x P products by numpy's "
+                      f"BLAS on all cores), times the {steps} Newton steps of the FP64 path",
+            "obs_evals_per_s": d.n * d.p / dt, **host_cpu()}
+
+
 def host_cpu():
     """The host's CPU model and the threads this process may use."""
     model = "unknown"
@@ -1304,7 +1330,12 @@ def mixed_leg(args, steps, warmup):
         "evaluation_roofline": {"bound": "hbm", "achieved": eval_bytes / eval_s / 1e9, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": eval_bytes / eval_s / 1e9 / HBM_PEAK_GBS,
                                 "algorithmic_bytes_per_evaluation": eval_bytes},
+        "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle Newton step (C risk-set sums, BLAS on all cores)")
+        out["cpu_baseline"] = cpu_baseline_newton(d, runs["f64"]["newton_steps"])
+        log(f"  {out['cpu_baseline']['sample']}")
     return out
 
 
