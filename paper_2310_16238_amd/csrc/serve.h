@@ -19,8 +19,10 @@ namespace serve {
 constexpr int kMaxP = 128;        // columns of a served fit (its Cholesky factor lives in LDS)
 constexpr int kRowPad = 64;       // rows are padded to a multiple of this
 constexpr int kEtaRows = 256;     // rows per work item of the X beta kernel
-constexpr int kXRange = 4096;     // rows per K range of the X' diag(b) X contraction (4 waves of 1024)
-constexpr int kZRange = 4096;     // event groups per K range of the Z'Z contraction
+constexpr int kMaxRange = 4096;   // rows (event groups) per K range of the contraction, at most
+constexpr int kMinRange = 1024;   //   and at least: a fit's range is about an eighth of its rows, in
+                                  //   steps of 256, so that a small fit's contraction still spreads
+                                  //   over several workgroups
 constexpr int kColBlock = 4;      // columns per wave of the column pass
 constexpr int kTile = 32;         // edge of a contraction tile (one MFMA block)
 constexpr int kScanTile = 4096;   // rows of a scan tile: a fit whose strata all fit one tile is laid
@@ -78,6 +80,7 @@ struct FitDesc {
     int ntc;                // scan tiles
     int p, G;               // columns, event groups
     int nxr, nzr;           // K ranges of the two products (nzr = 0 without events)
+    int xrange, zrange;     // rows of X, event groups of Z per K range (multiples of 256)
     int npairs, ntile;      // tile pairs of the upper triangle; X beta work items
     const double *gam;      // [p] l1 weights (0 for unpenalised columns); nullptr: an unpenalised fit
     const double *beta0;    // [p] start point; nullptr: zeros

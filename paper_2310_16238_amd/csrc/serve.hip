@@ -15,6 +15,7 @@
 //                              score X'a, diagonal (X o X)'b - sum d xbar^2
 //   syrk  (fit, tile pair, K range, product)
 //                              four waves: a 32 x 32 tile of X' diag(b) X or Z'Z
+//                              over 1024-4096 rows (event groups)
 //                              on the matrix cores (v_mfma_f32_32x32x2f32, FP32)
 //   info  (fit, tile pair)     the K-range partials summed in FP64 in range order:
 //                              the information matrix
@@ -471,7 +472,7 @@ __device__ __forceinline__ f32x16 syrk_partial(const FitDesc &F, int4 it, int v,
     const bool zpart = it.w != 0;
     const float *u = zpart ? F.z : F.xf;
     const int64_t ldu = zpart ? F.ldz : F.ld;
-    const int64_t range = zpart ? kZRange : kXRange, quarter = range / kSyrkWaves;
+    const int64_t range = zpart ? F.zrange : F.xrange, quarter = range / kSyrkWaves;
     const int64_t k0 = (int64_t)it.z * range + v * quarter;
     // k0 is a multiple of 64 and ldu a multiple of 64: steps of 32 fit exactly
     const int64_t k1 = k0 + quarter < ldu ? k0 + quarter : ldu;

@@ -106,7 +106,7 @@ private:
 // Where each piece of one fit lives inside its arena block (byte offsets).
 struct FitLayout {
     int64_t n = 0, ld = 0, ldz = 0, tile = 0;
-    int p = 0, G = 0, nxr = 0, nzr = 0, npairs = 0, ntile = 0, ntc = 0;
+    int p = 0, G = 0, nxr = 0, nzr = 0, xrange = 0, zrange = 0, npairs = 0, ntile = 0, ntc = 0;
     bool device = false;                            // X is gathered from the caller's device memory
     size_t meta = 0, gidx = 0, gam = 0, beta0 = 0, src = 0, x = 0, upload = 0;
                                                     // [0, upload) is uploaded in one copy: meta, gidx, the
@@ -162,8 +162,16 @@ FitLayout plan(int64_t n, int64_t ld, int64_t tile, int p, int64_t G, bool devic
     L.ldz = (int64_t)round_up((size_t)std::max<int64_t>(G, 1), kRowPad);
     const int nt = (p + kTile - 1) / kTile;
     L.npairs = nt * (nt + 1) / 2;
-    L.nxr = (int)((L.ld + kXRange - 1) / kXRange);
-    L.nzr = G > 0 ? (int)((L.ldz + kZRange - 1) / kZRange) : 0;
+    // K ranges of about an eighth of the rows, 1024 to 4096 of them, a multiple of 256 (each of
+    // the 4 waves of a contraction item then takes whole 64-row steps)
+    auto range_for = [](int64_t rows) {
+        const int64_t r = (int64_t)round_up((size_t)((rows + 7) / 8), 256);
+        return (int)std::min<int64_t>(kMaxRange, std::max<int64_t>(kMinRange, r));
+    };
+    L.xrange = range_for(L.ld);
+    L.zrange = range_for(L.ldz);
+    L.nxr = (int)((L.ld + L.xrange - 1) / L.xrange);
+    L.nzr = G > 0 ? (int)((L.ldz + L.zrange - 1) / L.zrange) : 0;
     L.ntile = (int)((L.ld + kEtaRows - 1) / kEtaRows);
     size_t o = 0;
     auto take = [&o](size_t bytes) {
@@ -504,6 +512,8 @@ FitDesc make_desc(cox_server *s, const Request &q, size_t off, int slot)
     F.G = L.G;
     F.nxr = L.nxr;
     F.nzr = L.nzr;
+    F.xrange = L.xrange;
+    F.zrange = L.zrange;
     F.npairs = L.npairs;
     F.ntile = L.ntile;
     F.gam = q.gam.empty() ? nullptr : reinterpret_cast<const double *>(B + L.gam);
@@ -528,6 +538,9 @@ bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_
            in(F.eta, 8 * ld) && in(F.w, 8 * ld) && in(F.zq, 8 * ld) && in(F.hz, 8 * ld) && in(F.b, 8 * ld) && in(F.bf, 4 * ld) && in(F.z, 4 * p * (size_t)L.ldz) && in(F.beta, 8 * p) &&
            in(F.prev, 8 * p) && in(F.grad, 8 * p) && in(F.diag2, 8 * p) && in(F.free_col, p) &&
            in(F.L, 8 * p * p) && in(F.part, 4 * (size_t)(L.nxr + L.nzr) * L.npairs * kTile * kTile) &&
+           F.xrange % 256 == 0 && F.zrange % 256 == 0 && F.xrange >= kMinRange && F.xrange <= kMaxRange &&
+           F.zrange >= kMinRange && F.zrange <= kMaxRange && (int64_t)F.nxr * F.xrange >= L.ld &&
+           (F.nzr == 0 || (int64_t)F.nzr * F.zrange >= L.ldz) &&
            in(F.tilemax, 8 * (size_t)L.ntile) && in(F.tpart, 16 * (size_t)L.ntc) &&
            in(F.cpart, 24 * (size_t)L.ntc * p) && (!F.gam || in(F.gam, 8 * p)) && (!F.beta0 || in(F.beta0, 8 * p)) &&
            (!L.device || (in(F.src, 4 * ld) && F.xs && F.ldxs >= L.n)) && F.tile > 0 && F.tile % kRowPad == 0 && F.ntc >= 1 &&
