@@ -95,7 +95,8 @@ typedef struct {
                                  FP64 (the persistent kernel's exp(x'beta - c)) was finished by (proximal)
                                  Newton steps on the full evaluation, whose running-maximum scans hold any
                                  range -- the same optimum; iters and coord_evals then count Newton steps
-                                 and full evaluations */
+                                 and full evaluations.  2: the same for a COX_CCD handle of dense X with
+                                 more rows than the persistent kernel holds (every fit on it) */
 } cox_fit_info;
 
 /* Fill *o with defaults: gamma 0, all columns penalised, COX_CCD, COX_F64,
@@ -121,10 +122,12 @@ void cox_default_options(cox_options *o);
  * Errors: COX_EINVAL (n < 1, p < 1, ldx < n, NULL x/time/event, non-finite
  * time, event not 0/1, on_device arrays not in device memory of the current
  * device), COX_EUNSUPPORTED (p > 12288, or p > 4096 in mode
- * COX_NEWTON_REFINE -- cox_evaluate_full also needs p <= 4096; in mode COX_CCD, n
- * beyond the persistent kernel's register-resident capacity of about
- * CUs x 512 x 16 rows -- a COX_NEWTON_REFINE handle of that size is created,
- * and then supports cox_fit and cox_evaluate_full only; x_precision COX_F32, or
+ * COX_NEWTON_REFINE -- cox_evaluate_full also needs p <= 4096; in mode COX_CCD with
+ * p > 4096, n beyond the persistent kernel's register-resident capacity of about
+ * CUs x 512 x 16 rows -- a handle of that size and p <= 4096 is created in either mode
+ * and then serves cox_fit by (proximal) Newton steps on the full evaluation
+ * (info->fallback = 2 in mode COX_CCD: the same optimum), cox_evaluate and
+ * cox_evaluate_full, but not cox_coordinate; x_precision COX_F32, or
  * COX_FP8_E4M3 outside mode COX_NEWTON_REFINE),
  * COX_ENOMEM, COX_EDEVICE.  On error *out is NULL and the
  * message is available through cox_last_error(NULL).
@@ -156,7 +159,8 @@ int cox_init(cox_handle **out, const cox_data *d, const cox_options *o);
  * In mode COX_CCD, when an event's risk-set sum under- or overflows FP64 after the
  * persistent kernel's single shift of X beta, the fit is finished by (proximal)
  * Newton steps on the full evaluation, whose running-maximum scans hold any range
- * (the same optimum; info->fallback = 1).
+ * (the same optimum; info->fallback = 1); a COX_CCD handle of dense X too long for the
+ * persistent kernel fits that way from the start (info->fallback = 2).
  * Returns COX_OK, COX_NOT_CONVERGED (max_iter sweeps done; beta_out filled),
  * COX_ENUMERIC (out of range on a handle of indicator X, which has no full
  * evaluation, or in the full evaluation itself), COX_EDEVICE.

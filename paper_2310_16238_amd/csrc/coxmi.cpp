@@ -243,10 +243,13 @@ static int check_options(const cox_options &opt, std::string &msg)
 }
 
 // Launch layout for h->meta (sets shape and pos); Newton fits fall back to the tile layout.
-static int layout_for(cox_handle *h, std::string &err)
+// dense: the handle will hold FP64 X, so the full evaluation and Newton fits can serve a COX_CCD
+// handle too long for the persistent kernel (p <= kMaxNewtonP).
+static int layout_for(cox_handle *h, std::string &err, bool dense)
 {
     int rc = choose_layout(h->meta, (int)h->p, h->shape, h->pos, err);
-    if (rc == COX_EUNSUPPORTED && h->opt.mode == COX_NEWTON_REFINE) {
+    if (rc == COX_EUNSUPPORTED &&
+        (h->opt.mode == COX_NEWTON_REFINE || (dense && h->p <= kMaxNewtonP))) {
         tile_layout(h->meta, h->shape, h->pos);
         rc = 0;
     }
@@ -354,7 +357,7 @@ extern "C" int cox_init(cox_handle **out, const cox_data *d, const cox_options *
         for (int64_t j = 0; j < p; ++j) h->gamma[j] = o->penalize[j] ? opt.gamma : 0.0;
 
     std::string err;
-    const int rc = layout_for(h, err);
+    const int rc = layout_for(h, err, true);
     if (rc != 0) {
         delete h;
         return fail(nullptr, rc, err);
@@ -443,7 +446,7 @@ extern "C" int cox_init_indicator(cox_handle **out, int64_t n, int64_t p, const 
     if (o && o->penalize)
         for (int64_t j = 0; j < p; ++j) h->gamma[(size_t)j] = o->penalize[j] ? opt.gamma : 0.0;
     std::string err;
-    const int rc = layout_for(h, err);
+    const int rc = layout_for(h, err, false);
     if (rc != 0) {
         delete h;
         return fail(nullptr, rc, err);
@@ -553,7 +556,7 @@ extern "C" int cox_init_sparse(cox_handle **out, int64_t n, int64_t p, const int
     if (o && o->penalize)
         for (int64_t j = 0; j < p; ++j) h->gamma[(size_t)j] = o->penalize[j] ? opt.gamma : 0.0;
     std::string err;
-    const int rc = layout_for(h, err);
+    const int rc = layout_for(h, err, false);
     if (rc != 0) {
         delete h;
         return fail(nullptr, rc, err);
@@ -718,7 +721,7 @@ extern "C" int cox_init_resample(cox_handle **out, const cox_handle *parent, con
         h->gamma = parent->gamma;
     }
     std::string err;
-    const int rc = layout_for(h, err);
+    const int rc = layout_for(h, err, parent->d_x != nullptr);
     if (rc != 0) {
         delete h;
         return fail(nullptr, rc, err);
@@ -857,7 +860,7 @@ extern "C" int cox_init_intervals(cox_handle **out, const cox_handle *parent, co
         for (int64_t c = 0; c < paug; ++c) h->gamma[(size_t)c] = parent->gamma[(size_t)rows.col_source[(size_t)c]];
     }
     std::string err;
-    const int rc = layout_for(h, err);
+    const int rc = layout_for(h, err, parent->d_x != nullptr);
     if (rc != 0) {
         delete h;
         return fail(nullptr, rc, err);
@@ -945,7 +948,7 @@ static int run_kernel(cox_handle *h, int mode, int j0, int j1, const double *bet
     if (h->shape.ipt == 0)
         return fail(h, COX_EUNSUPPORTED,
                     "n exceeds the register-resident capacity of the persistent kernel: this handle supports "
-                    "COX_NEWTON_REFINE fits and cox_evaluate_full only");
+                    "cox_fit (by Newton steps), cox_evaluate and cox_evaluate_full only");
     hipError_t e;
     if (beta_host) e = hipMemcpyAsync(h->beta(), beta_host, sizeof(double) * h->p, hipMemcpyHostToDevice, h->stream);
     else e = hipMemsetAsync(h->beta(), 0, sizeof(double) * h->p, h->stream);
@@ -1006,6 +1009,13 @@ extern "C" int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox
             if (!std::isfinite(beta0[j])) return fail(h, COX_EINVAL, "beta0 is not finite");
     if (info) info->fallback = 0;
     if (h->opt.mode == COX_NEWTON_REFINE) return newton_fit(h, beta0, beta_out, info);
+    if (h->shape.ipt == 0) {
+        // more rows than the persistent kernel holds (dense X): (proximal) Newton steps on the
+        // full evaluation reach the same optimum
+        const int rc2 = newton_fit(h, beta0, beta_out, info);
+        if (info && (rc2 == COX_OK || rc2 == COX_NOT_CONVERGED)) info->fallback = 2;
+        return rc2;
+    }
     double res[kResultSlots];
     int rc = run_kernel(h, kModeFit, 0, (int)h->p, beta0, res);
     if (rc == COX_ENUMERIC && h->d_x) {
@@ -1050,7 +1060,7 @@ extern "C" int cox_fit(cox_handle *h, const double *beta0, double *beta_out, cox
 // kernel's evaluation of one coordinate, or the full evaluation on a Newton handle.
 static int neg_loglik(cox_handle *h, const double *beta, double *nll)
 {
-    if (h->opt.mode == COX_NEWTON_REFINE) {
+    if (h->opt.mode == COX_NEWTON_REFINE || h->shape.ipt == 0) {
         double obj = 0.0;
         const int rc = cox_evaluate_full(h, beta, &obj, nullptr, nullptr, nullptr);
         if (rc != COX_OK) return rc;
@@ -1268,6 +1278,8 @@ extern "C" int cox_evaluate(cox_handle *h, const double *beta, double *objective
 {
     if (!h) return fail(nullptr, COX_EINVAL, "handle is NULL");
     if (!beta) return fail(h, COX_EINVAL, "beta is NULL");
+    if (h->shape.ipt == 0 && h->d_x)   // beyond the persistent kernel: the full evaluation
+        return cox_evaluate_full(h, beta, objective, grad, hess_diag, nullptr);
     double res[kResultSlots];
     int rc = run_kernel(h, kModeEval, 0, (int)h->p, beta, res);
     if (rc == COX_ENUMERIC && h->d_x) {

@@ -270,8 +270,10 @@ def test_full_evaluation_edge_cases():
 
 def test_newton_beyond_the_resident_kernel():
     """N = 2.5e6 rows exceeds the persistent kernel's register capacity (256 CUs x 512 x 16):
-    the handle takes the tile layout, Newton fits and full evaluations still match the oracle,
-    and the CCD entry points report COX_EUNSUPPORTED."""
+    the handle takes the tile layout; Newton fits, full evaluations and cox_evaluate (answered
+    by the full evaluation) match the oracle; a COX_CCD handle of the same data fits by
+    (proximal) Newton steps (fallback 2) to the oracle's optima, unpenalised and with l1
+    weights; cox_coordinate reports COX_EUNSUPPORTED."""
     d = synth.make("ar1", 2_500_000, 8, 1000, 21, beta_sd=0.5)
     _say("newton fit beyond the resident kernel n=2.5e6 p=8 K=1000")
     ref = orc.fit_newton(d.X, d.time, d.event, d.stratum, tol=1e-14)
@@ -283,17 +285,34 @@ def test_newton_beyond_the_resident_kernel():
             beta, info = m.fit()
             assert info["status"] == coxmi.COX_OK
             assert _rel(beta, ref.beta) <= 1e-10
-            with pytest.raises(coxmi.CoxError) as ei:
-                m.evaluate(beta)
-            assert ei.value.code == coxmi.COX_EUNSUPPORTED
             if prec == coxmi.COX_F64:
                 obj, g, hd, info_m = m.evaluate_full(beta)
                 fe = _oracle_eval(d, beta)
                 _check_first_order(d, obj, g, hd, fe)
                 assert np.all(np.abs(info_m - fe.info) <= 1e-11 * _scale(fe))
-    with pytest.raises(coxmi.CoxError) as ei:
-        coxmi.cox_init(d.X, d.time, d.event, d.stratum)   # CCD mode cannot hold it
-    assert ei.value.code == coxmi.COX_EUNSUPPORTED
+                obj2, g2, hd2 = m.evaluate(beta)   # the per-coordinate path cannot hold it
+                _check_first_order(d, obj2, g2, hd2, fe)
+    # the same data on a COX_CCD handle
+    L = orc.canonical_layout(d.time, d.event, d.stratum)
+    g0 = orc.full_eval(orc.to_canonical(d.X, L), L, np.zeros(d.p), want_info=False).grad
+    gam = 0.2 * float(np.max(np.abs(g0)))
+    with coxmi.CoxModel(d.X, d.time, d.event, d.stratum, tol=1e-13) as m:
+        beta, info = m.fit()
+        assert info["status"] == coxmi.COX_OK and info["fallback"] == 2, info
+        assert _rel(beta, ref.beta) <= 1e-10
+        with pytest.raises(coxmi.CoxError) as ei:
+            m.coordinate(beta, 0)
+        assert ei.value.code == coxmi.COX_EUNSUPPORTED
+        m.set_penalty(gam)
+        beta1, info1 = m.fit()
+    assert info1["status"] == coxmi.COX_OK and info1["fallback"] == 2, info1
+    # the l1 optimality conditions of the oracle's score (plain C, Eq. strat_g) at the estimate
+    fe1 = orc.full_eval(orc.to_canonical(d.X, L), L, beta1, want_info=False)
+    E = float(d.event.sum())
+    viol = np.where(beta1 != 0.0, np.abs(fe1.grad + gam * np.sign(beta1)), np.maximum(np.abs(fe1.grad) - gam, 0.0))
+    _say(f"  CCD handle, l1 at 0.2 gamma_max: {np.count_nonzero(beta1)} nonzero, max violation / E = "
+         f"{np.max(viol) / E:.2e}")
+    assert np.count_nonzero(beta1) < d.p and np.max(viol) <= 1e-9 * E
 
 
 def test_newton_fp8_heavy_tailed():
