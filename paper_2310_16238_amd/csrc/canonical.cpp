@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 
 #include "internal.h"
 
@@ -22,45 +23,36 @@ inline uint64_t desc_key(double t)
     return ~u;
 }
 
-struct KI {
-    uint64_t k;
-    int64_t i;
-};
-
-// Stable LSD radix sort of a[0, n) by k (8-bit digits; a digit on which all
-// keys agree is skipped).  tmp: scratch of n elements.
-void radix_by_key(KI *a, KI *tmp, int64_t n)
+// Stable LSD radix sort of a[0, n) by bits 32..63 (8-bit digits; a digit on which every
+// element agrees is skipped); the low 32 bits ride along.  All digit histograms are taken in
+// one read pass.  tmp: scratch of n elements.
+void radix_hi32(uint64_t *a, uint64_t *tmp, int64_t n)
 {
-    for (int shift = 0; shift < 64; shift += 8) {
-        int64_t cnt[257] = {0};
-        for (int64_t r = 0; r < n; ++r) ++cnt[((a[r].k >> shift) & 0xff) + 1];
+    std::vector<uint32_t> hist(4 * 256, 0u);
+    for (int64_t r = 0; r < n; ++r) {
+        const uint64_t v = a[r] >> 32;
+        ++hist[0 * 256 + (v & 0xff)];
+        ++hist[1 * 256 + ((v >> 8) & 0xff)];
+        ++hist[2 * 256 + ((v >> 16) & 0xff)];
+        ++hist[3 * 256 + ((v >> 24) & 0xff)];
+    }
+    uint64_t *src = a, *dst = tmp;
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t *h = &hist[(size_t)d * 256];
         bool trivial = false;
-        for (int d = 1; d <= 256; ++d) trivial |= cnt[d] == n;
+        for (int v = 0; v < 256; ++v) trivial |= (int64_t)h[v] == n;
         if (trivial) continue;
-        for (int d = 1; d <= 256; ++d) cnt[d] += cnt[d - 1];
-        for (int64_t r = 0; r < n; ++r) tmp[cnt[(a[r].k >> shift) & 0xff]++] = a[r];
-        std::memcpy(a, tmp, sizeof(KI) * (size_t)n);
-    }
-}
-
-// Stable sort of a[0, n) by k.
-void sort_by_key(KI *a, KI *tmp, int64_t n)
-{
-    if (n <= 32) {   // insertion sort
-        for (int64_t r = 1; r < n; ++r) {
-            const KI v = a[r];
-            int64_t q = r - 1;
-            while (q >= 0 && a[q].k > v.k) {
-                a[q + 1] = a[q];
-                --q;
-            }
-            a[q + 1] = v;
+        uint32_t off[256];
+        uint32_t sum = 0;
+        for (int v = 0; v < 256; ++v) {
+            off[v] = sum;
+            sum += h[v];
         }
-    } else if (n <= 4096) {   // indices ascend on entry, so (k, i) order is the stable order
-        std::sort(a, a + n, [](const KI &x, const KI &y) { return x.k != y.k ? x.k < y.k : x.i < y.i; });
-    } else {
-        radix_by_key(a, tmp, n);
+        const int shift = 32 + 8 * d;
+        for (int64_t r = 0; r < n; ++r) dst[off[(src[r] >> shift) & 0xff]++] = src[r];
+        std::swap(src, dst);
     }
+    if (src != a) std::memcpy(a, src, sizeof(uint64_t) * (size_t)n);
 }
 
 }  // namespace
@@ -68,11 +60,52 @@ void sort_by_key(KI *a, KI *tmp, int64_t n)
 void canonical_order(int64_t n, const double *time, const uint8_t *event, const int32_t *stratum,
                      std::vector<int64_t> &perm, std::vector<uint32_t> &meta)
 {
-    // 1. rows grouped by stratum (ascending label), original order kept inside a stratum
-    std::vector<KI> a((size_t)n), tmp((size_t)n);
-    std::vector<int64_t> seg;   // start of each stratum's run in a, then n
+    // 1. every row by time descending, then original index ascending: an LSD radix sort of
+    //    (top 32 bits of the order-preserving time key, row index) words, then each run of equal
+    //    top bits put in full-key order by a stable sort (equal times keep the index order).
+    //    Row indices fit in 32 bits (n <= 2^29 - 1).
+    std::unique_ptr<uint64_t[]> key(new uint64_t[(size_t)n]), a(new uint64_t[(size_t)n]),
+        tmp(new uint64_t[(size_t)n]);   // every entry is written before it is read
+    for (int64_t r = 0; r < n; ++r) {
+        key[(size_t)r] = desc_key(time[r]);
+        a[(size_t)r] = (key[(size_t)r] & 0xffffffff00000000ull) | (uint64_t)r;
+    }
+    radix_hi32(a.get(), tmp.get(), n);
+    const uint64_t *kp = key.get();
+    auto full_less = [kp](uint64_t x, uint64_t y) { return kp[x & 0xffffffffu] < kp[y & 0xffffffffu]; };
+    for (int64_t s0 = 0; s0 < n;) {
+        int64_t s1 = s0 + 1;
+        while (s1 < n && (a[(size_t)s1] >> 32) == (a[(size_t)s0] >> 32)) ++s1;
+        if (s1 - s0 > 1) {
+            uint64_t *b = a.get() + s0;
+            const int64_t len = s1 - s0;
+            if (len <= 32) {   // insertion sort (stable)
+                for (int64_t r = 1; r < len; ++r) {
+                    const uint64_t v = b[r];
+                    int64_t q = r - 1;
+                    while (q >= 0 && full_less(v, b[q])) {
+                        b[q + 1] = b[q];
+                        --q;
+                    }
+                    b[q + 1] = v;
+                }
+            } else {
+                std::stable_sort(b, b + len, full_less);
+            }
+        }
+        s0 = s1;
+    }
+    // 2. grouped by stratum (ascending label), the order of step 1 kept inside a stratum; the
+    //    time key travels with each row for the tie-group test of step 3
+    perm.resize((size_t)n);                  // row index of each canonical position
+    int64_t *order = perm.data();
+    uint64_t *okey = tmp.get();              // its time key
+    std::vector<int64_t> seg;                // start of each stratum's run, then n
     if (!stratum) {
-        for (int64_t r = 0; r < n; ++r) a[r] = KI{0, r};
+        for (int64_t r = 0; r < n; ++r) {
+            order[r] = (int64_t)(a[(size_t)r] & 0xffffffffu);
+            okey[r] = kp[order[r]];
+        }
         seg = {0, n};
     } else {
         int32_t lo = stratum[0], hi = stratum[0];
@@ -85,39 +118,42 @@ void canonical_order(int64_t n, const double *time, const uint8_t *event, const 
             std::vector<int64_t> start((size_t)range + 1, 0);   // start[c]: first position of label lo + c
             for (int64_t r = 0; r < n; ++r) ++start[(size_t)((int64_t)stratum[r] - lo) + 1];
             for (int64_t c = 0; c < range; ++c) {
-                if (start[c + 1] > 0) seg.push_back(start[c]);   // a label that occurs
-                start[c + 1] += start[c];
+                if (start[(size_t)c + 1] > 0) seg.push_back(start[(size_t)c]);   // a label that occurs
+                start[(size_t)c + 1] += start[(size_t)c];
             }
-            for (int64_t r = 0; r < n; ++r) a[start[(size_t)((int64_t)stratum[r] - lo)]++] = KI{0, r};
-        } else {   // stable radix sort on the label's order-preserving image
-            for (int64_t r = 0; r < n; ++r) a[r] = KI{(uint64_t)((uint32_t)stratum[r] ^ 0x80000000u), r};
-            radix_by_key(a.data(), tmp.data(), n);
-            for (int64_t r = 0; r < n; ++r)
-                if (r == 0 || a[r].k != a[r - 1].k) seg.push_back(r);
+            for (int64_t q = 0; q < n; ++q) {
+                const int64_t r = (int64_t)(a[(size_t)q] & 0xffffffffu);
+                const int64_t at = start[(size_t)((int64_t)stratum[r] - lo)]++;
+                order[at] = r;
+                okey[at] = kp[r];
+            }
+        } else {   // stable radix sort on the label's order-preserving image, positions of step 1 riding along
+            std::vector<uint64_t> lab((size_t)n), scratch((size_t)n);
+            for (int64_t q = 0; q < n; ++q) {
+                const int64_t r = (int64_t)(a[(size_t)q] & 0xffffffffu);
+                lab[(size_t)q] = ((uint64_t)((uint32_t)stratum[r] ^ 0x80000000u) << 32) | (uint64_t)q;
+            }
+            radix_hi32(lab.data(), scratch.data(), n);
+            for (int64_t q = 0; q < n; ++q) {
+                order[q] = (int64_t)(a[(size_t)(lab[(size_t)q] & 0xffffffffu)] & 0xffffffffu);
+                okey[q] = kp[order[q]];
+                if (q == 0 || (lab[(size_t)q] >> 32) != (lab[(size_t)q - 1] >> 32)) seg.push_back(q);
+            }
         }
         seg.push_back(n);
     }
-    // 2. inside each stratum: time descending, original index ascending
-    for (size_t g = 0; g + 1 < seg.size(); ++g) {
-        KI *b = a.data() + seg[g];
-        const int64_t len = seg[g + 1] - seg[g];
-        for (int64_t r = 0; r < len; ++r) b[r].k = desc_key(time[b[r].i]);
-        sort_by_key(b, tmp.data(), len);
-    }
     // 3. row words
-    perm.resize((size_t)n);
     meta.assign((size_t)n, 0u);
     for (size_t g = 0; g + 1 < seg.size(); ++g) {
         uint32_t gcount = 0;
         for (int64_t r = seg[g]; r < seg[g + 1]; ++r) {
-            perm[r] = a[r].i;
-            if (r == seg[g]) meta[r] |= kHeadBit;
-            else if (a[r].k != a[r - 1].k) gcount = 0;
-            if (event[a[r].i]) {
-                meta[r] |= kEventBit;
+            if (r == seg[g]) meta[(size_t)r] |= kHeadBit;
+            else if (okey[r] != okey[r - 1]) gcount = 0;
+            if (event[order[r]]) {
+                meta[(size_t)r] |= kEventBit;
                 ++gcount;
             }
-            if (r + 1 == seg[g + 1] || a[r + 1].k != a[r].k) meta[r] |= gcount;
+            if (r + 1 == seg[g + 1] || okey[r + 1] != okey[r]) meta[(size_t)r] |= gcount;
         }
     }
 }

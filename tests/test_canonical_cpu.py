@@ -1,8 +1,8 @@
 """The library's host canonical order (Sec. 2.7; cox_canonical_order) against the
-oracle's, bit-exact, across the paths of its sort: one stratum of every size
-class (insertion sort, comparison sort, radix sort), dense and sparse stratum
-labels (counting sort and radix sort on the label), ties, -0 and +0 times,
-negative and extreme times."""
+oracle's, bit-exact, across the paths of its sort: one stratum of many sizes, dense
+and sparse stratum labels (counting sort and radix sort on the label), times equal in
+their high bits (the full-key fix-up of the radix sort on the high word), ties, -0
+and +0 times, negative and extreme times."""
 import numpy as np
 import pytest
 
@@ -59,3 +59,27 @@ def test_errors():
         coxmi.cox_canonical_order(np.array([1.0, 2.0]), np.array([1, 2], np.uint8))
     with pytest.raises(coxmi.CoxError):
         coxmi.cox_canonical_order(np.zeros(0), np.zeros(0, np.uint8))
+
+
+@pytest.mark.parametrize("bases,spread", [(4, 8), (4, 1000), (700, 8), (700, 1000)])
+def test_times_that_differ_only_in_low_bits(bases, spread):
+    """Times equal in their top 32 bits and different below (runs of equal high words, put in
+    order by the full time: short runs by insertion, long runs by a stable merge), with exact
+    ties among them, one stratum and many."""
+    rng = np.random.default_rng(spread + bases)
+    n = 5000
+    pool = np.concatenate([[1.0, 3.5, -2.25, 1e-300], rng.exponential(1.0, bases)])[:bases]
+    base = pool[rng.integers(0, bases, n)]
+    t = base + rng.integers(0, spread, n) * np.spacing(np.abs(base))
+    e = (rng.random(n) < 0.5).astype(np.uint8)
+    _check(t, e)
+    _check(t, e, rng.integers(0, 40, n).astype(np.int32))
+
+
+def test_many_rows_many_strata():
+    rng = np.random.default_rng(77)
+    n = 300_000
+    t = rng.exponential(1.0, n)
+    t[rng.random(n) < 0.1] = 1.0   # a heavy tie
+    e = (rng.random(n) < 0.5).astype(np.uint8)
+    _check(t, e, rng.integers(0, 3000, n).astype(np.int32))
