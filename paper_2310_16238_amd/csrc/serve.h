@@ -99,7 +99,10 @@ int launch_admit(FitDesc *fits, const FitDesc *joining, const int *slots, const 
 int launch_eta(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_rows(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_cols(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
-int launch_syrk(const FitDesc *fits, const int4 *items, int nitems, hipStream_t s);
+// syrk: counts[0] per-pair items (fit, tile pair, K range, product), then items (fit, 0, K range,
+// product) grouped by the fit's tile count, counts[t] of fits with t tiles (host array of 5);
+// both forms give the same partials
+int launch_syrk(const FitDesc *fits, const int4 *items, const int *counts, hipStream_t s);
 int launch_info(const FitDesc *fits, const int2 *items, int nitems, hipStream_t s);
 int launch_step(const FitDesc *fits, const int *slots, int nslots, int max_p, hipStream_t s);
 
@@ -117,6 +120,7 @@ struct RoundWork {
     const int2 *info;
     const int *slots;                // the fits of the launch
     int ne, nr, nc, ns, ni, nf;
+    int syrk_per_pair;               // 1: syrk items are per tile pair (light rounds), else per fit and K range
     int max_rounds;
     int max_p;                       // largest p among the fits (sizes the step's LDS)
     const uint32_t *hold;            // host-mapped: nonzero asks the launch to end after the current round

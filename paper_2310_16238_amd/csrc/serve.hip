@@ -13,9 +13,9 @@
 //                              one wave: forward segmented scan of w x_j (S1),
 //                              xbar = S1/S0 at group ends, z = sqrt(d) xbar,
 //                              score X'a, diagonal (X o X)'b - sum d xbar^2
-//   syrk  (fit, tile pair, K range, product)
-//                              four waves: a 32 x 32 tile of X' diag(b) X or Z'Z
-//                              over 1024-4096 rows (event groups)
+//   syrk  (fit, K range, product), or (fit, tile pair, K range, product) in light rounds
+//                              four waves: the 32 x 32 tile pairs of X' diag(b) X or
+//                              Z'Z over 1024-4096 rows (event groups)
 //                              on the matrix cores (v_mfma_f32_32x32x2f32, FP32)
 //   info  (fit, tile pair)     the K-range partials summed in FP64 in range order:
 //                              the information matrix
@@ -460,8 +460,100 @@ __device__ __forceinline__ int pair_index(int ti, int tj, int nt)
 
 constexpr int kSyrkWaves = 4;
 
-// Wave v's product over the v-th quarter of the K range of item (fit, tile
-// pair, K range, product).  Rows of X (event groups of Z) come in steps of 32
+// Wave v's share of item (fit, K range, product): the v-th quarter of the range for every
+// tile pair (ti <= tj) of the fit.  Rows of X (event groups of Z) come in steps of 32 -- 16
+// consecutive per half-wave, as float4s.  A step loads the fragments of all NT tiles and the
+// weights once, then runs each pair's 16 products (A the weighted rows of tile ti, B the rows
+// of tile tj) in the order a loop over one pair would, so every pair's sums are those of such
+// a loop.  The next step's operands are loaded before this step's products.
+template <int NT>
+__device__ __forceinline__ void syrk_pairs(const FitDesc &F, int4 it, int v, int lane,
+                                           f32x16 (&acc)[NT * (NT + 1) / 2])
+{
+    constexpr int NP = NT * (NT + 1) / 2;
+    constexpr bool PF = true;
+    const bool zpart = it.w != 0;
+    const float *u = zpart ? F.z : F.xf;
+    const int64_t ldu = zpart ? F.ldz : F.ld;
+    const int64_t range = zpart ? F.zrange : F.xrange, quarter = range / kSyrkWaves;
+    const int64_t k0 = (int64_t)it.z * range + v * quarter;
+    // k0 is a multiple of 64 and ldu a multiple of 64: steps of 32 fit exactly
+    const int64_t k1 = k0 + quarter < ldu ? k0 + quarter : ldu;
+    const int kofs = 16 * (lane >> 5);
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 *ut[NT];
+    bool lt[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int row = t * kTile + (lane & 31);
+        lt[t] = row < F.p;
+        ut[t] = reinterpret_cast<const float4 *>(u + (int64_t)(lt[t] ? row : 0) * ldu + kofs);
+    }
+    const float4 *uc = zpart ? nullptr : reinterpret_cast<const float4 *>(F.bf + kofs);
+#pragma unroll
+    for (int pr = 0; pr < NP; ++pr)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[pr][i] = 0.0f;
+    float4 fn[NT][4], cn[4];
+    auto load = [&](float4(&f)[NT][4], float4(&c)[4], int64_t k) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) f[t][q] = ut[t][k / 4 + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = uc ? uc[k / 4 + q] : zero4;
+    };
+    if (PF && k0 < k1) load(fn, cn, k0);
+    for (int64_t k = k0; k < k1; k += 32) {
+        float4 fv[NT][4], cv[4];
+        if (PF) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fv[t][q] = fn[t][q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cv[q] = cn[q];
+            if (k + 32 < k1) load(fn, cn, k + 32);
+        } else {
+            load(fv, cv, k);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            if (!lt[t]) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fv[t][q] = zero4;   // rows beyond p (loaded from row 0)
+            }
+        int pr = 0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+            float4 av[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                av[q] = fv[ti][q];
+                if (uc) {
+                    av[q].x *= cv[q].x;
+                    av[q].y *= cv[q].y;
+                    av[q].z *= cv[q].z;
+                    av[q].w *= cv[q].w;
+                }
+            }
+#pragma unroll
+            for (int tj = ti; tj < NT; ++tj, ++pr) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    acc[pr] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].x, fv[tj][q].x, acc[pr], 0, 0, 0);
+                    acc[pr] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].y, fv[tj][q].y, acc[pr], 0, 0, 0);
+                    acc[pr] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].z, fv[tj][q].z, acc[pr], 0, 0, 0);
+                    acc[pr] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q].w, fv[tj][q].w, acc[pr], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
+// Wave v's product over the v-th quarter of the K range of a per-pair item (fit, tile
+// pair, K range, product): the same products, in the same order, as syrk_pairs makes for
+// that pair.  Rows of X (event groups of Z) come in steps of 32
 // -- 16 consecutive per half-wave, as float4s -- with the next step's operands
 // loaded before this step's 16 products.
 __device__ __forceinline__ f32x16 syrk_partial(const FitDesc &F, int4 it, int v, int lane)
@@ -532,52 +624,123 @@ __device__ __forceinline__ f32x16 syrk_partial(const FitDesc &F, int4 it, int v,
     return acc;
 }
 
-// Item (fit, tile pair, K range, product), run by kSyrkWaves waves (v = 0 .. 3):
-// the four accumulators are added in wave order through red ([3][16][64]
-// floats).  Every thread of the workgroup calls it the same number of times
-// (the barriers inside); `live` false leaves the item out.
-__device__ __forceinline__ void syrk_item(const FitDesc *fits, int4 it, bool live, int v, int lane, float *red)
+constexpr int kSyrkRed = (kSyrkWaves - 1) * 16 * kWave;   // floats of red
+
+// Per-pair item (fit, tile pair, K range, product) for light rounds, where spreading a fit's
+// pairs over workgroups shortens the round: the four wave accumulators are added in wave order
+// through red, as in syrk_item_nt, so the pair's partial is the same either way.
+__device__ void syrk_pair_item(const FitDesc *fits, int4 it, bool live, bool compute, int v, int lane,
+                               float *red)
 {
+    if (!live) return;
+    const FitDesc &F = fits[it.x];
     f32x16 acc;
-    if (live) {
-        acc = syrk_partial(fits[it.x], it, v, lane);
-    } else {
+    if (compute) {
+        acc = syrk_partial(F, it, v, lane);
+        if (v > 0) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
-    }
-    if (v > 0) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) red[((v - 1) * 16 + i) * kWave + lane] = acc[i];
+            for (int i = 0; i < 16; ++i) red[((v - 1) * 16 + i) * kWave + lane] = acc[i];
+        }
     }
     __syncthreads();
-    if (v == 0) {
+    if (compute && v == 0) {
 #pragma unroll
         for (int w = 0; w < kSyrkWaves - 1; ++w) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[i] += red[(w * 16 + i) * kWave + lane];
         }
+        const int slot = it.w != 0 ? F.nxr + it.z : it.z;
+        float *out = F.part + ((int64_t)slot * F.npairs + it.y) * (kTile * kTile);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = 8 * (i / 4) + 4 * (lane >> 5) + (i % 4), nn = lane & 31;
+            out[m * kTile + nn] = acc[i];
+        }
     }
     __syncthreads();   // red is rewritten by the next item
-    if (v != 0 || !live) return;
-    const FitDesc &F = fits[it.x];
-    const int slot = it.w != 0 ? F.nxr + it.z : it.z;
-    float *out = F.part + ((int64_t)slot * F.npairs + it.y) * (kTile * kTile);
+}
+
+
+
+// Item (fit, K range, product) of a fit with NT tiles: kSyrkWaves waves (v = 0 .. 3) compute;
+// in the persistent kernel the workgroup's other waves only keep the barrier count
+// (compute = false).  Each pair's four wave accumulators are added in wave order through
+// red ([3][16][64] floats), one pair after another, into the pair's partial of the range.
+template <int NT>
+__device__ __forceinline__ void syrk_item_nt(const FitDesc &F, int4 it, bool compute, int v, int lane,
+                                             float *red)
+{
+    constexpr int NP = NT * (NT + 1) / 2;
+    f32x16 acc[NP];
+    if (compute) {
+        syrk_pairs<NT>(F, it, v, lane, acc);
+    } else {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int m = 8 * (i / 4) + 4 * (lane >> 5) + (i % 4), nn = lane & 31;
-        out[m * kTile + nn] = acc[i];
+        for (int pr = 0; pr < NP; ++pr)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[pr][i] = 0.0f;
+    }
+    const int slot = it.w != 0 ? F.nxr + it.z : it.z;
+#pragma unroll
+    for (int pr = 0; pr < NP; ++pr) {
+        if (compute && v > 0) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) red[((v - 1) * 16 + i) * kWave + lane] = acc[pr][i];
+        }
+        __syncthreads();
+        if (compute && v == 0) {
+            f32x16 sum = acc[pr];
+#pragma unroll
+            for (int w = 0; w < kSyrkWaves - 1; ++w) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) sum[i] += red[(w * 16 + i) * kWave + lane];
+            }
+            float *out = F.part + ((int64_t)slot * F.npairs + pr) * (kTile * kTile);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = 8 * (i / 4) + 4 * (lane >> 5) + (i % 4), nn = lane & 31;
+                out[m * kTile + nn] = sum[i];
+            }
+        }
+        __syncthreads();   // red is rewritten for the next pair
     }
 }
 
-constexpr int kSyrkRed = (kSyrkWaves - 1) * 16 * kWave;   // floats of red per item
+// Item (fit, K range, product); the whole workgroup calls it (the barriers inside depend only
+// on the fit's tile count), `live` uniform: false leaves the item out.  Not inlined into the
+// persistent kernel, which would otherwise hold the registers of all four tile counts at once.
+__device__ __noinline__ void syrk_item(const FitDesc *fits, int4 it, bool live, bool compute, int v, int lane,
+                                       float *red)
+{
+    if (!live) return;
+    const FitDesc &F = fits[it.x];
+    switch (tile_count(F.p)) {
+    case 1: syrk_item_nt<1>(F, it, compute, v, lane, red); break;
+    case 2: syrk_item_nt<2>(F, it, compute, v, lane, red); break;
+    case 3: syrk_item_nt<3>(F, it, compute, v, lane, red); break;
+    default: syrk_item_nt<4>(F, it, compute, v, lane, red); break;   // p <= kMaxP = 128
+    }
+}
 
-// One workgroup per item.
-__global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_kernel(const FitDesc *fits, const int4 *items)
+// One workgroup per per-pair item.
+__global__ __launch_bounds__(kWave * kSyrkWaves) void syrk_pair_kernel(const FitDesc *fits, const int4 *items)
+{
+    __shared__ float red[kSyrkRed];
+    const int4 it = items[blockIdx.x];
+    const bool live = !(fit_flags(fits, it.x) & (kDone | kFrozen));
+    syrk_pair_item(fits, it, live, true, threadIdx.x / kWave, threadIdx.x & (kWave - 1), red);
+}
+
+// One workgroup per item of a fit with NT tiles (the items come grouped by tile count, so
+// each launch holds the registers its own tile count needs).
+template <int NT>
+__global__ __launch_bounds__(kWave * kSyrkWaves, NT <= 3 ? 2 : 1) void syrk_kernel(const FitDesc *fits,
+                                                                                  const int4 *items)
 {
     __shared__ float red[kSyrkRed];
     const int4 it = items[blockIdx.x];
     if (fit_flags(fits, it.x) & (kDone | kFrozen)) return;   // the whole workgroup
-    syrk_item(fits, it, true, threadIdx.x / kWave, threadIdx.x & (kWave - 1), red);
+    syrk_item_nt<NT>(fits[it.x], it, true, threadIdx.x / kWave, threadIdx.x & (kWave - 1), red);
 }
 
 // ------------------------------------------------------------------ info
@@ -1191,17 +1354,13 @@ __global__ __launch_bounds__(kRoundThreads) void round_kernel(RoundWork w)
         }
         lap(2);
         if (w.ns > 0) {
-            // contraction: half-workgroup items
-            float *red = reinterpret_cast<float *>(lds) + half * kSyrkRed;
-            for (int base = 0; base < w.ns; base += 2 * G) {
-                const int i = __builtin_amdgcn_readfirstlane(base + half * G + b);
-                int4 it = make_int4(0, 0, 0, 0);
-                bool live = false;
-                if (i < w.ns) {
-                    it = w.syrk[i];
-                    live = !(fit_flags(w.fits, it.x) & (kDone | kFrozen));
-                }
-                syrk_item(w.fits, it, live, wv & (kSyrkWaves - 1), lane, red);
+            // contraction: workgroup items, computed by waves 0-3 (the others keep the barriers)
+            float *red = reinterpret_cast<float *>(lds);
+            for (int i = b; i < w.ns; i += G) {
+                const int4 it = w.syrk[i];
+                const bool live = !(fit_flags(w.fits, it.x) & (kDone | kFrozen));
+                if (w.syrk_per_pair) syrk_pair_item(w.fits, it, live, wv < kSyrkWaves, wv & (kSyrkWaves - 1), lane, red);
+                else syrk_item(w.fits, it, live, wv < kSyrkWaves, wv & (kSyrkWaves - 1), lane, red);
             }
             if (round_barrier(w, ctl, ++epoch, false, round, &s_word) < 0) {
                 status = -1;
@@ -1269,9 +1428,18 @@ int launch_cols(const FitDesc *fits, const int2 *items, int nitems, hipStream_t 
     return (int)hipGetLastError();
 }
 
-int launch_syrk(const FitDesc *fits, const int4 *items, int nitems, hipStream_t s)
+int launch_syrk(const FitDesc *fits, const int4 *items, const int *counts, hipStream_t s)
 {
-    if (nitems > 0) syrk_kernel<<<nitems, kWave * kSyrkWaves, 0, s>>>(fits, items);
+    const int4 *at = items;
+    if (counts[0] > 0) syrk_pair_kernel<<<counts[0], kWave * kSyrkWaves, 0, s>>>(fits, at);
+    at += counts[0];
+    if (counts[1] > 0) syrk_kernel<1><<<counts[1], kWave * kSyrkWaves, 0, s>>>(fits, at);
+    at += counts[1];
+    if (counts[2] > 0) syrk_kernel<2><<<counts[2], kWave * kSyrkWaves, 0, s>>>(fits, at);
+    at += counts[2];
+    if (counts[3] > 0) syrk_kernel<3><<<counts[3], kWave * kSyrkWaves, 0, s>>>(fits, at);
+    at += counts[3];
+    if (counts[4] > 0) syrk_kernel<4><<<counts[4], kWave * kSyrkWaves, 0, s>>>(fits, at);
     return (int)hipGetLastError();
 }
 

@@ -553,6 +553,8 @@ bool check_desc(const cox_server *s, const FitDesc &F, const FitLayout &L, size_
 
 // Everything the worker does per round; returns false on a device error (message in `err`).
 constexpr int kRoundsAhead = 2;   // rounds queued on the compute stream at once
+// Below this many (fit, K range) contraction items a round gives each tile pair its own items.
+constexpr size_t kSyrkPerFitItems = 512;
 
 struct WorkerState {
     std::vector<int> uploading;   // slots whose upload was queued in the previous round
@@ -688,22 +690,29 @@ Result make_result(const cox_server *s, int sl, double t_done)
 struct RoundLists {
     size_t o_eta = 0, o_rows = 0, o_cols = 0, o_syrk = 0, o_info = 0, o_slots = 0;
     size_t ke = 0, kr = 0, kc = 0, ks = 0, ki = 0;
+    int ks_nt[5] = {0, 0, 0, 0, 0};   // contraction items: per tile pair, then of fits with 1..4 tiles
+    bool per_pair = false;
     int max_p = 1;
 };
 
 bool build_lists(cox_server *s, const std::vector<int> &act, RoundLists &R, std::string &err)
 {
-    size_t n_eta = 0, n_rows = 0, n_cols = 0, n_syrk = 0, n_info = 0;
+    size_t n_eta = 0, n_rows = 0, n_cols = 0, n_syrk = 0, n_syrk_pairs = 0, n_info = 0;
     for (int sl : act) {
         const FitLayout &L = s->slots[sl].req->lay;
         n_eta += L.ntile;
         n_rows += L.ntc;
         n_cols += (size_t)L.ntc * ((L.p + kColBlock - 1) / kColBlock);
         if (!s->slots[sl].frozen) {
-            n_syrk += (size_t)L.npairs * (L.nxr + L.nzr);
+            n_syrk += (size_t)(L.nxr + L.nzr);
+            n_syrk_pairs += (size_t)L.npairs * (L.nxr + L.nzr);
             n_info += L.npairs;
         }
     }
+    // a light round spreads each fit's tile pairs over workgroups (shorter critical path); a heavy
+    // one gives a workgroup all pairs of a K range (each row of X read once per range)
+    const bool per_pair = n_syrk < kSyrkPerFitItems;
+    if (per_pair) n_syrk = n_syrk_pairs;
     Packer pk;
     R.o_eta = pk.take<int2>(n_eta);
     R.o_rows = pk.take<int2>(n_rows);
@@ -732,11 +741,32 @@ bool build_lists(cox_server *s, const std::vector<int> &act, RoundLists &R, std:
             for (int j = 0; j < L.p; j += kColBlock) cols[kc++] = make_int2(sl, (t << 10) | j);
         }
         if (!s->slots[sl].frozen)
+            for (int pr = 0; pr < L.npairs; ++pr) info[ki++] = make_int2(sl, pr);
+    }
+    // contraction items: (fit, tile pair, K range, product), or (fit, 0, K range, product) grouped
+    // by the fit's tile count
+    R.per_pair = per_pair;
+    if (per_pair) {
+        for (int sl : act) {
+            const FitLayout &L = s->slots[sl].req->lay;
+            if (s->slots[sl].frozen) continue;
             for (int pr = 0; pr < L.npairs; ++pr) {
-                info[ki++] = make_int2(sl, pr);
                 for (int r = 0; r < L.nxr; ++r) syrk[ks++] = make_int4(sl, pr, r, 0);
                 for (int r = 0; r < L.nzr; ++r) syrk[ks++] = make_int4(sl, pr, r, 1);
             }
+        }
+        R.ks_nt[0] = (int)ks;
+    } else {
+        for (int nt = 1; nt <= 4; ++nt) {
+            const size_t ks0 = ks;
+            for (int sl : act) {
+                const FitLayout &L = s->slots[sl].req->lay;
+                if (s->slots[sl].frozen || (L.p + kTile - 1) / kTile != nt) continue;
+                for (int r = 0; r < L.nxr; ++r) syrk[ks++] = make_int4(sl, 0, r, 0);
+                for (int r = 0; r < L.nzr; ++r) syrk[ks++] = make_int4(sl, 0, r, 1);
+            }
+            R.ks_nt[nt] = (int)(ks - ks0);
+        }
     }
     if (ke != n_eta || kr != n_rows || kc != n_cols || ks != n_syrk || ki != n_info) {
         err = "internal error: work list sizes";
@@ -862,7 +892,7 @@ bool run_round(cox_server *s, WorkerState &ws, std::string &err)
         WCHECK((hipError_t)launch_cols(s->d_desc, reinterpret_cast<const int2 *>(D + R.o_cols), (int)R.kc, s->compute),
                "cols");
         if (R.ks) {
-            WCHECK((hipError_t)launch_syrk(s->d_desc, reinterpret_cast<const int4 *>(D + R.o_syrk), (int)R.ks,
+            WCHECK((hipError_t)launch_syrk(s->d_desc, reinterpret_cast<const int4 *>(D + R.o_syrk), R.ks_nt,
                                            s->compute),
                    "syrk");
             WCHECK((hipError_t)launch_info(s->d_desc, reinterpret_cast<const int2 *>(D + R.o_info), (int)R.ki,
@@ -950,6 +980,7 @@ bool run_launch_fused(cox_server *s, WorkerState &ws, std::string &err)
     w.ns = (int)R.ks;
     w.ni = (int)R.ki;
     w.nf = (int)act.size();
+    w.syrk_per_pair = R.per_pair ? 1 : 0;
     w.max_rounds = s->opt.fused_rounds;
     w.max_p = R.max_p;
     w.hold = reinterpret_cast<const uint32_t *>(s->dh_round);

@@ -319,3 +319,31 @@ def test_l1_submission_errors():
             assert e.value.code == coxmi.COX_EINVAL
         with pytest.raises(ValueError):
             srv.submit(d.X, d.time, d.event, d.stratum, gamma=1.0, penalize=np.ones(2, np.uint8))
+
+
+def test_contraction_modes_give_the_same_fit():
+    """A heavy round gives a workgroup every tile pair of a K range, a light one spreads the
+    pairs over workgroups (below 512 (fit, K range) items); both make each pair's products in
+    the same order, so a fit served among 59 others (heavy rounds: 23 or more resident fits of
+    n >= 60,000, each with 15 or more X ranges and 8 or more Z ranges) equals the same fit
+    served alone (light rounds) bit for bit.  Requests in device memory, so fits are
+    admitted as fast as their keys are sorted."""
+    reqs = _requests(60, seed=29, n_range=(60_000, 100_000), p_range=(30, 110))
+    dev = [_on_device(d) for d in reqs]
+    torch.cuda.synchronize()
+    with coxmi.CoxServer(hbm_budget=32 << 30, staging_bytes=256 << 20, prep_threads=8) as srv:
+        tickets = [srv.submit_device(*t) for t in dev]
+        assert srv.drain(timeout=150.0)
+        mixed = [srv.poll(t) for t in tickets]
+        st = srv.stats()
+    _say(f"  60 fits together: resident peak {st['resident_peak']}, {st['iterations']} rounds")
+    assert st["resident_peak"] >= 23
+    for k in (0, 29, 59):
+        d = reqs[k]
+        with coxmi.CoxServer(hbm_budget=1 << 30, prep_threads=1) as srv:
+            t = srv.submit(d.X, d.time, d.event, d.stratum)
+            assert srv.wait(t, timeout=60.0)
+            alone = srv.poll(t)
+        assert np.array_equal(alone[0], mixed[k][0]), (k, _rel(alone[0], mixed[k][0]))
+        assert alone[1]["iters"] == mixed[k][1]["iters"] and alone[1]["objective"] == mixed[k][1]["objective"]
+    _check_against_oracle(reqs[0], mixed[0][0], mixed[0][1])
