@@ -49,6 +49,16 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// x of lane src, for a src that is the same in every lane of the wave (two v_readlane, no
+// trip through the LDS crossbar as for a per-lane source)
+__device__ __forceinline__ double lane_value(double x, int src)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // ------------------------------------------------------------------ admit: FP32 copy of X
 
 // Item (k, t): rows [256 t, 256 t + 256) of joining fit k (X gathered from the
@@ -847,8 +857,8 @@ __device__ void prox_step(const FitDesc &F, double *A, double *y, const uint8_t 
                 const double a = s_a[j];
                 if (a == 0.0) continue;
                 const int src = j & (kWave - 1);
-                const double hj = __shfl(j < kWave ? hd0 : hd1, src, kWave);
-                const double dj = __shfl(j < kWave ? d0 : d1, src, kWave);
+                const double hj = lane_value(j < kWave ? hd0 : hd1, src);
+                const double dj = lane_value(j < kWave ? d0 : d1, src);
                 const double bj = s_b[j], gm = s_gm[j];
                 const double bb = s_g[j] + hj - a * dj;   // the model's slope at D with D_j removed
                 const double u = a * bj - bb;
@@ -1022,7 +1032,7 @@ __device__ __forceinline__ void step_fit(const FitDesc *fits, int slot, double *
 #pragma unroll
                 for (int c = 0; c < NB; ++c) {
                     if (c < kb) {
-                        double d = __shfl(r[c], c, kWave);
+                        double d = lane_value(r[c], c);
                         const bool ok = d > 0.0;
                         if (!ok) {
                             d = 1.0;
@@ -1033,7 +1043,7 @@ __device__ __forceinline__ void step_fit(const FitDesc *fits, int slot, double *
                         const double lc = r[c];   // L[k0 + lane][k0 + c] below the pivot
 #pragma unroll
                         for (int cc = c + 1; cc < NB; ++cc) {
-                            const double lcc = __shfl(lc, cc, kWave);   // L[k0 + cc][k0 + c]
+                            const double lcc = lane_value(lc, cc);   // L[k0 + cc][k0 + c]
                             if (cc < kb && lane >= cc) r[cc] = fma(-lc, lcc, r[cc]);
                         }
                     }
@@ -1121,7 +1131,7 @@ __device__ __forceinline__ void step_fit(const FitDesc *fits, int slot, double *
             double y0 = lane < p ? y[lane] : 0.0, y1 = lane + kWave < p ? y[lane + kWave] : 0.0;
             for (int k = 0; k < p; ++k) {
                 const double own = k < kWave ? y0 : y1;
-                const double yk = __shfl(own, k & (kWave - 1), kWave) / A[k * p + k];
+                const double yk = lane_value(own, k & (kWave - 1)) / A[k * p + k];
                 if (lane == (k & (kWave - 1))) {
                     if (k < kWave) y0 = yk;
                     else y1 = yk;
@@ -1131,7 +1141,7 @@ __device__ __forceinline__ void step_fit(const FitDesc *fits, int slot, double *
             }
             for (int k = p - 1; k >= 0; --k) {
                 const double own = k < kWave ? y0 : y1;
-                const double xk = __shfl(own, k & (kWave - 1), kWave) / A[k * p + k];
+                const double xk = lane_value(own, k & (kWave - 1)) / A[k * p + k];
                 if (lane == (k & (kWave - 1))) {
                     if (k < kWave) y0 = xk;
                     else y1 = xk;
