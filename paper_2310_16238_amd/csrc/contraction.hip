@@ -28,6 +28,16 @@ namespace {
 
 constexpr int kTile = 64, kKc = 32, kSyrkThreads = 256, kWaveC = 64;
 
+// x of lane src, for a src that is the same in every lane of the wave (two v_readlane, no
+// trip through the LDS crossbar as for a per-lane source)
+__device__ __forceinline__ double lane_value(double x, int src)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 __device__ __forceinline__ void tile_pair(int pair, int nt, int &ti, int &tj)
 {
     // pairs (ti <= tj) in row-major order of the upper triangle
@@ -348,7 +358,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
 #pragma unroll
                 for (int kk = 0; kk < kPanNB; ++kk) {
                     if (kk < nb) {
-                        double d = __shfl(D[kk], kk, kWaveC);
+                        double d = lane_value(D[kk], kk);
                         const bool ok = d > 0.0;
                         if (!ok) d = 1.0;
                         const double piv = sqrt(d), inv = 1.0 / piv;
@@ -462,7 +472,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
             for (int c = 0; c < kCholNB; ++c) {
                 if (c < nb) {
                     if (lane == c) yi /= Lr[c];
-                    const double yc = __shfl(yi, c, kWaveC);
+                    const double yc = lane_value(yi, c);
                     if (lane > c && lane < nb) yi = fma(-Lr[c], yc, yi);
                 }
             }
@@ -489,7 +499,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_blocked_kernel(double *A, i
             for (int c = kCholNB - 1; c >= 0; --c) {
                 if (c < nb) {
                     if (lane == c) xi /= Lc[c];
-                    const double xc = __shfl(xi, c, kWaveC);
+                    const double xc = lane_value(xi, c);
                     if (lane < c) xi = fma(-Lc[c], xc, xi);
                 }
             }
